@@ -1,0 +1,482 @@
+/*
+ * fmb_oracle.c -- plain FP64 CPU oracle for the sort-free, two-parameter Fuzzy
+ * Metaballs ray renderer (Keselman & Hebert, "Flexible Techniques for
+ * Differentiable Rendering with 3D Gaussians", WACV 2024) and its gradients.
+ *
+ * TEST INFRASTRUCTURE.  Only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark load this library.  It shares no code, header, table or
+ * helper with the GPU path, and the GPU path never calls it.
+ *
+ * What it computes, per ray (origin o, unit direction v) and Gaussian i with mean
+ * mu_i, precision Sigma_i^-1 = U_i^T U_i (U_i upper triangular) and weight
+ * lambda_i > 0, all in double precision, straight from the definitions:
+ *
+ *   t_i     = (mu_i - o)^T Sigma^-1 v / (v^T Sigma^-1 v)     peak of the density along
+ *                                                           the ray ("linear approach",
+ *                                                           Sec. 3.1, below Eq. (2))
+ *   d_i     = log(lambda_i) - 1/2 x^T Sigma^-1 x,  x = o + t_i v - mu_i    Eq. (2)
+ *   delta_i = exp(d_i)                                                    Eq. (4)
+ *   w_i     = exp(beta1 d_i - (beta2/eta) t_i)                            Eq. (7)
+ *   t_f     = sum_i w_i t_i / sum_i w_i                                   Eq. (3)
+ *   n_i     = Sigma^-1 x / |Sigma^-1 x|,  blended by Eq. (3), unit length  Eq. (17), Sec. 6
+ *   alpha   = 1 - exp(-sum_i delta_i)                                     Eq. (8)
+ *   flow    = pi_B(p) - pi_A(p),  p = o + t_f v                           Sec. 5
+ *
+ * Readings where the paper is silent (each also listed in the design notes):
+ *   - |y| is evaluated as sqrt(y.y + EPS_N) with EPS_N = 1e-30 so that a zero
+ *     vector normalises to zero instead of 0/0;
+ *   - the weights of Eq. (3) are normalised with the usual max shift
+ *     (exp(z - max z)), which leaves the ratio unchanged;
+ *   - no clamp for Gaussians behind the camera (t_i < 0) or for points behind the
+ *     second camera.
+ *
+ * The gradient is the plain reverse-mode chain rule through exactly these steps,
+ * with the full symmetric matrix A = U^T U and A's gradient folded back to U at the
+ * end (dL/dU = U (Abar + Abar^T), upper entries kept).  Every function here is
+ * pinned by the CPU tests: closed forms for a single isotropic Gaussian, a brute
+ * force line search for the peak density, the converted-3DGS alpha of 79/80
+ * (Sec. 7), blend and alpha identities for two Gaussians, permutation, scale and
+ * rigid-motion invariances, the rotation homography for flow, and central finite
+ * differences for every gradient.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define EPS_N 1e-30
+
+int fmbo_version(void) { return 1; }
+
+/* ----------------------------------------------------------------------------------- */
+/* Cameras: world-to-camera [R|T] (row-major 3x4, x_cam = R x + T), OpenCV axes,       */
+/* intrinsics (fx, fy, cx, cy), pixel (row i, col j) centred at (j + 1/2, i + 1/2).    */
+/* ----------------------------------------------------------------------------------- */
+
+static void cam_centre(const double *e, double *c)
+{
+    /* c = -R^T T */
+    for (int a = 0; a < 3; ++a)
+        c[a] = -(e[0 * 4 + a] * e[3] + e[1 * 4 + a] * e[7] + e[2 * 4 + a] * e[11]);
+}
+
+static void to_cam(const double *e, const double *p, double *q)
+{
+    for (int r = 0; r < 3; ++r)
+        q[r] = e[r * 4 + 0] * p[0] + e[r * 4 + 1] * p[1] + e[r * 4 + 2] * p[2] + e[r * 4 + 3];
+}
+
+static void project(const double *e, const double *k, const double *p, double *uv)
+{
+    double q[3];
+    to_cam(e, p, q);
+    uv[0] = k[0] * q[0] / q[2] + k[2];
+    uv[1] = k[1] * q[1] / q[2] + k[3];
+}
+
+/* Rays through pixel centres: o = camera centre, v = R^T d_c / |d_c| (world frame). */
+void fmbo_pixel_rays(int64_t p, const int32_t *view, const int32_t *row, const int32_t *col,
+                     const double *w2c, const double *intr, double *orig, double *dir)
+{
+    for (int64_t r = 0; r < p; ++r) {
+        const double *e = w2c + 12 * (int64_t)view[r];
+        const double *k = intr + 4 * (int64_t)view[r];
+        double dc[3] = {((double)col[r] + 0.5 - k[2]) / k[0], ((double)row[r] + 0.5 - k[3]) / k[1], 1.0};
+        double d[3], nn = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            d[a] = e[0 * 4 + a] * dc[0] + e[1 * 4 + a] * dc[1] + e[2 * 4 + a] * dc[2];
+            nn += d[a] * d[a];
+        }
+        nn = sqrt(nn);
+        for (int a = 0; a < 3; ++a) dir[3 * r + a] = d[a] / nn;
+        cam_centre(e, orig + 3 * r);
+    }
+}
+
+/* Rays given by direction: o = centre of camera view[r], v = dirs[r] / |dirs[r]|. */
+void fmbo_dir_rays(int64_t p, const int32_t *view, const double *dirs, const double *w2c,
+                   double *orig, double *dir)
+{
+    for (int64_t r = 0; r < p; ++r) {
+        const double *d = dirs + 3 * r;
+        double nn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        for (int a = 0; a < 3; ++a) dir[3 * r + a] = d[a] / nn;
+        cam_centre(w2c + 12 * (int64_t)view[r], orig + 3 * r);
+    }
+}
+
+/* Pinhole projection of world points into camera view[r] (pixel coordinates). */
+void fmbo_project(int64_t p, const int32_t *view, const double *pts, const double *w2c,
+                  const double *intr, double *uv)
+{
+    for (int64_t r = 0; r < p; ++r)
+        project(w2c + 12 * (int64_t)view[r], intr + 4 * (int64_t)view[r], pts + 3 * r, uv + 2 * r);
+}
+
+/* ----------------------------------------------------------------------------------- */
+/* Gaussians and the per-(ray, Gaussian) terms                                         */
+/* ----------------------------------------------------------------------------------- */
+
+typedef struct {
+    double U[9];   /* upper triangular factor, row-major */
+    double A[9];   /* Sigma^-1 = U^T U */
+    double mu[3];
+    double lam, loglam;
+} gauss_t;
+
+static void load_gaussians(int32_t n, const double *means, const double *prec, const double *weights,
+                           gauss_t *g)
+{
+    for (int32_t i = 0; i < n; ++i) {
+        const double *u = prec + 6 * (int64_t)i;
+        double U[9] = {u[0], u[1], u[2], 0.0, u[3], u[4], 0.0, 0.0, u[5]};
+        memcpy(g[i].U, U, sizeof U);
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double s = 0.0;
+                for (int k = 0; k < 3; ++k) s += U[k * 3 + a] * U[k * 3 + b];
+                g[i].A[a * 3 + b] = s;
+            }
+        for (int a = 0; a < 3; ++a) g[i].mu[a] = means[3 * (int64_t)i + a];
+        g[i].lam = weights[i];
+        g[i].loglam = log(weights[i]);
+    }
+}
+
+typedef struct {
+    double mup[3];  /* mu - o */
+    double Av[3];
+    double num, den, t;
+    double x[3];    /* o + t v - mu */
+    double Ax[3];   /* Sigma^-1 x, the unnormalised normal of Eq. (17) */
+    double m, d, delta, z;
+    double gn;      /* sqrt(|Ax|^2 + EPS_N) */
+    double n[3];
+} pair_t;
+
+static void mat3v(const double *M, const double *x, double *y)
+{
+    for (int a = 0; a < 3; ++a) y[a] = M[a * 3 + 0] * x[0] + M[a * 3 + 1] * x[1] + M[a * 3 + 2] * x[2];
+}
+
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+static void pair_eval(const gauss_t *g, const double *o, const double *v, double b1, double b2,
+                      double eta, pair_t *q)
+{
+    for (int a = 0; a < 3; ++a) q->mup[a] = g->mu[a] - o[a];
+    mat3v(g->A, v, q->Av);
+    q->num = dot3(q->mup, q->Av);
+    q->den = dot3(v, q->Av);
+    q->t = q->num / q->den;
+    for (int a = 0; a < 3; ++a) q->x[a] = o[a] + q->t * v[a] - g->mu[a];
+    mat3v(g->A, q->x, q->Ax);
+    q->m = dot3(q->x, q->Ax);
+    q->d = g->loglam - 0.5 * q->m;
+    q->delta = exp(q->d);
+    q->z = b1 * q->d - (b2 / eta) * q->t;
+    q->gn = sqrt(dot3(q->Ax, q->Ax) + EPS_N);
+    for (int a = 0; a < 3; ++a) q->n[a] = q->Ax[a] / q->gn;
+}
+
+/* Per-ray blend: softmax weights of z, then Eq. (3) for depth and normals, Eq. (8) for alpha. */
+typedef struct {
+    double M, S;
+    double tf, N[3], nN, nf[3], D, alpha;
+    double p[3];
+    double flow[2];
+} ray_t;
+
+static void ray_blend(int32_t n, const pair_t *q, double *wt, ray_t *r)
+{
+    r->M = -INFINITY;
+    for (int32_t i = 0; i < n; ++i)
+        if (q[i].z > r->M) r->M = q[i].z;
+    r->S = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        wt[i] = exp(q[i].z - r->M);
+        r->S += wt[i];
+    }
+    r->tf = 0.0;
+    r->N[0] = r->N[1] = r->N[2] = 0.0;
+    r->D = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        wt[i] /= r->S;
+        r->tf += wt[i] * q[i].t;
+        for (int a = 0; a < 3; ++a) r->N[a] += wt[i] * q[i].n[a];
+        r->D += q[i].delta;
+    }
+    r->nN = sqrt(dot3(r->N, r->N) + EPS_N);
+    for (int a = 0; a < 3; ++a) r->nf[a] = r->N[a] / r->nN;
+    r->alpha = -expm1(-r->D);
+}
+
+typedef struct {
+    int32_t n;
+    gauss_t *g;
+    double b1, b2, eta;
+    const double *orig, *dir;
+    const int32_t *view;
+    const double *w2c_a, *intr_a, *w2c_b, *intr_b;
+} ctx_t;
+
+static void ray_forward(const ctx_t *c, int64_t r, pair_t *q, double *wt, ray_t *ry)
+{
+    const double *o = c->orig + 3 * r, *v = c->dir + 3 * r;
+    for (int32_t i = 0; i < c->n; ++i) pair_eval(&c->g[i], o, v, c->b1, c->b2, c->eta, &q[i]);
+    ray_blend(c->n, q, wt, ry);
+    for (int a = 0; a < 3; ++a) ry->p[a] = o[a] + ry->tf * v[a];
+    if (c->w2c_b) {
+        int64_t k = c->view[r];
+        double ub[2], ua[2];
+        project(c->w2c_b + 12 * k, c->intr_b + 4 * k, ry->p, ub);
+        project(c->w2c_a + 12 * k, c->intr_a + 4 * k, ry->p, ua);
+        ry->flow[0] = ub[0] - ua[0];
+        ry->flow[1] = ub[1] - ua[1];
+    } else {
+        ry->flow[0] = ry->flow[1] = 0.0;
+    }
+}
+
+static int nthreads_of(int req)
+{
+#ifdef _OPENMP
+    return req > 0 ? req : omp_get_max_threads();
+#else
+    (void)req;
+    return 1;
+#endif
+}
+
+/* Forward render of p rays.  Any output pointer may be NULL.  Returns 0, or -1 on bad input. */
+int fmbo_render(int32_t n, const double *means, const double *prec, const double *weights,
+                const double *betas, double eta, int64_t p, const double *orig, const double *dir,
+                const int32_t *view, const double *w2c_a, const double *intr_a, const double *w2c_b,
+                const double *intr_b, double *depth, double *alpha, double *normal, double *flow,
+                int n_threads)
+{
+    if (n < 1 || p < 0 || !means || !prec || !weights || !betas || !orig || !dir) return -1;
+    if (w2c_b && (!view || !w2c_a || !intr_a || !intr_b)) return -1;
+    gauss_t *g = (gauss_t *)malloc(sizeof(gauss_t) * (size_t)n);
+    if (!g) return -1;
+    load_gaussians(n, means, prec, weights, g);
+    ctx_t c = {n, g, betas[0], betas[1], eta, orig, dir, view, w2c_a, intr_a, w2c_b, intr_b};
+    int nt = nthreads_of(n_threads);
+#pragma omp parallel num_threads(nt)
+    {
+        pair_t *q = (pair_t *)malloc(sizeof(pair_t) * (size_t)n);
+        double *wt = (double *)malloc(sizeof(double) * (size_t)n);
+        ray_t ry;
+#pragma omp for schedule(static)
+        for (int64_t r = 0; r < p; ++r) {
+            ray_forward(&c, r, q, wt, &ry);
+            if (depth) depth[r] = ry.tf;
+            if (alpha) alpha[r] = ry.alpha;
+            if (normal)
+                for (int a = 0; a < 3; ++a) normal[3 * r + a] = ry.nf[a];
+            if (flow) {
+                flow[2 * r] = ry.flow[0];
+                flow[2 * r + 1] = ry.flow[1];
+            }
+        }
+        free(q);
+        free(wt);
+    }
+    free(g);
+    return 0;
+}
+
+/* Per-Gaussian terms of one ray: t_i, d_i, z_i, n_i (for the tests). */
+void fmbo_ray_terms(int32_t n, const double *means, const double *prec, const double *weights,
+                    const double *betas, double eta, const double *o, const double *v, double *t,
+                    double *d, double *z, double *nrm)
+{
+    gauss_t *g = (gauss_t *)malloc(sizeof(gauss_t) * (size_t)n);
+    load_gaussians(n, means, prec, weights, g);
+    for (int32_t i = 0; i < n; ++i) {
+        pair_t q;
+        pair_eval(&g[i], o, v, betas[0], betas[1], eta, &q);
+        t[i] = q.t;
+        d[i] = q.d;
+        z[i] = q.z;
+        for (int a = 0; a < 3; ++a) nrm[3 * i + a] = q.n[a];
+    }
+    free(g);
+}
+
+/* ----------------------------------------------------------------------------------- */
+/* Reverse mode                                                                        */
+/* ----------------------------------------------------------------------------------- */
+
+/* d(pi(p))/dp for world point p: J (2x3 in camera coords) times R. */
+static void project_jac(const double *e, const double *k, const double *p, double Jw[6])
+{
+    double q[3];
+    to_cam(e, p, q);
+    double J[6] = {k[0] / q[2], 0.0, -k[0] * q[0] / (q[2] * q[2]),
+                   0.0, k[1] / q[2], -k[1] * q[1] / (q[2] * q[2])};
+    for (int r = 0; r < 2; ++r)
+        for (int a = 0; a < 3; ++a)
+            Jw[r * 3 + a] = J[r * 3 + 0] * e[0 * 4 + a] + J[r * 3 + 1] * e[1 * 4 + a] + J[r * 3 + 2] * e[2 * 4 + a];
+}
+
+/* Per-Gaussian gradient accumulator: dL/dmu (3), dL/dA (9, full), dL/dlambda (1). */
+typedef struct {
+    double mu[3];
+    double A[9];
+    double lam;
+} gacc_t;
+
+static void ray_backward(const ctx_t *c, int64_t r, const pair_t *q, const double *wt, const ray_t *ry,
+                         double gd, double ga, const double *gnrm, const double *gfl, gacc_t *acc,
+                         double *gb)
+{
+    const double *o = c->orig + 3 * r, *v = c->dir + 3 * r;
+    (void)o;
+    /* flow = pi_B(p) - pi_A(p), p = o + t_f v */
+    double tf_bar = gd;
+    if (c->w2c_b && gfl) {
+        int64_t k = c->view[r];
+        double Jb[6], Ja[6];
+        project_jac(c->w2c_b + 12 * k, c->intr_b + 4 * k, ry->p, Jb);
+        project_jac(c->w2c_a + 12 * k, c->intr_a + 4 * k, ry->p, Ja);
+        double pbar[3];
+        for (int a = 0; a < 3; ++a)
+            pbar[a] = gfl[0] * (Jb[a] - Ja[a]) + gfl[1] * (Jb[3 + a] - Ja[3 + a]);
+        tf_bar += dot3(pbar, v);
+    }
+    /* alpha = 1 - exp(-D) */
+    double D_bar = ga * exp(-ry->D);
+    /* n_f = N / sqrt(N.N + eps) */
+    double N_bar[3] = {0.0, 0.0, 0.0};
+    if (gnrm) {
+        double s = dot3(ry->nf, gnrm);
+        for (int a = 0; a < 3; ++a) N_bar[a] = (gnrm[a] - ry->nf[a] * s) / ry->nN;
+    }
+    /* t_f = sum wt t, N = sum wt n, wt = softmax(z) */
+    double mean_wbar = 0.0;
+    for (int32_t i = 0; i < c->n; ++i) mean_wbar += wt[i] * (tf_bar * q[i].t + dot3(N_bar, q[i].n));
+    for (int32_t i = 0; i < c->n; ++i) {
+        const pair_t *pq = &q[i];
+        const gauss_t *g = &c->g[i];
+        gacc_t *ac = &acc[i];
+        double w_bar = tf_bar * pq->t + dot3(N_bar, pq->n);
+        double z_bar = wt[i] * (w_bar - mean_wbar);
+        double t_bar = wt[i] * tf_bar;
+        double n_bar[3] = {wt[i] * N_bar[0], wt[i] * N_bar[1], wt[i] * N_bar[2]};
+        double delta_bar = D_bar;
+        /* z = b1 d - (b2/eta) t */
+        double d_bar = c->b1 * z_bar;
+        t_bar += -(c->b2 / c->eta) * z_bar;
+        gb[0] += z_bar * pq->d;
+        gb[1] += -z_bar * pq->t / c->eta;
+        /* delta = exp(d) */
+        d_bar += delta_bar * pq->delta;
+        /* d = log(lambda) - m/2 */
+        ac->lam += d_bar / g->lam;
+        double m_bar = -0.5 * d_bar;
+        /* n = g / sqrt(g.g + eps), g = A x */
+        double sg = dot3(pq->n, n_bar);
+        double g_bar[3];
+        for (int a = 0; a < 3; ++a) g_bar[a] = (n_bar[a] - pq->n[a] * sg) / pq->gn;
+        /* m = x^T A x ; g = A x */
+        double x_bar[3], Ag[3];
+        mat3v(g->A, g_bar, Ag);
+        for (int a = 0; a < 3; ++a) x_bar[a] = 2.0 * m_bar * pq->Ax[a] + Ag[a];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) ac->A[a * 3 + b] += m_bar * pq->x[a] * pq->x[b] + g_bar[a] * pq->x[b];
+        /* x = o + t v - mu */
+        t_bar += dot3(v, x_bar);
+        for (int a = 0; a < 3; ++a) ac->mu[a] -= x_bar[a];
+        /* t = num / den, num = (mu - o)^T A v, den = v^T A v */
+        double num_bar = t_bar / pq->den;
+        double den_bar = -t_bar * pq->t / pq->den;
+        for (int a = 0; a < 3; ++a) ac->mu[a] += num_bar * pq->Av[a];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                ac->A[a * 3 + b] += num_bar * pq->mup[a] * v[b] + den_bar * v[a] * v[b];
+    }
+}
+
+/* Gradients of sum_r [gd.depth + ga.alpha + gn.normal + gf.flow] with respect to the
+ * means, packed precision factors, weights and (beta1, beta2).  Outputs are
+ * overwritten.  Cotangent pointers may be NULL (zero). */
+int fmbo_backward(int32_t n, const double *means, const double *prec, const double *weights,
+                  const double *betas, double eta, int64_t p, const double *orig, const double *dir,
+                  const int32_t *view, const double *w2c_a, const double *intr_a, const double *w2c_b,
+                  const double *intr_b, const double *g_depth, const double *g_alpha,
+                  const double *g_normal, const double *g_flow, double *g_means, double *g_prec,
+                  double *g_weights, double *g_betas, int n_threads)
+{
+    if (n < 1 || p < 0 || !means || !prec || !weights || !betas || !orig || !dir) return -1;
+    if (!g_means || !g_prec || !g_weights || !g_betas) return -1;
+    if (w2c_b && (!view || !w2c_a || !intr_a || !intr_b)) return -1;
+    gauss_t *g = (gauss_t *)malloc(sizeof(gauss_t) * (size_t)n);
+    if (!g) return -1;
+    load_gaussians(n, means, prec, weights, g);
+    ctx_t c = {n, g, betas[0], betas[1], eta, orig, dir, view, w2c_a, intr_a, w2c_b, intr_b};
+    int nt = nthreads_of(n_threads);
+    /* one accumulator per contiguous chunk of rays, summed in chunk order afterwards */
+    gacc_t *acc = (gacc_t *)calloc((size_t)nt * (size_t)n, sizeof(gacc_t));
+    double *gb = (double *)calloc((size_t)nt * 2, sizeof(double));
+#pragma omp parallel num_threads(nt)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        int64_t lo = p * tid / nt, hi = p * (tid + 1) / nt;
+        pair_t *q = (pair_t *)malloc(sizeof(pair_t) * (size_t)n);
+        double *wt = (double *)malloc(sizeof(double) * (size_t)n);
+        ray_t ry;
+        for (int64_t r = lo; r < hi; ++r) {
+            ray_forward(&c, r, q, wt, &ry);
+            ray_backward(&c, r, q, wt, &ry, g_depth ? g_depth[r] : 0.0, g_alpha ? g_alpha[r] : 0.0,
+                         g_normal ? g_normal + 3 * r : NULL, g_flow ? g_flow + 2 * r : NULL,
+                         acc + (size_t)tid * n, gb + 2 * tid);
+        }
+        free(q);
+        free(wt);
+    }
+    g_betas[0] = g_betas[1] = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        gacc_t s;
+        memset(&s, 0, sizeof s);
+        for (int k = 0; k < nt; ++k) {
+            const gacc_t *a = &acc[(size_t)k * n + i];
+            for (int j = 0; j < 3; ++j) s.mu[j] += a->mu[j];
+            for (int j = 0; j < 9; ++j) s.A[j] += a->A[j];
+            s.lam += a->lam;
+        }
+        for (int j = 0; j < 3; ++j) g_means[3 * (int64_t)i + j] = s.mu[j];
+        g_weights[i] = s.lam;
+        /* A = U^T U  =>  dL/dU = U (Abar + Abar^T); keep the upper-triangular entries */
+        double Bs[9], GU[9];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) Bs[a * 3 + b] = s.A[a * 3 + b] + s.A[b * 3 + a];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double t = 0.0;
+                for (int k = 0; k < 3; ++k) t += g[i].U[a * 3 + k] * Bs[k * 3 + b];
+                GU[a * 3 + b] = t;
+            }
+        double *gp = g_prec + 6 * (int64_t)i;
+        gp[0] = GU[0];
+        gp[1] = GU[1];
+        gp[2] = GU[2];
+        gp[3] = GU[4];
+        gp[4] = GU[5];
+        gp[5] = GU[8];
+    }
+    for (int k = 0; k < nt; ++k) {
+        g_betas[0] += gb[2 * k];
+        g_betas[1] += gb[2 * k + 1];
+    }
+    free(acc);
+    free(gb);
+    free(g);
+    return 0;
+}

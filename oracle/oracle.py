@@ -1,0 +1,223 @@
+"""ctypes front-end of the FP64 oracle (fmb_oracle.c).
+
+TEST INFRASTRUCTURE: used by the tests, the smoke check and the CPU-baseline leg
+of the benchmark only.  Inputs are the float32 values the GPU path consumes,
+upcast to float64; all arithmetic is double precision.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fmb_oracle.c")
+_LIB = os.path.join(_HERE, "libfmb_oracle.so")
+_lib = None
+
+
+def lib_path() -> str:
+    return _LIB
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+                        "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.POINTER(ctypes.c_int32)
+
+
+def _configure(lib):
+    lib.fmbo_version.restype = ctypes.c_int
+    lib.fmbo_pixel_rays.argtypes = [ctypes.c_int64, _I, _I, _I, _D, _D, _D, _D]
+    lib.fmbo_dir_rays.argtypes = [ctypes.c_int64, _I, _D, _D, _D, _D]
+    lib.fmbo_project.argtypes = [ctypes.c_int64, _I, _D, _D, _D, _D]
+    common = [ctypes.c_int32, _D, _D, _D, _D, ctypes.c_double, ctypes.c_int64, _D, _D, _I,
+              _D, _D, _D, _D]
+    lib.fmbo_render.argtypes = common + [_D, _D, _D, _D, ctypes.c_int]
+    lib.fmbo_render.restype = ctypes.c_int
+    lib.fmbo_backward.argtypes = common + [_D, _D, _D, _D, _D, _D, _D, _D, ctypes.c_int]
+    lib.fmbo_backward.restype = ctypes.c_int
+    lib.fmbo_ray_terms.argtypes = [ctypes.c_int32, _D, _D, _D, _D, ctypes.c_double, _D, _D,
+                                   _D, _D, _D, _D]
+    return lib
+
+
+def load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        _lib = _configure(ctypes.CDLL(_LIB))
+    return _lib
+
+
+def use_library(path):
+    """Route every oracle call through another build of fmb_oracle.c (a planted-mistake
+    copy in the mutation tests); returns the previous handle for `restore_library`."""
+    global _lib
+    prev = load()
+    _lib = _configure(ctypes.CDLL(path))
+    return prev
+
+
+def restore_library(prev):
+    global _lib
+    _lib = prev
+
+
+def _d(a) -> Optional[np.ndarray]:
+    if a is None:
+        return None
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _p(a, typ=_D):
+    return None if a is None else a.ctypes.data_as(typ)
+
+
+def _i32(a) -> Optional[np.ndarray]:
+    if a is None:
+        return None
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+@dataclass
+class OracleScene:
+    """Gaussians (float64 copies) and blend parameters."""
+    means: np.ndarray
+    prec: np.ndarray
+    weights: np.ndarray
+    betas: np.ndarray
+    eta: float = 1.0
+
+    @classmethod
+    def of(cls, means, prec, weights, betas, eta=1.0) -> "OracleScene":
+        return cls(_d(means).reshape(-1, 3), _d(prec).reshape(-1, 6), _d(weights).reshape(-1),
+                   _d(betas).reshape(2), float(eta))
+
+    @property
+    def n(self) -> int:
+        return self.means.shape[0]
+
+
+def pixel_rays(view, row, col, w2c, intr):
+    """Ray origins and unit directions [P,3] through pixel centres (float64)."""
+    lib = load()
+    view, row, col = _i32(view), _i32(row), _i32(col)
+    w2c, intr = _d(w2c).reshape(-1, 12), _d(intr).reshape(-1, 4)
+    p = view.shape[0]
+    o = np.empty((p, 3))
+    v = np.empty((p, 3))
+    lib.fmbo_pixel_rays(p, _p(view, _I), _p(row, _I), _p(col, _I), _p(w2c), _p(intr), _p(o), _p(v))
+    return o, v
+
+
+def dir_rays(view, dirs, w2c):
+    lib = load()
+    view = _i32(view)
+    dirs, w2c = _d(dirs).reshape(-1, 3), _d(w2c).reshape(-1, 12)
+    p = view.shape[0]
+    o = np.empty((p, 3))
+    v = np.empty((p, 3))
+    lib.fmbo_dir_rays(p, _p(view, _I), _p(dirs), _p(w2c), _p(o), _p(v))
+    return o, v
+
+
+def project(view, pts, w2c, intr):
+    lib = load()
+    view = _i32(view)
+    pts, w2c, intr = _d(pts).reshape(-1, 3), _d(w2c).reshape(-1, 12), _d(intr).reshape(-1, 4)
+    uv = np.empty((view.shape[0], 2))
+    lib.fmbo_project(view.shape[0], _p(view, _I), _p(pts), _p(w2c), _p(intr), _p(uv))
+    return uv
+
+
+def _cams(view, w2c_a, intr_a, w2c_b, intr_b):
+    view = _i32(view)
+    a = _d(w2c_a).reshape(-1, 12) if w2c_a is not None else None
+    ia = _d(intr_a).reshape(-1, 4) if intr_a is not None else None
+    b = _d(w2c_b).reshape(-1, 12) if w2c_b is not None else None
+    ib = _d(intr_b).reshape(-1, 4) if intr_b is not None else None
+    return view, a, ia, b, ib
+
+
+def render(scene: OracleScene, orig, dirs, view=None, w2c_a=None, intr_a=None, w2c_b=None,
+           intr_b=None, n_threads: int = 0):
+    """Forward pass over explicit rays; returns dict(depth, alpha, normal, flow)."""
+    lib = load()
+    orig, dirs = _d(orig).reshape(-1, 3), _d(dirs).reshape(-1, 3)
+    p = orig.shape[0]
+    view, a, ia, b, ib = _cams(view, w2c_a, intr_a, w2c_b, intr_b)
+    out = {"depth": np.empty(p), "alpha": np.empty(p), "normal": np.empty((p, 3)),
+           "flow": np.empty((p, 2)) if b is not None else None}
+    rc = lib.fmbo_render(scene.n, _p(scene.means), _p(scene.prec), _p(scene.weights),
+                         _p(scene.betas), scene.eta, p, _p(orig), _p(dirs), _p(view, _I), _p(a),
+                         _p(ia), _p(b), _p(ib), _p(out["depth"]), _p(out["alpha"]),
+                         _p(out["normal"]), _p(out["flow"]), int(n_threads))
+    if rc != 0:
+        raise ValueError("oracle render rejected its arguments")
+    return out
+
+
+def backward(scene: OracleScene, orig, dirs, cot: dict, view=None, w2c_a=None, intr_a=None,
+             w2c_b=None, intr_b=None, n_threads: int = 0):
+    """Gradients of sum(cot . outputs) w.r.t. means [N,3], prec [N,6], weights [N], betas [2]."""
+    lib = load()
+    orig, dirs = _d(orig).reshape(-1, 3), _d(dirs).reshape(-1, 3)
+    p = orig.shape[0]
+    view, a, ia, b, ib = _cams(view, w2c_a, intr_a, w2c_b, intr_b)
+    gd, ga = _d(cot.get("depth")), _d(cot.get("alpha"))
+    gn, gf = _d(cot.get("normal")), _d(cot.get("flow"))
+    n = scene.n
+    out = {"means": np.empty((n, 3)), "prec": np.empty((n, 6)), "weights": np.empty(n),
+           "betas": np.empty(2)}
+    rc = lib.fmbo_backward(n, _p(scene.means), _p(scene.prec), _p(scene.weights),
+                           _p(scene.betas), scene.eta, p, _p(orig), _p(dirs), _p(view, _I), _p(a),
+                           _p(ia), _p(b), _p(ib), _p(gd), _p(ga), _p(gn), _p(gf),
+                           _p(out["means"]), _p(out["prec"]), _p(out["weights"]), _p(out["betas"]),
+                           int(n_threads))
+    if rc != 0:
+        raise ValueError("oracle backward rejected its arguments")
+    return out
+
+
+def ray_terms(scene: OracleScene, o, v):
+    """Per-Gaussian (t_i, d_i, z_i, n_i) of one ray."""
+    lib = load()
+    o, v = _d(o).reshape(3), _d(v).reshape(3)
+    n = scene.n
+    t, d, z, nrm = np.empty(n), np.empty(n), np.empty(n), np.empty((n, 3))
+    lib.fmbo_ray_terms(n, _p(scene.means), _p(scene.prec), _p(scene.weights), _p(scene.betas),
+                       scene.eta, _p(o), _p(v), _p(t), _p(d), _p(z), _p(nrm))
+    return t, d, z, nrm
+
+
+def render_workload_view(scene, cams, betas, eta, rays=None, n_threads: int = 0, cot=None):
+    """Render (and optionally differentiate) pixel rays of a workload camera set.
+
+    `scene` has means/prec/weights (float32 arrays), `cams` has w2c, intr, hw and the
+    optional second pose.  `rays` selects global ray indices (default: all).
+    Returns (outputs, grads or None, (view, row, col)).
+    """
+    from workloads import pixel_indices  # input bookkeeping only
+    view, row, col = pixel_indices(cams, rays)
+    o, v = pixel_rays(view, row, col, cams.w2c, cams.intr)
+    sc = OracleScene.of(scene.means, scene.prec, scene.weights, betas, eta)
+    kw = dict(view=view, w2c_a=cams.w2c, intr_a=cams.intr, w2c_b=cams.w2c_b, intr_b=cams.intr_b,
+              n_threads=n_threads)
+    out = render(sc, o, v, **kw)
+    grads = backward(sc, o, v, cot, **kw) if cot is not None else None
+    return out, grads, (view, row, col)

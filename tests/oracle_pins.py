@@ -1,0 +1,507 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself.
+
+Each `pin_*` function raises AssertionError when the oracle disagrees with:
+closed forms (single isotropic Gaussian, two-Gaussian blend), a brute-force line
+search of the density along the ray built from the covariance (not from the
+factor U), the converted-3DGS alpha the paper's Interoperability section implies,
+algebraic identities of Eq. (8), invariances (permutation, scale with eta,
+rigid motion), the rotation homography and translation parallax of the flow,
+and central finite differences of the oracle's own forward pass for every
+gradient.  The same functions run against deliberately broken copies of the
+oracle (tests/test_oracle_mutants.py) to show that each plausible slip fails at
+least one pin.
+"""
+
+from __future__ import annotations
+
+import math
+import os
+
+import numpy as np
+
+import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+B1, B2 = 21.4, 3.14
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def _unit(x):
+    x = np.asarray(x, dtype=np.float64)
+    return x / np.linalg.norm(x, axis=-1, keepdims=True)
+
+
+def _rot(g):
+    q = _unit(g.standard_normal(4))
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def _cov_and_packed(g, smin=0.05, smax=0.3):
+    """Random covariance Sigma = R diag(s^2) R^T and the packed upper factor of Sigma^-1."""
+    r = _rot(g)
+    s = np.exp(g.uniform(math.log(smin), math.log(smax), 3))
+    cov = r @ np.diag(s ** 2) @ r.T
+    lo = np.linalg.cholesky(np.linalg.inv(cov))
+    u = lo.T
+    return cov, np.array([u[0, 0], u[0, 1], u[0, 2], u[1, 1], u[1, 2], u[2, 2]])
+
+
+def _packed_iso(s):
+    return np.array([1 / s, 0, 0, 1 / s, 0, 1 / s])
+
+
+def _scene(means, prec, weights, betas=(B1, B2), eta=1.0):
+    return O.OracleScene.of(np.asarray(means), np.asarray(prec), np.asarray(weights),
+                            np.asarray(betas, dtype=np.float64), eta)
+
+
+def _random_scene(g, n, spread=0.6, betas=(B1, B2), eta=1.0):
+    means = g.uniform(-spread, spread, (n, 3))
+    covs, prec = zip(*[_cov_and_packed(g) for _ in range(n)])
+    w = g.uniform(0.5, 1.5, n)
+    return _scene(means, np.array(prec), w, betas, eta), np.array(covs)
+
+
+def _rays_at(g, targets, o, jitter=0.15):
+    """Unit rays from origin o aimed near the given points."""
+    aim = targets + jitter * g.standard_normal(targets.shape)
+    return np.tile(o, (len(aim), 1)), _unit(aim - o)
+
+
+def _close(a, b, rtol, atol, what):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    err = np.abs(a - b)
+    lim = atol + rtol * np.abs(b)
+    assert np.all(err <= lim), f"{what}: max err {err.max():.3e} (worst excess {np.max(err - lim):.3e})"
+
+
+# ---------------------------------------------------------------------------------------
+# Eq. (2), (4), (8), (17): single Gaussians
+# ---------------------------------------------------------------------------------------
+
+def pin_isotropic_closed_form():
+    """U = I/s: t = (mu-o).v, m = |o+tv-mu|^2/s^2, n = (o+tv-mu)/|.|, alpha = 1-exp(-lam e^{-m/2})."""
+    g = _rng(11)
+    for _ in range(20):
+        mu = g.uniform(-1, 1, 3)
+        s = g.uniform(0.05, 0.5)
+        lam = g.uniform(0.2, 3.0)
+        o = g.uniform(-4, 4, 3)
+        v = _unit(mu + 0.3 * g.standard_normal(3) - o)
+        sc = _scene(mu[None], _packed_iso(s)[None], [lam])
+        t, d, z, nrm = O.ray_terms(sc, o, v)
+        t_ref = (mu - o) @ v
+        x = o + t_ref * v - mu
+        m_ref = (x @ x) / s ** 2
+        _close(t[0], t_ref, 1e-12, 1e-12, "isotropic t")
+        _close(d[0], math.log(lam) - 0.5 * m_ref, 1e-12, 1e-12, "isotropic d")
+        _close(z[0], B1 * d[0] - B2 * t_ref, 1e-12, 1e-12, "isotropic z")
+        _close(nrm[0], x / np.linalg.norm(x), 1e-9, 1e-9, "isotropic normal")
+        out = O.render(sc, o[None], v[None])
+        _close(out["depth"][0], t_ref, 1e-12, 1e-12, "N=1 depth")
+        _close(out["alpha"][0], 1 - math.exp(-lam * math.exp(-0.5 * m_ref)), 1e-12, 1e-14,
+               "N=1 alpha")
+        _close(out["normal"][0], x / np.linalg.norm(x), 1e-9, 1e-9, "N=1 normal")
+
+
+def _maha_cov(cov, mu, x):
+    dx = x - mu
+    return float(dx @ np.linalg.solve(cov, dx))
+
+
+def _golden_max(f, lo, hi, iters=200):
+    gr = (math.sqrt(5) - 1) / 2
+    a, b = lo, hi
+    c, d = b - gr * (b - a), a + gr * (b - a)
+    fc, fd = f(c), f(d)
+    for _ in range(iters):
+        if fc > fd:
+            b, d, fd = d, c, fc
+            c = b - gr * (b - a)
+            fc = f(c)
+        else:
+            a, c, fc = c, d, fd
+            d = a + gr * (b - a)
+            fd = f(d)
+    return 0.5 * (a + b)
+
+
+def pin_bruteforce_peak():
+    """Anisotropic Gaussians: the oracle's t_i and d_i equal a golden-section maximisation
+    of log(lambda) - 1/2 (x-mu)^T Sigma^-1 (x-mu) along the ray, with Sigma^-1 applied by
+    solving against the covariance; its n_i is the direction of the finite-difference
+    gradient of that Mahalanobis form at the peak (Eq. 17)."""
+    g = _rng(12)
+    for _ in range(25):
+        cov, prec = _cov_and_packed(g)
+        mu = g.uniform(-1, 1, 3)
+        lam = g.uniform(0.3, 2.0)
+        o = g.uniform(-4, 4, 3)
+        v = _unit(mu + 0.2 * g.standard_normal(3) - o)
+        sc = _scene(mu[None], prec[None], [lam])
+        t, d, _, nrm = O.ray_terms(sc, o, v)
+        f = lambda tt: math.log(lam) - 0.5 * _maha_cov(cov, mu, o + tt * v)  # noqa: E731
+        grid = np.linspace(-10, 10, 4001)
+        k = int(np.argmax([f(tt) for tt in grid]))
+        tb = _golden_max(f, grid[max(k - 1, 0)], grid[min(k + 1, len(grid) - 1)])
+        _close(t[0], tb, 0, 2e-7, "peak depth vs line search")
+        _close(d[0], f(tb), 1e-10, 1e-10, "peak log-density vs line search")
+        x = o + tb * v
+        h = 1e-6
+        grad = np.array([(_maha_cov(cov, mu, x + h * e) - _maha_cov(cov, mu, x - h * e)) / (2 * h)
+                         for e in np.eye(3)])
+        _close(nrm[0], _unit(grad), 0, 2e-6, "normal vs gradient of the Mahalanobis form")
+        # optimality: the normal is perpendicular to the ray at the peak
+        assert abs(nrm[0] @ v) < 1e-9, "n_i . v != 0 at the peak"
+
+
+def read_golden(name):
+    vals = {}
+    with open(os.path.join(GOLDEN, name)) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].strip()
+            if not line:
+                continue
+            k, val = line.split("=", 1)
+            vals[k.strip()] = val.strip()
+    return vals
+
+
+def pin_interop_alpha():
+    """A converted 3DGS Gaussian has lambda = log 80; a ray through its mean renders alpha = 79/80
+    whatever its shape (Interoperability section with Eq. 8)."""
+    gold = read_golden("interop_alpha.txt")
+    lam = eval(gold["lambda"], {"log": math.log})  # noqa: S307 (fixture is ours)
+    alpha_ref = eval(gold["alpha"], {})  # noqa: S307
+    g = _rng(13)
+    for _ in range(10):
+        _, prec = _cov_and_packed(g)
+        mu = g.uniform(-1, 1, 3)
+        o = g.uniform(-4, 4, 3)
+        v = _unit(mu - o)
+        out = O.render(_scene(mu[None], prec[None], [lam]), o[None], v[None])
+        _close(out["alpha"][0], alpha_ref, 0, 1e-12, "alpha through the mean")
+        _close(out["depth"][0], np.linalg.norm(mu - o), 1e-10, 1e-10, "depth at the mean")
+
+
+def pin_alpha_identities():
+    """Eq. (8): 1 - alpha(A u B) = (1 - alpha(A)) (1 - alpha(B)); alpha in [0,1]; monotone in lambda."""
+    g = _rng(14)
+    sc, _ = _random_scene(g, 6)
+    o = np.array([0.0, 0.0, -3.0])
+    orig, dirs = _rays_at(g, sc.means, o)
+    a_all = O.render(sc, orig, dirs)["alpha"]
+    part = lambda idx: _scene(sc.means[idx], sc.prec[idx], sc.weights[idx])  # noqa: E731
+    a1 = O.render(part([0, 1, 2]), orig, dirs)["alpha"]
+    a2 = O.render(part([3, 4, 5]), orig, dirs)["alpha"]
+    _close(1 - a_all, (1 - a1) * (1 - a2), 1e-12, 1e-15, "alpha union")
+    assert np.all((a_all >= 0) & (a_all <= 1))
+    heavier = _scene(sc.means, sc.prec, sc.weights * np.array([1, 1, 1.5, 1, 1, 1]))
+    assert np.all(O.render(heavier, orig, dirs)["alpha"] >= a_all)
+
+
+# ---------------------------------------------------------------------------------------
+# Eq. (3), (7): blending
+# ---------------------------------------------------------------------------------------
+
+def _single_terms(sc, i, orig, dirs):
+    one = _scene(sc.means[[i]], sc.prec[[i]], sc.weights[[i]], sc.betas, sc.eta)
+    out = O.render(one, orig, dirs)
+    dens = -np.log1p(-out["alpha"])      # sum of delta = delta_i for N = 1
+    return out["depth"], np.log(dens), out["normal"]
+
+
+def pin_two_gaussian_blend():
+    """N = 2: t_f = t_2 + (t_1 - t_2) sigma(z_1 - z_2), z_i = beta1 d_i - (beta2/eta) t_i, with t_i, d_i,
+    n_i taken from one-Gaussian renders; the blended normal is the same convex combination, normalised."""
+    g = _rng(15)
+    for eta in (1.0, 2.5):
+        sc, _ = _random_scene(g, 2, spread=0.3, eta=eta)
+        o = np.array([0.3, -0.2, -3.0])
+        orig, dirs = _rays_at(g, np.repeat(sc.means, 4, axis=0), o, jitter=0.05)
+        t1, d1, n1 = _single_terms(sc, 0, orig, dirs)
+        t2, d2, n2 = _single_terms(sc, 1, orig, dirs)
+        z1, z2 = B1 * d1 - B2 / eta * t1, B1 * d2 - B2 / eta * t2
+        s = 1 / (1 + np.exp(-(z1 - z2)))
+        out = O.render(sc, orig, dirs)
+        _close(out["depth"], t2 + (t1 - t2) * s, 1e-9, 1e-9, "two-Gaussian depth blend")
+        nb = s[:, None] * n1 + (1 - s)[:, None] * n2
+        _close(out["normal"], _unit(nb), 1e-7, 1e-7, "two-Gaussian normal blend")
+
+
+def pin_zero_betas_mean():
+    """beta1 = beta2 = 0 makes every weight equal: t_f is the plain mean of the t_i."""
+    g = _rng(16)
+    sc, _ = _random_scene(g, 7, betas=(0.0, 0.0))
+    o = np.array([0.1, 0.2, -3.0])
+    orig, dirs = _rays_at(g, sc.means, o)
+    out = O.render(sc, orig, dirs)
+    for r in range(len(orig)):
+        ts = [_single_terms(sc, i, orig[[r]], dirs[[r]])[0][0] for i in range(sc.n)]
+        _close(out["depth"][r], np.mean(ts), 1e-10, 1e-10, "zero-beta mean depth")
+
+
+def pin_permutation():
+    g = _rng(17)
+    sc, _ = _random_scene(g, 9)
+    o = np.array([0.0, 0.0, -3.0])
+    orig, dirs = _rays_at(g, sc.means, o)
+    ref = O.render(sc, orig, dirs)
+    perm = g.permutation(sc.n)
+    out = O.render(_scene(sc.means[perm], sc.prec[perm], sc.weights[perm]), orig, dirs)
+    for k in ("depth", "alpha", "normal"):
+        _close(out[k], ref[k], 1e-10, 1e-12, f"permutation {k}")
+
+
+# ---------------------------------------------------------------------------------------
+# Cameras, rays and flow (Sec. 5)
+# ---------------------------------------------------------------------------------------
+
+def _look_at(c, target=(0, 0, 0)):
+    z = _unit(np.asarray(target, float) - c)
+    u = np.array([0.0, 0.0, 1.0])
+    y = _unit(-u + (u @ z) * z)
+    x = np.cross(y, z)
+    r = np.stack([x, y, z])
+    return np.concatenate([r, (-r @ c)[:, None]], axis=1)
+
+
+def pin_pixel_ray_hand_case():
+    """Camera at (0,0,-3), R = I, fx = fy = 64, cx = cy = 32: pixel (row 0, col 63) has the
+    camera-frame direction (31.5/64, -31.5/64, 1), normalised."""
+    e = np.array([[1.0, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 3]])
+    k = np.array([64.0, 64.0, 32.0, 32.0])
+    o, v = O.pixel_rays([0], [0], [63], e[None], k[None])
+    _close(o[0], [0, 0, -3], 0, 1e-15, "camera centre")
+    _close(v[0], _unit([31.5 / 64, -31.5 / 64, 1.0]), 0, 1e-15, "pixel direction")
+    uv = O.project([0], (o[0] + 2.7 * v[0])[None], e[None], k[None])
+    _close(uv[0], [63.5, 0.5], 0, 1e-12, "projection of a point on the pixel ray")
+
+
+def pin_rays_reproject():
+    """Points on the ray of pixel (i, j) project back onto the pixel centre (j + 1/2, i + 1/2)."""
+    g = _rng(18)
+    e = np.stack([_look_at(3 * _unit(g.standard_normal(3))) for _ in range(3)])
+    k = np.array([[80.0, 90.0, 40.0, 30.0], [64, 64, 32, 32], [100, 100, 60, 45]])
+    view = np.repeat(np.arange(3), 5).astype(np.int32)
+    row = g.integers(0, 60, 15).astype(np.int32)
+    col = g.integers(0, 80, 15).astype(np.int32)
+    o, v = O.pixel_rays(view, row, col, e, k)
+    uv = O.project(view, o + g.uniform(0.5, 6, (15, 1)) * v, e, k)
+    _close(uv, np.stack([col + 0.5, row + 0.5], axis=1), 0, 1e-10, "reprojection")
+
+
+def _flow_setup(g, n=6):
+    sc, _ = _random_scene(g, n, spread=0.5)
+    c = np.array([0.4, -2.6, 1.2])
+    ea = _look_at(c)
+    k = np.array([60.0, 60.0, 40.0, 30.0])
+    view = np.zeros(24, dtype=np.int32)
+    row = g.integers(0, 60, 24).astype(np.int32)
+    col = g.integers(0, 80, 24).astype(np.int32)
+    o, v = O.pixel_rays(view, row, col, ea[None], k[None])
+    return sc, ea, k, view, row, col, o, v
+
+
+def pin_flow_equal_poses():
+    g = _rng(19)
+    sc, ea, k, view, row, col, o, v = _flow_setup(g)
+    out = O.render(sc, o, v, view=view, w2c_a=ea[None], intr_a=k[None], w2c_b=ea[None], intr_b=k[None])
+    assert np.all(out["flow"] == 0.0), "flow must vanish for equal poses"
+
+
+def pin_flow_rotation_homography():
+    """Second pose rotated about the camera centre (R_B = Q R_A, T_B = Q T_A): the flow of pixel
+    (i, j) is the homography K Q K^-1 (j+1/2, i+1/2, 1) minus the pixel, whatever the scene."""
+    g = _rng(20)
+    sc, ea, k, view, row, col, o, v = _flow_setup(g)
+    axis = _unit(g.standard_normal(3))
+    ang = math.radians(3.0)
+    kx = np.array([[0, -axis[2], axis[1]], [axis[2], 0, -axis[0]], [-axis[1], axis[0], 0]])
+    q = np.eye(3) + math.sin(ang) * kx + (1 - math.cos(ang)) * kx @ kx
+    eb = np.concatenate([q @ ea[:, :3], (q @ ea[:, 3])[:, None]], axis=1)
+    out = O.render(sc, o, v, view=view, w2c_a=ea[None], intr_a=k[None], w2c_b=eb[None], intr_b=k[None])
+    kk = np.array([[k[0], 0, k[2]], [0, k[1], k[3]], [0, 0, 1]])
+    hom = kk @ q @ np.linalg.inv(kk)
+    px = np.stack([col + 0.5, row + 0.5, np.ones(len(col))], axis=0)
+    hp = hom @ px
+    ref = (hp[:2] / hp[2]).T - px[:2].T
+    _close(out["flow"], ref, 1e-9, 1e-9, "rotation homography flow")
+
+
+def pin_flow_translation():
+    """Second pose translated by c (same R): q_B = t_f * d_cam/|d_cam| - R c, projected with K, minus
+    the pixel; d_cam = ((j+1/2-cx)/fx, (i+1/2-cy)/fy, 1) is the pixel's camera-frame direction."""
+    g = _rng(21)
+    sc, ea, k, view, row, col, o, v = _flow_setup(g)
+    shift = np.array([0.05, -0.08, 0.03])
+    eb = ea.copy()
+    eb[:, 3] = ea[:, 3] - ea[:, :3] @ shift
+    out = O.render(sc, o, v, view=view, w2c_a=ea[None], intr_a=k[None], w2c_b=eb[None], intr_b=k[None])
+    dc = np.stack([(col + 0.5 - k[2]) / k[0], (row + 0.5 - k[3]) / k[1], np.ones(len(col))], axis=1)
+    qa = out["depth"][:, None] * _unit(dc)
+    qb = qa - (ea[:, :3] @ shift)[None]
+    ref = np.stack([k[0] * qb[:, 0] / qb[:, 2] + k[2], k[1] * qb[:, 1] / qb[:, 2] + k[3]], axis=1)
+    ref -= np.stack([col + 0.5, row + 0.5], axis=1)
+    _close(out["flow"], ref, 1e-9, 1e-9, "translation flow")
+
+
+# ---------------------------------------------------------------------------------------
+# Invariances
+# ---------------------------------------------------------------------------------------
+
+def pin_scale_invariance():
+    """Scene and cameras scaled by k with eta scaled by k: depth scales by k; alpha, normals and
+    flow are unchanged (pins the role of eta in Eq. 7)."""
+    g = _rng(22)
+    sc, ea, kk, view, row, col, o, v = _flow_setup(g)
+    eb = _look_at(np.array([0.5, -2.5, 1.1]))
+    ref = O.render(sc, o, v, view=view, w2c_a=ea[None], intr_a=kk[None], w2c_b=eb[None], intr_b=kk[None])
+    s = 2.75
+    sc2 = _scene(sc.means * s, sc.prec / s, sc.weights, sc.betas, sc.eta * s)
+    ea2, eb2 = ea.copy(), eb.copy()
+    ea2[:, 3] *= s
+    eb2[:, 3] *= s
+    o2, v2 = O.pixel_rays(view, row, col, ea2[None], kk[None])
+    out = O.render(sc2, o2, v2, view=view, w2c_a=ea2[None], intr_a=kk[None], w2c_b=eb2[None],
+                   intr_b=kk[None])
+    _close(out["depth"], s * ref["depth"], 1e-9, 1e-9, "scaled depth")
+    _close(out["alpha"], ref["alpha"], 1e-9, 1e-12, "scaled alpha")
+    _close(out["normal"], ref["normal"], 1e-7, 1e-8, "scaled normal")
+    _close(out["flow"], ref["flow"], 1e-7, 1e-8, "scaled flow")
+
+
+def pin_rigid_motion():
+    """Moving the world rigidly (x -> Q x + b), with the cameras moved along, leaves depth, alpha
+    and flow unchanged and rotates the normals by Q."""
+    g = _rng(23)
+    sc, ea, kk, view, row, col, o, v = _flow_setup(g)
+    eb = _look_at(np.array([0.5, -2.5, 1.1]))
+    ref = O.render(sc, o, v, view=view, w2c_a=ea[None], intr_a=kk[None], w2c_b=eb[None], intr_b=kk[None])
+    q = _rot(g)
+    b = g.uniform(-1, 1, 3)
+    means2 = sc.means @ q.T + b
+    prec2 = []
+    for p in sc.prec:
+        u = np.array([[p[0], p[1], p[2]], [0, p[3], p[4]], [0, 0, p[5]]])
+        a2 = q @ (u.T @ u) @ q.T
+        u2 = np.linalg.cholesky(a2).T
+        prec2.append([u2[0, 0], u2[0, 1], u2[0, 2], u2[1, 1], u2[1, 2], u2[2, 2]])
+    sc2 = _scene(means2, np.array(prec2), sc.weights)
+
+    def move(e):
+        r, t = e[:, :3], e[:, 3]
+        return np.concatenate([r @ q.T, (t - r @ q.T @ b)[:, None]], axis=1)
+
+    ea2, eb2 = move(ea), move(eb)
+    o2, v2 = O.pixel_rays(view, row, col, ea2[None], kk[None])
+    out = O.render(sc2, o2, v2, view=view, w2c_a=ea2[None], intr_a=kk[None], w2c_b=eb2[None],
+                   intr_b=kk[None])
+    _close(out["depth"], ref["depth"], 1e-9, 1e-9, "moved depth")
+    _close(out["alpha"], ref["alpha"], 1e-9, 1e-12, "moved alpha")
+    _close(out["normal"], ref["normal"] @ q.T, 1e-7, 1e-8, "moved normal")
+    _close(out["flow"], ref["flow"], 1e-7, 1e-7, "moved flow")
+
+
+def pin_normals_geometry():
+    """Every n_i is perpendicular to the ray at its peak, so the blended unit normal is too."""
+    g = _rng(24)
+    sc, _ = _random_scene(g, 8)
+    o = np.array([0.2, 0.1, -3.0])
+    orig, dirs = _rays_at(g, sc.means, o)
+    out = O.render(sc, orig, dirs)
+    assert np.max(np.abs(np.sum(out["normal"] * dirs, axis=1))) < 1e-9
+    _close(np.linalg.norm(out["normal"], axis=1), 1.0, 0, 1e-12, "unit normals")
+
+
+# ---------------------------------------------------------------------------------------
+# Gradients
+# ---------------------------------------------------------------------------------------
+
+def _loss(sc, orig, dirs, cam, cot):
+    out = O.render(sc, orig, dirs, **cam)
+    s = float(cot["depth"] @ out["depth"] + cot["alpha"] @ out["alpha"])
+    s += float(np.sum(cot["normal"] * out["normal"]))
+    if out["flow"] is not None:
+        s += float(np.sum(cot["flow"] * out["flow"]))
+    return s
+
+
+def pin_gradients_fd():
+    """Central differences of the oracle forward (step 1e-6 max(1,|x|)) match its adjoint for
+    means, packed precision factors, weights and both betas, through every output."""
+    g = _rng(25)
+    sc, ea, kk, view, row, col, o, v = _flow_setup(g, n=4)
+    view, o, v = view[:8], o[:8], v[:8]
+    eb = _look_at(np.array([0.5, -2.5, 1.1]))
+    cam = dict(view=view, w2c_a=ea[None], intr_a=kk[None], w2c_b=eb[None], intr_b=kk[None])
+    p = len(o)
+    cot = {"depth": g.standard_normal(p), "alpha": g.standard_normal(p),
+           "normal": g.standard_normal((p, 3)), "flow": g.standard_normal((p, 2))}
+    for eta in (1.0, 1.7):
+        sc = _scene(sc.means, sc.prec, sc.weights, (B1 * 0.3, B2), eta)
+        an = O.backward(sc, o, v, cot, **cam)
+        for name in ("means", "prec", "weights", "betas"):
+            base = getattr(sc, name)
+            fd = np.zeros_like(base)
+            flat, fdf = base.reshape(-1), fd.reshape(-1)
+            for j in range(flat.size):
+                h = 1e-6 * max(1.0, abs(flat[j]))
+                x0 = flat[j]
+                flat[j] = x0 + h
+                fp = _loss(sc, o, v, cam, cot)
+                flat[j] = x0 - h
+                fm = _loss(sc, o, v, cam, cot)
+                flat[j] = x0
+                fdf[j] = (fp - fm) / (2 * h)
+            scale = max(1.0, float(np.max(np.abs(fd))))
+            _close(an[name], fd, 1e-6, 1e-6 * scale, f"FD gradient {name} (eta={eta})")
+
+
+def pin_isotropic_depth_gradient():
+    """One isotropic Gaussian: t_f = (mu - o).v, so d t_f / d mu = v."""
+    g = _rng(26)
+    mu = g.uniform(-1, 1, 3)
+    o = np.array([0.0, 0.0, -3.0])
+    v = _unit(mu + 0.1 * g.standard_normal(3) - o)
+    sc = _scene(mu[None], _packed_iso(0.2)[None], [0.8])
+    gr = O.backward(sc, o[None], v[None], {"depth": np.ones(1)})
+    _close(gr["means"][0], v, 1e-10, 1e-12, "d t_f / d mu")
+    _close(gr["betas"], 0.0, 0, 1e-12, "d t_f / d beta")
+
+
+def pin_two_gaussian_beta_gradient():
+    """N = 2: d t_f / d beta1 = (t1 - t2) s (1 - s) (d1 - d2) and
+    d t_f / d beta2 = -(t1 - t2)^2 s (1 - s) / eta, s = sigma(z1 - z2)."""
+    g = _rng(27)
+    eta = 1.3
+    sc, _ = _random_scene(g, 2, spread=0.3, eta=eta)
+    o = np.array([0.3, -0.2, -3.0])
+    orig, dirs = _rays_at(g, sc.means, o, jitter=0.03)
+    for r in range(len(orig)):
+        t1, d1, _ = _single_terms(sc, 0, orig[[r]], dirs[[r]])
+        t2, d2, _ = _single_terms(sc, 1, orig[[r]], dirs[[r]])
+        z1, z2 = B1 * d1[0] - B2 / eta * t1[0], B1 * d2[0] - B2 / eta * t2[0]
+        s = 1 / (1 + math.exp(-(z1 - z2)))
+        gr = O.backward(sc, orig[[r]], dirs[[r]], {"depth": np.ones(1)})
+        _close(gr["betas"][0], (t1[0] - t2[0]) * s * (1 - s) * (d1[0] - d2[0]), 1e-8, 1e-12,
+               "d t_f / d beta1")
+        _close(gr["betas"][1], -((t1[0] - t2[0]) ** 2) * s * (1 - s) / eta, 1e-8, 1e-12,
+               "d t_f / d beta2")
+
+
+ALL_PINS = [
+    pin_isotropic_closed_form, pin_bruteforce_peak, pin_interop_alpha, pin_alpha_identities,
+    pin_two_gaussian_blend, pin_zero_betas_mean, pin_permutation, pin_pixel_ray_hand_case,
+    pin_rays_reproject, pin_flow_equal_poses, pin_flow_rotation_homography, pin_flow_translation,
+    pin_scale_invariance, pin_rigid_motion, pin_normals_geometry, pin_gradients_fd,
+    pin_isotropic_depth_gradient, pin_two_gaussian_beta_gradient,
+]
