@@ -1,0 +1,241 @@
+"""Benchmark: ray x Gaussian pairs per second, forward + backward, batched vs plain.
+
+One step is one pass of the whole hot path over the uneven 16-scene batch
+(N ~ U{10..100} Gaussians, 4..32 views of 64^2 / 128^2 / 256^2 per scene, seed 3):
+forward render (depth, alpha, normals) of every pixel ray against every Gaussian of
+its scene, the loss cotangents (alpha-weighted L1 depth + BCE alpha against targets
+rendered from a perturbed copy of each scene), and the adjoint pass producing the
+gradients of means, precision factors, weights and both blend parameters.
+
+The timed value replays the batch's captured HIP graphs (persistent forward kernel,
+cotangents, persistent backward + finalize kernels).  The same steps are also timed
+with one plain launch sequence per scene (`plain_value`).  Kernel durations for the
+roofline come from HIP events recorded around each kernel launch on its stream.
+
+Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Algorithmic floating-point operations per (ray, Gaussian) pair, counted from the
+# method's per-pair formulas (add/sub/mul/compare = 1, fused multiply-add = 2, exp /
+# reciprocal / rsqrt = 1), excluding the backward's recomputation of the forward pair
+# terms and the extra precision steps (hi/lo mean, Newton refinement of the peak).
+FLOPS_FWD_NORMALS = 75     # intersection, density, weight, online blend, normal blend
+FLOPS_FWD_PLAIN = 53       # without the normal terms
+FLOPS_ADJ_NORMALS = 87     # adjoint with a normal cotangent
+FLOPS_ADJ_PLAIN = 60       # adjoint of depth/alpha/flow cotangents only
+# Executed per pair by the kernels (VALU arithmetic incl. recompute, refinement, hi/lo).
+FLOPS_FWD_EXEC = 97
+FLOPS_BWD_EXEC_PLAIN = 144
+PEAK_FP32 = 157.3e12       # MI355X FP32 vector peak (packed FP32 at 2.4 GHz x 256 CUs)
+PEAK_FP32_SCALAR = 78.6e12  # without packed FP32 issue
+PEAK_HBM = 8.0e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, seconds):
+    """Time the FP64 oracle (as it stands) on the same workload, scene after scene, until about
+    `seconds` of work (or the whole batch); returns pairs/s of forward + backward."""
+    import numpy as np
+
+    import oracle as O
+    threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16")), 16)
+    pairs = 0
+    used = []
+    g = np.random.Generator(np.random.PCG64(9))
+    t0 = time.perf_counter()
+    for i, (sc, cams) in enumerate(zip(w.scenes, w.cameras)):
+        cot = {"depth": g.standard_normal(cams.n_rays), "alpha": g.standard_normal(cams.n_rays),
+               "normal": None, "flow": None}
+        O.render_workload_view(sc, cams, w.betas, w.eta, n_threads=threads, cot=cot)
+        pairs += cams.n_rays * sc.n
+        used.append(i)
+        if time.perf_counter() - t0 > seconds:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": pairs / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 oracle forward (depth, alpha, normals) + backward (depth and alpha "
+                      f"cotangents), all rays of scenes {used[0]}..{used[-1]} of the 16-scene batch "
+                      f"({len(used)} of 16): {pairs} pairs in {dt:.2f} s on {threads} threads"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+              "(the renderer shards by rays or scenes across GPUs only by design)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2308_14737_amd as fmb
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = W.make_config("batch16")
+    S = len(w.scenes)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=dev).contiguous()  # noqa: E731
+
+    def batch_of(scenes):
+        means = t(np.concatenate([s.means for s in scenes]))
+        prec = t(np.concatenate([s.prec for s in scenes]))
+        weights = t(np.concatenate([s.weights for s in scenes]))
+        betas = t(np.tile(w.betas, (S, 1)))
+        cams = [fmb.Cameras.from_numpy(c.w2c, c.intr, c.hw, device=dev) for c in w.cameras]
+        return fmb.Batch(means, prec, weights, betas, [w.eta] * S, [s.n for s in scenes], cams), \
+            (means, prec, weights, betas)
+
+    batch, params = batch_of(w.scenes)
+    P = batch.n_rays
+    pairs = w.n_pairs
+    print(f"# workload batch16: S={S} rays={P} pairs/step={pairs}", file=sys.stderr, flush=True)
+
+    # targets from the perturbed scenes (setup, untimed)
+    tb, _ = batch_of(w.targets)
+    tgt = tb.forward(tb.alloc_outputs(normals=False))
+    torch.cuda.synchronize()
+    d_t, a_t = tgt["depth"].clone(), tgt["alpha"].clone()
+    del tb, tgt
+
+    outs = batch.alloc_outputs(normals=True)
+    grads = batch.alloc_grads()
+    cot = {"depth": torch.empty(P, device=dev), "alpha": torch.empty(P, device=dev),
+           "normal": None, "flow": None}
+
+    def cotangents(o):
+        # L = mean(alpha_t |depth - depth_t|) + mean(BCE(clamp(alpha), alpha_t)); one HIP kernel
+        fmb.loss_grad(o, d_t, a_t, cot=cot)
+
+    # eager warm-up builds the item lists; then tune the tile variants on this batch
+    batch.forward(outs)
+    cotangents(outs)
+    batch.backward(outs, cot, grads)
+    torch.cuda.synchronize()
+    if not args.no_autotune:
+        batch.autotune(outs, cot, grads)
+        torch.cuda.synchronize()
+
+    st = torch.cuda.Stream(dev)
+    torch.cuda.synchronize()
+    batch.capture(outs, cot, grads, st)
+
+    def step_graph():
+        batch.graph_launch(0, st)
+        with torch.cuda.stream(st):
+            cotangents(outs)
+        batch.graph_launch(1, st)
+
+    def timed(fn, k):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / k
+
+    for _ in range(args.warmup):
+        step_graph()
+    ms_graph = timed(step_graph, args.steps) * 1e3
+    print(f"# graph step {ms_graph:.3f} ms", file=sys.stderr, flush=True)
+
+    # same steps, eager persistent launches, with HIP-event kernel timing
+    def step_eager():
+        batch.forward(outs)
+        cotangents(outs)
+        batch.backward(outs, cot, grads)
+
+    fmb.timing_enable(True)
+    fmb.kernel_times(reset=True)
+    ms_eager = timed(step_eager, args.steps) * 1e3
+    kt = fmb.kernel_times(reset=True)
+    fmb.timing_enable(False)
+    fwd_ms = kt["fwd_ms"] / max(kt["n_fwd"], 1)
+    bwd_ms = kt["bwd_ms"] / max(kt["n_bwd"], 1)
+    fin_ms = kt["fin_ms"] / max(kt["n_fin"], 1)
+    print(f"# eager step {ms_eager:.3f} ms; kernels fwd {fwd_ms:.3f} bwd {bwd_ms:.3f} fin {fin_ms:.3f} ms",
+          file=sys.stderr, flush=True)
+
+    # plain: one launch sequence per scene
+    plain_ms = None
+    if not args.no_plain:
+        scenes = []
+        for i, (sc, cams) in enumerate(zip(w.scenes, w.cameras)):
+            g0, g1 = batch.gauss_off[i], batch.gauss_off[i + 1]
+            r0, r1 = batch.ray_off[i], batch.ray_off[i + 1]
+            s = fmb.Scene(params[0][g0:g1], params[1][g0:g1], params[2][g0:g1], params[3][i], w.eta,
+                          fmb.Cameras.from_numpy(cams.w2c, cams.intr, cams.hw, device=dev))
+            o = {"depth": outs["depth"][r0:r1], "alpha": outs["alpha"][r0:r1], "normal": outs["normal"][r0:r1],
+                 "stash": outs["stash"][r0:r1]}
+            gr = {"means": grads["means"][g0:g1], "prec": grads["prec"][g0:g1],
+                  "weights": grads["weights"][g0:g1], "betas": grads["betas"][i]}
+            scenes.append((s, o, gr, r0, r1))
+
+        def step_plain():
+            for s, o, gr, r0, r1 in scenes:
+                s.render(normals=True, out=o)
+            cotangents(outs)
+            for s, o, gr, r0, r1 in scenes:
+                s.backward(o, cot["depth"][r0:r1], cot["alpha"][r0:r1], None, None, grads=gr)
+
+        for _ in range(args.warmup):
+            step_plain()
+        plain_ms = timed(step_plain, args.steps) * 1e3
+        print(f"# plain step {plain_ms:.3f} ms", file=sys.stderr, flush=True)
+
+    value = pairs / (ms_graph * 1e-3)
+    # dominant kernel: the persistent backward (adjoint with recompute)
+    flops_bwd_launch = pairs * FLOPS_ADJ_PLAIN
+    achieved = flops_bwd_launch / (bwd_ms * 1e-3)
+    step_flops = pairs * (FLOPS_FWD_NORMALS + FLOPS_ADJ_PLAIN)
+    res = {
+        "metric": "ray x Gaussian pairs/s fwd+bwd (batched vs plain), % FP32 VALU peak",
+        "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_graph, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch16: 16 uneven scenes, N~U{10..100}, V~U{4..32}, 64^2/128^2/256^2, "
+                               "fwd (depth, alpha, normals) + bwd (L1 depth + BCE alpha), seed 3",
+                   "scenes": S, "rays": P, "pairs_per_step": pairs, "global_batch": P,
+                   "parallelism": "single GPU, persistent batched kernels in HIP graphs"},
+        "plain_value": (pairs / (plain_ms * 1e-3)) if plain_ms else None,
+        "plain_ms_per_step": plain_ms,
+        "batched_over_plain": (plain_ms / ms_graph) if plain_ms else None,
+        "eager_ms_per_step": ms_eager,
+        "fp32_peak_frac_step": step_flops / (ms_graph * 1e-3) / PEAK_FP32,
+        "kernel_ms": {"forward": fwd_ms, "backward": bwd_ms, "finalize": fin_ms},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
+                     "kernel": "bwd_kernel (persistent)", "flops_per_pair": FLOPS_ADJ_PLAIN,
+                     "executed_flops_per_pair": FLOPS_BWD_EXEC_PLAIN,
+                     "executed_frac": pairs * FLOPS_BWD_EXEC_PLAIN / (bwd_ms * 1e-3) / PEAK_FP32,
+                     "peak_scalar_fp32": PEAK_FP32_SCALAR / 1e12},
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,235 @@
+/*
+ * fmb.h -- C ABI of the MI355X (gfx950) sort-free Fuzzy Metaballs ray renderer.
+ *
+ * The renderer is the simplified two-parameter model of Keselman & Hebert,
+ * "Flexible Techniques for Differentiable Rendering with 3D Gaussians" (WACV 2024):
+ * every pixel ray meets every Gaussian at its peak density (Sec. 3.1, Eq. 2), the
+ * per-Gaussian depths and normals (Eq. 17) are blended without sorting by the
+ * two-parameter weights (Eq. 3 with Eq. 7), opacity follows Eq. (8), and per-pixel
+ * optical flow is the change of the blended point's projection between two camera
+ * poses (Sec. 5).  The backward pass returns the exact gradients of those outputs.
+ *
+ * Conventions shared by every call
+ *   Gaussian i   mean mu_i (3 floats); precision Sigma_i^-1 = U_i^T U_i with U_i upper
+ *                triangular, packed as (U00, U01, U02, U11, U12, U22) -- the paper's
+ *                "inverse root precision" (Sec. 3.1); weight lambda_i > 0, linear (the
+ *                kernels use log lambda_i, Eq. 2).
+ *   blend        betas = (beta1, beta2) of Eq. (7), on the device (they are
+ *                differentiated); eta > 0 is the shape scale of Eq. (7), a host value.
+ *   camera k     world-to-camera [R|T], row-major 3x4 (x_cam = R x_world + T), OpenCV
+ *                axes (x right, y down, z forward); intrinsics (fx, fy, cx, cy); image
+ *                H x W.  Pixel (row i, col j) has its centre at (j + 1/2, i + 1/2); its ray
+ *                starts at the camera centre and has unit direction R^T d / |d| with
+ *                d = ((j + 1/2 - cx)/fx, (i + 1/2 - cy)/fy, 1) (Sec. 5 camera model).
+ *   rays         ordered view-major, then row-major: ray index of (k, i, j) is
+ *                sum_{k'<k} H_k' W_k' + i W_k + j.  P is the total ray count.
+ *   outputs      depth[P] = blended peak distance t_f along the unit ray (Eq. 3);
+ *                alpha[P] (Eq. 8); normal[P,3] unit world-frame blended normal;
+ *                flow[P,2] = pi_B(p) - pi_A(p) in pixels, p = origin + t_f * direction;
+ *                stash[P,8] = per-ray softmax state the backward pass reads (opaque).
+ *
+ * Memory: every float/int pointer called "device" is HIP device memory owned by the
+ * caller; the library never frees it and reads/writes it only inside the calls.
+ * "host" pointers are read during the call only.  All buffers are dense, row-major
+ * and 4-byte aligned (16-byte aligned for stash).  All work is enqueued on the HIP
+ * stream given (NULL = the default stream) and is asynchronous: results are ready
+ * once that stream has been synchronised.
+ *
+ * Errors: every call returns FMB_OK (0) or a positive FMB_ERR_* code, never throws,
+ * and leaves a thread-local message for fmb_last_error().  Argument checks happen
+ * before any work is enqueued; a failed call enqueues nothing.
+ */
+#ifndef FMB_H
+#define FMB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FMB_ABI_VERSION 1
+
+enum fmb_status {
+    FMB_OK = 0,
+    FMB_ERR_INVALID_ARG = 1, /* null pointer, non-positive size, bad flag or value */
+    FMB_ERR_SHAPE = 2,       /* sizes inconsistent with the scene or cameras */
+    FMB_ERR_HIP = 3,         /* a HIP runtime call failed (message has hipGetErrorString) */
+    FMB_ERR_OOM = 4,         /* device workspace allocation failed */
+    FMB_ERR_CAPTURE = 5,     /* graph capture misuse (e.g. stream already capturing) */
+    FMB_ERR_STATE = 6        /* call order violated (e.g. render before set_cameras) */
+};
+
+typedef struct fmb_scene fmb_scene;
+typedef struct fmb_batch fmb_batch;
+
+/* ABI version of the loaded library (FMB_ABI_VERSION at build time). */
+int fmb_abi_version(void);
+
+/* Message of the last failed call on this thread ("" if none).  The pointer stays
+ * valid until the next fmb_* call on the same thread. */
+const char *fmb_last_error(void);
+
+/* ------------------------------------------------------------------------------ */
+/* Single scene                                                                   */
+/* ------------------------------------------------------------------------------ */
+
+/* Create a scene of n >= 1 Gaussians (representation of Sec. 3.1).
+ *   means   device [n,3]; prec device [n,6] packed upper U; weights device [n] (> 0);
+ *   betas   device [2] (beta1, beta2 of Eq. 7); eta host scalar > 0 (Eq. 7).
+ * The pointers are BORROWED: they must stay valid while the scene is used and may be
+ * updated in place between calls (each render/backward reads their current values).
+ * Errors: FMB_ERR_INVALID_ARG for n < 1, a NULL pointer, eta <= 0 or misaligned input;
+ * FMB_ERR_HIP / FMB_ERR_OOM if the small device descriptors cannot be created.
+ * Values are not inspected (use fmb_validate). */
+int fmb_scene_create(fmb_scene **out, int32_t n, const float *means, const float *prec,
+                     const float *weights, const float *betas, float eta);
+
+/* Point an existing scene at other parameter buffers of the same size n. */
+int fmb_scene_rebind(fmb_scene *scene, const float *means, const float *prec,
+                     const float *weights, const float *betas);
+
+/* Release the scene and its workspace.  NULL is accepted.  The caller must make sure
+ * no work using the scene is still running (synchronise its streams first). */
+int fmb_scene_destroy(fmb_scene *scene);
+
+/* Set the v >= 1 views the scene is rendered from (all poses passed to the renderer,
+ * Sec. 5).  w2c device [v,3,4]; intr device [v,4] (fx, fy, cx, cy); hw host [v,2]
+ * (H, W >= 1).  w2c_b / intr_b: device [v,3,4] / [v,4] second pose per view for the
+ * flow output, or both NULL (no flow).  Borrowed like the scene parameters.  Sizes the
+ * workspace (P = sum H W rays, at most 2^31 - 1).
+ * Errors: FMB_ERR_INVALID_ARG (NULL, v < 1, H or W < 1, only one of w2c_b/intr_b),
+ * FMB_ERR_SHAPE (P too large), FMB_ERR_OOM / FMB_ERR_HIP. */
+int fmb_set_cameras(fmb_scene *scene, int32_t v, const float *w2c, const float *intr,
+                    const int32_t *hw, const float *w2c_b, const float *intr_b);
+
+/* Number of rays P of the current cameras (0 before fmb_set_cameras). */
+int64_t fmb_num_rays(const fmb_scene *scene);
+
+/* Forward pass (Eq. 2, 4, 7, 3, 8, 17 and the flow of Sec. 5) for all P rays.
+ *   depth, alpha: device [P] (required); normal: device [P,3] or NULL (not computed:
+ *   the normal terms are skipped); flow: device [P,2] or NULL (required NULL when the
+ *   cameras have no second pose); stash: device [P,8], 16-byte aligned, required by
+ *   fmb_backward (may be NULL if no backward pass follows).
+ * Errors: FMB_ERR_STATE (no cameras), FMB_ERR_INVALID_ARG, FMB_ERR_HIP. */
+int fmb_render(fmb_scene *scene, float *depth, float *alpha, float *normal, float *flow,
+               float *stash, void *stream);
+
+/* Backward (adjoint) pass: gradients of  sum_r  g_depth[r] depth[r] + g_alpha[r] alpha[r]
+ * + g_normal[r].normal[r] + g_flow[r].flow[r]  with respect to the means, packed
+ * precision factors, weights and (beta1, beta2).  The per-pair terms are recomputed,
+ * never stored.  Cotangents are device arrays shaped like the outputs; any may be NULL
+ * (zero).  depth and stash are the forward outputs for the SAME parameter values.
+ * Gradients are device arrays g_means [n,3], g_prec [n,6], g_weights [n], g_betas [2],
+ * overwritten (not accumulated).  The result is deterministic (fixed reduction order).
+ * If normals were not rendered (normal == NULL in fmb_render) g_normal must be NULL.
+ * Errors: FMB_ERR_STATE, FMB_ERR_INVALID_ARG, FMB_ERR_HIP. */
+int fmb_backward(fmb_scene *scene, const float *g_depth, const float *g_alpha,
+                 const float *g_normal, const float *g_flow, const float *depth,
+                 const float *stash, float *g_means, float *g_prec, float *g_weights,
+                 float *g_betas, void *stream);
+
+/* ------------------------------------------------------------------------------ */
+/* Batch of independent scenes (uneven Gaussian counts, view counts, resolutions) */
+/* ------------------------------------------------------------------------------ */
+
+/* Create a batch of s >= 1 scenes rendered together by persistent kernels.
+ *   n_host   host [s]: Gaussians per scene (>= 1); their parameters are concatenated
+ *            scene after scene in means [sum n,3], prec [sum n,6], weights [sum n]
+ *            (device); betas device [s,2]; eta host [s] (> 0).
+ *   v_host   host [s]: views per scene (>= 1); cameras concatenated in the same order:
+ *            w2c device [sum v,3,4], intr device [sum v,4], hw host [sum v,2],
+ *            w2c_b / intr_b device or both NULL.
+ * Rays and outputs are concatenated scene after scene, each scene in the single-scene
+ * ray order.  All device pointers are borrowed (see fmb_scene_create).
+ * Errors: as fmb_scene_create and fmb_set_cameras. */
+int fmb_batch_create(fmb_batch **out, int32_t s, const int32_t *n_host, const int32_t *v_host,
+                     const float *means, const float *prec, const float *weights,
+                     const float *betas, const float *eta, const float *w2c, const float *intr,
+                     const int32_t *hw, const float *w2c_b, const float *intr_b);
+
+int fmb_batch_destroy(fmb_batch *batch);
+
+/* Total rays of the batch and the offset of scene `i`'s first ray / Gaussian. */
+int64_t fmb_batch_num_rays(const fmb_batch *batch);
+int64_t fmb_batch_ray_offset(const fmb_batch *batch, int32_t i);
+int64_t fmb_batch_gauss_offset(const fmb_batch *batch, int32_t i);
+
+/* Forward / backward over the whole batch with one persistent kernel each (work items
+ * of (scene, view, ray tile) pulled from a device queue, largest first).  Arguments as
+ * fmb_render / fmb_backward with concatenated arrays; g_betas is [s,2]. */
+int fmb_batch_forward(fmb_batch *batch, float *depth, float *alpha, float *normal, float *flow,
+                      float *stash, void *stream);
+int fmb_batch_backward(fmb_batch *batch, const float *g_depth, const float *g_alpha,
+                       const float *g_normal, const float *g_flow, const float *depth,
+                       const float *stash, float *g_means, float *g_prec, float *g_weights,
+                       float *g_betas, void *stream);
+
+/* Capture the batch's forward pass and its backward pass, with these buffers, into two
+ * HIP graphs held by the batch (replacing earlier ones).  `stream` must be a non-default
+ * stream that is not already capturing (FMB_ERR_CAPTURE).  The graphs read the borrowed
+ * parameters, cameras and cotangent buffers at replay time, so in-place updates between
+ * replays are seen (a loss can fill the cotangents between the two replays).
+ * fmb_batch_graph_launch replays the forward (which = 0), the backward (1) or both (2)
+ * on `stream`; FMB_ERR_STATE if nothing was captured.  Replays of one batch must not
+ * overlap (they share the batch's work counters and partial-gradient workspace). */
+int fmb_batch_capture(fmb_batch *batch, float *depth, float *alpha, float *normal, float *flow,
+                      float *stash, const float *g_depth, const float *g_alpha,
+                      const float *g_normal, const float *g_flow, float *g_means,
+                      float *g_prec, float *g_weights, float *g_betas, void *stream);
+int fmb_batch_graph_launch(fmb_batch *batch, int32_t which, void *stream);
+
+/* ------------------------------------------------------------------------------ */
+/* Tuning and diagnostics                                                         */
+/* ------------------------------------------------------------------------------ */
+
+/* Time the compiled tile configurations of the forward and backward kernels on the
+ * scene's (or batch's) current shapes and keep the fastest.  This runs real kernels on
+ * `stream` with the given buffers (outputs and gradients are overwritten); the backward
+ * variants are timed with the cotangents given (NULL ones stay NULL, as in the real
+ * step).  If cache_path is non-NULL the choice is read from / appended to that text
+ * file, keyed by device, kernel version, shapes and which outputs/cotangents are used.
+ * Exactly one of `scene` and `batch` is non-NULL. */
+int fmb_autotune(fmb_scene *scene, fmb_batch *batch, float *depth, float *alpha, float *normal,
+                 float *flow, float *stash, const float *g_depth, const float *g_alpha,
+                 const float *g_normal, const float *g_flow, float *g_means, float *g_prec,
+                 float *g_weights, float *g_betas, const char *cache_path, void *stream);
+
+/* Gradient of the reconstruction loss of Sec. 4 (Eq. 11-14) with respect to one render's
+ * outputs, averaged over its p rays (the cotangents fmb_backward takes):
+ *   L = 1/p sum_r [ -(a*_r log a_r + (1 - a*_r) log(1 - a_r))      a_r = clamp(alpha_r,
+ *                                                                   1e-6, 1 - 1e-6)  (Eq. 11)
+ *                 + w_depth a*_r |depth_r - depth*_r|               (mask-weighted L1)
+ *                 + w_flow  a*_r |flow_r - flow*_r|_q ]             (Eq. 13; q = 1: L1 of
+ *                                                                   the 2 components, q = 2:
+ *                                                                   squared L2)
+ * where a* = alpha_t is the target mask.  depth, alpha, depth_t, alpha_t: device [p];
+ * flow, flow_t: device [p,2] or NULL (no flow term; then g_flow must be NULL too).
+ * g_depth, g_alpha: device [p] (written); g_flow: device [p,2] or NULL.  The clamp passes
+ * the gradient where 1e-6 <= alpha <= 1 - 1e-6; |x|' is sign(x) (0 at 0).
+ * block_loss: device [ceil(p / 1024)] or NULL; if given, receives per-block partial
+ * sums of L (sum them for the loss; the order is fixed).
+ * Errors: FMB_ERR_INVALID_ARG (p < 1, NULL required pointer, flow_norm not 1 or 2). */
+int fmb_loss_grad(int64_t p, const float *depth, const float *alpha, const float *flow,
+                  const float *depth_t, const float *alpha_t, const float *flow_t, float w_depth,
+                  float w_flow, int32_t flow_norm, float *g_depth, float *g_alpha, float *g_flow,
+                  float *block_loss, void *stream);
+
+/* Check the scene's parameters on the device: writes to *bad_host a bit mask of
+ * 1 = non-finite value, 2 = weight <= 0, 4 = zero diagonal entry of U, 8 = beta not
+ * finite, and synchronises `stream`. */
+int fmb_validate(fmb_scene *scene, int32_t *bad_host, void *stream);
+
+/* Kernel timing: when enabled, each fmb_render / fmb_backward / fmb_batch_* call
+ * records HIP events around its main kernels on the call's stream (around the whole
+ * graph for fmb_batch_graph_launch; nothing while a stream is capturing), and
+ * fmb_kernel_times returns the summed milliseconds and launch counts
+ * (fwd_ms, bwd_ms, fin_ms, n_fwd, n_bwd, n_fin) since the last reset. */
+int fmb_timing_enable(int enable);
+int fmb_kernel_times(double *out6, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FMB_H */

@@ -221,3 +221,35 @@ def render_workload_view(scene, cams, betas, eta, rays=None, n_threads: int = 0,
     out = render(sc, o, v, **kw)
     grads = backward(sc, o, v, cot, **kw) if cot is not None else None
     return out, grads, (view, row, col)
+
+
+def loss_grad(depth, alpha, depth_t, alpha_t, flow=None, flow_t=None, w_depth=1.0, w_flow=1.0,
+              flow_norm=2):
+    """Reconstruction loss of Sec. 4 (Eq. 11-14) averaged over rays, and its gradient with respect
+    to the rendered depth, alpha and flow (float64, straight from the definition):
+      L = mean_r [ -(a* log a + (1 - a*) log(1 - a)),  a = clamp(alpha, 1e-6, 1 - 1e-6)   (Eq. 11)
+                   + w_depth a* |depth - depth*|                        (mask-weighted L1)
+                   + w_flow a* |flow - flow*|_1 or squared L2 ]          (Eq. 13)
+    The clamp passes the gradient where 1e-6 <= alpha <= 1 - 1e-6 (bounds as float32 values);
+    d|x|/dx = sign(x)."""
+    d, a = np.asarray(depth, np.float64), np.asarray(alpha, np.float64)
+    dt, at = np.asarray(depth_t, np.float64), np.asarray(alpha_t, np.float64)
+    p = d.shape[0]
+    # The clamp decides which rays pass a gradient; that decision is taken on the single-
+    # precision outputs against the single-precision bounds, as the renderer does.
+    lo, hi = float(np.float32(1e-6)), float(np.float32(1.0 - 1e-6))
+    ac = np.clip(a, lo, hi)
+    inside = (a >= lo) & (a <= hi)
+    per_ray = -(at * np.log(ac) + (1 - at) * np.log(1 - ac)) + w_depth * at * np.abs(d - dt)
+    g_alpha = np.where(inside, -(at / ac) + (1 - at) / (1 - ac), 0.0) / p
+    g_depth = w_depth * at * np.sign(d - dt) / p
+    g_flow = None
+    if flow is not None:
+        df = np.asarray(flow, np.float64) - np.asarray(flow_t, np.float64)
+        if flow_norm == 1:
+            per_ray = per_ray + w_flow * at * np.abs(df).sum(axis=1)
+            g_flow = w_flow * at[:, None] * np.sign(df) / p
+        else:
+            per_ray = per_ray + w_flow * at * (df * df).sum(axis=1)
+            g_flow = 2.0 * w_flow * at[:, None] * df / p
+    return float(per_ray.sum() / p), {"depth": g_depth, "alpha": g_alpha, "flow": g_flow}

@@ -1,0 +1,944 @@
+// fmb_api.cpp -- host side of the C ABI declared in include/fmb.h.
+//
+// Holds the scene / batch descriptors, cuts the work into items (see
+// fmb_internal.h), owns the device workspace (item lists, partial gradients, work
+// counters), launches the kernels of fmb_kernels.hip on the caller's stream, captures
+// HIP graphs for batches, times the tile variants (autotuner) and records kernel
+// timings with HIP events.  No exception crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "fmb.h"
+#include "fmb_internal.h"
+
+namespace fmb {
+int num_fwd_variants();
+int fwd_variant_rays(int v);
+int num_bwd_variants();
+int bwd_variant_rt(int v);
+int block_size();
+hipError_t launch_fwd(int variant, bool nrm, bool flw, bool per, int grid, hipStream_t st, const Params &P,
+                      const FwdOut &O, const FwdItem *items, int n, const int *order, int *counter);
+hipError_t launch_bwd(int variant, bool nrm, bool flw, bool per, int grid, hipStream_t st, const Params &P,
+                      const BwdIn &I, const BwdItem *items, int n, const int *order, int *counter,
+                      float *partial, float *bpart);
+hipError_t launch_fin(int n_tasks, int n_groups, hipStream_t st, const Params &P, const FinTask *tasks,
+                      const FinGroup *groups, const float *partial, const float *bpart, double *stage,
+                      double *stage_beta, float *g_means, float *g_prec, float *g_weights, float *g_betas);
+hipError_t launch_fill(int *p, int n, int value, hipStream_t st);
+hipError_t launch_loss(int p, const float *depth, const float *alpha, const float *flow, const float *depth_t,
+                       const float *alpha_t, const float *flow_t, float w_depth, float w_flow, int flow_norm,
+                       float *g_depth, float *g_alpha, float *g_flow, float *block_loss, hipStream_t st);
+hipError_t launch_validate(const Params &P, int n_total, int n_scenes, int *flags, hipStream_t st);
+hipError_t occupancy_fwd(int variant, bool nrm, bool flw, int *blocks_per_cu);
+hipError_t occupancy_bwd(int variant, bool nrm, bool flw, int *blocks_per_cu);
+}  // namespace fmb
+
+using namespace fmb;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(x)                                                                                 \
+    do {                                                                                          \
+        hipError_t e_ = (x);                                                                      \
+        if (e_ != hipSuccess)                                                                     \
+            return fail(e_ == hipErrorOutOfMemory ? FMB_ERR_OOM : FMB_ERR_HIP,                    \
+                        std::string(#x) + ": " + hipGetErrorString(e_));                          \
+    } while (0)
+
+#define CHECK_ARG(cond, msg)                                                                      \
+    do {                                                                                          \
+        if (!(cond)) return fail(FMB_ERR_INVALID_ARG, msg);                                       \
+    } while (0)
+
+bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    hipError_t ensure(size_t n)
+    {
+        if (n <= bytes && p) return hipSuccess;
+        release();
+        hipError_t e = hipMalloc(&p, n > 0 ? n : 16);
+        if (e == hipSuccess) bytes = n > 0 ? n : 16;
+        return e;
+    }
+    template <class T>
+    hipError_t upload(const std::vector<T> &v)
+    {
+        hipError_t e = ensure(v.size() * sizeof(T));
+        if (e != hipSuccess || v.empty()) return e;
+        return hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+    }
+    template <class T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+// ---------------------------------------------------------------------------------------
+// Kernel timing with HIP events
+// ---------------------------------------------------------------------------------------
+
+struct Timing {
+    std::mutex mu;
+    bool enabled = false;
+    struct Rec {
+        hipEvent_t a, b;
+        int kind;
+    };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    double ms[3] = {0, 0, 0};
+    long count[3] = {0, 0, 0};
+
+    hipEvent_t get()
+    {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    void drain()
+    {
+        for (auto &r : pending) {
+            float t = 0.0f;
+            if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+                ms[r.kind] += t;
+                count[r.kind] += 1;
+            }
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        pending.clear();
+    }
+};
+Timing g_timing;
+
+bool stream_capturing(hipStream_t st)
+{
+    hipStreamCaptureStatus s = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &s) != hipSuccess) return false;
+    return s != hipStreamCaptureStatusNone;
+}
+
+struct TimedSpan {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t st;
+    int kind;
+    bool on = false;
+    TimedSpan(hipStream_t s, int k) : st(s), kind(k)
+    {
+        if (!g_timing.enabled || stream_capturing(st)) return;
+        std::lock_guard<std::mutex> lk(g_timing.mu);
+        a = g_timing.get();
+        b = g_timing.get();
+        if (a && b && hipEventRecord(a, st) == hipSuccess) on = true;
+    }
+    void stop()
+    {
+        if (!on) return;
+        on = false;
+        if (hipEventRecord(b, st) != hipSuccess) return;
+        std::lock_guard<std::mutex> lk(g_timing.mu);
+        g_timing.pending.push_back({a, b, kind});
+        if (g_timing.pending.size() > 4096) g_timing.drain();
+    }
+};
+
+// ---------------------------------------------------------------------------------------
+// Job: S scenes, their views, work items and workspace
+// ---------------------------------------------------------------------------------------
+
+struct Job {
+    int S = 0, V = 0;
+    int n_total = 0;
+    int64_t P = 0;
+    std::vector<SceneRec> scenes;
+    std::vector<ViewRec> views;
+    std::vector<float> eta;
+    std::vector<int64_t> ray_off_scene;
+    Params prm{};
+    bool has_flow = false;
+    bool cams_set = false;
+    int device = 0, n_cu = 0;
+    DevBuf d_scenes, d_views, d_eta, d_counter;
+
+    // forward work
+    int fwd_variant = 1, fwd_built = -1, n_fitems = 0;
+    DevBuf d_fitems, d_forder;
+    // backward work
+    int bwd_variant = 2, bwd_built = -1, n_bitems = 0, n_tasks = 0, n_groups = 0;
+    DevBuf d_bitems, d_border, d_tasks, d_groups, d_partial, d_bpart, d_stage, d_stage_beta;
+    size_t partial_floats = 0;
+
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};  // captured forward, backward
+
+    void drop_graphs()
+    {
+        for (auto &g : gexec) {
+            if (g) (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+    }
+    ~Job() { drop_graphs(); }
+
+    int init_device()
+    {
+        HIPCHK(hipGetDevice(&device));
+        HIPCHK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device));
+        HIPCHK(d_counter.ensure(4 * sizeof(int)));
+        return FMB_OK;
+    }
+
+    int upload_descriptors()
+    {
+        HIPCHK(d_scenes.upload(scenes));
+        HIPCHK(d_views.upload(views));
+        HIPCHK(d_eta.upload(eta));
+        prm.scenes = d_scenes.as<SceneRec>();
+        prm.views = d_views.as<ViewRec>();
+        prm.eta = d_eta.as<float>();
+        return FMB_OK;
+    }
+
+    int build_fwd(int variant)
+    {
+        if (fwd_built == variant) return FMB_OK;
+        const int R = fwd_variant_rays(variant);
+        std::vector<FwdItem> items;
+        std::vector<double> cost;
+        for (int k = 0; k < V; ++k) {
+            const int hw = views[k].h * views[k].w;
+            const int n = scenes[views[k].scene].n;
+            for (int r0 = 0; r0 < hw; r0 += R) {
+                items.push_back({k, r0});
+                cost.push_back((double)n * std::min(R, hw - r0));
+            }
+        }
+        std::vector<int> order(items.size());
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+        HIPCHK(d_fitems.upload(items));
+        HIPCHK(d_forder.upload(order));
+        n_fitems = (int)items.size();
+        fwd_built = variant;
+        return FMB_OK;
+    }
+
+    static void chunking(int n, int block, int &gc, int &slots)
+    {
+        if (n >= block) {
+            gc = block;
+            slots = 1;
+            return;
+        }
+        double best = 0.0;
+        int bc = 1;
+        std::vector<double> util(9, 0.0);
+        for (int c = 1; c <= 8; ++c) {
+            const int g = (n + c - 1) / c;
+            const int sl = block / g;
+            util[c] = (double)n * sl / ((double)c * block);
+            best = std::max(best, util[c]);
+        }
+        for (int c = 1; c <= 8; ++c)
+            if (util[c] >= 0.92 * best) {
+                bc = c;
+                break;
+            }
+        gc = (n + bc - 1) / bc;
+        slots = block / gc;
+    }
+
+    int build_bwd(int variant)
+    {
+        if (bwd_built == variant) return FMB_OK;
+        const int RT = bwd_variant_rt(variant);
+        const int B = block_size();
+        std::vector<int> gcs(S), sls(S), spans(S);
+        for (int s = 0; s < S; ++s) {
+            chunking(scenes[s].n, B, gcs[s], sls[s]);
+            spans[s] = std::max(RT, ((64 * sls[s] + RT - 1) / RT) * RT);
+        }
+        // Span of rays per item, chosen per scene only (so a scene is cut the same way alone
+        // and inside a batch): about 64 rays per lane, at most 16384 and, where the scene is
+        // small, at least 2048 items.
+        for (int s = 0; s < S; ++s) {
+            const int chunks = (scenes[s].n + gcs[s] - 1) / gcs[s];
+            auto count_items = [&](int span) {
+                int64_t c = 0;
+                for (int k = scenes[s].view_off; k < scenes[s].view_off + scenes[s].n_views; ++k) {
+                    const int hw = views[k].h * views[k].w;
+                    c += (int64_t)chunks * ((hw + span - 1) / span);
+                }
+                return c;
+            };
+            while (count_items(spans[s]) > 16384 && spans[s] < (1 << 22)) spans[s] *= 2;
+            while (count_items(spans[s]) < 2048 && spans[s] > RT) spans[s] /= 2;
+        }
+        std::vector<BwdItem> items;
+        std::vector<FinTask> tasks;
+        std::vector<int> tasks_item_begin, tasks_item_end;
+        std::vector<double> cost;
+        size_t poff = 0;
+        for (int s = 0; s < S; ++s) {
+            const int gc = gcs[s], sl = sls[s], span = spans[s];
+            const int n = scenes[s].n;
+            for (int g0 = 0; g0 < n; g0 += gc) {
+                FinTask t{};
+                t.scene = s;
+                t.g0 = g0;
+                t.gc = std::min(gc, n - g0);
+                tasks_item_begin.push_back((int)items.size());
+                for (int k = scenes[s].view_off; k < scenes[s].view_off + scenes[s].n_views; ++k) {
+                    const int hw = views[k].h * views[k].w;
+                    for (int r0 = 0; r0 < hw; r0 += span) {
+                        BwdItem it{};
+                        it.view = k;
+                        it.ray0 = r0;
+                        it.span = span;
+                        it.g0 = g0;
+                        it.gc = gc;
+                        it.slots = sl;
+                        if (poff > (size_t)INT32_MAX - (size_t)gc * kPartial)
+                            return fail(FMB_ERR_SHAPE, "backward partial buffer exceeds 2^31 floats");
+                        it.poff = (int)poff;
+                        it.seq = (int)items.size();
+                        poff += (size_t)gc * kPartial;
+                        items.push_back(it);
+                        cost.push_back((double)t.gc * std::min(span, hw - r0));
+                    }
+                }
+                tasks_item_end.push_back((int)items.size());
+                t.beta = (g0 == 0) ? 1 : 0;
+                tasks.push_back(t);
+            }
+        }
+        // first-stage reduction groups: runs of kGroupItems items inside each chunk
+        std::vector<FinGroup> groups;
+        size_t soff = 0;
+        int scene_first_group = 0, cur_scene = -1;
+        for (auto &t : tasks) {
+            if (t.scene != cur_scene) {
+                cur_scene = t.scene;
+                scene_first_group = (int)groups.size();
+            }
+            const int ib = tasks_item_begin[&t - &tasks[0]], ie = tasks_item_end[&t - &tasks[0]];
+            t.group_begin = (int)groups.size();
+            // about sqrt(items) items per group so both stages sum similar counts
+            const int gsz = std::max(kGroupItems, (int)std::ceil(std::sqrt((double)(ie - ib))));
+            for (int a = ib; a < ie; a += gsz) {
+                FinGroup g{};
+                g.item_begin = a;
+                g.item_end = std::min(ie, a + gsz);
+                g.poff = items[a].poff;
+                g.nval = items[a].gc * kPartial;
+                g.soff = (int)soff;
+                soff += (size_t)g.nval;
+                groups.push_back(g);
+            }
+            t.group_end = (int)groups.size();
+            t.sgroup_begin = scene_first_group;
+        }
+        for (auto &t : tasks) {
+            int e = 0;
+            for (auto &u : tasks)
+                if (u.scene == t.scene) e = std::max(e, u.group_end);
+            t.sgroup_end = e;
+        }
+        std::vector<int> order(items.size());
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+        HIPCHK(d_bitems.upload(items));
+        HIPCHK(d_border.upload(order));
+        HIPCHK(d_tasks.upload(tasks));
+        HIPCHK(d_groups.upload(groups));
+        HIPCHK(d_stage.ensure(std::max<size_t>(soff, 1) * sizeof(double)));
+        HIPCHK(d_stage_beta.ensure(std::max<size_t>(2 * groups.size(), 2) * sizeof(double)));
+        n_groups = (int)groups.size();
+        HIPCHK(d_partial.ensure(std::max<size_t>(poff, 1) * sizeof(float)));
+        HIPCHK(d_bpart.ensure(std::max<size_t>(2 * items.size(), 2) * sizeof(float)));
+        partial_floats = poff;
+        n_bitems = (int)items.size();
+        n_tasks = (int)tasks.size();
+        bwd_built = variant;
+        return FMB_OK;
+    }
+
+    std::map<int, int> occ_f, occ_b;  // blocks per CU of the persistent kernels
+
+    int grid_fwd(bool nrm, bool flw, int &grid)
+    {
+        const int key = fwd_variant * 4 + (nrm ? 2 : 0) + (flw ? 1 : 0);
+        auto it = occ_f.find(key);
+        if (it == occ_f.end()) {
+            int o = 0;
+            HIPCHK(occupancy_fwd(fwd_variant, nrm, flw, &o));
+            it = occ_f.emplace(key, std::max(1, o)).first;
+        }
+        grid = std::max(1, std::min(n_fitems, it->second * n_cu));
+        return FMB_OK;
+    }
+
+    int grid_bwd(bool nrm, bool flw, int &grid)
+    {
+        const int key = bwd_variant * 4 + (nrm ? 2 : 0) + (flw ? 1 : 0);
+        auto it = occ_b.find(key);
+        if (it == occ_b.end()) {
+            int o = 0;
+            HIPCHK(occupancy_bwd(bwd_variant, nrm, flw, &o));
+            it = occ_b.emplace(key, std::max(1, o)).first;
+        }
+        grid = std::max(1, std::min(n_bitems, it->second * n_cu));
+        return FMB_OK;
+    }
+
+    int forward(float *depth, float *alpha, float *normal, float *flow, float *stash, bool persist,
+                hipStream_t st)
+    {
+        if (!cams_set) return fail(FMB_ERR_STATE, "render before cameras were set");
+        CHECK_ARG(depth && alpha, "depth and alpha outputs are required");
+        CHECK_ARG(!flow || has_flow, "flow output given but the cameras have no second pose");
+        CHECK_ARG(!stash || aligned(stash, 16), "stash must be 16-byte aligned");
+        int rc = build_fwd(fwd_variant);
+        if (rc) return rc;
+        FwdOut O{depth, alpha, normal, flow, stash};
+        const bool nrm = normal != nullptr, flw = flow != nullptr;
+        int grid = n_fitems;
+        if (persist) {
+            if ((rc = grid_fwd(nrm, flw, grid))) return rc;
+            HIPCHK(launch_fill(d_counter.as<int>(), 1, 0, st));
+        }
+        TimedSpan ts(st, 0);
+        HIPCHK(launch_fwd(fwd_variant, nrm, flw, persist, grid, st, prm, O, d_fitems.as<FwdItem>(), n_fitems,
+                          persist ? d_forder.as<int>() : nullptr, persist ? d_counter.as<int>() : nullptr));
+        ts.stop();
+        return FMB_OK;
+    }
+
+    int backward(const float *g_depth, const float *g_alpha, const float *g_normal, const float *g_flow,
+                 const float *depth, const float *stash, float *g_means, float *g_prec, float *g_weights,
+                 float *g_betas, bool persist, hipStream_t st)
+    {
+        if (!cams_set) return fail(FMB_ERR_STATE, "backward before cameras were set");
+        CHECK_ARG(depth && stash, "depth and stash from the forward pass are required");
+        CHECK_ARG(aligned(stash, 16), "stash must be 16-byte aligned");
+        CHECK_ARG(g_means && g_prec && g_weights && g_betas, "gradient outputs are required");
+        CHECK_ARG(!g_flow || has_flow, "flow cotangent given but the cameras have no second pose");
+        int rc = build_bwd(bwd_variant);
+        if (rc) return rc;
+        BwdIn I{g_depth, g_alpha, g_normal, g_flow, depth, stash};
+        const bool nrm = g_normal != nullptr, flw = g_flow != nullptr;
+        int grid = n_bitems;
+        if (persist) {
+            if ((rc = grid_bwd(nrm, flw, grid))) return rc;
+            HIPCHK(launch_fill(d_counter.as<int>() + 1, 1, 0, st));
+        }
+        TimedSpan tb(st, 1);
+        HIPCHK(launch_bwd(bwd_variant, nrm, flw, persist, grid, st, prm, I, d_bitems.as<BwdItem>(), n_bitems,
+                          persist ? d_border.as<int>() : nullptr, persist ? d_counter.as<int>() + 1 : nullptr,
+                          d_partial.as<float>(), d_bpart.as<float>()));
+        tb.stop();
+        TimedSpan tf(st, 2);
+        HIPCHK(launch_fin(n_tasks, n_groups, st, prm, d_tasks.as<FinTask>(), d_groups.as<FinGroup>(),
+                          d_partial.as<float>(), d_bpart.as<float>(), d_stage.as<double>(),
+                          d_stage_beta.as<double>(), g_means, g_prec, g_weights, g_betas));
+        tf.stop();
+        return FMB_OK;
+    }
+};
+
+int check_params(const float *means, const float *prec, const float *weights, const float *betas)
+{
+    CHECK_ARG(means && prec && weights && betas, "scene parameter pointers must be non-NULL");
+    CHECK_ARG(aligned(means, 4) && aligned(prec, 4) && aligned(weights, 4) && aligned(betas, 4),
+              "scene parameters must be 4-byte aligned");
+    return FMB_OK;
+}
+
+int check_cams(const float *w2c, const float *intr, const int32_t *hw, int v, const float *w2c_b,
+               const float *intr_b, int64_t &p)
+{
+    CHECK_ARG(w2c && intr && hw, "w2c, intr and hw must be non-NULL");
+    CHECK_ARG(aligned(w2c, 4) && aligned(intr, 4), "camera arrays must be 4-byte aligned");
+    CHECK_ARG((w2c_b == nullptr) == (intr_b == nullptr), "w2c_b and intr_b must both be given or both NULL");
+    p = 0;
+    for (int k = 0; k < v; ++k) {
+        CHECK_ARG(hw[2 * k] >= 1 && hw[2 * k + 1] >= 1, "image sizes must be >= 1");
+        p += (int64_t)hw[2 * k] * hw[2 * k + 1];
+    }
+    if (p > INT32_MAX) return fail(FMB_ERR_SHAPE, "more than 2^31-1 rays");
+    return FMB_OK;
+}
+
+}  // namespace
+
+struct fmb_scene {
+    Job job;
+    int32_t n = 0;
+};
+struct fmb_batch {
+    Job job;
+};
+
+extern "C" {
+
+int fmb_abi_version(void) { return FMB_ABI_VERSION; }
+
+const char *fmb_last_error(void) { return g_err.c_str(); }
+
+int fmb_scene_create(fmb_scene **out, int32_t n, const float *means, const float *prec, const float *weights,
+                     const float *betas, float eta)
+{
+    g_err.clear();
+    CHECK_ARG(out, "out must be non-NULL");
+    *out = nullptr;
+    CHECK_ARG(n >= 1, "n must be >= 1");
+    CHECK_ARG(std::isfinite(eta) && eta > 0.0f, "eta must be finite and > 0");
+    int rc = check_params(means, prec, weights, betas);
+    if (rc) return rc;
+    fmb_scene *s = new (std::nothrow) fmb_scene();
+    if (!s) return fail(FMB_ERR_OOM, "host allocation failed");
+    s->n = n;
+    Job &j = s->job;
+    j.S = 1;
+    j.n_total = n;
+    j.scenes.push_back({n, 0, 0, 0});
+    j.eta.push_back(eta);
+    j.prm.means = means;
+    j.prm.prec = prec;
+    j.prm.weights = weights;
+    j.prm.betas = betas;
+    if ((rc = j.init_device()) || (rc = j.upload_descriptors())) {
+        delete s;
+        return rc;
+    }
+    *out = s;
+    return FMB_OK;
+}
+
+int fmb_scene_rebind(fmb_scene *s, const float *means, const float *prec, const float *weights,
+                     const float *betas)
+{
+    g_err.clear();
+    CHECK_ARG(s, "scene must be non-NULL");
+    int rc = check_params(means, prec, weights, betas);
+    if (rc) return rc;
+    s->job.prm.means = means;
+    s->job.prm.prec = prec;
+    s->job.prm.weights = weights;
+    s->job.prm.betas = betas;
+    return FMB_OK;
+}
+
+int fmb_scene_destroy(fmb_scene *s)
+{
+    g_err.clear();
+    delete s;
+    return FMB_OK;
+}
+
+int fmb_set_cameras(fmb_scene *s, int32_t v, const float *w2c, const float *intr, const int32_t *hw,
+                    const float *w2c_b, const float *intr_b)
+{
+    g_err.clear();
+    CHECK_ARG(s, "scene must be non-NULL");
+    CHECK_ARG(v >= 1, "v must be >= 1");
+    int64_t p = 0;
+    int rc = check_cams(w2c, intr, hw, v, w2c_b, intr_b, p);
+    if (rc) return rc;
+    Job &j = s->job;
+    j.V = v;
+    j.P = p;
+    j.views.clear();
+    int64_t off = 0;
+    for (int k = 0; k < v; ++k) {
+        j.views.push_back({hw[2 * k], hw[2 * k + 1], (int32_t)off, 0});
+        off += (int64_t)hw[2 * k] * hw[2 * k + 1];
+    }
+    j.scenes[0].view_off = 0;
+    j.scenes[0].n_views = v;
+    j.prm.w2c = w2c;
+    j.prm.intr = intr;
+    j.prm.w2c_b = w2c_b;
+    j.prm.intr_b = intr_b;
+    j.has_flow = w2c_b != nullptr;
+    j.fwd_built = j.bwd_built = -1;
+    j.cams_set = false;
+    if ((rc = j.upload_descriptors())) return rc;
+    j.cams_set = true;
+    return FMB_OK;
+}
+
+int64_t fmb_num_rays(const fmb_scene *s) { return (s && s->job.cams_set) ? s->job.P : 0; }
+
+int fmb_render(fmb_scene *s, float *depth, float *alpha, float *normal, float *flow, float *stash, void *stream)
+{
+    g_err.clear();
+    CHECK_ARG(s, "scene must be non-NULL");
+    return s->job.forward(depth, alpha, normal, flow, stash, false, (hipStream_t)stream);
+}
+
+int fmb_backward(fmb_scene *s, const float *g_depth, const float *g_alpha, const float *g_normal,
+                 const float *g_flow, const float *depth, const float *stash, float *g_means, float *g_prec,
+                 float *g_weights, float *g_betas, void *stream)
+{
+    g_err.clear();
+    CHECK_ARG(s, "scene must be non-NULL");
+    return s->job.backward(g_depth, g_alpha, g_normal, g_flow, depth, stash, g_means, g_prec, g_weights,
+                           g_betas, false, (hipStream_t)stream);
+}
+
+int fmb_batch_create(fmb_batch **out, int32_t s, const int32_t *n_host, const int32_t *v_host, const float *means,
+                     const float *prec, const float *weights, const float *betas, const float *eta,
+                     const float *w2c, const float *intr, const int32_t *hw, const float *w2c_b,
+                     const float *intr_b)
+{
+    g_err.clear();
+    CHECK_ARG(out, "out must be non-NULL");
+    *out = nullptr;
+    CHECK_ARG(s >= 1, "s must be >= 1");
+    CHECK_ARG(n_host && v_host && eta, "n_host, v_host and eta must be non-NULL");
+    int rc = check_params(means, prec, weights, betas);
+    if (rc) return rc;
+    int64_t n_total = 0, v_total = 0;
+    for (int i = 0; i < s; ++i) {
+        CHECK_ARG(n_host[i] >= 1 && v_host[i] >= 1, "every scene needs >= 1 Gaussian and >= 1 view");
+        CHECK_ARG(std::isfinite(eta[i]) && eta[i] > 0.0f, "eta must be finite and > 0");
+        n_total += n_host[i];
+        v_total += v_host[i];
+    }
+    if (n_total > INT32_MAX / 8 || v_total > INT32_MAX / 16) return fail(FMB_ERR_SHAPE, "batch too large");
+    int64_t p = 0;
+    if ((rc = check_cams(w2c, intr, hw, (int)v_total, w2c_b, intr_b, p))) return rc;
+    fmb_batch *b = new (std::nothrow) fmb_batch();
+    if (!b) return fail(FMB_ERR_OOM, "host allocation failed");
+    Job &j = b->job;
+    j.S = s;
+    j.V = (int)v_total;
+    j.P = p;
+    j.n_total = (int)n_total;
+    int goff = 0, voff = 0;
+    int64_t roff = 0;
+    for (int i = 0; i < s; ++i) {
+        j.scenes.push_back({n_host[i], goff, voff, v_host[i]});
+        j.eta.push_back(eta[i]);
+        j.ray_off_scene.push_back(roff);
+        for (int k = 0; k < v_host[i]; ++k) {
+            const int kk = voff + k;
+            j.views.push_back({hw[2 * kk], hw[2 * kk + 1], (int32_t)roff, i});
+            roff += (int64_t)hw[2 * kk] * hw[2 * kk + 1];
+        }
+        goff += n_host[i];
+        voff += v_host[i];
+    }
+    j.ray_off_scene.push_back(roff);
+    j.prm.means = means;
+    j.prm.prec = prec;
+    j.prm.weights = weights;
+    j.prm.betas = betas;
+    j.prm.w2c = w2c;
+    j.prm.intr = intr;
+    j.prm.w2c_b = w2c_b;
+    j.prm.intr_b = intr_b;
+    j.has_flow = w2c_b != nullptr;
+    if ((rc = j.init_device()) || (rc = j.upload_descriptors())) {
+        delete b;
+        return rc;
+    }
+    j.cams_set = true;
+    *out = b;
+    return FMB_OK;
+}
+
+int fmb_batch_destroy(fmb_batch *b)
+{
+    g_err.clear();
+    delete b;
+    return FMB_OK;
+}
+
+int64_t fmb_batch_num_rays(const fmb_batch *b) { return b ? b->job.P : 0; }
+
+int64_t fmb_batch_ray_offset(const fmb_batch *b, int32_t i)
+{
+    if (!b || i < 0 || i > b->job.S) return -1;
+    return b->job.ray_off_scene[i];
+}
+
+int64_t fmb_batch_gauss_offset(const fmb_batch *b, int32_t i)
+{
+    if (!b || i < 0 || i > b->job.S) return -1;
+    return i == b->job.S ? b->job.n_total : b->job.scenes[i].gauss_off;
+}
+
+int fmb_batch_forward(fmb_batch *b, float *depth, float *alpha, float *normal, float *flow, float *stash,
+                      void *stream)
+{
+    g_err.clear();
+    CHECK_ARG(b, "batch must be non-NULL");
+    return b->job.forward(depth, alpha, normal, flow, stash, true, (hipStream_t)stream);
+}
+
+int fmb_batch_backward(fmb_batch *b, const float *g_depth, const float *g_alpha, const float *g_normal,
+                       const float *g_flow, const float *depth, const float *stash, float *g_means, float *g_prec,
+                       float *g_weights, float *g_betas, void *stream)
+{
+    g_err.clear();
+    CHECK_ARG(b, "batch must be non-NULL");
+    return b->job.backward(g_depth, g_alpha, g_normal, g_flow, depth, stash, g_means, g_prec, g_weights, g_betas,
+                           true, (hipStream_t)stream);
+}
+
+int fmb_batch_capture(fmb_batch *b, float *depth, float *alpha, float *normal, float *flow, float *stash,
+                      const float *g_depth, const float *g_alpha, const float *g_normal, const float *g_flow,
+                      float *g_means, float *g_prec, float *g_weights, float *g_betas, void *stream)
+{
+    g_err.clear();
+    CHECK_ARG(b, "batch must be non-NULL");
+    CHECK_ARG(stash, "capture needs the stash buffer");
+    hipStream_t st = (hipStream_t)stream;
+    if (st == nullptr) return fail(FMB_ERR_CAPTURE, "graph capture needs a non-default stream");
+    if (stream_capturing(st)) return fail(FMB_ERR_CAPTURE, "stream is already capturing");
+    Job &j = b->job;
+    // item lists and occupancy are prepared outside the capture (they use synchronous copies)
+    int rc = j.build_fwd(j.fwd_variant);
+    int gdummy = 0;
+    if (!rc) rc = j.build_bwd(j.bwd_variant);
+    if (!rc) rc = j.grid_fwd(normal != nullptr, flow != nullptr, gdummy);
+    if (!rc) rc = j.grid_bwd(g_normal != nullptr, g_flow != nullptr, gdummy);
+    if (rc) return rc;
+    j.drop_graphs();
+    for (int which = 0; which < 2; ++which) {
+        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        int r = which == 0 ? j.forward(depth, alpha, normal, flow, stash, true, st)
+                           : j.backward(g_depth, g_alpha, g_normal, g_flow, depth, stash, g_means, g_prec,
+                                        g_weights, g_betas, true, st);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(st, &g);
+        if (r) {
+            if (g) (void)hipGraphDestroy(g);
+            j.drop_graphs();
+            return r;
+        }
+        if (e != hipSuccess) {
+            j.drop_graphs();
+            return fail(FMB_ERR_CAPTURE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        }
+        hipError_t ei = hipGraphInstantiate(&j.gexec[which], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            j.drop_graphs();
+            return fail(FMB_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+        }
+    }
+    return FMB_OK;
+}
+
+int fmb_batch_graph_launch(fmb_batch *b, int32_t which, void *stream)
+{
+    g_err.clear();
+    CHECK_ARG(b, "batch must be non-NULL");
+    CHECK_ARG(which >= 0 && which <= 2, "which must be 0 (forward), 1 (backward) or 2 (both)");
+    Job &j = b->job;
+    if (!j.gexec[0] || !j.gexec[1]) return fail(FMB_ERR_STATE, "no captured graph");
+    hipStream_t st = (hipStream_t)stream;
+    if (which != 1) {
+        TimedSpan t(st, 0);
+        HIPCHK(hipGraphLaunch(j.gexec[0], st));
+        t.stop();
+    }
+    if (which != 0) {
+        TimedSpan t(st, 1);
+        HIPCHK(hipGraphLaunch(j.gexec[1], st));
+        t.stop();
+    }
+    return FMB_OK;
+}
+
+int fmb_validate(fmb_scene *s, int32_t *bad_host, void *stream)
+{
+    g_err.clear();
+    CHECK_ARG(s && bad_host, "scene and bad_host must be non-NULL");
+    hipStream_t st = (hipStream_t)stream;
+    Job &j = s->job;
+    int rc = FMB_OK;
+    HIPCHK(launch_fill(j.d_counter.as<int>() + 2, 1, 0, st));
+    HIPCHK(launch_validate(j.prm, j.n_total, j.S, j.d_counter.as<int>() + 2, st));
+    int flags = 0;
+    HIPCHK(hipMemcpyAsync(&flags, j.d_counter.as<int>() + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *bad_host = flags;
+    return rc;
+}
+
+int fmb_timing_enable(int enable)
+{
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    g_timing.enabled = enable != 0;
+    return FMB_OK;
+}
+
+int fmb_kernel_times(double *out6, int reset)
+{
+    g_err.clear();
+    CHECK_ARG(out6, "out6 must be non-NULL");
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    g_timing.drain();
+    for (int k = 0; k < 3; ++k) {
+        out6[k] = g_timing.ms[k];
+        out6[3 + k] = (double)g_timing.count[k];
+    }
+    if (reset) {
+        for (int k = 0; k < 3; ++k) {
+            g_timing.ms[k] = 0.0;
+            g_timing.count[k] = 0;
+        }
+    }
+    return FMB_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// Autotuner: time every (forward variant) x (backward variant) on the real shapes.
+// ---------------------------------------------------------------------------------------
+
+static std::string tune_key(const Job &j, bool nrm, bool flw, int cot_mask)
+{
+    hipDeviceProp_t prop{};
+    (void)hipGetDeviceProperties(&prop, j.device);
+    std::ostringstream k;
+    k << prop.gcnArchName << ":cu" << j.n_cu << ":v2:S" << j.S << ":V" << j.V << ":P" << j.P << ":N" << j.n_total
+      << ":nrm" << nrm << ":flw" << flw << ":cot" << cot_mask;
+    return k.str();
+}
+
+int fmb_autotune(fmb_scene *s, fmb_batch *b, float *depth, float *alpha, float *normal, float *flow, float *stash,
+                 const float *g_depth, const float *g_alpha, const float *g_normal, const float *g_flow,
+                 float *g_means, float *g_prec, float *g_weights, float *g_betas, const char *cache_path,
+                 void *stream)
+{
+    g_err.clear();
+    CHECK_ARG((s != nullptr) != (b != nullptr), "exactly one of scene and batch must be given");
+    CHECK_ARG(depth && alpha && stash && g_means && g_prec && g_weights && g_betas, "buffers are required");
+    Job &j = s ? s->job : b->job;
+    const bool persist = b != nullptr;
+    hipStream_t st = (hipStream_t)stream;
+    if (!j.cams_set) return fail(FMB_ERR_STATE, "autotune before cameras were set");
+    const bool nrm = normal != nullptr, flw = flow != nullptr;
+    const int cot_mask = (g_depth ? 1 : 0) | (g_alpha ? 2 : 0) | (g_normal ? 4 : 0) | (g_flow ? 8 : 0);
+    const std::string key = tune_key(j, nrm, flw, cot_mask);
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string line;
+        while (std::getline(in, line)) {
+            std::istringstream ls(line);
+            std::string k;
+            int fv = -1, bv = -1;
+            if (ls >> k >> fv >> bv && k == key && fv >= 0 && fv < num_fwd_variants() && bv >= 0 &&
+                bv < num_bwd_variants()) {
+                j.fwd_variant = fv;
+                j.bwd_variant = bv;
+                return FMB_OK;
+            }
+        }
+    }
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    auto time_it = [&](auto &&fn, float &ms) -> int {
+        int rc = fn();
+        if (rc) return rc;
+        HIPCHK(hipEventRecord(e0, st));
+        for (int r = 0; r < 3; ++r)
+            if ((rc = fn())) return rc;
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        return FMB_OK;
+    };
+    int rc = FMB_OK;
+    float best_f = 1e30f, best_b = 1e30f;
+    int bf = j.fwd_variant, bb = j.bwd_variant;
+    for (int v = 0; v < num_fwd_variants() && !rc; ++v) {
+        j.fwd_variant = v;
+        float ms = 0.0f;
+        rc = time_it([&]() { return j.forward(depth, alpha, normal, flow, stash, persist, st); }, ms);
+        if (!rc && ms < best_f) {
+            best_f = ms;
+            bf = v;
+        }
+    }
+    j.fwd_variant = bf;
+    if (!rc) rc = j.forward(depth, alpha, normal, flow, stash, persist, st);
+    for (int v = 0; v < num_bwd_variants() && !rc; ++v) {
+        j.bwd_variant = v;
+        float ms = 0.0f;
+        rc = time_it([&]() {
+            return j.backward(g_depth, g_alpha, g_normal, g_flow, depth, stash, g_means, g_prec, g_weights, g_betas,
+                              persist, st);
+        }, ms);
+        if (!rc && ms < best_b) {
+            best_b = ms;
+            bb = v;
+        }
+    }
+    j.bwd_variant = bb;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if (cache_path) {
+        std::ofstream outf(cache_path, std::ios::app);
+        if (outf) outf << key << " " << bf << " " << bb << "\n";
+    }
+    return FMB_OK;
+}
+
+int fmb_loss_grad(int64_t p, const float *depth, const float *alpha, const float *flow, const float *depth_t,
+                  const float *alpha_t, const float *flow_t, float w_depth, float w_flow, int32_t flow_norm,
+                  float *g_depth, float *g_alpha, float *g_flow, float *block_loss, void *stream)
+{
+    g_err.clear();
+    CHECK_ARG(p >= 1 && p <= INT32_MAX, "p must be in [1, 2^31)");
+    CHECK_ARG(depth && alpha && depth_t && alpha_t && g_depth && g_alpha, "required pointer is NULL");
+    CHECK_ARG((flow == nullptr) == (flow_t == nullptr) && (flow == nullptr) == (g_flow == nullptr),
+              "flow, flow_t and g_flow must all be given or all be NULL");
+    CHECK_ARG(flow_norm == 1 || flow_norm == 2, "flow_norm must be 1 or 2");
+    HIPCHK(launch_loss((int)p, depth, alpha, flow, depth_t, alpha_t, flow_t, w_depth, w_flow, flow_norm, g_depth,
+                       g_alpha, g_flow, block_loss, (hipStream_t)stream));
+    return FMB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+// fmb_internal.h -- descriptors shared by the host library and the gfx950 kernels.
+//
+// A render job is always a "batch": S scenes, each with its own Gaussians, blend
+// parameters and views.  A single scene is the batch S = 1, so the plain and the
+// persistent kernels run the same per-item code.
+//
+// Work is cut into items:
+//   forward item  = (view, first ray of a tile of BLOCK*RPT rays of that view)
+//   backward item = (view, first ray of a span of rays, Gaussian chunk) plus the
+//                   (chunk size, slots) thread mapping and the offset of its partial
+//                   gradient record.
+#pragma once
+#include <stdint.h>
+
+namespace fmb {
+
+// log2(e): the kernels keep log-densities in base 2 so that exp() is one v_exp_f32.
+constexpr double kLog2e = 1.4426950408889634073599246810019;
+// 0/0 guard of every vector normalisation: |y| is sqrt(y.y + kEpsN).
+constexpr float kEpsN = 1e-30f;
+
+struct ViewRec {       // one per view of the batch (16-byte aligned pair of int4)
+    int32_t h, w;      // image size
+    int32_t ray_off;   // global index of the view's first ray
+    int32_t scene;     // owning scene
+};
+
+struct SceneRec {
+    int32_t n;         // Gaussians
+    int32_t gauss_off; // first Gaussian in the concatenated parameter arrays
+    int32_t view_off;  // first view
+    int32_t n_views;
+};
+
+struct FwdItem {       // 8 bytes
+    int32_t view;
+    int32_t ray0;      // first local ray (pixel index within the view)
+};
+
+struct BwdItem {       // 32 bytes
+    int32_t view;
+    int32_t ray0;      // first local ray of the span
+    int32_t span;      // rays in the span (clipped to the view by the kernel)
+    int32_t g0;        // first Gaussian (scene-local) of the chunk
+    int32_t gc;        // Gaussians in the chunk (<= block size)
+    int32_t slots;     // ray slots: thread t works on Gaussian t % gc, rays t / gc mod slots
+    int32_t poff;      // offset (floats) of this item's partial record [gc][kPartial]
+    int32_t seq;       // canonical item index (beta partials)
+};
+
+struct FinTask {       // one per (scene, Gaussian chunk)
+    int32_t scene;
+    int32_t g0;        // scene-local first Gaussian
+    int32_t gc;        // valid Gaussians of the chunk
+    int32_t group_begin, group_end;  // first-stage groups of this chunk's items
+    int32_t beta;      // 1 if this task also reduces the scene's beta partials
+    int32_t sgroup_begin, sgroup_end;  // all groups of the scene (beta partials)
+};
+
+// First stage of the deterministic gradient reduction: a group of consecutive
+// canonical items of one chunk, summed (FP64, item order) into stage[soff ...].
+struct FinGroup {
+    int32_t item_begin, item_end;
+    int32_t poff;      // partial offset (floats) of item_begin; items of a chunk are contiguous
+    int32_t nval;      // gc * kPartial values per item (gc = item chunk size)
+    int32_t soff;      // offset (doubles) of the group's sums in the stage buffer
+    int32_t pad[3];
+};
+constexpr int kGroupItems = 32;  // minimum items per first-stage group
+
+constexpr int kPartial = 10;   // per-Gaussian partial: dU (6), sum rho (3), dlog(lambda) (1)
+
+// Kernel argument blocks (passed by value).
+struct Params {
+    const float *means, *prec, *weights, *betas;   // concatenated over scenes; betas [S,2]
+    const float *eta;                               // device [S]
+    const float *w2c, *intr, *w2c_b, *intr_b;       // per global view
+    const ViewRec *views;
+    const SceneRec *scenes;
+};
+
+struct FwdOut {
+    float *depth, *alpha, *normal, *flow, *stash;
+};
+
+struct BwdIn {
+    const float *g_depth, *g_alpha, *g_normal, *g_flow;
+    const float *depth, *stash;
+};
+
+}  // namespace fmb

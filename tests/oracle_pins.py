@@ -498,10 +498,43 @@ def pin_two_gaussian_beta_gradient():
                "d t_f / d beta2")
 
 
+def pin_loss_gradient():
+    """The loss gradient equals central differences of the loss value (away from the kinks of the
+    clamp and of |x|), and a hand-computed single-ray value: alpha = 0.5, target mask 1, depth
+    error 0.25 with w_depth 2, flow error (0.1, -0.2) squared L2 with w_flow 3 gives
+    L = log 2 + 0.5 + 0.15."""
+    L, _ = O.loss_grad([1.25], [0.5], [1.0], [1.0], flow=[[0.1, -0.2]], flow_t=[[0.0, 0.0]],
+                       w_depth=2.0, w_flow=3.0, flow_norm=2)
+    _close(L, math.log(2.0) + 0.5 + 0.15, 1e-14, 1e-14, "hand-computed loss")
+    g = _rng(28)
+    p = 16
+    d, dt = g.uniform(1, 4, p), g.uniform(1, 4, p)
+    a, at = g.uniform(0.01, 0.99, p), g.uniform(0, 1, p)
+    f, ft = g.standard_normal((p, 2)), g.standard_normal((p, 2))
+    for norm in (1, 2):
+        _, gr = O.loss_grad(d, a, dt, at, f, ft, 1.5, 2.5, norm)
+        for name, x in (("depth", d), ("alpha", a), ("flow", f)):
+            fd = np.zeros_like(x)
+            flat = x.reshape(-1)
+            for j in range(flat.size):
+                h = 1e-7
+                x0 = flat[j]
+                flat[j] = x0 + h
+                lp, _ = O.loss_grad(d, a, dt, at, f, ft, 1.5, 2.5, norm)
+                flat[j] = x0 - h
+                lm, _ = O.loss_grad(d, a, dt, at, f, ft, 1.5, 2.5, norm)
+                flat[j] = x0
+                fd.reshape(-1)[j] = (lp - lm) / (2 * h)
+            _close(gr[name], fd, 1e-6, 1e-8, f"loss gradient {name} (q={norm})")
+    # outside the clamp range the alpha gradient vanishes
+    _, gr = O.loss_grad([1.0, 1.0], [0.0, 1.0], [1.0, 1.0], [0.5, 0.5])
+    assert np.all(gr["alpha"] == 0.0)
+
+
 ALL_PINS = [
     pin_isotropic_closed_form, pin_bruteforce_peak, pin_interop_alpha, pin_alpha_identities,
     pin_two_gaussian_blend, pin_zero_betas_mean, pin_permutation, pin_pixel_ray_hand_case,
     pin_rays_reproject, pin_flow_equal_poses, pin_flow_rotation_homography, pin_flow_translation,
     pin_scale_invariance, pin_rigid_motion, pin_normals_geometry, pin_gradients_fd,
-    pin_isotropic_depth_gradient, pin_two_gaussian_beta_gradient,
+    pin_isotropic_depth_gradient, pin_two_gaussian_beta_gradient, pin_loss_gradient,
 ]

@@ -1,0 +1,75 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol the header declares and
+rejects bad arguments before touching the GPU."""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fmb.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fmb_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2308_14737_amd import _lib
+    return _lib.load()
+
+
+def test_header_symbols_exported(lib):
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in fmb.h but not exported"
+
+
+def test_binding_covers_header():
+    from paper_2308_14737_amd import _lib
+    assert set(_declared()) == set(_lib.SIGNATURES), set(_declared()) ^ set(_lib.SIGNATURES)
+
+
+def test_abi_version(lib):
+    assert lib.fmb_abi_version() == 1
+
+
+def test_invalid_arguments_rejected_without_gpu(lib):
+    h = ctypes.c_void_p()
+    f = ctypes.c_float
+    assert lib.fmb_scene_create(None, 4, None, None, None, None, f(1.0)) == 1
+    assert lib.fmb_scene_create(ctypes.byref(h), 0, None, None, None, None, f(1.0)) == 1
+    assert b"n must be" in lib.fmb_last_error()
+    fake = ctypes.c_void_p(4096)
+    assert lib.fmb_scene_create(ctypes.byref(h), 4, fake, fake, fake, None, f(1.0)) == 1
+    assert lib.fmb_scene_create(ctypes.byref(h), 4, fake, fake, fake, fake, f(0.0)) == 1
+    assert b"eta" in lib.fmb_last_error()
+    assert lib.fmb_scene_create(ctypes.byref(h), 4, ctypes.c_void_p(4098), fake, fake, fake, f(1.0)) == 1
+    assert lib.fmb_render(None, None, None, None, None, None, None) == 1
+    assert lib.fmb_backward(None, *([None] * 11)) == 1
+    assert lib.fmb_set_cameras(None, 1, None, None, None, None, None) == 1
+    assert lib.fmb_batch_forward(None, None, None, None, None, None, None) == 1
+    assert lib.fmb_batch_graph_launch(None, 2, None) == 1
+    assert lib.fmb_scene_destroy(None) == 0
+    assert lib.fmb_batch_destroy(None) == 0
+    assert lib.fmb_num_rays(None) == 0
+    out = (ctypes.c_double * 6)()
+    assert lib.fmb_kernel_times(out, 1) == 0
+
+
+def test_batch_create_rejects_bad_sizes(lib):
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(4096)
+    n = (ctypes.c_int32 * 2)(3, 0)
+    v = (ctypes.c_int32 * 2)(1, 1)
+    eta = (ctypes.c_float * 2)(1.0, 1.0)
+    hw = (ctypes.c_int32 * 4)(4, 4, 4, 4)
+    rc = lib.fmb_batch_create(ctypes.byref(h), 2, n, v, fake, fake, fake, fake, eta, fake, fake, hw, None, None)
+    assert rc == 1 and b">= 1 Gaussian" in lib.fmb_last_error()

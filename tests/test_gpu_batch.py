@@ -1,0 +1,143 @@
+"""GPU tests of the batched persistent form and its HIP-graph capture."""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from tests.gpu_util import assert_forward, assert_grads, compare_forward, compare_grads, make_scene, to_np
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def fmb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2308_14737_amd as m
+    return m
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _batch_inputs(w, fmb):
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=DEV).contiguous()  # noqa: E731
+    means = t(np.concatenate([s.means for s in w.scenes]))
+    prec = t(np.concatenate([s.prec for s in w.scenes]))
+    weights = t(np.concatenate([s.weights for s in w.scenes]))
+    betas = t(np.tile(w.betas, (len(w.scenes), 1)))
+    cams = [fmb.Cameras.from_numpy(c.w2c, c.intr, c.hw, c.w2c_b, c.intr_b, device=DEV) for c in w.cameras]
+    b = fmb.Batch(means, prec, weights, betas, [w.eta] * len(w.scenes), [s.n for s in w.scenes], cams)
+    return b, (means, prec, weights, betas)
+
+
+def _cotangents(b, seed, normals=True):
+    cot = W.random_cotangents(b.n_rays, seed, flow=b.has_flow, normals=normals)
+    return {k: (None if v is None else torch.as_tensor(v, device=DEV).contiguous()) for k, v in cot.items()}
+
+
+@pytest.fixture(scope="module")
+def batch16(fmb):
+    w = W.make_config("batch16")
+    b, params = _batch_inputs(w, fmb)
+    return w, b, params
+
+
+def test_batch_equals_plain_bitwise(fmb, batch16):
+    """The persistent batched kernels and per-scene plain launches cut each scene into the
+    same items, so outputs and gradients agree bit for bit."""
+    w, b, params = batch16
+    _say(f"[batch] batch16 S={len(w.scenes)} P={b.n_rays} pairs={w.n_pairs}")
+    outs = b.forward(b.alloc_outputs(normals=True))
+    cot = _cotangents(b, 21)
+    grads = b.backward(outs, cot, b.alloc_grads())
+    torch.cuda.synchronize()
+    for i, (sc, cams) in enumerate(zip(w.scenes, w.cameras)):
+        scene, _ = make_scene(fmb, torch, sc, cams, w.betas, w.eta, DEV)
+        r0, r1 = b.ray_off[i], b.ray_off[i + 1]
+        g0, g1 = b.gauss_off[i], b.gauss_off[i + 1]
+        o = scene.render(normals=True)
+        gi = scene.backward(o, cot["depth"][r0:r1], cot["alpha"][r0:r1], cot["normal"][r0:r1])
+        torch.cuda.synchronize()
+        for k in ("depth", "alpha", "normal", "stash"):
+            assert torch.equal(o[k], outs[k][r0:r1]), (i, k)
+        for k in ("means", "prec", "weights"):
+            assert torch.equal(gi[k], grads[k][g0:g1]), (i, k)
+        assert torch.equal(gi["betas"], grads["betas"][i]), (i, "betas")
+
+
+def test_batch_vs_oracle(fmb, batch16):
+    """Scenes of the batch against the oracle: sampled rays forward, sampled-cotangent backward."""
+    w, b, params = batch16
+    outs = b.forward(b.alloc_outputs(normals=True))
+    cot = W.random_cotangents(b.n_rays, 33, flow=False)
+    g = np.random.Generator(np.random.PCG64(5))
+    for i in (0, 5, 8, 15):
+        sc, cams = w.scenes[i], w.cameras[i]
+        r0, r1 = b.ray_off[i], b.ray_off[i + 1]
+        rays = np.sort(g.choice(r1 - r0, size=min(4000, r1 - r0), replace=False))
+        ref, _, _ = O.render_workload_view(sc, cams, w.betas, w.eta, rays=rays)
+        sub = {k: (None if v is None else v[r0:r1]) for k, v in outs.items()}
+        torch.cuda.synchronize()
+        e = compare_forward(sub, ref, rays)
+        _say(f"[batch-oracle] scene {i} N={sc.n} V={cams.v} {cams.hw[0]}: {e}")
+        assert_forward(e, f"scene {i}")
+    # backward: cotangents only on sampled rays of scene 5 (others zero)
+    i = 5
+    sc, cams = w.scenes[i], w.cameras[i]
+    r0, r1 = b.ray_off[i], b.ray_off[i + 1]
+    rays = np.sort(g.choice(r1 - r0, size=min(4000, r1 - r0), replace=False))
+    full = {k: np.zeros_like(v) for k, v in cot.items() if v is not None}
+    for k in full:
+        full[k][r0 + rays] = cot[k][r0 + rays]
+    tc = {k: torch.as_tensor(v, device=DEV).contiguous() for k, v in full.items()}
+    grads = b.backward(outs, tc, b.alloc_grads())
+    torch.cuda.synchronize()
+    cs = {k: v[r0 + rays] for k, v in full.items()}
+    cs["flow"] = None
+    _, gref, _ = O.render_workload_view(sc, cams, w.betas, w.eta, rays=rays, cot=cs)
+    g0, g1 = b.gauss_off[i], b.gauss_off[i + 1]
+    gs = {"means": grads["means"][g0:g1], "prec": grads["prec"][g0:g1], "weights": grads["weights"][g0:g1],
+          "betas": grads["betas"][i]}
+    e = compare_grads(gs, gref)
+    _say(f"[batch-oracle] backward scene {i}: {e}")
+    assert_grads(e, "batch scene 5")
+    other = torch.cat([grads["means"][:g0].reshape(-1), grads["means"][g1:].reshape(-1)])
+    assert torch.count_nonzero(other).item() == 0
+
+
+def test_graph_replay(fmb, batch16):
+    """A captured forward+backward replays like the eager batched calls, several times with eager
+    work in between, and sees in-place parameter updates."""
+    w, b, (means, prec, weights, betas) = batch16
+    outs_e = b.alloc_outputs(normals=True)
+    grads_e = b.alloc_grads()
+    cot = _cotangents(b, 44)
+    outs_g = b.alloc_outputs(normals=True)
+    grads_g = b.alloc_grads()
+    st = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    _say("[graph] capture")
+    b.capture(outs_g, cot, grads_g, st)
+    for rep in range(3):
+        with torch.cuda.stream(st):
+            b.graph_launch(2, st)
+        st.synchronize()
+        b.forward(outs_e)
+        b.backward(outs_e, cot, grads_e)
+        torch.cuda.synchronize()
+        for k in ("depth", "alpha", "normal"):
+            assert torch.equal(outs_g[k], outs_e[k]), (rep, k)
+        for k in grads_e:
+            assert torch.equal(grads_g[k], grads_e[k]), (rep, k)
+        _say(f"[graph] replay {rep} matches eager")
+        # in-place update seen by the next replay
+        with torch.no_grad():
+            means.add_(0.001)
+            betas.mul_(1.01)

@@ -1,0 +1,339 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Full-size workloads render every ray on the GPU in the launch configuration the
+benchmark uses; where the oracle cannot render all rays in seconds it is evaluated
+on a seeded sample of rays (forward), and the backward pass is driven by cotangents
+that are zero except on that sample, so the oracle's gradient over the sample is the
+exact reference for the GPU gradient over the whole image.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from tests.gpu_util import (TOL_ALPHA, TOL_GRAD, TOL_REL, assert_forward, assert_grads, compare_forward,
+                            compare_grads, make_scene, maxabs, normwise, to_np)
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def fmb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2308_14737_amd as m
+    return m
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _sample(n_rays, k, seed):
+    if k is None or k >= n_rays:
+        return None
+    g = np.random.Generator(np.random.PCG64(seed))
+    return np.sort(g.choice(n_rays, size=k, replace=False))
+
+
+FULL = [("fwd64", None), ("fwdbwd128", None), ("flow480", 20000), ("large1080", 3000)]
+
+
+@pytest.mark.parametrize("name,sample", FULL, ids=[f[0] for f in FULL])
+def test_forward_parity(fmb, name, sample):
+    w = W.make_config(name)
+    sc, cams = w.scenes[0], w.cameras[0]
+    _say(f"[fwd] {name}: N={sc.n} P={cams.n_rays} sample={sample}")
+    scene, _ = make_scene(fmb, torch, sc, cams, w.betas, w.eta, DEV)
+    outs = scene.render(normals=w.normals)
+    torch.cuda.synchronize()
+    rays = _sample(cams.n_rays, sample, 7)
+    ref, _, _ = O.render_workload_view(sc, cams, w.betas, w.eta, rays=rays)
+    e = compare_forward(outs, ref, rays, normals=w.normals)
+    _say(f"[fwd] {name}: {e}")
+    assert_forward(e, name)
+    assert np.all(np.isfinite(to_np(outs["depth"]))) and np.all(np.isfinite(to_np(outs["alpha"])))
+
+
+BWD = [("fwd64", None), ("fwdbwd128", None), ("flow480", 20000), ("large1080", 2000)]
+
+
+@pytest.mark.parametrize("name,sample", BWD, ids=[b[0] for b in BWD])
+def test_backward_parity(fmb, name, sample):
+    w = W.make_config(name)
+    sc, cams = w.scenes[0], w.cameras[0]
+    p = cams.n_rays
+    _say(f"[bwd] {name}: N={sc.n} P={p} sample={sample}")
+    scene, _ = make_scene(fmb, torch, sc, cams, w.betas, w.eta, DEV)
+    outs = scene.render(normals=w.normals)
+    cot = W.random_cotangents(p, 1234, flow=cams.has_flow, normals=w.normals)
+    rays = _sample(p, sample, 11)
+    if rays is not None:
+        mask = np.zeros(p, dtype=bool)
+        mask[rays] = True
+        for k, v in cot.items():
+            if v is not None:
+                v[~mask] = 0.0
+    t = lambda a: None if a is None else torch.as_tensor(a, device=DEV).contiguous()  # noqa: E731
+    g = scene.backward(outs, t(cot["depth"]), t(cot["alpha"]), t(cot["normal"]), t(cot["flow"]))
+    torch.cuda.synchronize()
+    cot_s = {k: (None if v is None else (v if rays is None else v[rays])) for k, v in cot.items()}
+    _, gref, _ = O.render_workload_view(sc, cams, w.betas, w.eta, rays=rays, cot=cot_s)
+    e = compare_grads(g, gref)
+    _say(f"[bwd] {name}: {e}")
+    assert_grads(e, name)
+
+
+# ---------------------------------------------------------------------------------------
+# Ragged and degenerate cases
+# ---------------------------------------------------------------------------------------
+
+def _custom(n, views, seed, behind=False, flow=False, s_range=(0.05, 0.2)):
+    g = np.random.Generator(np.random.PCG64(seed))
+    means = g.uniform(-1, 1, (n, 3))
+    if behind:
+        means[: n // 3, 2] = g.uniform(-6, -3.5, n // 3)  # behind the front camera at z = -3
+    sc = W.make_scene(g, n, means, log_s_range=s_range)
+    e, k, hw = [], [], []
+    for i, (h, wd) in enumerate(views):
+        if i == 0:
+            e.append(np.concatenate([np.eye(3), [[0.0], [0.0], [3.0]]], axis=1))
+        else:
+            e.append(W.look_at(3.0 * W.fibonacci_sphere(len(views))[i]))
+        k.append([float(h), float(h), wd / 2.0, h / 2.0])
+        hw.append([h, wd])
+    e = np.array(e, np.float32)
+    cams = W.Cameras(e, np.array(k, np.float32), np.array(hw, np.int32))
+    if flow:
+        eb = e.copy()
+        eb[:, :, 3] += np.array([0.03, -0.02, 0.01], np.float32)
+        cams.w2c_b, cams.intr_b = eb, cams.intr.copy()
+    return sc, cams
+
+
+RAGGED = [
+    ("n1_1x1", 1, [(1, 1)]),
+    ("n1_odd", 1, [(17, 23)]),
+    ("n7_multi", 7, [(5, 3), (64, 64), (1, 1), (33, 65)]),
+    ("n129_two_tiles", 129, [(20, 31)]),
+    ("n257_chunks", 257, [(40, 50), (3, 7)]),
+    ("n600_tiny_img", 600, [(7, 9)]),
+]
+
+
+def _hit_mask_cot(cot, alpha_ref, thr=1e-4):
+    """Depth/normal/flow cotangents only on rays that see the scene (oracle alpha >= thr); the
+    alpha cotangent everywhere.  Over background rays the blend weights are decided by
+    log-density differences of order 1e4 that FP32 cannot resolve (see
+    test_background_rays_conditioning)."""
+    keep = alpha_ref >= thr
+    out = {}
+    for k, v in cot.items():
+        if v is None or k == "alpha":
+            out[k] = v
+        else:
+            out[k] = (v * keep.reshape(-1, *([1] * (v.ndim - 1)))).astype(np.float32)
+    return out
+
+
+@pytest.mark.parametrize("label,n,views", RAGGED, ids=[r[0] for r in RAGGED])
+def test_ragged_parity(fmb, label, n, views):
+    sc, cams = _custom(n, views, seed=n, flow=True)
+    betas = np.array([W.BETA1, W.BETA2], np.float32)
+    _say(f"[ragged] {label}: N={n} views={views}")
+    scene, _ = make_scene(fmb, torch, sc, cams, betas, 1.0, DEV)
+    outs = scene.render(normals=True)
+    ref, _, _ = O.render_workload_view(sc, cams, betas, 1.0)
+    cot = _hit_mask_cot(W.random_cotangents(cams.n_rays, 5, flow=True), ref["alpha"])
+    t = lambda a: torch.as_tensor(a, device=DEV).contiguous()  # noqa: E731
+    g = scene.backward(outs, t(cot["depth"]), t(cot["alpha"]), t(cot["normal"]), t(cot["flow"]))
+    torch.cuda.synchronize()
+    _, gref, _ = O.render_workload_view(sc, cams, betas, 1.0, cot=cot)
+    e = compare_forward(outs, ref)
+    eg = compare_grads(g, gref)
+    _say(f"[ragged] {label}: {e} {eg}")
+    assert_forward(e, label)
+    assert_grads(eg, label)
+
+
+def test_background_rays_conditioning(fmb):
+    """Unmasked random cotangents on a sparse scene whose image is mostly background.  There the
+    exact gradient itself moves by ~1e-3 when the FP32 inputs move by one ulp (measured below
+    with the oracle): background pairs have log-densities d of order -1e3..-1e4, and the blend
+    weights of Eq. (7) depend on differences of such values.  The kernels hold d in FP32, whose
+    rounding (|d| 2^-24) is larger than a one-ulp change of the inputs by about |d| / |x|, so the
+    bound is ten times the measured one-ulp sensitivity (and never below the 1e-3 contract)."""
+    sc, cams = _custom(7, [(5, 3), (64, 64), (1, 1), (33, 65)], seed=7, flow=True)
+    betas = np.array([W.BETA1, W.BETA2], np.float32)
+    _say("[background] N=7 sparse scene, unmasked cotangents")
+    scene, _ = make_scene(fmb, torch, sc, cams, betas, 1.0, DEV)
+    outs = scene.render(normals=True)
+    cot = W.random_cotangents(cams.n_rays, 5, flow=True)
+    t = lambda a: torch.as_tensor(a, device=DEV).contiguous()  # noqa: E731
+    g = scene.backward(outs, t(cot["depth"]), t(cot["alpha"]), t(cot["normal"]), t(cot["flow"]))
+    torch.cuda.synchronize()
+    _, gref, _ = O.render_workload_view(sc, cams, betas, 1.0, cot=cot)
+    rng = np.random.Generator(np.random.PCG64(1))
+    sens = {k: 0.0 for k in gref}
+    for _ in range(3):
+        jit = W.Scene(sc.means.astype(np.float64) * (1 + 2.0 ** -24 * rng.standard_normal(sc.means.shape)),
+                      sc.prec.astype(np.float64) * (1 + 2.0 ** -24 * rng.standard_normal(sc.prec.shape)),
+                      sc.weights)
+        _, gj, _ = O.render_workload_view(jit, cams, betas, 1.0, cot=cot)
+        for k in gref:
+            sens[k] = max(sens[k], normwise(gj[k], gref[k]))
+    eg = compare_grads(g, gref)
+    _say(f"[background] gpu {eg} oracle one-ulp sensitivity {sens}")
+    for k in eg:
+        assert eg[k] <= max(TOL_GRAD, 10.0 * sens[k]), (k, eg, sens)
+
+
+def test_loss_gradient_parity(fmb):
+    """Gradient of the workload loss (alpha-weighted L1 depth + BCE alpha against targets rendered
+    from the perturbed scene); targets and cotangents come from the oracle's own renders."""
+    w = W.make_config("fwdbwd128")
+    sc, cams = w.scenes[0], w.cameras[0]
+    _say("[loss] fwdbwd128 L1 depth + BCE alpha")
+    scene, _ = make_scene(fmb, torch, sc, cams, w.betas, w.eta, DEV)
+    outs = scene.render(normals=True)
+    ref, _, _ = O.render_workload_view(sc, cams, w.betas, w.eta)
+    tgt, _, _ = O.render_workload_view(w.targets[0], cams, w.betas, w.eta)
+    p = cams.n_rays
+    gd = tgt["alpha"] * np.sign(ref["depth"] - tgt["depth"]) / p
+    a = np.clip(ref["alpha"], 1e-6, 1 - 1e-6)
+    inside = (ref["alpha"] >= 1e-6) & (ref["alpha"] <= 1 - 1e-6)
+    ga = np.where(inside, (a - tgt["alpha"]) / (a * (1 - a)), 0.0) / p
+    cot = {"depth": gd.astype(np.float32), "alpha": ga.astype(np.float32), "normal": None, "flow": None}
+    t = lambda a: torch.as_tensor(a, device=DEV).contiguous()  # noqa: E731
+    g = scene.backward(outs, t(cot["depth"]), t(cot["alpha"]))
+    torch.cuda.synchronize()
+    _, gref, _ = O.render_workload_view(sc, cams, w.betas, w.eta, cot=cot)
+    eg = compare_grads(g, gref)
+    _say(f"[loss] {eg}")
+    assert_grads(eg, "loss")
+
+
+def test_behind_camera_and_eta(fmb):
+    """Gaussians behind the camera (t < 0) are blended like any other (Eq. 7 without clamp);
+    a non-unit eta rescales the depth term."""
+    sc, cams = _custom(30, [(48, 40)], seed=3, behind=True)
+    betas = np.array([W.BETA1 * 0.5, W.BETA2], np.float32)
+    _say("[behind] N=30, 48x40, eta=2.5")
+    scene, _ = make_scene(fmb, torch, sc, cams, betas, 2.5, DEV)
+    outs = scene.render(normals=True)
+    ref, _, _ = O.render_workload_view(sc, cams, betas, 2.5)
+    cot = _hit_mask_cot(W.random_cotangents(cams.n_rays, 9, flow=False), ref["alpha"])
+    t = lambda a: torch.as_tensor(a, device=DEV).contiguous()  # noqa: E731
+    g = scene.backward(outs, t(cot["depth"]), t(cot["alpha"]), t(cot["normal"]))
+    torch.cuda.synchronize()
+    _, gref, _ = O.render_workload_view(sc, cams, betas, 2.5, cot=cot)
+    assert_forward(compare_forward(outs, ref), "behind")
+    assert_grads(compare_grads(g, gref), "behind")
+
+
+def test_flow_equal_poses_is_zero(fmb):
+    sc, cams = _custom(20, [(32, 48), (16, 16)], seed=4)
+    cams.w2c_b, cams.intr_b = cams.w2c.copy(), cams.intr.copy()
+    betas = np.array([W.BETA1, W.BETA2], np.float32)
+    _say("[flow0] equal poses")
+    scene, _ = make_scene(fmb, torch, sc, cams, betas, 1.0, DEV)
+    outs = scene.render(normals=False)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(outs["flow"]).item() == 0
+
+
+def test_alpha_interop_value(fmb):
+    """A lone Gaussian with lambda = log 80 seen through its mean renders alpha = 79/80."""
+    means = np.zeros((1, 3), np.float32)
+    prec = np.array([[10.0, 1.0, -2.0, 8.0, 0.5, 12.0]], np.float32)
+    sc = W.Scene(means, prec, np.array([math.log(80.0)], np.float32))
+    cams = W.Cameras(np.concatenate([np.eye(3), [[0.0], [0.0], [3.0]]], axis=1)[None].astype(np.float32),
+                     np.array([[8.0, 8.0, 1.0, 1.0]], np.float32), np.array([[2, 2]], np.int32))
+    # pixel (0,0) has its centre at (0.5, 0.5) != principal point (1,1); use principal point (0.5,0.5)
+    cams.intr[0, 2:] = 0.5
+    betas = np.array([W.BETA1, W.BETA2], np.float32)
+    _say("[interop] alpha 79/80")
+    scene, _ = make_scene(fmb, torch, sc, cams, betas, 1.0, DEV)
+    outs = scene.render(normals=True)
+    torch.cuda.synchronize()
+    assert abs(float(outs["alpha"][0]) - 79.0 / 80.0) <= TOL_ALPHA
+    assert abs(float(outs["depth"][0]) - 3.0) <= 3.0 * TOL_REL
+
+
+def test_validate_flags(fmb):
+    sc, cams = _custom(8, [(8, 8)], seed=6)
+    betas = np.array([W.BETA1, W.BETA2], np.float32)
+    _say("[validate]")
+    scene, (m, p, wt, b) = make_scene(fmb, torch, sc, cams, betas, 1.0, DEV)
+    assert scene.validate() == 0
+    m[2, 1] = float("nan")
+    wt[3] = -1.0
+    p[4, 3] = 0.0
+    assert scene.validate() == 1 | 2 | 4
+
+
+def test_autograd_matches_backward(fmb):
+    w = W.make_config("fwd64")
+    sc, cams = w.scenes[0], w.cameras[0]
+    _say("[autograd] fwd64")
+    scene, (m, p, wt, b) = make_scene(fmb, torch, sc, cams, w.betas, w.eta, DEV)
+    params = [x.clone().requires_grad_(True) for x in (m, p, wt, b)]
+    depth, alpha, normal, _ = fmb.render(scene, *params, normals=True)
+    cot = W.random_cotangents(cams.n_rays, 77, flow=False)
+    t = lambda a: torch.as_tensor(a, device=DEV)  # noqa: E731
+    loss = (depth * t(cot["depth"])).sum() + (alpha * t(cot["alpha"])).sum() + (normal * t(cot["normal"])).sum()
+    loss.backward()
+    outs = scene.render(normals=True)
+    g = scene.backward(outs, t(cot["depth"]), t(cot["alpha"]), t(cot["normal"]))
+    torch.cuda.synchronize()
+    for x, k in zip(params, ("means", "prec", "weights", "betas")):
+        assert torch.equal(x.grad, g[k]), k
+
+
+def test_deterministic_backward(fmb):
+    w = W.make_config("fwdbwd128")
+    sc, cams = w.scenes[0], w.cameras[0]
+    _say("[determinism] fwdbwd128 twice")
+    scene, _ = make_scene(fmb, torch, sc, cams, w.betas, w.eta, DEV)
+    outs = scene.render(normals=True)
+    cot = W.random_cotangents(cams.n_rays, 3, flow=False)
+    t = lambda a: torch.as_tensor(a, device=DEV).contiguous()  # noqa: E731
+    g1 = {k: v.clone() for k, v in scene.backward(outs, t(cot["depth"]), t(cot["alpha"]), t(cot["normal"])).items()}
+    g2 = scene.backward(outs, t(cot["depth"]), t(cot["alpha"]), t(cot["normal"]))
+    torch.cuda.synchronize()
+    for k in g1:
+        assert torch.equal(g1[k], g2[k]), k
+
+
+@pytest.mark.parametrize("norm", [1, 2])
+def test_loss_grad_kernel(fmb, norm):
+    """The fused loss-gradient kernel against the oracle's definition of the Sec. 4 loss."""
+    g = np.random.Generator(np.random.PCG64(40 + norm))
+    p = 10007
+    depth = g.uniform(1, 5, p).astype(np.float32)
+    depth_t = depth.copy()
+    depth_t[::3] = g.uniform(1, 5, len(depth_t[::3])).astype(np.float32)   # some exact ties
+    alpha = g.uniform(0, 1, p).astype(np.float32)
+    alpha[:5] = [0.0, 1.0, 5e-7, 1 - 1e-7, 1e-6]                              # clamp edges
+    alpha_t = (g.uniform(0, 1, p) > 0.4).astype(np.float32)
+    flow = g.standard_normal((p, 2)).astype(np.float32)
+    flow_t = g.standard_normal((p, 2)).astype(np.float32)
+    _say(f"[loss-kernel] p={p} norm={norm}")
+    t = lambda a: torch.as_tensor(a, device=DEV).contiguous()  # noqa: E731
+    bl = torch.empty((p + 1023) // 1024, device=DEV)
+    cot = fmb.loss_grad({"depth": t(depth), "alpha": t(alpha), "flow": t(flow)}, t(depth_t), t(alpha_t),
+                        t(flow_t), w_depth=1.5, w_flow=2.5, flow_norm=norm, block_loss=bl)
+    torch.cuda.synchronize()
+    L, gref = O.loss_grad(depth, alpha, depth_t, alpha_t, flow, flow_t, 1.5, 2.5, norm)
+    for k in ("depth", "alpha", "flow"):
+        got = to_np(cot[k])
+        err = np.abs(got - gref[k])
+        assert np.all(err <= 1e-5 * np.abs(gref[k]) + 1e-12), (k, float(err.max()))
+    assert abs(float(bl.double().sum()) - L) <= 1e-5 * abs(L)
