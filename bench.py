@@ -225,6 +225,7 @@ def main():
         "eager_ms_per_step": ms_eager,
         "fp32_peak_frac_step": step_flops / (ms_graph * 1e-3) / PEAK_FP32,
         "kernel_ms": {"forward": fwd_ms, "backward": bwd_ms, "finalize": fin_ms},
+        "launch": fmb.launch_config(batch=batch),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
                      "kernel": "bwd_kernel (persistent)", "flops_per_pair": FLOPS_ADJ_PLAIN,

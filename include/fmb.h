@@ -215,6 +215,12 @@ int fmb_loss_grad(int64_t p, const float *depth, const float *alpha, const float
                   float w_flow, int32_t flow_norm, float *g_depth, float *g_alpha, float *g_flow,
                   float *block_loss, void *stream);
 
+/* Current launch configuration of a scene or batch (exactly one non-NULL), written to the
+ * host array out[8]: forward tile variant, rays per forward work item, backward variant,
+ * rays per backward LDS tile, forward and backward persistent-grid multipliers, and the
+ * forward and backward work-item counts (0 until the first call built them). */
+int fmb_get_config(const fmb_scene *scene, const fmb_batch *batch, int32_t *out);
+
 /* Check the scene's parameters on the device: writes to *bad_host a bit mask of
  * 1 = non-finite value, 2 = weight <= 0, 4 = zero diagonal entry of U, 8 = beta not
  * finite, and synchronises `stream`. */

@@ -10,6 +10,6 @@ from . import _lib
 
 _lib.load()
 
-from .render import Batch, Cameras, Scene, kernel_times, loss_grad, render, timing_enable  # noqa: E402,F401
+from .render import Batch, Cameras, Scene, kernel_times, launch_config, loss_grad, render, timing_enable  # noqa: E402,F401
 
-__all__ = ["Batch", "Cameras", "Scene", "kernel_times", "loss_grad", "render", "timing_enable"]
+__all__ = ["Batch", "Cameras", "Scene", "kernel_times", "launch_config", "loss_grad", "render", "timing_enable"]

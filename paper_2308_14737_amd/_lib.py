@@ -46,6 +46,7 @@ SIGNATURES = {
     "fmb_loss_grad": (_int, [_i64, _vp, _vp, _vp, _vp, _vp, _vp, _f32, _f32, _i32, _vp, _vp, _vp, _vp,
                              _vp]),
     "fmb_validate": (_int, [_vp, ctypes.POINTER(_i32), _vp]),
+    "fmb_get_config": (_int, [_vp, _vp, ctypes.POINTER(_i32)]),
     "fmb_timing_enable": (_int, [_int]),
     "fmb_kernel_times": (_int, [ctypes.POINTER(ctypes.c_double), _int]),
 }

@@ -399,6 +399,7 @@ struct Job {
     }
 
     std::map<int, int> occ_f, occ_b;  // blocks per CU of the persistent kernels
+    int persist_mult[2] = {1, 1};     // persistent grid = mult x occupancy x CUs (fwd, bwd)
 
     int grid_fwd(bool nrm, bool flw, int &grid)
     {
@@ -409,7 +410,7 @@ struct Job {
             HIPCHK(occupancy_fwd(fwd_variant, nrm, flw, &o));
             it = occ_f.emplace(key, std::max(1, o)).first;
         }
-        grid = std::max(1, std::min(n_fitems, it->second * n_cu));
+        grid = std::max(1, std::min(n_fitems, persist_mult[0] * it->second * n_cu));
         return FMB_OK;
     }
 
@@ -422,7 +423,7 @@ struct Job {
             HIPCHK(occupancy_bwd(bwd_variant, nrm, flw, &o));
             it = occ_b.emplace(key, std::max(1, o)).first;
         }
-        grid = std::max(1, std::min(n_bitems, it->second * n_cu));
+        grid = std::max(1, std::min(n_bitems, persist_mult[1] * it->second * n_cu));
         return FMB_OK;
     }
 
@@ -805,6 +806,23 @@ int fmb_validate(fmb_scene *s, int32_t *bad_host, void *stream)
     return rc;
 }
 
+int fmb_get_config(const fmb_scene *s, const fmb_batch *b, int32_t *out)
+{
+    g_err.clear();
+    CHECK_ARG((s != nullptr) != (b != nullptr), "exactly one of scene and batch must be given");
+    CHECK_ARG(out, "out must be non-NULL");
+    const Job &j = s ? s->job : b->job;
+    out[0] = j.fwd_variant;
+    out[1] = fwd_variant_rays(j.fwd_variant);
+    out[2] = j.bwd_variant;
+    out[3] = bwd_variant_rt(j.bwd_variant);
+    out[4] = j.persist_mult[0];
+    out[5] = j.persist_mult[1];
+    out[6] = j.fwd_built >= 0 ? j.n_fitems : 0;
+    out[7] = j.bwd_built >= 0 ? j.n_bitems : 0;
+    return FMB_OK;
+}
+
 int fmb_timing_enable(int enable)
 {
     std::lock_guard<std::mutex> lk(g_timing.mu);
@@ -840,7 +858,7 @@ static std::string tune_key(const Job &j, bool nrm, bool flw, int cot_mask)
     hipDeviceProp_t prop{};
     (void)hipGetDeviceProperties(&prop, j.device);
     std::ostringstream k;
-    k << prop.gcnArchName << ":cu" << j.n_cu << ":v2:S" << j.S << ":V" << j.V << ":P" << j.P << ":N" << j.n_total
+    k << prop.gcnArchName << ":cu" << j.n_cu << ":v3:S" << j.S << ":V" << j.V << ":P" << j.P << ":N" << j.n_total
       << ":nrm" << nrm << ":flw" << flw << ":cot" << cot_mask;
     return k.str();
 }
@@ -866,11 +884,13 @@ int fmb_autotune(fmb_scene *s, fmb_batch *b, float *depth, float *alpha, float *
         while (std::getline(in, line)) {
             std::istringstream ls(line);
             std::string k;
-            int fv = -1, bv = -1;
-            if (ls >> k >> fv >> bv && k == key && fv >= 0 && fv < num_fwd_variants() && bv >= 0 &&
-                bv < num_bwd_variants()) {
+            int fv = -1, bv = -1, mf = 1, mb = 1;
+            if (ls >> k >> fv >> bv >> mf >> mb && k == key && fv >= 0 && fv < num_fwd_variants() && bv >= 0 &&
+                bv < num_bwd_variants() && mf >= 1 && mf <= 2 && mb >= 1 && mb <= 2) {
                 j.fwd_variant = fv;
                 j.bwd_variant = bv;
+                j.persist_mult[0] = mf;
+                j.persist_mult[1] = mb;
                 return FMB_OK;
             }
         }
@@ -892,36 +912,46 @@ int fmb_autotune(fmb_scene *s, fmb_batch *b, float *depth, float *alpha, float *
     int rc = FMB_OK;
     float best_f = 1e30f, best_b = 1e30f;
     int bf = j.fwd_variant, bb = j.bwd_variant;
-    for (int v = 0; v < num_fwd_variants() && !rc; ++v) {
-        j.fwd_variant = v;
-        float ms = 0.0f;
-        rc = time_it([&]() { return j.forward(depth, alpha, normal, flow, stash, persist, st); }, ms);
-        if (!rc && ms < best_f) {
-            best_f = ms;
-            bf = v;
+    const int n_mult = persist ? 2 : 1;
+    int bmf = 1, bmb = 1;
+    for (int v = 0; v < num_fwd_variants() && !rc; ++v)
+        for (int m = 1; m <= n_mult && !rc; ++m) {
+            j.fwd_variant = v;
+            j.persist_mult[0] = m;
+            float ms = 0.0f;
+            rc = time_it([&]() { return j.forward(depth, alpha, normal, flow, stash, persist, st); }, ms);
+            if (!rc && ms < best_f) {
+                best_f = ms;
+                bf = v;
+                bmf = m;
+            }
         }
-    }
     j.fwd_variant = bf;
+    j.persist_mult[0] = bmf;
     if (!rc) rc = j.forward(depth, alpha, normal, flow, stash, persist, st);
-    for (int v = 0; v < num_bwd_variants() && !rc; ++v) {
-        j.bwd_variant = v;
-        float ms = 0.0f;
-        rc = time_it([&]() {
-            return j.backward(g_depth, g_alpha, g_normal, g_flow, depth, stash, g_means, g_prec, g_weights, g_betas,
-                              persist, st);
-        }, ms);
-        if (!rc && ms < best_b) {
-            best_b = ms;
-            bb = v;
+    for (int v = 0; v < num_bwd_variants() && !rc; ++v)
+        for (int m = 1; m <= n_mult && !rc; ++m) {
+            j.bwd_variant = v;
+            j.persist_mult[1] = m;
+            float ms = 0.0f;
+            rc = time_it([&]() {
+                return j.backward(g_depth, g_alpha, g_normal, g_flow, depth, stash, g_means, g_prec, g_weights,
+                                  g_betas, persist, st);
+            }, ms);
+            if (!rc && ms < best_b) {
+                best_b = ms;
+                bb = v;
+                bmb = m;
+            }
         }
-    }
     j.bwd_variant = bb;
+    j.persist_mult[1] = bmb;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
     if (cache_path) {
         std::ofstream outf(cache_path, std::ios::app);
-        if (outf) outf << key << " " << bf << " " << bb << "\n";
+        if (outf) outf << key << " " << bf << " " << bb << " " << bmf << " " << bmb << "\n";
     }
     return FMB_OK;
 }

@@ -17,7 +17,7 @@
 //
 // Per pair (ray o + t v with |v| = 1, Gaussian mu, U, lambda; mu' = mu - o):
 //   a = U v, t = v.c / a.a (peak of the density along the ray, Sec. 3.1),
-//   w = t v - mu' (with mu' as hi + lo), r = U w, one Newton refinement of t on
+//   r = U (t v - mu') formed as U (t v - hi) - U lo, one Newton refinement of t on
 //   |U(t v - mu')|^2, m = r.r, d = log lambda - m/2 (Eq. 2), delta = e^d (Eq. 4),
 //   z = beta1 d - (beta2/eta) t (log of Eq. 7), g = U^T r = Sigma^-1 x (Eq. 17).
 #include <hip/hip_runtime.h>
@@ -38,8 +38,8 @@ __device__ __forceinline__ float exp2_(float x) { return __builtin_amdgcn_exp2f(
 
 struct Ent {  // one (view, Gaussian) entry: 16 floats = 4 x float4 in LDS
     float u00, u01, u02, u11, u12, u22;  // packed upper U
-    float mh0, mh1, mh2;                 // mu - o, high part
-    float ml0, ml1, ml2;                 // mu - o, low part
+    float mh0, mh1, mh2;                 // mu - o rounded to float ("high part")
+    float ul0, ul1, ul2;                 // U (mu - o - high part): the low part, through U
     float c0, c1, c2;                    // Sigma^-1 (mu - o)
     float l2l;                           // log2 lambda
 };
@@ -58,13 +58,14 @@ __device__ __forceinline__ void cam_centre(const float *__restrict__ e, double o
                  (double)e[8 + a] * (double)e[11]);
 }
 
-// (view, Gaussian) entry in double, rounded to float (mu - o kept as hi + lo).
+// (view, Gaussian) entry in double, rounded to float.  mu - o is split as hi + lo; the
+// pair loop forms U (t v - mu') as U (t v - hi) - U lo, so only U lo is stored.
 __device__ __forceinline__ void make_entry(const float *__restrict__ mu, const float *__restrict__ u,
                                            float lam, const double o[3], float4 out[4])
 {
     const double m0 = (double)mu[0] - o[0], m1 = (double)mu[1] - o[1], m2 = (double)mu[2] - o[2];
     const float h0 = (float)m0, h1 = (float)m1, h2 = (float)m2;
-    const float l0 = (float)(m0 - (double)h0), l1 = (float)(m1 - (double)h1), l2 = (float)(m2 - (double)h2);
+    const double l0 = m0 - (double)h0, l1 = m1 - (double)h1, l2 = m2 - (double)h2;
     const double U00 = u[0], U01 = u[1], U02 = u[2], U11 = u[3], U12 = u[4], U22 = u[5];
     const double b0 = U00 * m0 + U01 * m1 + U02 * m2;
     const double b1 = U11 * m1 + U12 * m2;
@@ -72,9 +73,10 @@ __device__ __forceinline__ void make_entry(const float *__restrict__ mu, const f
     const double c0 = U00 * b0;
     const double c1 = U01 * b0 + U11 * b1;
     const double c2 = U02 * b0 + U12 * b1 + U22 * b2;
+    const double ul0 = U00 * l0 + U01 * l1 + U02 * l2, ul1 = U11 * l1 + U12 * l2, ul2 = U22 * l2;
     out[0] = make_float4(u[0], u[1], u[2], u[3]);
     out[1] = make_float4(u[4], u[5], h0, h1);
-    out[2] = make_float4(h2, l0, l1, l2);
+    out[2] = make_float4(h2, (float)ul0, (float)ul1, (float)ul2);
     out[3] = make_float4((float)c0, (float)c1, (float)c2, (float)log2((double)lam));
 }
 
@@ -122,12 +124,12 @@ __device__ __forceinline__ void pair_geo(const Ent &g, float v0, float v1, float
     const float vc = fmaf(v0, g.c0, fmaf(v1, g.c1, v2 * g.c2));
     q.raa = rcp_(aa);
     const float t0 = vc * q.raa;
-    const float w0 = fmaf(t0, v0, -g.mh0) - g.ml0;
-    const float w1 = fmaf(t0, v1, -g.mh1) - g.ml1;
-    const float w2 = fmaf(t0, v2, -g.mh2) - g.ml2;
-    const float r0 = fmaf(g.u00, w0, fmaf(g.u01, w1, g.u02 * w2));
-    const float r1 = fmaf(g.u11, w1, g.u12 * w2);
-    const float r2 = g.u22 * w2;
+    const float w0 = fmaf(t0, v0, -g.mh0);
+    const float w1 = fmaf(t0, v1, -g.mh1);
+    const float w2 = fmaf(t0, v2, -g.mh2);
+    const float r0 = fmaf(g.u00, w0, fmaf(g.u01, w1, fmaf(g.u02, w2, -g.ul0)));
+    const float r1 = fmaf(g.u11, w1, fmaf(g.u12, w2, -g.ul1));
+    const float r2 = fmaf(g.u22, w2, -g.ul2);
     // one Newton step on t -> |U (t v - mu')|^2 (exactly quadratic): dt = (a.r)/(a.a)
     const float dt = fmaf(q.a0, r0, fmaf(q.a1, r1, q.a2 * r2)) * q.raa;
     q.t = t0 - dt;
@@ -425,33 +427,44 @@ __global__ __launch_bounds__(BLOCK) void bwd_kernel(Params P, BwdIn I, const Bwd
                     aB1 = fmaf(zb, q.d2, aB1);
                     aB2 = fmaf(zb, q.t, aB2);
                     aL += db;
-                    // r_bar = U g_bar - d_bar r,  g_bar = wt (Nb - n (n.Nb)) / |g|
-                    float gb0 = 0, gb1 = 0, gb2 = 0;
+                    // r_bar = U g_bar - d_bar r with g_bar = wt (Nb - n (n.Nb)) / |g|; the peak-depth
+                    // adjoint tau = (t_bar + a.r_bar) / (a.a) uses a.r = 0 at the peak, and
+                    // rho = r_bar - tau a.  U_bar = sum r g_bar^T + rho w^T - tau r v^T with
+                    // w = t v - mu' is accumulated as sum r g_bar^T + (t rho - tau r) v^T; the
+                    // -(sum rho) mu'^T term is applied once per item.
+                    float gb0 = 0, gb1 = 0, gb2 = 0, ug0 = 0, ug1 = 0, ug2 = 0, tau;
                     if (NORMALS) {
                         const float ws = wt * rs;
                         gb0 = ws * fmaf(-n0, nN, x1.z);
                         gb1 = ws * fmaf(-n1, nN, x1.w);
                         gb2 = ws * fmaf(-n2, nN, x2.x);
+                        ug0 = fmaf(g.u00, gb0, fmaf(g.u01, gb1, g.u02 * gb2));
+                        ug1 = fmaf(g.u11, gb1, g.u12 * gb2);
+                        ug2 = g.u22 * gb2;
+                        tau = fmaf(q.a0, ug0, fmaf(q.a1, ug1, fmaf(q.a2, ug2, tb))) * q.raa;
+                    } else {
+                        tau = tb * q.raa;
                     }
-                    const float rb0 = fmaf(g.u00, gb0, fmaf(g.u01, gb1, fmaf(g.u02, gb2, -db * q.r0)));
-                    const float rb1 = fmaf(g.u11, gb1, fmaf(g.u12, gb2, -db * q.r1));
-                    const float rb2 = fmaf(g.u22, gb2, -db * q.r2);
-                    // peak-depth adjoint: tau = (t_bar + a.r_bar)/(a.a), rho = r_bar - tau a
-                    const float tau = fmaf(q.a0, rb0, fmaf(q.a1, rb1, fmaf(q.a2, rb2, tb))) * q.raa;
-                    const float p0 = fmaf(-tau, q.a0, rb0);
-                    const float p1 = fmaf(-tau, q.a1, rb1);
-                    const float p2 = fmaf(-tau, q.a2, rb2);
-                    // U_bar += r (g_bar - tau v)^T + rho w^T (upper triangle), w = t v - mu'
-                    const float h0 = fmaf(-tau, v0, gb0), h1 = fmaf(-tau, v1, gb1), h2 = fmaf(-tau, v2, gb2);
-                    const float w0 = fmaf(q.t, v0, -g.mh0) - g.ml0;
-                    const float w1 = fmaf(q.t, v1, -g.mh1) - g.ml1;
-                    const float w2 = fmaf(q.t, v2, -g.mh2) - g.ml2;
-                    aU0 = fmaf(q.r0, h0, fmaf(p0, w0, aU0));
-                    aU1 = fmaf(q.r0, h1, fmaf(p0, w1, aU1));
-                    aU2 = fmaf(q.r0, h2, fmaf(p0, w2, aU2));
-                    aU3 = fmaf(q.r1, h1, fmaf(p1, w1, aU3));
-                    aU4 = fmaf(q.r1, h2, fmaf(p1, w2, aU4));
-                    aU5 = fmaf(q.r2, h2, fmaf(p2, w2, aU5));
+                    const float p0 = fmaf(-tau, q.a0, fmaf(-db, q.r0, ug0));
+                    const float p1 = fmaf(-tau, q.a1, fmaf(-db, q.r1, ug1));
+                    const float p2 = fmaf(-tau, q.a2, fmaf(-db, q.r2, ug2));
+                    const float k0 = fmaf(q.t, p0, -tau * q.r0);
+                    const float k1 = fmaf(q.t, p1, -tau * q.r1);
+                    const float k2 = fmaf(q.t, p2, -tau * q.r2);
+                    if (NORMALS) {
+                        aU0 = fmaf(q.r0, gb0, aU0);
+                        aU1 = fmaf(q.r0, gb1, aU1);
+                        aU2 = fmaf(q.r0, gb2, aU2);
+                        aU3 = fmaf(q.r1, gb1, aU3);
+                        aU4 = fmaf(q.r1, gb2, aU4);
+                        aU5 = fmaf(q.r2, gb2, aU5);
+                    }
+                    aU0 = fmaf(k0, v0, aU0);
+                    aU1 = fmaf(k0, v1, aU1);
+                    aU2 = fmaf(k0, v2, aU2);
+                    aU3 = fmaf(k1, v1, aU3);
+                    aU4 = fmaf(k1, v2, aU4);
+                    aU5 = fmaf(k2, v2, aU5);
                     aP0 += p0;
                     aP1 += p1;
                     aP2 += p2;
@@ -475,9 +488,19 @@ __global__ __launch_bounds__(BLOCK) void bwd_kernel(Params P, BwdIn I, const Bwd
 #pragma unroll
                 for (int c = 0; c < kPartial; ++c) acc[c] += red[12 * (s * item.gc + gi) + c];
             }
+            // U_bar -= (sum rho) mu'^T (upper triangle), mu' = mu - o in double
+            const float *mu = P.means + 3 * (sr.gauss_off + item.g0 + gi);
+            const double m0 = (double)mu[0] - o[0], m1 = (double)mu[1] - o[1], m2 = (double)mu[2] - o[2];
+            const double r0 = acc[6], r1 = acc[7], r2 = acc[8];
             float *dst = partial + item.poff + kPartial * gi;
+            dst[0] = (float)((double)acc[0] - r0 * m0);
+            dst[1] = (float)((double)acc[1] - r0 * m1);
+            dst[2] = (float)((double)acc[2] - r0 * m2);
+            dst[3] = (float)((double)acc[3] - r1 * m1);
+            dst[4] = (float)((double)acc[4] - r1 * m2);
+            dst[5] = (float)((double)acc[5] - r2 * m2);
 #pragma unroll
-            for (int c = 0; c < kPartial; ++c) dst[c] = acc[c];
+            for (int c = 6; c < kPartial; ++c) dst[c] = acc[c];
         }
         if (tid < 64) {
             // lane l sums lanes l, l+64, ... in order, then a fixed butterfly over the wave

@@ -301,6 +301,16 @@ class Batch:
             self._h = None
 
 
+def launch_config(scene: Optional["Scene"] = None, batch: Optional["Batch"] = None) -> dict:
+    """Tile variants, persistent-grid multipliers and work-item counts in use."""
+    out = (ctypes.c_int32 * 8)()
+    _lib.call("fmb_get_config", scene.handle if scene is not None else None,
+              batch._h if batch is not None else None, out)
+    keys = ("fwd_variant", "fwd_rays_per_item", "bwd_variant", "bwd_rays_per_tile", "fwd_grid_mult",
+            "bwd_grid_mult", "fwd_items", "bwd_items")
+    return dict(zip(keys, list(out)))
+
+
 def loss_grad(outs: dict, depth_t, alpha_t, flow_t=None, w_depth: float = 1.0, w_flow: float = 1.0,
               flow_norm: int = 2, cot: Optional[dict] = None, block_loss: Optional[torch.Tensor] = None) -> dict:
     """Cotangents of the mask-weighted reconstruction loss (BCE alpha + w_depth alpha* L1 depth
