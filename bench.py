@@ -43,6 +43,26 @@ PEAK_FP32_SCALAR = 78.6e12  # without packed FP32 issue
 PEAK_HBM = 8.0e12
 
 
+def measured_traffic():
+    """HBM bytes per launch of the persistent backward kernel, from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, if the kernel source has not changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "batch16_bwd_traffic.md")
+    src = os.path.join(ROOT, "paper_2308_14737_amd", "csrc", "fmb_kernels.hip")
+    try:
+        vals = {}
+        for line in open(path):
+            if ":" in line and not line.startswith(("|", " ", "#")):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if vals.get("kernel_source_sha256") != sha:
+            return None
+        return float(vals["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -52,6 +72,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="time eager launches only")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after timing, copy a 256 MiB buffer once (a kernel of known traffic for "
+                         "scaling the FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
 
 
@@ -138,16 +162,6 @@ def main():
         batch.autotune(outs, cot, grads)
         torch.cuda.synchronize()
 
-    st = torch.cuda.Stream(dev)
-    torch.cuda.synchronize()
-    batch.capture(outs, cot, grads, st)
-
-    def step_graph():
-        batch.graph_launch(0, st)
-        with torch.cuda.stream(st):
-            cotangents(outs)
-        batch.graph_launch(1, st)
-
     def timed(fn, k):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -156,10 +170,22 @@ def main():
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / k
 
-    for _ in range(args.warmup):
-        step_graph()
-    ms_graph = timed(step_graph, args.steps) * 1e3
-    print(f"# graph step {ms_graph:.3f} ms", file=sys.stderr, flush=True)
+    ms_graph = None
+    if not args.no_graph:
+        st = torch.cuda.Stream(dev)
+        torch.cuda.synchronize()
+        batch.capture(outs, cot, grads, st)
+
+        def step_graph():
+            batch.graph_launch(0, st)
+            with torch.cuda.stream(st):
+                cotangents(outs)
+            batch.graph_launch(1, st)
+
+        for _ in range(args.warmup):
+            step_graph()
+        ms_graph = timed(step_graph, args.steps) * 1e3
+        print(f"# graph step {ms_graph:.3f} ms", file=sys.stderr, flush=True)
 
     # same steps, eager persistent launches, with HIP-event kernel timing
     def step_eager():
@@ -167,6 +193,8 @@ def main():
         cotangents(outs)
         batch.backward(outs, cot, grads)
 
+    for _ in range(args.warmup if args.no_graph else 0):
+        step_eager()
     fmb.timing_enable(True)
     fmb.kernel_times(reset=True)
     ms_eager = timed(step_eager, args.steps) * 1e3
@@ -205,7 +233,25 @@ def main():
         plain_ms = timed(step_plain, args.steps) * 1e3
         print(f"# plain step {plain_ms:.3f} ms", file=sys.stderr, flush=True)
 
-    value = pairs / (ms_graph * 1e-3)
+    if args.calibrate_copy:
+        # Kernels of known HBM traffic for scaling FETCH_SIZE / WRITE_SIZE: a 1 GiB device copy
+        # (the runtime's blit kernel) and a 1 GiB elementwise copy (dst = src + 1, plain
+        # per-lane loads), each on a source evicted from the caches by writing 1 GiB first.
+        src = torch.ones(256 << 20, device=dev)
+        dst = torch.empty_like(src)
+        evict = torch.zeros(256 << 20, device=dev)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        evict.fill_(2.0)
+        torch.cuda.synchronize()
+        torch.add(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del evict
+        print("# calibration: blit copy and elementwise add, each 1073741824 bytes read and written",
+              file=sys.stderr, flush=True)
+
+    ms_step = ms_graph if ms_graph is not None else ms_eager
+    value = pairs / (ms_step * 1e-3)
     # dominant kernel: the persistent backward (adjoint with recompute)
     flops_bwd_launch = pairs * FLOPS_ADJ_PLAIN
     achieved = flops_bwd_launch / (bwd_ms * 1e-3)
@@ -213,7 +259,7 @@ def main():
     res = {
         "metric": "ray x Gaussian pairs/s fwd+bwd (batched vs plain), % FP32 VALU peak",
         "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_graph, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "batch16: 16 uneven scenes, N~U{10..100}, V~U{4..32}, 64^2/128^2/256^2, "
                                "fwd (depth, alpha, normals) + bwd (L1 depth + BCE alpha), seed 3",
@@ -221,13 +267,15 @@ def main():
                    "parallelism": "single GPU, persistent batched kernels in HIP graphs"},
         "plain_value": (pairs / (plain_ms * 1e-3)) if plain_ms else None,
         "plain_ms_per_step": plain_ms,
-        "batched_over_plain": (plain_ms / ms_graph) if plain_ms else None,
+        "batched_over_plain": (plain_ms / ms_step) if plain_ms else None,
         "eager_ms_per_step": ms_eager,
-        "fp32_peak_frac_step": step_flops / (ms_graph * 1e-3) / PEAK_FP32,
+        "timed": "graph replays" if ms_graph is not None else "eager launches",
+        "fp32_peak_frac_step": step_flops / (ms_step * 1e-3) / PEAK_FP32,
         "kernel_ms": {"forward": fwd_ms, "backward": bwd_ms, "finalize": fin_ms},
         "launch": fmb.launch_config(batch=batch),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": measured_traffic(),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
                      "kernel": "bwd_kernel (persistent)", "flops_per_pair": FLOPS_ADJ_PLAIN,
                      "executed_flops_per_pair": FLOPS_BWD_EXEC_PLAIN,
                      "executed_frac": pairs * FLOPS_BWD_EXEC_PLAIN / (bwd_ms * 1e-3) / PEAK_FP32,

@@ -103,6 +103,17 @@ int fmb_scene_destroy(fmb_scene *scene);
 int fmb_set_cameras(fmb_scene *scene, int32_t v, const float *w2c, const float *intr,
                     const int32_t *hw, const float *w2c_b, const float *intr_b);
 
+/* Set the views and an explicit minibatch of rays instead of full images (the random ray
+ * minibatches across all frames of Sec. 4).  counts host [v]: rays of each view (>= 0,
+ * at least one > 0); rays are ordered view-major, view k's rays contiguous.  dirs device
+ * [P,3]: world-frame directions (normalised by the kernels; non-zero), borrowed; every ray
+ * starts at its view's camera centre.  w2c, intr, w2c_b, intr_b as fmb_set_cameras (intr is
+ * used for the flow projections).  fmb_render / fmb_backward then work on these P rays.
+ * Errors: as fmb_set_cameras. */
+int fmb_set_rays(fmb_scene *scene, int32_t v, const float *w2c, const float *intr,
+                 const int32_t *counts, const float *dirs, const float *w2c_b,
+                 const float *intr_b);
+
 /* Number of rays P of the current cameras (0 before fmb_set_cameras). */
 int64_t fmb_num_rays(const fmb_scene *scene);
 

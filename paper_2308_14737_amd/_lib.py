@@ -29,6 +29,7 @@ SIGNATURES = {
     "fmb_scene_rebind": (_int, [_vp, _vp, _vp, _vp, _vp]),
     "fmb_scene_destroy": (_int, [_vp]),
     "fmb_set_cameras": (_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "fmb_set_rays": (_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fmb_num_rays": (_i64, [_vp]),
     "fmb_render": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fmb_backward": (_int, [_vp] + [_vp] * 10 + [_vp]),

@@ -596,10 +596,52 @@ int fmb_set_cameras(fmb_scene *s, int32_t v, const float *w2c, const float *intr
     j.prm.intr = intr;
     j.prm.w2c_b = w2c_b;
     j.prm.intr_b = intr_b;
+    j.prm.dirs = nullptr;
     j.has_flow = w2c_b != nullptr;
     j.fwd_built = j.bwd_built = -1;
     j.cams_set = false;
     if ((rc = j.upload_descriptors())) return rc;
+    j.cams_set = true;
+    return FMB_OK;
+}
+
+int fmb_set_rays(fmb_scene *s, int32_t v, const float *w2c, const float *intr, const int32_t *counts,
+                 const float *dirs, const float *w2c_b, const float *intr_b)
+{
+    g_err.clear();
+    CHECK_ARG(s, "scene must be non-NULL");
+    CHECK_ARG(v >= 1, "v must be >= 1");
+    CHECK_ARG(counts && dirs && w2c && intr, "w2c, intr, counts and dirs must be non-NULL");
+    CHECK_ARG(aligned(w2c, 4) && aligned(intr, 4) && aligned(dirs, 4), "arrays must be 4-byte aligned");
+    CHECK_ARG((w2c_b == nullptr) == (intr_b == nullptr), "w2c_b and intr_b must both be given or both NULL");
+    int64_t p = 0;
+    for (int k = 0; k < v; ++k) {
+        CHECK_ARG(counts[k] >= 0, "ray counts must be >= 0");
+        p += counts[k];
+    }
+    CHECK_ARG(p >= 1, "at least one ray is needed");
+    if (p > INT32_MAX) return fail(FMB_ERR_SHAPE, "more than 2^31-1 rays");
+    Job &j = s->job;
+    j.V = v;
+    j.P = p;
+    j.views.clear();
+    int64_t off = 0;
+    for (int k = 0; k < v; ++k) {
+        j.views.push_back({counts[k], 1, (int32_t)off, 0});
+        off += counts[k];
+    }
+    j.scenes[0].view_off = 0;
+    j.scenes[0].n_views = v;
+    j.prm.w2c = w2c;
+    j.prm.intr = intr;
+    j.prm.w2c_b = w2c_b;
+    j.prm.intr_b = intr_b;
+    j.prm.dirs = dirs;
+    j.has_flow = w2c_b != nullptr;
+    j.fwd_built = j.bwd_built = -1;
+    j.cams_set = false;
+    int rc = j.upload_descriptors();
+    if (rc) return rc;
     j.cams_set = true;
     return FMB_OK;
 }

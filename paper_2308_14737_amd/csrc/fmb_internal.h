@@ -19,8 +19,8 @@ constexpr double kLog2e = 1.4426950408889634073599246810019;
 // 0/0 guard of every vector normalisation: |y| is sqrt(y.y + kEpsN).
 constexpr float kEpsN = 1e-30f;
 
-struct ViewRec {       // one per view of the batch (16-byte aligned pair of int4)
-    int32_t h, w;      // image size
+struct ViewRec {       // one per view of the batch
+    int32_t h, w;      // image size (explicit rays: h = ray count, w = 1)
     int32_t ray_off;   // global index of the view's first ray
     int32_t scene;     // owning scene
 };
@@ -75,6 +75,7 @@ struct Params {
     const float *means, *prec, *weights, *betas;   // concatenated over scenes; betas [S,2]
     const float *eta;                               // device [S]
     const float *w2c, *intr, *w2c_b, *intr_b;       // per global view
+    const float *dirs;                              // explicit ray directions [P,3] or NULL (pixel rays)
     const ViewRec *views;
     const SceneRec *scenes;
 };

@@ -95,6 +95,22 @@ __device__ __forceinline__ void pixel_dir(const float *__restrict__ e, const flo
     v2 = z * inv;
 }
 
+// Direction of ray `local` of view `vr`: the pixel ray, or the given direction normalised.
+__device__ __forceinline__ void ray_dir(const Params &P, const ViewRec &vr, const float *__restrict__ e,
+                                        const float *__restrict__ k, int local, float &v0, float &v1, float &v2)
+{
+    if (P.dirs) {
+        const float *d = P.dirs + 3 * ((size_t)vr.ray_off + local);
+        const float x = d[0], y = d[1], z = d[2];
+        const float inv = 1.0f / sqrtf(fmaf(x, x, fmaf(y, y, z * z)));
+        v0 = x * inv;
+        v1 = y * inv;
+        v2 = z * inv;
+    } else {
+        pixel_dir(e, k, local / vr.w, local % vr.w, v0, v1, v2);
+    }
+}
+
 __device__ __forceinline__ void project(const float *__restrict__ e, const float *__restrict__ k, float p0,
                                         float p1, float p2, float &u, float &v)
 {
@@ -197,7 +213,7 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
         for (int j = 0; j < RPT; ++j) {
             loc[j] = item.ray0 + (int)threadIdx.x + j * BLOCK;
             const int lc = loc[j] < hw ? loc[j] : hw - 1;
-            pixel_dir(e, kk, lc / vr.w, lc % vr.w, v0[j], v1[j], v2[j]);
+            ray_dir(P, vr, e, kk, lc, v0[j], v1[j], v2[j]);
             M[j] = -INFINITY;
             S[j] = T[j] = N0[j] = N1[j] = N2[j] = D[j] = 0.0f;
         }
@@ -301,7 +317,7 @@ __device__ __forceinline__ void ray_prologue(const Params &P, const BwdIn &I, in
         return;
     }
     float v0, v1, v2;
-    pixel_dir(e, kk, local / vr.w, local % vr.w, v0, v1, v2);
+    ray_dir(P, vr, e, kk, local, v0, v1, v2);
     const int r = vr.ray_off + local;
     const float tf = I.depth[r];
     const float4 s0 = reinterpret_cast<const float4 *>(I.stash)[2 * (size_t)r];

@@ -111,6 +111,19 @@ class Scene:
         self.cameras = cams
         self._hw = hw
 
+    def set_rays(self, cams: Cameras, counts, dirs: torch.Tensor):
+        """Render an explicit ray minibatch: counts[k] rays of view k (view-major, contiguous),
+        directions dirs [P,3] on the GPU (normalised by the kernels)."""
+        _check_dev(dirs, "dirs")
+        cnt = np.ascontiguousarray(np.asarray(counts, dtype=np.int32))
+        if dirs.shape != (int(cnt.sum()), 3):
+            raise ValueError("dirs must be [sum(counts), 3]")
+        _lib.call("fmb_set_rays", self._h, int(cnt.shape[0]), _vp(cams.w2c), _vp(cams.intr),
+                  cnt.ctypes.data_as(ctypes.c_void_p), _vp(dirs), _vp(cams.w2c_b), _vp(cams.intr_b))
+        self.cameras = cams
+        self._dirs = dirs
+        self._hw = cnt
+
     @property
     def n_rays(self) -> int:
         return int(_lib.load().fmb_num_rays(self._h))

@@ -337,3 +337,43 @@ def test_loss_grad_kernel(fmb, norm):
         err = np.abs(got - gref[k])
         assert np.all(err <= 1e-5 * np.abs(gref[k]) + 1e-12), (k, float(err.max()))
     assert abs(float(bl.double().sum()) - L) <= 1e-5 * abs(L)
+
+
+def test_explicit_ray_minibatch(fmb):
+    """A random minibatch of rays across all views (uneven counts, one empty view, sub-pixel
+    directions) through fmb_set_rays, against the oracle on the same float32 directions."""
+    w = W.make_config("flow480")
+    sc, cams = w.scenes[0], w.cameras[0]
+    g = np.random.Generator(np.random.PCG64(77))
+    counts = g.integers(1000, 9000, size=cams.v).astype(np.int32)
+    counts[3] = 0
+    views = np.repeat(np.arange(cams.v), counts).astype(np.int32)
+    p = int(counts.sum())
+    # directions through random sub-pixel positions, built in float64 from the camera, then float32
+    px = np.stack([g.uniform(0, 640, p), g.uniform(0, 480, p)], axis=1)
+    k = cams.intr[views].astype(np.float64)
+    dc = np.stack([(px[:, 0] - k[:, 2]) / k[:, 0], (px[:, 1] - k[:, 3]) / k[:, 1], np.ones(p)], axis=1)
+    rot = cams.w2c[views, :, :3].astype(np.float64)
+    dirs = (np.einsum("pji,pj->pi", rot, dc) * g.uniform(0.5, 2.0, (p, 1))).astype(np.float32)
+    _say(f"[minibatch] flow480 views counts={counts.tolist()} P={p}")
+    t = lambda a: torch.as_tensor(a, device=DEV).contiguous()  # noqa: E731
+    params = (t(sc.means), t(sc.prec), t(sc.weights), t(w.betas))
+    c = fmb.Cameras.from_numpy(cams.w2c, cams.intr, cams.hw, cams.w2c_b, cams.intr_b, device=DEV)
+    scene = fmb.Scene(*params, w.eta)
+    td = t(dirs)
+    scene.set_rays(c, counts, td)
+    assert scene.n_rays == p
+    outs = scene.render(normals=True)
+    o, v = O.dir_rays(views, dirs, cams.w2c)
+    osc = O.OracleScene.of(sc.means, sc.prec, sc.weights, w.betas, w.eta)
+    kw = dict(view=views, w2c_a=cams.w2c, intr_a=cams.intr, w2c_b=cams.w2c_b, intr_b=cams.intr_b)
+    ref = O.render(osc, o, v, **kw)
+    cot = _hit_mask_cot(W.random_cotangents(p, 12, flow=True), ref["alpha"])
+    gr = scene.backward(outs, t(cot["depth"]), t(cot["alpha"]), t(cot["normal"]), t(cot["flow"]))
+    torch.cuda.synchronize()
+    gref = O.backward(osc, o, v, cot, **kw)
+    e = compare_forward(outs, ref)
+    eg = compare_grads(gr, gref)
+    _say(f"[minibatch] {e} {eg}")
+    assert_forward(e, "minibatch")
+    assert_grads(eg, "minibatch")
