@@ -21,6 +21,8 @@
  *   n_i     = Sigma^-1 x / |Sigma^-1 x|,  blended by Eq. (3), unit length  Eq. (17), Sec. 6
  *   alpha   = 1 - exp(-sum_i delta_i)                                     Eq. (8)
  *   flow    = pi_B(p) - pi_A(p),  p = o + t_f v                           Sec. 5
+ *   colour  = sum_i w_i c_i / sum_i w_i,  c_i = sigmoid(q_i) per channel   Eq. (3), Sec. 4
+ *             (q_i unconstrained, as the paper parameterises colours)
  *
  * Readings where the paper is silent (each also listed in the design notes):
  *   - |y| is evaluated as sqrt(y.y + EPS_N) with EPS_N = 1e-30 so that a zero
@@ -125,10 +127,11 @@ typedef struct {
     double A[9];   /* Sigma^-1 = U^T U */
     double mu[3];
     double lam, loglam;
+    double col[3]; /* sigmoid(q): linear RGB in [0,1] */
 } gauss_t;
 
 static void load_gaussians(int32_t n, const double *means, const double *prec, const double *weights,
-                           gauss_t *g)
+                           const double *colors, gauss_t *g)
 {
     for (int32_t i = 0; i < n; ++i) {
         const double *u = prec + 6 * (int64_t)i;
@@ -143,6 +146,7 @@ static void load_gaussians(int32_t n, const double *means, const double *prec, c
         for (int a = 0; a < 3; ++a) g[i].mu[a] = means[3 * (int64_t)i + a];
         g[i].lam = weights[i];
         g[i].loglam = log(weights[i]);
+        for (int a = 0; a < 3; ++a) g[i].col[a] = colors ? 1.0 / (1.0 + exp(-colors[3 * (int64_t)i + a])) : 0.0;
     }
 }
 
@@ -186,11 +190,12 @@ static void pair_eval(const gauss_t *g, const double *o, const double *v, double
 typedef struct {
     double M, S;
     double tf, N[3], nN, nf[3], D, alpha;
+    double C[3];
     double p[3];
     double flow[2];
 } ray_t;
 
-static void ray_blend(int32_t n, const pair_t *q, double *wt, ray_t *r)
+static void ray_blend(int32_t n, const gauss_t *g, const pair_t *q, double *wt, ray_t *r)
 {
     r->M = -INFINITY;
     for (int32_t i = 0; i < n; ++i)
@@ -202,11 +207,13 @@ static void ray_blend(int32_t n, const pair_t *q, double *wt, ray_t *r)
     }
     r->tf = 0.0;
     r->N[0] = r->N[1] = r->N[2] = 0.0;
+    r->C[0] = r->C[1] = r->C[2] = 0.0;
     r->D = 0.0;
     for (int32_t i = 0; i < n; ++i) {
         wt[i] /= r->S;
         r->tf += wt[i] * q[i].t;
         for (int a = 0; a < 3; ++a) r->N[a] += wt[i] * q[i].n[a];
+        for (int a = 0; a < 3; ++a) r->C[a] += wt[i] * g[i].col[a];
         r->D += q[i].delta;
     }
     r->nN = sqrt(dot3(r->N, r->N) + EPS_N);
@@ -227,7 +234,7 @@ static void ray_forward(const ctx_t *c, int64_t r, pair_t *q, double *wt, ray_t 
 {
     const double *o = c->orig + 3 * r, *v = c->dir + 3 * r;
     for (int32_t i = 0; i < c->n; ++i) pair_eval(&c->g[i], o, v, c->b1, c->b2, c->eta, &q[i]);
-    ray_blend(c->n, q, wt, ry);
+    ray_blend(c->n, c->g, q, wt, ry);
     for (int a = 0; a < 3; ++a) ry->p[a] = o[a] + ry->tf * v[a];
     if (c->w2c_b) {
         int64_t k = c->view[r];
@@ -253,16 +260,16 @@ static int nthreads_of(int req)
 
 /* Forward render of p rays.  Any output pointer may be NULL.  Returns 0, or -1 on bad input. */
 int fmbo_render(int32_t n, const double *means, const double *prec, const double *weights,
-                const double *betas, double eta, int64_t p, const double *orig, const double *dir,
-                const int32_t *view, const double *w2c_a, const double *intr_a, const double *w2c_b,
-                const double *intr_b, double *depth, double *alpha, double *normal, double *flow,
-                int n_threads)
+                const double *colors, const double *betas, double eta, int64_t p, const double *orig,
+                const double *dir, const int32_t *view, const double *w2c_a, const double *intr_a,
+                const double *w2c_b, const double *intr_b, double *depth, double *alpha, double *normal,
+                double *flow, double *color, int n_threads)
 {
     if (n < 1 || p < 0 || !means || !prec || !weights || !betas || !orig || !dir) return -1;
     if (w2c_b && (!view || !w2c_a || !intr_a || !intr_b)) return -1;
     gauss_t *g = (gauss_t *)malloc(sizeof(gauss_t) * (size_t)n);
     if (!g) return -1;
-    load_gaussians(n, means, prec, weights, g);
+    load_gaussians(n, means, prec, weights, colors, g);
     ctx_t c = {n, g, betas[0], betas[1], eta, orig, dir, view, w2c_a, intr_a, w2c_b, intr_b};
     int nt = nthreads_of(n_threads);
 #pragma omp parallel num_threads(nt)
@@ -281,6 +288,8 @@ int fmbo_render(int32_t n, const double *means, const double *prec, const double
                 flow[2 * r] = ry.flow[0];
                 flow[2 * r + 1] = ry.flow[1];
             }
+            if (color)
+                for (int a = 0; a < 3; ++a) color[3 * r + a] = ry.C[a];
         }
         free(q);
         free(wt);
@@ -295,7 +304,7 @@ void fmbo_ray_terms(int32_t n, const double *means, const double *prec, const do
                     double *d, double *z, double *nrm)
 {
     gauss_t *g = (gauss_t *)malloc(sizeof(gauss_t) * (size_t)n);
-    load_gaussians(n, means, prec, weights, g);
+    load_gaussians(n, means, prec, weights, NULL, g);
     for (int32_t i = 0; i < n; ++i) {
         pair_t q;
         pair_eval(&g[i], o, v, betas[0], betas[1], eta, &q);
@@ -328,11 +337,12 @@ typedef struct {
     double mu[3];
     double A[9];
     double lam;
+    double col[3]; /* dL/d(sigmoid colour) */
 } gacc_t;
 
 static void ray_backward(const ctx_t *c, int64_t r, const pair_t *q, const double *wt, const ray_t *ry,
-                         double gd, double ga, const double *gnrm, const double *gfl, gacc_t *acc,
-                         double *gb)
+                         double gd, double ga, const double *gnrm, const double *gfl, const double *gcol,
+                         gacc_t *acc, double *gb)
 {
     const double *o = c->orig + 3 * r, *v = c->dir + 3 * r;
     (void)o;
@@ -356,14 +366,20 @@ static void ray_backward(const ctx_t *c, int64_t r, const pair_t *q, const doubl
         double s = dot3(ry->nf, gnrm);
         for (int a = 0; a < 3; ++a) N_bar[a] = (gnrm[a] - ry->nf[a] * s) / ry->nN;
     }
-    /* t_f = sum wt t, N = sum wt n, wt = softmax(z) */
+    /* colour = sum wt c */
+    double C_bar[3] = {0.0, 0.0, 0.0};
+    if (gcol)
+        for (int a = 0; a < 3; ++a) C_bar[a] = gcol[a];
+    /* t_f = sum wt t, N = sum wt n, C = sum wt c, wt = softmax(z) */
     double mean_wbar = 0.0;
-    for (int32_t i = 0; i < c->n; ++i) mean_wbar += wt[i] * (tf_bar * q[i].t + dot3(N_bar, q[i].n));
+    for (int32_t i = 0; i < c->n; ++i)
+        mean_wbar += wt[i] * (tf_bar * q[i].t + dot3(N_bar, q[i].n) + dot3(C_bar, c->g[i].col));
     for (int32_t i = 0; i < c->n; ++i) {
         const pair_t *pq = &q[i];
         const gauss_t *g = &c->g[i];
         gacc_t *ac = &acc[i];
-        double w_bar = tf_bar * pq->t + dot3(N_bar, pq->n);
+        for (int a = 0; a < 3; ++a) ac->col[a] += wt[i] * C_bar[a];
+        double w_bar = tf_bar * pq->t + dot3(N_bar, pq->n) + dot3(C_bar, g->col);
         double z_bar = wt[i] * (w_bar - mean_wbar);
         double t_bar = wt[i] * tf_bar;
         double n_bar[3] = {wt[i] * N_bar[0], wt[i] * N_bar[1], wt[i] * N_bar[2]};
@@ -405,18 +421,20 @@ static void ray_backward(const ctx_t *c, int64_t r, const pair_t *q, const doubl
  * means, packed precision factors, weights and (beta1, beta2).  Outputs are
  * overwritten.  Cotangent pointers may be NULL (zero). */
 int fmbo_backward(int32_t n, const double *means, const double *prec, const double *weights,
-                  const double *betas, double eta, int64_t p, const double *orig, const double *dir,
-                  const int32_t *view, const double *w2c_a, const double *intr_a, const double *w2c_b,
-                  const double *intr_b, const double *g_depth, const double *g_alpha,
-                  const double *g_normal, const double *g_flow, double *g_means, double *g_prec,
-                  double *g_weights, double *g_betas, int n_threads)
+                  const double *colors, const double *betas, double eta, int64_t p, const double *orig,
+                  const double *dir, const int32_t *view, const double *w2c_a, const double *intr_a,
+                  const double *w2c_b, const double *intr_b, const double *g_depth,
+                  const double *g_alpha, const double *g_normal, const double *g_flow,
+                  const double *g_color, double *g_means, double *g_prec, double *g_weights,
+                  double *g_colors, double *g_betas, int n_threads)
 {
     if (n < 1 || p < 0 || !means || !prec || !weights || !betas || !orig || !dir) return -1;
     if (!g_means || !g_prec || !g_weights || !g_betas) return -1;
     if (w2c_b && (!view || !w2c_a || !intr_a || !intr_b)) return -1;
+    if (g_color && !colors) return -1;
     gauss_t *g = (gauss_t *)malloc(sizeof(gauss_t) * (size_t)n);
     if (!g) return -1;
-    load_gaussians(n, means, prec, weights, g);
+    load_gaussians(n, means, prec, weights, colors, g);
     ctx_t c = {n, g, betas[0], betas[1], eta, orig, dir, view, w2c_a, intr_a, w2c_b, intr_b};
     int nt = nthreads_of(n_threads);
     /* one accumulator per contiguous chunk of rays, summed in chunk order afterwards */
@@ -436,7 +454,7 @@ int fmbo_backward(int32_t n, const double *means, const double *prec, const doub
             ray_forward(&c, r, q, wt, &ry);
             ray_backward(&c, r, q, wt, &ry, g_depth ? g_depth[r] : 0.0, g_alpha ? g_alpha[r] : 0.0,
                          g_normal ? g_normal + 3 * r : NULL, g_flow ? g_flow + 2 * r : NULL,
-                         acc + (size_t)tid * n, gb + 2 * tid);
+                         g_color ? g_color + 3 * r : NULL, acc + (size_t)tid * n, gb + 2 * tid);
         }
         free(q);
         free(wt);
@@ -450,7 +468,11 @@ int fmbo_backward(int32_t n, const double *means, const double *prec, const doub
             for (int j = 0; j < 3; ++j) s.mu[j] += a->mu[j];
             for (int j = 0; j < 9; ++j) s.A[j] += a->A[j];
             s.lam += a->lam;
+            for (int j = 0; j < 3; ++j) s.col[j] += a->col[j];
         }
+        /* c = sigmoid(q)  =>  dL/dq = dL/dc c (1 - c) */
+        if (g_colors)
+            for (int j = 0; j < 3; ++j) g_colors[3 * (int64_t)i + j] = s.col[j] * g[i].col[j] * (1.0 - g[i].col[j]);
         for (int j = 0; j < 3; ++j) g_means[3 * (int64_t)i + j] = s.mu[j];
         g_weights[i] = s.lam;
         /* A = U^T U  =>  dL/dU = U (Abar + Abar^T); keep the upper-triangular entries */

@@ -44,11 +44,11 @@ def _configure(lib):
     lib.fmbo_pixel_rays.argtypes = [ctypes.c_int64, _I, _I, _I, _D, _D, _D, _D]
     lib.fmbo_dir_rays.argtypes = [ctypes.c_int64, _I, _D, _D, _D, _D]
     lib.fmbo_project.argtypes = [ctypes.c_int64, _I, _D, _D, _D, _D]
-    common = [ctypes.c_int32, _D, _D, _D, _D, ctypes.c_double, ctypes.c_int64, _D, _D, _I,
+    common = [ctypes.c_int32, _D, _D, _D, _D, _D, ctypes.c_double, ctypes.c_int64, _D, _D, _I,
               _D, _D, _D, _D]
-    lib.fmbo_render.argtypes = common + [_D, _D, _D, _D, ctypes.c_int]
+    lib.fmbo_render.argtypes = common + [_D, _D, _D, _D, _D, ctypes.c_int]
     lib.fmbo_render.restype = ctypes.c_int
-    lib.fmbo_backward.argtypes = common + [_D, _D, _D, _D, _D, _D, _D, _D, ctypes.c_int]
+    lib.fmbo_backward.argtypes = common + [_D, _D, _D, _D, _D, _D, _D, _D, _D, _D, ctypes.c_int]
     lib.fmbo_backward.restype = ctypes.c_int
     lib.fmbo_ray_terms.argtypes = [ctypes.c_int32, _D, _D, _D, _D, ctypes.c_double, _D, _D,
                                    _D, _D, _D, _D]
@@ -96,17 +96,19 @@ def _i32(a) -> Optional[np.ndarray]:
 
 @dataclass
 class OracleScene:
-    """Gaussians (float64 copies) and blend parameters."""
+    """Gaussians (float64 copies), optional unconstrained colours [N,3], blend parameters."""
     means: np.ndarray
     prec: np.ndarray
     weights: np.ndarray
     betas: np.ndarray
     eta: float = 1.0
+    colors: Optional[np.ndarray] = None
 
     @classmethod
-    def of(cls, means, prec, weights, betas, eta=1.0) -> "OracleScene":
+    def of(cls, means, prec, weights, betas, eta=1.0, colors=None) -> "OracleScene":
         return cls(_d(means).reshape(-1, 3), _d(prec).reshape(-1, 6), _d(weights).reshape(-1),
-                   _d(betas).reshape(2), float(eta))
+                   _d(betas).reshape(2), float(eta),
+                   None if colors is None else _d(colors).reshape(-1, 3))
 
     @property
     def n(self) -> int:
@@ -162,11 +164,13 @@ def render(scene: OracleScene, orig, dirs, view=None, w2c_a=None, intr_a=None, w
     p = orig.shape[0]
     view, a, ia, b, ib = _cams(view, w2c_a, intr_a, w2c_b, intr_b)
     out = {"depth": np.empty(p), "alpha": np.empty(p), "normal": np.empty((p, 3)),
-           "flow": np.empty((p, 2)) if b is not None else None}
+           "flow": np.empty((p, 2)) if b is not None else None,
+           "color": np.empty((p, 3)) if scene.colors is not None else None}
     rc = lib.fmbo_render(scene.n, _p(scene.means), _p(scene.prec), _p(scene.weights),
-                         _p(scene.betas), scene.eta, p, _p(orig), _p(dirs), _p(view, _I), _p(a),
-                         _p(ia), _p(b), _p(ib), _p(out["depth"]), _p(out["alpha"]),
-                         _p(out["normal"]), _p(out["flow"]), int(n_threads))
+                         _p(scene.colors), _p(scene.betas), scene.eta, p, _p(orig), _p(dirs),
+                         _p(view, _I), _p(a), _p(ia), _p(b), _p(ib), _p(out["depth"]),
+                         _p(out["alpha"]), _p(out["normal"]), _p(out["flow"]), _p(out["color"]),
+                         int(n_threads))
     if rc != 0:
         raise ValueError("oracle render rejected its arguments")
     return out
@@ -180,15 +184,15 @@ def backward(scene: OracleScene, orig, dirs, cot: dict, view=None, w2c_a=None, i
     p = orig.shape[0]
     view, a, ia, b, ib = _cams(view, w2c_a, intr_a, w2c_b, intr_b)
     gd, ga = _d(cot.get("depth")), _d(cot.get("alpha"))
-    gn, gf = _d(cot.get("normal")), _d(cot.get("flow"))
+    gn, gf, gc = _d(cot.get("normal")), _d(cot.get("flow")), _d(cot.get("color"))
     n = scene.n
     out = {"means": np.empty((n, 3)), "prec": np.empty((n, 6)), "weights": np.empty(n),
-           "betas": np.empty(2)}
+           "betas": np.empty(2), "colors": np.empty((n, 3)) if scene.colors is not None else None}
     rc = lib.fmbo_backward(n, _p(scene.means), _p(scene.prec), _p(scene.weights),
-                           _p(scene.betas), scene.eta, p, _p(orig), _p(dirs), _p(view, _I), _p(a),
-                           _p(ia), _p(b), _p(ib), _p(gd), _p(ga), _p(gn), _p(gf),
-                           _p(out["means"]), _p(out["prec"]), _p(out["weights"]), _p(out["betas"]),
-                           int(n_threads))
+                           _p(scene.colors), _p(scene.betas), scene.eta, p, _p(orig), _p(dirs),
+                           _p(view, _I), _p(a), _p(ia), _p(b), _p(ib), _p(gd), _p(ga), _p(gn),
+                           _p(gf), _p(gc), _p(out["means"]), _p(out["prec"]), _p(out["weights"]),
+                           _p(out["colors"]), _p(out["betas"]), int(n_threads))
     if rc != 0:
         raise ValueError("oracle backward rejected its arguments")
     return out
@@ -205,7 +209,8 @@ def ray_terms(scene: OracleScene, o, v):
     return t, d, z, nrm
 
 
-def render_workload_view(scene, cams, betas, eta, rays=None, n_threads: int = 0, cot=None):
+def render_workload_view(scene, cams, betas, eta, rays=None, n_threads: int = 0, cot=None,
+                         colors=None):
     """Render (and optionally differentiate) pixel rays of a workload camera set.
 
     `scene` has means/prec/weights (float32 arrays), `cams` has w2c, intr, hw and the
@@ -215,7 +220,7 @@ def render_workload_view(scene, cams, betas, eta, rays=None, n_threads: int = 0,
     from workloads import pixel_indices  # input bookkeeping only
     view, row, col = pixel_indices(cams, rays)
     o, v = pixel_rays(view, row, col, cams.w2c, cams.intr)
-    sc = OracleScene.of(scene.means, scene.prec, scene.weights, betas, eta)
+    sc = OracleScene.of(scene.means, scene.prec, scene.weights, betas, eta, colors)
     kw = dict(view=view, w2c_a=cams.w2c, intr_a=cams.intr, w2c_b=cams.w2c_b, intr_b=cams.intr_b,
               n_threads=n_threads)
     out = render(sc, o, v, **kw)

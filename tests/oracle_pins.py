@@ -432,12 +432,14 @@ def _loss(sc, orig, dirs, cam, cot):
     s += float(np.sum(cot["normal"] * out["normal"]))
     if out["flow"] is not None:
         s += float(np.sum(cot["flow"] * out["flow"]))
+    if out["color"] is not None:
+        s += float(np.sum(cot["color"] * out["color"]))
     return s
 
 
 def pin_gradients_fd():
     """Central differences of the oracle forward (step 1e-6 max(1,|x|)) match its adjoint for
-    means, packed precision factors, weights and both betas, through every output."""
+    means, packed precision factors, weights, colours and both betas, through every output."""
     g = _rng(25)
     sc, ea, kk, view, row, col, o, v = _flow_setup(g, n=4)
     view, o, v = view[:8], o[:8], v[:8]
@@ -445,11 +447,13 @@ def pin_gradients_fd():
     cam = dict(view=view, w2c_a=ea[None], intr_a=kk[None], w2c_b=eb[None], intr_b=kk[None])
     p = len(o)
     cot = {"depth": g.standard_normal(p), "alpha": g.standard_normal(p),
-           "normal": g.standard_normal((p, 3)), "flow": g.standard_normal((p, 2))}
+           "normal": g.standard_normal((p, 3)), "flow": g.standard_normal((p, 2)),
+           "color": g.standard_normal((p, 3))}
+    colors = g.standard_normal((sc.n, 3))
     for eta in (1.0, 1.7):
-        sc = _scene(sc.means, sc.prec, sc.weights, (B1 * 0.3, B2), eta)
+        sc = O.OracleScene.of(sc.means, sc.prec, sc.weights, (B1 * 0.3, B2), eta, colors)
         an = O.backward(sc, o, v, cot, **cam)
-        for name in ("means", "prec", "weights", "betas"):
+        for name in ("means", "prec", "weights", "betas", "colors"):
             base = getattr(sc, name)
             fd = np.zeros_like(base)
             flat, fdf = base.reshape(-1), fd.reshape(-1)
@@ -464,6 +468,29 @@ def pin_gradients_fd():
                 fdf[j] = (fp - fm) / (2 * h)
             scale = max(1.0, float(np.max(np.abs(fd))))
             _close(an[name], fd, 1e-6, 1e-6 * scale, f"FD gradient {name} (eta={eta})")
+
+
+def pin_colour_blend():
+    """Colours c_i = sigmoid(q_i) blend by Eq. (3): one Gaussian renders sigmoid(q) exactly; two
+    render s c_1 + (1 - s) c_2 with s = sigma(z_1 - z_2) from one-Gaussian renders; beta = 0 gives
+    the plain mean of the colours."""
+    g = _rng(29)
+    sc, _ = _random_scene(g, 2, spread=0.3)
+    q = g.standard_normal((2, 3)) * 2.0
+    c = 1.0 / (1.0 + np.exp(-q))
+    o = np.array([0.3, -0.2, -3.0])
+    orig, dirs = _rays_at(g, np.repeat(sc.means, 3, axis=0), o, jitter=0.05)
+    one = O.OracleScene.of(sc.means[[0]], sc.prec[[0]], sc.weights[[0]], sc.betas, sc.eta, q[[0]])
+    _close(O.render(one, orig, dirs)["color"], np.tile(c[0], (len(orig), 1)), 1e-14, 1e-15, "one colour")
+    t1, d1, _ = _single_terms(sc, 0, orig, dirs)
+    t2, d2, _ = _single_terms(sc, 1, orig, dirs)
+    s = 1 / (1 + np.exp(-((B1 * d1 - B2 * t1) - (B1 * d2 - B2 * t2))))
+    two = O.OracleScene.of(sc.means, sc.prec, sc.weights, sc.betas, sc.eta, q)
+    _close(O.render(two, orig, dirs)["color"], s[:, None] * c[0] + (1 - s)[:, None] * c[1], 1e-9, 1e-9,
+           "two-colour blend")
+    flat = O.OracleScene.of(sc.means, sc.prec, sc.weights, (0.0, 0.0), sc.eta, q)
+    _close(O.render(flat, orig, dirs)["color"], np.tile(c.mean(axis=0), (len(orig), 1)), 1e-12, 1e-12,
+           "zero-beta colour mean")
 
 
 def pin_isotropic_depth_gradient():
@@ -537,4 +564,5 @@ ALL_PINS = [
     pin_rays_reproject, pin_flow_equal_poses, pin_flow_rotation_homography, pin_flow_translation,
     pin_scale_invariance, pin_rigid_motion, pin_normals_geometry, pin_gradients_fd,
     pin_isotropic_depth_gradient, pin_two_gaussian_beta_gradient, pin_loss_gradient,
+    pin_colour_blend,
 ]

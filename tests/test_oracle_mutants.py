@@ -35,6 +35,9 @@ MUTANTS = {
                                  "double z_bar = wt[i] * w_bar;"),
     "adj_flow_rows_swapped": ("gfl[0] * (Jb[a] - Ja[a]) + gfl[1] * (Jb[3 + a] - Ja[3 + a])",
                               "gfl[1] * (Jb[a] - Ja[a]) + gfl[0] * (Jb[3 + a] - Ja[3 + a])"),
+    "colour_unweighted": ("for (int a = 0; a < 3; ++a) r->C[a] += wt[i] * g[i].col[a];",
+                          "for (int a = 0; a < 3; ++a) r->C[a] += g[i].col[a];"),
+    "adj_colour_no_sigmoid_slope": ("s.col[j] * g[i].col[j] * (1.0 - g[i].col[j])", "s.col[j]"),
     "adj_U_fold_transposed": ("t += g[i].U[a * 3 + k] * Bs[k * 3 + b];",
                               "t += g[i].U[k * 3 + a] * Bs[k * 3 + b];"),
 }
