@@ -16,6 +16,8 @@
  *                kernels use log lambda_i, Eq. 2).
  *   blend        betas = (beta1, beta2) of Eq. (7), on the device (they are
  *                differentiated); eta > 0 is the shape scale of Eq. (7), a host value.
+ *   colour       optional per-Gaussian colours [n,3], unconstrained; the rendered colour
+ *                is sigmoid(q) per channel blended by Eq. (3) (Sec. 4: linear RGB).
  *   camera k     world-to-camera [R|T], row-major 3x4 (x_cam = R x_world + T), OpenCV
  *                axes (x right, y down, z forward); intrinsics (fx, fy, cx, cy); image
  *                H x W.  Pixel (row i, col j) has its centre at (j + 1/2, i + 1/2); its ray
@@ -26,7 +28,10 @@
  *   outputs      depth[P] = blended peak distance t_f along the unit ray (Eq. 3);
  *                alpha[P] (Eq. 8); normal[P,3] unit world-frame blended normal;
  *                flow[P,2] = pi_B(p) - pi_A(p) in pixels, p = origin + t_f * direction;
- *                stash[P,8] = per-ray softmax state the backward pass reads (opaque).
+ *                color[P,3] blended colour; stash[P,8] = per-ray state the backward pass
+ *                reads: (running max of the base-2 log weights, 1/sum of the shifted weights
+ *                = max_i of the normalised weights (the Sec. 6 quality test), unnormalised
+ *                blended normal (3), sum of densities, 0, 0).
  *
  * Memory: every float/int pointer called "device" is HIP device memory owned by the
  * caller; the library never frees it and reads/writes it only inside the calls.
@@ -48,7 +53,7 @@
 extern "C" {
 #endif
 
-#define FMB_ABI_VERSION 1
+#define FMB_ABI_VERSION 2
 
 enum fmb_status {
     FMB_OK = 0,
@@ -117,28 +122,35 @@ int fmb_set_rays(fmb_scene *scene, int32_t v, const float *w2c, const float *int
 /* Number of rays P of the current cameras (0 before fmb_set_cameras). */
 int64_t fmb_num_rays(const fmb_scene *scene);
 
+/* Set (or with NULL clear) the per-Gaussian colours of a scene or batch (exactly one
+ * non-NULL): device [n,3] (batch: [sum n,3]) unconstrained parameters q, borrowed; the
+ * kernels use sigmoid(q) (Sec. 4).  Needed for a colour output / cotangent. */
+int fmb_set_colors(fmb_scene *scene, fmb_batch *batch, const float *colors);
+
 /* Forward pass (Eq. 2, 4, 7, 3, 8, 17 and the flow of Sec. 5) for all P rays.
  *   depth, alpha: device [P] (required); normal: device [P,3] or NULL (not computed:
- *   the normal terms are skipped); flow: device [P,2] or NULL (required NULL when the
- *   cameras have no second pose); stash: device [P,8], 16-byte aligned, required by
- *   fmb_backward (may be NULL if no backward pass follows).
+ *   the normal terms are skipped); flow: device [P,2] or NULL (must be NULL when the
+ *   cameras have no second pose); color: device [P,3] or NULL (needs fmb_set_colors);
+ *   stash: device [P,8], 16-byte aligned, required by fmb_backward (may be NULL if no
+ *   backward pass follows).
  * Errors: FMB_ERR_STATE (no cameras), FMB_ERR_INVALID_ARG, FMB_ERR_HIP. */
 int fmb_render(fmb_scene *scene, float *depth, float *alpha, float *normal, float *flow,
-               float *stash, void *stream);
+               float *color, float *stash, void *stream);
 
 /* Backward (adjoint) pass: gradients of  sum_r  g_depth[r] depth[r] + g_alpha[r] alpha[r]
- * + g_normal[r].normal[r] + g_flow[r].flow[r]  with respect to the means, packed
- * precision factors, weights and (beta1, beta2).  The per-pair terms are recomputed,
- * never stored.  Cotangents are device arrays shaped like the outputs; any may be NULL
- * (zero).  depth and stash are the forward outputs for the SAME parameter values.
- * Gradients are device arrays g_means [n,3], g_prec [n,6], g_weights [n], g_betas [2],
+ * + g_normal[r].normal[r] + g_flow[r].flow[r] + g_color[r].color[r]  with respect to the
+ * means, packed precision factors, weights, colours and (beta1, beta2).  The per-pair
+ * terms are recomputed, never stored.  Cotangents are device arrays shaped like the
+ * outputs; any may be NULL (zero).  depth, color and stash are the forward outputs for the
+ * SAME parameter values (color only needed with g_color).  Gradients are device arrays
+ * g_means [n,3], g_prec [n,6], g_weights [n], g_colors [n,3] (or NULL), g_betas [2],
  * overwritten (not accumulated).  The result is deterministic (fixed reduction order).
- * If normals were not rendered (normal == NULL in fmb_render) g_normal must be NULL.
- * Errors: FMB_ERR_STATE, FMB_ERR_INVALID_ARG, FMB_ERR_HIP. */
+ * g_normal needs the normals to have been rendered (their unnormalised sum is read from
+ * the stash).  Errors: FMB_ERR_STATE, FMB_ERR_INVALID_ARG, FMB_ERR_HIP. */
 int fmb_backward(fmb_scene *scene, const float *g_depth, const float *g_alpha,
-                 const float *g_normal, const float *g_flow, const float *depth,
-                 const float *stash, float *g_means, float *g_prec, float *g_weights,
-                 float *g_betas, void *stream);
+                 const float *g_normal, const float *g_flow, const float *g_color,
+                 const float *depth, const float *color, const float *stash, float *g_means,
+                 float *g_prec, float *g_weights, float *g_colors, float *g_betas, void *stream);
 
 /* ------------------------------------------------------------------------------ */
 /* Batch of independent scenes (uneven Gaussian counts, view counts, resolutions) */
@@ -170,10 +182,11 @@ int64_t fmb_batch_gauss_offset(const fmb_batch *batch, int32_t i);
  * of (scene, view, ray tile) pulled from a device queue, largest first).  Arguments as
  * fmb_render / fmb_backward with concatenated arrays; g_betas is [s,2]. */
 int fmb_batch_forward(fmb_batch *batch, float *depth, float *alpha, float *normal, float *flow,
-                      float *stash, void *stream);
+                      float *color, float *stash, void *stream);
 int fmb_batch_backward(fmb_batch *batch, const float *g_depth, const float *g_alpha,
-                       const float *g_normal, const float *g_flow, const float *depth,
-                       const float *stash, float *g_means, float *g_prec, float *g_weights,
+                       const float *g_normal, const float *g_flow, const float *g_color,
+                       const float *depth, const float *color, const float *stash,
+                       float *g_means, float *g_prec, float *g_weights, float *g_colors,
                        float *g_betas, void *stream);
 
 /* Capture the batch's forward pass and its backward pass, with these buffers, into two
@@ -185,9 +198,10 @@ int fmb_batch_backward(fmb_batch *batch, const float *g_depth, const float *g_al
  * on `stream`; FMB_ERR_STATE if nothing was captured.  Replays of one batch must not
  * overlap (they share the batch's work counters and partial-gradient workspace). */
 int fmb_batch_capture(fmb_batch *batch, float *depth, float *alpha, float *normal, float *flow,
-                      float *stash, const float *g_depth, const float *g_alpha,
-                      const float *g_normal, const float *g_flow, float *g_means,
-                      float *g_prec, float *g_weights, float *g_betas, void *stream);
+                      float *color, float *stash, const float *g_depth, const float *g_alpha,
+                      const float *g_normal, const float *g_flow, const float *g_color,
+                      float *g_means, float *g_prec, float *g_weights, float *g_colors,
+                      float *g_betas, void *stream);
 int fmb_batch_graph_launch(fmb_batch *batch, int32_t which, void *stream);
 
 /* ------------------------------------------------------------------------------ */
@@ -202,29 +216,33 @@ int fmb_batch_graph_launch(fmb_batch *batch, int32_t which, void *stream);
  * file, keyed by device, kernel version, shapes and which outputs/cotangents are used.
  * Exactly one of `scene` and `batch` is non-NULL. */
 int fmb_autotune(fmb_scene *scene, fmb_batch *batch, float *depth, float *alpha, float *normal,
-                 float *flow, float *stash, const float *g_depth, const float *g_alpha,
-                 const float *g_normal, const float *g_flow, float *g_means, float *g_prec,
-                 float *g_weights, float *g_betas, const char *cache_path, void *stream);
+                 float *flow, float *color, float *stash, const float *g_depth,
+                 const float *g_alpha, const float *g_normal, const float *g_flow,
+                 const float *g_color, float *g_means, float *g_prec, float *g_weights,
+                 float *g_colors, float *g_betas, const char *cache_path, void *stream);
 
 /* Gradient of the reconstruction loss of Sec. 4 (Eq. 11-14) with respect to one render's
  * outputs, averaged over its p rays (the cotangents fmb_backward takes):
  *   L = 1/p sum_r [ -(a*_r log a_r + (1 - a*_r) log(1 - a_r))      a_r = clamp(alpha_r,
  *                                                                   1e-6, 1 - 1e-6)  (Eq. 11)
  *                 + w_depth a*_r |depth_r - depth*_r|               (mask-weighted L1)
+ *                 + w_color a*_r |color_r - color*_r|_1              (Eq. 12)
  *                 + w_flow  a*_r |flow_r - flow*_r|_q ]             (Eq. 13; q = 1: L1 of
  *                                                                   the 2 components, q = 2:
  *                                                                   squared L2)
- * where a* = alpha_t is the target mask.  depth, alpha, depth_t, alpha_t: device [p];
- * flow, flow_t: device [p,2] or NULL (no flow term; then g_flow must be NULL too).
- * g_depth, g_alpha: device [p] (written); g_flow: device [p,2] or NULL.  The clamp passes
- * the gradient where 1e-6 <= alpha <= 1 - 1e-6; |x|' is sign(x) (0 at 0).
- * block_loss: device [ceil(p / 1024)] or NULL; if given, receives per-block partial
- * sums of L (sum them for the loss; the order is fixed).
+ * where a* = alpha_t is the target mask (the paper's lambda_C = 4.5 and lambda_F = 210 are
+ * w_color and w_flow).  depth, alpha, depth_t, alpha_t: device [p]; flow, flow_t: device
+ * [p,2] or NULL (no flow term; then g_flow must be NULL too); color, color_t: [p,3] or
+ * NULL likewise.  g_depth, g_alpha: device [p] (written); g_flow [p,2], g_color [p,3] or
+ * NULL.  The clamp passes the gradient where 1e-6 <= alpha <= 1 - 1e-6 (float32 bounds);
+ * |x|' is sign(x) (0 at 0).  block_loss: device [ceil(p / 1024)] or NULL; if given,
+ * receives per-block partial sums of L (sum them for the loss; the order is fixed).
  * Errors: FMB_ERR_INVALID_ARG (p < 1, NULL required pointer, flow_norm not 1 or 2). */
 int fmb_loss_grad(int64_t p, const float *depth, const float *alpha, const float *flow,
-                  const float *depth_t, const float *alpha_t, const float *flow_t, float w_depth,
-                  float w_flow, int32_t flow_norm, float *g_depth, float *g_alpha, float *g_flow,
-                  float *block_loss, void *stream);
+                  const float *color, const float *depth_t, const float *alpha_t,
+                  const float *flow_t, const float *color_t, float w_depth, float w_flow,
+                  int32_t flow_norm, float w_color, float *g_depth, float *g_alpha,
+                  float *g_flow, float *g_color, float *block_loss, void *stream);
 
 /* Current launch configuration of a scene or batch (exactly one non-NULL), written to the
  * host array out[8]: forward tile variant, rays per forward work item, backward variant,

@@ -229,11 +229,12 @@ def render_workload_view(scene, cams, betas, eta, rays=None, n_threads: int = 0,
 
 
 def loss_grad(depth, alpha, depth_t, alpha_t, flow=None, flow_t=None, w_depth=1.0, w_flow=1.0,
-              flow_norm=2):
+              flow_norm=2, color=None, color_t=None, w_color=1.0):
     """Reconstruction loss of Sec. 4 (Eq. 11-14) averaged over rays, and its gradient with respect
     to the rendered depth, alpha and flow (float64, straight from the definition):
       L = mean_r [ -(a* log a + (1 - a*) log(1 - a)),  a = clamp(alpha, 1e-6, 1 - 1e-6)   (Eq. 11)
                    + w_depth a* |depth - depth*|                        (mask-weighted L1)
+                   + w_color a* |color - color*|_1                      (Eq. 12)
                    + w_flow a* |flow - flow*|_1 or squared L2 ]          (Eq. 13)
     The clamp passes the gradient where 1e-6 <= alpha <= 1 - 1e-6 (bounds as float32 values);
     d|x|/dx = sign(x)."""
@@ -257,4 +258,9 @@ def loss_grad(depth, alpha, depth_t, alpha_t, flow=None, flow_t=None, w_depth=1.
         else:
             per_ray = per_ray + w_flow * at * (df * df).sum(axis=1)
             g_flow = 2.0 * w_flow * at[:, None] * df / p
-    return float(per_ray.sum() / p), {"depth": g_depth, "alpha": g_alpha, "flow": g_flow}
+    g_color = None
+    if color is not None:
+        dc = np.asarray(color, np.float64) - np.asarray(color_t, np.float64)
+        per_ray = per_ray + w_color * at * np.abs(dc).sum(axis=1)
+        g_color = w_color * at[:, None] * np.sign(dc) / p
+    return float(per_ray.sum() / p), {"depth": g_depth, "alpha": g_alpha, "flow": g_flow, "color": g_color}

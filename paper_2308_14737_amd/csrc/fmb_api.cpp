@@ -28,24 +28,34 @@ int fwd_variant_rays(int v);
 int num_bwd_variants();
 int bwd_variant_rt(int v);
 int block_size();
-hipError_t launch_fwd(int variant, bool nrm, bool flw, bool per, int grid, hipStream_t st, const Params &P,
-                      const FwdOut &O, const FwdItem *items, int n, const int *order, int *counter);
-hipError_t launch_bwd(int variant, bool nrm, bool flw, bool per, int grid, hipStream_t st, const Params &P,
-                      const BwdIn &I, const BwdItem *items, int n, const int *order, int *counter,
-                      float *partial, float *bpart);
+hipError_t launch_fwd(int variant, int flags, int grid, hipStream_t st, const Params &P, const FwdOut &O,
+                      const FwdItem *items, int n, const int *order, int *counter);
+hipError_t launch_bwd(int variant, int flags, int grid, hipStream_t st, const Params &P, const BwdIn &I,
+                      const BwdItem *items, int n, const int *order, int *counter, float *partial, float *bpart);
 hipError_t launch_fin(int n_tasks, int n_groups, hipStream_t st, const Params &P, const FinTask *tasks,
                       const FinGroup *groups, const float *partial, const float *bpart, double *stage,
-                      double *stage_beta, float *g_means, float *g_prec, float *g_weights, float *g_betas);
+                      double *stage_beta, float *g_means, float *g_prec, float *g_weights, float *g_colors,
+                      float *g_betas);
 hipError_t launch_fill(int *p, int n, int value, hipStream_t st);
-hipError_t launch_loss(int p, const float *depth, const float *alpha, const float *flow, const float *depth_t,
-                       const float *alpha_t, const float *flow_t, float w_depth, float w_flow, int flow_norm,
-                       float *g_depth, float *g_alpha, float *g_flow, float *block_loss, hipStream_t st);
+hipError_t launch_loss(int p, const float *depth, const float *alpha, const float *flow, const float *color,
+                       const float *depth_t, const float *alpha_t, const float *flow_t, const float *color_t,
+                       float w_depth, float w_flow, int flow_norm, float w_color, float *g_depth, float *g_alpha,
+                       float *g_flow, float *g_color, float *block_loss, hipStream_t st);
 hipError_t launch_validate(const Params &P, int n_total, int n_scenes, int *flags, hipStream_t st);
-hipError_t occupancy_fwd(int variant, bool nrm, bool flw, int *blocks_per_cu);
-hipError_t occupancy_bwd(int variant, bool nrm, bool flw, int *blocks_per_cu);
+hipError_t occupancy_fwd(int variant, int flags, int *blocks_per_cu);
+hipError_t occupancy_bwd(int variant, int flags, int *blocks_per_cu);
 }  // namespace fmb
 
 using namespace fmb;
+
+namespace {
+constexpr int kFlagNrm = 1, kFlagFlw = 2, kFlagPer = 4, kFlagCol = 8;
+
+// Gradient outputs of a backward call.
+struct Grads {
+    float *means, *prec, *weights, *colors, *betas;
+};
+}  // namespace
 
 namespace {
 
@@ -283,9 +293,11 @@ struct Job {
         slots = block / gc;
     }
 
-    int build_bwd(int variant)
+    int build_bwd(int variant, bool colour)
     {
-        if (bwd_built == variant) return FMB_OK;
+        const int key = variant * 2 + (colour ? 1 : 0);
+        if (bwd_built == key) return FMB_OK;
+        const int rec = colour ? kPartialColor : kPartial;
         const int RT = bwd_variant_rt(variant);
         const int B = block_size();
         std::vector<int> gcs(S), sls(S), spans(S);
@@ -333,17 +345,18 @@ struct Job {
                         it.g0 = g0;
                         it.gc = gc;
                         it.slots = sl;
-                        if (poff > (size_t)INT32_MAX - (size_t)gc * kPartial)
+                        if (poff > (size_t)INT32_MAX - (size_t)gc * rec)
                             return fail(FMB_ERR_SHAPE, "backward partial buffer exceeds 2^31 floats");
                         it.poff = (int)poff;
                         it.seq = (int)items.size();
-                        poff += (size_t)gc * kPartial;
+                        poff += (size_t)gc * rec;
                         items.push_back(it);
                         cost.push_back((double)t.gc * std::min(span, hw - r0));
                     }
                 }
                 tasks_item_end.push_back((int)items.size());
                 t.beta = (g0 == 0) ? 1 : 0;
+                t.rec = rec;
                 tasks.push_back(t);
             }
         }
@@ -365,7 +378,7 @@ struct Job {
                 g.item_begin = a;
                 g.item_end = std::min(ie, a + gsz);
                 g.poff = items[a].poff;
-                g.nval = items[a].gc * kPartial;
+                g.nval = items[a].gc * rec;
                 g.soff = (int)soff;
                 soff += (size_t)g.nval;
                 groups.push_back(g);
@@ -394,89 +407,97 @@ struct Job {
         partial_floats = poff;
         n_bitems = (int)items.size();
         n_tasks = (int)tasks.size();
-        bwd_built = variant;
+        bwd_built = key;
         return FMB_OK;
     }
 
     std::map<int, int> occ_f, occ_b;  // blocks per CU of the persistent kernels
     int persist_mult[2] = {1, 1};     // persistent grid = mult x occupancy x CUs (fwd, bwd)
 
-    int grid_fwd(bool nrm, bool flw, int &grid)
+    int grid_fwd(int flags, int &grid)
     {
-        const int key = fwd_variant * 4 + (nrm ? 2 : 0) + (flw ? 1 : 0);
+        const int key = fwd_variant * 16 + (flags | kFlagPer);
         auto it = occ_f.find(key);
         if (it == occ_f.end()) {
             int o = 0;
-            HIPCHK(occupancy_fwd(fwd_variant, nrm, flw, &o));
+            HIPCHK(occupancy_fwd(fwd_variant, flags | kFlagPer, &o));
             it = occ_f.emplace(key, std::max(1, o)).first;
         }
         grid = std::max(1, std::min(n_fitems, persist_mult[0] * it->second * n_cu));
         return FMB_OK;
     }
 
-    int grid_bwd(bool nrm, bool flw, int &grid)
+    int grid_bwd(int flags, int &grid)
     {
-        const int key = bwd_variant * 4 + (nrm ? 2 : 0) + (flw ? 1 : 0);
+        const int key = bwd_variant * 16 + (flags | kFlagPer);
         auto it = occ_b.find(key);
         if (it == occ_b.end()) {
             int o = 0;
-            HIPCHK(occupancy_bwd(bwd_variant, nrm, flw, &o));
+            HIPCHK(occupancy_bwd(bwd_variant, flags | kFlagPer, &o));
             it = occ_b.emplace(key, std::max(1, o)).first;
         }
         grid = std::max(1, std::min(n_bitems, persist_mult[1] * it->second * n_cu));
         return FMB_OK;
     }
 
-    int forward(float *depth, float *alpha, float *normal, float *flow, float *stash, bool persist,
-                hipStream_t st)
+    static int fwd_flags(const FwdOut &O, bool persist)
+    {
+        return (O.normal ? kFlagNrm : 0) | (O.flow ? kFlagFlw : 0) | (persist ? kFlagPer : 0) |
+               (O.color ? kFlagCol : 0);
+    }
+    static int bwd_flags(const BwdIn &I, bool persist)
+    {
+        return (I.g_normal ? kFlagNrm : 0) | (I.g_flow ? kFlagFlw : 0) | (persist ? kFlagPer : 0) |
+               (I.g_color ? kFlagCol : 0);
+    }
+
+    int forward(const FwdOut &O, bool persist, hipStream_t st)
     {
         if (!cams_set) return fail(FMB_ERR_STATE, "render before cameras were set");
-        CHECK_ARG(depth && alpha, "depth and alpha outputs are required");
-        CHECK_ARG(!flow || has_flow, "flow output given but the cameras have no second pose");
-        CHECK_ARG(!stash || aligned(stash, 16), "stash must be 16-byte aligned");
+        CHECK_ARG(O.depth && O.alpha, "depth and alpha outputs are required");
+        CHECK_ARG(!O.flow || has_flow, "flow output given but the cameras have no second pose");
+        CHECK_ARG(!O.color || prm.colors, "colour output given but no colours were set");
+        CHECK_ARG(!O.stash || aligned(O.stash, 16), "stash must be 16-byte aligned");
         int rc = build_fwd(fwd_variant);
         if (rc) return rc;
-        FwdOut O{depth, alpha, normal, flow, stash};
-        const bool nrm = normal != nullptr, flw = flow != nullptr;
+        const int flags = fwd_flags(O, persist);
         int grid = n_fitems;
         if (persist) {
-            if ((rc = grid_fwd(nrm, flw, grid))) return rc;
+            if ((rc = grid_fwd(flags, grid))) return rc;
             HIPCHK(launch_fill(d_counter.as<int>(), 1, 0, st));
         }
         TimedSpan ts(st, 0);
-        HIPCHK(launch_fwd(fwd_variant, nrm, flw, persist, grid, st, prm, O, d_fitems.as<FwdItem>(), n_fitems,
+        HIPCHK(launch_fwd(fwd_variant, flags, grid, st, prm, O, d_fitems.as<FwdItem>(), n_fitems,
                           persist ? d_forder.as<int>() : nullptr, persist ? d_counter.as<int>() : nullptr));
         ts.stop();
         return FMB_OK;
     }
 
-    int backward(const float *g_depth, const float *g_alpha, const float *g_normal, const float *g_flow,
-                 const float *depth, const float *stash, float *g_means, float *g_prec, float *g_weights,
-                 float *g_betas, bool persist, hipStream_t st)
+    int backward(const BwdIn &I, const Grads &G, bool persist, hipStream_t st)
     {
         if (!cams_set) return fail(FMB_ERR_STATE, "backward before cameras were set");
-        CHECK_ARG(depth && stash, "depth and stash from the forward pass are required");
-        CHECK_ARG(aligned(stash, 16), "stash must be 16-byte aligned");
-        CHECK_ARG(g_means && g_prec && g_weights && g_betas, "gradient outputs are required");
-        CHECK_ARG(!g_flow || has_flow, "flow cotangent given but the cameras have no second pose");
-        int rc = build_bwd(bwd_variant);
+        CHECK_ARG(I.depth && I.stash, "depth and stash from the forward pass are required");
+        CHECK_ARG(aligned(I.stash, 16), "stash must be 16-byte aligned");
+        CHECK_ARG(G.means && G.prec && G.weights && G.betas, "gradient outputs are required");
+        CHECK_ARG(!I.g_flow || has_flow, "flow cotangent given but the cameras have no second pose");
+        CHECK_ARG(!I.g_color || (prm.colors && I.color), "colour cotangent needs colours and the colour output");
+        int rc = build_bwd(bwd_variant, I.g_color != nullptr);
         if (rc) return rc;
-        BwdIn I{g_depth, g_alpha, g_normal, g_flow, depth, stash};
-        const bool nrm = g_normal != nullptr, flw = g_flow != nullptr;
+        const int flags = bwd_flags(I, persist);
         int grid = n_bitems;
         if (persist) {
-            if ((rc = grid_bwd(nrm, flw, grid))) return rc;
+            if ((rc = grid_bwd(flags, grid))) return rc;
             HIPCHK(launch_fill(d_counter.as<int>() + 1, 1, 0, st));
         }
         TimedSpan tb(st, 1);
-        HIPCHK(launch_bwd(bwd_variant, nrm, flw, persist, grid, st, prm, I, d_bitems.as<BwdItem>(), n_bitems,
+        HIPCHK(launch_bwd(bwd_variant, flags, grid, st, prm, I, d_bitems.as<BwdItem>(), n_bitems,
                           persist ? d_border.as<int>() : nullptr, persist ? d_counter.as<int>() + 1 : nullptr,
                           d_partial.as<float>(), d_bpart.as<float>()));
         tb.stop();
         TimedSpan tf(st, 2);
         HIPCHK(launch_fin(n_tasks, n_groups, st, prm, d_tasks.as<FinTask>(), d_groups.as<FinGroup>(),
                           d_partial.as<float>(), d_bpart.as<float>(), d_stage.as<double>(),
-                          d_stage_beta.as<double>(), g_means, g_prec, g_weights, g_betas));
+                          d_stage_beta.as<double>(), G.means, G.prec, G.weights, G.colors, G.betas));
         tf.stop();
         return FMB_OK;
     }
@@ -648,21 +669,33 @@ int fmb_set_rays(fmb_scene *s, int32_t v, const float *w2c, const float *intr, c
 
 int64_t fmb_num_rays(const fmb_scene *s) { return (s && s->job.cams_set) ? s->job.P : 0; }
 
-int fmb_render(fmb_scene *s, float *depth, float *alpha, float *normal, float *flow, float *stash, void *stream)
+int fmb_set_colors(fmb_scene *s, fmb_batch *b, const float *colors)
+{
+    g_err.clear();
+    CHECK_ARG((s != nullptr) != (b != nullptr), "exactly one of scene and batch must be given");
+    CHECK_ARG(!colors || aligned(colors, 4), "colors must be 4-byte aligned");
+    Job &j = s ? s->job : b->job;
+    j.prm.colors = colors;
+    return FMB_OK;
+}
+
+int fmb_render(fmb_scene *s, float *depth, float *alpha, float *normal, float *flow, float *color, float *stash,
+               void *stream)
 {
     g_err.clear();
     CHECK_ARG(s, "scene must be non-NULL");
-    return s->job.forward(depth, alpha, normal, flow, stash, false, (hipStream_t)stream);
+    return s->job.forward(FwdOut{depth, alpha, normal, flow, color, stash}, false, (hipStream_t)stream);
 }
 
 int fmb_backward(fmb_scene *s, const float *g_depth, const float *g_alpha, const float *g_normal,
-                 const float *g_flow, const float *depth, const float *stash, float *g_means, float *g_prec,
-                 float *g_weights, float *g_betas, void *stream)
+                 const float *g_flow, const float *g_color, const float *depth, const float *color,
+                 const float *stash, float *g_means, float *g_prec, float *g_weights, float *g_colors,
+                 float *g_betas, void *stream)
 {
     g_err.clear();
     CHECK_ARG(s, "scene must be non-NULL");
-    return s->job.backward(g_depth, g_alpha, g_normal, g_flow, depth, stash, g_means, g_prec, g_weights,
-                           g_betas, false, (hipStream_t)stream);
+    return s->job.backward(BwdIn{g_depth, g_alpha, g_normal, g_flow, g_color, depth, color, stash},
+                           Grads{g_means, g_prec, g_weights, g_colors, g_betas}, false, (hipStream_t)stream);
 }
 
 int fmb_batch_create(fmb_batch **out, int32_t s, const int32_t *n_host, const int32_t *v_host, const float *means,
@@ -748,27 +781,29 @@ int64_t fmb_batch_gauss_offset(const fmb_batch *b, int32_t i)
     return i == b->job.S ? b->job.n_total : b->job.scenes[i].gauss_off;
 }
 
-int fmb_batch_forward(fmb_batch *b, float *depth, float *alpha, float *normal, float *flow, float *stash,
-                      void *stream)
+int fmb_batch_forward(fmb_batch *b, float *depth, float *alpha, float *normal, float *flow, float *color,
+                      float *stash, void *stream)
 {
     g_err.clear();
     CHECK_ARG(b, "batch must be non-NULL");
-    return b->job.forward(depth, alpha, normal, flow, stash, true, (hipStream_t)stream);
+    return b->job.forward(FwdOut{depth, alpha, normal, flow, color, stash}, true, (hipStream_t)stream);
 }
 
 int fmb_batch_backward(fmb_batch *b, const float *g_depth, const float *g_alpha, const float *g_normal,
-                       const float *g_flow, const float *depth, const float *stash, float *g_means, float *g_prec,
-                       float *g_weights, float *g_betas, void *stream)
+                       const float *g_flow, const float *g_color, const float *depth, const float *color,
+                       const float *stash, float *g_means, float *g_prec, float *g_weights, float *g_colors,
+                       float *g_betas, void *stream)
 {
     g_err.clear();
     CHECK_ARG(b, "batch must be non-NULL");
-    return b->job.backward(g_depth, g_alpha, g_normal, g_flow, depth, stash, g_means, g_prec, g_weights, g_betas,
-                           true, (hipStream_t)stream);
+    return b->job.backward(BwdIn{g_depth, g_alpha, g_normal, g_flow, g_color, depth, color, stash},
+                           Grads{g_means, g_prec, g_weights, g_colors, g_betas}, true, (hipStream_t)stream);
 }
 
-int fmb_batch_capture(fmb_batch *b, float *depth, float *alpha, float *normal, float *flow, float *stash,
-                      const float *g_depth, const float *g_alpha, const float *g_normal, const float *g_flow,
-                      float *g_means, float *g_prec, float *g_weights, float *g_betas, void *stream)
+int fmb_batch_capture(fmb_batch *b, float *depth, float *alpha, float *normal, float *flow, float *color,
+                      float *stash, const float *g_depth, const float *g_alpha, const float *g_normal,
+                      const float *g_flow, const float *g_color, float *g_means, float *g_prec, float *g_weights,
+                      float *g_colors, float *g_betas, void *stream)
 {
     g_err.clear();
     CHECK_ARG(b, "batch must be non-NULL");
@@ -777,19 +812,20 @@ int fmb_batch_capture(fmb_batch *b, float *depth, float *alpha, float *normal, f
     if (st == nullptr) return fail(FMB_ERR_CAPTURE, "graph capture needs a non-default stream");
     if (stream_capturing(st)) return fail(FMB_ERR_CAPTURE, "stream is already capturing");
     Job &j = b->job;
+    const FwdOut O{depth, alpha, normal, flow, color, stash};
+    const BwdIn I{g_depth, g_alpha, g_normal, g_flow, g_color, depth, color, stash};
+    const Grads G{g_means, g_prec, g_weights, g_colors, g_betas};
     // item lists and occupancy are prepared outside the capture (they use synchronous copies)
     int rc = j.build_fwd(j.fwd_variant);
     int gdummy = 0;
-    if (!rc) rc = j.build_bwd(j.bwd_variant);
-    if (!rc) rc = j.grid_fwd(normal != nullptr, flow != nullptr, gdummy);
-    if (!rc) rc = j.grid_bwd(g_normal != nullptr, g_flow != nullptr, gdummy);
+    if (!rc) rc = j.build_bwd(j.bwd_variant, g_color != nullptr);
+    if (!rc) rc = j.grid_fwd(Job::fwd_flags(O, true), gdummy);
+    if (!rc) rc = j.grid_bwd(Job::bwd_flags(I, true), gdummy);
     if (rc) return rc;
     j.drop_graphs();
     for (int which = 0; which < 2; ++which) {
         HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        int r = which == 0 ? j.forward(depth, alpha, normal, flow, stash, true, st)
-                           : j.backward(g_depth, g_alpha, g_normal, g_flow, depth, stash, g_means, g_prec,
-                                        g_weights, g_betas, true, st);
+        int r = which == 0 ? j.forward(O, true, st) : j.backward(I, G, true, st);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(st, &g);
         if (r) {
@@ -895,20 +931,21 @@ int fmb_kernel_times(double *out6, int reset)
 // Autotuner: time every (forward variant) x (backward variant) on the real shapes.
 // ---------------------------------------------------------------------------------------
 
-static std::string tune_key(const Job &j, bool nrm, bool flw, int cot_mask)
+static std::string tune_key(const Job &j, int fflags, int unused, int cot_mask)
 {
     hipDeviceProp_t prop{};
     (void)hipGetDeviceProperties(&prop, j.device);
     std::ostringstream k;
-    k << prop.gcnArchName << ":cu" << j.n_cu << ":v3:S" << j.S << ":V" << j.V << ":P" << j.P << ":N" << j.n_total
-      << ":nrm" << nrm << ":flw" << flw << ":cot" << cot_mask;
+    k << prop.gcnArchName << ":cu" << j.n_cu << ":v4:S" << j.S << ":V" << j.V << ":P" << j.P << ":N" << j.n_total
+      << ":out" << fflags << ":cot" << cot_mask;
+    (void)unused;
     return k.str();
 }
 
-int fmb_autotune(fmb_scene *s, fmb_batch *b, float *depth, float *alpha, float *normal, float *flow, float *stash,
-                 const float *g_depth, const float *g_alpha, const float *g_normal, const float *g_flow,
-                 float *g_means, float *g_prec, float *g_weights, float *g_betas, const char *cache_path,
-                 void *stream)
+int fmb_autotune(fmb_scene *s, fmb_batch *b, float *depth, float *alpha, float *normal, float *flow, float *color,
+                 float *stash, const float *g_depth, const float *g_alpha, const float *g_normal,
+                 const float *g_flow, const float *g_color, float *g_means, float *g_prec, float *g_weights,
+                 float *g_colors, float *g_betas, const char *cache_path, void *stream)
 {
     g_err.clear();
     CHECK_ARG((s != nullptr) != (b != nullptr), "exactly one of scene and batch must be given");
@@ -917,9 +954,12 @@ int fmb_autotune(fmb_scene *s, fmb_batch *b, float *depth, float *alpha, float *
     const bool persist = b != nullptr;
     hipStream_t st = (hipStream_t)stream;
     if (!j.cams_set) return fail(FMB_ERR_STATE, "autotune before cameras were set");
-    const bool nrm = normal != nullptr, flw = flow != nullptr;
-    const int cot_mask = (g_depth ? 1 : 0) | (g_alpha ? 2 : 0) | (g_normal ? 4 : 0) | (g_flow ? 8 : 0);
-    const std::string key = tune_key(j, nrm, flw, cot_mask);
+    const FwdOut O{depth, alpha, normal, flow, color, stash};
+    const BwdIn I{g_depth, g_alpha, g_normal, g_flow, g_color, depth, color, stash};
+    const Grads G{g_means, g_prec, g_weights, g_colors, g_betas};
+    const int cot_mask = (g_depth ? 1 : 0) | (g_alpha ? 2 : 0) | (g_normal ? 4 : 0) | (g_flow ? 8 : 0) |
+                         (g_color ? 16 : 0);
+    const std::string key = tune_key(j, Job::fwd_flags(O, false), 0, cot_mask);
     if (cache_path) {
         std::ifstream in(cache_path);
         std::string line;
@@ -961,7 +1001,7 @@ int fmb_autotune(fmb_scene *s, fmb_batch *b, float *depth, float *alpha, float *
             j.fwd_variant = v;
             j.persist_mult[0] = m;
             float ms = 0.0f;
-            rc = time_it([&]() { return j.forward(depth, alpha, normal, flow, stash, persist, st); }, ms);
+            rc = time_it([&]() { return j.forward(O, persist, st); }, ms);
             if (!rc && ms < best_f) {
                 best_f = ms;
                 bf = v;
@@ -970,16 +1010,13 @@ int fmb_autotune(fmb_scene *s, fmb_batch *b, float *depth, float *alpha, float *
         }
     j.fwd_variant = bf;
     j.persist_mult[0] = bmf;
-    if (!rc) rc = j.forward(depth, alpha, normal, flow, stash, persist, st);
+    if (!rc) rc = j.forward(O, persist, st);
     for (int v = 0; v < num_bwd_variants() && !rc; ++v)
         for (int m = 1; m <= n_mult && !rc; ++m) {
             j.bwd_variant = v;
             j.persist_mult[1] = m;
             float ms = 0.0f;
-            rc = time_it([&]() {
-                return j.backward(g_depth, g_alpha, g_normal, g_flow, depth, stash, g_means, g_prec, g_weights,
-                                  g_betas, persist, st);
-            }, ms);
+            rc = time_it([&]() { return j.backward(I, G, persist, st); }, ms);
             if (!rc && ms < best_b) {
                 best_b = ms;
                 bb = v;
@@ -998,18 +1035,21 @@ int fmb_autotune(fmb_scene *s, fmb_batch *b, float *depth, float *alpha, float *
     return FMB_OK;
 }
 
-int fmb_loss_grad(int64_t p, const float *depth, const float *alpha, const float *flow, const float *depth_t,
-                  const float *alpha_t, const float *flow_t, float w_depth, float w_flow, int32_t flow_norm,
-                  float *g_depth, float *g_alpha, float *g_flow, float *block_loss, void *stream)
+int fmb_loss_grad(int64_t p, const float *depth, const float *alpha, const float *flow, const float *color,
+                  const float *depth_t, const float *alpha_t, const float *flow_t, const float *color_t,
+                  float w_depth, float w_flow, int32_t flow_norm, float w_color, float *g_depth, float *g_alpha,
+                  float *g_flow, float *g_color, float *block_loss, void *stream)
 {
     g_err.clear();
     CHECK_ARG(p >= 1 && p <= INT32_MAX, "p must be in [1, 2^31)");
     CHECK_ARG(depth && alpha && depth_t && alpha_t && g_depth && g_alpha, "required pointer is NULL");
     CHECK_ARG((flow == nullptr) == (flow_t == nullptr) && (flow == nullptr) == (g_flow == nullptr),
               "flow, flow_t and g_flow must all be given or all be NULL");
+    CHECK_ARG((color == nullptr) == (color_t == nullptr) && (color == nullptr) == (g_color == nullptr),
+              "color, color_t and g_color must all be given or all be NULL");
     CHECK_ARG(flow_norm == 1 || flow_norm == 2, "flow_norm must be 1 or 2");
-    HIPCHK(launch_loss((int)p, depth, alpha, flow, depth_t, alpha_t, flow_t, w_depth, w_flow, flow_norm, g_depth,
-                       g_alpha, g_flow, block_loss, (hipStream_t)stream));
+    HIPCHK(launch_loss((int)p, depth, alpha, flow, color, depth_t, alpha_t, flow_t, color_t, w_depth, w_flow,
+                       flow_norm, w_color, g_depth, g_alpha, g_flow, g_color, block_loss, (hipStream_t)stream));
     return FMB_OK;
 }
 

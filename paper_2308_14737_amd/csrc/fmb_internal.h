@@ -55,6 +55,8 @@ struct FinTask {       // one per (scene, Gaussian chunk)
     int32_t group_begin, group_end;  // first-stage groups of this chunk's items
     int32_t beta;      // 1 if this task also reduces the scene's beta partials
     int32_t sgroup_begin, sgroup_end;  // all groups of the scene (beta partials)
+    int32_t rec;       // floats per Gaussian in the partial records (kPartial or kPartialColor)
+    int32_t pad[3];
 };
 
 // First stage of the deterministic gradient reduction: a group of consecutive
@@ -68,7 +70,8 @@ struct FinGroup {
 };
 constexpr int kGroupItems = 32;  // minimum items per first-stage group
 
-constexpr int kPartial = 10;   // per-Gaussian partial: dU (6), sum rho (3), dlog(lambda) (1)
+constexpr int kPartial = 10;       // per-Gaussian partial: dU (6), sum rho (3), dlog(lambda) (1)
+constexpr int kPartialColor = 13;  // ... and dL/d(colour) (3)
 
 // Kernel argument blocks (passed by value).
 struct Params {
@@ -76,17 +79,18 @@ struct Params {
     const float *eta;                               // device [S]
     const float *w2c, *intr, *w2c_b, *intr_b;       // per global view
     const float *dirs;                              // explicit ray directions [P,3] or NULL (pixel rays)
+    const float *colors;                            // unconstrained colours [N,3] or NULL
     const ViewRec *views;
     const SceneRec *scenes;
 };
 
 struct FwdOut {
-    float *depth, *alpha, *normal, *flow, *stash;
+    float *depth, *alpha, *normal, *flow, *color, *stash;
 };
 
 struct BwdIn {
-    const float *g_depth, *g_alpha, *g_normal, *g_flow;
-    const float *depth, *stash;
+    const float *g_depth, *g_alpha, *g_normal, *g_flow, *g_color;
+    const float *depth, *color, *stash;
 };
 
 }  // namespace fmb

@@ -176,15 +176,34 @@ __device__ __forceinline__ Blend blend_of(const Params &P, int s)
 }
 
 // ------------------------------------------------------------------------------------
+// Kernel variants: F is a bit set of the outputs/cotangents a launch handles.
+// ------------------------------------------------------------------------------------
+
+constexpr int kNrm = 1;  // normals (Eq. 17)
+constexpr int kFlw = 2;  // flow to a second pose (Sec. 5)
+constexpr int kPer = 4;  // persistent work queue
+constexpr int kCol = 8;  // per-Gaussian colour blended by Eq. (3)
+
+// Colour of a Gaussian: sigmoid of the unconstrained parameters (double, rounded).
+__device__ __forceinline__ float4 colour_entry(const float *__restrict__ q)
+{
+    return make_float4((float)(1.0 / (1.0 + exp(-(double)q[0]))), (float)(1.0 / (1.0 + exp(-(double)q[1]))),
+                       (float)(1.0 / (1.0 + exp(-(double)q[2]))), 0.0f);
+}
+
+// ------------------------------------------------------------------------------------
 // Forward
 // ------------------------------------------------------------------------------------
 
-template <int BLOCK, int RPT, int TG, bool NORMALS, bool FLOW, bool PERSIST>
+template <int BLOCK, int RPT, int TG, int F>
 __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const FwdItem *__restrict__ items,
                                                    int n_items, const int *__restrict__ order,
                                                    int *__restrict__ counter)
 {
-    __shared__ float4 tile[TG * 4];
+    constexpr bool NORMALS = (F & kNrm) != 0, FLOW = (F & kFlw) != 0, PERSIST = (F & kPer) != 0;
+    constexpr bool COLOR = (F & kCol) != 0;
+    constexpr int EW = COLOR ? 5 : 4;  // float4 per LDS entry
+    __shared__ float4 tile[TG * EW];
     __shared__ int s_item;
     int pos = blockIdx.x;
     for (;;) {
@@ -207,7 +226,7 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
         const int hw = vr.h * vr.w;
 
         float v0[RPT], v1[RPT], v2[RPT];
-        float M[RPT], S[RPT], T[RPT], N0[RPT], N1[RPT], N2[RPT], D[RPT];
+        float M[RPT], S[RPT], T[RPT], N0[RPT], N1[RPT], N2[RPT], D[RPT], C0[RPT], C1[RPT], C2[RPT];
         int loc[RPT];
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
@@ -215,7 +234,7 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
             const int lc = loc[j] < hw ? loc[j] : hw - 1;
             ray_dir(P, vr, e, kk, lc, v0[j], v1[j], v2[j]);
             M[j] = -INFINITY;
-            S[j] = T[j] = N0[j] = N1[j] = N2[j] = D[j] = 0.0f;
+            S[j] = T[j] = N0[j] = N1[j] = N2[j] = D[j] = C0[j] = C1[j] = C2[j] = 0.0f;
         }
 
         for (int gb = 0; gb < sr.n; gb += TG) {
@@ -223,12 +242,15 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
             if (gb > 0 || !PERSIST) __syncthreads();
             for (int q = threadIdx.x; q < cnt; q += BLOCK) {
                 const int gi = sr.gauss_off + gb + q;
-                make_entry(P.means + 3 * gi, P.prec + 6 * gi, P.weights[gi], o, &tile[4 * q]);
+                make_entry(P.means + 3 * gi, P.prec + 6 * gi, P.weights[gi], o, &tile[EW * q]);
+                if (COLOR) tile[EW * q + 4] = colour_entry(P.colors + 3 * gi);
             }
             __syncthreads();
 #pragma unroll 2
             for (int i = 0; i < cnt; ++i) {
-                const Ent g = ent_from(tile[4 * i], tile[4 * i + 1], tile[4 * i + 2], tile[4 * i + 3]);
+                const Ent g = ent_from(tile[EW * i], tile[EW * i + 1], tile[EW * i + 2], tile[EW * i + 3]);
+                float4 cc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (COLOR) cc = tile[EW * i + 4];
 #pragma unroll
                 for (int j = 0; j < RPT; ++j) {
                     Geo q;
@@ -242,6 +264,11 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
                             N0[j] *= sc;
                             N1[j] *= sc;
                             N2[j] *= sc;
+                        }
+                        if (COLOR) {
+                            C0[j] *= sc;
+                            C1[j] *= sc;
+                            C2[j] *= sc;
                         }
                         M[j] = q.z2;
                     }
@@ -257,6 +284,11 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
                         N0[j] = fmaf(es, g0, N0[j]);
                         N1[j] = fmaf(es, g1, N1[j]);
                         N2[j] = fmaf(es, g2, N2[j]);
+                    }
+                    if (COLOR) {
+                        C0[j] = fmaf(ew, cc.x, C0[j]);
+                        C1[j] = fmaf(ew, cc.y, C1[j]);
+                        C2[j] = fmaf(ew, cc.z, C2[j]);
                     }
                 }
             }
@@ -286,6 +318,11 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
                 O.flow[2 * r + 0] = ub - ua;
                 O.flow[2 * r + 1] = vb - va;
             }
+            if (COLOR) {
+                O.color[3 * r + 0] = C0[j] * invS;
+                O.color[3 * r + 1] = C1[j] * invS;
+                O.color[3 * r + 2] = C2[j] * invS;
+            }
             if (O.stash) {
                 float4 *st = reinterpret_cast<float4 *>(O.stash) + 2 * (size_t)r;
                 st[0] = make_float4(M[j], invS, n0, n1);
@@ -300,20 +337,23 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
 // Backward
 // ------------------------------------------------------------------------------------
 
-// Per-ray adjoint prologue, staged in LDS as 3 x float4:
-//   (v0, v1, v2, M2) (invS, tf_bar, Nb0, Nb1) (Nb2, kappa, D_bar, 0)
+// Per-ray adjoint prologue, staged in LDS as RW float4:
+//   (v0, v1, v2, M2) (invS, tf_bar, Nb0, Nb1) (Nb2, kappa, D_bar, 0) [(Cb0, Cb1, Cb2, 0)]
 // with tf_bar = dL/dt_f (depth + flow), Nb = dL/dN for the unnormalised blended normal,
-// kappa = tf_bar t_f + Nb.N, D_bar = dL/d(sum delta) = g_alpha exp(-D).
-template <bool NORMALS, bool FLOW>
+// Cb = dL/dC for the blended colour, kappa = tf_bar t_f + Nb.N + Cb.C, and
+// D_bar = dL/d(sum delta) = g_alpha exp(-D).
+template <int F>
 __device__ __forceinline__ void ray_prologue(const Params &P, const BwdIn &I, int view, const ViewRec &vr,
                                              const float *__restrict__ e, const float *__restrict__ kk,
                                              const float o0, const float o1, const float o2, int local,
-                                             bool valid, float4 out[3])
+                                             bool valid, float4 out[4])
 {
+    constexpr bool NORMALS = (F & kNrm) != 0, FLOW = (F & kFlw) != 0, COLOR = (F & kCol) != 0;
     if (!valid) {
         out[0] = make_float4(0.0f, 0.0f, 1.0f, INFINITY);
         out[1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         out[2] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        out[3] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         return;
     }
     float v0, v1, v2;
@@ -324,7 +364,7 @@ __device__ __forceinline__ void ray_prologue(const Params &P, const BwdIn &I, in
     const float4 s1 = reinterpret_cast<const float4 *>(I.stash)[2 * (size_t)r + 1];
     const float Nx = s0.z, Ny = s0.w, Nz = s1.x, Dsum = s1.y;
     float tfb = I.g_depth ? I.g_depth[r] : 0.0f;
-    if (FLOW && I.g_flow) {
+    if (FLOW) {
         // flow = pi_B(p) - pi_A(p), p = o + t_f v; pi_A(o + t v) does not depend on t.
         const float *__restrict__ eb = P.w2c_b + 12 * view;
         const float *__restrict__ kb = P.intr_b + 4 * view;
@@ -342,7 +382,7 @@ __device__ __forceinline__ void ray_prologue(const Params &P, const BwdIn &I, in
     }
     const float Db = I.g_alpha ? I.g_alpha[r] * expf(-Dsum) : 0.0f;
     float nb0 = 0.0f, nb1 = 0.0f, nb2 = 0.0f;
-    if (NORMALS && I.g_normal) {
+    if (NORMALS) {
         const float s = sqrtf(fmaf(Nx, Nx, fmaf(Ny, Ny, fmaf(Nz, Nz, kEpsN))));
         const float is = 1.0f / s;
         const float f0 = Nx * is, f1 = Ny * is, f2 = Nz * is;
@@ -352,20 +392,32 @@ __device__ __forceinline__ void ray_prologue(const Params &P, const BwdIn &I, in
         nb1 = (g1 - f1 * dp) * is;
         nb2 = (g2 - f2 * dp) * is;
     }
-    const float kap = fmaf(tfb, tf, fmaf(nb0, Nx, fmaf(nb1, Ny, nb2 * Nz)));
+    float kap = fmaf(tfb, tf, fmaf(nb0, Nx, fmaf(nb1, Ny, nb2 * Nz)));
+    float cb0 = 0.0f, cb1 = 0.0f, cb2 = 0.0f;
+    if (COLOR) {
+        cb0 = I.g_color[3 * r];
+        cb1 = I.g_color[3 * r + 1];
+        cb2 = I.g_color[3 * r + 2];
+        kap = fmaf(cb0, I.color[3 * r], fmaf(cb1, I.color[3 * r + 1], fmaf(cb2, I.color[3 * r + 2], kap)));
+    }
     out[0] = make_float4(v0, v1, v2, s0.x);
     out[1] = make_float4(s0.y, tfb, nb0, nb1);
     out[2] = make_float4(nb2, kap, Db, 0.0f);
+    out[3] = make_float4(cb0, cb1, cb2, 0.0f);
 }
 
-template <int BLOCK, int RT, bool NORMALS, bool FLOW, bool PERSIST>
+template <int BLOCK, int RT, int F>
 __global__ __launch_bounds__(BLOCK) void bwd_kernel(Params P, BwdIn I, const BwdItem *__restrict__ items,
                                                    int n_items, const int *__restrict__ order,
                                                    int *__restrict__ counter, float *__restrict__ partial,
                                                    float *__restrict__ beta_partial)
 {
-    __shared__ float4 rays[RT * 3];
-    __shared__ float red[BLOCK * 12];
+    constexpr bool NORMALS = (F & kNrm) != 0, PERSIST = (F & kPer) != 0, COLOR = (F & kCol) != 0;
+    constexpr int RW = COLOR ? 4 : 3;             // float4 per staged ray
+    constexpr int REC = COLOR ? kPartialColor : kPartial;  // partial record per Gaussian
+    constexpr int RS = REC + 2;                   // reduction record per lane (+ two betas)
+    __shared__ float4 rays[RT * RW];
+    __shared__ float red[BLOCK * RS];
     __shared__ int s_item;
     int pos = blockIdx.x;
     const int tid = threadIdx.x;
@@ -394,29 +446,33 @@ __global__ __launch_bounds__(BLOCK) void bwd_kernel(Params P, BwdIn I, const Bwd
         const int slot = tid / item.gc;
         const bool active = slot < item.slots && item.g0 + gi < sr.n;
         Ent g;
+        float4 cc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         if (active) {
             const int gg = sr.gauss_off + item.g0 + gi;
             float4 q[4];
             make_entry(P.means + 3 * gg, P.prec + 6 * gg, P.weights[gg], o, q);
             g = ent_from(q[0], q[1], q[2], q[3]);
+            if (COLOR) cc = colour_entry(P.colors + 3 * gg);
         }
         float aU0 = 0, aU1 = 0, aU2 = 0, aU3 = 0, aU4 = 0, aU5 = 0;
         float aP0 = 0, aP1 = 0, aP2 = 0, aL = 0, aB1 = 0, aB2 = 0;
+        float aC0 = 0, aC1 = 0, aC2 = 0;
 
         for (int r0 = item.ray0; r0 < end; r0 += RT) {
             const int cnt = min(RT, end - r0);
             __syncthreads();
             for (int q = tid; q < RT; q += BLOCK) {
-                float4 pr[3];
-                ray_prologue<NORMALS, FLOW>(P, I, item.view, vr, e, kk, o0, o1, o2, r0 + q, q < cnt, pr);
-                rays[3 * q] = pr[0];
-                rays[3 * q + 1] = pr[1];
-                rays[3 * q + 2] = pr[2];
+                float4 pr[4];
+                ray_prologue<F>(P, I, item.view, vr, e, kk, o0, o1, o2, r0 + q, q < cnt, pr);
+#pragma unroll
+                for (int k = 0; k < RW; ++k) rays[RW * q + k] = pr[k];
             }
             __syncthreads();
             if (active) {
                 for (int j = slot; j < cnt; j += item.slots) {
-                    const float4 x0 = rays[3 * j], x1 = rays[3 * j + 1], x2 = rays[3 * j + 2];
+                    const float4 x0 = rays[RW * j], x1 = rays[RW * j + 1], x2 = rays[RW * j + 2];
+                    float4 x3 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                    if (COLOR) x3 = rays[RW * j + 3];
                     const float v0 = x0.x, v1 = x0.y, v2 = x0.z;
                     Geo q;
                     pair_geo(g, v0, v1, v2, bl.hm, bl.b1, bl.nc2, q);
@@ -436,8 +492,15 @@ __global__ __launch_bounds__(BLOCK) void bwd_kernel(Params P, BwdIn I, const Bwd
                         n2 = g2 * rs;
                         nN = fmaf(n0, x1.z, fmaf(n1, x1.w, n2 * x2.x));
                     }
-                    // softmax adjoint: z_bar = wt (tf_bar t + Nb.n - kappa)
-                    const float zb = wt * (fmaf(tfb, q.t, nN) - x2.y);
+                    // softmax adjoint: z_bar = wt (tf_bar t + Nb.n + Cb.c - kappa)
+                    float lin = fmaf(tfb, q.t, nN);
+                    if (COLOR) {
+                        lin = fmaf(x3.x, cc.x, fmaf(x3.y, cc.y, fmaf(x3.z, cc.z, lin)));
+                        aC0 = fmaf(wt, x3.x, aC0);
+                        aC1 = fmaf(wt, x3.y, aC1);
+                        aC2 = fmaf(wt, x3.z, aC2);
+                    }
+                    const float zb = wt * (lin - x2.y);
                     const float tb = fmaf(-bl.cb, zb, wt * tfb);
                     const float db = fmaf(bl.b1, zb, x2.z * delta);
                     aB1 = fmaf(zb, q.d2, aB1);
@@ -491,24 +554,28 @@ __global__ __launch_bounds__(BLOCK) void bwd_kernel(Params P, BwdIn I, const Bwd
         // deterministic block reduction: Gaussian partials over the slots, betas over all lanes
         __syncthreads();
         {
-            float *my = red + 12 * tid;
+            float *my = red + RS * tid;
             my[0] = aU0; my[1] = aU1; my[2] = aU2; my[3] = aU3; my[4] = aU4; my[5] = aU5;
-            my[6] = aP0; my[7] = aP1; my[8] = aP2; my[9] = aL; my[10] = aB1; my[11] = aB2;
+            my[6] = aP0; my[7] = aP1; my[8] = aP2; my[9] = aL;
+            if (COLOR) {
+                my[10] = aC0; my[11] = aC1; my[12] = aC2;
+            }
+            my[REC] = aB1; my[REC + 1] = aB2;
         }
         __syncthreads();
         if (slot == 0 && gi < item.gc && item.g0 + gi < sr.n) {
-            float acc[kPartial];
+            float acc[REC];
 #pragma unroll
-            for (int c = 0; c < kPartial; ++c) acc[c] = red[12 * gi + c];
+            for (int c = 0; c < REC; ++c) acc[c] = red[RS * gi + c];
             for (int s = 1; s < item.slots; ++s) {
 #pragma unroll
-                for (int c = 0; c < kPartial; ++c) acc[c] += red[12 * (s * item.gc + gi) + c];
+                for (int c = 0; c < REC; ++c) acc[c] += red[RS * (s * item.gc + gi) + c];
             }
             // U_bar -= (sum rho) mu'^T (upper triangle), mu' = mu - o in double
             const float *mu = P.means + 3 * (sr.gauss_off + item.g0 + gi);
             const double m0 = (double)mu[0] - o[0], m1 = (double)mu[1] - o[1], m2 = (double)mu[2] - o[2];
             const double r0 = acc[6], r1 = acc[7], r2 = acc[8];
-            float *dst = partial + item.poff + kPartial * gi;
+            float *dst = partial + item.poff + REC * gi;
             dst[0] = (float)((double)acc[0] - r0 * m0);
             dst[1] = (float)((double)acc[1] - r0 * m1);
             dst[2] = (float)((double)acc[2] - r0 * m2);
@@ -516,14 +583,14 @@ __global__ __launch_bounds__(BLOCK) void bwd_kernel(Params P, BwdIn I, const Bwd
             dst[4] = (float)((double)acc[4] - r1 * m2);
             dst[5] = (float)((double)acc[5] - r2 * m2);
 #pragma unroll
-            for (int c = 6; c < kPartial; ++c) dst[c] = acc[c];
+            for (int c = 6; c < REC; ++c) dst[c] = acc[c];
         }
         if (tid < 64) {
             // lane l sums lanes l, l+64, ... in order, then a fixed butterfly over the wave
             float s1 = 0.0f, s2 = 0.0f;
             for (int k = tid; k < BLOCK; k += 64) {
-                s1 += red[12 * k + 10];
-                s2 += red[12 * k + 11];
+                s1 += red[RS * k + REC];
+                s2 += red[RS * k + REC + 1];
             }
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) {
@@ -589,17 +656,19 @@ __global__ __launch_bounds__(BLOCK) void fin2_kernel(Params P, const FinTask *__
                                                     const double *__restrict__ stage,
                                                     const double *__restrict__ stage_beta,
                                                     float *__restrict__ g_means, float *__restrict__ g_prec,
-                                                    float *__restrict__ g_weights, float *__restrict__ g_betas)
+                                                    float *__restrict__ g_weights, float *__restrict__ g_colors,
+                                                    float *__restrict__ g_betas)
 {
-    __shared__ double sums[kFinSlice * kPartial];
+    __shared__ double sums[kFinSlice * kPartialColor];
     const FinTask task = tasks[blockIdx.x];
     const int g_lo = blockIdx.y * kFinSlice;
     if (g_lo >= task.gc) return;
     const int ng = min(kFinSlice, task.gc - g_lo);
+    const int rec = task.rec;
     const SceneRec sr = P.scenes[task.scene];
     const int tid = threadIdx.x;
-    if (tid < ng * kPartial) {
-        const int v = g_lo * kPartial + tid;
+    for (int tv = tid; tv < ng * rec; tv += BLOCK) {
+        const int v = g_lo * rec + tv;
         double s = 0.0;
         int gi = task.group_begin;
         for (; gi + 8 <= task.group_end; gi += 8) {
@@ -610,12 +679,12 @@ __global__ __launch_bounds__(BLOCK) void fin2_kernel(Params P, const FinTask *__
             for (int k = 0; k < 8; ++k) s += x[k];
         }
         for (; gi < task.group_end; ++gi) s += stage[groups[gi].soff + v];
-        sums[tid] = s;
+        sums[tv] = s;
     }
     __syncthreads();
     if (tid < ng) {
         const int gg = sr.gauss_off + task.g0 + g_lo + tid;
-        const double *sm = sums + kPartial * tid;
+        const double *sm = sums + rec * tid;
         const float *u = P.prec + 6 * gg;
         float *gp = g_prec + 6 * gg;
 #pragma unroll
@@ -625,6 +694,14 @@ __global__ __launch_bounds__(BLOCK) void fin2_kernel(Params P, const FinTask *__
         g_means[3 * gg + 1] = (float)(-((double)u[1] * r0 + (double)u[3] * r1));
         g_means[3 * gg + 2] = (float)(-((double)u[2] * r0 + (double)u[4] * r1 + (double)u[5] * r2));
         g_weights[gg] = (float)(sm[9] / (double)P.weights[gg]);
+        if (rec == kPartialColor && g_colors) {
+            // colour = sigmoid(q): dL/dq = dL/dc c (1 - c)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double col = 1.0 / (1.0 + exp(-(double)P.colors[3 * gg + c]));
+                g_colors[3 * gg + c] = (float)(sm[10 + c] * col * (1.0 - col));
+            }
+        }
     }
     if (task.beta && blockIdx.y == 0 && tid < 2) {
         const double sb = ordered_sum(stage_beta + 2 * task.sgroup_begin + tid, task.sgroup_end - task.sgroup_begin, 2);
@@ -640,11 +717,14 @@ constexpr int kLossBlock = 1024;
 __global__ __launch_bounds__(kLossBlock) void loss_kernel(int p, const float *__restrict__ depth,
                                                          const float *__restrict__ alpha,
                                                          const float *__restrict__ flow,
+                                                         const float *__restrict__ color,
                                                          const float *__restrict__ depth_t,
                                                          const float *__restrict__ alpha_t,
-                                                         const float *__restrict__ flow_t, float w_depth,
-                                                         float w_flow, int flow_norm, float *__restrict__ g_depth,
-                                                         float *__restrict__ g_alpha, float *__restrict__ g_flow,
+                                                         const float *__restrict__ flow_t,
+                                                         const float *__restrict__ color_t, float w_depth,
+                                                         float w_flow, int flow_norm, float w_color,
+                                                         float *__restrict__ g_depth, float *__restrict__ g_alpha,
+                                                         float *__restrict__ g_flow, float *__restrict__ g_color,
                                                          float *__restrict__ block_loss)
 {
     __shared__ float red[kLossBlock / 64];
@@ -672,6 +752,14 @@ __global__ __launch_bounds__(kLossBlock) void loss_kernel(int p, const float *__
                 l += w_flow * at * (f0 * f0 + f1 * f1);
             }
         }
+        if (color) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float dc = color[3 * r + c] - color_t[3 * r + c];
+                g_color[3 * r + c] = w_color * at * (float)((dc > 0.0f) - (dc < 0.0f)) * inv_p;
+                l += w_color * at * fabsf(dc);
+            }
+        }
         l *= inv_p;
     }
     if (block_loss) {
@@ -687,13 +775,14 @@ __global__ __launch_bounds__(kLossBlock) void loss_kernel(int p, const float *__
     }
 }
 
-hipError_t launch_loss(int p, const float *depth, const float *alpha, const float *flow, const float *depth_t,
-                       const float *alpha_t, const float *flow_t, float w_depth, float w_flow, int flow_norm,
-                       float *g_depth, float *g_alpha, float *g_flow, float *block_loss, hipStream_t st)
+hipError_t launch_loss(int p, const float *depth, const float *alpha, const float *flow, const float *color,
+                       const float *depth_t, const float *alpha_t, const float *flow_t, const float *color_t,
+                       float w_depth, float w_flow, int flow_norm, float w_color, float *g_depth, float *g_alpha,
+                       float *g_flow, float *g_color, float *block_loss, hipStream_t st)
 {
     hipLaunchKernelGGL(loss_kernel, dim3((p + kLossBlock - 1) / kLossBlock), dim3(kLossBlock), 0, st, p, depth, alpha,
-                       flow, depth_t, alpha_t, flow_t, w_depth, w_flow, flow_norm, g_depth, g_alpha, g_flow,
-                       block_loss);
+                       flow, color, depth_t, alpha_t, flow_t, color_t, w_depth, w_flow, flow_norm, w_color, g_depth,
+                       g_alpha, g_flow, g_color, block_loss);
     return hipGetLastError();
 }
 
@@ -736,49 +825,39 @@ struct FwdVariant {
 static const FwdVariant kFwdVariants[] = {{1, 128}, {2, 128}, {2, 256}, {4, 128}};
 static const int kBwdRT[] = {64, 128, 256};
 
-template <int RPT, int TG, bool NRM, bool FLW, bool PER>
-static void launch_fwd_t(int grid, hipStream_t st, const Params &P, const FwdOut &O, const FwdItem *items,
-                         int n, const int *order, int *counter)
-{
-    hipLaunchKernelGGL((fwd_kernel<kBlock, RPT, TG, NRM, FLW, PER>), dim3(grid), dim3(kBlock), 0, st, P, O,
-                       items, n, order, counter);
-}
+// F dispatch: calls body<F>() for the runtime flag set f (0..15).
+#define FMB_DISPATCH_F(f, CALL)                                                                            \
+    switch (f) {                                                                                           \
+    case 0: CALL(0); break;   case 1: CALL(1); break;   case 2: CALL(2); break;   case 3: CALL(3); break;   \
+    case 4: CALL(4); break;   case 5: CALL(5); break;   case 6: CALL(6); break;   case 7: CALL(7); break;   \
+    case 8: CALL(8); break;   case 9: CALL(9); break;   case 10: CALL(10); break; case 11: CALL(11); break; \
+    case 12: CALL(12); break; case 13: CALL(13); break; case 14: CALL(14); break; case 15: CALL(15); break; \
+    default: return hipErrorInvalidValue;                                                                  \
+    }
 
 template <int RPT, int TG>
-static void launch_fwd_v(bool nrm, bool flw, bool per, int grid, hipStream_t st, const Params &P,
-                         const FwdOut &O, const FwdItem *items, int n, const int *order, int *counter)
+static hipError_t launch_fwd_v(int f, int grid, hipStream_t st, const Params &P, const FwdOut &O,
+                               const FwdItem *items, int n, const int *order, int *counter)
 {
-#define FMB_F(a, b, c)                                                                        \
-    if (nrm == a && flw == b && per == c) {                                                   \
-        launch_fwd_t<RPT, TG, a, b, c>(grid, st, P, O, items, n, order, counter);              \
-        return;                                                                               \
-    }
-    FMB_F(false, false, false) FMB_F(false, false, true) FMB_F(false, true, false) FMB_F(false, true, true)
-    FMB_F(true, false, false) FMB_F(true, false, true) FMB_F(true, true, false) FMB_F(true, true, true)
-#undef FMB_F
-}
-
-template <int RT, bool NRM, bool FLW, bool PER>
-static void launch_bwd_t(int grid, hipStream_t st, const Params &P, const BwdIn &I, const BwdItem *items,
-                         int n, const int *order, int *counter, float *partial, float *bpart)
-{
-    hipLaunchKernelGGL((bwd_kernel<kBlock, RT, NRM, FLW, PER>), dim3(grid), dim3(kBlock), 0, st, P, I, items,
-                       n, order, counter, partial, bpart);
+#define FMB_FWD_CALL(F)                                                                                    \
+    hipLaunchKernelGGL((fwd_kernel<kBlock, RPT, TG, F>), dim3(grid), dim3(kBlock), 0, st, P, O, items, n, order, \
+                       counter)
+    FMB_DISPATCH_F(f, FMB_FWD_CALL)
+#undef FMB_FWD_CALL
+    return hipGetLastError();
 }
 
 template <int RT>
-static void launch_bwd_v(bool nrm, bool flw, bool per, int grid, hipStream_t st, const Params &P,
-                         const BwdIn &I, const BwdItem *items, int n, const int *order, int *counter,
-                         float *partial, float *bpart)
+static hipError_t launch_bwd_v(int f, int grid, hipStream_t st, const Params &P, const BwdIn &I,
+                               const BwdItem *items, int n, const int *order, int *counter, float *partial,
+                               float *bpart)
 {
-#define FMB_B(a, b, c)                                                                        \
-    if (nrm == a && flw == b && per == c) {                                                   \
-        launch_bwd_t<RT, a, b, c>(grid, st, P, I, items, n, order, counter, partial, bpart);   \
-        return;                                                                               \
-    }
-    FMB_B(false, false, false) FMB_B(false, false, true) FMB_B(false, true, false) FMB_B(false, true, true)
-    FMB_B(true, false, false) FMB_B(true, false, true) FMB_B(true, true, false) FMB_B(true, true, true)
-#undef FMB_B
+#define FMB_BWD_CALL(F)                                                                                    \
+    hipLaunchKernelGGL((bwd_kernel<kBlock, RT, F>), dim3(grid), dim3(kBlock), 0, st, P, I, items, n, order,     \
+                       counter, partial, bpart)
+    FMB_DISPATCH_F(f, FMB_BWD_CALL)
+#undef FMB_BWD_CALL
+    return hipGetLastError();
 }
 
 int num_fwd_variants() { return (int)(sizeof kFwdVariants / sizeof kFwdVariants[0]); }
@@ -787,42 +866,41 @@ int num_bwd_variants() { return (int)(sizeof kBwdRT / sizeof kBwdRT[0]); }
 int bwd_variant_rt(int v) { return kBwdRT[v]; }
 int block_size() { return kBlock; }
 
-hipError_t launch_fwd(int variant, bool nrm, bool flw, bool per, int grid, hipStream_t st, const Params &P,
-                      const FwdOut &O, const FwdItem *items, int n, const int *order, int *counter)
+// flags: bit 0 normals, 1 flow, 2 persistent, 3 colour
+hipError_t launch_fwd(int variant, int flags, int grid, hipStream_t st, const Params &P, const FwdOut &O,
+                      const FwdItem *items, int n, const int *order, int *counter)
 {
     switch (variant) {
-    case 0: launch_fwd_v<1, 128>(nrm, flw, per, grid, st, P, O, items, n, order, counter); break;
-    case 1: launch_fwd_v<2, 128>(nrm, flw, per, grid, st, P, O, items, n, order, counter); break;
-    case 2: launch_fwd_v<2, 256>(nrm, flw, per, grid, st, P, O, items, n, order, counter); break;
-    case 3: launch_fwd_v<4, 128>(nrm, flw, per, grid, st, P, O, items, n, order, counter); break;
+    case 0: return launch_fwd_v<1, 128>(flags, grid, st, P, O, items, n, order, counter);
+    case 1: return launch_fwd_v<2, 128>(flags, grid, st, P, O, items, n, order, counter);
+    case 2: return launch_fwd_v<2, 256>(flags, grid, st, P, O, items, n, order, counter);
+    case 3: return launch_fwd_v<4, 128>(flags, grid, st, P, O, items, n, order, counter);
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
-hipError_t launch_bwd(int variant, bool nrm, bool flw, bool per, int grid, hipStream_t st, const Params &P,
-                      const BwdIn &I, const BwdItem *items, int n, const int *order, int *counter,
-                      float *partial, float *bpart)
+hipError_t launch_bwd(int variant, int flags, int grid, hipStream_t st, const Params &P, const BwdIn &I,
+                      const BwdItem *items, int n, const int *order, int *counter, float *partial, float *bpart)
 {
     switch (variant) {
-    case 0: launch_bwd_v<64>(nrm, flw, per, grid, st, P, I, items, n, order, counter, partial, bpart); break;
-    case 1: launch_bwd_v<128>(nrm, flw, per, grid, st, P, I, items, n, order, counter, partial, bpart); break;
-    case 2: launch_bwd_v<256>(nrm, flw, per, grid, st, P, I, items, n, order, counter, partial, bpart); break;
+    case 0: return launch_bwd_v<64>(flags, grid, st, P, I, items, n, order, counter, partial, bpart);
+    case 1: return launch_bwd_v<128>(flags, grid, st, P, I, items, n, order, counter, partial, bpart);
+    case 2: return launch_bwd_v<256>(flags, grid, st, P, I, items, n, order, counter, partial, bpart);
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_fin(int n_tasks, int n_groups, hipStream_t st, const Params &P, const FinTask *tasks,
                       const FinGroup *groups, const float *partial, const float *bpart, double *stage,
-                      double *stage_beta, float *g_means, float *g_prec, float *g_weights, float *g_betas)
+                      double *stage_beta, float *g_means, float *g_prec, float *g_weights, float *g_colors,
+                      float *g_betas)
 {
     hipLaunchKernelGGL((fin1_kernel<256>), dim3(n_groups), dim3(256), 0, st, groups, partial, bpart, stage,
                        stage_beta);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((fin2_kernel<256>), dim3(n_tasks, (kBlock + kFinSlice - 1) / kFinSlice), dim3(256), 0, st, P,
-                       tasks, groups, stage, stage_beta, g_means, g_prec, g_weights, g_betas);
+                       tasks, groups, stage, stage_beta, g_means, g_prec, g_weights, g_colors, g_betas);
     return hipGetLastError();
 }
 
@@ -839,56 +917,50 @@ hipError_t launch_validate(const Params &P, int n_total, int n_scenes, int *flag
     return hipGetLastError();
 }
 
-hipError_t occupancy_fwd(int variant, bool nrm, bool flw, int *blocks_per_cu)
+template <typename K>
+static hipError_t occ(K kernel, int *blocks)
 {
-    // persistent variants have the same resources as the plain ones; query the plain kernel
-#define FMB_OCC(RPT, TG)                                                                                  \
-    {                                                                                                     \
-        if (nrm && flw)                                                                                   \
-            return hipOccupancyMaxActiveBlocksPerMultiprocessor(                                          \
-                blocks_per_cu, fwd_kernel<kBlock, RPT, TG, true, true, true>, kBlock, 0);                 \
-        if (nrm)                                                                                          \
-            return hipOccupancyMaxActiveBlocksPerMultiprocessor(                                          \
-                blocks_per_cu, fwd_kernel<kBlock, RPT, TG, true, false, true>, kBlock, 0);                \
-        if (flw)                                                                                          \
-            return hipOccupancyMaxActiveBlocksPerMultiprocessor(                                          \
-                blocks_per_cu, fwd_kernel<kBlock, RPT, TG, false, true, true>, kBlock, 0);                \
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(                                              \
-            blocks_per_cu, fwd_kernel<kBlock, RPT, TG, false, false, true>, kBlock, 0);                   \
-    }
-    switch (variant) {
-    case 0: FMB_OCC(1, 128)
-    case 1: FMB_OCC(2, 128)
-    case 2: FMB_OCC(2, 256)
-    case 3: FMB_OCC(4, 128)
-    default: return hipErrorInvalidValue;
-    }
-#undef FMB_OCC
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, kernel, kBlock, 0);
 }
 
-hipError_t occupancy_bwd(int variant, bool nrm, bool flw, int *blocks_per_cu)
+// Occupancy of the persistent kernels (flags include kPer).
+hipError_t occupancy_fwd(int variant, int flags, int *blocks_per_cu)
 {
-#define FMB_OCC(RT)                                                                                       \
-    {                                                                                                     \
-        if (nrm && flw)                                                                                   \
-            return hipOccupancyMaxActiveBlocksPerMultiprocessor(                                          \
-                blocks_per_cu, bwd_kernel<kBlock, RT, true, true, true>, kBlock, 0);                      \
-        if (nrm)                                                                                          \
-            return hipOccupancyMaxActiveBlocksPerMultiprocessor(                                          \
-                blocks_per_cu, bwd_kernel<kBlock, RT, true, false, true>, kBlock, 0);                     \
-        if (flw)                                                                                          \
-            return hipOccupancyMaxActiveBlocksPerMultiprocessor(                                          \
-                blocks_per_cu, bwd_kernel<kBlock, RT, false, true, true>, kBlock, 0);                     \
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(                                              \
-            blocks_per_cu, bwd_kernel<kBlock, RT, false, false, true>, kBlock, 0);                        \
+#define FMB_OCC_F(F) return occ(fwd_kernel<kBlock, RPT, TG, F>, blocks_per_cu)
+#define FMB_OCC_V(RPT_, TG_)                                                                               \
+    {                                                                                                      \
+        constexpr int RPT = RPT_, TG = TG_;                                                                \
+        FMB_DISPATCH_F(flags, FMB_OCC_F)                                                                   \
     }
     switch (variant) {
-    case 0: FMB_OCC(64)
-    case 1: FMB_OCC(128)
-    case 2: FMB_OCC(256)
+    case 0: FMB_OCC_V(1, 128)
+    case 1: FMB_OCC_V(2, 128)
+    case 2: FMB_OCC_V(2, 256)
+    case 3: FMB_OCC_V(4, 128)
     default: return hipErrorInvalidValue;
     }
-#undef FMB_OCC
+#undef FMB_OCC_V
+#undef FMB_OCC_F
+    return hipErrorInvalidValue;
+}
+
+hipError_t occupancy_bwd(int variant, int flags, int *blocks_per_cu)
+{
+#define FMB_OCC_F(F) return occ(bwd_kernel<kBlock, RT, F>, blocks_per_cu)
+#define FMB_OCC_V(RT_)                                                                                     \
+    {                                                                                                      \
+        constexpr int RT = RT_;                                                                            \
+        FMB_DISPATCH_F(flags, FMB_OCC_F)                                                                   \
+    }
+    switch (variant) {
+    case 0: FMB_OCC_V(64)
+    case 1: FMB_OCC_V(128)
+    case 2: FMB_OCC_V(256)
+    default: return hipErrorInvalidValue;
+    }
+#undef FMB_OCC_V
+#undef FMB_OCC_F
+    return hipErrorInvalidValue;
 }
 
 }  // namespace fmb

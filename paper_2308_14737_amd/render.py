@@ -96,6 +96,15 @@ class Scene:
     def handle(self):
         return self._h
 
+    def set_colors(self, colors: Optional[torch.Tensor]):
+        """Per-Gaussian colours [N,3] (unconstrained; rendered as sigmoid), or None."""
+        if colors is not None:
+            _check_dev(colors, "colors")
+            if tuple(colors.shape) != (self.n, 3):
+                raise ValueError("colors must be [N,3]")
+        _lib.call("fmb_set_colors", self._h, None, _vp(colors))
+        self._colors = colors
+
     def rebind(self, means, prec, weights, betas):
         for t, nm in ((means, "means"), (prec, "prec"), (weights, "weights"), (betas, "betas")):
             _check_dev(t, nm)
@@ -129,10 +138,11 @@ class Scene:
         return int(_lib.load().fmb_num_rays(self._h))
 
     def render(self, normals: bool = True, flow: Optional[bool] = None, stash: bool = True,
-               out: Optional[dict] = None) -> dict:
+               out: Optional[dict] = None, color: Optional[bool] = None) -> dict:
         if self.cameras is None:
             raise RuntimeError("set_cameras first")
         flow = self.cameras.has_flow if flow is None else flow
+        color = (getattr(self, "_colors", None) is not None) if color is None else color
         p = self.n_rays
         o = out or {}
         dev = self.device
@@ -144,25 +154,32 @@ class Scene:
         fl = None
         if flow:
             fl = o.get("flow") if o.get("flow") is not None else torch.empty(p, 2, device=dev)
+        col = None
+        if color:
+            col = o.get("color") if o.get("color") is not None else torch.empty(p, 3, device=dev)
         st = None
         if stash:
             st = o.get("stash") if o.get("stash") is not None else torch.empty(p, STASH, device=dev)
-        _lib.call("fmb_render", self._h, _vp(depth), _vp(alpha), _vp(normal), _vp(fl), _vp(st),
+        _lib.call("fmb_render", self._h, _vp(depth), _vp(alpha), _vp(normal), _vp(fl), _vp(col), _vp(st),
                   _stream(dev))
-        return {"depth": depth, "alpha": alpha, "normal": normal, "flow": fl, "stash": st}
+        return {"depth": depth, "alpha": alpha, "normal": normal, "flow": fl, "color": col, "stash": st}
 
     def backward(self, outs: dict, g_depth=None, g_alpha=None, g_normal=None, g_flow=None,
-                 grads: Optional[dict] = None) -> dict:
+                 grads: Optional[dict] = None, g_color=None) -> dict:
         dev = self.device
         g = grads or {}
         gm = g.get("means") if g.get("means") is not None else torch.empty(self.n, 3, device=dev)
         gp = g.get("prec") if g.get("prec") is not None else torch.empty(self.n, 6, device=dev)
         gw = g.get("weights") if g.get("weights") is not None else torch.empty(self.n, device=dev)
         gb = g.get("betas") if g.get("betas") is not None else torch.empty(2, device=dev)
-        cot = [None if c is None else c.contiguous() for c in (g_depth, g_alpha, g_normal, g_flow)]
+        gc = None
+        if g_color is not None:
+            gc = g.get("colors") if g.get("colors") is not None else torch.empty(self.n, 3, device=dev)
+        cot = [None if c is None else c.contiguous() for c in (g_depth, g_alpha, g_normal, g_flow, g_color)]
         _lib.call("fmb_backward", self._h, *[_vp(c) for c in cot], _vp(outs["depth"]),
-                  _vp(outs["stash"]), _vp(gm), _vp(gp), _vp(gw), _vp(gb), _stream(dev))
-        return {"means": gm, "prec": gp, "weights": gw, "betas": gb}
+                  _vp(outs.get("color")), _vp(outs["stash"]), _vp(gm), _vp(gp), _vp(gw), _vp(gc), _vp(gb),
+                  _stream(dev))
+        return {"means": gm, "prec": gp, "weights": gw, "betas": gb, "colors": gc}
 
     def validate(self) -> int:
         bad = ctypes.c_int32(0)
@@ -171,10 +188,7 @@ class Scene:
 
     def autotune(self, outs: dict, cot: dict, grads: dict, cache_path: Optional[str] = None):
         """Pick the fastest compiled tile variants for these outputs and cotangents."""
-        _lib.call("fmb_autotune", self._h, None, _vp(outs["depth"]), _vp(outs["alpha"]),
-                  _vp(outs.get("normal")), _vp(outs.get("flow")), _vp(outs["stash"]),
-                  _vp(cot.get("depth")), _vp(cot.get("alpha")), _vp(cot.get("normal")), _vp(cot.get("flow")),
-                  _vp(grads["means"]), _vp(grads["prec"]), _vp(grads["weights"]), _vp(grads["betas"]),
+        _lib.call("fmb_autotune", self._h, None, *_tune_args(outs, cot, grads),
                   None if cache_path is None else cache_path.encode(), _stream(self.device))
 
     def __del__(self):
@@ -190,36 +204,51 @@ class Scene:
 
 class _RenderFn(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, scene: Scene, normals: bool, means, prec, weights, betas):
+    def forward(ctx, scene: Scene, normals: bool, means, prec, weights, betas, colors):
         scene.rebind(means.detach().contiguous(), prec.detach().contiguous(),
                      weights.detach().contiguous(), betas.detach().contiguous())
-        outs = scene.render(normals=normals)
+        scene.set_colors(None if colors is None else colors.detach().contiguous())
+        outs = scene.render(normals=normals, color=colors is not None)
         ctx.scene = scene
         ctx.outs = outs
-        ctx.save_for_backward(means, prec, weights, betas)
-        nr = outs["normal"] if outs["normal"] is not None else outs["depth"].new_zeros(0)
-        fl = outs["flow"] if outs["flow"] is not None else outs["depth"].new_zeros(0)
+        ctx.has_colors = colors is not None
+        ctx.save_for_backward(means, prec, weights, betas, colors)
+        empty = outs["depth"].new_zeros(0)
+        nr = outs["normal"] if outs["normal"] is not None else empty
+        fl = outs["flow"] if outs["flow"] is not None else empty
+        co = outs["color"] if outs["color"] is not None else empty
         ctx.mark_non_differentiable(outs["stash"])
-        return outs["depth"], outs["alpha"], nr, fl
+        return outs["depth"], outs["alpha"], nr, fl, co
 
     @staticmethod
-    def backward(ctx, g_depth, g_alpha, g_normal, g_flow):
+    def backward(ctx, g_depth, g_alpha, g_normal, g_flow, g_color):
         scene = ctx.scene
         outs = ctx.outs
-        means, prec, weights, betas = ctx.saved_tensors
+        means, prec, weights, betas, colors = ctx.saved_tensors
         scene.rebind(means.detach().contiguous(), prec.detach().contiguous(),
                      weights.detach().contiguous(), betas.detach().contiguous())
-        gn = g_normal if (outs["normal"] is not None and g_normal is not None
-                          and g_normal.numel() > 0) else None
-        gf = g_flow if (outs["flow"] is not None and g_flow is not None and g_flow.numel() > 0) else None
-        gr = scene.backward(outs, g_depth, g_alpha, gn, gf)
-        return None, None, gr["means"], gr["prec"], gr["weights"], gr["betas"]
+        scene.set_colors(None if colors is None else colors.detach().contiguous())
+        use = lambda g, o: g if (o is not None and g is not None and g.numel() > 0) else None  # noqa: E731
+        gr = scene.backward(outs, g_depth, g_alpha, use(g_normal, outs["normal"]), use(g_flow, outs["flow"]),
+                            g_color=use(g_color, outs["color"]))
+        gcol = gr["colors"] if ctx.has_colors else None
+        if ctx.has_colors and gcol is None:
+            gcol = torch.zeros_like(colors)
+        return None, None, gr["means"], gr["prec"], gr["weights"], gr["betas"], gcol
 
 
-def render(scene: Scene, means, prec, weights, betas, normals: bool = True):
+def render(scene: Scene, means, prec, weights, betas, normals: bool = True, colors=None):
     """Differentiable render: returns (depth [P], alpha [P], normal [P,3] or empty, flow [P,2] or
-    empty); gradients flow to means, prec, weights and betas through the HIP adjoint kernel."""
-    return _RenderFn.apply(scene, normals, means, prec, weights, betas)
+    empty, colour [P,3] or empty); gradients flow to means, prec, weights, betas and colours
+    through the HIP adjoint kernel."""
+    return _RenderFn.apply(scene, normals, means, prec, weights, betas, colors)
+
+
+def _tune_args(outs, cot, grads):
+    return (_vp(outs["depth"]), _vp(outs["alpha"]), _vp(outs.get("normal")), _vp(outs.get("flow")),
+            _vp(outs.get("color")), _vp(outs["stash"]), _vp(cot.get("depth")), _vp(cot.get("alpha")),
+            _vp(cot.get("normal")), _vp(cot.get("flow")), _vp(cot.get("color")), _vp(grads["means"]),
+            _vp(grads["prec"]), _vp(grads["weights"]), _vp(grads.get("colors")), _vp(grads["betas"]))
 
 
 class Batch:
@@ -259,36 +288,46 @@ class Batch:
     def has_flow(self) -> bool:
         return self.w2c_b is not None
 
-    def alloc_outputs(self, normals=True):
+    def set_colors(self, colors: Optional[torch.Tensor]):
+        """Per-Gaussian colours [sum N, 3] (unconstrained), or None."""
+        if colors is not None:
+            _check_dev(colors, "colors")
+        _lib.call("fmb_set_colors", None, self._h, _vp(colors))
+        self._colors = colors
+
+    def alloc_outputs(self, normals=True, color=False):
         p, dev = self.n_rays, self.device
         return {"depth": torch.empty(p, device=dev), "alpha": torch.empty(p, device=dev),
                 "normal": torch.empty(p, 3, device=dev) if normals else None,
                 "flow": torch.empty(p, 2, device=dev) if self.has_flow else None,
+                "color": torch.empty(p, 3, device=dev) if color else None,
                 "stash": torch.empty(p, STASH, device=dev)}
 
-    def alloc_grads(self):
+    def alloc_grads(self, colors=False):
         n, dev = self.n_total, self.device
         return {"means": torch.empty(n, 3, device=dev), "prec": torch.empty(n, 6, device=dev),
-                "weights": torch.empty(n, device=dev), "betas": torch.empty(self.s, 2, device=dev)}
+                "weights": torch.empty(n, device=dev), "betas": torch.empty(self.s, 2, device=dev),
+                "colors": torch.empty(n, 3, device=dev) if colors else None}
 
     def forward(self, outs: dict):
         _lib.call("fmb_batch_forward", self._h, _vp(outs["depth"]), _vp(outs["alpha"]),
-                  _vp(outs["normal"]), _vp(outs["flow"]), _vp(outs["stash"]), _stream(self.device))
+                  _vp(outs["normal"]), _vp(outs["flow"]), _vp(outs.get("color")), _vp(outs["stash"]),
+                  _stream(self.device))
         return outs
 
     def backward(self, outs: dict, cot: dict, grads: dict):
         _lib.call("fmb_batch_backward", self._h, _vp(cot.get("depth")), _vp(cot.get("alpha")),
-                  _vp(cot.get("normal")), _vp(cot.get("flow")), _vp(outs["depth"]), _vp(outs["stash"]),
-                  _vp(grads["means"]), _vp(grads["prec"]), _vp(grads["weights"]), _vp(grads["betas"]),
-                  _stream(self.device))
+                  _vp(cot.get("normal")), _vp(cot.get("flow")), _vp(cot.get("color")), _vp(outs["depth"]),
+                  _vp(outs.get("color")), _vp(outs["stash"]), _vp(grads["means"]), _vp(grads["prec"]),
+                  _vp(grads["weights"]), _vp(grads.get("colors")), _vp(grads["betas"]), _stream(self.device))
         return grads
 
     def capture(self, outs: dict, cot: dict, grads: dict, stream: torch.cuda.Stream):
         _lib.call("fmb_batch_capture", self._h, _vp(outs["depth"]), _vp(outs["alpha"]),
-                  _vp(outs["normal"]), _vp(outs["flow"]), _vp(outs["stash"]), _vp(cot.get("depth")),
-                  _vp(cot.get("alpha")), _vp(cot.get("normal")), _vp(cot.get("flow")),
-                  _vp(grads["means"]), _vp(grads["prec"]), _vp(grads["weights"]), _vp(grads["betas"]),
-                  ctypes.c_void_p(stream.cuda_stream))
+                  _vp(outs["normal"]), _vp(outs["flow"]), _vp(outs.get("color")), _vp(outs["stash"]),
+                  _vp(cot.get("depth")), _vp(cot.get("alpha")), _vp(cot.get("normal")), _vp(cot.get("flow")),
+                  _vp(cot.get("color")), _vp(grads["means"]), _vp(grads["prec"]), _vp(grads["weights"]),
+                  _vp(grads.get("colors")), _vp(grads["betas"]), ctypes.c_void_p(stream.cuda_stream))
 
     def graph_launch(self, which: int = 2, stream: Optional[torch.cuda.Stream] = None):
         """Replay the captured forward (0), backward (1) or both (2)."""
@@ -297,10 +336,7 @@ class Batch:
 
     def autotune(self, outs: dict, cot: dict, grads: dict, cache_path: Optional[str] = None):
         """Pick the fastest compiled tile variants for these outputs and cotangents."""
-        _lib.call("fmb_autotune", None, self._h, _vp(outs["depth"]), _vp(outs["alpha"]),
-                  _vp(outs.get("normal")), _vp(outs.get("flow")), _vp(outs["stash"]),
-                  _vp(cot.get("depth")), _vp(cot.get("alpha")), _vp(cot.get("normal")), _vp(cot.get("flow")),
-                  _vp(grads["means"]), _vp(grads["prec"]), _vp(grads["weights"]), _vp(grads["betas"]),
+        _lib.call("fmb_autotune", None, self._h, *_tune_args(outs, cot, grads),
                   None if cache_path is None else cache_path.encode(), _stream(self.device))
 
     def __del__(self):
@@ -325,22 +361,26 @@ def launch_config(scene: Optional["Scene"] = None, batch: Optional["Batch"] = No
 
 
 def loss_grad(outs: dict, depth_t, alpha_t, flow_t=None, w_depth: float = 1.0, w_flow: float = 1.0,
-              flow_norm: int = 2, cot: Optional[dict] = None, block_loss: Optional[torch.Tensor] = None) -> dict:
+              flow_norm: int = 2, cot: Optional[dict] = None, block_loss: Optional[torch.Tensor] = None,
+              color_t=None, w_color: float = 1.0) -> dict:
     """Cotangents of the mask-weighted reconstruction loss (BCE alpha + w_depth alpha* L1 depth
-    + w_flow alpha* flow term, averaged over rays) for one render's outputs, in one HIP kernel."""
+    + w_color alpha* L1 colour + w_flow alpha* flow term, averaged over rays) in one HIP kernel."""
     p = int(outs["depth"].numel())
     dev = outs["depth"].device
     c = cot if cot is not None else {}
     gd = c.get("depth") if c.get("depth") is not None else torch.empty(p, device=dev)
     ga = c.get("alpha") if c.get("alpha") is not None else torch.empty(p, device=dev)
-    use_flow = flow_t is not None
-    gf = None
-    if use_flow:
+    gf = gc = None
+    if flow_t is not None:
         gf = c.get("flow") if c.get("flow") is not None else torch.empty(p, 2, device=dev)
-    _lib.call("fmb_loss_grad", p, _vp(outs["depth"]), _vp(outs["alpha"]), _vp(outs["flow"] if use_flow else None),
-              _vp(depth_t), _vp(alpha_t), _vp(flow_t), ctypes.c_float(w_depth), ctypes.c_float(w_flow),
-              int(flow_norm), _vp(gd), _vp(ga), _vp(gf), _vp(block_loss), _stream(dev))
-    return {"depth": gd, "alpha": ga, "normal": None, "flow": gf}
+    if color_t is not None:
+        gc = c.get("color") if c.get("color") is not None else torch.empty(p, 3, device=dev)
+    _lib.call("fmb_loss_grad", p, _vp(outs["depth"]), _vp(outs["alpha"]),
+              _vp(outs["flow"] if flow_t is not None else None),
+              _vp(outs["color"] if color_t is not None else None), _vp(depth_t), _vp(alpha_t), _vp(flow_t),
+              _vp(color_t), ctypes.c_float(w_depth), ctypes.c_float(w_flow), int(flow_norm),
+              ctypes.c_float(w_color), _vp(gd), _vp(ga), _vp(gf), _vp(gc), _vp(block_loss), _stream(dev))
+    return {"depth": gd, "alpha": ga, "normal": None, "flow": gf, "color": gc}
 
 
 def timing_enable(on: bool = True):

@@ -533,26 +533,30 @@ def pin_loss_gradient():
     L, _ = O.loss_grad([1.25], [0.5], [1.0], [1.0], flow=[[0.1, -0.2]], flow_t=[[0.0, 0.0]],
                        w_depth=2.0, w_flow=3.0, flow_norm=2)
     _close(L, math.log(2.0) + 0.5 + 0.15, 1e-14, 1e-14, "hand-computed loss")
+    L, _ = O.loss_grad([1.0], [0.5], [1.0], [1.0], color=[[0.2, 0.5, 0.9]], color_t=[[0.1, 0.5, 1.0]],
+                       w_color=4.5)
+    _close(L, math.log(2.0) + 4.5 * 0.2, 1e-14, 1e-14, "hand-computed colour loss")
     g = _rng(28)
     p = 16
     d, dt = g.uniform(1, 4, p), g.uniform(1, 4, p)
     a, at = g.uniform(0.01, 0.99, p), g.uniform(0, 1, p)
     f, ft = g.standard_normal((p, 2)), g.standard_normal((p, 2))
+    c, ct = g.uniform(0, 1, (p, 3)), g.uniform(0, 1, (p, 3))
     for norm in (1, 2):
-        _, gr = O.loss_grad(d, a, dt, at, f, ft, 1.5, 2.5, norm)
-        for name, x in (("depth", d), ("alpha", a), ("flow", f)):
+        _, gr = O.loss_grad(d, a, dt, at, f, ft, 1.5, 2.5, norm, c, ct, 4.5)
+        for name, x in (("depth", d), ("alpha", a), ("flow", f), ("color", c)):
             fd = np.zeros_like(x)
             flat = x.reshape(-1)
             for j in range(flat.size):
-                h = 1e-7
+                h = 1e-6
                 x0 = flat[j]
                 flat[j] = x0 + h
-                lp, _ = O.loss_grad(d, a, dt, at, f, ft, 1.5, 2.5, norm)
+                lp, _ = O.loss_grad(d, a, dt, at, f, ft, 1.5, 2.5, norm, c, ct, 4.5)
                 flat[j] = x0 - h
-                lm, _ = O.loss_grad(d, a, dt, at, f, ft, 1.5, 2.5, norm)
+                lm, _ = O.loss_grad(d, a, dt, at, f, ft, 1.5, 2.5, norm, c, ct, 4.5)
                 flat[j] = x0
                 fd.reshape(-1)[j] = (lp - lm) / (2 * h)
-            _close(gr[name], fd, 1e-6, 1e-8, f"loss gradient {name} (q={norm})")
+            _close(gr[name], fd, 1e-6, 1e-7, f"loss gradient {name} (q={norm})")
     # outside the clamp range the alpha gradient vanishes
     _, gr = O.loss_grad([1.0, 1.0], [0.0, 1.0], [1.0, 1.0], [0.5, 0.5])
     assert np.all(gr["alpha"] == 0.0)

@@ -38,7 +38,7 @@ def test_binding_covers_header():
 
 
 def test_abi_version(lib):
-    assert lib.fmb_abi_version() == 1
+    assert lib.fmb_abi_version() == 2
 
 
 def test_invalid_arguments_rejected_without_gpu(lib):
@@ -52,10 +52,11 @@ def test_invalid_arguments_rejected_without_gpu(lib):
     assert lib.fmb_scene_create(ctypes.byref(h), 4, fake, fake, fake, fake, f(0.0)) == 1
     assert b"eta" in lib.fmb_last_error()
     assert lib.fmb_scene_create(ctypes.byref(h), 4, ctypes.c_void_p(4098), fake, fake, fake, f(1.0)) == 1
-    assert lib.fmb_render(None, None, None, None, None, None, None) == 1
-    assert lib.fmb_backward(None, *([None] * 11)) == 1
+    assert lib.fmb_render(None, None, None, None, None, None, None, None) == 1
+    assert lib.fmb_backward(None, *([None] * 14)) == 1
+    assert lib.fmb_set_colors(None, None, None) == 1
     assert lib.fmb_set_cameras(None, 1, None, None, None, None, None) == 1
-    assert lib.fmb_batch_forward(None, None, None, None, None, None, None) == 1
+    assert lib.fmb_batch_forward(None, None, None, None, None, None, None, None) == 1
     assert lib.fmb_batch_graph_launch(None, 2, None) == 1
     assert lib.fmb_scene_destroy(None) == 0
     assert lib.fmb_batch_destroy(None) == 0

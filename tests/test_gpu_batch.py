@@ -135,7 +135,8 @@ def test_graph_replay(fmb, batch16):
         for k in ("depth", "alpha", "normal"):
             assert torch.equal(outs_g[k], outs_e[k]), (rep, k)
         for k in grads_e:
-            assert torch.equal(grads_g[k], grads_e[k]), (rep, k)
+            if grads_e[k] is not None:
+                assert torch.equal(grads_g[k], grads_e[k]), (rep, k)
         _say(f"[graph] replay {rep} matches eager")
         # in-place update seen by the next replay
         with torch.no_grad():

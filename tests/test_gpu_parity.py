@@ -128,8 +128,8 @@ RAGGED = [
 ]
 
 
-def _hit_mask_cot(cot, alpha_ref, thr=1e-4):
-    """Depth/normal/flow cotangents only on rays that see the scene (oracle alpha >= thr); the
+def _hit_mask_cot(cot, alpha_ref, thr=1e-3):
+    """Depth/normal/flow/colour cotangents only on rays that see the scene (oracle alpha >= thr); the
     alpha cotangent everywhere.  Over background rays the blend weights are decided by
     log-density differences of order 1e4 that FP32 cannot resolve (see
     test_background_rays_conditioning)."""
@@ -285,7 +285,7 @@ def test_autograd_matches_backward(fmb):
     _say("[autograd] fwd64")
     scene, (m, p, wt, b) = make_scene(fmb, torch, sc, cams, w.betas, w.eta, DEV)
     params = [x.clone().requires_grad_(True) for x in (m, p, wt, b)]
-    depth, alpha, normal, _ = fmb.render(scene, *params, normals=True)
+    depth, alpha, normal, _, _ = fmb.render(scene, *params, normals=True)
     cot = W.random_cotangents(cams.n_rays, 77, flow=False)
     t = lambda a: torch.as_tensor(a, device=DEV)  # noqa: E731
     loss = (depth * t(cot["depth"])).sum() + (alpha * t(cot["alpha"])).sum() + (normal * t(cot["normal"])).sum()
@@ -305,7 +305,8 @@ def test_deterministic_backward(fmb):
     outs = scene.render(normals=True)
     cot = W.random_cotangents(cams.n_rays, 3, flow=False)
     t = lambda a: torch.as_tensor(a, device=DEV).contiguous()  # noqa: E731
-    g1 = {k: v.clone() for k, v in scene.backward(outs, t(cot["depth"]), t(cot["alpha"]), t(cot["normal"])).items()}
+    g1 = {k: v.clone() for k, v in scene.backward(outs, t(cot["depth"]), t(cot["alpha"]), t(cot["normal"])).items()
+          if v is not None}
     g2 = scene.backward(outs, t(cot["depth"]), t(cot["alpha"]), t(cot["normal"]))
     torch.cuda.synchronize()
     for k in g1:
@@ -325,14 +326,17 @@ def test_loss_grad_kernel(fmb, norm):
     alpha_t = (g.uniform(0, 1, p) > 0.4).astype(np.float32)
     flow = g.standard_normal((p, 2)).astype(np.float32)
     flow_t = g.standard_normal((p, 2)).astype(np.float32)
+    color = g.uniform(0, 1, (p, 3)).astype(np.float32)
+    color_t = g.uniform(0, 1, (p, 3)).astype(np.float32)
     _say(f"[loss-kernel] p={p} norm={norm}")
     t = lambda a: torch.as_tensor(a, device=DEV).contiguous()  # noqa: E731
     bl = torch.empty((p + 1023) // 1024, device=DEV)
-    cot = fmb.loss_grad({"depth": t(depth), "alpha": t(alpha), "flow": t(flow)}, t(depth_t), t(alpha_t),
-                        t(flow_t), w_depth=1.5, w_flow=2.5, flow_norm=norm, block_loss=bl)
+    cot = fmb.loss_grad({"depth": t(depth), "alpha": t(alpha), "flow": t(flow), "color": t(color)}, t(depth_t),
+                        t(alpha_t), t(flow_t), w_depth=1.5, w_flow=2.5, flow_norm=norm, block_loss=bl,
+                        color_t=t(color_t), w_color=4.5)
     torch.cuda.synchronize()
-    L, gref = O.loss_grad(depth, alpha, depth_t, alpha_t, flow, flow_t, 1.5, 2.5, norm)
-    for k in ("depth", "alpha", "flow"):
+    L, gref = O.loss_grad(depth, alpha, depth_t, alpha_t, flow, flow_t, 1.5, 2.5, norm, color, color_t, 4.5)
+    for k in ("depth", "alpha", "flow", "color"):
         got = to_np(cot[k])
         err = np.abs(got - gref[k])
         assert np.all(err <= 1e-5 * np.abs(gref[k]) + 1e-12), (k, float(err.max()))
@@ -377,3 +381,74 @@ def test_explicit_ray_minibatch(fmb):
     _say(f"[minibatch] {e} {eg}")
     assert_forward(e, "minibatch")
     assert_grads(eg, "minibatch")
+
+
+def test_colour_parity(fmb):
+    """Per-Gaussian colours (sigmoid of unconstrained parameters, blended by Eq. 3): forward colour
+    and the gradients of depth/alpha/normal/colour cotangents, against the oracle."""
+    w = W.make_config("fwdbwd128")
+    sc, cams = w.scenes[0], w.cameras[0]
+    g = np.random.Generator(np.random.PCG64(91))
+    q = (1.5 * g.standard_normal((sc.n, 3))).astype(np.float32)
+    _say(f"[colour] fwdbwd128 N={sc.n} P={cams.n_rays}")
+    scene, _ = make_scene(fmb, torch, sc, cams, w.betas, w.eta, DEV)
+    t = lambda a: torch.as_tensor(a, device=DEV).contiguous()  # noqa: E731
+    tq = t(q)
+    scene.set_colors(tq)
+    outs = scene.render(normals=True)
+    ref, _, _ = O.render_workload_view(sc, cams, w.betas, w.eta, colors=q)
+    e = compare_forward(outs, ref)
+    e["color"] = normwise(to_np(outs["color"]), ref["color"])
+    cot = _hit_mask_cot(W.random_cotangents(cams.n_rays, 31, flow=False), ref["alpha"])
+    cot["color"] = (g.standard_normal((cams.n_rays, 3)) * (ref["alpha"] >= 1e-3)[:, None]).astype(np.float32)
+    gr = scene.backward(outs, t(cot["depth"]), t(cot["alpha"]), t(cot["normal"]), None, g_color=t(cot["color"]))
+    torch.cuda.synchronize()
+    _, gref, _ = O.render_workload_view(sc, cams, w.betas, w.eta, cot=cot, colors=q)
+    eg = compare_grads(gr, gref)
+    eg["colors"] = normwise(to_np(gr["colors"]), gref["colors"])
+    _say(f"[colour] {e} {eg}")
+    assert_forward(e, "colour")
+    assert e["color"] <= TOL_REL
+    assert_grads(eg, "colour")
+
+
+def test_colour_autograd_and_batch(fmb):
+    """Colours through the autograd function, and the batched persistent path with colours equals
+    the per-scene path bit for bit."""
+    w = W.make_config("batch16")
+    idx = [1, 8, 14]
+    scenes = [w.scenes[i] for i in idx]
+    camsl = [w.cameras[i] for i in idx]
+    g = np.random.Generator(np.random.PCG64(92))
+    qs = [(1.5 * g.standard_normal((s.n, 3))).astype(np.float32) for s in scenes]
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=DEV).contiguous()  # noqa: E731
+    means = t(np.concatenate([s.means for s in scenes]))
+    prec = t(np.concatenate([s.prec for s in scenes]))
+    weights = t(np.concatenate([s.weights for s in scenes]))
+    betas = t(np.tile(w.betas, (len(scenes), 1)))
+    colors = t(np.concatenate(qs))
+    cams = [fmb.Cameras.from_numpy(c.w2c, c.intr, c.hw, device=DEV) for c in camsl]
+    b = fmb.Batch(means, prec, weights, betas, [w.eta] * len(scenes), [s.n for s in scenes], cams)
+    b.set_colors(colors)
+    _say(f"[colour-batch] scenes {idx} P={b.n_rays}")
+    outs = b.forward(b.alloc_outputs(normals=True, color=True))
+    gc = W.random_cotangents(b.n_rays, 93, flow=False)
+    cot = {"depth": t(gc["depth"]), "alpha": t(gc["alpha"]), "normal": None, "flow": None,
+           "color": t(g.standard_normal((b.n_rays, 3)).astype(np.float32))}
+    grads = b.backward(outs, cot, b.alloc_grads(colors=True))
+    torch.cuda.synchronize()
+    for i in range(len(scenes)):
+        r0, r1 = b.ray_off[i], b.ray_off[i + 1]
+        g0, g1 = b.gauss_off[i], b.gauss_off[i + 1]
+        scene = fmb.Scene(means[g0:g1], prec[g0:g1], weights[g0:g1], betas[i], w.eta, cams[i])
+        params = [x.clone().requires_grad_(True) for x in (means[g0:g1], prec[g0:g1], weights[g0:g1],
+                                                               betas[i], colors[g0:g1])]
+        depth, alpha, normal, _, color = fmb.render(scene, *params[:4], normals=True, colors=params[4])
+        assert torch.equal(color, outs["color"][r0:r1]) and torch.equal(depth, outs["depth"][r0:r1])
+        loss = (depth * cot["depth"][r0:r1]).sum() + (alpha * cot["alpha"][r0:r1]).sum() \
+            + (color * cot["color"][r0:r1]).sum() + 0.0 * normal.sum()
+        loss.backward()
+        torch.cuda.synchronize()
+        for x, k in zip(params, ("means", "prec", "weights", "betas", "colors")):
+            ref = grads[k][i] if k == "betas" else grads[k][g0:g1]
+            assert torch.equal(x.grad, ref), (i, k)
