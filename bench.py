@@ -31,13 +31,10 @@ if ROOT not in sys.path:
 # method's per-pair formulas (add/sub/mul/compare = 1, fused multiply-add = 2, exp /
 # reciprocal / rsqrt = 1), excluding the backward's recomputation of the forward pair
 # terms and the extra precision steps (hi/lo mean, Newton refinement of the peak).
-FLOPS_FWD_NORMALS = 75     # intersection, density, weight, online blend, normal blend
-FLOPS_FWD_PLAIN = 53       # without the normal terms
-FLOPS_ADJ_NORMALS = 87     # adjoint with a normal cotangent
-FLOPS_ADJ_PLAIN = 60       # adjoint of depth/alpha/flow cotangents only
-# Executed per pair by the kernels (VALU arithmetic incl. recompute, refinement, hi/lo).
-FLOPS_FWD_EXEC = 97
-FLOPS_BWD_EXEC_PLAIN = 144
+FLOPS_FWD_NORMALS = 76     # intersection, density, weight, online blend, normal blend
+FLOPS_FWD_PLAIN = 54       # without the normal terms
+FLOPS_ADJ_NORMALS = 92     # adjoint with a normal cotangent
+FLOPS_ADJ_PLAIN = 61       # adjoint of depth/alpha/flow cotangents only
 PEAK_FP32 = 157.3e12       # MI355X FP32 vector peak (packed FP32 at 2.4 GHz x 256 CUs)
 PEAK_FP32_SCALAR = 78.6e12  # without packed FP32 issue
 PEAK_HBM = 8.0e12
@@ -277,8 +274,6 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": measured_traffic(),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
                      "kernel": "bwd_kernel (persistent)", "flops_per_pair": FLOPS_ADJ_PLAIN,
-                     "executed_flops_per_pair": FLOPS_BWD_EXEC_PLAIN,
-                     "executed_frac": pairs * FLOPS_BWD_EXEC_PLAIN / (bwd_ms * 1e-3) / PEAK_FP32,
                      "peak_scalar_fp32": PEAK_FP32_SCALAR / 1e12},
     }
     if not args.no_cpu_baseline:

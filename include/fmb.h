@@ -27,7 +27,8 @@
  *                sum_{k'<k} H_k' W_k' + i W_k + j.  P is the total ray count.
  *   outputs      depth[P] = blended peak distance t_f along the unit ray (Eq. 3);
  *                alpha[P] (Eq. 8); normal[P,3] unit world-frame blended normal;
- *                flow[P,2] = pi_B(p) - pi_A(p) in pixels, p = origin + t_f * direction;
+ *                flow[P,2] = pi_B(p) - pi_A(p) in pixels, p = origin + t_f * direction
+ *                ([P,4] with a second flow target, see fmb_set_flow_pose2);
  *                color[P,3] blended colour; stash[P,8] = per-ray state the backward pass
  *                reads: (running max of the base-2 log weights, 1/sum of the shifted weights
  *                = max_i of the normalised weights (the Sec. 6 quality test), unnormalised
@@ -53,7 +54,7 @@
 extern "C" {
 #endif
 
-#define FMB_ABI_VERSION 2
+#define FMB_ABI_VERSION 3
 
 enum fmb_status {
     FMB_OK = 0,
@@ -121,6 +122,14 @@ int fmb_set_rays(fmb_scene *scene, int32_t v, const float *w2c, const float *int
 
 /* Number of rays P of the current cameras (0 before fmb_set_cameras). */
 int64_t fmb_num_rays(const fmb_scene *scene);
+
+/* Add (or with NULL remove) a second flow target per view, so that every ray gets both the
+ * forward and the backward flow (Sec. 5: poses i+1 and i-1): w2c_c device [v,3,4], intr_c
+ * device [v,4] (batch: concatenated views), borrowed.  The flow output and cotangent then
+ * have 4 columns per ray: (flow to pose B, flow to pose C).  Needs the first target
+ * (w2c_b) to be set; fmb_set_cameras / fmb_set_rays clear it. */
+int fmb_set_flow_pose2(fmb_scene *scene, fmb_batch *batch, const float *w2c_c,
+                       const float *intr_c);
 
 /* Set (or with NULL clear) the per-Gaussian colours of a scene or batch (exactly one
  * non-NULL): device [n,3] (batch: [sum n,3]) unconstrained parameters q, borrowed; the
@@ -228,20 +237,21 @@ int fmb_autotune(fmb_scene *scene, fmb_batch *batch, float *depth, float *alpha,
  *                 + w_depth a*_r |depth_r - depth*_r|               (mask-weighted L1)
  *                 + w_color a*_r |color_r - color*_r|_1              (Eq. 12)
  *                 + w_flow  a*_r |flow_r - flow*_r|_q ]             (Eq. 13; q = 1: L1 of
- *                                                                   the 2 components, q = 2:
+ *                                                                   the flow components, q = 2:
  *                                                                   squared L2)
  * where a* = alpha_t is the target mask (the paper's lambda_C = 4.5 and lambda_F = 210 are
  * w_color and w_flow).  depth, alpha, depth_t, alpha_t: device [p]; flow, flow_t: device
- * [p,2] or NULL (no flow term; then g_flow must be NULL too); color, color_t: [p,3] or
- * NULL likewise.  g_depth, g_alpha: device [p] (written); g_flow [p,2], g_color [p,3] or
- * NULL.  The clamp passes the gradient where 1e-6 <= alpha <= 1 - 1e-6 (float32 bounds);
+ * [p,flow_cols] (flow_cols 2, or 4 for forward and backward flow) or NULL (no flow term;
+ * then g_flow must be NULL too); color, color_t: [p,3] or NULL likewise.  g_depth, g_alpha:
+ * device [p] (written); g_flow [p,flow_cols], g_color [p,3] or NULL.  The clamp passes the gradient where 1e-6 <= alpha <= 1 - 1e-6 (float32 bounds);
  * |x|' is sign(x) (0 at 0).  block_loss: device [ceil(p / 1024)] or NULL; if given,
  * receives per-block partial sums of L (sum them for the loss; the order is fixed).
- * Errors: FMB_ERR_INVALID_ARG (p < 1, NULL required pointer, flow_norm not 1 or 2). */
+ * Errors: FMB_ERR_INVALID_ARG (p < 1, NULL required pointer, flow_norm not 1 or 2,
+ * flow_cols not 2 or 4). */
 int fmb_loss_grad(int64_t p, const float *depth, const float *alpha, const float *flow,
                   const float *color, const float *depth_t, const float *alpha_t,
                   const float *flow_t, const float *color_t, float w_depth, float w_flow,
-                  int32_t flow_norm, float w_color, float *g_depth, float *g_alpha,
+                  int32_t flow_norm, int32_t flow_cols, float w_color, float *g_depth, float *g_alpha,
                   float *g_flow, float *g_color, float *block_loss, void *stream);
 
 /* Current launch configuration of a scene or batch (exactly one non-NULL), written to the

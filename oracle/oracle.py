@@ -157,8 +157,19 @@ def _cams(view, w2c_a, intr_a, w2c_b, intr_b):
 
 
 def render(scene: OracleScene, orig, dirs, view=None, w2c_a=None, intr_a=None, w2c_b=None,
-           intr_b=None, n_threads: int = 0):
-    """Forward pass over explicit rays; returns dict(depth, alpha, normal, flow)."""
+           intr_b=None, n_threads: int = 0, w2c_c=None, intr_c=None):
+    """Forward pass over explicit rays; returns dict(depth, alpha, normal, flow, color).
+
+    With a third pose (w2c_c, intr_c) the flow has 4 columns per ray: the flow to pose B and
+    the flow to pose C (Sec. 5 estimates forward and backward flow for every ray); each is the
+    same definition, pi_X(p) - pi_A(p), evaluated for its own target pose."""
+    if w2c_c is not None:
+        if w2c_b is None:
+            raise ValueError("a third pose needs the second one")
+        out = render(scene, orig, dirs, view, w2c_a, intr_a, w2c_b, intr_b, n_threads)
+        back = render(scene, orig, dirs, view, w2c_a, intr_a, w2c_c, intr_c, n_threads)
+        out["flow"] = np.concatenate([out["flow"], back["flow"]], axis=1)
+        return out
     lib = load()
     orig, dirs = _d(orig).reshape(-1, 3), _d(dirs).reshape(-1, 3)
     p = orig.shape[0]
@@ -177,8 +188,20 @@ def render(scene: OracleScene, orig, dirs, view=None, w2c_a=None, intr_a=None, w
 
 
 def backward(scene: OracleScene, orig, dirs, cot: dict, view=None, w2c_a=None, intr_a=None,
-             w2c_b=None, intr_b=None, n_threads: int = 0):
-    """Gradients of sum(cot . outputs) w.r.t. means [N,3], prec [N,6], weights [N], betas [2]."""
+             w2c_b=None, intr_b=None, n_threads: int = 0, w2c_c=None, intr_c=None):
+    """Gradients of sum(cot . outputs) w.r.t. means [N,3], prec [N,6], weights [N], betas [2]
+    (and colours [N,3] when the scene has them).
+
+    With a third pose the flow cotangent has 4 columns; the objective is then the sum of the
+    usual one (flow to B) and the flow-to-C term alone, so its gradient is the sum of the two
+    gradients (linearity of the derivative)."""
+    if w2c_c is not None:
+        gf = np.asarray(cot["flow"], np.float64).reshape(-1, 4)
+        first = dict(cot, flow=gf[:, :2])
+        g1 = backward(scene, orig, dirs, first, view, w2c_a, intr_a, w2c_b, intr_b, n_threads)
+        g2 = backward(scene, orig, dirs, {"flow": gf[:, 2:]}, view, w2c_a, intr_a, w2c_c, intr_c,
+                      n_threads)
+        return {k: None if g1[k] is None else g1[k] + g2[k] for k in g1}
     lib = load()
     orig, dirs = _d(orig).reshape(-1, 3), _d(dirs).reshape(-1, 3)
     p = orig.shape[0]
@@ -196,6 +219,19 @@ def backward(scene: OracleScene, orig, dirs, cot: dict, view=None, w2c_a=None, i
     if rc != 0:
         raise ValueError("oracle backward rejected its arguments")
     return out
+
+
+def max_weight(scene: OracleScene, orig, dirs):
+    """max_i of the normalised blend weights w_i = exp(z_i) / sum_j exp(z_j) per ray: the
+    direct-intersection quality of Sec. 6 (points with max_i w_i <= eps are rejected for mesh
+    export).  Small inputs only: one ray_terms call per ray."""
+    orig, dirs = _d(orig).reshape(-1, 3), _d(dirs).reshape(-1, 3)
+    q = np.empty(orig.shape[0])
+    for r in range(orig.shape[0]):
+        _, _, z, _ = ray_terms(scene, orig[r], dirs[r])
+        w = np.exp(z - z.max())
+        q[r] = (w / w.sum()).max()
+    return q
 
 
 def ray_terms(scene: OracleScene, o, v):
@@ -222,7 +258,8 @@ def render_workload_view(scene, cams, betas, eta, rays=None, n_threads: int = 0,
     o, v = pixel_rays(view, row, col, cams.w2c, cams.intr)
     sc = OracleScene.of(scene.means, scene.prec, scene.weights, betas, eta, colors)
     kw = dict(view=view, w2c_a=cams.w2c, intr_a=cams.intr, w2c_b=cams.w2c_b, intr_b=cams.intr_b,
-              n_threads=n_threads)
+              n_threads=n_threads, w2c_c=getattr(cams, "w2c_c", None),
+              intr_c=getattr(cams, "intr_c", None))
     out = render(sc, o, v, **kw)
     grads = backward(sc, o, v, cot, **kw) if cot is not None else None
     return out, grads, (view, row, col)

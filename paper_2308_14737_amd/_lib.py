@@ -32,6 +32,7 @@ SIGNATURES = {
     "fmb_set_rays": (_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fmb_num_rays": (_i64, [_vp]),
     "fmb_set_colors": (_int, [_vp, _vp, _vp]),
+    "fmb_set_flow_pose2": (_int, [_vp, _vp, _vp, _vp]),
     "fmb_render": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fmb_backward": (_int, [_vp] + [_vp] * 13 + [_vp]),
     "fmb_batch_create": (_int, [ctypes.POINTER(_vp), _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
@@ -45,7 +46,7 @@ SIGNATURES = {
     "fmb_batch_capture": (_int, [_vp] + [_vp] * 16 + [_vp]),
     "fmb_batch_graph_launch": (_int, [_vp, _i32, _vp]),
     "fmb_autotune": (_int, [_vp, _vp] + [_vp] * 16 + [ctypes.c_char_p, _vp]),
-    "fmb_loss_grad": (_int, [_i64] + [_vp] * 8 + [_f32, _f32, _i32, _f32] + [_vp] * 5 + [_vp]),
+    "fmb_loss_grad": (_int, [_i64] + [_vp] * 8 + [_f32, _f32, _i32, _i32, _f32] + [_vp] * 5 + [_vp]),
     "fmb_validate": (_int, [_vp, ctypes.POINTER(_i32), _vp]),
     "fmb_get_config": (_int, [_vp, _vp, ctypes.POINTER(_i32)]),
     "fmb_timing_enable": (_int, [_int]),

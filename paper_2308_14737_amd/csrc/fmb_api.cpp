@@ -39,8 +39,8 @@ hipError_t launch_fin(int n_tasks, int n_groups, hipStream_t st, const Params &P
 hipError_t launch_fill(int *p, int n, int value, hipStream_t st);
 hipError_t launch_loss(int p, const float *depth, const float *alpha, const float *flow, const float *color,
                        const float *depth_t, const float *alpha_t, const float *flow_t, const float *color_t,
-                       float w_depth, float w_flow, int flow_norm, float w_color, float *g_depth, float *g_alpha,
-                       float *g_flow, float *g_color, float *block_loss, hipStream_t st);
+                       float w_depth, float w_flow, int flow_norm, int flow_cols, float w_color, float *g_depth,
+                       float *g_alpha, float *g_flow, float *g_color, float *block_loss, hipStream_t st);
 hipError_t launch_validate(const Params &P, int n_total, int n_scenes, int *flags, hipStream_t st);
 hipError_t occupancy_fwd(int variant, int flags, int *blocks_per_cu);
 hipError_t occupancy_bwd(int variant, int flags, int *blocks_per_cu);
@@ -617,6 +617,7 @@ int fmb_set_cameras(fmb_scene *s, int32_t v, const float *w2c, const float *intr
     j.prm.intr = intr;
     j.prm.w2c_b = w2c_b;
     j.prm.intr_b = intr_b;
+    j.prm.w2c_c = j.prm.intr_c = nullptr;
     j.prm.dirs = nullptr;
     j.has_flow = w2c_b != nullptr;
     j.fwd_built = j.bwd_built = -1;
@@ -657,6 +658,7 @@ int fmb_set_rays(fmb_scene *s, int32_t v, const float *w2c, const float *intr, c
     j.prm.intr = intr;
     j.prm.w2c_b = w2c_b;
     j.prm.intr_b = intr_b;
+    j.prm.w2c_c = j.prm.intr_c = nullptr;
     j.prm.dirs = dirs;
     j.has_flow = w2c_b != nullptr;
     j.fwd_built = j.bwd_built = -1;
@@ -668,6 +670,20 @@ int fmb_set_rays(fmb_scene *s, int32_t v, const float *w2c, const float *intr, c
 }
 
 int64_t fmb_num_rays(const fmb_scene *s) { return (s && s->job.cams_set) ? s->job.P : 0; }
+
+int fmb_set_flow_pose2(fmb_scene *s, fmb_batch *b, const float *w2c_c, const float *intr_c)
+{
+    g_err.clear();
+    CHECK_ARG((s != nullptr) != (b != nullptr), "exactly one of scene and batch must be given");
+    CHECK_ARG((w2c_c == nullptr) == (intr_c == nullptr), "w2c_c and intr_c must both be given or both NULL");
+    CHECK_ARG(!w2c_c || (aligned(w2c_c, 4) && aligned(intr_c, 4)), "camera arrays must be 4-byte aligned");
+    Job &j = s ? s->job : b->job;
+    if (!j.cams_set) return fail(FMB_ERR_STATE, "set the cameras first");
+    CHECK_ARG(!w2c_c || j.has_flow, "a second flow target needs the first one (w2c_b, intr_b)");
+    j.prm.w2c_c = w2c_c;
+    j.prm.intr_c = intr_c;
+    return FMB_OK;
+}
 
 int fmb_set_colors(fmb_scene *s, fmb_batch *b, const float *colors)
 {
@@ -1037,8 +1053,8 @@ int fmb_autotune(fmb_scene *s, fmb_batch *b, float *depth, float *alpha, float *
 
 int fmb_loss_grad(int64_t p, const float *depth, const float *alpha, const float *flow, const float *color,
                   const float *depth_t, const float *alpha_t, const float *flow_t, const float *color_t,
-                  float w_depth, float w_flow, int32_t flow_norm, float w_color, float *g_depth, float *g_alpha,
-                  float *g_flow, float *g_color, float *block_loss, void *stream)
+                  float w_depth, float w_flow, int32_t flow_norm, int32_t flow_cols, float w_color,
+                  float *g_depth, float *g_alpha, float *g_flow, float *g_color, float *block_loss, void *stream)
 {
     g_err.clear();
     CHECK_ARG(p >= 1 && p <= INT32_MAX, "p must be in [1, 2^31)");
@@ -1048,8 +1064,9 @@ int fmb_loss_grad(int64_t p, const float *depth, const float *alpha, const float
     CHECK_ARG((color == nullptr) == (color_t == nullptr) && (color == nullptr) == (g_color == nullptr),
               "color, color_t and g_color must all be given or all be NULL");
     CHECK_ARG(flow_norm == 1 || flow_norm == 2, "flow_norm must be 1 or 2");
+    CHECK_ARG(flow_cols == 2 || flow_cols == 4, "flow_cols must be 2 or 4");
     HIPCHK(launch_loss((int)p, depth, alpha, flow, color, depth_t, alpha_t, flow_t, color_t, w_depth, w_flow,
-                       flow_norm, w_color, g_depth, g_alpha, g_flow, g_color, block_loss, (hipStream_t)stream));
+                       flow_norm, flow_cols, w_color, g_depth, g_alpha, g_flow, g_color, block_loss, (hipStream_t)stream));
     return FMB_OK;
 }
 

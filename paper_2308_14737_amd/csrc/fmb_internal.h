@@ -78,6 +78,7 @@ struct Params {
     const float *means, *prec, *weights, *betas;   // concatenated over scenes; betas [S,2]
     const float *eta;                               // device [S]
     const float *w2c, *intr, *w2c_b, *intr_b;       // per global view
+    const float *w2c_c, *intr_c;                    // optional second flow target per view, or NULL
     const float *dirs;                              // explicit ray directions [P,3] or NULL (pixel rays)
     const float *colors;                            // unconstrained colours [N,3] or NULL
     const ViewRec *views;

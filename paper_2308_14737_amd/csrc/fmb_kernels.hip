@@ -311,12 +311,20 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
                 O.normal[3 * r + 2] = n2 * inn;
             }
             if (FLOW) {
+                // flow to the second pose (and, if given, to a third: forward and backward flow)
                 const float p0 = fmaf(tf, v0[j], o0), p1 = fmaf(tf, v1[j], o1), p2 = fmaf(tf, v2[j], o2);
                 float ub, vb, ua, va;
                 project(P.w2c_b + 12 * item.view, P.intr_b + 4 * item.view, p0, p1, p2, ub, vb);
                 project(e, kk, p0, p1, p2, ua, va);
-                O.flow[2 * r + 0] = ub - ua;
-                O.flow[2 * r + 1] = vb - va;
+                const int fk = P.w2c_c ? 4 : 2;
+                O.flow[fk * r + 0] = ub - ua;
+                O.flow[fk * r + 1] = vb - va;
+                if (P.w2c_c) {
+                    float uc, vc;
+                    project(P.w2c_c + 12 * item.view, P.intr_c + 4 * item.view, p0, p1, p2, uc, vc);
+                    O.flow[fk * r + 2] = uc - ua;
+                    O.flow[fk * r + 3] = vc - va;
+                }
             }
             if (COLOR) {
                 O.color[3 * r + 0] = C0[j] * invS;
@@ -336,6 +344,23 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
 // ------------------------------------------------------------------------------------
 // Backward
 // ------------------------------------------------------------------------------------
+
+// g . d pi(p + t v)/dt at t = 0 for camera e (world-to-camera) and intrinsics k.
+__device__ __forceinline__ float flow_dot(const float *__restrict__ e, const float *__restrict__ k, float p0,
+                                          float p1, float p2, float v0, float v1, float v2,
+                                          const float *__restrict__ g)
+{
+    const float q0 = fmaf(e[0], p0, fmaf(e[1], p1, fmaf(e[2], p2, e[3])));
+    const float q1 = fmaf(e[4], p0, fmaf(e[5], p1, fmaf(e[6], p2, e[7])));
+    const float q2 = fmaf(e[8], p0, fmaf(e[9], p1, fmaf(e[10], p2, e[11])));
+    const float u0 = fmaf(e[0], v0, fmaf(e[1], v1, e[2] * v2));
+    const float u1 = fmaf(e[4], v0, fmaf(e[5], v1, e[6] * v2));
+    const float u2 = fmaf(e[8], v0, fmaf(e[9], v1, e[10] * v2));
+    const float iz = 1.0f / q2;
+    const float j0 = k[0] * (u0 - q0 * iz * u2) * iz;
+    const float j1 = k[1] * (u1 - q1 * iz * u2) * iz;
+    return fmaf(g[0], j0, g[1] * j1);
+}
 
 // Per-ray adjoint prologue, staged in LDS as RW float4:
 //   (v0, v1, v2, M2) (invS, tf_bar, Nb0, Nb1) (Nb2, kappa, D_bar, 0) [(Cb0, Cb1, Cb2, 0)]
@@ -365,20 +390,13 @@ __device__ __forceinline__ void ray_prologue(const Params &P, const BwdIn &I, in
     const float Nx = s0.z, Ny = s0.w, Nz = s1.x, Dsum = s1.y;
     float tfb = I.g_depth ? I.g_depth[r] : 0.0f;
     if (FLOW) {
-        // flow = pi_B(p) - pi_A(p), p = o + t_f v; pi_A(o + t v) does not depend on t.
-        const float *__restrict__ eb = P.w2c_b + 12 * view;
-        const float *__restrict__ kb = P.intr_b + 4 * view;
+        // flow = pi_B(p) - pi_A(p), p = o + t_f v; pi_A(o + t v) does not depend on t, so
+        // d flow / d t_f = J_B R_B v (and likewise for the optional third pose).
         const float p0 = fmaf(tf, v0, o0), p1 = fmaf(tf, v1, o1), p2 = fmaf(tf, v2, o2);
-        const float q0 = fmaf(eb[0], p0, fmaf(eb[1], p1, fmaf(eb[2], p2, eb[3])));
-        const float q1 = fmaf(eb[4], p0, fmaf(eb[5], p1, fmaf(eb[6], p2, eb[7])));
-        const float q2 = fmaf(eb[8], p0, fmaf(eb[9], p1, fmaf(eb[10], p2, eb[11])));
-        const float u0 = fmaf(eb[0], v0, fmaf(eb[1], v1, eb[2] * v2));
-        const float u1 = fmaf(eb[4], v0, fmaf(eb[5], v1, eb[6] * v2));
-        const float u2 = fmaf(eb[8], v0, fmaf(eb[9], v1, eb[10] * v2));
-        const float iz = 1.0f / q2;
-        const float j0 = kb[0] * (u0 - q0 * iz * u2) * iz;
-        const float j1 = kb[1] * (u1 - q1 * iz * u2) * iz;
-        tfb = fmaf(I.g_flow[2 * r], j0, fmaf(I.g_flow[2 * r + 1], j1, tfb));
+        const int fk = P.w2c_c ? 4 : 2;
+        tfb += flow_dot(P.w2c_b + 12 * view, P.intr_b + 4 * view, p0, p1, p2, v0, v1, v2, I.g_flow + fk * r);
+        if (P.w2c_c)
+            tfb += flow_dot(P.w2c_c + 12 * view, P.intr_c + 4 * view, p0, p1, p2, v0, v1, v2, I.g_flow + fk * r + 2);
     }
     const float Db = I.g_alpha ? I.g_alpha[r] * expf(-Dsum) : 0.0f;
     float nb0 = 0.0f, nb1 = 0.0f, nb2 = 0.0f;
@@ -722,8 +740,8 @@ __global__ __launch_bounds__(kLossBlock) void loss_kernel(int p, const float *__
                                                          const float *__restrict__ alpha_t,
                                                          const float *__restrict__ flow_t,
                                                          const float *__restrict__ color_t, float w_depth,
-                                                         float w_flow, int flow_norm, float w_color,
-                                                         float *__restrict__ g_depth, float *__restrict__ g_alpha,
+                                                         float w_flow, int flow_norm, int flow_cols,
+                                                         float w_color, float *__restrict__ g_depth, float *__restrict__ g_alpha,
                                                          float *__restrict__ g_flow, float *__restrict__ g_color,
                                                          float *__restrict__ block_loss)
 {
@@ -741,15 +759,15 @@ __global__ __launch_bounds__(kLossBlock) void loss_kernel(int p, const float *__
         g_depth[r] = w_depth * at * (float)((dd > 0.0f) - (dd < 0.0f)) * inv_p;
         l = -(at * logf(ac) + (1.0f - at) * logf(1.0f - ac)) + w_depth * at * fabsf(dd);
         if (flow) {
-            const float f0 = flow[2 * r] - flow_t[2 * r], f1 = flow[2 * r + 1] - flow_t[2 * r + 1];
-            if (flow_norm == 1) {
-                g_flow[2 * r] = w_flow * at * (float)((f0 > 0.0f) - (f0 < 0.0f)) * inv_p;
-                g_flow[2 * r + 1] = w_flow * at * (float)((f1 > 0.0f) - (f1 < 0.0f)) * inv_p;
-                l += w_flow * at * (fabsf(f0) + fabsf(f1));
-            } else {
-                g_flow[2 * r] = 2.0f * w_flow * at * f0 * inv_p;
-                g_flow[2 * r + 1] = 2.0f * w_flow * at * f1 * inv_p;
-                l += w_flow * at * (f0 * f0 + f1 * f1);
+            for (int c = 0; c < flow_cols; ++c) {
+                const float f = flow[flow_cols * r + c] - flow_t[flow_cols * r + c];
+                if (flow_norm == 1) {
+                    g_flow[flow_cols * r + c] = w_flow * at * (float)((f > 0.0f) - (f < 0.0f)) * inv_p;
+                    l += w_flow * at * fabsf(f);
+                } else {
+                    g_flow[flow_cols * r + c] = 2.0f * w_flow * at * f * inv_p;
+                    l += w_flow * at * f * f;
+                }
             }
         }
         if (color) {
@@ -777,11 +795,11 @@ __global__ __launch_bounds__(kLossBlock) void loss_kernel(int p, const float *__
 
 hipError_t launch_loss(int p, const float *depth, const float *alpha, const float *flow, const float *color,
                        const float *depth_t, const float *alpha_t, const float *flow_t, const float *color_t,
-                       float w_depth, float w_flow, int flow_norm, float w_color, float *g_depth, float *g_alpha,
-                       float *g_flow, float *g_color, float *block_loss, hipStream_t st)
+                       float w_depth, float w_flow, int flow_norm, int flow_cols, float w_color, float *g_depth,
+                       float *g_alpha, float *g_flow, float *g_color, float *block_loss, hipStream_t st)
 {
     hipLaunchKernelGGL(loss_kernel, dim3((p + kLossBlock - 1) / kLossBlock), dim3(kLossBlock), 0, st, p, depth, alpha,
-                       flow, color, depth_t, alpha_t, flow_t, color_t, w_depth, w_flow, flow_norm, w_color, g_depth,
+                       flow, color, depth_t, alpha_t, flow_t, color_t, w_depth, w_flow, flow_norm, flow_cols, w_color, g_depth,
                        g_alpha, g_flow, g_color, block_loss);
     return hipGetLastError();
 }

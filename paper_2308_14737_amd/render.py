@@ -49,13 +49,20 @@ class Cameras:
     hw: np.ndarray
     w2c_b: Optional[torch.Tensor] = None
     intr_b: Optional[torch.Tensor] = None
+    w2c_c: Optional[torch.Tensor] = None   # optional second flow target (backward flow)
+    intr_c: Optional[torch.Tensor] = None
 
     @classmethod
-    def from_numpy(cls, w2c, intr, hw, w2c_b=None, intr_b=None, device="cuda") -> "Cameras":
+    def from_numpy(cls, w2c, intr, hw, w2c_b=None, intr_b=None, device="cuda", w2c_c=None,
+                   intr_c=None) -> "Cameras":
+        opt = lambda a: None if a is None else _dev_f32(a, device)  # noqa: E731
         return cls(_dev_f32(w2c, device), _dev_f32(intr, device),
-                   np.ascontiguousarray(np.asarray(hw, dtype=np.int32)),
-                   None if w2c_b is None else _dev_f32(w2c_b, device),
-                   None if intr_b is None else _dev_f32(intr_b, device))
+                   np.ascontiguousarray(np.asarray(hw, dtype=np.int32)), opt(w2c_b), opt(intr_b),
+                   opt(w2c_c), opt(intr_c))
+
+    @property
+    def flow_cols(self) -> int:
+        return 0 if self.w2c_b is None else (4 if self.w2c_c is not None else 2)
 
     @property
     def v(self) -> int:
@@ -117,6 +124,8 @@ class Scene:
         hw = np.ascontiguousarray(cams.hw, dtype=np.int32)
         _lib.call("fmb_set_cameras", self._h, cams.v, _vp(cams.w2c), _vp(cams.intr),
                   hw.ctypes.data_as(ctypes.c_void_p), _vp(cams.w2c_b), _vp(cams.intr_b))
+        if cams.w2c_c is not None:
+            _lib.call("fmb_set_flow_pose2", self._h, None, _vp(cams.w2c_c), _vp(cams.intr_c))
         self.cameras = cams
         self._hw = hw
 
@@ -129,6 +138,8 @@ class Scene:
             raise ValueError("dirs must be [sum(counts), 3]")
         _lib.call("fmb_set_rays", self._h, int(cnt.shape[0]), _vp(cams.w2c), _vp(cams.intr),
                   cnt.ctypes.data_as(ctypes.c_void_p), _vp(dirs), _vp(cams.w2c_b), _vp(cams.intr_b))
+        if cams.w2c_c is not None:
+            _lib.call("fmb_set_flow_pose2", self._h, None, _vp(cams.w2c_c), _vp(cams.intr_c))
         self.cameras = cams
         self._dirs = dirs
         self._hw = cnt
@@ -153,7 +164,8 @@ class Scene:
             normal = o.get("normal") if o.get("normal") is not None else torch.empty(p, 3, device=dev)
         fl = None
         if flow:
-            fl = o.get("flow") if o.get("flow") is not None else torch.empty(p, 2, device=dev)
+            fl = o.get("flow") if o.get("flow") is not None else torch.empty(p, self.cameras.flow_cols,
+                                                                             device=dev)
         col = None
         if color:
             col = o.get("color") if o.get("color") is not None else torch.empty(p, 3, device=dev)
@@ -163,6 +175,12 @@ class Scene:
         _lib.call("fmb_render", self._h, _vp(depth), _vp(alpha), _vp(normal), _vp(fl), _vp(col), _vp(st),
                   _stream(dev))
         return {"depth": depth, "alpha": alpha, "normal": normal, "flow": fl, "color": col, "stash": st}
+
+    @staticmethod
+    def quality(outs: dict) -> torch.Tensor:
+        """max_i of the normalised blend weights per ray (the Sec. 6 direct-intersection test
+        max_i w_i > eps for point export), read from the stash."""
+        return outs["stash"][:, 1]
 
     def backward(self, outs: dict, g_depth=None, g_alpha=None, g_normal=None, g_flow=None,
                  grads: Optional[dict] = None, g_color=None) -> dict:
@@ -271,6 +289,11 @@ class Batch:
             raise ValueError("either every scene or none has a second pose")
         self.w2c_b = torch.cat([c.w2c_b.reshape(-1, 12) for c in cams]).contiguous() if all(flows) else None
         self.intr_b = torch.cat([c.intr_b.reshape(-1, 4) for c in cams]).contiguous() if all(flows) else None
+        second = [c.w2c_c is not None for c in cams]
+        if any(second) and not all(second):
+            raise ValueError("either every scene or none has a second flow target")
+        self.w2c_c = torch.cat([c.w2c_c.reshape(-1, 12) for c in cams]).contiguous() if all(second) else None
+        self.intr_c = torch.cat([c.intr_c.reshape(-1, 4) for c in cams]).contiguous() if all(second) else None
         self.n_total = int(self.n_host.sum())
         self._keep = (means, prec, weights, betas)
         h = ctypes.c_void_p()
@@ -279,6 +302,8 @@ class Batch:
                   _vp(betas), self.eta.ctypes.data_as(ctypes.c_void_p), _vp(self.w2c), _vp(self.intr),
                   self.hw.ctypes.data_as(ctypes.c_void_p), _vp(self.w2c_b), _vp(self.intr_b))
         self._h = h
+        if self.w2c_c is not None:
+            _lib.call("fmb_set_flow_pose2", None, h, _vp(self.w2c_c), _vp(self.intr_c))
         lib = _lib.load()
         self.n_rays = int(lib.fmb_batch_num_rays(h))
         self.ray_off = [int(lib.fmb_batch_ray_offset(h, i)) for i in range(self.s + 1)]
@@ -287,6 +312,10 @@ class Batch:
     @property
     def has_flow(self) -> bool:
         return self.w2c_b is not None
+
+    @property
+    def flow_cols(self) -> int:
+        return 0 if self.w2c_b is None else (4 if self.w2c_c is not None else 2)
 
     def set_colors(self, colors: Optional[torch.Tensor]):
         """Per-Gaussian colours [sum N, 3] (unconstrained), or None."""
@@ -299,7 +328,7 @@ class Batch:
         p, dev = self.n_rays, self.device
         return {"depth": torch.empty(p, device=dev), "alpha": torch.empty(p, device=dev),
                 "normal": torch.empty(p, 3, device=dev) if normals else None,
-                "flow": torch.empty(p, 2, device=dev) if self.has_flow else None,
+                "flow": torch.empty(p, self.flow_cols, device=dev) if self.has_flow else None,
                 "color": torch.empty(p, 3, device=dev) if color else None,
                 "stash": torch.empty(p, STASH, device=dev)}
 
@@ -372,13 +401,14 @@ def loss_grad(outs: dict, depth_t, alpha_t, flow_t=None, w_depth: float = 1.0, w
     ga = c.get("alpha") if c.get("alpha") is not None else torch.empty(p, device=dev)
     gf = gc = None
     if flow_t is not None:
-        gf = c.get("flow") if c.get("flow") is not None else torch.empty(p, 2, device=dev)
+        gf = c.get("flow") if c.get("flow") is not None else torch.empty_like(outs["flow"])
     if color_t is not None:
         gc = c.get("color") if c.get("color") is not None else torch.empty(p, 3, device=dev)
     _lib.call("fmb_loss_grad", p, _vp(outs["depth"]), _vp(outs["alpha"]),
               _vp(outs["flow"] if flow_t is not None else None),
               _vp(outs["color"] if color_t is not None else None), _vp(depth_t), _vp(alpha_t), _vp(flow_t),
               _vp(color_t), ctypes.c_float(w_depth), ctypes.c_float(w_flow), int(flow_norm),
+              int(outs["flow"].shape[1]) if flow_t is not None else 2,
               ctypes.c_float(w_color), _vp(gd), _vp(ga), _vp(gf), _vp(gc), _vp(block_loss), _stream(dev))
     return {"depth": gd, "alpha": ga, "normal": None, "flow": gf, "color": gc}
 

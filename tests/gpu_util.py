@@ -29,7 +29,8 @@ def maxabs(a, b):
 def make_scene(fmb, torch, sc, cams, betas, eta, dev):
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=dev).contiguous()  # noqa: E731
     params = (t(sc.means), t(sc.prec), t(sc.weights), t(np.asarray(betas, np.float32)))
-    c = fmb.Cameras.from_numpy(cams.w2c, cams.intr, cams.hw, cams.w2c_b, cams.intr_b, device=dev)
+    c = fmb.Cameras.from_numpy(cams.w2c, cams.intr, cams.hw, cams.w2c_b, cams.intr_b, device=dev,
+                               w2c_c=cams.w2c_c, intr_c=cams.intr_c)
     return fmb.Scene(*params, eta, c), params
 
 

@@ -354,6 +354,71 @@ def pin_flow_translation():
     _close(out["flow"], ref, 1e-9, 1e-9, "translation flow")
 
 
+def pin_flow_both_directions():
+    """Forward and backward flow (Sec. 5): with the third pose translated by -c when the second is
+    translated by +c, both follow the translation parallax formula with their own shift; with the
+    third pose equal to the first, the backward columns are exactly zero; and the gradient of a
+    4-column flow objective matches central differences."""
+    g = _rng(30)
+    sc, ea, k, view, row, col, o, v = _flow_setup(g)
+    shift = np.array([0.05, -0.08, 0.03])
+    eb, ec = ea.copy(), ea.copy()
+    eb[:, 3] = ea[:, 3] - ea[:, :3] @ shift
+    ec[:, 3] = ea[:, 3] + ea[:, :3] @ shift
+    cam = dict(view=view, w2c_a=ea[None], intr_a=k[None], w2c_b=eb[None], intr_b=k[None],
+               w2c_c=ec[None], intr_c=k[None])
+    out = O.render(sc, o, v, **cam)
+    assert out["flow"].shape == (len(o), 4)
+    dc = np.stack([(col + 0.5 - k[2]) / k[0], (row + 0.5 - k[3]) / k[1], np.ones(len(col))], axis=1)
+    qa = out["depth"][:, None] * _unit(dc)
+    px = np.stack([col + 0.5, row + 0.5], axis=1)
+    for cols, sgn in ((slice(0, 2), 1.0), (slice(2, 4), -1.0)):
+        qx = qa - sgn * (ea[:, :3] @ shift)[None]
+        ref = np.stack([k[0] * qx[:, 0] / qx[:, 2] + k[2], k[1] * qx[:, 1] / qx[:, 2] + k[3]], axis=1)
+        _close(out["flow"][:, cols], ref - px, 1e-9, 1e-9, f"two-way translation flow {cols}")
+    same = O.render(sc, o, v, **dict(cam, w2c_c=ea[None]))
+    assert np.all(same["flow"][:, 2:] == 0.0), "backward flow to the first pose must vanish"
+    _close(same["flow"][:, :2], out["flow"][:, :2], 0.0, 0.0, "forward flow independent of pose C")
+    # gradient of sum(cot . flow4) through means, against central differences
+    o8, v8, cam8 = o[:6], v[:6], dict(cam, view=view[:6])
+    cot = {"flow": g.standard_normal((6, 4))}
+    an = O.backward(sc, o8, v8, cot, **cam8)
+    base = sc.means.reshape(-1)
+    fd = np.zeros_like(base)
+    for j in range(base.size):
+        x0 = base[j]
+        h = 1e-6 * max(1.0, abs(x0))
+        base[j] = x0 + h
+        fp = float(np.sum(cot["flow"] * O.render(sc, o8, v8, **cam8)["flow"]))
+        base[j] = x0 - h
+        fm = float(np.sum(cot["flow"] * O.render(sc, o8, v8, **cam8)["flow"]))
+        base[j] = x0
+        fd[j] = (fp - fm) / (2 * h)
+    scale = max(1.0, float(np.max(np.abs(fd))))
+    _close(an["means"].reshape(-1), fd, 1e-6, 1e-6 * scale, "FD gradient of two-way flow")
+
+
+def pin_max_weight():
+    """Direct-intersection quality max_i w_i (Sec. 6): 1 for a single Gaussian; 1/K for K identical
+    Gaussians; for two equal isotropic Gaussians centred on the ray at t_1 < t_2 (both d_i equal),
+    sigma((beta2/eta)(t_2 - t_1)), the weight of the nearer one."""
+    g = _rng(31)
+    o = np.array([0.0, 0.0, -3.0])
+    dirs = _unit(np.array([[0.0, 0.0, 1.0], [0.02, -0.01, 1.0], [-0.03, 0.02, 1.0]]))
+    orig = np.tile(o, (len(dirs), 1))
+    one = _scene([[0.0, 0.0, 0.0]], [_packed_iso(0.2)], [1.0])
+    assert np.all(np.abs(O.max_weight(one, orig, dirs) - 1.0) <= 1e-15)
+    for kk in (2, 3, 5):
+        many = _scene(np.zeros((kk, 3)), np.tile(_packed_iso(0.2), (kk, 1)), np.ones(kk))
+        _close(O.max_weight(many, orig, dirs), np.full(len(dirs), 1.0 / kk), 1e-14, 0.0, f"{kk} copies")
+    for eta in (1.0, 2.0):
+        gap = float(g.uniform(0.05, 0.4))
+        pair = _scene([[0.0, 0.0, 0.0], [0.0, 0.0, gap]], np.tile(_packed_iso(0.25), (2, 1)),
+                      [1.0, 1.0], eta=eta)
+        q = O.max_weight(pair, orig[:1], dirs[:1])
+        _close(q, [1.0 / (1.0 + math.exp(-B2 / eta * gap))], 1e-12, 0.0, "two on-axis Gaussians")
+
+
 # ---------------------------------------------------------------------------------------
 # Invariances
 # ---------------------------------------------------------------------------------------
@@ -568,5 +633,5 @@ ALL_PINS = [
     pin_rays_reproject, pin_flow_equal_poses, pin_flow_rotation_homography, pin_flow_translation,
     pin_scale_invariance, pin_rigid_motion, pin_normals_geometry, pin_gradients_fd,
     pin_isotropic_depth_gradient, pin_two_gaussian_beta_gradient, pin_loss_gradient,
-    pin_colour_blend,
+    pin_colour_blend, pin_flow_both_directions, pin_max_weight,
 ]

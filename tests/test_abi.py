@@ -38,7 +38,7 @@ def test_binding_covers_header():
 
 
 def test_abi_version(lib):
-    assert lib.fmb_abi_version() == 2
+    assert lib.fmb_abi_version() == 3
 
 
 def test_invalid_arguments_rejected_without_gpu(lib):

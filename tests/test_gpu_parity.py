@@ -452,3 +452,61 @@ def test_colour_autograd_and_batch(fmb):
         for x, k in zip(params, ("means", "prec", "weights", "betas", "colors")):
             ref = grads[k][i] if k == "betas" else grads[k][g0:g1]
             assert torch.equal(x.grad, ref), (i, k)
+
+
+def test_two_way_flow_and_quality(fmb):
+    """Forward and backward flow per ray (Sec. 5) and the direct-intersection quality max_i w_i
+    (Sec. 6, read from the stash) against the oracle; the 4-column loss kernel; and the batched
+    path with a third pose equal to the per-scene path bit for bit."""
+    sc, cams = _custom(40, [(48, 64), (33, 17), (1, 5)], seed=44, flow=True)
+    cams = W.with_backward_flow(cams, seed=45)
+    betas = np.array([W.BETA1, W.BETA2], np.float32)
+    _say(f"[two-way] N=40 P={cams.n_rays}")
+    scene, params = make_scene(fmb, torch, sc, cams, betas, 1.0, DEV)
+    outs = scene.render(normals=True)
+    assert tuple(outs["flow"].shape) == (cams.n_rays, 4)
+    ref, _, (view, row, col) = O.render_workload_view(sc, cams, betas, 1.0)
+    e = compare_forward(outs, ref)
+    e["flow_back"] = normwise(to_np(outs["flow"])[:, 2:], ref["flow"][:, 2:])
+    # quality on a sample of rays, one oracle ray at a time
+    rs = _sample(cams.n_rays, 400, 46)
+    o, v = O.pixel_rays(view[rs], row[rs], col[rs], cams.w2c, cams.intr)
+    osc = O.OracleScene.of(sc.means, sc.prec, sc.weights, betas, 1.0)
+    q_ref = O.max_weight(osc, o, v)
+    q = to_np(fmb.Scene.quality(outs))[rs]
+    # compared where the ray sees the scene: over background rays the weights are decided by
+    # log-density differences FP32 cannot resolve (as for the gradients there)
+    hit = ref["alpha"][rs] >= 1e-3
+    assert hit.sum() >= 100
+    e["quality"] = float(np.max(np.abs(q - q_ref)[hit]))
+    cot = _hit_mask_cot(W.random_cotangents(cams.n_rays, 47, flow=True), ref["alpha"])
+    g = np.random.Generator(np.random.PCG64(48))
+    cot["flow"] = (g.standard_normal((cams.n_rays, 4)) * (ref["alpha"] >= 1e-3)[:, None]).astype(np.float32)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=DEV).contiguous()  # noqa: E731
+    gr = scene.backward(outs, t(cot["depth"]), t(cot["alpha"]), t(cot["normal"]), t(cot["flow"]))
+    torch.cuda.synchronize()
+    _, gref, _ = O.render_workload_view(sc, cams, betas, 1.0, cot=cot)
+    eg = compare_grads(gr, gref)
+    _say(f"[two-way] {e} {eg}")
+    assert_forward(e, "two-way")
+    assert e["flow_back"] <= TOL_REL
+    assert e["quality"] <= TOL_REL
+    assert_grads(eg, "two-way")
+    # loss over both flows
+    flow_t = g.standard_normal((cams.n_rays, 4)).astype(np.float32)
+    alpha_t = (ref["alpha"] > 0.5).astype(np.float32)
+    depth_t = (to_np(outs["depth"]) + g.uniform(-0.1, 0.1, cams.n_rays)).astype(np.float32)
+    lc = fmb.loss_grad(outs, t(depth_t), t(alpha_t), t(flow_t), w_flow=0.5, flow_norm=2)
+    torch.cuda.synchronize()
+    _, lref = O.loss_grad(to_np(outs["depth"]), to_np(outs["alpha"]), depth_t, alpha_t,
+                          to_np(outs["flow"]), flow_t, 1.0, 0.5, 2)
+    err = np.abs(to_np(lc["flow"]) - lref["flow"])
+    assert np.all(err <= 1e-5 * np.abs(lref["flow"]) + 1e-12), float(err.max())
+    # batched persistent path with the third pose: identical to the per-scene path
+    c = fmb.Cameras.from_numpy(cams.w2c, cams.intr, cams.hw, cams.w2c_b, cams.intr_b, device=DEV,
+                               w2c_c=cams.w2c_c, intr_c=cams.intr_c)
+    b = fmb.Batch(*params, [1.0], [sc.n], [c])
+    bo = b.forward(b.alloc_outputs(normals=True))
+    torch.cuda.synchronize()
+    for k in ("depth", "alpha", "normal", "flow", "stash"):
+        assert torch.equal(bo[k], outs[k]), k

@@ -9,5 +9,5 @@ from .synth import (  # noqa: F401
     BETA1, BETA2, ETA,
     Scene, Cameras, Workload,
     make_config, make_scene, look_at, fibonacci_sphere, perturb_means,
-    pixel_indices, random_cotangents, config_names,
+    pixel_indices, random_cotangents, config_names, with_backward_flow,
 )

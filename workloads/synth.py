@@ -69,6 +69,8 @@ class Cameras:
     hw: np.ndarray                      # [V,2] int32 (H, W)
     w2c_b: Optional[np.ndarray] = None  # [V,3,4] second pose (flow target) or None
     intr_b: Optional[np.ndarray] = None  # [V,4] or None
+    w2c_c: Optional[np.ndarray] = None  # [V,3,4] optional third pose (backward-flow target)
+    intr_c: Optional[np.ndarray] = None  # [V,4] or None
 
     @property
     def v(self) -> int:
@@ -226,6 +228,32 @@ def _axis_angle(axis: np.ndarray, ang: float) -> np.ndarray:
     return np.eye(3) + math.sin(ang) * k + (1 - math.cos(ang)) * (k @ k)
 
 
+def _perturbed_pose(g: np.random.Generator, r: np.ndarray, c: np.ndarray, rot_sigma_deg: float,
+                    trans_sigma: float) -> np.ndarray:
+    """World-to-camera [3,4] of a pose near (rotation r, centre c): the camera-to-world rotation
+    premultiplied by a rotation of N(0, rot_sigma_deg^2) degrees about a uniformly random axis
+    (about the camera centre), the centre moved by N(0, trans_sigma^2 I)."""
+    axis = g.standard_normal(3)
+    ang = math.radians(rot_sigma_deg) * g.standard_normal()
+    r_b = (_axis_angle(axis, ang) @ r.T).T
+    c_b = c + trans_sigma * g.standard_normal(3)
+    return np.concatenate([r_b, (-r_b @ c_b)[:, None]], axis=1)
+
+
+def with_backward_flow(cams: Cameras, seed: int, rot_sigma_deg: float = 2.0,
+                       trans_sigma: float = 0.05) -> Cameras:
+    """Copy of a flow camera set with a third pose per view (the previous frame, for backward
+    flow), drawn with the same recipe as the second pose from its own seeded stream."""
+    if cams.w2c_b is None:
+        raise ValueError("backward flow needs a camera set that already has a second pose")
+    g = _rng(seed)
+    ec = []
+    for e in cams.w2c.astype(np.float64):
+        ec.append(_perturbed_pose(g, e[:, :3], -e[:, :3].T @ e[:, 3], rot_sigma_deg, trans_sigma))
+    return Cameras(cams.w2c, cams.intr, cams.hw, cams.w2c_b, cams.intr_b,
+                   np.stack(ec).astype(np.float32), cams.intr.copy())
+
+
 def _flow_cameras(g: np.random.Generator, v: int, h: int, w: int,
                   rot_sigma_deg: float = 2.0, trans_sigma: float = 0.05) -> Cameras:
     """First poses look at the origin from directions uniform on the sphere (radius 3).
@@ -240,14 +268,8 @@ def _flow_cameras(g: np.random.Generator, v: int, h: int, w: int,
     for k in range(v):
         c = 3.0 * dirs[k]
         e = look_at(c)
-        r = e[:, :3]
-        axis = g.standard_normal(3)
-        ang = math.radians(rot_sigma_deg) * g.standard_normal()
-        r_c2w_b = _axis_angle(axis, ang) @ r.T
-        c_b = c + trans_sigma * g.standard_normal(3)
-        r_b = r_c2w_b.T
         ea.append(e)
-        eb.append(np.concatenate([r_b, (-r_b @ c_b)[:, None]], axis=1))
+        eb.append(_perturbed_pose(g, e[:, :3], c, rot_sigma_deg, trans_sigma))
     intr = np.tile(_intr(h, w), (v, 1)).astype(np.float32)
     return Cameras(np.stack(ea).astype(np.float32), intr,
                    np.tile(np.array([h, w], dtype=np.int32), (v, 1)),
