@@ -24,6 +24,16 @@
  *   colour  = sum_i w_i c_i / sum_i w_i,  c_i = sigmoid(q_i) per channel   Eq. (3), Sec. 4
  *             (q_i unconstrained, as the paper parameterises colours)
  *
+ * The zero-parameter model (Sec. 3.3) replaces Eq. (7) by alpha compositing:
+ *   w_i     = T_i (1 - exp(-delta_i)),  T_i = exp(-sum_j delta_j [t_j < t_i])  Eq. (9), (10)
+ * evaluated here without a sort, by the O(N^2) sum over all j with t_j < t_i (a strict
+ * inequality: Gaussians with equal t_i do not attenuate one another).  The weights go into
+ * Eq. (3) as logarithms, log w_i = -sum_j delta_j [t_j < t_i] + log(1 - exp(-delta_i)),
+ * normalised with the same max shift; log(1 - exp(-delta)) is evaluated as
+ * log(-expm1(-delta)), and as d itself once delta = exp(d) is below 1e-300 (where the
+ * two agree to double precision), so rays far from every Gaussian keep finite weights.
+ * alpha is Eq. (8) for both models; betas and eta are not used by this model.
+ *
  * Readings where the paper is silent (each also listed in the design notes):
  *   - |y| is evaluated as sqrt(y.y + EPS_N) with EPS_N = 1e-30 so that a zero
  *     vector normalises to zero instead of 0/0;
@@ -223,6 +233,7 @@ static void ray_blend(int32_t n, const gauss_t *g, const pair_t *q, double *wt, 
 
 typedef struct {
     int32_t n;
+    int32_t model;  /* 0: two-parameter blend (Eq. 7); 1: alpha compositing (Eq. 9-10) */
     gauss_t *g;
     double b1, b2, eta;
     const double *orig, *dir;
@@ -230,10 +241,34 @@ typedef struct {
     const double *w2c_a, *intr_a, *w2c_b, *intr_b;
 } ctx_t;
 
+/* log(1 - exp(-delta)) with log(delta) = d: the log opacity of one Gaussian in Eq. (9). */
+static double log_opacity(double delta, double d)
+{
+    return delta < 1e-300 ? d : log(-expm1(-delta));
+}
+
+/* d/dd of log(1 - exp(-exp(d))) = delta / expm1(delta) (-> 1 as delta -> 0). */
+static double log_opacity_slope(double delta)
+{
+    return delta < 1e-300 ? 1.0 : delta / expm1(delta);
+}
+
+/* Zero-parameter model: z_i = log w_i = -sum_j delta_j [t_j < t_i] + log(1 - exp(-delta_i)). */
+static void composite_log_weights(int32_t n, pair_t *q)
+{
+    for (int32_t i = 0; i < n; ++i) {
+        double before = 0.0;
+        for (int32_t j = 0; j < n; ++j)
+            if (q[j].t < q[i].t) before += q[j].delta;
+        q[i].z = -before + log_opacity(q[i].delta, q[i].d);
+    }
+}
+
 static void ray_forward(const ctx_t *c, int64_t r, pair_t *q, double *wt, ray_t *ry)
 {
     const double *o = c->orig + 3 * r, *v = c->dir + 3 * r;
     for (int32_t i = 0; i < c->n; ++i) pair_eval(&c->g[i], o, v, c->b1, c->b2, c->eta, &q[i]);
+    if (c->model == 1) composite_log_weights(c->n, q);
     ray_blend(c->n, c->g, q, wt, ry);
     for (int a = 0; a < 3; ++a) ry->p[a] = o[a] + ry->tf * v[a];
     if (c->w2c_b) {
@@ -258,19 +293,22 @@ static int nthreads_of(int req)
 #endif
 }
 
-/* Forward render of p rays.  Any output pointer may be NULL.  Returns 0, or -1 on bad input. */
-int fmbo_render(int32_t n, const double *means, const double *prec, const double *weights,
-                const double *colors, const double *betas, double eta, int64_t p, const double *orig,
-                const double *dir, const int32_t *view, const double *w2c_a, const double *intr_a,
-                const double *w2c_b, const double *intr_b, double *depth, double *alpha, double *normal,
-                double *flow, double *color, int n_threads)
+/* Forward render of p rays with model 0 (two-parameter blend) or 1 (alpha compositing).
+ * Any output pointer may be NULL.  Returns 0, or -1 on bad input. */
+int fmbo_render_model(int32_t model, int32_t n, const double *means, const double *prec,
+                      const double *weights, const double *colors, const double *betas, double eta,
+                      int64_t p, const double *orig, const double *dir, const int32_t *view,
+                      const double *w2c_a, const double *intr_a, const double *w2c_b,
+                      const double *intr_b, double *depth, double *alpha, double *normal, double *flow,
+                      double *color, int n_threads)
 {
     if (n < 1 || p < 0 || !means || !prec || !weights || !betas || !orig || !dir) return -1;
+    if (model != 0 && model != 1) return -1;
     if (w2c_b && (!view || !w2c_a || !intr_a || !intr_b)) return -1;
     gauss_t *g = (gauss_t *)malloc(sizeof(gauss_t) * (size_t)n);
     if (!g) return -1;
     load_gaussians(n, means, prec, weights, colors, g);
-    ctx_t c = {n, g, betas[0], betas[1], eta, orig, dir, view, w2c_a, intr_a, w2c_b, intr_b};
+    ctx_t c = {n, model, g, betas[0], betas[1], eta, orig, dir, view, w2c_a, intr_a, w2c_b, intr_b};
     int nt = nthreads_of(n_threads);
 #pragma omp parallel num_threads(nt)
     {
@@ -294,6 +332,39 @@ int fmbo_render(int32_t n, const double *means, const double *prec, const double
         free(q);
         free(wt);
     }
+    free(g);
+    return 0;
+}
+
+int fmbo_render(int32_t n, const double *means, const double *prec, const double *weights,
+                const double *colors, const double *betas, double eta, int64_t p, const double *orig,
+                const double *dir, const int32_t *view, const double *w2c_a, const double *intr_a,
+                const double *w2c_b, const double *intr_b, double *depth, double *alpha, double *normal,
+                double *flow, double *color, int n_threads)
+{
+    return fmbo_render_model(0, n, means, prec, weights, colors, betas, eta, p, orig, dir, view, w2c_a,
+                             intr_a, w2c_b, intr_b, depth, alpha, normal, flow, color, n_threads);
+}
+
+/* Normalised blend weights w_i / sum_j w_j of Eq. (3) along one ray, for model 0 or 1. */
+int fmbo_ray_weights(int32_t model, int32_t n, const double *means, const double *prec,
+                     const double *weights, const double *betas, double eta, const double *o,
+                     const double *v, double *wt)
+{
+    if (n < 1 || (model != 0 && model != 1)) return -1;
+    gauss_t *g = (gauss_t *)malloc(sizeof(gauss_t) * (size_t)n);
+    pair_t *q = (pair_t *)malloc(sizeof(pair_t) * (size_t)n);
+    if (!g || !q) {
+        free(g);
+        free(q);
+        return -1;
+    }
+    load_gaussians(n, means, prec, weights, NULL, g);
+    for (int32_t i = 0; i < n; ++i) pair_eval(&g[i], o, v, betas[0], betas[1], eta, &q[i]);
+    if (model == 1) composite_log_weights(n, q);
+    ray_t ry;
+    ray_blend(n, g, q, wt, &ry);
+    free(q);
     free(g);
     return 0;
 }
@@ -342,7 +413,7 @@ typedef struct {
 
 static void ray_backward(const ctx_t *c, int64_t r, const pair_t *q, const double *wt, const ray_t *ry,
                          double gd, double ga, const double *gnrm, const double *gfl, const double *gcol,
-                         gacc_t *acc, double *gb)
+                         gacc_t *acc, double *gb, double *zbar)
 {
     const double *o = c->orig + 3 * r, *v = c->dir + 3 * r;
     (void)o;
@@ -374,6 +445,8 @@ static void ray_backward(const ctx_t *c, int64_t r, const pair_t *q, const doubl
     double mean_wbar = 0.0;
     for (int32_t i = 0; i < c->n; ++i)
         mean_wbar += wt[i] * (tf_bar * q[i].t + dot3(N_bar, q[i].n) + dot3(C_bar, c->g[i].col));
+    for (int32_t i = 0; i < c->n; ++i)
+        zbar[i] = wt[i] * (tf_bar * q[i].t + dot3(N_bar, q[i].n) + dot3(C_bar, c->g[i].col) - mean_wbar);
     for (int32_t i = 0; i < c->n; ++i) {
         const pair_t *pq = &q[i];
         const gauss_t *g = &c->g[i];
@@ -384,11 +457,22 @@ static void ray_backward(const ctx_t *c, int64_t r, const pair_t *q, const doubl
         double t_bar = wt[i] * tf_bar;
         double n_bar[3] = {wt[i] * N_bar[0], wt[i] * N_bar[1], wt[i] * N_bar[2]};
         double delta_bar = D_bar;
-        /* z = b1 d - (b2/eta) t */
-        double d_bar = c->b1 * z_bar;
-        t_bar += -(c->b2 / c->eta) * z_bar;
-        gb[0] += z_bar * pq->d;
-        gb[1] += -z_bar * pq->t / c->eta;
+        double d_bar;
+        if (c->model == 1) {
+            /* z_i = -sum_j delta_j [t_j < t_i] + log(1 - exp(-delta_i)): delta_i enters every
+             * z_k with t_i < t_k; the indicator is piecewise constant, so t gets nothing */
+            double later = 0.0;
+            for (int32_t k = 0; k < c->n; ++k)
+                if (pq->t < q[k].t) later += zbar[k];
+            delta_bar -= later;
+            d_bar = z_bar * log_opacity_slope(pq->delta);
+        } else {
+            /* z = b1 d - (b2/eta) t */
+            d_bar = c->b1 * z_bar;
+            t_bar += -(c->b2 / c->eta) * z_bar;
+            gb[0] += z_bar * pq->d;
+            gb[1] += -z_bar * pq->t / c->eta;
+        }
         /* delta = exp(d) */
         d_bar += delta_bar * pq->delta;
         /* d = log(lambda) - m/2 */
@@ -417,25 +501,27 @@ static void ray_backward(const ctx_t *c, int64_t r, const pair_t *q, const doubl
     }
 }
 
-/* Gradients of sum_r [gd.depth + ga.alpha + gn.normal + gf.flow] with respect to the
- * means, packed precision factors, weights and (beta1, beta2).  Outputs are
- * overwritten.  Cotangent pointers may be NULL (zero). */
-int fmbo_backward(int32_t n, const double *means, const double *prec, const double *weights,
-                  const double *colors, const double *betas, double eta, int64_t p, const double *orig,
-                  const double *dir, const int32_t *view, const double *w2c_a, const double *intr_a,
-                  const double *w2c_b, const double *intr_b, const double *g_depth,
-                  const double *g_alpha, const double *g_normal, const double *g_flow,
-                  const double *g_color, double *g_means, double *g_prec, double *g_weights,
-                  double *g_colors, double *g_betas, int n_threads)
+/* Gradients of sum_r [gd.depth + ga.alpha + gn.normal + gf.flow + gc.colour] with respect
+ * to the means, packed precision factors, weights, colours and (beta1, beta2; zero for
+ * model 1).  Outputs are overwritten.  Cotangent pointers may be NULL (zero). */
+int fmbo_backward_model(int32_t model, int32_t n, const double *means, const double *prec,
+                        const double *weights, const double *colors, const double *betas, double eta,
+                        int64_t p, const double *orig, const double *dir, const int32_t *view,
+                        const double *w2c_a, const double *intr_a, const double *w2c_b,
+                        const double *intr_b, const double *g_depth, const double *g_alpha,
+                        const double *g_normal, const double *g_flow, const double *g_color,
+                        double *g_means, double *g_prec, double *g_weights, double *g_colors,
+                        double *g_betas, int n_threads)
 {
     if (n < 1 || p < 0 || !means || !prec || !weights || !betas || !orig || !dir) return -1;
+    if (model != 0 && model != 1) return -1;
     if (!g_means || !g_prec || !g_weights || !g_betas) return -1;
     if (w2c_b && (!view || !w2c_a || !intr_a || !intr_b)) return -1;
     if (g_color && !colors) return -1;
     gauss_t *g = (gauss_t *)malloc(sizeof(gauss_t) * (size_t)n);
     if (!g) return -1;
     load_gaussians(n, means, prec, weights, colors, g);
-    ctx_t c = {n, g, betas[0], betas[1], eta, orig, dir, view, w2c_a, intr_a, w2c_b, intr_b};
+    ctx_t c = {n, model, g, betas[0], betas[1], eta, orig, dir, view, w2c_a, intr_a, w2c_b, intr_b};
     int nt = nthreads_of(n_threads);
     /* one accumulator per contiguous chunk of rays, summed in chunk order afterwards */
     gacc_t *acc = (gacc_t *)calloc((size_t)nt * (size_t)n, sizeof(gacc_t));
@@ -449,15 +535,17 @@ int fmbo_backward(int32_t n, const double *means, const double *prec, const doub
         int64_t lo = p * tid / nt, hi = p * (tid + 1) / nt;
         pair_t *q = (pair_t *)malloc(sizeof(pair_t) * (size_t)n);
         double *wt = (double *)malloc(sizeof(double) * (size_t)n);
+        double *zbar = (double *)malloc(sizeof(double) * (size_t)n);
         ray_t ry;
         for (int64_t r = lo; r < hi; ++r) {
             ray_forward(&c, r, q, wt, &ry);
             ray_backward(&c, r, q, wt, &ry, g_depth ? g_depth[r] : 0.0, g_alpha ? g_alpha[r] : 0.0,
                          g_normal ? g_normal + 3 * r : NULL, g_flow ? g_flow + 2 * r : NULL,
-                         g_color ? g_color + 3 * r : NULL, acc + (size_t)tid * n, gb + 2 * tid);
+                         g_color ? g_color + 3 * r : NULL, acc + (size_t)tid * n, gb + 2 * tid, zbar);
         }
         free(q);
         free(wt);
+        free(zbar);
     }
     g_betas[0] = g_betas[1] = 0.0;
     for (int32_t i = 0; i < n; ++i) {
@@ -501,4 +589,17 @@ int fmbo_backward(int32_t n, const double *means, const double *prec, const doub
     free(gb);
     free(g);
     return 0;
+}
+
+int fmbo_backward(int32_t n, const double *means, const double *prec, const double *weights,
+                  const double *colors, const double *betas, double eta, int64_t p, const double *orig,
+                  const double *dir, const int32_t *view, const double *w2c_a, const double *intr_a,
+                  const double *w2c_b, const double *intr_b, const double *g_depth,
+                  const double *g_alpha, const double *g_normal, const double *g_flow,
+                  const double *g_color, double *g_means, double *g_prec, double *g_weights,
+                  double *g_colors, double *g_betas, int n_threads)
+{
+    return fmbo_backward_model(0, n, means, prec, weights, colors, betas, eta, p, orig, dir, view, w2c_a,
+                               intr_a, w2c_b, intr_b, g_depth, g_alpha, g_normal, g_flow, g_color,
+                               g_means, g_prec, g_weights, g_colors, g_betas, n_threads);
 }

@@ -50,6 +50,13 @@ def _configure(lib):
     lib.fmbo_render.restype = ctypes.c_int
     lib.fmbo_backward.argtypes = common + [_D, _D, _D, _D, _D, _D, _D, _D, _D, _D, ctypes.c_int]
     lib.fmbo_backward.restype = ctypes.c_int
+    lib.fmbo_render_model.argtypes = [ctypes.c_int32] + lib.fmbo_render.argtypes
+    lib.fmbo_render_model.restype = ctypes.c_int
+    lib.fmbo_backward_model.argtypes = [ctypes.c_int32] + lib.fmbo_backward.argtypes
+    lib.fmbo_backward_model.restype = ctypes.c_int
+    lib.fmbo_ray_weights.argtypes = [ctypes.c_int32, ctypes.c_int32, _D, _D, _D, _D, ctypes.c_double,
+                                     _D, _D, _D]
+    lib.fmbo_ray_weights.restype = ctypes.c_int
     lib.fmbo_ray_terms.argtypes = [ctypes.c_int32, _D, _D, _D, _D, ctypes.c_double, _D, _D,
                                    _D, _D, _D, _D]
     return lib
@@ -156,9 +163,21 @@ def _cams(view, w2c_a, intr_a, w2c_b, intr_b):
     return view, a, ia, b, ib
 
 
+MODELS = {"blend": 0, "composite": 1}
+
+
+def _model(model):
+    if model not in MODELS:
+        raise ValueError(f"model must be one of {sorted(MODELS)}")
+    return MODELS[model]
+
+
 def render(scene: OracleScene, orig, dirs, view=None, w2c_a=None, intr_a=None, w2c_b=None,
-           intr_b=None, n_threads: int = 0, w2c_c=None, intr_c=None):
+           intr_b=None, n_threads: int = 0, w2c_c=None, intr_c=None, model: str = "blend"):
     """Forward pass over explicit rays; returns dict(depth, alpha, normal, flow, color).
+
+    model "blend": the two-parameter weights of Eq. (7); "composite": the zero-parameter
+    alpha-compositing weights of Eq. (9)-(10) (betas and eta unused).
 
     With a third pose (w2c_c, intr_c) the flow has 4 columns per ray: the flow to pose B and
     the flow to pose C (Sec. 5 estimates forward and backward flow for every ray); each is the
@@ -166,8 +185,8 @@ def render(scene: OracleScene, orig, dirs, view=None, w2c_a=None, intr_a=None, w
     if w2c_c is not None:
         if w2c_b is None:
             raise ValueError("a third pose needs the second one")
-        out = render(scene, orig, dirs, view, w2c_a, intr_a, w2c_b, intr_b, n_threads)
-        back = render(scene, orig, dirs, view, w2c_a, intr_a, w2c_c, intr_c, n_threads)
+        out = render(scene, orig, dirs, view, w2c_a, intr_a, w2c_b, intr_b, n_threads, model=model)
+        back = render(scene, orig, dirs, view, w2c_a, intr_a, w2c_c, intr_c, n_threads, model=model)
         out["flow"] = np.concatenate([out["flow"], back["flow"]], axis=1)
         return out
     lib = load()
@@ -177,7 +196,7 @@ def render(scene: OracleScene, orig, dirs, view=None, w2c_a=None, intr_a=None, w
     out = {"depth": np.empty(p), "alpha": np.empty(p), "normal": np.empty((p, 3)),
            "flow": np.empty((p, 2)) if b is not None else None,
            "color": np.empty((p, 3)) if scene.colors is not None else None}
-    rc = lib.fmbo_render(scene.n, _p(scene.means), _p(scene.prec), _p(scene.weights),
+    rc = lib.fmbo_render_model(_model(model), scene.n, _p(scene.means), _p(scene.prec), _p(scene.weights),
                          _p(scene.colors), _p(scene.betas), scene.eta, p, _p(orig), _p(dirs),
                          _p(view, _I), _p(a), _p(ia), _p(b), _p(ib), _p(out["depth"]),
                          _p(out["alpha"]), _p(out["normal"]), _p(out["flow"]), _p(out["color"]),
@@ -188,7 +207,8 @@ def render(scene: OracleScene, orig, dirs, view=None, w2c_a=None, intr_a=None, w
 
 
 def backward(scene: OracleScene, orig, dirs, cot: dict, view=None, w2c_a=None, intr_a=None,
-             w2c_b=None, intr_b=None, n_threads: int = 0, w2c_c=None, intr_c=None):
+             w2c_b=None, intr_b=None, n_threads: int = 0, w2c_c=None, intr_c=None,
+             model: str = "blend"):
     """Gradients of sum(cot . outputs) w.r.t. means [N,3], prec [N,6], weights [N], betas [2]
     (and colours [N,3] when the scene has them).
 
@@ -198,9 +218,10 @@ def backward(scene: OracleScene, orig, dirs, cot: dict, view=None, w2c_a=None, i
     if w2c_c is not None:
         gf = np.asarray(cot["flow"], np.float64).reshape(-1, 4)
         first = dict(cot, flow=gf[:, :2])
-        g1 = backward(scene, orig, dirs, first, view, w2c_a, intr_a, w2c_b, intr_b, n_threads)
+        g1 = backward(scene, orig, dirs, first, view, w2c_a, intr_a, w2c_b, intr_b, n_threads,
+                      model=model)
         g2 = backward(scene, orig, dirs, {"flow": gf[:, 2:]}, view, w2c_a, intr_a, w2c_c, intr_c,
-                      n_threads)
+                      n_threads, model=model)
         return {k: None if g1[k] is None else g1[k] + g2[k] for k in g1}
     lib = load()
     orig, dirs = _d(orig).reshape(-1, 3), _d(dirs).reshape(-1, 3)
@@ -211,7 +232,7 @@ def backward(scene: OracleScene, orig, dirs, cot: dict, view=None, w2c_a=None, i
     n = scene.n
     out = {"means": np.empty((n, 3)), "prec": np.empty((n, 6)), "weights": np.empty(n),
            "betas": np.empty(2), "colors": np.empty((n, 3)) if scene.colors is not None else None}
-    rc = lib.fmbo_backward(n, _p(scene.means), _p(scene.prec), _p(scene.weights),
+    rc = lib.fmbo_backward_model(_model(model), n, _p(scene.means), _p(scene.prec), _p(scene.weights),
                            _p(scene.colors), _p(scene.betas), scene.eta, p, _p(orig), _p(dirs),
                            _p(view, _I), _p(a), _p(ia), _p(b), _p(ib), _p(gd), _p(ga), _p(gn),
                            _p(gf), _p(gc), _p(out["means"]), _p(out["prec"]), _p(out["weights"]),
@@ -221,17 +242,24 @@ def backward(scene: OracleScene, orig, dirs, cot: dict, view=None, w2c_a=None, i
     return out
 
 
-def max_weight(scene: OracleScene, orig, dirs):
-    """max_i of the normalised blend weights w_i = exp(z_i) / sum_j exp(z_j) per ray: the
-    direct-intersection quality of Sec. 6 (points with max_i w_i <= eps are rejected for mesh
-    export).  Small inputs only: one ray_terms call per ray."""
+def blend_weights(scene: OracleScene, o, v, model: str = "blend"):
+    """Normalised blend weights w_i / sum_j w_j of Eq. (3) along one ray."""
+    lib = load()
+    o, v = _d(o).reshape(3), _d(v).reshape(3)
+    wt = np.empty(scene.n)
+    rc = lib.fmbo_ray_weights(_model(model), scene.n, _p(scene.means), _p(scene.prec),
+                              _p(scene.weights), _p(scene.betas), scene.eta, _p(o), _p(v), _p(wt))
+    if rc != 0:
+        raise ValueError("oracle ray_weights rejected its arguments")
+    return wt
+
+
+def max_weight(scene: OracleScene, orig, dirs, model: str = "blend"):
+    """max_i of the normalised blend weights per ray: the direct-intersection quality of
+    Sec. 6 (points with max_i w_i <= eps are rejected for mesh export).  Small inputs only:
+    one call per ray."""
     orig, dirs = _d(orig).reshape(-1, 3), _d(dirs).reshape(-1, 3)
-    q = np.empty(orig.shape[0])
-    for r in range(orig.shape[0]):
-        _, _, z, _ = ray_terms(scene, orig[r], dirs[r])
-        w = np.exp(z - z.max())
-        q[r] = (w / w.sum()).max()
-    return q
+    return np.array([blend_weights(scene, orig[r], dirs[r], model).max() for r in range(orig.shape[0])])
 
 
 def ray_terms(scene: OracleScene, o, v):
@@ -246,7 +274,7 @@ def ray_terms(scene: OracleScene, o, v):
 
 
 def render_workload_view(scene, cams, betas, eta, rays=None, n_threads: int = 0, cot=None,
-                         colors=None):
+                         colors=None, model: str = "blend"):
     """Render (and optionally differentiate) pixel rays of a workload camera set.
 
     `scene` has means/prec/weights (float32 arrays), `cams` has w2c, intr, hw and the
@@ -259,7 +287,7 @@ def render_workload_view(scene, cams, betas, eta, rays=None, n_threads: int = 0,
     sc = OracleScene.of(scene.means, scene.prec, scene.weights, betas, eta, colors)
     kw = dict(view=view, w2c_a=cams.w2c, intr_a=cams.intr, w2c_b=cams.w2c_b, intr_b=cams.intr_b,
               n_threads=n_threads, w2c_c=getattr(cams, "w2c_c", None),
-              intr_c=getattr(cams, "intr_c", None))
+              intr_c=getattr(cams, "intr_c", None), model=model)
     out = render(sc, o, v, **kw)
     grads = backward(sc, o, v, cot, **kw) if cot is not None else None
     return out, grads, (view, row, col)

@@ -420,6 +420,150 @@ def pin_max_weight():
 
 
 # ---------------------------------------------------------------------------------------
+# Zero-parameter model: alpha compositing, Eq. (9)-(10)
+# ---------------------------------------------------------------------------------------
+
+def _single_t_delta_n(sc, orig, dirs):
+    """Per-Gaussian (t_i, delta_i, n_i) of each ray from one-Gaussian renders: depth = t_i,
+    delta_i = -log(1 - alpha_i) (Eq. 8 inverted), normal = n_i."""
+    ts, ds, ns = [], [], []
+    for i in range(sc.n):
+        one = _scene(sc.means[[i]], sc.prec[[i]], sc.weights[[i]])
+        out = O.render(one, orig, dirs)
+        ts.append(out["depth"])
+        ds.append(-np.log1p(-out["alpha"]))
+        ns.append(out["normal"])
+    return np.array(ts).T, np.array(ds).T, np.stack(ns, axis=1)
+
+
+def _sorted_composite(t, delta, nrm):
+    """Eq. (9)-(10) by sorting the intersections and multiplying transmittances front to back
+    (the description of the paper's sort-based renderer), then Eq. (3)."""
+    depth, normal = np.empty(len(t)), np.empty((len(t), 3))
+    for r in range(len(t)):
+        order = np.argsort(t[r], kind="stable")
+        trans, wsum, tsum, nsum = 1.0, 0.0, 0.0, np.zeros(3)
+        for i in order:
+            w = trans * (1.0 - math.exp(-delta[r, i]))
+            wsum += w
+            tsum += w * t[r, i]
+            nsum += w * nrm[r, i]
+            trans *= math.exp(-delta[r, i])
+        depth[r] = tsum / wsum
+        normal[r] = nsum / np.linalg.norm(nsum)
+    return depth, normal
+
+
+def pin_composite_single_gaussian():
+    """With one Gaussian the compositing weight is its own: depth t_1, the same alpha and normal
+    as the two-parameter model."""
+    g = _rng(40)
+    sc, _ = _random_scene(g, 1, spread=0.2)
+    orig, dirs = _rays_at(g, np.repeat(sc.means, 6, axis=0), np.array([0.2, 0.1, -3.0]), jitter=0.1)
+    a, b = O.render(sc, orig, dirs), O.render(sc, orig, dirs, model="composite")
+    for k in ("depth", "alpha", "normal"):
+        _close(b[k], a[k], 1e-14, 1e-14, f"single-Gaussian composite {k}")
+
+
+def pin_composite_sorted_reference():
+    """Random scenes of up to 6 Gaussians: the oracle's unsorted strict-inequality sums match a
+    front-to-back sort with running transmittance built from one-Gaussian renders."""
+    g = _rng(41)
+    for n in (2, 4, 6):
+        sc, _ = _random_scene(g, n, spread=0.35)
+        orig, dirs = _rays_at(g, np.repeat(sc.means, 3, axis=0), np.array([0.3, -0.2, -3.0]), jitter=0.08)
+        t, delta, nrm = _single_t_delta_n(sc, orig, dirs)
+        ref_d, ref_n = _sorted_composite(t, delta, nrm)
+        out = O.render(sc, orig, dirs, model="composite")
+        _close(out["depth"], ref_d, 1e-9, 1e-9, f"composite depth vs sorted (N={n})")
+        _close(out["normal"], ref_n, 1e-8, 1e-8, f"composite normal vs sorted (N={n})")
+        _close(out["alpha"], -np.expm1(-delta.sum(axis=1)), 1e-12, 1e-14, "composite alpha (Eq. 8)")
+
+
+def pin_composite_ties():
+    """Equal t_i do not attenuate one another (strict inequality of Eq. 10): three identical
+    Gaussians behind a fourth on the ray axis each get T = exp(-delta_front)."""
+    prec = np.tile(_packed_iso(0.2), (4, 1))
+    means = np.array([[0.0, 0.0, 0.5], [0.0, 0.0, 0.5], [0.0, 0.0, 0.5], [0.0, 0.0, 0.0]])
+    sc = _scene(means, prec, [0.8, 0.8, 0.8, 0.6])
+    orig = np.tile([0.0, 0.0, -3.0], (3, 1))
+    dirs = _unit(np.array([[0.0, 0.0, 1.0], [0.01, 0.02, 1.0], [-0.02, 0.01, 1.0]]))
+    t, delta, _ = _single_t_delta_n(sc, orig, dirs)
+    wf = -np.expm1(-delta[:, 3])
+    wb = np.exp(-delta[:, 3]) * -np.expm1(-delta[:, 0])
+    ref = (wf * t[:, 3] + 3 * wb * t[:, 0]) / (wf + 3 * wb)
+    out = O.render(sc, orig, dirs, model="composite")
+    _close(out["depth"], ref, 1e-12, 1e-12, "composite with tied intersections")
+    q = O.max_weight(sc, orig, dirs, model="composite")
+    _close(q, np.maximum(wf, wb) / (wf + 3 * wb), 1e-12, 0.0, "composite max weight with ties")
+
+
+def pin_composite_background():
+    """A ray far from every Gaussian (all densities underflow): every T_i is 1 and the log
+    opacity equals d_i, so the weights are softmax(d_i)."""
+    g = _rng(42)
+    covs = [_cov_and_packed(g, 0.03, 0.06)[1] for _ in range(5)]
+    sc = _scene(g.uniform(-0.3, 0.3, (5, 3)), np.array(covs), g.uniform(0.5, 1.5, 5))
+    orig = np.array([[0.0, 0.0, -3.0]])
+    dirs = _unit(np.array([[1.0, 0.2, 0.05]]))
+    t, d, _, _ = O.ray_terms(sc, orig[0], dirs[0])
+    assert np.all(d < -700), "the test ray must miss every Gaussian by far"
+    w = np.exp(d - d.max())
+    out = O.render(sc, orig, dirs, model="composite")
+    assert np.isfinite(out["depth"]).all()
+    _close(out["depth"], [(w * t).sum() / w.sum()], 1e-12, 1e-12, "background composite depth")
+
+
+def pin_composite_scale_invariance():
+    """Scene and camera scaled by k: the zero-parameter model needs no eta; depth scales by k,
+    alpha and normals are unchanged."""
+    g = _rng(43)
+    sc, _ = _random_scene(g, 6, spread=0.4)
+    o = np.array([0.2, -0.3, -3.0])
+    orig, dirs = _rays_at(g, np.repeat(sc.means, 2, axis=0), o, jitter=0.1)
+    base = O.render(sc, orig, dirs, model="composite")
+    k = 3.7
+    big = _scene(sc.means * k, sc.prec / k, sc.weights)
+    out = O.render(big, orig * k, dirs, model="composite")
+    _close(out["depth"], base["depth"] * k, 1e-10, 1e-10, "composite depth scale")
+    _close(out["alpha"], base["alpha"], 1e-12, 1e-12, "composite alpha scale")
+    _close(out["normal"], base["normal"], 1e-9, 1e-9, "composite normal scale")
+
+
+def pin_composite_gradients_fd():
+    """Central differences of the composite forward match its adjoint for means, precision
+    factors, weights and colours through every output; the beta gradient is zero."""
+    g = _rng(44)
+    sc, ea, kk, view, row, col, o, v = _flow_setup(g, n=5)
+    view, o, v = view[:8], o[:8], v[:8]
+    eb = _look_at(np.array([0.5, -2.5, 1.1]))
+    cam = dict(view=view, w2c_a=ea[None], intr_a=kk[None], w2c_b=eb[None], intr_b=kk[None],
+               model="composite")
+    p = len(o)
+    cot = {"depth": g.standard_normal(p), "alpha": g.standard_normal(p),
+           "normal": g.standard_normal((p, 3)), "flow": g.standard_normal((p, 2)),
+           "color": g.standard_normal((p, 3))}
+    sc = O.OracleScene.of(sc.means, sc.prec, sc.weights * 3.0, (B1, B2), 1.0, g.standard_normal((sc.n, 3)))
+    an = O.backward(sc, o, v, cot, **cam)
+    assert np.all(an["betas"] == 0.0)
+    for name in ("means", "prec", "weights", "colors"):
+        base = getattr(sc, name)
+        fd = np.zeros_like(base)
+        flat, fdf = base.reshape(-1), fd.reshape(-1)
+        for j in range(flat.size):
+            h = 1e-6 * max(1.0, abs(flat[j]))
+            x0 = flat[j]
+            flat[j] = x0 + h
+            fp = _loss(sc, o, v, cam, cot)
+            flat[j] = x0 - h
+            fm = _loss(sc, o, v, cam, cot)
+            flat[j] = x0
+            fdf[j] = (fp - fm) / (2 * h)
+        scale = max(1.0, float(np.max(np.abs(fd))))
+        _close(an[name], fd, 1e-6, 1e-6 * scale, f"composite FD gradient {name}")
+
+
+# ---------------------------------------------------------------------------------------
 # Invariances
 # ---------------------------------------------------------------------------------------
 
@@ -634,4 +778,6 @@ ALL_PINS = [
     pin_scale_invariance, pin_rigid_motion, pin_normals_geometry, pin_gradients_fd,
     pin_isotropic_depth_gradient, pin_two_gaussian_beta_gradient, pin_loss_gradient,
     pin_colour_blend, pin_flow_both_directions, pin_max_weight,
+    pin_composite_single_gaussian, pin_composite_sorted_reference, pin_composite_ties,
+    pin_composite_background, pin_composite_scale_invariance, pin_composite_gradients_fd,
 ]

@@ -40,6 +40,17 @@ MUTANTS = {
     "adj_colour_no_sigmoid_slope": ("s.col[j] * g[i].col[j] * (1.0 - g[i].col[j])", "s.col[j]"),
     "adj_U_fold_transposed": ("t += g[i].U[a * 3 + k] * Bs[k * 3 + b];",
                               "t += g[i].U[k * 3 + a] * Bs[k * 3 + b];"),
+    "composite_non_strict": ("if (q[j].t < q[i].t) before += q[j].delta;",
+                             "if (q[j].t <= q[i].t) before += q[j].delta;"),
+    "composite_back_to_front": ("if (q[j].t < q[i].t) before += q[j].delta;",
+                                "if (q[j].t > q[i].t) before += q[j].delta;"),
+    "composite_density_not_opacity": ("q[i].z = -before + log_opacity(q[i].delta, q[i].d);",
+                                      "q[i].z = -before + q[i].d;"),
+    "composite_tiny_branch_drops_d": ("return delta < 1e-300 ? d : log(-expm1(-delta));",
+                                      "return delta < 1e-300 ? 0.0 : log(-expm1(-delta));"),
+    "adj_composite_wrong_side": ("if (pq->t < q[k].t) later += zbar[k];",
+                                 "if (pq->t > q[k].t) later += zbar[k];"),
+    "adj_composite_slope_dropped": ("d_bar = z_bar * log_opacity_slope(pq->delta);", "d_bar = z_bar;"),
 }
 
 
