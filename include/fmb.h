@@ -66,6 +66,12 @@ enum fmb_status {
     FMB_ERR_STATE = 6        /* call order violated (e.g. render before set_cameras) */
 };
 
+/* Blend weights of Eq. (3) (see fmb_set_model). */
+enum fmb_model {
+    FMB_MODEL_BLEND = 0,     /* two-parameter model: w_i = exp(beta1 d_i - beta2 t_i / eta) (Eq. 7) */
+    FMB_MODEL_COMPOSITE = 1  /* zero-parameter model: alpha compositing (Eq. 9-10) */
+};
+
 typedef struct fmb_scene fmb_scene;
 typedef struct fmb_batch fmb_batch;
 
@@ -130,6 +136,18 @@ int64_t fmb_num_rays(const fmb_scene *scene);
  * (w2c_b) to be set; fmb_set_cameras / fmb_set_rays clear it. */
 int fmb_set_flow_pose2(fmb_scene *scene, fmb_batch *batch, const float *w2c_c,
                        const float *intr_c);
+
+/* Choose the blend weights of a scene or batch (exactly one non-NULL); the default is
+ * FMB_MODEL_BLEND.  FMB_MODEL_COMPOSITE is the zero-parameter renderer of Sec. 3.3:
+ * w_i = T_i (1 - exp(-delta_i)), T_i = exp(-sum_j delta_j [t_j < t_i]) (Eq. 9-10; Gaussians
+ * at equal t_i do not attenuate one another), blended by Eq. (3) for depth, normals and
+ * colour, alpha by Eq. (8); betas and eta are not used and their gradient is 0.  Every
+ * other call keeps its meaning, arguments and outputs; the stash holds the same fields
+ * (the running maximum is that of log2 w_i).  Captured graphs are dropped when the model
+ * changes; fmb_autotune leaves a compositing job as it is (one launch configuration).
+ * Errors: FMB_ERR_INVALID_ARG (bad model), FMB_ERR_SHAPE (a scene has more than 256
+ * Gaussians: the compositing kernels hold at most 4 per lane of a 64-lane ray). */
+int fmb_set_model(fmb_scene *scene, fmb_batch *batch, int32_t model);
 
 /* Set (or with NULL clear) the per-Gaussian colours of a scene or batch (exactly one
  * non-NULL): device [n,3] (batch: [sum n,3]) unconstrained parameters q, borrowed; the

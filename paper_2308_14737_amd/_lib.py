@@ -33,6 +33,7 @@ SIGNATURES = {
     "fmb_num_rays": (_i64, [_vp]),
     "fmb_set_colors": (_int, [_vp, _vp, _vp]),
     "fmb_set_flow_pose2": (_int, [_vp, _vp, _vp, _vp]),
+    "fmb_set_model": (_int, [_vp, _vp, _i32]),
     "fmb_render": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fmb_backward": (_int, [_vp] + [_vp] * 13 + [_vp]),
     "fmb_batch_create": (_int, [ctypes.POINTER(_vp), _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,

@@ -42,6 +42,10 @@ hipError_t launch_loss(int p, const float *depth, const float *alpha, const floa
                        float w_depth, float w_flow, int flow_norm, int flow_cols, float w_color, float *g_depth,
                        float *g_alpha, float *g_flow, float *g_color, float *block_loss, hipStream_t st);
 hipError_t launch_validate(const Params &P, int n_total, int n_scenes, int *flags, hipStream_t st);
+hipError_t launch_fwdc(int km, int flags, int n_items, hipStream_t st, const Params &P, const FwdOut &O,
+                       const BwdItem *items);
+hipError_t launch_bwdc(int km, int flags, int n_items, hipStream_t st, const Params &P, const BwdIn &I,
+                       const BwdItem *items, float *partial, float *beta_partial);
 hipError_t occupancy_fwd(int variant, int flags, int *blocks_per_cu);
 hipError_t occupancy_bwd(int variant, int flags, int *blocks_per_cu);
 }  // namespace fmb
@@ -203,6 +207,7 @@ struct Job {
     Params prm{};
     bool has_flow = false;
     bool cams_set = false;
+    int model = FMB_MODEL_BLEND;
     int device = 0, n_cu = 0;
     DevBuf d_scenes, d_views, d_eta, d_counter;
 
@@ -293,21 +298,49 @@ struct Job {
         slots = block / gc;
     }
 
+    // Lanes' Gaussians per ray slot of the compositing kernels (1, 2 or 4) for this job.
+    int comp_km() const
+    {
+        int km = 1;
+        for (const auto &sc : scenes) {
+            const int k = (sc.n + comp_seg(sc.n) - 1) / comp_seg(sc.n);
+            km = std::max(km, k <= 1 ? 1 : (k <= 2 ? 2 : 4));
+        }
+        return km;
+    }
+
+    // Backward items (and, for the compositing model, the forward items too).  The key
+    // records the model, the colour record size and the blend backward's variant.
+    int bwd_key(int variant, bool colour) const
+    {
+        return model == FMB_MODEL_COMPOSITE ? (colour ? 3 : 1) : (variant * 2 + (colour ? 1 : 0)) * 2;
+    }
+
     int build_bwd(int variant, bool colour)
     {
-        const int key = variant * 2 + (colour ? 1 : 0);
+        const int key = bwd_key(variant, colour);
         if (bwd_built == key) return FMB_OK;
+        const bool comp = model == FMB_MODEL_COMPOSITE;
         const int rec = colour ? kPartialColor : kPartial;
         const int RT = bwd_variant_rt(variant);
         const int B = block_size();
-        std::vector<int> gcs(S), sls(S), spans(S);
+        std::vector<int> gcs(S), sls(S), spans(S), min_span(S);
         for (int s = 0; s < S; ++s) {
-            chunking(scenes[s].n, B, gcs[s], sls[s]);
-            spans[s] = std::max(RT, ((64 * sls[s] + RT - 1) / RT) * RT);
+            if (comp) {
+                // one chunk holds the whole scene; a step of the block covers 4 * 64 / seg rays
+                gcs[s] = scenes[s].n;
+                sls[s] = 1;
+                min_span[s] = 4 * (64 / comp_seg(scenes[s].n));
+                spans[s] = 16 * min_span[s];
+            } else {
+                chunking(scenes[s].n, B, gcs[s], sls[s]);
+                min_span[s] = RT;
+                spans[s] = std::max(RT, ((64 * sls[s] + RT - 1) / RT) * RT);
+            }
         }
         // Span of rays per item, chosen per scene only (so a scene is cut the same way alone
-        // and inside a batch): about 64 rays per lane, at most 16384 and, where the scene is
-        // small, at least 2048 items.
+        // and inside a batch): about 64 rays per lane (16 steps when compositing), at most
+        // 16384 and, where the scene is small, at least 2048 items.
         for (int s = 0; s < S; ++s) {
             const int chunks = (scenes[s].n + gcs[s] - 1) / gcs[s];
             auto count_items = [&](int span) {
@@ -319,7 +352,7 @@ struct Job {
                 return c;
             };
             while (count_items(spans[s]) > 16384 && spans[s] < (1 << 22)) spans[s] *= 2;
-            while (count_items(spans[s]) < 2048 && spans[s] > RT) spans[s] /= 2;
+            while (count_items(spans[s]) < 2048 && spans[s] > min_span[s]) spans[s] /= 2;
         }
         std::vector<BwdItem> items;
         std::vector<FinTask> tasks;
@@ -458,6 +491,15 @@ struct Job {
         CHECK_ARG(!O.flow || has_flow, "flow output given but the cameras have no second pose");
         CHECK_ARG(!O.color || prm.colors, "colour output given but no colours were set");
         CHECK_ARG(!O.stash || aligned(O.stash, 16), "stash must be 16-byte aligned");
+        if (model == FMB_MODEL_COMPOSITE) {
+            // items shared with the backward pass: keep whichever colour record is built
+            int rc = (bwd_built == 1 || bwd_built == 3) ? FMB_OK : build_bwd(bwd_variant, prm.colors != nullptr);
+            if (rc) return rc;
+            TimedSpan ts(st, 0);
+            HIPCHK(launch_fwdc(comp_km(), fwd_flags(O, false), n_bitems, st, prm, O, d_bitems.as<BwdItem>()));
+            ts.stop();
+            return FMB_OK;
+        }
         int rc = build_fwd(fwd_variant);
         if (rc) return rc;
         const int flags = fwd_flags(O, persist);
@@ -483,17 +525,24 @@ struct Job {
         CHECK_ARG(!I.g_color || (prm.colors && I.color), "colour cotangent needs colours and the colour output");
         int rc = build_bwd(bwd_variant, I.g_color != nullptr);
         if (rc) return rc;
-        const int flags = bwd_flags(I, persist);
-        int grid = n_bitems;
-        if (persist) {
-            if ((rc = grid_bwd(flags, grid))) return rc;
-            HIPCHK(launch_fill(d_counter.as<int>() + 1, 1, 0, st));
+        if (model == FMB_MODEL_COMPOSITE) {
+            TimedSpan tb(st, 1);
+            HIPCHK(launch_bwdc(comp_km(), bwd_flags(I, false), n_bitems, st, prm, I, d_bitems.as<BwdItem>(),
+                               d_partial.as<float>(), d_bpart.as<float>()));
+            tb.stop();
+        } else {
+            const int flags = bwd_flags(I, persist);
+            int grid = n_bitems;
+            if (persist) {
+                if ((rc = grid_bwd(flags, grid))) return rc;
+                HIPCHK(launch_fill(d_counter.as<int>() + 1, 1, 0, st));
+            }
+            TimedSpan tb(st, 1);
+            HIPCHK(launch_bwd(bwd_variant, flags, grid, st, prm, I, d_bitems.as<BwdItem>(), n_bitems,
+                              persist ? d_border.as<int>() : nullptr, persist ? d_counter.as<int>() + 1 : nullptr,
+                              d_partial.as<float>(), d_bpart.as<float>()));
+            tb.stop();
         }
-        TimedSpan tb(st, 1);
-        HIPCHK(launch_bwd(bwd_variant, flags, grid, st, prm, I, d_bitems.as<BwdItem>(), n_bitems,
-                          persist ? d_border.as<int>() : nullptr, persist ? d_counter.as<int>() + 1 : nullptr,
-                          d_partial.as<float>(), d_bpart.as<float>()));
-        tb.stop();
         TimedSpan tf(st, 2);
         HIPCHK(launch_fin(n_tasks, n_groups, st, prm, d_tasks.as<FinTask>(), d_groups.as<FinGroup>(),
                           d_partial.as<float>(), d_bpart.as<float>(), d_stage.as<double>(),
@@ -685,6 +734,24 @@ int fmb_set_flow_pose2(fmb_scene *s, fmb_batch *b, const float *w2c_c, const flo
     return FMB_OK;
 }
 
+int fmb_set_model(fmb_scene *s, fmb_batch *b, int32_t model)
+{
+    g_err.clear();
+    CHECK_ARG((s != nullptr) != (b != nullptr), "exactly one of scene and batch must be given");
+    CHECK_ARG(model == FMB_MODEL_BLEND || model == FMB_MODEL_COMPOSITE, "model must be FMB_MODEL_BLEND or "
+                                                                        "FMB_MODEL_COMPOSITE");
+    Job &j = s ? s->job : b->job;
+    if (model == FMB_MODEL_COMPOSITE)
+        for (const auto &sc : j.scenes)
+            if (sc.n > kCompMaxN) return fail(FMB_ERR_SHAPE, "the compositing renderer takes at most 256 Gaussians per scene");
+    if (model != j.model) {
+        j.model = model;
+        j.bwd_built = -1;
+        j.drop_graphs();
+    }
+    return FMB_OK;
+}
+
 int fmb_set_colors(fmb_scene *s, fmb_batch *b, const float *colors)
 {
     g_err.clear();
@@ -832,11 +899,13 @@ int fmb_batch_capture(fmb_batch *b, float *depth, float *alpha, float *normal, f
     const BwdIn I{g_depth, g_alpha, g_normal, g_flow, g_color, depth, color, stash};
     const Grads G{g_means, g_prec, g_weights, g_colors, g_betas};
     // item lists and occupancy are prepared outside the capture (they use synchronous copies)
-    int rc = j.build_fwd(j.fwd_variant);
-    int gdummy = 0;
-    if (!rc) rc = j.build_bwd(j.bwd_variant, g_color != nullptr);
-    if (!rc) rc = j.grid_fwd(Job::fwd_flags(O, true), gdummy);
-    if (!rc) rc = j.grid_bwd(Job::bwd_flags(I, true), gdummy);
+    int rc = j.build_bwd(j.bwd_variant, g_color != nullptr);
+    if (j.model == FMB_MODEL_BLEND) {
+        int gdummy = 0;
+        if (!rc) rc = j.build_fwd(j.fwd_variant);
+        if (!rc) rc = j.grid_fwd(Job::fwd_flags(O, true), gdummy);
+        if (!rc) rc = j.grid_bwd(Job::bwd_flags(I, true), gdummy);
+    }
     if (rc) return rc;
     j.drop_graphs();
     for (int which = 0; which < 2; ++which) {
@@ -970,6 +1039,7 @@ int fmb_autotune(fmb_scene *s, fmb_batch *b, float *depth, float *alpha, float *
     const bool persist = b != nullptr;
     hipStream_t st = (hipStream_t)stream;
     if (!j.cams_set) return fail(FMB_ERR_STATE, "autotune before cameras were set");
+    if (j.model == FMB_MODEL_COMPOSITE) return FMB_OK;  // one launch configuration
     const FwdOut O{depth, alpha, normal, flow, color, stash};
     const BwdIn I{g_depth, g_alpha, g_normal, g_flow, g_color, depth, color, stash};
     const Grads G{g_means, g_prec, g_weights, g_colors, g_betas};

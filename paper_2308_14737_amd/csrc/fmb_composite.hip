@@ -1,0 +1,416 @@
+// fmb_composite.hip -- gfx950 kernels of the zero-parameter Fuzzy Metaballs renderer
+// (alpha compositing, Keselman & Hebert, WACV 2024, Sec. 3.3, Eq. 9-10).
+//
+// Weights: w_i = T_i (1 - exp(-delta_i)), T_i = exp(-sum_j delta_j [t_j < t_i]), blended by
+// Eq. (3) for depth, normals and colour; alpha is Eq. (8) as in the two-parameter model.
+//
+// Layout: one ray per segment of `seg` consecutive lanes of a wave, seg the smallest power of
+// two >= N (at most 64); lane l of the segment holds Gaussians l, l + seg, ... (ke <= KM of
+// them).  The segment writes its (t_i, delta_i) to LDS and every lane sums, for each of its
+// Gaussians, the densities of the Gaussians strictly in front of it: an O(N) loop of LDS
+// broadcasts per pair and no sort, with the strict inequality of Eq. (10) taken literally
+// (Gaussians at equal depth do not attenuate one another).  Segment sums (max, weights,
+// blended values) are butterflies over the segment's lanes.  A block of 256 lanes handles
+// 4 * 64 / seg rays per step and loops over the rays of its item.
+//
+// Numerics: the weights enter Eq. (3) as base-2 logarithms,
+//   log2 w_i = -log2(e) sum_{t_j < t_i} delta_j + log2(1 - exp(-delta_i)),
+// shifted by their maximum over the ray, so rays far from every Gaussian keep finite weights;
+// log2(1 - exp(-delta)) = log2(delta) + log2(e) (-delta/2 + delta^2/24 - delta^4/2880) below
+// delta = 1/16 (truncation < 1e-12 relative), log2(1 - 2^(-delta log2 e)) above.
+//
+// Backward (per ray, same layout): with z_i = log w_i and z_bar_i = wt_i (tf_bar t_i +
+// Nb.n_i + Cb.c_i - kappa) the softmax adjoint, delta_j enters every z_i behind it, so
+//   d_bar_j = z_bar_j delta_j / expm1(delta_j) + delta_j (D_bar - sum_{t_j < t_i} z_bar_i),
+//   t_bar_j = wt_j tf_bar (the indicator is piecewise constant),
+// the second sum again an O(N) LDS loop; the rest of the per-pair adjoint is shared with the
+// two-parameter renderer.  Partial gradients per item go to the same deterministic finalize.
+#include "fmb_device.h"
+
+namespace fmb {
+
+constexpr int kCompBlock = 256;
+
+// log2(1 - exp(-delta)) with log2(delta) = d2.
+__device__ __forceinline__ float log2_opacity(float delta, float d2)
+{
+    const float series = fmaf((float)kLog2e * delta, fmaf(delta, fmaf(delta * delta, -1.0f / 2880.0f, 1.0f / 24.0f), -0.5f), d2);
+    const float direct = __builtin_amdgcn_logf(1.0f - exp2_(-(float)kLog2e * delta));
+    return delta < 0.0625f ? series : direct;
+}
+
+// delta / expm1(delta) = d log(1 - exp(-delta)) / d log(delta).
+__device__ __forceinline__ float opacity_slope(float delta)
+{
+    const float series = fmaf(delta, fmaf(delta, fmaf(delta * delta, -1.0f / 720.0f, 1.0f / 12.0f), -0.5f), 1.0f);
+    const float em = exp2_(-(float)kLog2e * delta);
+    const float direct = delta * em * rcp_(1.0f - em);
+    return delta < 0.0625f ? series : direct;
+}
+
+__device__ __forceinline__ float seg_sum(float x, int seg)
+{
+    for (int off = seg >> 1; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+__device__ __forceinline__ float seg_max(float x, int seg)
+{
+    for (int off = seg >> 1; off > 0; off >>= 1) x = fmaxf(x, __shfl_xor(x, off, 64));
+    return x;
+}
+
+// Lane geometry of a scene with n Gaussians.
+struct CompLanes {
+    int seg, ke;        // lanes per ray, Gaussians per lane
+    int sl, sg, rpw;    // lane within the segment, segment within the wave, rays per wave
+    int sbase;          // first LDS slot of the segment
+};
+
+template <int KM>
+__device__ __forceinline__ CompLanes comp_lanes(int n)
+{
+    CompLanes c;
+    c.seg = comp_seg(n);
+    c.ke = (n + c.seg - 1) / c.seg;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    c.sl = lane & (c.seg - 1);
+    c.sg = lane / c.seg;
+    c.rpw = 64 / c.seg;
+    c.sbase = (wave * 64 + c.sg * c.seg) * KM;
+    return c;
+}
+
+// Entries of the lane's Gaussians; a slot past the last Gaussian takes the last one's entry
+// (finite arithmetic, zero weight and density).
+template <int KM, bool COLOR>
+__device__ __forceinline__ void comp_entries(const Params &P, const SceneRec &sr, const CompLanes &c,
+                                             const double o[3], Ent g[KM], float4 cc[KM], bool gv[KM])
+{
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        gv[k] = false;
+        if (k < c.ke) {
+            const int j = k * c.seg + c.sl;
+            gv[k] = j < sr.n;
+            const int gg = sr.gauss_off + (gv[k] ? j : sr.n - 1);
+            float4 q[4];
+            make_entry(P.means + 3 * gg, P.prec + 6 * gg, P.weights[gg], o, q);
+            g[k] = ent_from(q[0], q[1], q[2], q[3]);
+            if (COLOR) cc[k] = colour_entry(P.colors + 3 * gg);
+        }
+    }
+}
+
+// sum over the ray's Gaussians j of x_j where t_j < t (before) or t_j > t (after).
+template <bool AFTER>
+__device__ __forceinline__ float ordered_partial(const float2 *__restrict__ slots, int n, float t)
+{
+    float s = 0.0f;
+    int j = 0;
+    for (; j + 4 <= n; j += 4) {
+        const float2 a = slots[j], b = slots[j + 1], c = slots[j + 2], d = slots[j + 3];
+        s += (AFTER ? a.x > t : a.x < t) ? a.y : 0.0f;
+        s += (AFTER ? b.x > t : b.x < t) ? b.y : 0.0f;
+        s += (AFTER ? c.x > t : c.x < t) ? c.y : 0.0f;
+        s += (AFTER ? d.x > t : d.x < t) ? d.y : 0.0f;
+    }
+    for (; j < n; ++j) {
+        const float2 a = slots[j];
+        s += (AFTER ? a.x > t : a.x < t) ? a.y : 0.0f;
+    }
+    return s;
+}
+
+// ------------------------------------------------------------------------------------
+// Forward
+// ------------------------------------------------------------------------------------
+
+template <int KM, int F>
+__global__ __launch_bounds__(kCompBlock) void fwdc_kernel(Params P, FwdOut O, const BwdItem *__restrict__ items)
+{
+    constexpr bool NORMALS = (F & kNrm) != 0, COLOR = (F & kCol) != 0;
+    __shared__ float2 tdl[kCompBlock * KM];
+    const BwdItem item = items[blockIdx.x];
+    const ViewRec vr = P.views[item.view];
+    const SceneRec sr = P.scenes[vr.scene];
+    const int n = sr.n;
+    const CompLanes c = comp_lanes<KM>(n);
+    const int wave = threadIdx.x >> 6;
+    const float *__restrict__ e = P.w2c + 12 * item.view;
+    const float *__restrict__ kk = P.intr + 4 * item.view;
+    double o[3];
+    cam_centre(e, o);
+    const float o0 = (float)o[0], o1 = (float)o[1], o2 = (float)o[2];
+    const float hm = (float)(-0.5 * kLog2e);
+    Ent g[KM];
+    float4 cc[KM];
+    bool gv[KM];
+    comp_entries<KM, COLOR>(P, sr, c, o, g, cc, gv);
+    const int hw = vr.h * vr.w;
+    const int end = min(item.ray0 + item.span, hw);
+
+    for (int base = item.ray0; base < end; base += 4 * c.rpw) {
+        const int local = base + wave * c.rpw + c.sg;
+        const bool valid = local < end;
+        float v0, v1, v2;
+        ray_dir(P, vr, e, kk, valid ? local : end - 1, v0, v1, v2);
+        Geo q[KM];
+        float dl[KM];
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            if (k < c.ke) {
+                pair_geo(g[k], v0, v1, v2, hm, 0.0f, 0.0f, q[k]);
+                dl[k] = gv[k] ? exp2_(q[k].d2) : 0.0f;
+            }
+        }
+        __syncthreads();  // the previous step is done with the slots
+#pragma unroll
+        for (int k = 0; k < KM; ++k)
+            if (k < c.ke) tdl[c.sbase + k * c.seg + c.sl] = make_float2(q[k].t, dl[k]);
+        __syncthreads();
+        float l2[KM];
+        float mx = -INFINITY;
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            l2[k] = -INFINITY;
+            if (k < c.ke && gv[k]) {
+                const float front = ordered_partial<false>(tdl + c.sbase, n, q[k].t);
+                l2[k] = fmaf(-(float)kLog2e, front, log2_opacity(dl[k], q[k].d2));
+            }
+            mx = fmaxf(mx, l2[k]);
+        }
+        mx = seg_max(mx, c.seg);
+        float S = 0, T = 0, N0 = 0, N1 = 0, N2 = 0, C0 = 0, C1 = 0, C2 = 0, D = 0;
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            if (k < c.ke) {
+                const float ew = exp2_(l2[k] - mx);  // 0 for an empty slot
+                S += ew;
+                T = fmaf(ew, q[k].t, T);
+                D += dl[k];
+                if (NORMALS) {
+                    const PairNormal pn = pair_normal(g[k], q[k], 0.0f, 0.0f, 0.0f);
+                    N0 = fmaf(ew, pn.n0, N0);
+                    N1 = fmaf(ew, pn.n1, N1);
+                    N2 = fmaf(ew, pn.n2, N2);
+                }
+                if (COLOR) {
+                    C0 = fmaf(ew, cc[k].x, C0);
+                    C1 = fmaf(ew, cc[k].y, C1);
+                    C2 = fmaf(ew, cc[k].z, C2);
+                }
+            }
+        }
+        S = seg_sum(S, c.seg);
+        T = seg_sum(T, c.seg);
+        D = seg_sum(D, c.seg);
+        if (NORMALS) {
+            N0 = seg_sum(N0, c.seg);
+            N1 = seg_sum(N1, c.seg);
+            N2 = seg_sum(N2, c.seg);
+        }
+        if (COLOR) {
+            C0 = seg_sum(C0, c.seg);
+            C1 = seg_sum(C1, c.seg);
+            C2 = seg_sum(C2, c.seg);
+        }
+        if (c.sl == 0 && valid)
+            write_ray<F>(P, O, item.view, vr.ray_off + local, e, kk, o0, o1, o2, v0, v1, v2, mx, S, T, N0, N1, N2,
+                         C0, C1, C2, D);
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// Backward
+// ------------------------------------------------------------------------------------
+
+template <int KM, int F>
+__global__ __launch_bounds__(kCompBlock) void bwdc_kernel(Params P, BwdIn I, const BwdItem *__restrict__ items,
+                                                          float *__restrict__ partial, float *__restrict__ beta_partial)
+{
+    constexpr bool NORMALS = (F & kNrm) != 0, COLOR = (F & kCol) != 0;
+    constexpr int RW = COLOR ? 4 : 3;                        // float4 per staged ray
+    constexpr int REC = COLOR ? kPartialColor : kPartial;   // partial record per Gaussian
+    constexpr int RAYS4 = kCompBlock * RW;
+    constexpr int RED4 = (kCompBlock * KM * REC + 3) / 4;
+    __shared__ float4 smem[RAYS4 > RED4 ? RAYS4 : RED4];     // staged rays, then the reduction
+    __shared__ float2 tdl[kCompBlock * KM];
+    const int tid = threadIdx.x;
+    const BwdItem item = items[blockIdx.x];
+    const ViewRec vr = P.views[item.view];
+    const SceneRec sr = P.scenes[vr.scene];
+    const int n = sr.n;
+    const CompLanes c = comp_lanes<KM>(n);
+    const int wave = tid >> 6;
+    const float *__restrict__ e = P.w2c + 12 * item.view;
+    const float *__restrict__ kk = P.intr + 4 * item.view;
+    double o[3];
+    cam_centre(e, o);
+    const float o0 = (float)o[0], o1 = (float)o[1], o2 = (float)o[2];
+    const float hm = (float)(-0.5 * kLog2e);
+    Ent g[KM];
+    float4 cc[KM];
+    bool gv[KM];
+    comp_entries<KM, COLOR>(P, sr, c, o, g, cc, gv);
+    PairAcc acc[KM];
+    float aC[KM][3];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) aC[k][0] = aC[k][1] = aC[k][2] = 0.0f;
+    const int hw = vr.h * vr.w;
+    const int end = min(item.ray0 + item.span, hw);
+    const int step = 4 * c.rpw;
+
+    for (int base = item.ray0; base < end; base += step) {
+        __syncthreads();  // the previous step is done with the staged rays and the slots
+        if (tid < step) {
+            float4 pr[4];
+            ray_prologue<F>(P, I, item.view, vr, e, kk, o0, o1, o2, base + tid, base + tid < end, pr);
+#pragma unroll
+            for (int w = 0; w < RW; ++w) smem[RW * tid + w] = pr[w];
+        }
+        __syncthreads();
+        const int ry = wave * c.rpw + c.sg;
+        const float4 x0 = smem[RW * ry], x1 = smem[RW * ry + 1], x2 = smem[RW * ry + 2];
+        float4 x3 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (COLOR) x3 = smem[RW * ry + 3];
+        const float v0 = x0.x, v1 = x0.y, v2 = x0.z, M2 = x0.w, invS = x1.x, tfb = x1.y;
+        const float nb0 = x1.z, nb1 = x1.w, nb2 = x2.x, kap = x2.y, Db = x2.z;
+        Geo q[KM];
+        float dl[KM];
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            if (k < c.ke) {
+                pair_geo(g[k], v0, v1, v2, hm, 0.0f, 0.0f, q[k]);
+                dl[k] = gv[k] ? exp2_(q[k].d2) : 0.0f;
+                tdl[c.sbase + k * c.seg + c.sl] = make_float2(q[k].t, dl[k]);
+            }
+        }
+        __syncthreads();
+        float wt[KM], zb[KM];
+        PairNormal pn[KM];
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            wt[k] = zb[k] = 0.0f;
+            pn[k] = PairNormal{0, 0, 0, 0, 0};
+            if (k < c.ke) {
+                if (gv[k]) {
+                    const float front = ordered_partial<false>(tdl + c.sbase, n, q[k].t);
+                    wt[k] = exp2_(fmaf(-(float)kLog2e, front, log2_opacity(dl[k], q[k].d2)) - M2) * invS;
+                }
+                if (NORMALS) pn[k] = pair_normal(g[k], q[k], nb0, nb1, nb2);
+                float lin = fmaf(tfb, q[k].t, pn[k].nN);
+                if (COLOR) lin = fmaf(x3.x, cc[k].x, fmaf(x3.y, cc[k].y, fmaf(x3.z, cc[k].z, lin)));
+                zb[k] = wt[k] * (lin - kap);
+            }
+        }
+        __syncthreads();  // everyone is done reading (t, delta)
+#pragma unroll
+        for (int k = 0; k < KM; ++k)
+            if (k < c.ke) tdl[c.sbase + k * c.seg + c.sl] = make_float2(q[k].t, zb[k]);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            if (k < c.ke) {
+                const float behind = ordered_partial<true>(tdl + c.sbase, n, q[k].t);
+                const float db = fmaf(zb[k], opacity_slope(dl[k]), dl[k] * (Db - behind));
+                const float tb = wt[k] * tfb;
+                if (COLOR) {
+                    aC[k][0] = fmaf(wt[k], x3.x, aC[k][0]);
+                    aC[k][1] = fmaf(wt[k], x3.y, aC[k][1]);
+                    aC[k][2] = fmaf(wt[k], x3.z, aC[k][2]);
+                }
+                pair_adjoint<NORMALS>(g[k], q[k], v0, v1, v2, wt[k], pn[k], nb0, nb1, nb2, tb, db, acc[k]);
+            }
+        }
+    }
+
+    // deterministic reduction over the block's segments: Gaussian j's record sums the lanes
+    // holding it in wave order, then segment order
+    __syncthreads();
+    float *red = reinterpret_cast<float *>(smem);
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        float *my = red + (tid * KM + k) * REC;
+        const PairAcc &a = acc[k];
+        my[0] = a.u0; my[1] = a.u1; my[2] = a.u2; my[3] = a.u3; my[4] = a.u4; my[5] = a.u5;
+        my[6] = a.p0; my[7] = a.p1; my[8] = a.p2; my[9] = a.l;
+        if (COLOR) {
+            my[10] = aC[k][0]; my[11] = aC[k][1]; my[12] = aC[k][2];
+        }
+    }
+    __syncthreads();
+    if (tid < n) {
+        const int k = tid / c.seg, l = tid % c.seg;
+        float sum[REC];
+#pragma unroll
+        for (int v = 0; v < REC; ++v) sum[v] = 0.0f;
+        for (int w = 0; w < kCompBlock / 64; ++w)
+            for (int s = 0; s < c.rpw; ++s) {
+                const float *src = red + ((w * 64 + s * c.seg + l) * KM + k) * REC;
+#pragma unroll
+                for (int v = 0; v < REC; ++v) sum[v] += src[v];
+            }
+        write_partial(partial + item.poff + REC * tid, sum, REC, P.means + 3 * (sr.gauss_off + tid), o);
+    }
+    if (tid < 2) beta_partial[2 * item.seq + tid] = 0.0f;  // the model has no blend parameters
+}
+
+// ------------------------------------------------------------------------------------
+// Launchers
+// ------------------------------------------------------------------------------------
+
+#define FMB_COMP_DISPATCH(KM_, flags, CALL)                                                                \
+    switch (flags) {                                                                                      \
+    case 0: CALL(KM_, 0); break;                                                                          \
+    case 1: CALL(KM_, 1); break;                                                                          \
+    case 2: CALL(KM_, 2); break;                                                                          \
+    case 3: CALL(KM_, 3); break;                                                                          \
+    case 8: CALL(KM_, 8); break;                                                                          \
+    case 9: CALL(KM_, 9); break;                                                                          \
+    case 10: CALL(KM_, 10); break;                                                                        \
+    case 11: CALL(KM_, 11); break;                                                                        \
+    default: return hipErrorInvalidValue;                                                                 \
+    }
+
+#define FMB_FWDC_CALL(KM_, F_)                                                                            \
+    hipLaunchKernelGGL((fwdc_kernel<KM_, F_>), dim3(n_items), dim3(kCompBlock), 0, st, P, O, items)
+#define FMB_BWDC_CALL(KM_, F_)                                                                            \
+    hipLaunchKernelGGL((bwdc_kernel<KM_, F_>), dim3(n_items), dim3(kCompBlock), 0, st, P, I, items, partial, \
+                       beta_partial)
+
+hipError_t launch_fwdc(int km, int flags, int n_items, hipStream_t st, const Params &P, const FwdOut &O,
+                       const BwdItem *items)
+{
+    flags &= ~kPer;
+    if (n_items < 1) return hipSuccess;
+    if (km == 1) {
+        FMB_COMP_DISPATCH(1, flags, FMB_FWDC_CALL)
+    } else if (km == 2) {
+        FMB_COMP_DISPATCH(2, flags, FMB_FWDC_CALL)
+    } else if (km == 4) {
+        FMB_COMP_DISPATCH(4, flags, FMB_FWDC_CALL)
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_bwdc(int km, int flags, int n_items, hipStream_t st, const Params &P, const BwdIn &I,
+                       const BwdItem *items, float *partial, float *beta_partial)
+{
+    flags &= ~kPer;
+    if (n_items < 1) return hipSuccess;
+    if (km == 1) {
+        FMB_COMP_DISPATCH(1, flags, FMB_BWDC_CALL)
+    } else if (km == 2) {
+        FMB_COMP_DISPATCH(2, flags, FMB_BWDC_CALL)
+    } else if (km == 4) {
+        FMB_COMP_DISPATCH(4, flags, FMB_BWDC_CALL)
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace fmb

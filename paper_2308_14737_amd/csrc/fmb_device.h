@@ -1,0 +1,408 @@
+// fmb_device.h -- device helpers shared by the gfx950 kernels of both renderers: the
+// (view, Gaussian) entry formed in FP64, rays and projections, the geometry of one
+// (ray, Gaussian) pair, the per-ray adjoint prologue and the per-pair adjoint that maps
+// (dL/dt_i, dL/dd_i, dL/dn_i) to the Gaussian's parameters.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "fmb_internal.h"
+
+namespace fmb {
+
+// ------------------------------------------------------------------------------------
+// Small helpers
+// ------------------------------------------------------------------------------------
+
+__device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float rsq_(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float exp2_(float x) { return __builtin_amdgcn_exp2f(x); }
+
+struct Ent {  // one (view, Gaussian) entry: 16 floats = 4 x float4 in LDS
+    float u00, u01, u02, u11, u12, u22;  // packed upper U
+    float mh0, mh1, mh2;                 // mu - o rounded to float ("high part")
+    float ul0, ul1, ul2;                 // U (mu - o - high part): the low part, through U
+    float c0, c1, c2;                    // Sigma^-1 (mu - o)
+    float l2l;                           // log2 lambda
+};
+
+__device__ __forceinline__ Ent ent_from(const float4 a, const float4 b, const float4 c, const float4 d)
+{
+    return Ent{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w, d.x, d.y, d.z, d.w};
+}
+
+// Camera centre o = -R^T T in double.
+__device__ __forceinline__ void cam_centre(const float *__restrict__ e, double o[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        o[a] = -((double)e[a] * (double)e[3] + (double)e[4 + a] * (double)e[7] +
+                 (double)e[8 + a] * (double)e[11]);
+}
+
+// (view, Gaussian) entry in double, rounded to float.  mu - o is split as hi + lo; the
+// pair loop forms U (t v - mu') as U (t v - hi) - U lo, so only U lo is stored.
+__device__ __forceinline__ void make_entry(const float *__restrict__ mu, const float *__restrict__ u,
+                                           float lam, const double o[3], float4 out[4])
+{
+    const double m0 = (double)mu[0] - o[0], m1 = (double)mu[1] - o[1], m2 = (double)mu[2] - o[2];
+    const float h0 = (float)m0, h1 = (float)m1, h2 = (float)m2;
+    const double l0 = m0 - (double)h0, l1 = m1 - (double)h1, l2 = m2 - (double)h2;
+    const double U00 = u[0], U01 = u[1], U02 = u[2], U11 = u[3], U12 = u[4], U22 = u[5];
+    const double b0 = U00 * m0 + U01 * m1 + U02 * m2;
+    const double b1 = U11 * m1 + U12 * m2;
+    const double b2 = U22 * m2;
+    const double c0 = U00 * b0;
+    const double c1 = U01 * b0 + U11 * b1;
+    const double c2 = U02 * b0 + U12 * b1 + U22 * b2;
+    const double ul0 = U00 * l0 + U01 * l1 + U02 * l2, ul1 = U11 * l1 + U12 * l2, ul2 = U22 * l2;
+    out[0] = make_float4(u[0], u[1], u[2], u[3]);
+    out[1] = make_float4(u[4], u[5], h0, h1);
+    out[2] = make_float4(h2, (float)ul0, (float)ul1, (float)ul2);
+    out[3] = make_float4((float)c0, (float)c1, (float)c2, (float)log2((double)lam));
+}
+
+// Unit direction of the ray through the centre of pixel (row, col).
+__device__ __forceinline__ void pixel_dir(const float *__restrict__ e, const float *__restrict__ k, int row,
+                                          int col, float &v0, float &v1, float &v2)
+{
+    const float dx = ((float)col + 0.5f - k[2]) / k[0];
+    const float dy = ((float)row + 0.5f - k[3]) / k[1];
+    const float x = fmaf(e[0], dx, fmaf(e[4], dy, e[8]));
+    const float y = fmaf(e[1], dx, fmaf(e[5], dy, e[9]));
+    const float z = fmaf(e[2], dx, fmaf(e[6], dy, e[10]));
+    const float inv = 1.0f / sqrtf(fmaf(x, x, fmaf(y, y, z * z)));
+    v0 = x * inv;
+    v1 = y * inv;
+    v2 = z * inv;
+}
+
+// Direction of ray `local` of view `vr`: the pixel ray, or the given direction normalised.
+__device__ __forceinline__ void ray_dir(const Params &P, const ViewRec &vr, const float *__restrict__ e,
+                                        const float *__restrict__ k, int local, float &v0, float &v1, float &v2)
+{
+    if (P.dirs) {
+        const float *d = P.dirs + 3 * ((size_t)vr.ray_off + local);
+        const float x = d[0], y = d[1], z = d[2];
+        const float inv = 1.0f / sqrtf(fmaf(x, x, fmaf(y, y, z * z)));
+        v0 = x * inv;
+        v1 = y * inv;
+        v2 = z * inv;
+    } else {
+        pixel_dir(e, k, local / vr.w, local % vr.w, v0, v1, v2);
+    }
+}
+
+__device__ __forceinline__ void project(const float *__restrict__ e, const float *__restrict__ k, float p0,
+                                        float p1, float p2, float &u, float &v)
+{
+    const float q0 = fmaf(e[0], p0, fmaf(e[1], p1, fmaf(e[2], p2, e[3])));
+    const float q1 = fmaf(e[4], p0, fmaf(e[5], p1, fmaf(e[6], p2, e[7])));
+    const float q2 = fmaf(e[8], p0, fmaf(e[9], p1, fmaf(e[10], p2, e[11])));
+    const float iz = 1.0f / q2;
+    u = fmaf(k[0] * q0, iz, k[2]);
+    v = fmaf(k[1] * q1, iz, k[3]);
+}
+
+// Geometry of one (ray, Gaussian) pair.
+struct Geo {
+    float a0, a1, a2, raa;  // a = U v, 1/(a.a)
+    float t;                // refined peak depth
+    float r0, r1, r2;       // r = U (t v - mu')
+    float d2, z2;           // log2 density, log2 blend weight
+};
+
+__device__ __forceinline__ void pair_geo(const Ent &g, float v0, float v1, float v2, float hm, float b1,
+                                         float nc2, Geo &q)
+{
+    q.a0 = fmaf(g.u00, v0, fmaf(g.u01, v1, g.u02 * v2));
+    q.a1 = fmaf(g.u11, v1, g.u12 * v2);
+    q.a2 = g.u22 * v2;
+    const float aa = fmaf(q.a0, q.a0, fmaf(q.a1, q.a1, q.a2 * q.a2));
+    const float vc = fmaf(v0, g.c0, fmaf(v1, g.c1, v2 * g.c2));
+    q.raa = rcp_(aa);
+    const float t0 = vc * q.raa;
+    const float w0 = fmaf(t0, v0, -g.mh0);
+    const float w1 = fmaf(t0, v1, -g.mh1);
+    const float w2 = fmaf(t0, v2, -g.mh2);
+    const float r0 = fmaf(g.u00, w0, fmaf(g.u01, w1, fmaf(g.u02, w2, -g.ul0)));
+    const float r1 = fmaf(g.u11, w1, fmaf(g.u12, w2, -g.ul1));
+    const float r2 = fmaf(g.u22, w2, -g.ul2);
+    // one Newton step on t -> |U (t v - mu')|^2 (exactly quadratic): dt = (a.r)/(a.a)
+    const float dt = fmaf(q.a0, r0, fmaf(q.a1, r1, q.a2 * r2)) * q.raa;
+    q.t = t0 - dt;
+    q.r0 = fmaf(-dt, q.a0, r0);
+    q.r1 = fmaf(-dt, q.a1, r1);
+    q.r2 = fmaf(-dt, q.a2, r2);
+    const float m = fmaf(q.r0, q.r0, fmaf(q.r1, q.r1, q.r2 * q.r2));
+    q.d2 = fmaf(hm, m, g.l2l);
+    q.z2 = fmaf(b1, q.d2, nc2 * q.t);
+}
+
+// Per-item blend constants of a scene: hm = -log2(e)/2, b1 = beta1, nc2 = -beta2 log2(e)/eta.
+struct Blend {
+    float hm, b1, nc2, cb;  // cb = beta2 / eta (natural units, backward)
+    float inv_eta;
+};
+
+__device__ __forceinline__ Blend blend_of(const Params &P, int s)
+{
+    const double b1 = P.betas[2 * s], b2 = P.betas[2 * s + 1], eta = P.eta[s];
+    Blend b;
+    b.hm = (float)(-0.5 * kLog2e);
+    b.b1 = (float)b1;
+    b.nc2 = (float)(-b2 * kLog2e / eta);
+    b.cb = (float)(b2 / eta);
+    b.inv_eta = (float)(1.0 / eta);
+    return b;
+}
+
+// ------------------------------------------------------------------------------------
+// Kernel variants: F is a bit set of the outputs/cotangents a launch handles.
+// ------------------------------------------------------------------------------------
+
+constexpr int kNrm = 1;  // normals (Eq. 17)
+constexpr int kFlw = 2;  // flow to a second pose (Sec. 5)
+constexpr int kPer = 4;  // persistent work queue
+constexpr int kCol = 8;  // per-Gaussian colour blended by Eq. (3)
+
+// Colour of a Gaussian: sigmoid of the unconstrained parameters (double, rounded).
+__device__ __forceinline__ float4 colour_entry(const float *__restrict__ q)
+{
+    return make_float4((float)(1.0 / (1.0 + exp(-(double)q[0]))), (float)(1.0 / (1.0 + exp(-(double)q[1]))),
+                       (float)(1.0 / (1.0 + exp(-(double)q[2]))), 0.0f);
+}
+
+// Outputs of ray r (global index) of view `view` from its blended sums, common to both
+// renderers: S = sum of the weights scaled by 2^-M (M the running maximum of their base-2
+// logarithms), T = sum w t, N = sum w n, C = sum w c (same scale) and D = sum delta.  Writes
+// depth = T/S (Eq. 3), alpha (Eq. 8), the unit normal, the flow to the second (and third)
+// pose, the colour and the stash (M, 1/S, N/S, D, 0, 0).
+template <int F>
+__device__ __forceinline__ void write_ray(const Params &P, const FwdOut &O, int view, int r,
+                                          const float *__restrict__ e, const float *__restrict__ kk, float o0,
+                                          float o1, float o2, float v0, float v1, float v2, float M, float S,
+                                          float T, float N0, float N1, float N2, float C0, float C1, float C2,
+                                          float D)
+{
+    constexpr bool NORMALS = (F & kNrm) != 0, FLOW = (F & kFlw) != 0, COLOR = (F & kCol) != 0;
+    const float invS = 1.0f / S;
+    const float tf = T * invS;
+    const float n0 = N0 * invS, n1 = N1 * invS, n2 = N2 * invS;
+    O.depth[r] = tf;
+    O.alpha[r] = -expm1f(-D);
+    if (NORMALS) {
+        const float inn = 1.0f / sqrtf(fmaf(n0, n0, fmaf(n1, n1, fmaf(n2, n2, kEpsN))));
+        O.normal[3 * r + 0] = n0 * inn;
+        O.normal[3 * r + 1] = n1 * inn;
+        O.normal[3 * r + 2] = n2 * inn;
+    }
+    if (FLOW) {
+        // flow to the second pose (and, if given, to a third: forward and backward flow)
+        const float p0 = fmaf(tf, v0, o0), p1 = fmaf(tf, v1, o1), p2 = fmaf(tf, v2, o2);
+        float ub, vb, ua, va;
+        project(P.w2c_b + 12 * view, P.intr_b + 4 * view, p0, p1, p2, ub, vb);
+        project(e, kk, p0, p1, p2, ua, va);
+        const int fk = P.w2c_c ? 4 : 2;
+        O.flow[fk * r + 0] = ub - ua;
+        O.flow[fk * r + 1] = vb - va;
+        if (P.w2c_c) {
+            float uc, vc;
+            project(P.w2c_c + 12 * view, P.intr_c + 4 * view, p0, p1, p2, uc, vc);
+            O.flow[fk * r + 2] = uc - ua;
+            O.flow[fk * r + 3] = vc - va;
+        }
+    }
+    if (COLOR) {
+        O.color[3 * r + 0] = C0 * invS;
+        O.color[3 * r + 1] = C1 * invS;
+        O.color[3 * r + 2] = C2 * invS;
+    }
+    if (O.stash) {
+        float4 *st = reinterpret_cast<float4 *>(O.stash) + 2 * (size_t)r;
+        st[0] = make_float4(M, invS, n0, n1);
+        st[1] = make_float4(n2, D, 0.0f, 0.0f);
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// Adjoint helpers
+// ------------------------------------------------------------------------------------
+
+// g . d pi(p + t v)/dt at t = 0 for camera e (world-to-camera) and intrinsics k.
+__device__ __forceinline__ float flow_dot(const float *__restrict__ e, const float *__restrict__ k, float p0,
+                                          float p1, float p2, float v0, float v1, float v2,
+                                          const float *__restrict__ g)
+{
+    const float q0 = fmaf(e[0], p0, fmaf(e[1], p1, fmaf(e[2], p2, e[3])));
+    const float q1 = fmaf(e[4], p0, fmaf(e[5], p1, fmaf(e[6], p2, e[7])));
+    const float q2 = fmaf(e[8], p0, fmaf(e[9], p1, fmaf(e[10], p2, e[11])));
+    const float u0 = fmaf(e[0], v0, fmaf(e[1], v1, e[2] * v2));
+    const float u1 = fmaf(e[4], v0, fmaf(e[5], v1, e[6] * v2));
+    const float u2 = fmaf(e[8], v0, fmaf(e[9], v1, e[10] * v2));
+    const float iz = 1.0f / q2;
+    const float j0 = k[0] * (u0 - q0 * iz * u2) * iz;
+    const float j1 = k[1] * (u1 - q1 * iz * u2) * iz;
+    return fmaf(g[0], j0, g[1] * j1);
+}
+
+// Per-ray adjoint prologue, staged in LDS as RW float4:
+//   (v0, v1, v2, M2) (invS, tf_bar, Nb0, Nb1) (Nb2, kappa, D_bar, 0) [(Cb0, Cb1, Cb2, 0)]
+// with tf_bar = dL/dt_f (depth + flow), Nb = dL/dN for the unnormalised blended normal,
+// Cb = dL/dC for the blended colour, kappa = tf_bar t_f + Nb.N + Cb.C, and
+// D_bar = dL/d(sum delta) = g_alpha exp(-D).
+template <int F>
+__device__ __forceinline__ void ray_prologue(const Params &P, const BwdIn &I, int view, const ViewRec &vr,
+                                             const float *__restrict__ e, const float *__restrict__ kk,
+                                             const float o0, const float o1, const float o2, int local,
+                                             bool valid, float4 out[4])
+{
+    constexpr bool NORMALS = (F & kNrm) != 0, FLOW = (F & kFlw) != 0, COLOR = (F & kCol) != 0;
+    if (!valid) {
+        out[0] = make_float4(0.0f, 0.0f, 1.0f, INFINITY);
+        out[1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        out[2] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        out[3] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        return;
+    }
+    float v0, v1, v2;
+    ray_dir(P, vr, e, kk, local, v0, v1, v2);
+    const int r = vr.ray_off + local;
+    const float tf = I.depth[r];
+    const float4 s0 = reinterpret_cast<const float4 *>(I.stash)[2 * (size_t)r];
+    const float4 s1 = reinterpret_cast<const float4 *>(I.stash)[2 * (size_t)r + 1];
+    const float Nx = s0.z, Ny = s0.w, Nz = s1.x, Dsum = s1.y;
+    float tfb = I.g_depth ? I.g_depth[r] : 0.0f;
+    if (FLOW) {
+        // flow = pi_B(p) - pi_A(p), p = o + t_f v; pi_A(o + t v) does not depend on t, so
+        // d flow / d t_f = J_B R_B v (and likewise for the optional third pose).
+        const float p0 = fmaf(tf, v0, o0), p1 = fmaf(tf, v1, o1), p2 = fmaf(tf, v2, o2);
+        const int fk = P.w2c_c ? 4 : 2;
+        tfb += flow_dot(P.w2c_b + 12 * view, P.intr_b + 4 * view, p0, p1, p2, v0, v1, v2, I.g_flow + fk * r);
+        if (P.w2c_c)
+            tfb += flow_dot(P.w2c_c + 12 * view, P.intr_c + 4 * view, p0, p1, p2, v0, v1, v2, I.g_flow + fk * r + 2);
+    }
+    const float Db = I.g_alpha ? I.g_alpha[r] * expf(-Dsum) : 0.0f;
+    float nb0 = 0.0f, nb1 = 0.0f, nb2 = 0.0f;
+    if (NORMALS) {
+        const float s = sqrtf(fmaf(Nx, Nx, fmaf(Ny, Ny, fmaf(Nz, Nz, kEpsN))));
+        const float is = 1.0f / s;
+        const float f0 = Nx * is, f1 = Ny * is, f2 = Nz * is;
+        const float g0 = I.g_normal[3 * r], g1 = I.g_normal[3 * r + 1], g2 = I.g_normal[3 * r + 2];
+        const float dp = fmaf(f0, g0, fmaf(f1, g1, f2 * g2));
+        nb0 = (g0 - f0 * dp) * is;
+        nb1 = (g1 - f1 * dp) * is;
+        nb2 = (g2 - f2 * dp) * is;
+    }
+    float kap = fmaf(tfb, tf, fmaf(nb0, Nx, fmaf(nb1, Ny, nb2 * Nz)));
+    float cb0 = 0.0f, cb1 = 0.0f, cb2 = 0.0f;
+    if (COLOR) {
+        cb0 = I.g_color[3 * r];
+        cb1 = I.g_color[3 * r + 1];
+        cb2 = I.g_color[3 * r + 2];
+        kap = fmaf(cb0, I.color[3 * r], fmaf(cb1, I.color[3 * r + 1], fmaf(cb2, I.color[3 * r + 2], kap)));
+    }
+    out[0] = make_float4(v0, v1, v2, s0.x);
+    out[1] = make_float4(s0.y, tfb, nb0, nb1);
+    out[2] = make_float4(nb2, kap, Db, 0.0f);
+    out[3] = make_float4(cb0, cb1, cb2, 0.0f);
+}
+
+// Normal of Eq. (17) for one pair: g = U^T r = Sigma^-1 x, n = g / |g|, and n . Nb for the
+// per-ray normal cotangent Nb.
+struct PairNormal {
+    float n0, n1, n2;  // unit normal
+    float rs;          // 1 / |g|
+    float nN;          // n . Nb
+};
+
+__device__ __forceinline__ PairNormal pair_normal(const Ent &g, const Geo &q, float nb0, float nb1, float nb2)
+{
+    const float g0 = g.u00 * q.r0;
+    const float g1 = fmaf(g.u01, q.r0, g.u11 * q.r1);
+    const float g2 = fmaf(g.u02, q.r0, fmaf(g.u12, q.r1, g.u22 * q.r2));
+    PairNormal pn;
+    pn.rs = rsq_(fmaf(g0, g0, fmaf(g1, g1, fmaf(g2, g2, kEpsN))));
+    pn.n0 = g0 * pn.rs;
+    pn.n1 = g1 * pn.rs;
+    pn.n2 = g2 * pn.rs;
+    pn.nN = fmaf(pn.n0, nb0, fmaf(pn.n1, nb1, pn.n2 * nb2));
+    return pn;
+}
+
+// Per-Gaussian gradient accumulator of one lane: dL/dU (upper, without the -(sum rho) mu'^T
+// term), sum rho = dL/d(U mu') and dL/dlog(lambda).
+struct PairAcc {
+    float u0 = 0, u1 = 0, u2 = 0, u3 = 0, u4 = 0, u5 = 0;
+    float p0 = 0, p1 = 0, p2 = 0;
+    float l = 0;
+};
+
+// Adjoint of one pair given tb = dL/dt_i (peak depth), db = dL/dd_i (log density) and the
+// normal's cotangent wt * Nb.  r_bar = U g_bar - d_bar r with g_bar = wt (Nb - n (n.Nb)) / |g|;
+// the peak-depth adjoint tau = (t_bar + a.r_bar) / (a.a) uses a.r = 0 at the peak, and
+// rho = r_bar - tau a.  U_bar = sum r g_bar^T + rho w^T - tau r v^T with w = t v - mu' is
+// accumulated as sum r g_bar^T + (t rho - tau r) v^T; the -(sum rho) mu'^T term is applied
+// once per item.
+template <bool NORMALS>
+__device__ __forceinline__ void pair_adjoint(const Ent &g, const Geo &q, float v0, float v1, float v2, float wt,
+                                             const PairNormal &pn, float nb0, float nb1, float nb2, float tb,
+                                             float db, PairAcc &a)
+{
+    a.l += db;
+    float gb0 = 0, gb1 = 0, gb2 = 0, ug0 = 0, ug1 = 0, ug2 = 0, tau;
+    if (NORMALS) {
+        const float ws = wt * pn.rs;
+        gb0 = ws * fmaf(-pn.n0, pn.nN, nb0);
+        gb1 = ws * fmaf(-pn.n1, pn.nN, nb1);
+        gb2 = ws * fmaf(-pn.n2, pn.nN, nb2);
+        ug0 = fmaf(g.u00, gb0, fmaf(g.u01, gb1, g.u02 * gb2));
+        ug1 = fmaf(g.u11, gb1, g.u12 * gb2);
+        ug2 = g.u22 * gb2;
+        tau = fmaf(q.a0, ug0, fmaf(q.a1, ug1, fmaf(q.a2, ug2, tb))) * q.raa;
+    } else {
+        tau = tb * q.raa;
+    }
+    const float p0 = fmaf(-tau, q.a0, fmaf(-db, q.r0, ug0));
+    const float p1 = fmaf(-tau, q.a1, fmaf(-db, q.r1, ug1));
+    const float p2 = fmaf(-tau, q.a2, fmaf(-db, q.r2, ug2));
+    const float k0 = fmaf(q.t, p0, -tau * q.r0);
+    const float k1 = fmaf(q.t, p1, -tau * q.r1);
+    const float k2 = fmaf(q.t, p2, -tau * q.r2);
+    if (NORMALS) {
+        a.u0 = fmaf(q.r0, gb0, a.u0);
+        a.u1 = fmaf(q.r0, gb1, a.u1);
+        a.u2 = fmaf(q.r0, gb2, a.u2);
+        a.u3 = fmaf(q.r1, gb1, a.u3);
+        a.u4 = fmaf(q.r1, gb2, a.u4);
+        a.u5 = fmaf(q.r2, gb2, a.u5);
+    }
+    a.u0 = fmaf(k0, v0, a.u0);
+    a.u1 = fmaf(k0, v1, a.u1);
+    a.u2 = fmaf(k0, v2, a.u2);
+    a.u3 = fmaf(k1, v1, a.u3);
+    a.u4 = fmaf(k1, v2, a.u4);
+    a.u5 = fmaf(k2, v2, a.u5);
+    a.p0 += p0;
+    a.p1 += p1;
+    a.p2 += p2;
+}
+
+// Write one Gaussian's partial record: dU with the -(sum rho) mu'^T term applied in double
+// (mu' = mu - o), then sum rho, dL/dlog(lambda) and the remaining values as given.
+__device__ __forceinline__ void write_partial(float *__restrict__ dst, const float *acc, int rec,
+                                              const float *__restrict__ mu, const double o[3])
+{
+    const double m0 = (double)mu[0] - o[0], m1 = (double)mu[1] - o[1], m2 = (double)mu[2] - o[2];
+    const double r0 = acc[6], r1 = acc[7], r2 = acc[8];
+    dst[0] = (float)((double)acc[0] - r0 * m0);
+    dst[1] = (float)((double)acc[1] - r0 * m1);
+    dst[2] = (float)((double)acc[2] - r0 * m2);
+    dst[3] = (float)((double)acc[3] - r1 * m1);
+    dst[4] = (float)((double)acc[4] - r1 * m2);
+    dst[5] = (float)((double)acc[5] - r2 * m2);
+    for (int c = 6; c < rec; ++c) dst[c] = acc[c];
+}
+
+}  // namespace fmb

@@ -73,6 +73,17 @@ constexpr int kGroupItems = 32;  // minimum items per first-stage group
 constexpr int kPartial = 10;       // per-Gaussian partial: dU (6), sum rho (3), dlog(lambda) (1)
 constexpr int kPartialColor = 13;  // ... and dL/d(colour) (3)
 
+// Zero-parameter (alpha-compositing) renderer: lanes per ray for a scene of n Gaussians (the
+// smallest power of two >= n, at most 64; a lane holds n / 64 Gaussians beyond that) and the
+// largest scene it takes (4 Gaussians per lane).
+constexpr int comp_seg(int n)
+{
+    int s = 1;
+    while (s < n && s < 64) s <<= 1;
+    return s;
+}
+constexpr int kCompMaxN = 256;
+
 // Kernel argument blocks (passed by value).
 struct Params {
     const float *means, *prec, *weights, *betas;   // concatenated over scenes; betas [S,2]

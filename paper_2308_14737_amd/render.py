@@ -17,6 +17,14 @@ import torch
 from . import _lib
 
 STASH = 8  # floats of per-ray softmax state kept for the backward pass
+# Blend weights of Eq. (3): the two-parameter model (Eq. 7) or alpha compositing (Eq. 9-10).
+MODELS = {"blend": 0, "composite": 1}
+
+
+def _model_id(model: str) -> int:
+    if model not in MODELS:
+        raise ValueError(f"model must be one of {sorted(MODELS)}")
+    return MODELS[model]
 
 
 def _vp(t: Optional[torch.Tensor]):
@@ -96,6 +104,7 @@ class Scene:
                   _vp(betas), ctypes.c_float(self.eta))
         self._h = h
         self.cameras = None
+        self.model = "blend"
         if cameras is not None:
             self.set_cameras(cameras)
 
@@ -111,6 +120,12 @@ class Scene:
                 raise ValueError("colors must be [N,3]")
         _lib.call("fmb_set_colors", self._h, None, _vp(colors))
         self._colors = colors
+
+    def set_model(self, model: str):
+        """"blend" (two-parameter weights, Eq. 7) or "composite" (zero-parameter alpha
+        compositing, Eq. 9-10; at most 256 Gaussians)."""
+        _lib.call("fmb_set_model", self._h, None, _model_id(model))
+        self.model = model
 
     def rebind(self, means, prec, weights, betas):
         for t, nm in ((means, "means"), (prec, "prec"), (weights, "weights"), (betas, "betas")):
@@ -295,6 +310,7 @@ class Batch:
         self.w2c_c = torch.cat([c.w2c_c.reshape(-1, 12) for c in cams]).contiguous() if all(second) else None
         self.intr_c = torch.cat([c.intr_c.reshape(-1, 4) for c in cams]).contiguous() if all(second) else None
         self.n_total = int(self.n_host.sum())
+        self.model = "blend"
         self._keep = (means, prec, weights, betas)
         h = ctypes.c_void_p()
         _lib.call("fmb_batch_create", ctypes.byref(h), self.s, self.n_host.ctypes.data_as(ctypes.c_void_p),
@@ -323,6 +339,11 @@ class Batch:
             _check_dev(colors, "colors")
         _lib.call("fmb_set_colors", None, self._h, _vp(colors))
         self._colors = colors
+
+    def set_model(self, model: str):
+        """"blend" or "composite" for every scene of the batch (see Scene.set_model)."""
+        _lib.call("fmb_set_model", None, self._h, _model_id(model))
+        self.model = model
 
     def alloc_outputs(self, normals=True, color=False):
         p, dev = self.n_rays, self.device

@@ -4,6 +4,8 @@ from __future__ import annotations
 
 import numpy as np
 
+import workloads as W
+
 # Tolerances of the renderer's contract: norm-wise relative for depth, normals, flow
 # and gradients (per tensor), max absolute for alpha.
 TOL_REL = 1e-4
@@ -62,3 +64,44 @@ def compare_grads(g, gref):
 def assert_grads(e, what=""):
     for k, v in e.items():
         assert v <= TOL_GRAD, f"{what} grad {k}: {e}"
+
+
+def custom_scene(n, views, seed, behind=False, flow=False, s_range=(0.05, 0.2)):
+    """n Gaussians uniform in [-1,1]^3 (a third behind the front camera if `behind`), views of the
+    given (H, W): a front camera at z = -3, the others on a sphere of radius 3, and, with
+    `flow`, a second pose shifted by a small translation."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    means = g.uniform(-1, 1, (n, 3))
+    if behind:
+        means[: n // 3, 2] = g.uniform(-6, -3.5, n // 3)  # behind the front camera at z = -3
+    sc = W.make_scene(g, n, means, log_s_range=s_range)
+    e, k, hw = [], [], []
+    for i, (h, wd) in enumerate(views):
+        if i == 0:
+            e.append(np.concatenate([np.eye(3), [[0.0], [0.0], [3.0]]], axis=1))
+        else:
+            e.append(W.look_at(3.0 * W.fibonacci_sphere(len(views))[i]))
+        k.append([float(h), float(h), wd / 2.0, h / 2.0])
+        hw.append([h, wd])
+    e = np.array(e, np.float32)
+    cams = W.Cameras(e, np.array(k, np.float32), np.array(hw, np.int32))
+    if flow:
+        eb = e.copy()
+        eb[:, :, 3] += np.array([0.03, -0.02, 0.01], np.float32)
+        cams.w2c_b, cams.intr_b = eb, cams.intr.copy()
+    return sc, cams
+
+
+def hit_mask_cot(cot, alpha_ref, thr=1e-3):
+    """Depth/normal/flow/colour cotangents only on rays that see the scene (oracle alpha >= thr); the
+    alpha cotangent everywhere.  Over background rays the blend weights are decided by
+    log-density differences of order 1e4 that FP32 cannot resolve (see
+    test_background_rays_conditioning)."""
+    keep = alpha_ref >= thr
+    out = {}
+    for k, v in cot.items():
+        if v is None or k == "alpha":
+            out[k] = v
+        else:
+            out[k] = (v * keep.reshape(-1, *([1] * (v.ndim - 1)))).astype(np.float32)
+    return out

@@ -1,0 +1,216 @@
+"""GPU parity of the zero-parameter renderer (alpha compositing, Eq. 9-10) against the oracle.
+
+Every case renders through the C ABI with the compositing model selected and compares with
+the FP64 oracle's compositing model on the same seeded inputs: scene sizes that use one, two
+and four Gaussians per lane (N = 1 ... 256), ragged images, tied intersections, Gaussians
+behind the camera, colours and both flow directions, the batched path, and the gradient of the
+workload loss.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from tests.gpu_util import (TOL_REL, assert_forward, assert_grads, compare_forward, compare_grads,
+                            custom_scene, hit_mask_cot, make_scene, normwise, to_np)
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+BETAS = np.array([W.BETA1, W.BETA2], np.float32)
+
+
+@pytest.fixture(scope="module")
+def fmb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2308_14737_amd as m
+    return m
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _t(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device=DEV).contiguous()
+
+
+def _composite_scene(fmb, sc, cams):
+    scene, params = make_scene(fmb, torch, sc, cams, BETAS, 1.0, DEV)
+    scene.set_model("composite")
+    return scene, params
+
+
+CASES = [
+    ("n1_odd", 1, [(17, 23)]),
+    ("n7_multi", 7, [(5, 3), (64, 64), (1, 1), (33, 65)]),
+    ("n40", 40, [(48, 64), (31, 17)]),
+    ("n64_full_wave", 64, [(40, 50)]),
+    ("n100_two_per_lane", 100, [(40, 50), (3, 7)]),
+    ("n256_four_per_lane", 256, [(24, 32)]),
+]
+
+
+@pytest.mark.parametrize("label,n,views", CASES, ids=[c[0] for c in CASES])
+def test_composite_parity(fmb, label, n, views):
+    sc, cams = custom_scene(n, views, seed=100 + n, flow=True)
+    _say(f"[composite] {label}: N={n} views={views}")
+    scene, _ = _composite_scene(fmb, sc, cams)
+    outs = scene.render(normals=True)
+    ref, _, _ = O.render_workload_view(sc, cams, BETAS, 1.0, model="composite")
+    cot = hit_mask_cot(W.random_cotangents(cams.n_rays, 6, flow=True), ref["alpha"])
+    g = scene.backward(outs, _t(cot["depth"]), _t(cot["alpha"]), _t(cot["normal"]), _t(cot["flow"]))
+    torch.cuda.synchronize()
+    _, gref, _ = O.render_workload_view(sc, cams, BETAS, 1.0, cot=cot, model="composite")
+    e = compare_forward(outs, ref)
+    eg = compare_grads(g, gref)
+    _say(f"[composite] {label}: {e} {eg}")
+    assert_forward(e, label)
+    assert_grads(eg, label)
+    assert torch.count_nonzero(g["betas"]).item() == 0
+
+
+def test_composite_ties_and_behind(fmb):
+    """Copies of the same Gaussian (equal t on every ray: no mutual attenuation) and Gaussians
+    behind the front camera."""
+    sc, cams = custom_scene(30, [(40, 48), (17, 9)], seed=7, behind=True)
+    dup = np.array([3, 3, 3, 11, 11])
+    sc = W.Scene(np.concatenate([sc.means, sc.means[dup]]), np.concatenate([sc.prec, sc.prec[dup]]),
+                 np.concatenate([sc.weights, sc.weights[dup]]))
+    _say(f"[composite-ties] N={sc.n} P={cams.n_rays}")
+    scene, _ = _composite_scene(fmb, sc, cams)
+    outs = scene.render(normals=True)
+    ref, _, _ = O.render_workload_view(sc, cams, BETAS, 1.0, model="composite")
+    cot = hit_mask_cot(W.random_cotangents(cams.n_rays, 8, flow=False), ref["alpha"])
+    g = scene.backward(outs, _t(cot["depth"]), _t(cot["alpha"]), _t(cot["normal"]))
+    torch.cuda.synchronize()
+    _, gref, _ = O.render_workload_view(sc, cams, BETAS, 1.0, cot=cot, model="composite")
+    e, eg = compare_forward(outs, ref), compare_grads(g, gref)
+    _say(f"[composite-ties] {e} {eg}")
+    assert_forward(e, "ties")
+    assert_grads(eg, "ties")
+
+
+def test_composite_colour_two_way_flow_quality(fmb):
+    """Colours, forward and backward flow, and the quality value max_i w_i (from the stash)."""
+    sc, cams = custom_scene(50, [(36, 44), (20, 30)], seed=9, flow=True)
+    cams = W.with_backward_flow(cams, seed=10)
+    g = np.random.Generator(np.random.PCG64(11))
+    q = (1.5 * g.standard_normal((sc.n, 3))).astype(np.float32)
+    _say(f"[composite-colour] N={sc.n} P={cams.n_rays}")
+    scene, _ = _composite_scene(fmb, sc, cams)
+    scene.set_colors(_t(q))
+    outs = scene.render(normals=True)
+    ref, _, (view, row, col) = O.render_workload_view(sc, cams, BETAS, 1.0, colors=q, model="composite")
+    e = compare_forward(outs, ref)
+    e["color"] = normwise(to_np(outs["color"]), ref["color"])
+    hit = ref["alpha"] >= 1e-3
+    cot = hit_mask_cot(W.random_cotangents(cams.n_rays, 12, flow=False), ref["alpha"])
+    cot["flow"] = (g.standard_normal((cams.n_rays, 4)) * hit[:, None]).astype(np.float32)
+    cot["color"] = (g.standard_normal((cams.n_rays, 3)) * hit[:, None]).astype(np.float32)
+    gr = scene.backward(outs, _t(cot["depth"]), _t(cot["alpha"]), _t(cot["normal"]), _t(cot["flow"]),
+                        g_color=_t(cot["color"]))
+    torch.cuda.synchronize()
+    _, gref, _ = O.render_workload_view(sc, cams, BETAS, 1.0, cot=cot, colors=q, model="composite")
+    eg = compare_grads(gr, gref)
+    eg["colors"] = normwise(to_np(gr["colors"]), gref["colors"])
+    rs = np.flatnonzero(hit)[:: max(1, int(hit.sum()) // 300)]
+    o, v = O.pixel_rays(view[rs], row[rs], col[rs], cams.w2c, cams.intr)
+    osc = O.OracleScene.of(sc.means, sc.prec, sc.weights, BETAS, 1.0)
+    e["quality"] = float(np.max(np.abs(to_np(fmb.Scene.quality(outs))[rs]
+                                       - O.max_weight(osc, o, v, model="composite"))))
+    _say(f"[composite-colour] {e} {eg}")
+    assert_forward(e, "colour")
+    assert e["color"] <= TOL_REL and e["quality"] <= TOL_REL
+    assert_grads(eg, "colour")
+
+
+def test_composite_loss_gradient_fwdbwd128(fmb):
+    """The fwdbwd128 workload (N = 40, 20 views of 128 x 128) with the compositing model: every
+    ray's forward outputs, and the gradient of the workload loss (alpha-weighted L1 depth + BCE
+    alpha against targets rendered from the perturbed scene by the oracle)."""
+    w = W.make_config("fwdbwd128")
+    sc, cams = w.scenes[0], w.cameras[0]
+    _say("[composite-loss] fwdbwd128")
+    scene, _ = _composite_scene(fmb, sc, cams)
+    outs = scene.render(normals=True)
+    ref, _, _ = O.render_workload_view(sc, cams, w.betas, w.eta, model="composite")
+    tgt, _, _ = O.render_workload_view(w.targets[0], cams, w.betas, w.eta, model="composite")
+    p = cams.n_rays
+    gd = tgt["alpha"] * np.sign(ref["depth"] - tgt["depth"]) / p
+    a = np.clip(ref["alpha"], 1e-6, 1 - 1e-6)
+    inside = (ref["alpha"] >= 1e-6) & (ref["alpha"] <= 1 - 1e-6)
+    ga = np.where(inside, (a - tgt["alpha"]) / (a * (1 - a)), 0.0) / p
+    cot = {"depth": gd.astype(np.float32), "alpha": ga.astype(np.float32), "normal": None, "flow": None}
+    g = scene.backward(outs, _t(cot["depth"]), _t(cot["alpha"]))
+    torch.cuda.synchronize()
+    _, gref, _ = O.render_workload_view(sc, cams, w.betas, w.eta, cot=cot, model="composite")
+    e, eg = compare_forward(outs, ref), compare_grads(g, gref)
+    _say(f"[composite-loss] {e} {eg}")
+    assert_forward(e, "fwdbwd128 composite")
+    assert_grads(eg, "fwdbwd128 composite loss")
+
+
+def test_composite_batch(fmb):
+    """Batched compositing: scenes that all fit one Gaussian per lane match their single-scene
+    renders bit for bit; a batch mixing one and two Gaussians per lane matches the oracle."""
+    w = W.make_config("batch16")
+    for idx, exact in (([2, 8, 10], True), ([1, 12, 3], False)):
+        scenes = [w.scenes[i] for i in idx]
+        camsl = [w.cameras[i] for i in idx]
+        ns = [s.n for s in scenes]
+        assert exact == (max(ns) <= 64), ns
+        means = _t(np.concatenate([s.means for s in scenes]))
+        prec = _t(np.concatenate([s.prec for s in scenes]))
+        weights = _t(np.concatenate([s.weights for s in scenes]))
+        betas = _t(np.tile(w.betas, (len(scenes), 1)))
+        cams = [fmb.Cameras.from_numpy(c.w2c, c.intr, c.hw, device=DEV) for c in camsl]
+        b = fmb.Batch(means, prec, weights, betas, [w.eta] * len(scenes), ns, cams)
+        b.set_model("composite")
+        _say(f"[composite-batch] scenes {idx} N={ns} P={b.n_rays}")
+        outs = b.forward(b.alloc_outputs(normals=True))
+        gc = W.random_cotangents(b.n_rays, 21, flow=False)
+        cot = {"depth": _t(gc["depth"]), "alpha": _t(gc["alpha"]), "normal": _t(gc["normal"]), "flow": None}
+        grads = b.backward(outs, cot, b.alloc_grads())
+        torch.cuda.synchronize()
+        for i in range(len(scenes)):
+            r0, r1 = b.ray_off[i], b.ray_off[i + 1]
+            g0, g1 = b.gauss_off[i], b.gauss_off[i + 1]
+            if exact:
+                scene = fmb.Scene(means[g0:g1], prec[g0:g1], weights[g0:g1], betas[i], w.eta, cams[i])
+                scene.set_model("composite")
+                so = scene.render(normals=True)
+                sg = scene.backward(so, cot["depth"][r0:r1], cot["alpha"][r0:r1], cot["normal"][r0:r1])
+                torch.cuda.synchronize()
+                for k in ("depth", "alpha", "normal", "stash"):
+                    assert torch.equal(outs[k][r0:r1], so[k]), (idx, i, k)
+                for k in ("means", "prec", "weights"):
+                    assert torch.equal(grads[k][g0:g1], sg[k]), (idx, i, k)
+            else:
+                ref, _, _ = O.render_workload_view(scenes[i], camsl[i], w.betas, w.eta, model="composite")
+                e = compare_forward({k: v[r0:r1] if v is not None else None for k, v in outs.items()}, ref)
+                _say(f"[composite-batch] scene {idx[i]} N={ns[i]} {e}")
+                assert_forward(e, f"batch scene {idx[i]}")
+
+
+def test_composite_model_switch(fmb):
+    """Switching a scene between the two models gives each model's own result, and the
+    compositing model rejects scenes of more than 256 Gaussians."""
+    sc, cams = custom_scene(20, [(16, 16)], seed=3)
+    scene, _ = make_scene(fmb, torch, sc, cams, BETAS, 1.0, DEV)
+    blend1 = scene.render(normals=False)["depth"].clone()
+    scene.set_model("composite")
+    comp = scene.render(normals=False)["depth"].clone()
+    scene.set_model("blend")
+    blend2 = scene.render(normals=False)["depth"].clone()
+    torch.cuda.synchronize()
+    assert torch.equal(blend1, blend2)
+    assert not torch.equal(blend1, comp)
+    big, bcams = custom_scene(257, [(4, 4)], seed=4)
+    bscene, _ = make_scene(fmb, torch, big, bcams, BETAS, 1.0, DEV)
+    with pytest.raises(fmb.FmbError):
+        bscene.set_model("composite")

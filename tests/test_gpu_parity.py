@@ -17,7 +17,7 @@ import pytest
 import oracle as O
 import workloads as W
 from tests.gpu_util import (TOL_ALPHA, TOL_GRAD, TOL_REL, assert_forward, assert_grads, compare_forward,
-                            compare_grads, make_scene, maxabs, normwise, to_np)
+                            compare_grads, custom_scene, hit_mask_cot, make_scene, maxabs, normwise, to_np)
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -95,29 +95,6 @@ def test_backward_parity(fmb, name, sample):
 # Ragged and degenerate cases
 # ---------------------------------------------------------------------------------------
 
-def _custom(n, views, seed, behind=False, flow=False, s_range=(0.05, 0.2)):
-    g = np.random.Generator(np.random.PCG64(seed))
-    means = g.uniform(-1, 1, (n, 3))
-    if behind:
-        means[: n // 3, 2] = g.uniform(-6, -3.5, n // 3)  # behind the front camera at z = -3
-    sc = W.make_scene(g, n, means, log_s_range=s_range)
-    e, k, hw = [], [], []
-    for i, (h, wd) in enumerate(views):
-        if i == 0:
-            e.append(np.concatenate([np.eye(3), [[0.0], [0.0], [3.0]]], axis=1))
-        else:
-            e.append(W.look_at(3.0 * W.fibonacci_sphere(len(views))[i]))
-        k.append([float(h), float(h), wd / 2.0, h / 2.0])
-        hw.append([h, wd])
-    e = np.array(e, np.float32)
-    cams = W.Cameras(e, np.array(k, np.float32), np.array(hw, np.int32))
-    if flow:
-        eb = e.copy()
-        eb[:, :, 3] += np.array([0.03, -0.02, 0.01], np.float32)
-        cams.w2c_b, cams.intr_b = eb, cams.intr.copy()
-    return sc, cams
-
-
 RAGGED = [
     ("n1_1x1", 1, [(1, 1)]),
     ("n1_odd", 1, [(17, 23)]),
@@ -128,30 +105,15 @@ RAGGED = [
 ]
 
 
-def _hit_mask_cot(cot, alpha_ref, thr=1e-3):
-    """Depth/normal/flow/colour cotangents only on rays that see the scene (oracle alpha >= thr); the
-    alpha cotangent everywhere.  Over background rays the blend weights are decided by
-    log-density differences of order 1e4 that FP32 cannot resolve (see
-    test_background_rays_conditioning)."""
-    keep = alpha_ref >= thr
-    out = {}
-    for k, v in cot.items():
-        if v is None or k == "alpha":
-            out[k] = v
-        else:
-            out[k] = (v * keep.reshape(-1, *([1] * (v.ndim - 1)))).astype(np.float32)
-    return out
-
-
 @pytest.mark.parametrize("label,n,views", RAGGED, ids=[r[0] for r in RAGGED])
 def test_ragged_parity(fmb, label, n, views):
-    sc, cams = _custom(n, views, seed=n, flow=True)
+    sc, cams = custom_scene(n, views, seed=n, flow=True)
     betas = np.array([W.BETA1, W.BETA2], np.float32)
     _say(f"[ragged] {label}: N={n} views={views}")
     scene, _ = make_scene(fmb, torch, sc, cams, betas, 1.0, DEV)
     outs = scene.render(normals=True)
     ref, _, _ = O.render_workload_view(sc, cams, betas, 1.0)
-    cot = _hit_mask_cot(W.random_cotangents(cams.n_rays, 5, flow=True), ref["alpha"])
+    cot = hit_mask_cot(W.random_cotangents(cams.n_rays, 5, flow=True), ref["alpha"])
     t = lambda a: torch.as_tensor(a, device=DEV).contiguous()  # noqa: E731
     g = scene.backward(outs, t(cot["depth"]), t(cot["alpha"]), t(cot["normal"]), t(cot["flow"]))
     torch.cuda.synchronize()
@@ -170,7 +132,7 @@ def test_background_rays_conditioning(fmb):
     weights of Eq. (7) depend on differences of such values.  The kernels hold d in FP32, whose
     rounding (|d| 2^-24) is larger than a one-ulp change of the inputs by about |d| / |x|, so the
     bound is ten times the measured one-ulp sensitivity (and never below the 1e-3 contract)."""
-    sc, cams = _custom(7, [(5, 3), (64, 64), (1, 1), (33, 65)], seed=7, flow=True)
+    sc, cams = custom_scene(7, [(5, 3), (64, 64), (1, 1), (33, 65)], seed=7, flow=True)
     betas = np.array([W.BETA1, W.BETA2], np.float32)
     _say("[background] N=7 sparse scene, unmasked cotangents")
     scene, _ = make_scene(fmb, torch, sc, cams, betas, 1.0, DEV)
@@ -223,13 +185,13 @@ def test_loss_gradient_parity(fmb):
 def test_behind_camera_and_eta(fmb):
     """Gaussians behind the camera (t < 0) are blended like any other (Eq. 7 without clamp);
     a non-unit eta rescales the depth term."""
-    sc, cams = _custom(30, [(48, 40)], seed=3, behind=True)
+    sc, cams = custom_scene(30, [(48, 40)], seed=3, behind=True)
     betas = np.array([W.BETA1 * 0.5, W.BETA2], np.float32)
     _say("[behind] N=30, 48x40, eta=2.5")
     scene, _ = make_scene(fmb, torch, sc, cams, betas, 2.5, DEV)
     outs = scene.render(normals=True)
     ref, _, _ = O.render_workload_view(sc, cams, betas, 2.5)
-    cot = _hit_mask_cot(W.random_cotangents(cams.n_rays, 9, flow=False), ref["alpha"])
+    cot = hit_mask_cot(W.random_cotangents(cams.n_rays, 9, flow=False), ref["alpha"])
     t = lambda a: torch.as_tensor(a, device=DEV).contiguous()  # noqa: E731
     g = scene.backward(outs, t(cot["depth"]), t(cot["alpha"]), t(cot["normal"]))
     torch.cuda.synchronize()
@@ -239,7 +201,7 @@ def test_behind_camera_and_eta(fmb):
 
 
 def test_flow_equal_poses_is_zero(fmb):
-    sc, cams = _custom(20, [(32, 48), (16, 16)], seed=4)
+    sc, cams = custom_scene(20, [(32, 48), (16, 16)], seed=4)
     cams.w2c_b, cams.intr_b = cams.w2c.copy(), cams.intr.copy()
     betas = np.array([W.BETA1, W.BETA2], np.float32)
     _say("[flow0] equal poses")
@@ -268,7 +230,7 @@ def test_alpha_interop_value(fmb):
 
 
 def test_validate_flags(fmb):
-    sc, cams = _custom(8, [(8, 8)], seed=6)
+    sc, cams = custom_scene(8, [(8, 8)], seed=6)
     betas = np.array([W.BETA1, W.BETA2], np.float32)
     _say("[validate]")
     scene, (m, p, wt, b) = make_scene(fmb, torch, sc, cams, betas, 1.0, DEV)
@@ -372,7 +334,7 @@ def test_explicit_ray_minibatch(fmb):
     osc = O.OracleScene.of(sc.means, sc.prec, sc.weights, w.betas, w.eta)
     kw = dict(view=views, w2c_a=cams.w2c, intr_a=cams.intr, w2c_b=cams.w2c_b, intr_b=cams.intr_b)
     ref = O.render(osc, o, v, **kw)
-    cot = _hit_mask_cot(W.random_cotangents(p, 12, flow=True), ref["alpha"])
+    cot = hit_mask_cot(W.random_cotangents(p, 12, flow=True), ref["alpha"])
     gr = scene.backward(outs, t(cot["depth"]), t(cot["alpha"]), t(cot["normal"]), t(cot["flow"]))
     torch.cuda.synchronize()
     gref = O.backward(osc, o, v, cot, **kw)
@@ -399,7 +361,7 @@ def test_colour_parity(fmb):
     ref, _, _ = O.render_workload_view(sc, cams, w.betas, w.eta, colors=q)
     e = compare_forward(outs, ref)
     e["color"] = normwise(to_np(outs["color"]), ref["color"])
-    cot = _hit_mask_cot(W.random_cotangents(cams.n_rays, 31, flow=False), ref["alpha"])
+    cot = hit_mask_cot(W.random_cotangents(cams.n_rays, 31, flow=False), ref["alpha"])
     cot["color"] = (g.standard_normal((cams.n_rays, 3)) * (ref["alpha"] >= 1e-3)[:, None]).astype(np.float32)
     gr = scene.backward(outs, t(cot["depth"]), t(cot["alpha"]), t(cot["normal"]), None, g_color=t(cot["color"]))
     torch.cuda.synchronize()
@@ -458,7 +420,7 @@ def test_two_way_flow_and_quality(fmb):
     """Forward and backward flow per ray (Sec. 5) and the direct-intersection quality max_i w_i
     (Sec. 6, read from the stash) against the oracle; the 4-column loss kernel; and the batched
     path with a third pose equal to the per-scene path bit for bit."""
-    sc, cams = _custom(40, [(48, 64), (33, 17), (1, 5)], seed=44, flow=True)
+    sc, cams = custom_scene(40, [(48, 64), (33, 17), (1, 5)], seed=44, flow=True)
     cams = W.with_backward_flow(cams, seed=45)
     betas = np.array([W.BETA1, W.BETA2], np.float32)
     _say(f"[two-way] N=40 P={cams.n_rays}")
@@ -479,7 +441,7 @@ def test_two_way_flow_and_quality(fmb):
     hit = ref["alpha"][rs] >= 1e-3
     assert hit.sum() >= 100
     e["quality"] = float(np.max(np.abs(q - q_ref)[hit]))
-    cot = _hit_mask_cot(W.random_cotangents(cams.n_rays, 47, flow=True), ref["alpha"])
+    cot = hit_mask_cot(W.random_cotangents(cams.n_rays, 47, flow=True), ref["alpha"])
     g = np.random.Generator(np.random.PCG64(48))
     cot["flow"] = (g.standard_normal((cams.n_rays, 4)) * (ref["alpha"] >= 1e-3)[:, None]).astype(np.float32)
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=DEV).contiguous()  # noqa: E731
