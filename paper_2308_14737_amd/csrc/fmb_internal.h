@@ -18,6 +18,10 @@ namespace fmb {
 constexpr double kLog2e = 1.4426950408889634073599246810019;
 // 0/0 guard of every vector normalisation: |y| is sqrt(y.y + kEpsN).
 constexpr float kEpsN = 1e-30f;
+// Base-2 log of the smallest blend weight (relative to the ray's running maximum) that the
+// kernels evaluate: 2^-150 is below half of FP32's smallest subnormal, so such a weight is
+// exactly zero and its terms are skipped.
+constexpr float kSkipLog2 = -150.0f;
 
 struct ViewRec {       // one per view of the batch
     int32_t h, w;      // image size (explicit rays: h = ray count, w = 1)
