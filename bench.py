@@ -35,6 +35,12 @@ FLOPS_FWD_NORMALS = 76     # intersection, density, weight, online blend, normal
 FLOPS_FWD_PLAIN = 54       # without the normal terms
 FLOPS_ADJ_NORMALS = 92     # adjoint with a normal cotangent
 FLOPS_ADJ_PLAIN = 61       # adjoint of depth/alpha/flow cotangents only
+# Zero-parameter (alpha-compositing) kernels: per pair the same geometry as the blend model up
+# to the density, the log opacity log(1 - exp(-delta)) instead of the blend exponent, and the
+# sum over the Gaussians in front (compare + add for each of the scene's N Gaussians, 2N); the
+# backward adds the sum over the Gaussians behind (another 2N) and the opacity slope.
+FLOPS_COMP_FWD_NORMALS = 81   # + 2N per pair
+FLOPS_COMP_ADJ_PLAIN = 73     # + 2N per pair (the front sum is recomputation, not counted)
 PEAK_FP32 = 157.3e12       # MI355X FP32 vector peak (packed FP32 at 2.4 GHz x 256 CUs)
 PEAK_FP32_SCALAR = 78.6e12  # without packed FP32 issue
 PEAK_HBM = 8.0e12
@@ -70,6 +76,8 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches only")
+    ap.add_argument("--no-composite", action="store_true",
+                    help="skip the alpha-compositing (zero-parameter) leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after timing, copy a 256 MiB buffer once (a kernel of known traffic for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -230,6 +238,36 @@ def main():
         plain_ms = timed(step_plain, args.steps) * 1e3
         print(f"# plain step {plain_ms:.3f} ms", file=sys.stderr, flush=True)
 
+    launch = fmb.launch_config(batch=batch)
+    # the zero-parameter renderer on the same batch: eager step, HIP-event kernel times
+    comp = None
+    if not args.no_composite:
+        batch.set_model("composite")
+        for _ in range(args.warmup):
+            step_eager()
+        fmb.timing_enable(True)
+        fmb.kernel_times(reset=True)
+        ms_comp = timed(step_eager, args.steps) * 1e3
+        kc = fmb.kernel_times(reset=True)
+        fmb.timing_enable(False)
+        batch.set_model("blend")
+        cf = kc["fwd_ms"] / max(kc["n_fwd"], 1)
+        cb = kc["bwd_ms"] / max(kc["n_bwd"], 1)
+        cfin = kc["fin_ms"] / max(kc["n_fin"], 1)
+        nsq = sum(c.n_rays * s.n * s.n for s, c in zip(w.scenes, w.cameras))  # sum over rays of N^2
+        fl_f = pairs * FLOPS_COMP_FWD_NORMALS + 2 * nsq
+        fl_b = pairs * FLOPS_COMP_ADJ_PLAIN + 2 * nsq
+        comp = {"value": pairs / (ms_comp * 1e-3), "unit": "pairs/s", "ms_per_step": ms_comp,
+                "timed": "eager launches",
+                "kernel_ms": {"forward": cf, "backward": cb, "finalize": cfin},
+                "forward_tflops": fl_f / (cf * 1e-3) / 1e12, "backward_tflops": fl_b / (cb * 1e-3) / 1e12,
+                "forward_frac": fl_f / (cf * 1e-3) / PEAK_FP32, "backward_frac": fl_b / (cb * 1e-3) / PEAK_FP32,
+                "flops_per_pair": {"forward": f"{FLOPS_COMP_FWD_NORMALS} + 2N",
+                                   "backward": f"{FLOPS_COMP_ADJ_PLAIN} + 2N"},
+                "over_blend": ms_comp / ms_eager}
+        print(f"# composite step {ms_comp:.3f} ms; kernels fwd {cf:.3f} bwd {cb:.3f} fin {cfin:.3f} ms",
+              file=sys.stderr, flush=True)
+
     if args.calibrate_copy:
         # Kernels of known HBM traffic for scaling FETCH_SIZE / WRITE_SIZE: a 1 GiB device copy
         # (the runtime's blit kernel) and a 1 GiB elementwise copy (dst = src + 1, plain
@@ -269,7 +307,8 @@ def main():
         "timed": "graph replays" if ms_graph is not None else "eager launches",
         "fp32_peak_frac_step": step_flops / (ms_step * 1e-3) / PEAK_FP32,
         "kernel_ms": {"forward": fwd_ms, "backward": bwd_ms, "finalize": fin_ms},
-        "launch": fmb.launch_config(batch=batch),
+        "launch": launch,
+        "composite": comp,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": measured_traffic(),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",

@@ -272,10 +272,19 @@ int fmb_loss_grad(int64_t p, const float *depth, const float *alpha, const float
                   int32_t flow_norm, int32_t flow_cols, float w_color, float *g_depth, float *g_alpha,
                   float *g_flow, float *g_color, float *block_loss, void *stream);
 
+/* Pin the launch configuration of a scene or batch (exactly one non-NULL) instead of
+ * autotuning it: forward variant in [0, 4), backward variant in [0, 6) (see
+ * fmb_get_config), persistent-grid multipliers 1 or 2.  Every variant computes the same
+ * results to rounding; captured graphs are dropped.  Errors: FMB_ERR_INVALID_ARG. */
+int fmb_set_config(fmb_scene *scene, fmb_batch *batch, int32_t fwd_variant, int32_t bwd_variant,
+                   int32_t fwd_grid_mult, int32_t bwd_grid_mult);
+
 /* Current launch configuration of a scene or batch (exactly one non-NULL), written to the
  * host array out[8]: forward tile variant, rays per forward work item, backward variant,
- * rays per backward LDS tile, forward and backward persistent-grid multipliers, and the
- * forward and backward work-item counts (0 until the first call built them). */
+ * rays per backward tile (staged in LDS for variants 0-2, which give each lane a Gaussian;
+ * held by the block's lanes for variants 3-5, which give each lane rays as the forward pass
+ * does), forward and backward persistent-grid multipliers, and the forward and backward
+ * work-item counts (0 until the first call built them). */
 int fmb_get_config(const fmb_scene *scene, const fmb_batch *batch, int32_t *out);
 
 /* Check the scene's parameters on the device: writes to *bad_host a bit mask of

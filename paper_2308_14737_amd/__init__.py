@@ -12,6 +12,8 @@ from ._lib import FmbError  # noqa: F401
 
 _lib.load()
 
-from .render import Batch, Cameras, Scene, kernel_times, launch_config, loss_grad, render, timing_enable  # noqa: E402,F401
+from .render import (Batch, Cameras, Scene, kernel_times, launch_config, loss_grad, render,  # noqa: E402,F401
+                     set_launch_config, timing_enable)
 
-__all__ = ["Batch", "Cameras", "FmbError", "Scene", "kernel_times", "launch_config", "loss_grad", "render", "timing_enable"]
+__all__ = ["Batch", "Cameras", "FmbError", "Scene", "kernel_times", "launch_config", "loss_grad", "render",
+           "set_launch_config", "timing_enable"]

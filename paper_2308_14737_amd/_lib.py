@@ -34,6 +34,7 @@ SIGNATURES = {
     "fmb_set_colors": (_int, [_vp, _vp, _vp]),
     "fmb_set_flow_pose2": (_int, [_vp, _vp, _vp, _vp]),
     "fmb_set_model": (_int, [_vp, _vp, _i32]),
+    "fmb_set_config": (_int, [_vp, _vp, _i32, _i32, _i32, _i32]),
     "fmb_render": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fmb_backward": (_int, [_vp] + [_vp] * 13 + [_vp]),
     "fmb_batch_create": (_int, [ctypes.POINTER(_vp), _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,

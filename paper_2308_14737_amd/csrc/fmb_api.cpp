@@ -27,6 +27,7 @@ int num_fwd_variants();
 int fwd_variant_rays(int v);
 int num_bwd_variants();
 int bwd_variant_rt(int v);
+int bwd_variant_ray_tile(int v);
 int block_size();
 hipError_t launch_fwd(int variant, int flags, int grid, hipStream_t st, const Params &P, const FwdOut &O,
                       const FwdItem *items, int n, const int *order, int *counter);
@@ -323,6 +324,7 @@ struct Job {
         const bool comp = model == FMB_MODEL_COMPOSITE;
         const int rec = colour ? kPartialColor : kPartial;
         const int RT = bwd_variant_rt(variant);
+        const int ray_tile = comp ? 0 : bwd_variant_ray_tile(variant);
         const int B = block_size();
         std::vector<int> gcs(S), sls(S), spans(S), min_span(S);
         for (int s = 0; s < S; ++s) {
@@ -332,6 +334,12 @@ struct Job {
                 sls[s] = 1;
                 min_span[s] = 4 * (64 / comp_seg(scenes[s].n));
                 spans[s] = 16 * min_span[s];
+            } else if (ray_tile > 0) {
+                // ray-lane kernel: the whole scene per item, two ray tiles per item to start
+                gcs[s] = scenes[s].n;
+                sls[s] = 1;
+                min_span[s] = ray_tile;
+                spans[s] = 2 * ray_tile;
             } else {
                 chunking(scenes[s].n, B, gcs[s], sls[s]);
                 min_span[s] = RT;
@@ -969,6 +977,24 @@ int fmb_validate(fmb_scene *s, int32_t *bad_host, void *stream)
     return rc;
 }
 
+int fmb_set_config(fmb_scene *s, fmb_batch *b, int32_t fwd_variant, int32_t bwd_variant, int32_t fwd_grid_mult,
+                   int32_t bwd_grid_mult)
+{
+    g_err.clear();
+    CHECK_ARG((s != nullptr) != (b != nullptr), "exactly one of scene and batch must be given");
+    CHECK_ARG(fwd_variant >= 0 && fwd_variant < num_fwd_variants(), "forward variant out of range");
+    CHECK_ARG(bwd_variant >= 0 && bwd_variant < num_bwd_variants(), "backward variant out of range");
+    CHECK_ARG(fwd_grid_mult >= 1 && fwd_grid_mult <= 2 && bwd_grid_mult >= 1 && bwd_grid_mult <= 2,
+              "grid multipliers must be 1 or 2");
+    Job &j = s ? s->job : b->job;
+    j.fwd_variant = fwd_variant;
+    j.bwd_variant = bwd_variant;
+    j.persist_mult[0] = fwd_grid_mult;
+    j.persist_mult[1] = bwd_grid_mult;
+    j.drop_graphs();
+    return FMB_OK;
+}
+
 int fmb_get_config(const fmb_scene *s, const fmb_batch *b, int32_t *out)
 {
     g_err.clear();
@@ -978,7 +1004,7 @@ int fmb_get_config(const fmb_scene *s, const fmb_batch *b, int32_t *out)
     out[0] = j.fwd_variant;
     out[1] = fwd_variant_rays(j.fwd_variant);
     out[2] = j.bwd_variant;
-    out[3] = bwd_variant_rt(j.bwd_variant);
+    out[3] = bwd_variant_rt(j.bwd_variant) > 0 ? bwd_variant_rt(j.bwd_variant) : bwd_variant_ray_tile(j.bwd_variant);
     out[4] = j.persist_mult[0];
     out[5] = j.persist_mult[1];
     out[6] = j.fwd_built >= 0 ? j.n_fitems : 0;
@@ -1021,7 +1047,7 @@ static std::string tune_key(const Job &j, int fflags, int unused, int cot_mask)
     hipDeviceProp_t prop{};
     (void)hipGetDeviceProperties(&prop, j.device);
     std::ostringstream k;
-    k << prop.gcnArchName << ":cu" << j.n_cu << ":v4:S" << j.S << ":V" << j.V << ":P" << j.P << ":N" << j.n_total
+    k << prop.gcnArchName << ":cu" << j.n_cu << ":v5:S" << j.S << ":V" << j.V << ":P" << j.P << ":N" << j.n_total
       << ":out" << fflags << ":cot" << cot_mask;
     (void)unused;
     return k.str();

@@ -89,6 +89,10 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
                     Geo q;
                     pair_geo(g, v0[j], v1[j], v2[j], bl.hm, bl.b1, bl.nc2, q);
                     const float delta = exp2_(q.d2);
+                    D[j] += delta;
+                    // A weight below 2^-150 of the running maximum is zero in FP32: its terms are
+                    // skipped (the branch is uniform over a wave for most distant Gaussians).
+                    if (q.z2 - M[j] < kSkipLog2) continue;
                     if (q.z2 > M[j]) {  // new running maximum: rescale the sums (rare)
                         const float sc = exp2_(M[j] - q.z2);
                         S[j] *= sc;
@@ -108,7 +112,6 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
                     const float ew = exp2_(q.z2 - M[j]);
                     S[j] += ew;
                     T[j] = fmaf(ew, q.t, T[j]);
-                    D[j] += delta;
                     if (NORMALS) {
                         const float g0 = g.u00 * q.r0;
                         const float g1 = fmaf(g.u01, q.r0, g.u11 * q.r1);
@@ -275,6 +278,177 @@ __global__ __launch_bounds__(BLOCK) void bwd_kernel(Params P, BwdIn I, const Bwd
                 beta_partial[2 * item.seq] = s1;
                 beta_partial[2 * item.seq + 1] = s2;
             }
+        }
+        if (!PERSIST) break;
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// Backward, ray-lane layout: one lane per ray (RPT rays per lane) as in the forward pass,
+// the item's Gaussians staged through LDS in tiles of TG.  For each Gaussian the lanes'
+// terms are summed over the wave (butterfly) and the wave sums in LDS, over the item's ray
+// tiles, so an item writes one partial record per Gaussian of its scene.  A Gaussian whose
+// blend weight is exactly zero (below 2^-150 of the ray's maximum) on every ray of the wave
+// takes only the density term of alpha, and one whose density is zero too is skipped.
+// ------------------------------------------------------------------------------------
+
+__device__ __forceinline__ float wave_sum(float x)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+template <int BLOCK, int RPT, int TG, int F>
+__global__ __launch_bounds__(BLOCK) void bwdr_kernel(Params P, BwdIn I, const BwdItem *__restrict__ items,
+                                                    int n_items, const int *__restrict__ order,
+                                                    int *__restrict__ counter, float *__restrict__ partial,
+                                                    float *__restrict__ beta_partial)
+{
+    constexpr bool NORMALS = (F & kNrm) != 0, PERSIST = (F & kPer) != 0, COLOR = (F & kCol) != 0;
+    constexpr int EW = COLOR ? 5 : 4;                       // float4 per LDS entry
+    constexpr int REC = COLOR ? kPartialColor : kPartial;  // partial record per Gaussian
+    constexpr int NW = BLOCK / 64;
+    __shared__ float4 tile[TG * EW];
+    __shared__ float wsum[NW * TG * REC];   // per wave, per Gaussian of the tile
+    __shared__ float bsum[NW * 2];
+    __shared__ int s_item;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int pos = blockIdx.x;
+    for (;;) {
+        if (PERSIST) {
+            __syncthreads();
+            if (tid == 0) s_item = atomicAdd(counter, 1);
+            __syncthreads();
+            pos = s_item;
+        }
+        if (pos >= n_items) break;
+        const int it = order ? order[pos] : pos;
+        const BwdItem item = items[it];
+        const ViewRec vr = P.views[item.view];
+        const SceneRec sr = P.scenes[vr.scene];
+        const float *__restrict__ e = P.w2c + 12 * item.view;
+        const float *__restrict__ kk = P.intr + 4 * item.view;
+        double o[3];
+        cam_centre(e, o);
+        const float o0 = (float)o[0], o1 = (float)o[1], o2 = (float)o[2];
+        const Blend bl = blend_of(P, vr.scene);
+        const int hw = vr.h * vr.w;
+        const int end = min(item.ray0 + item.span, hw);
+        float aB1 = 0.0f, aB2 = 0.0f;
+
+        for (int gb = 0; gb < sr.n; gb += TG) {
+            const int cnt = min(TG, sr.n - gb);
+            __syncthreads();  // the previous tile's entries and sums are no longer read
+            for (int q = tid; q < cnt; q += BLOCK) {
+                const int gi = sr.gauss_off + gb + q;
+                make_entry(P.means + 3 * gi, P.prec + 6 * gi, P.weights[gi], o, &tile[EW * q]);
+                if (COLOR) tile[EW * q + 4] = colour_entry(P.colors + 3 * gi);
+            }
+            for (int q = tid; q < NW * TG * REC; q += BLOCK) wsum[q] = 0.0f;
+            __syncthreads();
+            for (int rb = item.ray0; rb < end; rb += BLOCK * RPT) {
+                float4 x0[RPT], x1[RPT], x2[RPT], x3[RPT];
+#pragma unroll
+                for (int j = 0; j < RPT; ++j) {
+                    const int local = rb + tid + j * BLOCK;
+                    float4 pr[4];
+                    ray_prologue<F>(P, I, item.view, vr, e, kk, o0, o1, o2, local, local < end, pr);
+                    x0[j] = pr[0];
+                    x1[j] = pr[1];
+                    x2[j] = pr[2];
+                    x3[j] = pr[3];
+                }
+                for (int i = 0; i < cnt; ++i) {
+                    const Ent g = ent_from(tile[EW * i], tile[EW * i + 1], tile[EW * i + 2], tile[EW * i + 3]);
+                    float4 cc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                    if (COLOR) cc = tile[EW * i + 4];
+                    Geo q[RPT];
+                    float delta[RPT], wt[RPT];
+                    bool need_w = false, need_d = false;
+#pragma unroll
+                    for (int j = 0; j < RPT; ++j) {
+                        pair_geo(g, x0[j].x, x0[j].y, x0[j].z, bl.hm, bl.b1, bl.nc2, q[j]);
+                        delta[j] = exp2_(q[j].d2);
+                        const bool w_on = q[j].z2 - x0[j].w >= kSkipLog2;
+                        wt[j] = w_on ? exp2_(q[j].z2 - x0[j].w) * x1[j].x : 0.0f;
+                        need_w |= w_on;
+                        need_d |= x2[j].z * delta[j] != 0.0f;
+                    }
+                    PairAcc a;
+                    float aC0 = 0.0f, aC1 = 0.0f, aC2 = 0.0f;
+                    if (__any(need_w)) {
+#pragma unroll
+                        for (int j = 0; j < RPT; ++j) {
+                            const float tfb = x1[j].y;
+                            PairNormal pn{0, 0, 0, 0, 0};
+                            if (NORMALS) pn = pair_normal(g, q[j], x1[j].z, x1[j].w, x2[j].x);
+                            float lin = fmaf(tfb, q[j].t, pn.nN);
+                            if (COLOR) {
+                                lin = fmaf(x3[j].x, cc.x, fmaf(x3[j].y, cc.y, fmaf(x3[j].z, cc.z, lin)));
+                                aC0 = fmaf(wt[j], x3[j].x, aC0);
+                                aC1 = fmaf(wt[j], x3[j].y, aC1);
+                                aC2 = fmaf(wt[j], x3[j].z, aC2);
+                            }
+                            const float zb = wt[j] * (lin - x2[j].y);
+                            const float tb = fmaf(-bl.cb, zb, wt[j] * tfb);
+                            const float db = fmaf(bl.b1, zb, x2[j].z * delta[j]);
+                            aB1 = fmaf(zb, q[j].d2, aB1);
+                            aB2 = fmaf(zb, q[j].t, aB2);
+                            pair_adjoint<NORMALS>(g, q[j], x0[j].x, x0[j].y, x0[j].z, wt[j], pn, x1[j].z, x1[j].w,
+                                                  x2[j].x, tb, db, a);
+                        }
+                    } else if (__any(need_d)) {
+                        // zero weight on every ray of the wave: only d(alpha)/d(delta) remains
+#pragma unroll
+                        for (int j = 0; j < RPT; ++j) {
+                            const PairNormal pn{0, 0, 0, 0, 0};
+                            pair_adjoint<false>(g, q[j], x0[j].x, x0[j].y, x0[j].z, 0.0f, pn, 0.0f, 0.0f, 0.0f,
+                                                0.0f, x2[j].z * delta[j], a);
+                        }
+                    } else {
+                        continue;  // no term of this Gaussian on this wave's rays
+                    }
+                    float v[REC];
+                    v[0] = a.u0; v[1] = a.u1; v[2] = a.u2; v[3] = a.u3; v[4] = a.u4; v[5] = a.u5;
+                    v[6] = a.p0; v[7] = a.p1; v[8] = a.p2; v[9] = a.l;
+                    if (COLOR) {
+                        v[10] = aC0; v[11] = aC1; v[12] = aC2;
+                    }
+#pragma unroll
+                    for (int c = 0; c < REC; ++c) v[c] = wave_sum(v[c]);
+                    if (lane == 0) {
+                        float *dst = wsum + (wave * TG + i) * REC;
+#pragma unroll
+                        for (int c = 0; c < REC; ++c) dst[c] += v[c];
+                    }
+                }
+            }
+            __syncthreads();
+            // the tile's partial records: waves summed in order, -(sum rho) mu'^T applied in double
+            for (int q = tid; q < cnt; q += BLOCK) {
+                float sum[REC];
+#pragma unroll
+                for (int c = 0; c < REC; ++c) sum[c] = wsum[q * REC + c];
+                for (int w = 1; w < NW; ++w) {
+#pragma unroll
+                    for (int c = 0; c < REC; ++c) sum[c] += wsum[(w * TG + q) * REC + c];
+                }
+                write_partial(partial + item.poff + REC * (gb + q), sum, REC, P.means + 3 * (sr.gauss_off + gb + q), o);
+            }
+        }
+        // betas: lanes summed over the wave, then the waves in order
+        aB1 = wave_sum(aB1);
+        aB2 = wave_sum(aB2);
+        if (lane == 0) {
+            bsum[2 * wave] = aB1;
+            bsum[2 * wave + 1] = aB2;
+        }
+        __syncthreads();
+        if (tid < 2) {
+            float sb = 0.0f;
+            for (int w = 0; w < NW; ++w) sb += bsum[2 * w + tid];
+            beta_partial[2 * item.seq + tid] = sb;
         }
         if (!PERSIST) break;
     }
@@ -497,7 +671,14 @@ struct FwdVariant {
     int rpt, tg;
 };
 static const FwdVariant kFwdVariants[] = {{1, 128}, {2, 128}, {2, 256}, {4, 128}};
+// Backward variants: 0-2 the Gaussian-lane kernel with RT rays staged per pass; 3-5 the
+// ray-lane kernel with (RPT rays per lane, TG Gaussians per tile).
 static const int kBwdRT[] = {64, 128, 256};
+struct BwdRayVariant {
+    int rpt, tg;
+};
+static const BwdRayVariant kBwdRay[] = {{2, 64}, {4, 64}, {4, 128}};
+constexpr int kNumBwdGauss = (int)(sizeof kBwdRT / sizeof kBwdRT[0]);
 
 // F dispatch: calls body<F>() for the runtime flag set f (0..15).
 #define FMB_DISPATCH_F(f, CALL)                                                                            \
@@ -521,6 +702,19 @@ static hipError_t launch_fwd_v(int f, int grid, hipStream_t st, const Params &P,
     return hipGetLastError();
 }
 
+template <int RPT, int TG>
+static hipError_t launch_bwdr_v(int f, int grid, hipStream_t st, const Params &P, const BwdIn &I,
+                                const BwdItem *items, int n, const int *order, int *counter, float *partial,
+                                float *bpart)
+{
+#define FMB_BWDR_CALL(F)                                                                                   \
+    hipLaunchKernelGGL((bwdr_kernel<kBlock, RPT, TG, F>), dim3(grid), dim3(kBlock), 0, st, P, I, items, n,      \
+                       order, counter, partial, bpart)
+    FMB_DISPATCH_F(f, FMB_BWDR_CALL)
+#undef FMB_BWDR_CALL
+    return hipGetLastError();
+}
+
 template <int RT>
 static hipError_t launch_bwd_v(int f, int grid, hipStream_t st, const Params &P, const BwdIn &I,
                                const BwdItem *items, int n, const int *order, int *counter, float *partial,
@@ -536,8 +730,11 @@ static hipError_t launch_bwd_v(int f, int grid, hipStream_t st, const Params &P,
 
 int num_fwd_variants() { return (int)(sizeof kFwdVariants / sizeof kFwdVariants[0]); }
 int fwd_variant_rays(int v) { return kBlock * kFwdVariants[v].rpt; }
-int num_bwd_variants() { return (int)(sizeof kBwdRT / sizeof kBwdRT[0]); }
-int bwd_variant_rt(int v) { return kBwdRT[v]; }
+int num_bwd_variants() { return kNumBwdGauss + (int)(sizeof kBwdRay / sizeof kBwdRay[0]); }
+// Gaussian-lane variants: rays staged per pass; ray-lane variants: 0.
+int bwd_variant_rt(int v) { return v < kNumBwdGauss ? kBwdRT[v] : 0; }
+// Ray-lane variants: rays per block tile (BLOCK * RPT); Gaussian-lane variants: 0.
+int bwd_variant_ray_tile(int v) { return v < kNumBwdGauss ? 0 : kBlock * kBwdRay[v - kNumBwdGauss].rpt; }
 int block_size() { return kBlock; }
 
 // flags: bit 0 normals, 1 flow, 2 persistent, 3 colour
@@ -560,6 +757,9 @@ hipError_t launch_bwd(int variant, int flags, int grid, hipStream_t st, const Pa
     case 0: return launch_bwd_v<64>(flags, grid, st, P, I, items, n, order, counter, partial, bpart);
     case 1: return launch_bwd_v<128>(flags, grid, st, P, I, items, n, order, counter, partial, bpart);
     case 2: return launch_bwd_v<256>(flags, grid, st, P, I, items, n, order, counter, partial, bpart);
+    case 3: return launch_bwdr_v<2, 64>(flags, grid, st, P, I, items, n, order, counter, partial, bpart);
+    case 4: return launch_bwdr_v<4, 64>(flags, grid, st, P, I, items, n, order, counter, partial, bpart);
+    case 5: return launch_bwdr_v<4, 128>(flags, grid, st, P, I, items, n, order, counter, partial, bpart);
     default: return hipErrorInvalidValue;
     }
 }
@@ -630,6 +830,20 @@ hipError_t occupancy_bwd(int variant, int flags, int *blocks_per_cu)
     case 0: FMB_OCC_V(64)
     case 1: FMB_OCC_V(128)
     case 2: FMB_OCC_V(256)
+    default: break;
+    }
+#undef FMB_OCC_V
+#undef FMB_OCC_F
+#define FMB_OCC_F(F) return occ(bwdr_kernel<kBlock, RPT, TG, F>, blocks_per_cu)
+#define FMB_OCC_V(RPT_, TG_)                                                                               \
+    {                                                                                                      \
+        constexpr int RPT = RPT_, TG = TG_;                                                                \
+        FMB_DISPATCH_F(flags, FMB_OCC_F)                                                                   \
+    }
+    switch (variant) {
+    case 3: FMB_OCC_V(2, 64)
+    case 4: FMB_OCC_V(4, 64)
+    case 5: FMB_OCC_V(4, 128)
     default: return hipErrorInvalidValue;
     }
 #undef FMB_OCC_V

@@ -400,6 +400,14 @@ class Batch:
             self._h = None
 
 
+def set_launch_config(scene: Optional["Scene"] = None, batch: Optional["Batch"] = None, fwd_variant: int = 3,
+                      bwd_variant: int = 2, fwd_grid_mult: int = 1, bwd_grid_mult: int = 1):
+    """Pin the tile variants and persistent-grid multipliers (see launch_config)."""
+    _lib.call("fmb_set_config", scene.handle if scene is not None else None,
+              batch._h if batch is not None else None, int(fwd_variant), int(bwd_variant), int(fwd_grid_mult),
+              int(bwd_grid_mult))
+
+
 def launch_config(scene: Optional["Scene"] = None, batch: Optional["Batch"] = None) -> dict:
     """Tile variants, persistent-grid multipliers and work-item counts in use."""
     out = (ctypes.c_int32 * 8)()

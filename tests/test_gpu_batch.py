@@ -142,3 +142,31 @@ def test_graph_replay(fmb, batch16):
         with torch.no_grad():
             means.add_(0.001)
             betas.mul_(1.01)
+
+
+@pytest.mark.parametrize("variant", [3, 5])
+def test_ray_lane_batch_bitwise(fmb, batch16, variant):
+    """The ray-lane backward kernels, batched and persistent, equal per-scene plain launches of
+    the same variant bit for bit (items are cut per scene)."""
+    w, b, params = batch16
+    fmb.set_launch_config(batch=b, bwd_variant=variant)
+    _say(f"[ray-lane] batch16 bwd variant {variant}")
+    outs = b.forward(b.alloc_outputs(normals=True))
+    cot = _cotangents(b, 23)
+    grads = b.backward(outs, cot, b.alloc_grads())
+    torch.cuda.synchronize()
+    means, prec, weights, betas = params  # the batch's current parameters (other tests update them)
+    for i in (0, 6, 8, 12):
+        cams = w.cameras[i]
+        r0, r1 = b.ray_off[i], b.ray_off[i + 1]
+        g0, g1 = b.gauss_off[i], b.gauss_off[i + 1]
+        scene = fmb.Scene(means[g0:g1], prec[g0:g1], weights[g0:g1], betas[i], w.eta,
+                          fmb.Cameras.from_numpy(cams.w2c, cams.intr, cams.hw, cams.w2c_b, cams.intr_b, device=DEV))
+        fmb.set_launch_config(scene=scene, bwd_variant=variant)
+        o = scene.render(normals=True)
+        gi = scene.backward(o, cot["depth"][r0:r1], cot["alpha"][r0:r1], cot["normal"][r0:r1])
+        torch.cuda.synchronize()
+        for k in ("means", "prec", "weights"):
+            assert torch.equal(gi[k], grads[k][g0:g1]), (i, k)
+        assert torch.equal(gi["betas"], grads["betas"][i]), (i, "betas")
+    fmb.set_launch_config(batch=b)

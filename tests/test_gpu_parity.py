@@ -472,3 +472,42 @@ def test_two_way_flow_and_quality(fmb):
     torch.cuda.synchronize()
     for k in ("depth", "alpha", "normal", "flow", "stash"):
         assert torch.equal(bo[k], outs[k]), k
+
+
+VARIANT_CASES = [
+    ("n7_multi", 7, [(5, 3), (64, 64), (1, 1), (33, 65)]),
+    ("n90", 90, [(37, 41)]),
+    ("n257", 257, [(40, 50), (3, 7)]),
+]
+
+
+@pytest.mark.parametrize("variant", range(6))
+@pytest.mark.parametrize("label,n,views", VARIANT_CASES, ids=[c[0] for c in VARIANT_CASES])
+def test_backward_variants(fmb, variant, label, n, views):
+    """Every backward variant (Gaussian-lane 0-2, ray-lane 3-5) against the oracle, with normal,
+    flow (both directions) and colour cotangents."""
+    sc, cams = custom_scene(n, views, seed=300 + n, flow=True)
+    cams = W.with_backward_flow(cams, seed=301)
+    g = np.random.Generator(np.random.PCG64(302))
+    q = (1.5 * g.standard_normal((sc.n, 3))).astype(np.float32)
+    _say(f"[variant] {label} bwd variant {variant}: N={n} views={views}")
+    scene, _ = make_scene(fmb, torch, sc, cams, np.array([W.BETA1, W.BETA2], np.float32), 1.0, DEV)
+    fmb.set_launch_config(scene=scene, bwd_variant=variant)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=DEV).contiguous()  # noqa: E731
+    scene.set_colors(t(q))
+    outs = scene.render(normals=True)
+    betas = np.array([W.BETA1, W.BETA2], np.float32)
+    ref, _, _ = O.render_workload_view(sc, cams, betas, 1.0, colors=q)
+    hit = ref["alpha"] >= 1e-3
+    cot = hit_mask_cot(W.random_cotangents(cams.n_rays, 303, flow=False), ref["alpha"])
+    cot["flow"] = (g.standard_normal((cams.n_rays, 4)) * hit[:, None]).astype(np.float32)
+    cot["color"] = (g.standard_normal((cams.n_rays, 3)) * hit[:, None]).astype(np.float32)
+    gr = scene.backward(outs, t(cot["depth"]), t(cot["alpha"]), t(cot["normal"]), t(cot["flow"]),
+                        g_color=t(cot["color"]))
+    torch.cuda.synchronize()
+    assert fmb.launch_config(scene=scene)["bwd_variant"] == variant
+    _, gref, _ = O.render_workload_view(sc, cams, betas, 1.0, cot=cot, colors=q)
+    eg = compare_grads(gr, gref)
+    eg["colors"] = normwise(to_np(gr["colors"]), gref["colors"])
+    _say(f"[variant] {label} v{variant}: {eg}")
+    assert_grads(eg, f"{label} variant {variant}")
