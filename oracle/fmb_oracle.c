@@ -603,3 +603,44 @@ int fmbo_backward(int32_t n, const double *means, const double *prec, const doub
                                intr_a, w2c_b, intr_b, g_depth, g_alpha, g_normal, g_flow, g_color,
                                g_means, g_prec, g_weights, g_colors, g_betas, n_threads);
 }
+
+/* Split statistic of Sec. 8: lbar_i = (1/p) sum_r loss_r w_ri over the p rays, with w_ri the
+ * normalised blend weights of Eq. (3) (model 0: Eq. 7; model 1: Eq. 9-10).  lbar: [n]. */
+int fmbo_split_statistic(int32_t model, int32_t n, const double *means, const double *prec,
+                         const double *weights, const double *betas, double eta, int64_t p,
+                         const double *orig, const double *dir, const double *loss, double *lbar,
+                         int n_threads)
+{
+    if (n < 1 || p < 1 || (model != 0 && model != 1) || !loss || !lbar) return -1;
+    gauss_t *g = (gauss_t *)malloc(sizeof(gauss_t) * (size_t)n);
+    if (!g) return -1;
+    load_gaussians(n, means, prec, weights, NULL, g);
+    ctx_t c = {n, model, g, betas[0], betas[1], eta, orig, dir, NULL, NULL, NULL, NULL, NULL};
+    int nt = nthreads_of(n_threads);
+    double *acc = (double *)calloc((size_t)nt * (size_t)n, sizeof(double));
+#pragma omp parallel num_threads(nt)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        int64_t lo = p * tid / nt, hi = p * (tid + 1) / nt;
+        pair_t *q = (pair_t *)malloc(sizeof(pair_t) * (size_t)n);
+        double *wt = (double *)malloc(sizeof(double) * (size_t)n);
+        ray_t ry;
+        for (int64_t r = lo; r < hi; ++r) {
+            ray_forward(&c, r, q, wt, &ry);
+            for (int32_t i = 0; i < n; ++i) acc[(size_t)tid * n + i] += loss[r] * wt[i];
+        }
+        free(q);
+        free(wt);
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int k = 0; k < nt; ++k) s += acc[(size_t)k * n + i];
+        lbar[i] = s / (double)p;
+    }
+    free(acc);
+    free(g);
+    return 0;
+}

@@ -57,6 +57,9 @@ def _configure(lib):
     lib.fmbo_ray_weights.argtypes = [ctypes.c_int32, ctypes.c_int32, _D, _D, _D, _D, ctypes.c_double,
                                      _D, _D, _D]
     lib.fmbo_ray_weights.restype = ctypes.c_int
+    lib.fmbo_split_statistic.argtypes = [ctypes.c_int32, ctypes.c_int32, _D, _D, _D, _D, ctypes.c_double,
+                                         ctypes.c_int64, _D, _D, _D, _D, ctypes.c_int]
+    lib.fmbo_split_statistic.restype = ctypes.c_int
     lib.fmbo_ray_terms.argtypes = [ctypes.c_int32, _D, _D, _D, _D, ctypes.c_double, _D, _D,
                                    _D, _D, _D, _D]
     return lib
@@ -260,6 +263,21 @@ def max_weight(scene: OracleScene, orig, dirs, model: str = "blend"):
     one call per ray."""
     orig, dirs = _d(orig).reshape(-1, 3), _d(dirs).reshape(-1, 3)
     return np.array([blend_weights(scene, orig[r], dirs[r], model).max() for r in range(orig.shape[0])])
+
+
+def split_statistic(scene: OracleScene, orig, dirs, loss, model: str = "blend", n_threads: int = 0):
+    """Average loss assigned to each Gaussian over a batch of M rays (Sec. 8):
+    lbar_i = (1/M) sum_j L_j w_ji with w_ji the normalised blend weights of ray j."""
+    lib = load()
+    orig, dirs = _d(orig).reshape(-1, 3), _d(dirs).reshape(-1, 3)
+    loss = _d(loss).reshape(-1)
+    out = np.empty(scene.n)
+    rc = lib.fmbo_split_statistic(_model(model), scene.n, _p(scene.means), _p(scene.prec), _p(scene.weights),
+                                  _p(scene.betas), scene.eta, orig.shape[0], _p(orig), _p(dirs), _p(loss),
+                                  _p(out), int(n_threads))
+    if rc != 0:
+        raise ValueError("oracle split_statistic rejected its arguments")
+    return out
 
 
 def ray_terms(scene: OracleScene, o, v):

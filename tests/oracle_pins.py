@@ -564,6 +564,45 @@ def pin_composite_gradients_fd():
 
 
 # ---------------------------------------------------------------------------------------
+# Split statistic (Sec. 8)
+# ---------------------------------------------------------------------------------------
+
+def pin_split_statistic():
+    """lbar_i = (1/M) sum_j L_j w_ji: the mean loss for one Gaussian; the weights of a ray sum to
+    one, so sum_i lbar_i = mean(L) for both models; equal weights (zero betas) give mean(L)/N; two
+    Gaussians follow the sigmoid of z_1 - z_2 (blend) and the front-to-back compositing weights
+    built from one-Gaussian renders (composite)."""
+    g = _rng(50)
+    o = np.array([0.2, -0.1, -3.0])
+    sc, _ = _random_scene(g, 5, spread=0.4)
+    orig, dirs = _rays_at(g, np.repeat(sc.means, 4, axis=0), o, jitter=0.2)
+    loss = g.uniform(0.0, 2.0, len(orig))
+    one = _scene(sc.means[[2]], sc.prec[[2]], sc.weights[[2]])
+    for model in ("blend", "composite"):
+        _close(O.split_statistic(one, orig, dirs, loss, model), [loss.mean()], 1e-14, 0.0, f"one Gaussian {model}")
+        _close([O.split_statistic(sc, orig, dirs, loss, model).sum()], [loss.mean()], 1e-12, 0.0,
+               f"weights sum to one ({model})")
+    flat = _scene(sc.means, sc.prec, sc.weights, betas=(0.0, 0.0))
+    _close(O.split_statistic(flat, orig, dirs, loss), np.full(sc.n, loss.mean() / sc.n), 1e-12, 0.0,
+           "zero betas")
+    two = _scene(sc.means[:2], sc.prec[:2], sc.weights[:2])
+    t1, d1, _ = _single_terms(two, 0, orig, dirs)
+    t2, d2, _ = _single_terms(two, 1, orig, dirs)
+    s1 = 1.0 / (1.0 + np.exp(-((B1 * d1 - B2 * t1) - (B1 * d2 - B2 * t2))))
+    _close(O.split_statistic(two, orig, dirs, loss), [np.mean(loss * s1), np.mean(loss * (1 - s1))],
+           1e-10, 1e-12, "two Gaussians (blend)")
+    t, delta, _ = _single_t_delta_n(two, orig, dirs)
+    w = np.empty_like(t)
+    for r in range(len(t)):
+        a, b = (0, 1) if t[r, 0] < t[r, 1] else (1, 0)
+        w[r, a] = -math.expm1(-delta[r, a])
+        w[r, b] = math.exp(-delta[r, a]) * -math.expm1(-delta[r, b])
+    w /= w.sum(axis=1, keepdims=True)
+    _close(O.split_statistic(two, orig, dirs, loss, "composite"), (loss[:, None] * w).mean(axis=0), 1e-10,
+           1e-12, "two Gaussians (composite)")
+
+
+# ---------------------------------------------------------------------------------------
 # Invariances
 # ---------------------------------------------------------------------------------------
 
@@ -780,4 +819,5 @@ ALL_PINS = [
     pin_colour_blend, pin_flow_both_directions, pin_max_weight,
     pin_composite_single_gaussian, pin_composite_sorted_reference, pin_composite_ties,
     pin_composite_background, pin_composite_scale_invariance, pin_composite_gradients_fd,
+    pin_split_statistic,
 ]

@@ -51,6 +51,8 @@ MUTANTS = {
     "adj_composite_wrong_side": ("if (pq->t < q[k].t) later += zbar[k];",
                                  "if (pq->t > q[k].t) later += zbar[k];"),
     "adj_composite_slope_dropped": ("d_bar = z_bar * log_opacity_slope(pq->delta);", "d_bar = z_bar;"),
+    "split_mean_over_gaussians": ("lbar[i] = s / (double)p;", "lbar[i] = s / (double)n;"),
+    "split_unweighted": ("acc[(size_t)tid * n + i] += loss[r] * wt[i];", "acc[(size_t)tid * n + i] += loss[r];"),
 }
 
 
