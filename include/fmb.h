@@ -272,6 +272,39 @@ int fmb_loss_grad(int64_t p, const float *depth, const float *alpha, const float
                   int32_t flow_norm, int32_t flow_cols, float w_color, float *g_depth, float *g_alpha,
                   float *g_flow, float *g_color, float *block_loss, void *stream);
 
+/* Split statistic of Sec. 8 for a scene or batch (exactly one non-NULL): the average loss
+ * assigned to each Gaussian over the M rays of its scene,
+ *   lbar_i = (1/M) sum_j loss_j w_ji,
+ * w_ji the normalised Eq. (3) weights of the current model (Eq. 7 or Eq. 9-10).  loss: device
+ * [P] per-ray loss (any reconstruction loss; typically over a random ~5 % of the rays set with
+ * fmb_set_rays); stash: device [P,8] from the forward pass of the same model and parameters;
+ * lbar: device [n] (batch: [sum n]), written.  Sums run in a fixed order (deterministic).
+ * Errors: FMB_ERR_STATE (no cameras), FMB_ERR_INVALID_ARG, FMB_ERR_HIP. */
+int fmb_split_statistic(fmb_scene *scene, fmb_batch *batch, const float *loss, const float *stash,
+                        float *lbar, void *stream);
+
+/* Removal and splitting of Gaussians (Sec. 8), host arrays, double-precision host code.
+ *
+ * fmb_prune_mask: remove[i] = 1 where weights[i] <= mean - z * std over the n weights (the
+ * population standard deviation; the paper's z is 2), else 0.
+ * fmb_split_mask: split[i] = 1 where lbar[i] >= mean + z * std over the n values (z = 1 in
+ * the paper; lbar from fmb_split_statistic), else 0.
+ * fmb_split_gaussians: each of the n given Gaussians becomes two, written at 2i and 2i + 1:
+ * means mu +- sigma_1 sqrt(2/pi) v_1 (v_1 the dominant axis of Sigma, sigma_1 the standard
+ * deviation along it, v_1's largest-magnitude component taken positive), both with Sigma's
+ * axes and sigma_1 scaled by sqrt(1 - 2/pi) (packed upper factor of the new precision, positive
+ * diagonal); weights lambda exp(noise_w[k]) and colours (unconstrained) colors + noise_c[k],
+ * the noise drawn by the caller (the paper: N(0, 0.1^2) each).  means [n,3], prec [n,6],
+ * weights [n], colors [n,3] or NULL, noise_w [2n], noise_c [2n,3] (NULL with colors NULL);
+ * outputs out_means [2n,3], out_prec [2n,6], out_weights [2n], out_colors [2n,3] or NULL.
+ * Errors: FMB_ERR_INVALID_ARG (bad sizes or pointers, a precision factor that is not
+ * positive definite). */
+int fmb_prune_mask(int32_t n, const float *weights, float z, uint8_t *remove);
+int fmb_split_mask(int32_t n, const float *lbar, float z, uint8_t *split);
+int fmb_split_gaussians(int32_t n, const float *means, const float *prec, const float *weights,
+                        const float *colors, const float *noise_w, const float *noise_c,
+                        float *out_means, float *out_prec, float *out_weights, float *out_colors);
+
 /* Pin the launch configuration of a scene or batch (exactly one non-NULL) instead of
  * autotuning it: forward variant in [0, 4), backward variant in [0, 6) (see
  * fmb_get_config), persistent-grid multipliers 1 or 2.  Every variant computes the same

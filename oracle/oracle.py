@@ -8,6 +8,7 @@ upcast to float64; all arithmetic is double precision.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from dataclasses import dataclass
@@ -277,6 +278,55 @@ def split_statistic(scene: OracleScene, orig, dirs, loss, model: str = "blend", 
                                   _p(out), int(n_threads))
     if rc != 0:
         raise ValueError("oracle split_statistic rejected its arguments")
+    return out
+
+
+def prune_mask(weights, z=2.0):
+    """Removal test of Sec. 8: lambda_i <= mean(lambda) - z std(lambda) (population std)."""
+    w = np.asarray(weights, np.float64)
+    return w <= w.mean() - z * w.std()
+
+
+def split_mask(lbar, z=1.0):
+    """Split test of Sec. 8: lbar_i >= mean(lbar) + z std(lbar)."""
+    x = np.asarray(lbar, np.float64)
+    return x >= x.mean() + z * x.std()
+
+
+def split_gaussians(means, prec, weights, colors=None, noise_w=None, noise_c=None):
+    """Split of Sec. 8 by the half-normal distribution: each Gaussian gives two with means
+    mu +- sigma_1 sqrt(2/pi) v_1 (v_1 the dominant eigenvector of Sigma, sigma_1^2 its
+    eigenvalue: sigma_1 is read as the standard deviation along v_1, the reading under which
+    the shift is a length) and the same covariance with sigma_1 scaled by sqrt(1 - 2/pi);
+    log-weights and unconstrained colours get the caller's noise.  v_1's largest-magnitude
+    component is taken positive; child 2i is the + shift.  Returns float64 arrays."""
+    means = np.asarray(means, np.float64)
+    prec = np.asarray(prec, np.float64)
+    n = means.shape[0]
+    noise_w = np.zeros(2 * n) if noise_w is None else np.asarray(noise_w, np.float64)
+    out = {"means": np.empty((2 * n, 3)), "prec": np.empty((2 * n, 6)), "weights": np.empty(2 * n),
+           "colors": None if colors is None else np.empty((2 * n, 3))}
+    for i in range(n):
+        u = prec[i]
+        U = np.array([[u[0], u[1], u[2]], [0.0, u[3], u[4]], [0.0, 0.0, u[5]]])
+        cov = np.linalg.inv(U.T @ U)
+        vals, vecs = np.linalg.eigh(cov)            # ascending
+        v1 = vecs[:, -1]
+        if v1[np.argmax(np.abs(v1))] < 0:
+            v1 = -v1
+        sigma1 = math.sqrt(vals[-1])
+        vals2 = vals.copy()
+        vals2[-1] = vals[-1] * (1.0 - 2.0 / math.pi)
+        cov2 = vecs @ np.diag(vals2) @ vecs.T
+        L = np.linalg.cholesky(np.linalg.inv(cov2))  # Sigma'^-1 = L L^T, U' = L^T
+        Up = L.T
+        for child, sgn in ((0, 1.0), (1, -1.0)):
+            o = 2 * i + child
+            out["means"][o] = means[i] + sgn * sigma1 * math.sqrt(2.0 / math.pi) * v1
+            out["prec"][o] = [Up[0, 0], Up[0, 1], Up[0, 2], Up[1, 1], Up[1, 2], Up[2, 2]]
+            out["weights"][o] = float(weights[i]) * math.exp(noise_w[o])
+            if colors is not None:
+                out["colors"][o] = np.asarray(colors[i], np.float64) + np.asarray(noise_c[o], np.float64)
     return out
 
 

@@ -35,6 +35,10 @@ SIGNATURES = {
     "fmb_set_flow_pose2": (_int, [_vp, _vp, _vp, _vp]),
     "fmb_set_model": (_int, [_vp, _vp, _i32]),
     "fmb_set_config": (_int, [_vp, _vp, _i32, _i32, _i32, _i32]),
+    "fmb_split_statistic": (_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "fmb_prune_mask": (_int, [_i32, _vp, _f32, _vp]),
+    "fmb_split_mask": (_int, [_i32, _vp, _f32, _vp]),
+    "fmb_split_gaussians": (_int, [_i32] + [_vp] * 10),
     "fmb_render": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fmb_backward": (_int, [_vp] + [_vp] * 13 + [_vp]),
     "fmb_batch_create": (_int, [ctypes.POINTER(_vp), _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,

@@ -45,6 +45,11 @@ hipError_t launch_loss(int p, const float *depth, const float *alpha, const floa
 hipError_t launch_validate(const Params &P, int n_total, int n_scenes, int *flags, hipStream_t st);
 hipError_t launch_fwdc(int km, int flags, int n_items, hipStream_t st, const Params &P, const FwdOut &O,
                        const BwdItem *items);
+hipError_t launch_stat(int n_items, int n_tasks, int max_gc, hipStream_t st, const Params &P, const float *loss,
+                       const float *stash, const BwdItem *items, const StatTask *tasks, float *partial,
+                       const int64_t *rays_per_scene, float *lbar);
+hipError_t launch_statc(int km, int n_items, hipStream_t st, const Params &P, const float *loss, const float *stash,
+                        const BwdItem *items, float *partial);
 hipError_t launch_bwdc(int km, int flags, int n_items, hipStream_t st, const Params &P, const BwdIn &I,
                        const BwdItem *items, float *partial, float *beta_partial);
 hipError_t occupancy_fwd(int variant, int flags, int *blocks_per_cu);
@@ -452,6 +457,90 @@ struct Job {
         return FMB_OK;
     }
 
+    // split statistic: its own items (Gaussian-lane chunks for the blend model, whole scenes
+    // for compositing) and buffers, so captured graphs of the passes stay valid
+    int stat_built = -1, n_sitems = 0, n_stasks = 0, stat_max_gc = 0;
+    DevBuf d_sitems, d_stasks, d_spartial, d_srays;
+
+    int build_stat()
+    {
+        if (stat_built == model) return FMB_OK;
+        const bool comp = model == FMB_MODEL_COMPOSITE;
+        const int B = block_size();
+        std::vector<BwdItem> items;
+        std::vector<StatTask> tasks;
+        std::vector<int64_t> rays(S, 0);
+        size_t poff = 0;
+        stat_max_gc = 0;
+        for (int s = 0; s < S; ++s) {
+            const int n = scenes[s].n;
+            int gc = n, sl = 1, span;
+            if (comp) {
+                span = 16 * 4 * (64 / comp_seg(n));
+            } else {
+                chunking(n, B, gc, sl);
+                span = 64 * sl;
+            }
+            stat_max_gc = std::max(stat_max_gc, gc);
+            for (int k = scenes[s].view_off; k < scenes[s].view_off + scenes[s].n_views; ++k)
+                rays[s] += (int64_t)views[k].h * views[k].w;
+            for (int g0 = 0; g0 < n; g0 += gc) {
+                StatTask t{};
+                t.scene = s;
+                t.g0 = g0;
+                t.gc = std::min(gc, n - g0);
+                t.item_begin = (int)items.size();
+                for (int k = scenes[s].view_off; k < scenes[s].view_off + scenes[s].n_views; ++k) {
+                    const int hw = views[k].h * views[k].w;
+                    for (int r0 = 0; r0 < hw; r0 += span) {
+                        BwdItem it{};
+                        it.view = k;
+                        it.ray0 = r0;
+                        it.span = span;
+                        it.g0 = g0;
+                        it.gc = gc;
+                        it.slots = sl;
+                        if (poff > (size_t)INT32_MAX - (size_t)gc)
+                            return fail(FMB_ERR_SHAPE, "split statistic partials exceed 2^31 floats");
+                        it.poff = (int)poff;
+                        it.seq = (int)items.size();
+                        poff += (size_t)gc;
+                        items.push_back(it);
+                    }
+                }
+                t.item_end = (int)items.size();
+                tasks.push_back(t);
+            }
+        }
+        HIPCHK(d_sitems.upload(items));
+        HIPCHK(d_stasks.upload(tasks));
+        HIPCHK(d_srays.upload(rays));
+        HIPCHK(d_spartial.ensure(std::max<size_t>(poff, 1) * sizeof(float)));
+        n_sitems = (int)items.size();
+        n_stasks = (int)tasks.size();
+        stat_built = model;
+        return FMB_OK;
+    }
+
+    int split_statistic(const float *loss, const float *stash, float *lbar, hipStream_t st)
+    {
+        if (!cams_set) return fail(FMB_ERR_STATE, "split statistic before cameras were set");
+        CHECK_ARG(loss && stash && lbar, "loss, stash and lbar must be non-NULL");
+        CHECK_ARG(aligned(stash, 16), "stash must be 16-byte aligned");
+        int rc = build_stat();
+        if (rc) return rc;
+        if (model == FMB_MODEL_COMPOSITE) {
+            HIPCHK(launch_statc(comp_km(), n_sitems, st, prm, loss, stash, d_sitems.as<BwdItem>(),
+                                d_spartial.as<float>()));
+            HIPCHK(launch_stat(0, n_stasks, stat_max_gc, st, prm, loss, stash, d_sitems.as<BwdItem>(),
+                               d_stasks.as<StatTask>(), d_spartial.as<float>(), d_srays.as<int64_t>(), lbar));
+        } else {
+            HIPCHK(launch_stat(n_sitems, n_stasks, stat_max_gc, st, prm, loss, stash, d_sitems.as<BwdItem>(),
+                               d_stasks.as<StatTask>(), d_spartial.as<float>(), d_srays.as<int64_t>(), lbar));
+        }
+        return FMB_OK;
+    }
+
     std::map<int, int> occ_f, occ_b;  // blocks per CU of the persistent kernels
     int persist_mult[2] = {1, 1};     // persistent grid = mult x occupancy x CUs (fwd, bwd)
 
@@ -677,7 +766,7 @@ int fmb_set_cameras(fmb_scene *s, int32_t v, const float *w2c, const float *intr
     j.prm.w2c_c = j.prm.intr_c = nullptr;
     j.prm.dirs = nullptr;
     j.has_flow = w2c_b != nullptr;
-    j.fwd_built = j.bwd_built = -1;
+    j.fwd_built = j.bwd_built = j.stat_built = -1;
     j.cams_set = false;
     if ((rc = j.upload_descriptors())) return rc;
     j.cams_set = true;
@@ -718,7 +807,7 @@ int fmb_set_rays(fmb_scene *s, int32_t v, const float *w2c, const float *intr, c
     j.prm.w2c_c = j.prm.intr_c = nullptr;
     j.prm.dirs = dirs;
     j.has_flow = w2c_b != nullptr;
-    j.fwd_built = j.bwd_built = -1;
+    j.fwd_built = j.bwd_built = j.stat_built = -1;
     j.cams_set = false;
     int rc = j.upload_descriptors();
     if (rc) return rc;
@@ -975,6 +1064,14 @@ int fmb_validate(fmb_scene *s, int32_t *bad_host, void *stream)
     HIPCHK(hipStreamSynchronize(st));
     *bad_host = flags;
     return rc;
+}
+
+int fmb_split_statistic(fmb_scene *s, fmb_batch *b, const float *loss, const float *stash, float *lbar,
+                        void *stream)
+{
+    g_err.clear();
+    CHECK_ARG((s != nullptr) != (b != nullptr), "exactly one of scene and batch must be given");
+    return (s ? s->job : b->job).split_statistic(loss, stash, lbar, (hipStream_t)stream);
 }
 
 int fmb_set_config(fmb_scene *s, fmb_batch *b, int32_t fwd_variant, int32_t bwd_variant, int32_t fwd_grid_mult,

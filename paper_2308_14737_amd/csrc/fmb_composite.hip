@@ -357,6 +357,94 @@ __global__ __launch_bounds__(kCompBlock) void bwdc_kernel(Params P, BwdIn I, con
 }
 
 // ------------------------------------------------------------------------------------
+// Split statistic (Sec. 8) with the compositing weights: lbar_i = (1/M) sum_j L_j w_ji,
+// same layout as the backward; the running maximum and 1/S come from the forward's stash.
+// ------------------------------------------------------------------------------------
+
+template <int KM>
+__global__ __launch_bounds__(kCompBlock) void statc_kernel(Params P, const float *__restrict__ loss,
+                                                           const float *__restrict__ stash,
+                                                           const BwdItem *__restrict__ items,
+                                                           float *__restrict__ partial)
+{
+    __shared__ float4 rays[kCompBlock * 2];
+    __shared__ float2 tdl[kCompBlock * KM];
+    __shared__ float red[kCompBlock * KM];
+    const int tid = threadIdx.x;
+    const BwdItem item = items[blockIdx.x];
+    const ViewRec vr = P.views[item.view];
+    const SceneRec sr = P.scenes[vr.scene];
+    const int n = sr.n;
+    const CompLanes c = comp_lanes<KM>(n);
+    const int wave = tid >> 6;
+    const float *__restrict__ e = P.w2c + 12 * item.view;
+    const float *__restrict__ kk = P.intr + 4 * item.view;
+    double o[3];
+    cam_centre(e, o);
+    const float hm = (float)(-0.5 * kLog2e);
+    Ent g[KM];
+    float4 cc[KM];
+    bool gv[KM];
+    comp_entries<KM, false>(P, sr, c, o, g, cc, gv);
+    float acc[KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) acc[k] = 0.0f;
+    const int hw = vr.h * vr.w;
+    const int end = min(item.ray0 + item.span, hw);
+    const int step = 4 * c.rpw;
+    for (int base = item.ray0; base < end; base += step) {
+        __syncthreads();
+        if (tid < step) {
+            const int local = base + tid;
+            float4 a = make_float4(0.0f, 0.0f, 1.0f, INFINITY), b = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (local < end) {
+                const int r = vr.ray_off + local;
+                float v0, v1, v2;
+                ray_dir(P, vr, e, kk, local, v0, v1, v2);
+                const float4 s0 = reinterpret_cast<const float4 *>(stash)[2 * (size_t)r];
+                a = make_float4(v0, v1, v2, s0.x);
+                b = make_float4(s0.y, loss[r], 0.0f, 0.0f);
+            }
+            rays[2 * tid] = a;
+            rays[2 * tid + 1] = b;
+        }
+        __syncthreads();
+        const int ry = wave * c.rpw + c.sg;
+        const float4 x0 = rays[2 * ry], x1 = rays[2 * ry + 1];
+        Geo q[KM];
+        float dl[KM];
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            if (k < c.ke) {
+                pair_geo(g[k], x0.x, x0.y, x0.z, hm, 0.0f, 0.0f, q[k]);
+                dl[k] = gv[k] ? exp2_(q[k].d2) : 0.0f;
+                tdl[c.sbase + k * c.seg + c.sl] = make_float2(q[k].t, dl[k]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            if (k < c.ke && gv[k]) {
+                const float front = ordered_partial<false>(tdl + c.sbase, n, q[k].t);
+                const float wt = exp2_(fmaf(-(float)kLog2e, front, log2_opacity(dl[k], q[k].d2)) - x0.w) * x1.x;
+                acc[k] = fmaf(x1.y, wt, acc[k]);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KM; ++k) red[tid * KM + k] = acc[k];
+    __syncthreads();
+    if (tid < n) {
+        const int k = tid / c.seg, l = tid % c.seg;
+        float sum = 0.0f;
+        for (int w = 0; w < kCompBlock / 64; ++w)
+            for (int sgi = 0; sgi < c.rpw; ++sgi) sum += red[(w * 64 + sgi * c.seg + l) * KM + k];
+        partial[item.poff + tid] = sum;
+    }
+}
+
+// ------------------------------------------------------------------------------------
 // Launchers
 // ------------------------------------------------------------------------------------
 
@@ -410,6 +498,21 @@ hipError_t launch_bwdc(int km, int flags, int n_items, hipStream_t st, const Par
     } else {
         return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_statc(int km, int n_items, hipStream_t st, const Params &P, const float *loss, const float *stash,
+                        const BwdItem *items, float *partial)
+{
+    if (n_items < 1) return hipSuccess;
+    if (km == 1)
+        hipLaunchKernelGGL((statc_kernel<1>), dim3(n_items), dim3(kCompBlock), 0, st, P, loss, stash, items, partial);
+    else if (km == 2)
+        hipLaunchKernelGGL((statc_kernel<2>), dim3(n_items), dim3(kCompBlock), 0, st, P, loss, stash, items, partial);
+    else if (km == 4)
+        hipLaunchKernelGGL((statc_kernel<4>), dim3(n_items), dim3(kCompBlock), 0, st, P, loss, stash, items, partial);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -74,6 +74,15 @@ struct FinGroup {
 };
 constexpr int kGroupItems = 32;  // minimum items per first-stage group
 
+// Split statistic (one value per Gaussian and item): the items of a (scene, Gaussian chunk)
+// are consecutive, [item_begin, item_end), and their partial sums are added in that order.
+struct StatTask {
+    int32_t scene;
+    int32_t g0, gc;                 // scene-local first Gaussian and chunk size
+    int32_t item_begin, item_end;
+    int32_t pad[3];
+};
+
 constexpr int kPartial = 10;       // per-Gaussian partial: dU (6), sum rho (3), dlog(lambda) (1)
 constexpr int kPartialColor = 13;  // ... and dL/d(colour) (3)
 

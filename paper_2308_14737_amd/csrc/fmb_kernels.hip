@@ -558,6 +558,88 @@ __global__ __launch_bounds__(BLOCK) void fin2_kernel(Params P, const FinTask *__
     }
 }
 
+// ------------------------------------------------------------------------------------
+// Split statistic (Sec. 8): lbar_i = (1/M) sum_j L_j w_ji over a scene's M rays, w_ji the
+// normalised blend weights of Eq. (3) (Eq. 7 here), read back from the forward pass's stash.
+// Gaussian-lane layout as the backward: rays staged through LDS (direction, running max,
+// 1/S, loss), one partial sum per (item, Gaussian), reduced over the slots in LDS.
+// ------------------------------------------------------------------------------------
+
+template <int BLOCK, int RT>
+__global__ __launch_bounds__(BLOCK) void stat_kernel(Params P, const float *__restrict__ loss,
+                                                    const float *__restrict__ stash,
+                                                    const BwdItem *__restrict__ items, float *__restrict__ partial)
+{
+    __shared__ float4 rays[RT * 2];
+    __shared__ float red[BLOCK];
+    const int tid = threadIdx.x;
+    const BwdItem item = items[blockIdx.x];
+    const ViewRec vr = P.views[item.view];
+    const SceneRec sr = P.scenes[vr.scene];
+    const float *__restrict__ e = P.w2c + 12 * item.view;
+    const float *__restrict__ kk = P.intr + 4 * item.view;
+    double o[3];
+    cam_centre(e, o);
+    const Blend bl = blend_of(P, vr.scene);
+    const int hw = vr.h * vr.w;
+    const int end = min(item.ray0 + item.span, hw);
+    const int gi = tid % item.gc;
+    const int slot = tid / item.gc;
+    const bool active = slot < item.slots && item.g0 + gi < sr.n;
+    Ent g;
+    if (active) {
+        const int gg = sr.gauss_off + item.g0 + gi;
+        float4 q[4];
+        make_entry(P.means + 3 * gg, P.prec + 6 * gg, P.weights[gg], o, q);
+        g = ent_from(q[0], q[1], q[2], q[3]);
+    }
+    float acc = 0.0f;
+    for (int r0 = item.ray0; r0 < end; r0 += RT) {
+        const int cnt = min(RT, end - r0);
+        __syncthreads();
+        for (int q = tid; q < cnt; q += BLOCK) {
+            const int r = vr.ray_off + r0 + q;
+            float v0, v1, v2;
+            ray_dir(P, vr, e, kk, r0 + q, v0, v1, v2);
+            const float4 s0 = reinterpret_cast<const float4 *>(stash)[2 * (size_t)r];
+            rays[2 * q] = make_float4(v0, v1, v2, s0.x);
+            rays[2 * q + 1] = make_float4(s0.y, loss[r], 0.0f, 0.0f);
+        }
+        __syncthreads();
+        if (active) {
+            for (int j = slot; j < cnt; j += item.slots) {
+                const float4 x0 = rays[2 * j], x1 = rays[2 * j + 1];
+                Geo q;
+                pair_geo(g, x0.x, x0.y, x0.z, bl.hm, bl.b1, bl.nc2, q);
+                if (q.z2 - x0.w >= kSkipLog2) acc = fmaf(x1.y, exp2_(q.z2 - x0.w) * x1.x, acc);
+            }
+        }
+    }
+    __syncthreads();
+    red[tid] = acc;
+    __syncthreads();
+    if (slot == 0 && gi < item.gc && item.g0 + gi < sr.n) {
+        float s = red[gi];
+        for (int k = 1; k < item.slots; ++k) s += red[k * item.gc + gi];
+        partial[item.poff + gi] = s;
+    }
+}
+
+// lbar of every Gaussian of a (scene, chunk): its items' partial sums added in item order in
+// double, divided by the scene's ray count.
+__global__ void stat_fin_kernel(Params P, const StatTask *__restrict__ tasks, const BwdItem *__restrict__ items,
+                                const float *__restrict__ partial, const int64_t *__restrict__ rays_per_scene,
+                                float *__restrict__ lbar)
+{
+    const StatTask t = tasks[blockIdx.x];
+    const int g = threadIdx.x + blockIdx.y * blockDim.x;
+    if (g >= t.gc) return;
+    double s = 0.0;
+    for (int it = t.item_begin; it < t.item_end; ++it) s += (double)partial[items[it].poff + g];
+    const SceneRec sr = P.scenes[t.scene];
+    lbar[sr.gauss_off + t.g0 + g] = (float)(s / (double)rays_per_scene[t.scene]);
+}
+
 // Gradient of the Sec. 4 reconstruction loss (mask BCE, mask-weighted L1 depth, mask-weighted
 // flow term) with respect to one render's outputs; per-block loss partials in fixed order.
 constexpr int kLossBlock = 1024;
@@ -775,6 +857,19 @@ hipError_t launch_fin(int n_tasks, int n_groups, hipStream_t st, const Params &P
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((fin2_kernel<256>), dim3(n_tasks, (kBlock + kFinSlice - 1) / kFinSlice), dim3(256), 0, st, P,
                        tasks, groups, stage, stage_beta, g_means, g_prec, g_weights, g_colors, g_betas);
+    return hipGetLastError();
+}
+
+hipError_t launch_stat(int n_items, int n_tasks, int max_gc, hipStream_t st, const Params &P, const float *loss,
+                       const float *stash, const BwdItem *items, const StatTask *tasks, float *partial,
+                       const int64_t *rays_per_scene, float *lbar)
+{
+    if (n_items > 0)
+        hipLaunchKernelGGL((stat_kernel<kBlock, 256>), dim3(n_items), dim3(kBlock), 0, st, P, loss, stash, items,
+                           partial);
+    if (n_tasks > 0)
+        hipLaunchKernelGGL(stat_fin_kernel, dim3(n_tasks, (max_gc + 255) / 256), dim3(256), 0, st, P, tasks, items,
+                           partial, rays_per_scene, lbar);
     return hipGetLastError();
 }
 

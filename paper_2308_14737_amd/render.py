@@ -127,6 +127,15 @@ class Scene:
         _lib.call("fmb_set_model", self._h, None, _model_id(model))
         self.model = model
 
+    def split_statistic(self, loss: torch.Tensor, outs: dict, lbar: Optional[torch.Tensor] = None):
+        """lbar_i = (1/M) sum_j loss_j w_ji over this scene's M rays (Sec. 8); `outs` is the
+        forward result (its stash) for the same parameters and model."""
+        _check_dev(loss, "loss")
+        out = lbar if lbar is not None else torch.empty(self.n, device=loss.device)
+        _lib.call("fmb_split_statistic", self._h, None, _vp(loss), _vp(outs["stash"]), _vp(out),
+                  _stream(loss.device))
+        return out
+
     def rebind(self, means, prec, weights, betas):
         for t, nm in ((means, "means"), (prec, "prec"), (weights, "weights"), (betas, "betas")):
             _check_dev(t, nm)
@@ -344,6 +353,14 @@ class Batch:
         """"blend" or "composite" for every scene of the batch (see Scene.set_model)."""
         _lib.call("fmb_set_model", None, self._h, _model_id(model))
         self.model = model
+
+    def split_statistic(self, loss: torch.Tensor, outs: dict, lbar: Optional[torch.Tensor] = None):
+        """Scene.split_statistic for every scene of the batch: lbar [sum N]."""
+        _check_dev(loss, "loss")
+        out = lbar if lbar is not None else torch.empty(self.n_total, device=loss.device)
+        _lib.call("fmb_split_statistic", None, self._h, _vp(loss), _vp(outs["stash"]), _vp(out),
+                  _stream(loss.device))
+        return out
 
     def alloc_outputs(self, normals=True, color=False):
         p, dev = self.n_rays, self.device

@@ -602,6 +602,53 @@ def pin_split_statistic():
            1e-12, "two Gaussians (composite)")
 
 
+def _cov_of_packed(u):
+    U = np.array([[u[0], u[1], u[2]], [0.0, u[3], u[4]], [0.0, 0.0, u[5]]])
+    return np.linalg.inv(U.T @ U)
+
+
+def pin_split_gaussians():
+    """Half-normal split: an axis-aligned Gaussian with standard deviations (0.3, 0.1, 0.05) splits
+    along x into means mu +- 0.3 sqrt(2/pi) e_x with x deviation 0.3 sqrt(1 - 2/pi); for random
+    Gaussians the equal mixture of the two children has exactly the parent's mean and
+    covariance; weights and colours take the given noise."""
+    mu = np.array([0.1, -0.2, 0.3])
+    sd = np.array([0.3, 0.1, 0.05])
+    out = O.split_gaussians(mu[None], [[1 / sd[0], 0, 0, 1 / sd[1], 0, 1 / sd[2]]], [0.7])
+    d = 0.3 * math.sqrt(2 / math.pi)
+    _close(out["means"], [mu + [d, 0, 0], mu - [d, 0, 0]], 1e-14, 1e-14, "axis-aligned split means")
+    sd2 = sd * [math.sqrt(1 - 2 / math.pi), 1, 1]
+    _close(out["prec"], np.tile([1 / sd2[0], 0, 0, 1 / sd2[1], 0, 1 / sd2[2]], (2, 1)), 1e-12, 1e-12,
+           "axis-aligned split precision")
+    _close(out["weights"], [0.7, 0.7], 1e-15, 0.0, "split weights without noise")
+    g = _rng(51)
+    for _ in range(20):
+        cov, packed = _cov_and_packed(g)
+        m = g.standard_normal(3)
+        nw, nc = g.standard_normal(2), g.standard_normal((2, 3))
+        col = g.standard_normal((1, 3))
+        o = O.split_gaussians(m[None], packed[None], [1.3], col, nw, nc)
+        ma, mb = o["means"]
+        _close(0.5 * (ma + mb), m, 1e-12, 1e-12, "mixture mean")
+        c2 = _cov_of_packed(o["prec"][0])
+        _close(_cov_of_packed(o["prec"][1]), c2, 1e-12, 1e-14, "children share the covariance")
+        mix = c2 + 0.5 * (np.outer(ma - m, ma - m) + np.outer(mb - m, mb - m))
+        _close(mix, cov, 1e-10, 1e-12, "mixture covariance")
+        _close(o["weights"], 1.3 * np.exp(nw), 1e-14, 0.0, "log-weight noise")
+        _close(o["colors"], col + nc, 1e-14, 0.0, "colour noise")
+
+
+def pin_prune_split_masks():
+    """Removal at mean - 2 std of the weights, split at mean + 1 std of lbar (hand values)."""
+    w = np.array([1.0] * 9 + [0.0])          # mean 0.9, std 0.3: 0.0 <= 0.3 removed
+    assert list(O.prune_mask(w)) == [False] * 9 + [True]
+    x = np.array([0.0, 0.0, 0.0, 4.0])       # mean 1, std sqrt(3): 4 >= 2.73 split
+    assert list(O.split_mask(x)) == [False, False, False, True]
+    # zero spread: every value sits on the threshold and the non-strict tests mark it
+    assert O.split_mask(np.full(5, 2.0)).all()
+    assert O.prune_mask(np.full(5, 2.0)).all()
+
+
 # ---------------------------------------------------------------------------------------
 # Invariances
 # ---------------------------------------------------------------------------------------
@@ -819,5 +866,5 @@ ALL_PINS = [
     pin_colour_blend, pin_flow_both_directions, pin_max_weight,
     pin_composite_single_gaussian, pin_composite_sorted_reference, pin_composite_ties,
     pin_composite_background, pin_composite_scale_invariance, pin_composite_gradients_fd,
-    pin_split_statistic,
+    pin_split_statistic, pin_split_gaussians, pin_prune_split_masks,
 ]
