@@ -316,8 +316,9 @@ int fmb_set_config(fmb_scene *scene, fmb_batch *batch, int32_t fwd_variant, int3
  * host array out[8]: forward tile variant, rays per forward work item, backward variant,
  * rays per backward tile (staged in LDS for variants 0-2, which give each lane a Gaussian;
  * held by the block's lanes for variants 3-5, which give each lane rays as the forward pass
- * does), forward and backward persistent-grid multipliers, and the forward and backward
- * work-item counts (0 until the first call built them). */
+ * does and sum each Gaussian's terms over the wave per tile), forward and backward
+ * persistent-grid multipliers, and the forward and backward work-item counts (0 until the
+ * first call built them). */
 int fmb_get_config(const fmb_scene *scene, const fmb_batch *batch, int32_t *out);
 
 /* Check the scene's parameters on the device: writes to *bad_host a bit mask of

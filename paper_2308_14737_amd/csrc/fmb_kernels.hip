@@ -761,6 +761,7 @@ struct BwdRayVariant {
 };
 static const BwdRayVariant kBwdRay[] = {{2, 64}, {4, 64}, {4, 128}};
 constexpr int kNumBwdGauss = (int)(sizeof kBwdRT / sizeof kBwdRT[0]);
+constexpr int kNumBwdRay = (int)(sizeof kBwdRay / sizeof kBwdRay[0]);
 
 // F dispatch: calls body<F>() for the runtime flag set f (0..15).
 #define FMB_DISPATCH_F(f, CALL)                                                                            \
@@ -812,11 +813,11 @@ static hipError_t launch_bwd_v(int f, int grid, hipStream_t st, const Params &P,
 
 int num_fwd_variants() { return (int)(sizeof kFwdVariants / sizeof kFwdVariants[0]); }
 int fwd_variant_rays(int v) { return kBlock * kFwdVariants[v].rpt; }
-int num_bwd_variants() { return kNumBwdGauss + (int)(sizeof kBwdRay / sizeof kBwdRay[0]); }
-// Gaussian-lane variants: rays staged per pass; ray-lane variants: 0.
+int num_bwd_variants() { return kNumBwdGauss + kNumBwdRay; }
+// Gaussian-lane variants: rays staged per pass; others: 0.
 int bwd_variant_rt(int v) { return v < kNumBwdGauss ? kBwdRT[v] : 0; }
-// Ray-lane variants: rays per block tile (BLOCK * RPT); Gaussian-lane variants: 0.
-int bwd_variant_ray_tile(int v) { return v < kNumBwdGauss ? 0 : kBlock * kBwdRay[v - kNumBwdGauss].rpt; }
+// Ray-lane variants 3-5: rays per block tile (BLOCK * RPT); others: 0.
+int bwd_variant_ray_tile(int v) { return v >= kNumBwdGauss ? kBlock * kBwdRay[v - kNumBwdGauss].rpt : 0; }
 int block_size() { return kBlock; }
 
 // flags: bit 0 normals, 1 flow, 2 persistent, 3 colour
