@@ -46,11 +46,11 @@ PEAK_FP32_SCALAR = 78.6e12  # without packed FP32 issue
 PEAK_HBM = 8.0e12
 
 
-def measured_traffic():
-    """HBM bytes per launch of the persistent backward kernel, from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary, if the kernel source has not changed since it was taken."""
+def _profile_values(name):
+    """key: value lines of a committed rocprofv3 summary under profiles/, or {} if the kernel
+    source has changed since it was taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "batch16_bwd_traffic.md")
+    path = os.path.join(ROOT, "profiles", name)
     src = os.path.join(ROOT, "paper_2308_14737_amd", "csrc", "fmb_kernels.hip")
     try:
         vals = {}
@@ -58,12 +58,31 @@ def measured_traffic():
             if ":" in line and not line.startswith(("|", " ", "#")):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if vals.get("kernel_source_sha256") != sha:
-            return None
-        return float(vals["traffic_bytes_per_launch"])
-    except (OSError, KeyError, ValueError):
+        if vals.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+            return {}
+        return vals
+    except OSError:
+        return {}
+
+
+def measured_traffic():
+    """HBM bytes per launch of the persistent backward kernel, from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, if the kernel source has not changed since it was taken."""
+    try:
+        return float(_profile_values("batch16_bwd_traffic.md")["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
         return None
+
+
+def executed(pairs, bwd_ms):
+    """FP32 arithmetic the backward kernel executes per pair (rocprofv3 counters, including the
+    recomputed pair terms), and the resulting rate, if the committed counters are current."""
+    vals = _profile_values("batch16_valu.md")
+    try:
+        fl = float(vals["bwd_executed_flops_per_pair"])
+    except (KeyError, ValueError):
+        return {"executed_flops_per_pair": None, "executed_frac": None}
+    return {"executed_flops_per_pair": fl, "executed_frac": pairs * fl / (bwd_ms * 1e-3) / PEAK_FP32}
 
 
 def parse():
@@ -313,7 +332,7 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": measured_traffic(),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
                      "kernel": "bwd_kernel (persistent)", "flops_per_pair": FLOPS_ADJ_PLAIN,
-                     "peak_scalar_fp32": PEAK_FP32_SCALAR / 1e12},
+                     "peak_scalar_fp32": PEAK_FP32_SCALAR / 1e12, **executed(pairs, bwd_ms)},
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
