@@ -48,15 +48,35 @@ __device__ __forceinline__ float opacity_slope(float delta)
     return delta < 0.0625f ? series : direct;
 }
 
+// Lane exchanges within groups of 4, 8 and 16 lanes (DPP): quad_perm [1,0,3,2] and [2,3,0,1],
+// and the mirror of each half-row (8 lanes) and row (16 lanes).  After the quad steps every
+// lane of a quad holds the same value, so the mirrors pair each group with its neighbour.
+template <int CTRL>
+__device__ __forceinline__ float dpp_(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+// Sum (max) over the aligned group of `seg` lanes, left in every lane of the group.
 __device__ __forceinline__ float seg_sum(float x, int seg)
 {
-    for (int off = seg >> 1; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (seg > 1) x += dpp_<0xB1>(x);
+    if (seg > 2) x += dpp_<0x4E>(x);
+    if (seg > 4) x += dpp_<0x141>(x);
+    if (seg > 8) x += dpp_<0x140>(x);
+    if (seg > 16) x += __shfl_xor(x, 16, 64);
+    if (seg > 32) x += __shfl_xor(x, 32, 64);
     return x;
 }
 
 __device__ __forceinline__ float seg_max(float x, int seg)
 {
-    for (int off = seg >> 1; off > 0; off >>= 1) x = fmaxf(x, __shfl_xor(x, off, 64));
+    if (seg > 1) x = fmaxf(x, dpp_<0xB1>(x));
+    if (seg > 2) x = fmaxf(x, dpp_<0x4E>(x));
+    if (seg > 4) x = fmaxf(x, dpp_<0x141>(x));
+    if (seg > 8) x = fmaxf(x, dpp_<0x140>(x));
+    if (seg > 16) x = fmaxf(x, __shfl_xor(x, 16, 64));
+    if (seg > 32) x = fmaxf(x, __shfl_xor(x, 32, 64));
     return x;
 }
 
@@ -122,21 +142,59 @@ __device__ __forceinline__ float ordered_partial(const float2 *__restrict__ slot
     return s;
 }
 
+// Writes the segment's pairs (t_j, x_j) with x_j != 0 to its LDS slots, in Gaussian order,
+// and returns their count (the same in every lane of the segment).  Terms with x_j = 0 add
+// nothing to the sums below, so they are left out of the loops.
+template <int KM>
+__device__ __forceinline__ int compact_slots(float2 *__restrict__ slots, const CompLanes &c, const Geo q[KM],
+                                             const float x[KM])
+{
+    const int l0 = (threadIdx.x & 63) - c.sl;  // first lane of the segment
+    const unsigned long long segmask = c.seg == 64 ? ~0ull : ((1ull << c.seg) - 1ull);
+    const unsigned long long below = (1ull << c.sl) - 1ull;
+    int cnt = 0;
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        if (k < c.ke) {
+            const bool nz = x[k] != 0.0f;
+            const unsigned long long bits = (__ballot(nz) >> l0) & segmask;
+            if (nz) slots[cnt + __popcll(bits & below)] = make_float2(q[k].t, x[k]);
+            cnt += __popcll(bits);
+        }
+    }
+    return cnt;
+}
+
+// For each of the lane's Gaussians k: the sum of x_j over the `cnt` compacted slots with
+// t_j < t_k (AFTER = false) or t_j > t_k.
+template <int KM, bool AFTER>
+__device__ __forceinline__ void ordered_sums(const float2 *__restrict__ slots, int cnt, const CompLanes &c,
+                                             const Geo q[KM], float out[KM])
+{
+#pragma unroll
+    for (int k = 0; k < KM; ++k) out[k] = (k < c.ke) ? ordered_partial<AFTER>(slots, cnt, q[k].t) : 0.0f;
+}
+
 // ------------------------------------------------------------------------------------
 // Forward
 // ------------------------------------------------------------------------------------
+
+// Per-ray results wait in LDS (one record per ray) until the wave holds 64 of them; then
+// each lane writes one ray's outputs.
+constexpr int kEpiRec = 12;  // local ray index, M, S, T, N (3), C (3), D
 
 template <int KM, int F>
 __global__ __launch_bounds__(kCompBlock) void fwdc_kernel(Params P, FwdOut O, const BwdItem *__restrict__ items)
 {
     constexpr bool NORMALS = (F & kNrm) != 0, COLOR = (F & kCol) != 0;
     __shared__ float2 tdl[kCompBlock * KM];
+    __shared__ float epi[kCompBlock * kEpiRec];
     const BwdItem item = items[blockIdx.x];
     const ViewRec vr = P.views[item.view];
     const SceneRec sr = P.scenes[vr.scene];
     const int n = sr.n;
     const CompLanes c = comp_lanes<KM>(n);
-    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const float *__restrict__ e = P.w2c + 12 * item.view;
     const float *__restrict__ kk = P.intr + 4 * item.view;
     double o[3];
@@ -149,6 +207,8 @@ __global__ __launch_bounds__(kCompBlock) void fwdc_kernel(Params P, FwdOut O, co
     comp_entries<KM, COLOR>(P, sr, c, o, g, cc, gv);
     const int hw = vr.h * vr.w;
     const int end = min(item.ray0 + item.span, hw);
+    float *__restrict__ my_epi = epi + wave * 64 * kEpiRec;
+    int filled = 0;  // records waiting in this wave's slice (the same in every wave)
 
     for (int base = item.ray0; base < end; base += 4 * c.rpw) {
         const int local = base + wave * c.rpw + c.sg;
@@ -162,22 +222,21 @@ __global__ __launch_bounds__(kCompBlock) void fwdc_kernel(Params P, FwdOut O, co
             if (k < c.ke) {
                 pair_geo(g[k], v0, v1, v2, hm, 0.0f, 0.0f, q[k]);
                 dl[k] = gv[k] ? exp2_(q[k].d2) : 0.0f;
+            } else {
+                dl[k] = 0.0f;
             }
         }
         __syncthreads();  // the previous step is done with the slots
-#pragma unroll
-        for (int k = 0; k < KM; ++k)
-            if (k < c.ke) tdl[c.sbase + k * c.seg + c.sl] = make_float2(q[k].t, dl[k]);
+        const int cnt = compact_slots<KM>(tdl + c.sbase, c, q, dl);
         __syncthreads();
+        float front[KM];
+        ordered_sums<KM, false>(tdl + c.sbase, cnt, c, q, front);
         float l2[KM];
         float mx = -INFINITY;
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
             l2[k] = -INFINITY;
-            if (k < c.ke && gv[k]) {
-                const float front = ordered_partial<false>(tdl + c.sbase, n, q[k].t);
-                l2[k] = fmaf(-(float)kLog2e, front, log2_opacity(dl[k], q[k].d2));
-            }
+            if (k < c.ke && gv[k]) l2[k] = fmaf(-(float)kLog2e, front[k], log2_opacity(dl[k], q[k].d2));
             mx = fmaxf(mx, l2[k]);
         }
         mx = seg_max(mx, c.seg);
@@ -215,9 +274,28 @@ __global__ __launch_bounds__(kCompBlock) void fwdc_kernel(Params P, FwdOut O, co
             C1 = seg_sum(C1, c.seg);
             C2 = seg_sum(C2, c.seg);
         }
-        if (c.sl == 0 && valid)
-            write_ray<F>(P, O, item.view, vr.ray_off + local, e, kk, o0, o1, o2, v0, v1, v2, mx, S, T, N0, N1, N2,
-                         C0, C1, C2, D);
+        if (c.sl == 0) {
+            float *r = my_epi + (filled + c.sg) * kEpiRec;
+            r[0] = __int_as_float(valid ? local : -1);
+            r[1] = mx; r[2] = S; r[3] = T; r[4] = N0; r[5] = N1; r[6] = N2;
+            r[7] = C0; r[8] = C1; r[9] = C2; r[10] = D;
+        }
+        filled += c.rpw;
+        if (filled == 64 || base + 4 * c.rpw >= end) {
+            __syncthreads();
+            if (lane < filled) {
+                const float *r = my_epi + lane * kEpiRec;
+                const int rl = __float_as_int(r[0]);
+                if (rl >= 0) {
+                    float w0, w1, w2;
+                    ray_dir(P, vr, e, kk, rl, w0, w1, w2);
+                    write_ray<F>(P, O, item.view, vr.ray_off + rl, e, kk, o0, o1, o2, w0, w1, w2, r[1], r[2], r[3],
+                                 r[4], r[5], r[6], r[7], r[8], r[9], r[10]);
+                }
+            }
+            __syncthreads();
+            filled = 0;
+        }
     }
 }
 
@@ -261,66 +339,69 @@ __global__ __launch_bounds__(kCompBlock) void bwdc_kernel(Params P, BwdIn I, con
     const int end = min(item.ray0 + item.span, hw);
     const int step = 4 * c.rpw;
 
-    for (int base = item.ray0; base < end; base += step) {
-        __syncthreads();  // the previous step is done with the staged rays and the slots
-        if (tid < step) {
+    // rays are staged kCompBlock at a time (one prologue per thread), then taken a step of
+    // 4 * 64 / seg rays at a time
+    for (int sb = item.ray0; sb < end; sb += kCompBlock) {
+        __syncthreads();  // the previous stage is done with the staged rays
+        {
             float4 pr[4];
-            ray_prologue<F>(P, I, item.view, vr, e, kk, o0, o1, o2, base + tid, base + tid < end, pr);
+            ray_prologue<F>(P, I, item.view, vr, e, kk, o0, o1, o2, sb + tid, sb + tid < end, pr);
 #pragma unroll
             for (int w = 0; w < RW; ++w) smem[RW * tid + w] = pr[w];
         }
-        __syncthreads();
-        const int ry = wave * c.rpw + c.sg;
-        const float4 x0 = smem[RW * ry], x1 = smem[RW * ry + 1], x2 = smem[RW * ry + 2];
-        float4 x3 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (COLOR) x3 = smem[RW * ry + 3];
-        const float v0 = x0.x, v1 = x0.y, v2 = x0.z, M2 = x0.w, invS = x1.x, tfb = x1.y;
-        const float nb0 = x1.z, nb1 = x1.w, nb2 = x2.x, kap = x2.y, Db = x2.z;
-        Geo q[KM];
-        float dl[KM];
+        for (int s0 = 0; s0 < kCompBlock && sb + s0 < end; s0 += step) {
+            __syncthreads();  // staged rays visible; the previous step is done with the slots
+            const int ry = s0 + wave * c.rpw + c.sg;
+            const float4 x0 = smem[RW * ry], x1 = smem[RW * ry + 1], x2 = smem[RW * ry + 2];
+            float4 x3 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (COLOR) x3 = smem[RW * ry + 3];
+            const float v0 = x0.x, v1 = x0.y, v2 = x0.z, M2 = x0.w, invS = x1.x, tfb = x1.y;
+            const float nb0 = x1.z, nb1 = x1.w, nb2 = x2.x, kap = x2.y, Db = x2.z;
+            Geo q[KM];
+            float dl[KM];
 #pragma unroll
-        for (int k = 0; k < KM; ++k) {
-            if (k < c.ke) {
-                pair_geo(g[k], v0, v1, v2, hm, 0.0f, 0.0f, q[k]);
-                dl[k] = gv[k] ? exp2_(q[k].d2) : 0.0f;
-                tdl[c.sbase + k * c.seg + c.sl] = make_float2(q[k].t, dl[k]);
-            }
-        }
-        __syncthreads();
-        float wt[KM], zb[KM];
-        PairNormal pn[KM];
-#pragma unroll
-        for (int k = 0; k < KM; ++k) {
-            wt[k] = zb[k] = 0.0f;
-            pn[k] = PairNormal{0, 0, 0, 0, 0};
-            if (k < c.ke) {
-                if (gv[k]) {
-                    const float front = ordered_partial<false>(tdl + c.sbase, n, q[k].t);
-                    wt[k] = exp2_(fmaf(-(float)kLog2e, front, log2_opacity(dl[k], q[k].d2)) - M2) * invS;
+            for (int k = 0; k < KM; ++k) {
+                dl[k] = 0.0f;
+                if (k < c.ke) {
+                    pair_geo(g[k], v0, v1, v2, hm, 0.0f, 0.0f, q[k]);
+                    dl[k] = gv[k] ? exp2_(q[k].d2) : 0.0f;
                 }
-                if (NORMALS) pn[k] = pair_normal(g[k], q[k], nb0, nb1, nb2);
-                float lin = fmaf(tfb, q[k].t, pn[k].nN);
-                if (COLOR) lin = fmaf(x3.x, cc[k].x, fmaf(x3.y, cc[k].y, fmaf(x3.z, cc[k].z, lin)));
-                zb[k] = wt[k] * (lin - kap);
             }
-        }
-        __syncthreads();  // everyone is done reading (t, delta)
+            const int cnt = compact_slots<KM>(tdl + c.sbase, c, q, dl);
+            __syncthreads();
+            float front[KM];
+            ordered_sums<KM, false>(tdl + c.sbase, cnt, c, q, front);
+            float wt[KM], zb[KM];
+            PairNormal pn[KM];
 #pragma unroll
-        for (int k = 0; k < KM; ++k)
-            if (k < c.ke) tdl[c.sbase + k * c.seg + c.sl] = make_float2(q[k].t, zb[k]);
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < KM; ++k) {
-            if (k < c.ke) {
-                const float behind = ordered_partial<true>(tdl + c.sbase, n, q[k].t);
-                const float db = fmaf(zb[k], opacity_slope(dl[k]), dl[k] * (Db - behind));
-                const float tb = wt[k] * tfb;
-                if (COLOR) {
-                    aC[k][0] = fmaf(wt[k], x3.x, aC[k][0]);
-                    aC[k][1] = fmaf(wt[k], x3.y, aC[k][1]);
-                    aC[k][2] = fmaf(wt[k], x3.z, aC[k][2]);
+            for (int k = 0; k < KM; ++k) {
+                wt[k] = zb[k] = 0.0f;
+                pn[k] = PairNormal{0, 0, 0, 0, 0};
+                if (k < c.ke) {
+                    if (gv[k]) wt[k] = exp2_(fmaf(-(float)kLog2e, front[k], log2_opacity(dl[k], q[k].d2)) - M2) * invS;
+                    if (NORMALS) pn[k] = pair_normal(g[k], q[k], nb0, nb1, nb2);
+                    float lin = fmaf(tfb, q[k].t, pn[k].nN);
+                    if (COLOR) lin = fmaf(x3.x, cc[k].x, fmaf(x3.y, cc[k].y, fmaf(x3.z, cc[k].z, lin)));
+                    zb[k] = wt[k] * (lin - kap);
                 }
-                pair_adjoint<NORMALS>(g[k], q[k], v0, v1, v2, wt[k], pn[k], nb0, nb1, nb2, tb, db, acc[k]);
+            }
+            __syncthreads();  // everyone is done reading (t, delta)
+            const int cnt_b = compact_slots<KM>(tdl + c.sbase, c, q, zb);
+            __syncthreads();
+            float behind[KM];
+            ordered_sums<KM, true>(tdl + c.sbase, cnt_b, c, q, behind);
+#pragma unroll
+            for (int k = 0; k < KM; ++k) {
+                if (k < c.ke) {
+                    const float db = fmaf(zb[k], opacity_slope(dl[k]), dl[k] * (Db - behind[k]));
+                    const float tb = wt[k] * tfb;
+                    if (COLOR) {
+                        aC[k][0] = fmaf(wt[k], x3.x, aC[k][0]);
+                        aC[k][1] = fmaf(wt[k], x3.y, aC[k][1]);
+                        aC[k][2] = fmaf(wt[k], x3.z, aC[k][2]);
+                    }
+                    pair_adjoint<NORMALS>(g[k], q[k], v0, v1, v2, wt[k], pn[k], nb0, nb1, nb2, tb, db, acc[k]);
+                }
             }
         }
     }
@@ -415,18 +496,20 @@ __global__ __launch_bounds__(kCompBlock) void statc_kernel(Params P, const float
         float dl[KM];
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
+            dl[k] = 0.0f;
             if (k < c.ke) {
                 pair_geo(g[k], x0.x, x0.y, x0.z, hm, 0.0f, 0.0f, q[k]);
                 dl[k] = gv[k] ? exp2_(q[k].d2) : 0.0f;
-                tdl[c.sbase + k * c.seg + c.sl] = make_float2(q[k].t, dl[k]);
             }
         }
+        const int cnt = compact_slots<KM>(tdl + c.sbase, c, q, dl);
         __syncthreads();
+        float front[KM];
+        ordered_sums<KM, false>(tdl + c.sbase, cnt, c, q, front);
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
             if (k < c.ke && gv[k]) {
-                const float front = ordered_partial<false>(tdl + c.sbase, n, q[k].t);
-                const float wt = exp2_(fmaf(-(float)kLog2e, front, log2_opacity(dl[k], q[k].d2)) - x0.w) * x1.x;
+                const float wt = exp2_(fmaf(-(float)kLog2e, front[k], log2_opacity(dl[k], q[k].d2)) - x0.w) * x1.x;
                 acc[k] = fmaf(x1.y, wt, acc[k]);
             }
         }
