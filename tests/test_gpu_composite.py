@@ -214,3 +214,39 @@ def test_composite_model_switch(fmb):
     bscene, _ = make_scene(fmb, torch, big, bcams, BETAS, 1.0, DEV)
     with pytest.raises(fmb.FmbError):
         bscene.set_model("composite")
+
+
+def test_composite_graph_replay(fmb):
+    """The compositing passes captured in HIP graphs replay like the eager calls, several times
+    with eager work in between, and see in-place parameter updates."""
+    w = W.make_config("batch16")
+    idx = [2, 5, 9]
+    scenes = [w.scenes[i] for i in idx]
+    means = _t(np.concatenate([s.means for s in scenes]))
+    prec = _t(np.concatenate([s.prec for s in scenes]))
+    weights = _t(np.concatenate([s.weights for s in scenes]))
+    betas = _t(np.tile(w.betas, (len(scenes), 1)))
+    cams = [fmb.Cameras.from_numpy(w.cameras[i].w2c, w.cameras[i].intr, w.cameras[i].hw, device=DEV) for i in idx]
+    b = fmb.Batch(means, prec, weights, betas, [w.eta] * len(scenes), [s.n for s in scenes], cams)
+    b.set_model("composite")
+    gc = W.random_cotangents(b.n_rays, 55, flow=False)
+    cot = {"depth": _t(gc["depth"]), "alpha": _t(gc["alpha"]), "normal": _t(gc["normal"]), "flow": None}
+    outs_g, grads_g = b.alloc_outputs(normals=True), b.alloc_grads()
+    outs_e, grads_e = b.alloc_outputs(normals=True), b.alloc_grads()
+    st = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    _say(f"[composite-graph] scenes {idx} P={b.n_rays}")
+    b.capture(outs_g, cot, grads_g, st)
+    for rep in range(3):
+        with torch.cuda.stream(st):
+            b.graph_launch(2, st)
+        st.synchronize()
+        b.forward(outs_e)
+        b.backward(outs_e, cot, grads_e)
+        torch.cuda.synchronize()
+        for k in ("depth", "alpha", "normal", "stash"):
+            assert torch.equal(outs_g[k], outs_e[k]), (rep, k)
+        for k in ("means", "prec", "weights", "betas"):
+            assert torch.equal(grads_g[k], grads_e[k]), (rep, k)
+        with torch.no_grad():
+            means.add_(0.001)
