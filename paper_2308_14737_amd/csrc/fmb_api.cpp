@@ -1104,8 +1104,12 @@ int fmb_get_config(const fmb_scene *s, const fmb_batch *b, int32_t *out)
     out[3] = bwd_variant_rt(j.bwd_variant) > 0 ? bwd_variant_rt(j.bwd_variant) : bwd_variant_ray_tile(j.bwd_variant);
     out[4] = j.persist_mult[0];
     out[5] = j.persist_mult[1];
-    out[6] = j.fwd_built >= 0 ? j.n_fitems : 0;
-    out[7] = j.bwd_built >= 0 ? j.n_bitems : 0;
+    // item counts of the lists built for the configuration in use (0 until built)
+    const bool comp = j.model == FMB_MODEL_COMPOSITE;
+    const bool bwd_cur = comp ? (j.bwd_built == 1 || j.bwd_built == 3)
+                              : (j.bwd_built >= 0 && j.bwd_built % 2 == 0 && j.bwd_built / 4 == j.bwd_variant);
+    out[6] = comp ? (bwd_cur ? j.n_bitems : 0) : (j.fwd_built == j.fwd_variant ? j.n_fitems : 0);
+    out[7] = bwd_cur ? j.n_bitems : 0;
     return FMB_OK;
 }
 

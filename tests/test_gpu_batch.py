@@ -170,3 +170,59 @@ def test_ray_lane_batch_bitwise(fmb, batch16, variant):
             assert torch.equal(gi[k], grads[k][g0:g1]), (i, k)
         assert torch.equal(gi["betas"], grads["betas"][i]), (i, "betas")
     fmb.set_launch_config(batch=b)
+
+
+def test_bench_configuration(fmb, batch16):
+    """The benchmark's own configuration: the autotuned persistent kernels on batch16 with the
+    loss kernel's cotangents.  Forward outputs on sampled rays of four scenes and the gradient of
+    one scene (cotangents kept on sampled rays of that scene only) against the oracle."""
+    w, b, (means, prec, weights, betas) = batch16
+    outs = b.alloc_outputs(normals=True)
+    grads = b.alloc_grads()
+    g = np.random.Generator(np.random.PCG64(91))
+    d_t = torch.as_tensor(g.uniform(1.0, 5.0, b.n_rays).astype(np.float32), device=DEV)
+    a_t = torch.as_tensor((g.uniform(0, 1, b.n_rays) > 0.5).astype(np.float32), device=DEV)
+    cot = {"depth": torch.empty(b.n_rays, device=DEV), "alpha": torch.empty(b.n_rays, device=DEV),
+           "normal": None, "flow": None}
+    b.forward(outs)
+    fmb.loss_grad(outs, d_t, a_t, cot=cot)
+    b.backward(outs, cot, grads)
+    b.autotune(outs, cot, grads)
+    cfg = fmb.launch_config(batch=b)
+    _say(f"[bench-config] {cfg}")
+    b.forward(outs)
+    fmb.loss_grad(outs, d_t, a_t, cot=cot)
+    torch.cuda.synchronize()
+    sc_means = to_np(means).astype(np.float32)
+    sc_prec = to_np(prec).astype(np.float32)
+    sc_weights = to_np(weights).astype(np.float32)
+    for i in (0, 3, 8, 12):
+        cams = w.cameras[i]
+        g0, g1 = b.gauss_off[i], b.gauss_off[i + 1]
+        r0, r1 = b.ray_off[i], b.ray_off[i + 1]
+        sc = W.Scene(sc_means[g0:g1], sc_prec[g0:g1], sc_weights[g0:g1])
+        rays = np.sort(g.choice(r1 - r0, size=min(3000, r1 - r0), replace=False))
+        ref, _, _ = O.render_workload_view(sc, cams, to_np(betas[i]).astype(np.float32), w.eta, rays=rays)
+        sub = {k: (None if v is None else v[r0:r1]) for k, v in outs.items()}
+        e = compare_forward(sub, ref, rays)
+        _say(f"[bench-config] scene {i} forward {e}")
+        assert_forward(e, f"bench configuration scene {i}")
+    i = 8
+    cams = w.cameras[i]
+    g0, g1 = b.gauss_off[i], b.gauss_off[i + 1]
+    r0, r1 = b.ray_off[i], b.ray_off[i + 1]
+    rays = np.sort(g.choice(r1 - r0, size=3000, replace=False))
+    keep = torch.zeros(b.n_rays, device=DEV)
+    keep[r0 + torch.as_tensor(rays, device=DEV)] = 1.0
+    masked = {"depth": cot["depth"] * keep, "alpha": cot["alpha"] * keep, "normal": None, "flow": None}
+    grads = b.backward(outs, masked, grads)
+    torch.cuda.synchronize()
+    sc = W.Scene(sc_means[g0:g1], sc_prec[g0:g1], sc_weights[g0:g1])
+    cs = {"depth": to_np(masked["depth"])[r0 + rays], "alpha": to_np(masked["alpha"])[r0 + rays],
+          "normal": None, "flow": None}
+    _, gref, _ = O.render_workload_view(sc, cams, to_np(betas[i]).astype(np.float32), w.eta, rays=rays, cot=cs)
+    gs = {"means": grads["means"][g0:g1], "prec": grads["prec"][g0:g1], "weights": grads["weights"][g0:g1],
+          "betas": grads["betas"][i]}
+    e = compare_grads(gs, gref)
+    _say(f"[bench-config] scene {i} backward {e}")
+    assert_grads(e, "bench configuration backward")

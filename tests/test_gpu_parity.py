@@ -511,3 +511,27 @@ def test_backward_variants(fmb, variant, label, n, views):
     eg["colors"] = normwise(to_np(gr["colors"]), gref["colors"])
     _say(f"[variant] {label} v{variant}: {eg}")
     assert_grads(eg, f"{label} variant {variant}")
+
+
+@pytest.mark.parametrize("variant", range(4))
+def test_forward_variants(fmb, variant):
+    """Every forward tile variant (rays per lane 1, 2, 4; tile 128 or 256 Gaussians) against the
+    oracle on ragged views, with normals, two-way flow and colour."""
+    sc, cams = custom_scene(257, [(40, 50), (3, 7), (1, 1)], seed=400, flow=True)
+    cams = W.with_backward_flow(cams, seed=401)
+    g = np.random.Generator(np.random.PCG64(402))
+    q = (1.5 * g.standard_normal((sc.n, 3))).astype(np.float32)
+    betas = np.array([W.BETA1, W.BETA2], np.float32)
+    _say(f"[fwd-variant] {variant}: N={sc.n} P={cams.n_rays}")
+    scene, _ = make_scene(fmb, torch, sc, cams, betas, 1.0, DEV)
+    fmb.set_launch_config(scene=scene, fwd_variant=variant)
+    scene.set_colors(torch.as_tensor(q, device=DEV).contiguous())
+    outs = scene.render(normals=True)
+    torch.cuda.synchronize()
+    assert fmb.launch_config(scene=scene)["fwd_variant"] == variant
+    ref, _, _ = O.render_workload_view(sc, cams, betas, 1.0, colors=q)
+    e = compare_forward(outs, ref)
+    e["color"] = normwise(to_np(outs["color"]), ref["color"])
+    _say(f"[fwd-variant] {variant}: {e}")
+    assert_forward(e, f"forward variant {variant}")
+    assert e["color"] <= TOL_REL
