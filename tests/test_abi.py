@@ -74,3 +74,24 @@ def test_batch_create_rejects_bad_sizes(lib):
     hw = (ctypes.c_int32 * 4)(4, 4, 4, 4)
     rc = lib.fmb_batch_create(ctypes.byref(h), 2, n, v, fake, fake, fake, fake, eta, fake, fake, hw, None, None)
     assert rc == 1 and b">= 1 Gaussian" in lib.fmb_last_error()
+
+
+def test_new_entry_points_reject_bad_arguments(lib):
+    """Model, flow-target, configuration, split-statistic and split entry points check their
+    arguments on the host."""
+    assert lib.fmb_set_model(None, None, 1) == 1
+    assert lib.fmb_set_flow_pose2(None, None, None, None) == 1
+    assert lib.fmb_set_config(None, None, 0, 0, 1, 1) == 1
+    assert lib.fmb_split_statistic(None, None, None, None, None, None) == 1
+    assert lib.fmb_prune_mask(0, None, ctypes.c_float(2.0), None) == 1
+    assert lib.fmb_split_mask(0, None, ctypes.c_float(1.0), None) == 1
+    assert lib.fmb_split_gaussians(-1, *([None] * 10)) == 1
+    # a precision factor that is not positive definite is refused
+    mean = (ctypes.c_float * 3)(0, 0, 0)
+    prec = (ctypes.c_float * 6)(0, 0, 0, 0, 0, 0)
+    w = (ctypes.c_float * 1)(1.0)
+    nw = (ctypes.c_float * 2)(0, 0)
+    om, op, ow = (ctypes.c_float * 6)(), (ctypes.c_float * 12)(), (ctypes.c_float * 2)()
+    assert lib.fmb_split_gaussians(1, mean, prec, w, None, nw, None, om, op, ow, None) == 1
+    assert lib.fmb_loss_grad(4, *([None] * 8), ctypes.c_float(1), ctypes.c_float(1), 2, 3, ctypes.c_float(1),
+                             *([None] * 5), None) == 1
