@@ -43,7 +43,6 @@ FLOPS_COMP_FWD_NORMALS = 81   # + 2N per pair
 FLOPS_COMP_ADJ_PLAIN = 73     # + 2N per pair (the front sum is recomputation, not counted)
 PEAK_FP32 = 157.3e12       # MI355X FP32 vector peak (packed FP32 at 2.4 GHz x 256 CUs)
 PEAK_FP32_SCALAR = 78.6e12  # without packed FP32 issue
-PEAK_HBM = 8.0e12
 
 
 def _profile_values(name):
@@ -332,6 +331,10 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": measured_traffic(),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
                      "kernel": "bwd_kernel (persistent)", "flops_per_pair": FLOPS_ADJ_PLAIN,
+                     "algorithmic_flops_per_pair": {"forward_normals": FLOPS_FWD_NORMALS,
+                                                    "forward_plain": FLOPS_FWD_PLAIN,
+                                                    "adjoint_normals": FLOPS_ADJ_NORMALS,
+                                                    "adjoint_plain": FLOPS_ADJ_PLAIN},
                      "peak_scalar_fp32": PEAK_FP32_SCALAR / 1e12, **executed(pairs, bwd_ms)},
     }
     if not args.no_cpu_baseline:
