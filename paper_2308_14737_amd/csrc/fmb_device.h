@@ -108,13 +108,16 @@ __device__ __forceinline__ void project(const float *__restrict__ e, const float
 // Geometry of one (ray, Gaussian) pair.
 struct Geo {
     float a0, a1, a2, raa;  // a = U v, 1/(a.a)
-    float t;                // refined peak depth
+    float t;                // peak depth (first estimate, refined by pair_refine)
     float r0, r1, r2;       // r = U (t v - mu')
     float d2, z2;           // log2 density, log2 blend weight
 };
 
-__device__ __forceinline__ void pair_geo(const Ent &g, float v0, float v1, float v2, float hm, float b1,
-                                         float nc2, Geo &q)
+// First estimate of the peak: t = v.c / a.a and r = U (t v - mu') with mu' = hi + lo as
+// U (t v - hi) - U lo, then m = r.r, the log2 density d2 and the log2 weight z2.  The error
+// of t enters m only to second order (m is minimal at the peak), so d2 and z2 are final here.
+__device__ __forceinline__ void pair_geo_coarse(const Ent &g, float v0, float v1, float v2, float hm, float b1,
+                                                float nc2, Geo &q)
 {
     q.a0 = fmaf(g.u00, v0, fmaf(g.u01, v1, g.u02 * v2));
     q.a1 = fmaf(g.u11, v1, g.u12 * v2);
@@ -122,22 +125,35 @@ __device__ __forceinline__ void pair_geo(const Ent &g, float v0, float v1, float
     const float aa = fmaf(q.a0, q.a0, fmaf(q.a1, q.a1, q.a2 * q.a2));
     const float vc = fmaf(v0, g.c0, fmaf(v1, g.c1, v2 * g.c2));
     q.raa = rcp_(aa);
-    const float t0 = vc * q.raa;
-    const float w0 = fmaf(t0, v0, -g.mh0);
-    const float w1 = fmaf(t0, v1, -g.mh1);
-    const float w2 = fmaf(t0, v2, -g.mh2);
-    const float r0 = fmaf(g.u00, w0, fmaf(g.u01, w1, fmaf(g.u02, w2, -g.ul0)));
-    const float r1 = fmaf(g.u11, w1, fmaf(g.u12, w2, -g.ul1));
-    const float r2 = fmaf(g.u22, w2, -g.ul2);
-    // one Newton step on t -> |U (t v - mu')|^2 (exactly quadratic): dt = (a.r)/(a.a)
-    const float dt = fmaf(q.a0, r0, fmaf(q.a1, r1, q.a2 * r2)) * q.raa;
-    q.t = t0 - dt;
-    q.r0 = fmaf(-dt, q.a0, r0);
-    q.r1 = fmaf(-dt, q.a1, r1);
-    q.r2 = fmaf(-dt, q.a2, r2);
+    q.t = vc * q.raa;
+    const float w0 = fmaf(q.t, v0, -g.mh0);
+    const float w1 = fmaf(q.t, v1, -g.mh1);
+    const float w2 = fmaf(q.t, v2, -g.mh2);
+    q.r0 = fmaf(g.u00, w0, fmaf(g.u01, w1, fmaf(g.u02, w2, -g.ul0)));
+    q.r1 = fmaf(g.u11, w1, fmaf(g.u12, w2, -g.ul1));
+    q.r2 = fmaf(g.u22, w2, -g.ul2);
     const float m = fmaf(q.r0, q.r0, fmaf(q.r1, q.r1, q.r2 * q.r2));
     q.d2 = fmaf(hm, m, g.l2l);
     q.z2 = fmaf(b1, q.d2, nc2 * q.t);
+}
+
+// One Newton step on t -> |U (t v - mu')|^2 (exactly quadratic): dt = (a.r)/(a.a).  The
+// residual r, unlike m, has a first-order error in t, and the normal g = U^T r amplifies it
+// by |U|; after the step a.r = 0 to rounding, which the adjoint relies on.
+__device__ __forceinline__ void pair_refine(Geo &q)
+{
+    const float dt = fmaf(q.a0, q.r0, fmaf(q.a1, q.r1, q.a2 * q.r2)) * q.raa;
+    q.t -= dt;
+    q.r0 = fmaf(-dt, q.a0, q.r0);
+    q.r1 = fmaf(-dt, q.a1, q.r1);
+    q.r2 = fmaf(-dt, q.a2, q.r2);
+}
+
+__device__ __forceinline__ void pair_geo(const Ent &g, float v0, float v1, float v2, float hm, float b1,
+                                         float nc2, Geo &q)
+{
+    pair_geo_coarse(g, v0, v1, v2, hm, b1, nc2, q);
+    pair_refine(q);
 }
 
 // Per-item blend constants of a scene: hm = -log2(e)/2, b1 = beta1, nc2 = -beta2 log2(e)/eta.

@@ -33,7 +33,7 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
                                                    int n_items, const int *__restrict__ order,
                                                    int *__restrict__ counter)
 {
-    constexpr bool NORMALS = (F & kNrm) != 0, FLOW = (F & kFlw) != 0, PERSIST = (F & kPer) != 0;
+    constexpr bool NORMALS = (F & kNrm) != 0, PERSIST = (F & kPer) != 0;
     constexpr bool COLOR = (F & kCol) != 0;
     constexpr int EW = COLOR ? 5 : 4;  // float4 per LDS entry
     __shared__ float4 tile[TG * EW];
@@ -87,12 +87,13 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
 #pragma unroll
                 for (int j = 0; j < RPT; ++j) {
                     Geo q;
-                    pair_geo(g, v0[j], v1[j], v2[j], bl.hm, bl.b1, bl.nc2, q);
+                    pair_geo_coarse(g, v0[j], v1[j], v2[j], bl.hm, bl.b1, bl.nc2, q);
                     const float delta = exp2_(q.d2);
                     D[j] += delta;
                     // A weight below 2^-150 of the running maximum is zero in FP32: its terms are
                     // skipped (the branch is uniform over a wave for most distant Gaussians).
                     if (q.z2 - M[j] < kSkipLog2) continue;
+                    pair_refine(q);
                     if (q.z2 > M[j]) {  // new running maximum: rescale the sums (rare)
                         const float sc = exp2_(M[j] - q.z2);
                         S[j] *= sc;
@@ -609,8 +610,8 @@ __global__ __launch_bounds__(BLOCK) void stat_kernel(Params P, const float *__re
         if (active) {
             for (int j = slot; j < cnt; j += item.slots) {
                 const float4 x0 = rays[2 * j], x1 = rays[2 * j + 1];
-                Geo q;
-                pair_geo(g, x0.x, x0.y, x0.z, bl.hm, bl.b1, bl.nc2, q);
+                Geo q;  // the weight needs no refined peak
+                pair_geo_coarse(g, x0.x, x0.y, x0.z, bl.hm, bl.b1, bl.nc2, q);
                 if (q.z2 - x0.w >= kSkipLog2) acc = fmaf(x1.y, exp2_(q.z2 - x0.w) * x1.x, acc);
             }
         }
