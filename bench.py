@@ -41,8 +41,7 @@ FLOPS_ADJ_PLAIN = 61       # adjoint of depth/alpha/flow cotangents only
 # backward adds the sum over the Gaussians behind (another 2N) and the opacity slope.
 FLOPS_COMP_FWD_NORMALS = 81   # + 2N per pair
 FLOPS_COMP_ADJ_PLAIN = 73     # + 2N per pair (the front sum is recomputation, not counted)
-PEAK_FP32 = 157.3e12       # MI355X FP32 vector peak (packed FP32 at 2.4 GHz x 256 CUs)
-PEAK_FP32_SCALAR = 78.6e12  # without packed FP32 issue
+PEAK_FP32 = 157.3e12       # MI355X FP32 vector peak (published; 256 CUs x 128 FMA lanes x 2.4 GHz)
 
 
 def _profile_values(name):
@@ -335,7 +334,7 @@ def main():
                                                     "forward_plain": FLOPS_FWD_PLAIN,
                                                     "adjoint_normals": FLOPS_ADJ_NORMALS,
                                                     "adjoint_plain": FLOPS_ADJ_PLAIN},
-                     "peak_scalar_fp32": PEAK_FP32_SCALAR / 1e12, **executed(pairs, bwd_ms)},
+                     **executed(pairs, bwd_ms)},
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
