@@ -345,7 +345,7 @@ __global__ __launch_bounds__(kCompBlock) void bwdc_kernel(Params P, BwdIn I, con
         __syncthreads();  // the previous stage is done with the staged rays
         {
             float4 pr[4];
-            ray_prologue<F>(P, I, item.view, vr, e, kk, o0, o1, o2, sb + tid, sb + tid < end, pr);
+            ray_prologue<F>(P, I, item.view, vr, e, kk, o0, o1, o2, sb + tid, sb + tid < end, 0.0f, 0.0f, pr);
 #pragma unroll
             for (int w = 0; w < RW; ++w) smem[RW * tid + w] = pr[w];
         }

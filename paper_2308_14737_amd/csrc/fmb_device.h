@@ -142,11 +142,21 @@ __device__ __forceinline__ void pair_geo_coarse(const Ent &g, float v0, float v1
 // by |U|; after the step a.r = 0 to rounding, which the adjoint relies on.
 __device__ __forceinline__ void pair_refine(Geo &q)
 {
-    const float dt = fmaf(q.a0, q.r0, fmaf(q.a1, q.r1, q.a2 * q.r2)) * q.raa;
+    // __fmul_rn keeps the product out of any contraction, so that pair_refine_t gives the
+    // same t bit for bit (the backward's softmax adjoint relies on it)
+    const float dt = __fmul_rn(fmaf(q.a0, q.r0, fmaf(q.a1, q.r1, q.a2 * q.r2)), q.raa);
     q.t -= dt;
     q.r0 = fmaf(-dt, q.a0, q.r0);
     q.r1 = fmaf(-dt, q.a1, q.r1);
     q.r2 = fmaf(-dt, q.a2, q.r2);
+}
+
+// The Newton step on t alone, for code that needs the refined depth but not r (the depth the
+// forward blends is the refined one, and its adjoint must see the same value).
+__device__ __forceinline__ void pair_refine_t(Geo &q)
+{
+    const float dt = __fmul_rn(fmaf(q.a0, q.r0, fmaf(q.a1, q.r1, q.a2 * q.r2)), q.raa);
+    q.t -= dt;
 }
 
 __device__ __forceinline__ void pair_geo(const Ent &g, float v0, float v1, float v2, float hm, float b1,
@@ -263,16 +273,20 @@ __device__ __forceinline__ float flow_dot(const float *__restrict__ e, const flo
     return fmaf(g[0], j0, g[1] * j1);
 }
 
-// Per-ray adjoint prologue, staged in LDS as RW float4:
-//   (v0, v1, v2, M2) (invS, tf_bar, Nb0, Nb1) (Nb2, kappa, D_bar, 0) [(Cb0, Cb1, Cb2, 0)]
+// Per-ray adjoint prologue:
+//   (v0, v1, v2, M2) (invS, tf_bar, Nb0, Nb1) (Nb2, kappa, D_bar, t_f) (Cb0, Cb1, Cb2, dc)
 // with tf_bar = dL/dt_f (depth + flow), Nb = dL/dN for the unnormalised blended normal,
 // Cb = dL/dC for the blended colour, kappa = tf_bar t_f + Nb.N + Cb.C, and
-// D_bar = dL/d(sum delta) = g_alpha exp(-D).
+// D_bar = dL/d(sum delta) = g_alpha exp(-D).  t_f and dc centre the blend-parameter sums: the
+// softmax adjoints z_bar_i of a ray sum to zero, so sum z_bar_i (t_i - t_f) and
+// sum z_bar_i (d2_i - dc) equal sum z_bar_i t_i and sum z_bar_i d2_i, without the rounding
+// residual of sum z_bar_i times a large depth or log-density; dc = (M2 - nc2 t_f) / b1 is the
+// log2 density of a Gaussian at depth t_f with the ray's largest weight (0 without b1).
 template <int F>
 __device__ __forceinline__ void ray_prologue(const Params &P, const BwdIn &I, int view, const ViewRec &vr,
                                              const float *__restrict__ e, const float *__restrict__ kk,
                                              const float o0, const float o1, const float o2, int local,
-                                             bool valid, float4 out[4])
+                                             bool valid, float b1, float nc2, float4 out[4])
 {
     constexpr bool NORMALS = (F & kNrm) != 0, FLOW = (F & kFlw) != 0, COLOR = (F & kCol) != 0;
     if (!valid) {
@@ -319,10 +333,12 @@ __device__ __forceinline__ void ray_prologue(const Params &P, const BwdIn &I, in
         cb2 = I.g_color[3 * r + 2];
         kap = fmaf(cb0, I.color[3 * r], fmaf(cb1, I.color[3 * r + 1], fmaf(cb2, I.color[3 * r + 2], kap)));
     }
+    float dc = (s0.x - nc2 * tf) / b1;
+    if (!isfinite(dc)) dc = 0.0f;
     out[0] = make_float4(v0, v1, v2, s0.x);
     out[1] = make_float4(s0.y, tfb, nb0, nb1);
-    out[2] = make_float4(nb2, kap, Db, 0.0f);
-    out[3] = make_float4(cb0, cb1, cb2, 0.0f);
+    out[2] = make_float4(nb2, kap, Db, tf);
+    out[3] = make_float4(cb0, cb1, cb2, dc);
 }
 
 // Normal of Eq. (17) for one pair: g = U^T r = Sigma^-1 x, n = g / |g|, and n . Nb for the
@@ -403,6 +419,77 @@ __device__ __forceinline__ void pair_adjoint(const Ent &g, const Geo &q, float v
     a.p0 += p0;
     a.p1 += p1;
     a.p2 += p2;
+}
+
+// Adjoint of one pair without a normal cotangent, in a form that needs neither r nor the
+// refined peak.  With a = U v, b = U mu' and r = t a - b at the peak, the per-pair terms of the
+// general adjoint are rho = -beta a + db b and k = alpha a + beta b, where
+//   tau = tb / (a.a),  beta = tau + db t,  alpha = -t (tau + beta),
+// so over the rays of one view sum k v^T = U A + b Bv^T and sum rho = -U Bv + L b with
+//   A = sum alpha v v^T (symmetric),  Bv = sum beta v,  L = sum db.
+// A lane therefore accumulates A (6), Bv (3) and L; write_partial_plain forms the record.
+// The envelope condition a.r = 0 is not needed to the last bit: it enters only through terms of
+// relative size |t - t_peak| |a| / |r|, so r may be the first estimate's residual; t itself is
+// the refined peak depth, the one the forward blended.
+struct PlainAcc {
+    float a00 = 0, a01 = 0, a02 = 0, a11 = 0, a12 = 0, a22 = 0;
+    float b0 = 0, b1 = 0, b2 = 0;
+    float l = 0;
+};
+
+// vv = (v0 v0, v0 v1, v0 v2, v1 v1) and (v1 v2, v2 v2) of the ray, staged with it.
+__device__ __forceinline__ void pair_adjoint_plain(float t, float raa, float v0, float v1, float v2,
+                                                   const float4 &vva, const float4 &vvb, float tb, float db,
+                                                   PlainAcc &a)
+{
+    const float tau = tb * raa;
+    const float be = fmaf(db, t, tau);
+    const float al = -t * (tau + be);
+    a.a00 = fmaf(al, vva.x, a.a00);
+    a.a01 = fmaf(al, vva.y, a.a01);
+    a.a02 = fmaf(al, vva.z, a.a02);
+    a.a11 = fmaf(al, vva.w, a.a11);
+    a.a12 = fmaf(al, vvb.x, a.a12);
+    a.a22 = fmaf(al, vvb.y, a.a22);
+    a.b0 = fmaf(be, v0, a.b0);
+    a.b1 = fmaf(be, v1, a.b1);
+    a.b2 = fmaf(be, v2, a.b2);
+    a.l += db;
+}
+
+// Partial record of one Gaussian from the sums (A, Bv, L) of pair_adjoint_plain, in double:
+// dU = U A + b Bv^T - (sum rho) mu'^T (upper triangle), sum rho = L b - U Bv, dL/dlog(lambda)
+// = L, then the remaining values (colour) as given.
+__device__ __forceinline__ void write_partial_plain(float *__restrict__ dst, const float *acc, int rec,
+                                                    const float *__restrict__ prec, const float *__restrict__ mu,
+                                                    const double o[3])
+{
+    const double u00 = prec[0], u01 = prec[1], u02 = prec[2], u11 = prec[3], u12 = prec[4], u22 = prec[5];
+    const double m0 = (double)mu[0] - o[0], m1 = (double)mu[1] - o[1], m2 = (double)mu[2] - o[2];
+    const double A00 = acc[0], A01 = acc[1], A02 = acc[2], A11 = acc[3], A12 = acc[4], A22 = acc[5];
+    const double B0 = acc[6], B1 = acc[7], B2 = acc[8], L = acc[9];
+    const double b0 = u00 * m0 + u01 * m1 + u02 * m2, b1 = u11 * m1 + u12 * m2, b2 = u22 * m2;
+    const double r0 = L * b0 - (u00 * B0 + u01 * B1 + u02 * B2);
+    const double r1 = L * b1 - (u11 * B1 + u12 * B2);
+    const double r2 = L * b2 - u22 * B2;
+    // rows of U A (upper rows only are needed: entries (0,0..2), (1,1..2), (2,2))
+    const double ua00 = u00 * A00 + u01 * A01 + u02 * A02;
+    const double ua01 = u00 * A01 + u01 * A11 + u02 * A12;
+    const double ua02 = u00 * A02 + u01 * A12 + u02 * A22;
+    const double ua11 = u11 * A11 + u12 * A12;
+    const double ua12 = u11 * A12 + u12 * A22;
+    const double ua22 = u22 * A22;
+    dst[0] = (float)(ua00 + b0 * B0 - r0 * m0);
+    dst[1] = (float)(ua01 + b0 * B1 - r0 * m1);
+    dst[2] = (float)(ua02 + b0 * B2 - r0 * m2);
+    dst[3] = (float)(ua11 + b1 * B1 - r1 * m1);
+    dst[4] = (float)(ua12 + b1 * B2 - r1 * m2);
+    dst[5] = (float)(ua22 + b2 * B2 - r2 * m2);
+    dst[6] = (float)r0;
+    dst[7] = (float)r1;
+    dst[8] = (float)r2;
+    dst[9] = (float)L;
+    for (int c = 10; c < rec; ++c) dst[c] = acc[c];
 }
 
 // Write one Gaussian's partial record: dU with the -(sum rho) mu'^T term applied in double

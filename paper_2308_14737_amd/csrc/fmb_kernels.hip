@@ -154,11 +154,18 @@ __global__ __launch_bounds__(BLOCK) void bwd_kernel(Params P, BwdIn I, const Bwd
                                                    float *__restrict__ beta_partial)
 {
     constexpr bool NORMALS = (F & kNrm) != 0, PERSIST = (F & kPer) != 0, COLOR = (F & kCol) != 0;
-    constexpr int RW = COLOR ? 4 : 3;             // float4 per staged ray
+    // Without a normal cotangent the pairs take pair_adjoint_plain: the staged ray is
+    // (v, M2) (invS, tf_bar, kappa, D_bar) (v v^T: 4) (v v^T: 2, t_f, dc) [(Cb, 0)]; with one it
+    // is the prologue as written by ray_prologue (four float4).
+    constexpr bool PLAIN = !NORMALS;
+    constexpr int RW = PLAIN ? (COLOR ? 5 : 4) : 4;  // float4 per staged ray
     constexpr int REC = COLOR ? kPartialColor : kPartial;  // partial record per Gaussian
     constexpr int RS = REC + 2;                   // reduction record per lane (+ two betas)
-    __shared__ float4 rays[RT * RW];
-    __shared__ float red[BLOCK * RS];
+    // the staged rays and, after an item's pair loop, the reduction records share the LDS
+    constexpr int SM4 = RT * RW > BLOCK * RS / 4 ? RT * RW : (BLOCK * RS + 3) / 4;
+    __shared__ float4 smem[SM4];
+    float4 *rays = smem;
+    float *red = reinterpret_cast<float *>(smem);
     __shared__ int s_item;
     int pos = blockIdx.x;
     const int tid = threadIdx.x;
@@ -196,6 +203,7 @@ __global__ __launch_bounds__(BLOCK) void bwd_kernel(Params P, BwdIn I, const Bwd
             if (COLOR) cc = colour_entry(P.colors + 3 * gg);
         }
         PairAcc acc;
+        PlainAcc pacc;
         float aB1 = 0, aB2 = 0;
         float aC0 = 0, aC1 = 0, aC2 = 0;
 
@@ -204,16 +212,51 @@ __global__ __launch_bounds__(BLOCK) void bwd_kernel(Params P, BwdIn I, const Bwd
             __syncthreads();
             for (int q = tid; q < RT; q += BLOCK) {
                 float4 pr[4];
-                ray_prologue<F>(P, I, item.view, vr, e, kk, o0, o1, o2, r0 + q, q < cnt, pr);
+                ray_prologue<F>(P, I, item.view, vr, e, kk, o0, o1, o2, r0 + q, q < cnt, bl.b1, bl.nc2, pr);
+                if (PLAIN) {
+                    const float v0 = pr[0].x, v1 = pr[0].y, v2 = pr[0].z;
+                    rays[RW * q] = pr[0];
+                    rays[RW * q + 1] = make_float4(pr[1].x, pr[1].y, pr[2].y, pr[2].z);
+                    rays[RW * q + 2] = make_float4(v0 * v0, v0 * v1, v0 * v2, v1 * v1);
+                    rays[RW * q + 3] = make_float4(v1 * v2, v2 * v2, pr[2].w, pr[3].w);
+                    if (COLOR) rays[RW * q + 4] = pr[3];
+                } else {
 #pragma unroll
-                for (int k = 0; k < RW; ++k) rays[RW * q + k] = pr[k];
+                    for (int k = 0; k < RW; ++k) rays[RW * q + k] = pr[k];
+                }
             }
             __syncthreads();
-            if (active) {
+            if (active && PLAIN) {
+                for (int j = slot; j < cnt; j += item.slots) {
+                    const float4 x0 = rays[RW * j], x1 = rays[RW * j + 1];
+                    const float4 vva = rays[RW * j + 2], vvb = rays[RW * j + 3];
+                    float4 x4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                    if (COLOR) x4 = rays[RW * j + 4];
+                    const float v0 = x0.x, v1 = x0.y, v2 = x0.z;
+                    Geo q;
+                    pair_geo_coarse(g, v0, v1, v2, bl.hm, bl.b1, bl.nc2, q);
+                    pair_refine_t(q);
+                    const float delta = exp2_(q.d2);
+                    const float wt = exp2_(q.z2 - x0.w) * x1.x;   // normalised blend weight
+                    const float tfb = x1.y;
+                    float lin = tfb * q.t;
+                    if (COLOR) {
+                        lin = fmaf(x4.x, cc.x, fmaf(x4.y, cc.y, fmaf(x4.z, cc.z, lin)));
+                        aC0 = fmaf(wt, x4.x, aC0);
+                        aC1 = fmaf(wt, x4.y, aC1);
+                        aC2 = fmaf(wt, x4.z, aC2);
+                    }
+                    const float zb = wt * (lin - x1.z);
+                    const float tb = fmaf(-bl.cb, zb, wt * tfb);
+                    const float db = fmaf(bl.b1, zb, x1.w * delta);
+                    aB1 = fmaf(zb, q.d2 - vvb.w, aB1);
+                    aB2 = fmaf(zb, q.t - vvb.z, aB2);
+                    pair_adjoint_plain(q.t, q.raa, v0, v1, v2, vva, vvb, tb, db, pacc);
+                }
+            } else if (active) {
                 for (int j = slot; j < cnt; j += item.slots) {
                     const float4 x0 = rays[RW * j], x1 = rays[RW * j + 1], x2 = rays[RW * j + 2];
-                    float4 x3 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                    if (COLOR) x3 = rays[RW * j + 3];
+                    const float4 x3 = rays[RW * j + 3];
                     const float v0 = x0.x, v1 = x0.y, v2 = x0.z;
                     Geo q;
                     pair_geo(g, v0, v1, v2, bl.hm, bl.b1, bl.nc2, q);
@@ -234,8 +277,8 @@ __global__ __launch_bounds__(BLOCK) void bwd_kernel(Params P, BwdIn I, const Bwd
                     // z = beta1 d - (beta2/eta) t
                     const float tb = fmaf(-bl.cb, zb, wt * tfb);
                     const float db = fmaf(bl.b1, zb, x2.z * delta);
-                    aB1 = fmaf(zb, q.d2, aB1);
-                    aB2 = fmaf(zb, q.t, aB2);
+                    aB1 = fmaf(zb, q.d2 - x3.w, aB1);
+                    aB2 = fmaf(zb, q.t - x2.w, aB2);
                     pair_adjoint<NORMALS>(g, q, v0, v1, v2, wt, pn, x1.z, x1.w, x2.x, tb, db, acc);
                 }
             }
@@ -245,8 +288,13 @@ __global__ __launch_bounds__(BLOCK) void bwd_kernel(Params P, BwdIn I, const Bwd
         __syncthreads();
         {
             float *my = red + RS * tid;
-            my[0] = acc.u0; my[1] = acc.u1; my[2] = acc.u2; my[3] = acc.u3; my[4] = acc.u4; my[5] = acc.u5;
-            my[6] = acc.p0; my[7] = acc.p1; my[8] = acc.p2; my[9] = acc.l;
+            if (PLAIN) {
+                my[0] = pacc.a00; my[1] = pacc.a01; my[2] = pacc.a02; my[3] = pacc.a11; my[4] = pacc.a12;
+                my[5] = pacc.a22; my[6] = pacc.b0; my[7] = pacc.b1; my[8] = pacc.b2; my[9] = pacc.l;
+            } else {
+                my[0] = acc.u0; my[1] = acc.u1; my[2] = acc.u2; my[3] = acc.u3; my[4] = acc.u4; my[5] = acc.u5;
+                my[6] = acc.p0; my[7] = acc.p1; my[8] = acc.p2; my[9] = acc.l;
+            }
             if (COLOR) {
                 my[10] = aC0; my[11] = aC1; my[12] = aC2;
             }
@@ -261,7 +309,11 @@ __global__ __launch_bounds__(BLOCK) void bwd_kernel(Params P, BwdIn I, const Bwd
 #pragma unroll
                 for (int c = 0; c < REC; ++c) sum[c] += red[RS * (s * item.gc + gi) + c];
             }
-            write_partial(partial + item.poff + REC * gi, sum, REC, P.means + 3 * (sr.gauss_off + item.g0 + gi), o);
+            const int gg = sr.gauss_off + item.g0 + gi;
+            if (PLAIN)
+                write_partial_plain(partial + item.poff + REC * gi, sum, REC, P.prec + 6 * gg, P.means + 3 * gg, o);
+            else
+                write_partial(partial + item.poff + REC * gi, sum, REC, P.means + 3 * gg, o);
         }
         if (tid < 64) {
             // lane l sums lanes l, l+64, ... in order, then a fixed butterfly over the wave
@@ -354,7 +406,7 @@ __global__ __launch_bounds__(BLOCK) void bwdr_kernel(Params P, BwdIn I, const Bw
                 for (int j = 0; j < RPT; ++j) {
                     const int local = rb + tid + j * BLOCK;
                     float4 pr[4];
-                    ray_prologue<F>(P, I, item.view, vr, e, kk, o0, o1, o2, local, local < end, pr);
+                    ray_prologue<F>(P, I, item.view, vr, e, kk, o0, o1, o2, local, local < end, bl.b1, bl.nc2, pr);
                     x0[j] = pr[0];
                     x1[j] = pr[1];
                     x2[j] = pr[2];
@@ -394,8 +446,8 @@ __global__ __launch_bounds__(BLOCK) void bwdr_kernel(Params P, BwdIn I, const Bw
                             const float zb = wt[j] * (lin - x2[j].y);
                             const float tb = fmaf(-bl.cb, zb, wt[j] * tfb);
                             const float db = fmaf(bl.b1, zb, x2[j].z * delta[j]);
-                            aB1 = fmaf(zb, q[j].d2, aB1);
-                            aB2 = fmaf(zb, q[j].t, aB2);
+                            aB1 = fmaf(zb, q[j].d2 - x3[j].w, aB1);
+                            aB2 = fmaf(zb, q[j].t - x2[j].w, aB2);
                             pair_adjoint<NORMALS>(g, q[j], x0[j].x, x0[j].y, x0[j].z, wt[j], pn, x1[j].z, x1[j].w,
                                                   x2[j].x, tb, db, a);
                         }

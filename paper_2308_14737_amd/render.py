@@ -260,6 +260,9 @@ class _RenderFn(torch.autograd.Function):
         fl = outs["flow"] if outs["flow"] is not None else empty
         co = outs["color"] if outs["color"] is not None else empty
         ctx.mark_non_differentiable(outs["stash"])
+        # an output the loss does not use passes no cotangent (not zeros), so that, e.g., a
+        # loss without the normals takes the backward without the normal adjoint
+        ctx.set_materialize_grads(False)
         return outs["depth"], outs["alpha"], nr, fl, co
 
     @staticmethod
@@ -271,7 +274,8 @@ class _RenderFn(torch.autograd.Function):
                      weights.detach().contiguous(), betas.detach().contiguous())
         scene.set_colors(None if colors is None else colors.detach().contiguous())
         use = lambda g, o: g if (o is not None and g is not None and g.numel() > 0) else None  # noqa: E731
-        gr = scene.backward(outs, g_depth, g_alpha, use(g_normal, outs["normal"]), use(g_flow, outs["flow"]),
+        gr = scene.backward(outs, use(g_depth, outs["depth"]), use(g_alpha, outs["alpha"]),
+                            use(g_normal, outs["normal"]), use(g_flow, outs["flow"]),
                             g_color=use(g_color, outs["color"]))
         gcol = gr["colors"] if ctx.has_colors else None
         if ctx.has_colors and gcol is None:
