@@ -515,6 +515,38 @@ def test_backward_variants(fmb, variant, label, n, views):
     assert_grads(eg, f"{label} variant {variant}")
 
 
+@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("label,n,views", VARIANT_CASES, ids=[c[0] for c in VARIANT_CASES])
+def test_backward_variants_without_normals(fmb, variant, label, n, views):
+    """The Gaussian-lane variants without a normal cotangent take the (A, Bv, L) form of the
+    adjoint: against the oracle with depth, alpha, two-way flow and colour cotangents."""
+    sc, cams = custom_scene(n, views, seed=310 + n, flow=True)
+    cams = W.with_backward_flow(cams, seed=311)
+    g = np.random.Generator(np.random.PCG64(312))
+    q = (1.5 * g.standard_normal((sc.n, 3))).astype(np.float32)
+    _say(f"[variant-plain] {label} bwd variant {variant}: N={n} views={views}")
+    betas = np.array([W.BETA1, W.BETA2], np.float32)
+    scene, _ = make_scene(fmb, torch, sc, cams, betas, 1.0, DEV)
+    fmb.set_launch_config(scene=scene, bwd_variant=variant)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=DEV).contiguous()  # noqa: E731
+    scene.set_colors(t(q))
+    outs = scene.render(normals=True)
+    ref, _, _ = O.render_workload_view(sc, cams, betas, 1.0, colors=q)
+    hit = ref["alpha"] >= 1e-3
+    cot = hit_mask_cot(W.random_cotangents(cams.n_rays, 313, flow=False), ref["alpha"])
+    cot["normal"] = None
+    cot["flow"] = (g.standard_normal((cams.n_rays, 4)) * hit[:, None]).astype(np.float32)
+    cot["color"] = (g.standard_normal((cams.n_rays, 3)) * hit[:, None]).astype(np.float32)
+    gr = scene.backward(outs, t(cot["depth"]), t(cot["alpha"]), None, t(cot["flow"]), g_color=t(cot["color"]))
+    torch.cuda.synchronize()
+    assert fmb.launch_config(scene=scene)["bwd_variant"] == variant
+    _, gref, _ = O.render_workload_view(sc, cams, betas, 1.0, cot=cot, colors=q)
+    eg = compare_grads(gr, gref)
+    eg["colors"] = normwise(to_np(gr["colors"]), gref["colors"])
+    _say(f"[variant-plain] {label} v{variant}: {eg}")
+    assert_grads(eg, f"{label} variant {variant} without normals")
+
+
 @pytest.mark.parametrize("variant", range(4))
 def test_forward_variants(fmb, variant):
     """Every forward tile variant (rays per lane 1, 2, 4; tile 128 or 256 Gaussians) against the
