@@ -44,19 +44,31 @@ FLOPS_COMP_ADJ_PLAIN = 73     # + 2N per pair (the front sum is recomputation, n
 PEAK_FP32 = 157.3e12       # MI355X FP32 vector peak (published; 256 CUs x 128 FMA lanes x 2.4 GHz)
 
 
+KERNEL_SOURCES = ("fmb_kernels.hip", "fmb_device.h", "fmb_internal.h")
+
+
+def kernel_source_sha256():
+    """SHA-256 over the sources the blend-model kernels are compiled from, in a fixed order."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2308_14737_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def _profile_values(name):
     """key: value lines of a committed rocprofv3 summary under profiles/, or {} if the kernel
-    source has changed since it was taken."""
-    import hashlib
+    sources have changed since it was taken."""
     path = os.path.join(ROOT, "profiles", name)
-    src = os.path.join(ROOT, "paper_2308_14737_amd", "csrc", "fmb_kernels.hip")
     try:
         vals = {}
-        for line in open(path):
-            if ":" in line and not line.startswith(("|", " ", "#")):
-                k, v = line.split(":", 1)
-                vals[k.strip()] = v.strip()
-        if vals.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        with open(path) as f:
+            for line in f:
+                if ":" in line and not line.startswith(("#", "|", " ")):
+                    k, v = line.split(":", 1)
+                    vals[k.strip()] = v.strip()
+        if vals.get("kernel_source_sha256") != kernel_source_sha256():
             return {}
         return vals
     except OSError:
