@@ -44,11 +44,12 @@ FLOPS_COMP_ADJ_PLAIN = 73     # + 2N per pair (the front sum is recomputation, n
 PEAK_FP32 = 157.3e12       # MI355X FP32 vector peak (published; 256 CUs x 128 FMA lanes x 2.4 GHz)
 
 
-KERNEL_SOURCES = ("fmb_kernels.hip", "fmb_device.h", "fmb_internal.h")
+KERNEL_SOURCES = ("fmb_kernels.hip", "fmb_device.h", "fmb_internal.h", "fmb_api.cpp")
 
 
 def kernel_source_sha256():
-    """SHA-256 over the sources the blend-model kernels are compiled from, in a fixed order."""
+    """SHA-256 over the sources of the blend-model kernels and of the work items they are launched
+    over (the host code that cuts items), in a fixed order."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:

@@ -348,11 +348,11 @@ struct Job {
             } else {
                 chunking(scenes[s].n, B, gcs[s], sls[s]);
                 min_span[s] = RT;
-                spans[s] = std::max(RT, ((64 * sls[s] + RT - 1) / RT) * RT);
+                spans[s] = std::max(RT, ((256 * sls[s] + RT - 1) / RT) * RT);
             }
         }
         // Span of rays per item, chosen per scene only (so a scene is cut the same way alone
-        // and inside a batch): about 64 rays per lane (16 steps when compositing), at most
+        // and inside a batch): about 256 rays per lane (16 steps when compositing), at most
         // 16384 and, where the scene is small, at least 2048 items.
         for (int s = 0; s < S; ++s) {
             const int chunks = (scenes[s].n + gcs[s] - 1) / gcs[s];
