@@ -259,6 +259,55 @@ def test_autograd_matches_backward(fmb):
         assert torch.equal(x.grad, g[k]), k
 
 
+@pytest.mark.parametrize("with_normals", [True, False], ids=["normals", "depth_alpha"])
+def test_finite_differences_on_gpu(fmb, with_normals):
+    """Loose sanity check of the adjoint with the GPU alone: central differences of the FP32
+    forward pass (loss accumulated in FP64 on the host) against the backward pass, on the
+    entries of each parameter tensor with the largest gradients.  With and without a normal
+    cotangent (the two forms of the pair adjoint)."""
+    w = W.make_config("fwd64")
+    sc, cams = w.scenes[0], w.cameras[0]
+    _say(f"[fd] fwd64 normals={with_normals}")
+    scene, (m, p, wt, b) = make_scene(fmb, torch, sc, cams, w.betas, w.eta, DEV)
+    cot = W.random_cotangents(cams.n_rays, 91, flow=False)
+    cd, ca, cn = (torch.as_tensor(cot[k], device=DEV, dtype=torch.float64) for k in ("depth", "alpha", "normal"))
+
+    def loss():
+        o = scene.render(normals=True)
+        torch.cuda.synchronize()
+        v = (o["depth"].double() * cd).sum() + (o["alpha"].double() * ca).sum()
+        if with_normals:
+            v = v + (o["normal"].double() * cn).sum()
+        return float(v)
+
+    outs = scene.render(normals=True)
+    t = lambda a: torch.as_tensor(a, device=DEV).contiguous()  # noqa: E731
+    g = scene.backward(outs, t(cot["depth"]), t(cot["alpha"]), t(cot["normal"]) if with_normals else None)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for name, x in (("means", m), ("prec", p), ("weights", wt), ("betas", b)):
+        gx = g[name].reshape(-1).double().cpu()
+        flat = x.view(-1)
+        top = torch.argsort(gx.abs(), descending=True)[:4 if name != "betas" else 2]
+        for idx in top.tolist():
+            x0 = float(flat[idx])
+            # small steps where the loss bends over a Gaussian's width; the blend parameters
+            # are smooth and their gradients small, so a larger step keeps FP32 noise down
+            h = (1e-3 if name == "betas" else 1e-4) * max(1.0, abs(x0))
+            flat[idx] = x0 + h
+            xp = float(flat[idx])  # the float32 values actually rendered
+            lp = loss()
+            flat[idx] = x0 - h
+            xm = float(flat[idx])
+            lm = loss()
+            flat[idx] = x0
+            fd = (lp - lm) / (xp - xm)
+            rel = abs(fd - float(gx[idx])) / max(abs(float(gx[idx])), 1e-2 * float(gx.abs().max()))
+            worst = max(worst, rel)
+            _say(f"[fd] {name}[{idx}] fd {fd:.6e} adjoint {float(gx[idx]):.6e} rel {rel:.2e}")
+    assert worst <= 2e-2, worst
+
+
 def test_deterministic_backward(fmb):
     w = W.make_config("fwdbwd128")
     sc, cams = w.scenes[0], w.cameras[0]
