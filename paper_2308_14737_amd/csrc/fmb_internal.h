@@ -87,12 +87,14 @@ constexpr int kPartial = 10;       // per-Gaussian partial: dU (6), sum rho (3),
 constexpr int kPartialColor = 13;  // ... and dL/d(colour) (3)
 
 // Zero-parameter (alpha-compositing) renderer: lanes per ray for a scene of n Gaussians (the
-// smallest power of two >= n, at most 64; a lane holds n / 64 Gaussians beyond that) and the
-// largest scene it takes (4 Gaussians per lane).
+// smallest power of two >= n / 2, at most 64, so a lane holds two Gaussians, or up to four
+// beyond 128, and the per-ray work of a segment is shared by twice the pairs) and the largest
+// scene it takes (4 Gaussians per lane).
 constexpr int comp_seg(int n)
 {
+    const int h = (n + 1) / 2;
     int s = 1;
-    while (s < n && s < 64) s <<= 1;
+    while (s < h && s < 64) s <<= 1;
     return s;
 }
 constexpr int kCompMaxN = 256;
