@@ -122,29 +122,12 @@ __device__ __forceinline__ void comp_entries(const Params &P, const SceneRec &sr
     }
 }
 
-// sum over the ray's Gaussians j of x_j where t_j < t (before) or t_j > t (after).
-template <bool AFTER>
-__device__ __forceinline__ float ordered_partial(const float2 *__restrict__ slots, int n, float t)
-{
-    float s = 0.0f;
-    int j = 0;
-    for (; j + 4 <= n; j += 4) {
-        const float2 a = slots[j], b = slots[j + 1], c = slots[j + 2], d = slots[j + 3];
-        s += (AFTER ? a.x > t : a.x < t) ? a.y : 0.0f;
-        s += (AFTER ? b.x > t : b.x < t) ? b.y : 0.0f;
-        s += (AFTER ? c.x > t : c.x < t) ? c.y : 0.0f;
-        s += (AFTER ? d.x > t : d.x < t) ? d.y : 0.0f;
-    }
-    for (; j < n; ++j) {
-        const float2 a = slots[j];
-        s += (AFTER ? a.x > t : a.x < t) ? a.y : 0.0f;
-    }
-    return s;
-}
-
 // Writes the segment's pairs (t_j, x_j) with x_j != 0 to its LDS slots, in Gaussian order,
-// and returns their count (the same in every lane of the segment).  Terms with x_j = 0 add
-// nothing to the sums below, so they are left out of the loops.
+// and (0, 0) to the rest of its seg * KM slots; returns the largest such count over the wave's
+// segments, the same in every lane.  Terms with x_j = 0 add nothing to the sums below, so the
+// slot loops run that wave-uniform count (a scalar loop) and skip the Gaussians that cannot
+// contribute.  The zero fill and the packed writes are LDS writes of one wave, which the LDS
+// performs in program order.
 template <int KM>
 __device__ __forceinline__ int compact_slots(float2 *__restrict__ slots, const CompLanes &c, const Geo q[KM],
                                              const float x[KM])
@@ -152,6 +135,8 @@ __device__ __forceinline__ int compact_slots(float2 *__restrict__ slots, const C
     const int l0 = (threadIdx.x & 63) - c.sl;  // first lane of the segment
     const unsigned long long segmask = c.seg == 64 ? ~0ull : ((1ull << c.seg) - 1ull);
     const unsigned long long below = (1ull << c.sl) - 1ull;
+#pragma unroll
+    for (int k = 0; k < KM; ++k) slots[c.sl + k * c.seg] = make_float2(0.0f, 0.0f);
     int cnt = 0;
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
@@ -162,17 +147,41 @@ __device__ __forceinline__ int compact_slots(float2 *__restrict__ slots, const C
             cnt += __popcll(bits);
         }
     }
-    return cnt;
+    for (int off = c.seg; off < 64; off <<= 1) cnt = max(cnt, __shfl_xor(cnt, off, 64));
+    return __builtin_amdgcn_readfirstlane(cnt);
 }
 
-// For each of the lane's Gaussians k: the sum of x_j over the `cnt` compacted slots with
-// t_j < t_k (AFTER = false) or t_j > t_k.
+// For each of the lane's Gaussians k: the sum of x_j over the first n slots with t_j < t_k
+// (AFTER = false) or t_j > t_k, one pass over the slots for all of them.
 template <int KM, bool AFTER>
-__device__ __forceinline__ void ordered_sums(const float2 *__restrict__ slots, int cnt, const CompLanes &c,
+__device__ __forceinline__ void ordered_sums(const float2 *__restrict__ slots, int n, const CompLanes &c,
                                              const Geo q[KM], float out[KM])
 {
+    float t[KM];
 #pragma unroll
-    for (int k = 0; k < KM; ++k) out[k] = (k < c.ke) ? ordered_partial<AFTER>(slots, cnt, q[k].t) : 0.0f;
+    for (int k = 0; k < KM; ++k) {
+        out[k] = 0.0f;
+        t[k] = q[k].t;
+    }
+    int j = 0;
+    for (; j + 4 <= n; j += 4) {
+        const float2 a = slots[j], b = slots[j + 1], cc = slots[j + 2], d = slots[j + 3];
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {  // k >= ke: computed and not used
+            out[k] += (AFTER ? a.x > t[k] : a.x < t[k]) ? a.y : 0.0f;
+            out[k] += (AFTER ? b.x > t[k] : b.x < t[k]) ? b.y : 0.0f;
+            out[k] += (AFTER ? cc.x > t[k] : cc.x < t[k]) ? cc.y : 0.0f;
+            out[k] += (AFTER ? d.x > t[k] : d.x < t[k]) ? d.y : 0.0f;
+        }
+    }
+    for (; j < n; ++j) {
+        const float2 a = slots[j];
+#pragma unroll
+        for (int k = 0; k < KM; ++k) out[k] += (AFTER ? a.x > t[k] : a.x < t[k]) ? a.y : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < KM; ++k)
+        if (k >= c.ke) out[k] = 0.0f;
 }
 
 // ------------------------------------------------------------------------------------
