@@ -106,6 +106,8 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches only")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the colour, two-way flow and split-statistic legs")
     ap.add_argument("--no-composite", action="store_true",
                     help="skip the alpha-compositing (zero-parameter) leg")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -300,6 +302,75 @@ def main():
         print(f"# composite step {ms_comp:.3f} ms; kernels fwd {cf:.3f} bwd {cb:.3f} fin {cfin:.3f} ms",
               file=sys.stderr, flush=True)
 
+    # the other rows of the path, each timed as eager launches with HIP-event kernel times:
+    # colour on the same batch, two-way flow on the 480x640 flow workload, split statistic
+    extras = None
+    if not args.no_extras:
+        extras = {}
+        g = np.random.Generator(np.random.PCG64(7))
+
+        def leg(step, k, pairs_per_step):
+            for _ in range(max(args.warmup, 3)):
+                step()
+            fmb.timing_enable(True)
+            fmb.kernel_times(reset=True)
+            ms = timed(step, k) * 1e3
+            kt = fmb.kernel_times(reset=True)
+            fmb.timing_enable(False)
+            per = {n: kt[n + "_ms"] / kt["n_" + n] for n in ("fwd", "bwd", "fin") if kt["n_" + n]}
+            return {"value": pairs_per_step / (ms * 1e-3), "unit": "pairs/s", "ms_per_step": ms,
+                    "kernel_ms": per}
+
+        # colour (sigmoid colours blended like depth; colour cotangent added to the loss's)
+        q = t((1.5 * g.standard_normal((sum(s.n for s in w.scenes), 3))).astype(np.float32))
+        batch.set_colors(q)
+        outs_c = batch.alloc_outputs(normals=True, color=True)
+        grads_c = batch.alloc_grads(colors=True)
+        cot_c = dict(cot)
+        cot_c["color"] = t((1e-6 * g.standard_normal((P, 3))).astype(np.float32))
+
+        def step_colour():
+            batch.forward(outs_c)
+            cotangents(outs_c)
+            batch.backward(outs_c, cot_c, grads_c)
+
+        extras["colour"] = leg(step_colour, args.steps, pairs)
+        batch.set_colors(None)
+
+        # two-way flow: depth, alpha and flow to the poses before and after each view
+        wf = W.make_config("flow480")
+        sf, cf = wf.scenes[0], W.with_backward_flow(wf.cameras[0], seed=11)
+        scene_f = fmb.Scene(t(sf.means), t(sf.prec), t(sf.weights), t(wf.betas), wf.eta,
+                            fmb.Cameras.from_numpy(cf.w2c, cf.intr, cf.hw, w2c_b=cf.w2c_b, intr_b=cf.intr_b,
+                                                   device=dev, w2c_c=cf.w2c_c, intr_c=cf.intr_c))
+        pf = scene_f.n_rays
+        gd, ga = (t((1e-6 * g.standard_normal(pf)).astype(np.float32)) for _ in range(2))
+        gf = t((1e-6 * g.standard_normal((pf, 4))).astype(np.float32))
+        outs_f = scene_f.render(normals=False, flow=True)
+        grads_f = scene_f.backward(outs_f, gd, ga, None, gf)
+
+        def step_flow():
+            scene_f.render(normals=False, flow=True, out=outs_f)
+            scene_f.backward(outs_f, gd, ga, None, gf, grads=grads_f)
+
+        extras["two_way_flow"] = leg(step_flow, max(args.steps // 2, 5), pf * sf.n)
+        extras["two_way_flow"]["workload"] = "flow480: N=100, 8 views 480x640, flow to both neighbouring poses"
+
+        # split statistic: lbar_i = (1/M) sum_j L_j w_ji over the batch's rays
+        lossr = t(g.random(P).astype(np.float32))
+        lbar = torch.empty(sum(s.n for s in w.scenes), device=dev)
+        batch.forward(outs)
+
+        def step_split():
+            batch.split_statistic(lossr, outs, lbar)
+
+        for _ in range(max(args.warmup, 3)):
+            step_split()
+        ms_split = timed(step_split, args.steps) * 1e3
+        extras["split_statistic"] = {"value": pairs / (ms_split * 1e-3), "unit": "pairs/s", "ms_per_call": ms_split}
+        print("# extras: " + ", ".join(f"{k} {v.get('ms_per_step', v.get('ms_per_call')):.3f} ms"
+                                       for k, v in extras.items()), file=sys.stderr, flush=True)
+
     if args.calibrate_copy:
         # Kernels of known HBM traffic for scaling FETCH_SIZE / WRITE_SIZE: a 1 GiB device copy
         # (the runtime's blit kernel) and a 1 GiB elementwise copy (dst = src + 1, plain
@@ -341,6 +412,7 @@ def main():
         "kernel_ms": {"forward": fwd_ms, "backward": bwd_ms, "finalize": fin_ms},
         "launch": launch,
         "composite": comp,
+        "other_rows": extras,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": measured_traffic(),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",

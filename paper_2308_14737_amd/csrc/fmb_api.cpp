@@ -479,7 +479,7 @@ struct Job {
                 span = 16 * 4 * (64 / comp_seg(n));
             } else {
                 chunking(n, B, gc, sl);
-                span = 64 * sl;
+                span = 256 * sl;  // about 256 rays per lane
             }
             stat_max_gc = std::max(stat_max_gc, gc);
             for (int k = scenes[s].view_off; k < scenes[s].view_off + scenes[s].n_views; ++k)

@@ -678,19 +678,32 @@ __global__ __launch_bounds__(BLOCK) void stat_kernel(Params P, const float *__re
     }
 }
 
-// lbar of every Gaussian of a (scene, chunk): its items' partial sums added in item order in
-// double, divided by the scene's ray count.
-__global__ void stat_fin_kernel(Params P, const StatTask *__restrict__ tasks, const BwdItem *__restrict__ items,
-                                const float *__restrict__ partial, const int64_t *__restrict__ rays_per_scene,
-                                float *__restrict__ lbar)
+// lbar of one Gaussian of a (scene, chunk) per block: thread j adds the partial sums of items
+// j, j + 256, ... in double, then a fixed tree over the threads, divided by the scene's ray
+// count (the same order on every call).
+__global__ __launch_bounds__(256) void stat_fin_kernel(Params P, const StatTask *__restrict__ tasks,
+                                                      const BwdItem *__restrict__ items,
+                                                      const float *__restrict__ partial,
+                                                      const int64_t *__restrict__ rays_per_scene,
+                                                      float *__restrict__ lbar)
 {
+    __shared__ double red[256];
     const StatTask t = tasks[blockIdx.x];
-    const int g = threadIdx.x + blockIdx.y * blockDim.x;
-    if (g >= t.gc) return;
+    const int g = blockIdx.y;
+    if (g >= t.gc) return;  // uniform over the block
     double s = 0.0;
-    for (int it = t.item_begin; it < t.item_end; ++it) s += (double)partial[items[it].poff + g];
-    const SceneRec sr = P.scenes[t.scene];
-    lbar[sr.gauss_off + t.g0 + g] = (float)(s / (double)rays_per_scene[t.scene]);
+    for (int it = t.item_begin + (int)threadIdx.x; it < t.item_end; it += 256)
+        s += (double)partial[items[it].poff + g];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const SceneRec sr = P.scenes[t.scene];
+        lbar[sr.gauss_off + t.g0 + g] = (float)(red[0] / (double)rays_per_scene[t.scene]);
+    }
 }
 
 // Gradient of the Sec. 4 reconstruction loss (mask BCE, mask-weighted L1 depth, mask-weighted
@@ -922,8 +935,8 @@ hipError_t launch_stat(int n_items, int n_tasks, int max_gc, hipStream_t st, con
         hipLaunchKernelGGL((stat_kernel<kBlock, 256>), dim3(n_items), dim3(kBlock), 0, st, P, loss, stash, items,
                            partial);
     if (n_tasks > 0)
-        hipLaunchKernelGGL(stat_fin_kernel, dim3(n_tasks, (max_gc + 255) / 256), dim3(256), 0, st, P, tasks, items,
-                           partial, rays_per_scene, lbar);
+        hipLaunchKernelGGL(stat_fin_kernel, dim3(n_tasks, max_gc), dim3(256), 0, st, P, tasks, items, partial,
+                           rays_per_scene, lbar);
     return hipGetLastError();
 }
 
