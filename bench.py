@@ -356,6 +356,26 @@ def main():
         extras["two_way_flow"] = leg(step_flow, max(args.steps // 2, 5), pf * sf.n)
         extras["two_way_flow"]["workload"] = "flow480: N=100, 8 views 480x640, flow to both neighbouring poses"
 
+        # the single-scene workloads: 40 Gaussians x 20 views of 128x128, and 10 000 Gaussians x
+        # 1080x1920 (no culling); forward with normals, backward of depth and alpha cotangents
+        for name, k in (("fwdbwd128", args.steps), ("large1080", 5)):
+            wk = W.make_config(name)
+            sk, ck = wk.scenes[0], wk.cameras[0]
+            scene_k = fmb.Scene(t(sk.means), t(sk.prec), t(sk.weights), t(wk.betas), wk.eta,
+                                fmb.Cameras.from_numpy(ck.w2c, ck.intr, ck.hw, device=dev))
+            pk = scene_k.n_rays
+            gdk, gak = (t((1e-6 * g.standard_normal(pk)).astype(np.float32)) for _ in range(2))
+            outs_k = scene_k.render(normals=True)
+            grads_k = scene_k.backward(outs_k, gdk, gak)
+            scene_k.autotune(outs_k, {"depth": gdk, "alpha": gak, "normal": None, "flow": None}, grads_k)
+
+            def step_k():
+                scene_k.render(normals=True, out=outs_k)
+                scene_k.backward(outs_k, gdk, gak, grads=grads_k)
+
+            extras[name] = leg(step_k, k, pk * sk.n)
+            del scene_k, outs_k, grads_k
+
         # split statistic: lbar_i = (1/M) sum_j L_j w_ji over the batch's rays
         lossr = t(g.random(P).astype(np.float32))
         lbar = torch.empty(sum(s.n for s in w.scenes), device=dev)
