@@ -259,6 +259,24 @@ def test_autograd_matches_backward(fmb):
         assert torch.equal(x.grad, g[k]), k
 
 
+def test_autograd_unused_outputs(fmb):
+    """Outputs the loss does not use pass no cotangent: a loss of alpha alone equals the
+    backward with only an alpha cotangent, bit for bit."""
+    w = W.make_config("fwd64")
+    sc, cams = w.scenes[0], w.cameras[0]
+    _say("[autograd-unused] fwd64")
+    scene, (m, p, wt, b) = make_scene(fmb, torch, sc, cams, w.betas, w.eta, DEV)
+    params = [x.clone().requires_grad_(True) for x in (m, p, wt, b)]
+    depth, alpha, normal, _, _ = fmb.render(scene, *params, normals=True)
+    ga = torch.as_tensor(W.random_cotangents(cams.n_rays, 79, flow=False)["alpha"], device=DEV)
+    (alpha * ga).sum().backward()
+    outs = scene.render(normals=True)
+    g = scene.backward(outs, None, ga.contiguous(), None)
+    torch.cuda.synchronize()
+    for x, k in zip(params, ("means", "prec", "weights", "betas")):
+        assert torch.equal(x.grad, g[k]), k
+
+
 @pytest.mark.parametrize("with_normals", [True, False], ids=["normals", "depth_alpha"])
 def test_finite_differences_on_gpu(fmb, with_normals):
     """Loose sanity check of the adjoint with the GPU alone: central differences of the FP32
