@@ -108,14 +108,16 @@ __device__ __forceinline__ void project(const float *__restrict__ e, const float
 // Geometry of one (ray, Gaussian) pair.
 struct Geo {
     float a0, a1, a2, raa;  // a = U v, 1/(a.a)
-    float t;                // peak depth (first estimate, refined by pair_refine)
-    float r0, r1, r2;       // r = U (t v - mu')
+    float t;                // peak depth
+    float r0, r1, r2;       // r = U (t v - mu'), at the refined peak after pair_refine
     float d2, z2;           // log2 density, log2 blend weight
 };
 
-// First estimate of the peak: t = v.c / a.a and r = U (t v - mu') with mu' = hi + lo as
-// U (t v - hi) - U lo, then m = r.r, the log2 density d2 and the log2 weight z2.  The error
-// of t enters m only to second order (m is minimal at the peak), so d2 and z2 are final here.
+// The peak t = v.c / a.a and r = U (t v - mu') with mu' = hi + lo as U (t v - hi) - U lo, then
+// m = r.r, the log2 density d2 and the log2 weight z2.  The rounding error of t is below
+// cond(Sigma^-1) times a few ulp (v.c is a dot product whose terms are at most that factor
+// larger than the sum); it enters m only to second order (m is minimal at the peak), so t is
+// the pair's depth and d2 and z2 are final here.
 __device__ __forceinline__ void pair_geo_coarse(const Ent &g, float v0, float v1, float v2, float hm, float b1,
                                                 float nc2, Geo &q)
 {
@@ -137,26 +139,17 @@ __device__ __forceinline__ void pair_geo_coarse(const Ent &g, float v0, float v1
     q.z2 = fmaf(b1, q.d2, nc2 * q.t);
 }
 
-// One Newton step on t -> |U (t v - mu')|^2 (exactly quadratic): dt = (a.r)/(a.a).  The
-// residual r, unlike m, has a first-order error in t, and the normal g = U^T r amplifies it
-// by |U|; after the step a.r = 0 to rounding, which the adjoint relies on.
+// The residual at the refined peak: one Newton step on t -> |U (t v - mu')|^2 (exactly
+// quadratic), dt = (a.r)/(a.a), applied to r only.  r, unlike m, has a first-order error in t,
+// and the normal g = U^T r amplifies it by |U|; after the step a.r = 0 to rounding, which the
+// general adjoint relies on.  The depth stays t (its own error is ~1e-6 relative), so every
+// kernel blends and differentiates the same depth.
 __device__ __forceinline__ void pair_refine(Geo &q)
 {
-    // __fmul_rn keeps the product out of any contraction, so that pair_refine_t gives the
-    // same t bit for bit (the backward's softmax adjoint relies on it)
-    const float dt = __fmul_rn(fmaf(q.a0, q.r0, fmaf(q.a1, q.r1, q.a2 * q.r2)), q.raa);
-    q.t -= dt;
+    const float dt = fmaf(q.a0, q.r0, fmaf(q.a1, q.r1, q.a2 * q.r2)) * q.raa;
     q.r0 = fmaf(-dt, q.a0, q.r0);
     q.r1 = fmaf(-dt, q.a1, q.r1);
     q.r2 = fmaf(-dt, q.a2, q.r2);
-}
-
-// The Newton step on t alone, for code that needs the refined depth but not r (the depth the
-// forward blends is the refined one, and its adjoint must see the same value).
-__device__ __forceinline__ void pair_refine_t(Geo &q)
-{
-    const float dt = __fmul_rn(fmaf(q.a0, q.r0, fmaf(q.a1, q.r1, q.a2 * q.r2)), q.raa);
-    q.t -= dt;
 }
 
 __device__ __forceinline__ void pair_geo(const Ent &g, float v0, float v1, float v2, float hm, float b1,
@@ -429,8 +422,7 @@ __device__ __forceinline__ void pair_adjoint(const Ent &g, const Geo &q, float v
 //   A = sum alpha v v^T (symmetric),  Bv = sum beta v,  L = sum db.
 // A lane therefore accumulates A (6), Bv (3) and L; write_partial_plain forms the record.
 // The envelope condition a.r = 0 is not needed to the last bit: it enters only through terms of
-// relative size |t - t_peak| |a| / |r|, so r may be the first estimate's residual; t itself is
-// the refined peak depth, the one the forward blended.
+// relative size |t - t_peak| |a| / |r|, so neither t nor r needs the Newton step here.
 struct PlainAcc {
     float a00 = 0, a01 = 0, a02 = 0, a11 = 0, a12 = 0, a22 = 0;
     float b0 = 0, b1 = 0, b2 = 0;

@@ -235,7 +235,6 @@ __global__ __launch_bounds__(BLOCK) void bwd_kernel(Params P, BwdIn I, const Bwd
                     const float v0 = x0.x, v1 = x0.y, v2 = x0.z;
                     Geo q;
                     pair_geo_coarse(g, v0, v1, v2, bl.hm, bl.b1, bl.nc2, q);
-                    pair_refine_t(q);
                     const float delta = exp2_(q.d2);
                     const float wt = exp2_(q.z2 - x0.w) * x1.x;   // normalised blend weight
                     const float tfb = x1.y;
