@@ -122,13 +122,19 @@ __device__ __forceinline__ void comp_entries(const Params &P, const SceneRec &sr
     }
 }
 
-// Writes the segment's pairs (t_j, x_j) with x_j != 0 to its LDS slots, in Gaussian order,
-// and (0, 0) to the rest of its seg * KM slots; returns the largest such count over the wave's
-// segments, the same in every lane.  Terms with x_j = 0 add nothing to the sums below, so the
-// slot loops run that wave-uniform count (a scalar loop) and skip the Gaussians that cannot
-// contribute.  The zero fill and the packed writes are LDS writes of one wave, which the LDS
-// performs in program order.
-template <int KM>
+// Densities below this are left out of the front sums: with at most 256 Gaussians they change a
+// sum by less than 2^-22, so a log2 weight -log2(e) F + log2(1 - e^-delta) by less than
+// 3.5e-7 (FP32 rounding of the weight itself), while about three quarters of the pairs of a
+// typical ray have a density below it (the ray passes more than ~6 standard deviations away).
+constexpr float kCompMinDensity = 0x1p-30f;
+
+// Writes the segment's pairs (t_j, x_j) with x_j != 0 (DENSITY: x_j > kCompMinDensity) to its
+// LDS slots, in Gaussian order, and (0, 0) to the rest of its seg * KM slots; returns the
+// largest such count over the wave's segments, the same in every lane.  Terms left out add
+// nothing (or below rounding) to the sums below, so the slot loops run that wave-uniform count
+// (a scalar loop) and skip the Gaussians that cannot contribute.  The zero fill and the packed
+// writes are LDS writes of one wave, which the LDS performs in program order.
+template <int KM, bool DENSITY>
 __device__ __forceinline__ int compact_slots(float2 *__restrict__ slots, const CompLanes &c, const Geo q[KM],
                                              const float x[KM])
 {
@@ -141,7 +147,7 @@ __device__ __forceinline__ int compact_slots(float2 *__restrict__ slots, const C
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
         if (k < c.ke) {
-            const bool nz = x[k] != 0.0f;
+            const bool nz = DENSITY ? x[k] > kCompMinDensity : x[k] != 0.0f;
             const unsigned long long bits = (__ballot(nz) >> l0) & segmask;
             if (nz) slots[cnt + __popcll(bits & below)] = make_float2(q[k].t, x[k]);
             cnt += __popcll(bits);
@@ -236,7 +242,7 @@ __global__ __launch_bounds__(kCompBlock) void fwdc_kernel(Params P, FwdOut O, co
             }
         }
         __syncthreads();  // the previous step is done with the slots
-        const int cnt = compact_slots<KM>(tdl + c.sbase, c, q, dl);
+        const int cnt = compact_slots<KM, true>(tdl + c.sbase, c, q, dl);
         __syncthreads();
         float front[KM];
         ordered_sums<KM, false>(tdl + c.sbase, cnt, c, q, front);
@@ -376,7 +382,7 @@ __global__ __launch_bounds__(kCompBlock) void bwdc_kernel(Params P, BwdIn I, con
                     dl[k] = gv[k] ? exp2_(q[k].d2) : 0.0f;
                 }
             }
-            const int cnt = compact_slots<KM>(tdl + c.sbase, c, q, dl);
+            const int cnt = compact_slots<KM, true>(tdl + c.sbase, c, q, dl);
             __syncthreads();
             float front[KM];
             ordered_sums<KM, false>(tdl + c.sbase, cnt, c, q, front);
@@ -395,7 +401,7 @@ __global__ __launch_bounds__(kCompBlock) void bwdc_kernel(Params P, BwdIn I, con
                 }
             }
             __syncthreads();  // everyone is done reading (t, delta)
-            const int cnt_b = compact_slots<KM>(tdl + c.sbase, c, q, zb);
+            const int cnt_b = compact_slots<KM, false>(tdl + c.sbase, c, q, zb);
             __syncthreads();
             float behind[KM];
             ordered_sums<KM, true>(tdl + c.sbase, cnt_b, c, q, behind);
@@ -511,7 +517,7 @@ __global__ __launch_bounds__(kCompBlock) void statc_kernel(Params P, const float
                 dl[k] = gv[k] ? exp2_(q[k].d2) : 0.0f;
             }
         }
-        const int cnt = compact_slots<KM>(tdl + c.sbase, c, q, dl);
+        const int cnt = compact_slots<KM, true>(tdl + c.sbase, c, q, dl);
         __syncthreads();
         float front[KM];
         ordered_sums<KM, false>(tdl + c.sbase, cnt, c, q, front);
