@@ -140,8 +140,10 @@ int fmb_set_flow_pose2(fmb_scene *scene, fmb_batch *batch, const float *w2c_c,
 /* Choose the blend weights of a scene or batch (exactly one non-NULL); the default is
  * FMB_MODEL_BLEND.  FMB_MODEL_COMPOSITE is the zero-parameter renderer of Sec. 3.3:
  * w_i = T_i (1 - exp(-delta_i)), T_i = exp(-sum_j delta_j [t_j < t_i]) (Eq. 9-10; Gaussians
- * at equal t_i do not attenuate one another), blended by Eq. (3) for depth, normals and
- * colour, alpha by Eq. (8); betas and eta are not used and their gradient is 0.  Every
+ * at equal t_i do not attenuate one another; densities below 2^-30 are left out of the
+ * sums over j, which moves a weight by less than 3.5e-7 relative), blended by Eq. (3) for
+ * depth, normals and colour, alpha by Eq. (8) over every density; betas and eta are not
+ * used and their gradient is 0.  Every
  * other call keeps its meaning, arguments and outputs; the stash holds the same fields
  * (the running maximum is that of log2 w_i).  Captured graphs are dropped when the model
  * changes; fmb_autotune leaves a compositing job as it is (one launch configuration).
