@@ -7,10 +7,12 @@ its scene, the loss cotangents (alpha-weighted L1 depth + BCE alpha against targ
 rendered from a perturbed copy of each scene), and the adjoint pass producing the
 gradients of means, precision factors, weights and both blend parameters.
 
-The timed value replays the batch's captured HIP graphs (persistent forward kernel,
-cotangents, persistent backward + finalize kernels).  The same steps are also timed
-with one plain launch sequence per scene (`plain_value`).  Kernel durations for the
-roofline come from HIP events recorded around each kernel launch on its stream.
+The timed value replays one HIP graph of the whole step (persistent forward kernel, loss
+cotangents, persistent backward + finalize kernels), captured from the stream the library
+calls run on; the batch's own captured forward and backward graphs are timed too.  The same
+steps are also timed with one plain launch sequence per scene (`plain_value`).  Kernel
+durations for the roofline come from HIP events recorded around each kernel launch on its
+stream.
 
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -226,9 +228,10 @@ def main():
     print(f"# eager step {ms_eager:.3f} ms; kernels fwd {fwd_ms:.3f} bwd {bwd_ms:.3f} fin {fin_ms:.3f} ms",
           file=sys.stderr, flush=True)
 
-    # the timed value: the same steps replayed from the batch's captured graphs (after the
-    # eager leg, so both legs run on a GPU that has been busy for a while)
-    ms_graph = None
+    # the same steps replayed from graphs (after the eager leg, so that they run on a GPU that
+    # has been busy for a while): the batch's own captured forward and backward graphs, then
+    # one graph of the whole step
+    ms_graph = ms_graph_api = None
     if not args.no_graph:
         st = torch.cuda.Stream(dev)
         torch.cuda.synchronize()
@@ -242,7 +245,24 @@ def main():
 
         for _ in range(args.warmup):
             step_graph()
-        ms_graph = timed(step_graph, args.steps) * 1e3
+        ms_graph_api = timed(step_graph, args.steps) * 1e3
+        print(f"# library graphs (forward, backward; loss kernel between) {ms_graph_api:.3f} ms",
+              file=sys.stderr, flush=True)
+
+        # the timed value: the whole step (forward, loss cotangents, backward, finalize) as ONE
+        # graph captured from the stream the library calls run on, replayed as one launch
+        s2 = torch.cuda.Stream(dev)
+        s2.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s2):
+            step_eager()
+        torch.cuda.current_stream().wait_stream(s2)
+        torch.cuda.synchronize()
+        g_step = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g_step):
+            step_eager()
+        for _ in range(args.warmup):
+            g_step.replay()
+        ms_graph = timed(g_step.replay, args.steps) * 1e3
         print(f"# graph step {ms_graph:.3f} ms", file=sys.stderr, flush=True)
 
     # plain: one launch sequence per scene
@@ -427,7 +447,8 @@ def main():
         "plain_ms_per_step": plain_ms,
         "batched_over_plain": (plain_ms / ms_step) if plain_ms else None,
         "eager_ms_per_step": ms_eager,
-        "timed": "graph replays" if ms_graph is not None else "eager launches",
+        "timed": "replays of one graph of the whole step" if ms_graph is not None else "eager launches",
+        "library_graphs_ms_per_step": ms_graph_api,
         "fp32_peak_frac_step": step_flops / (ms_step * 1e-3) / PEAK_FP32,
         "kernel_ms": {"forward": fwd_ms, "backward": bwd_ms, "finalize": fin_ms},
         "launch": launch,

@@ -144,6 +144,49 @@ def test_graph_replay(fmb, batch16):
             betas.mul_(1.01)
 
 
+def test_whole_step_single_graph(fmb, batch16):
+    """The whole training step — forward, the loss kernel's cotangents, backward, finalize — captured
+    from its stream as ONE graph replays like the eager calls, several times with eager work in
+    between (the library calls allocate nothing and record no memset)."""
+    w, b, _ = batch16
+    outs = b.alloc_outputs(normals=True)
+    grads = b.alloc_grads()
+    g = np.random.Generator(np.random.PCG64(45))
+    d_t = torch.as_tensor(3.0 + g.random(b.n_rays).astype(np.float32), device=DEV)
+    a_t = torch.as_tensor((g.random(b.n_rays) > 0.5).astype(np.float32), device=DEV)
+    cot = {"depth": torch.empty(b.n_rays, device=DEV), "alpha": torch.empty(b.n_rays, device=DEV),
+           "normal": None, "flow": None}
+
+    def step():
+        b.forward(outs)
+        fmb.loss_grad(outs, d_t, a_t, cot=cot)
+        b.backward(outs, cot, grads)
+
+    s2 = torch.cuda.Stream()
+    s2.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s2):
+        step()
+    torch.cuda.current_stream().wait_stream(s2)
+    torch.cuda.synchronize()
+    ref = {k: v.clone() for k, v in grads.items() if v is not None}
+    graph = torch.cuda.CUDAGraph()
+    _say("[step-graph] capture")
+    with torch.cuda.graph(graph):
+        step()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for v in grads.values():
+            if v is not None:
+                v.fill_(float("nan"))
+        graph.replay()
+        torch.cuda.synchronize()
+        for k, v in ref.items():
+            assert torch.equal(grads[k], v), (rep, k)
+        step()  # eager work between replays
+        torch.cuda.synchronize()
+        _say(f"[step-graph] replay {rep} matches eager")
+
+
 @pytest.mark.parametrize("variant", [3, 5])
 def test_ray_lane_batch_bitwise(fmb, batch16, variant):
     """The ray-lane backward kernels, batched and persistent, equal per-scene plain launches of
