@@ -10,16 +10,18 @@
 //   * backward: one lane per (Gaussian, ray slot); rays of the item's span are staged
 //     through LDS with their per-ray adjoint prologue; every lane recomputes its pairs
 //     and accumulates its Gaussian's gradient in registers -- no per-pair cross-lane
-//     reduction and no P x N storage.  Partial gradients per item are reduced
-//     deterministically by the finalize kernel.
+//     reduction and no P x N storage (without a normal cotangent in the short form of
+//     pair_adjoint_plain).  Partial gradients per item are reduced deterministically by
+//     the finalize kernel.
 //   * persistent variants pull items from a device counter (reset by a fill kernel)
 //     in the order given by the host (largest item first).
 //
 // Per pair (ray o + t v with |v| = 1, Gaussian mu, U, lambda; mu' = mu - o):
 //   a = U v, t = v.c / a.a (peak of the density along the ray, Sec. 3.1),
-//   r = U (t v - mu') formed as U (t v - hi) - U lo, one Newton refinement of t on
-//   |U(t v - mu')|^2, m = r.r, d = log lambda - m/2 (Eq. 2), delta = e^d (Eq. 4),
-//   z = beta1 d - (beta2/eta) t (log of Eq. 7), g = U^T r = Sigma^-1 x (Eq. 17).
+//   r = U (t v - mu') formed as U (t v - hi) - U lo, m = r.r, d = log lambda - m/2 (Eq. 2),
+//   delta = e^d (Eq. 4), z = beta1 d - (beta2/eta) t (log of Eq. 7); where a normal is
+//   needed, one Newton step on |U(t v - mu')|^2 moves r to the peak, g = U^T r =
+//   Sigma^-1 x (Eq. 17).
 #include "fmb_device.h"
 
 namespace fmb {
@@ -661,7 +663,7 @@ __global__ __launch_bounds__(BLOCK) void stat_kernel(Params P, const float *__re
         if (active) {
             for (int j = slot; j < cnt; j += item.slots) {
                 const float4 x0 = rays[2 * j], x1 = rays[2 * j + 1];
-                Geo q;  // the weight needs no refined peak
+                Geo q;  // the weight needs no residual at the peak
                 pair_geo_coarse(g, x0.x, x0.y, x0.z, bl.hm, bl.b1, bl.nc2, q);
                 if (q.z2 - x0.w >= kSkipLog2) acc = fmaf(x1.y, exp2_(q.z2 - x0.w) * x1.x, acc);
             }
