@@ -73,6 +73,32 @@ def test_split_statistic(fmb, model):
     assert abs(total - float(loss.astype(np.float64).mean())) <= 1e-4 * float(loss.mean())
 
 
+def test_split_statistic_full_scene(fmb):
+    """Every ray of the largest scene of the 16-scene batch (83 Gaussians, 1.57e6 rays): the
+    finalize then sums thousands of items per Gaussian (strided over the threads of its block,
+    then a fixed tree), against the oracle over the same rays."""
+    w = W.make_config("batch16")
+    sc, cams = w.scenes[0], w.cameras[0]
+    scene = fmb.Scene(_t(sc.means), _t(sc.prec), _t(sc.weights), _t(w.betas), w.eta,
+                      fmb.Cameras.from_numpy(cams.w2c, cams.intr, cams.hw, device=DEV))
+    outs = scene.render(normals=False)
+    g = np.random.Generator(np.random.PCG64(73))
+    loss_t = _t(g.uniform(0.5, 2.0, scene.n_rays).astype(np.float32)) * outs["alpha"]
+    lbar = scene.split_statistic(loss_t, outs)
+    torch.cuda.synchronize()
+    loss = to_np(loss_t)
+    _say(f"[split-full] N={sc.n} P={scene.n_rays}")
+    from workloads import pixel_indices
+    view, row, col = pixel_indices(cams)
+    o, v = O.pixel_rays(view, row, col, cams.w2c, cams.intr)
+    osc = O.OracleScene.of(sc.means, sc.prec, sc.weights, w.betas, w.eta)
+    lref = O.split_statistic(osc, o, v, loss, "blend")
+    e = normwise(to_np(lbar), lref)
+    _say(f"[split-full] normwise {e:.3e}")
+    assert e <= 1e-4
+    assert abs(float(to_np(lbar).sum()) - float(loss.astype(np.float64).mean())) <= 1e-4 * float(loss.mean())
+
+
 def test_split_statistic_batch(fmb):
     """Batched statistic equals each scene's own, bit for bit."""
     w = W.make_config("batch16")
