@@ -69,6 +69,33 @@ __device__ __forceinline__ float seg_sum(float x, int seg)
     return x;
 }
 
+// Sums of eight values over the aligned group of `seg` >= 8 lanes, scattered over its lanes:
+// three halving exchanges (each lane keeps half of its values and adds its partner's copy of
+// that half, lanes seg/2, seg/4, seg/8 apart), then a sum over the remaining groups of seg/8
+// lanes.  Lane l of the segment ends with the total of value seg8_index(l, seg) -- half the
+// exchanges of eight separate sums, and no DPP (which issues at half rate).
+__device__ __forceinline__ int seg8_index(int sl, int seg)
+{
+    return ((sl & (seg >> 1)) ? 4 : 0) + ((sl & (seg >> 2)) ? 2 : 0) + ((sl & (seg >> 3)) ? 1 : 0);
+}
+
+__device__ __forceinline__ float seg_sum8(const float x[8], int sl, int seg)
+{
+    float y[4], z[2];
+    int o = seg >> 1;
+    bool up = (sl & o) != 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) y[i] = (up ? x[i + 4] : x[i]) + __shfl_xor(up ? x[i] : x[i + 4], o, 64);
+    o >>= 1;
+    up = (sl & o) != 0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) z[i] = (up ? y[i + 2] : y[i]) + __shfl_xor(up ? y[i] : y[i + 2], o, 64);
+    o >>= 1;
+    up = (sl & o) != 0;
+    const float w = (up ? z[1] : z[0]) + __shfl_xor(up ? z[0] : z[1], o, 64);
+    return seg_sum(w, seg >> 3);
+}
+
 __device__ __forceinline__ float seg_max(float x, int seg)
 {
     if (seg > 1) x = fmaxf(x, dpp_<0xB1>(x));
@@ -276,24 +303,40 @@ __global__ __launch_bounds__(kCompBlock) void fwdc_kernel(Params P, FwdOut O, co
                 }
             }
         }
-        S = seg_sum(S, c.seg);
-        T = seg_sum(T, c.seg);
-        D = seg_sum(D, c.seg);
-        if (NORMALS) {
-            N0 = seg_sum(N0, c.seg);
-            N1 = seg_sum(N1, c.seg);
-            N2 = seg_sum(N2, c.seg);
-        }
-        if (COLOR) {
-            C0 = seg_sum(C0, c.seg);
-            C1 = seg_sum(C1, c.seg);
-            C2 = seg_sum(C2, c.seg);
-        }
-        if (c.sl == 0) {
-            float *r = my_epi + (filled + c.sg) * kEpiRec;
-            r[0] = __int_as_float(valid ? local : -1);
-            r[1] = mx; r[2] = S; r[3] = T; r[4] = N0; r[5] = N1; r[6] = N2;
-            r[7] = C0; r[8] = C1; r[9] = C2; r[10] = D;
+        float *r = my_epi + (filled + c.sg) * kEpiRec;
+        if (c.seg >= 8) {
+            // S, T, D, N, C0, C1 scattered over the segment, each written by the lanes that hold it
+            const float x[8] = {S, T, D, N0, N1, N2, C0, C1};
+            const float v = seg_sum8(x, c.sl, c.seg);
+            if (COLOR) C2 = seg_sum(C2, c.seg);
+            if ((c.sl & ((c.seg >> 3) - 1)) == 0) {
+                const int i = seg8_index(c.sl, c.seg);
+                r[i < 2 ? 2 + i : (i == 2 ? 10 : 1 + i)] = v;  // S, T at 2, 3; D at 10; N, C0, C1 at 4..8
+            }
+            if (c.sl == 0) {
+                r[0] = __int_as_float(valid ? local : -1);
+                r[1] = mx;
+                r[9] = C2;
+            }
+        } else {
+            S = seg_sum(S, c.seg);
+            T = seg_sum(T, c.seg);
+            D = seg_sum(D, c.seg);
+            if (NORMALS) {
+                N0 = seg_sum(N0, c.seg);
+                N1 = seg_sum(N1, c.seg);
+                N2 = seg_sum(N2, c.seg);
+            }
+            if (COLOR) {
+                C0 = seg_sum(C0, c.seg);
+                C1 = seg_sum(C1, c.seg);
+                C2 = seg_sum(C2, c.seg);
+            }
+            if (c.sl == 0) {
+                r[0] = __int_as_float(valid ? local : -1);
+                r[1] = mx; r[2] = S; r[3] = T; r[4] = N0; r[5] = N1; r[6] = N2;
+                r[7] = C0; r[8] = C1; r[9] = C2; r[10] = D;
+            }
         }
         filled += c.rpw;
         if (filled == 64 || base + 4 * c.rpw >= end) {
