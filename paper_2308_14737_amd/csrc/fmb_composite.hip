@@ -107,6 +107,17 @@ __device__ __forceinline__ float seg_max(float x, int seg)
     return x;
 }
 
+// Orders the LDS accesses of one wave around this point, for data that only lanes of the same
+// wave share (a segment's slots, a wave's epilogue records): the LDS performs one wave's
+// operations in program order, and the fence and barrier keep the compiler from moving them
+// across.  No block barrier, so the waves of a block do not wait for one another.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Lane geometry of a scene with n Gaussians.
 struct CompLanes {
     int seg, ke;        // lanes per ray, Gaussians per lane
@@ -268,9 +279,9 @@ __global__ __launch_bounds__(kCompBlock) void fwdc_kernel(Params P, FwdOut O, co
                 dl[k] = 0.0f;
             }
         }
-        __syncthreads();  // the previous step is done with the slots
+        wave_sync();  // the previous step is done with the slots
         const int cnt = compact_slots<KM, true>(tdl + c.sbase, c, q, dl);
-        __syncthreads();
+        wave_sync();
         float front[KM];
         ordered_sums<KM, false>(tdl + c.sbase, cnt, c, q, front);
         float l2[KM];
@@ -340,7 +351,7 @@ __global__ __launch_bounds__(kCompBlock) void fwdc_kernel(Params P, FwdOut O, co
         }
         filled += c.rpw;
         if (filled == 64 || base + 4 * c.rpw >= end) {
-            __syncthreads();
+            wave_sync();
             if (lane < filled) {
                 const float *r = my_epi + lane * kEpiRec;
                 const int rl = __float_as_int(r[0]);
@@ -351,7 +362,7 @@ __global__ __launch_bounds__(kCompBlock) void fwdc_kernel(Params P, FwdOut O, co
                                  r[4], r[5], r[6], r[7], r[8], r[9], r[10]);
                 }
             }
-            __syncthreads();
+            wave_sync();
             filled = 0;
         }
     }
@@ -407,8 +418,9 @@ __global__ __launch_bounds__(kCompBlock) void bwdc_kernel(Params P, BwdIn I, con
 #pragma unroll
             for (int w = 0; w < RW; ++w) smem[RW * tid + w] = pr[w];
         }
+        __syncthreads();  // the staged rays are visible to every wave
         for (int s0 = 0; s0 < kCompBlock && sb + s0 < end; s0 += step) {
-            __syncthreads();  // staged rays visible; the previous step is done with the slots
+            wave_sync();  // the previous step is done with the slots
             const int ry = s0 + wave * c.rpw + c.sg;
             const float4 x0 = smem[RW * ry], x1 = smem[RW * ry + 1], x2 = smem[RW * ry + 2];
             float4 x3 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -426,7 +438,7 @@ __global__ __launch_bounds__(kCompBlock) void bwdc_kernel(Params P, BwdIn I, con
                 }
             }
             const int cnt = compact_slots<KM, true>(tdl + c.sbase, c, q, dl);
-            __syncthreads();
+            wave_sync();
             float front[KM];
             ordered_sums<KM, false>(tdl + c.sbase, cnt, c, q, front);
             float wt[KM], zb[KM];
@@ -443,9 +455,9 @@ __global__ __launch_bounds__(kCompBlock) void bwdc_kernel(Params P, BwdIn I, con
                     zb[k] = wt[k] * (lin - kap);
                 }
             }
-            __syncthreads();  // everyone is done reading (t, delta)
+            wave_sync();  // the segment is done reading (t, delta)
             const int cnt_b = compact_slots<KM, false>(tdl + c.sbase, c, q, zb);
-            __syncthreads();
+            wave_sync();
             float behind[KM];
             ordered_sums<KM, true>(tdl + c.sbase, cnt_b, c, q, behind);
 #pragma unroll
