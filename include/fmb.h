@@ -141,7 +141,8 @@ int fmb_set_flow_pose2(fmb_scene *scene, fmb_batch *batch, const float *w2c_c,
  * FMB_MODEL_BLEND.  FMB_MODEL_COMPOSITE is the zero-parameter renderer of Sec. 3.3:
  * w_i = T_i (1 - exp(-delta_i)), T_i = exp(-sum_j delta_j [t_j < t_i]) (Eq. 9-10; Gaussians
  * at equal t_i do not attenuate one another; densities below 2^-30 are left out of the
- * sums over j, which moves a weight by less than 3.5e-7 relative), blended by Eq. (3) for
+ * sums over j, which moves a weight by less than 3.5e-7 relative, and the backward leaves
+ * weights below 2^-40 out of its sums over the Gaussians behind), blended by Eq. (3) for
  * depth, normals and colour, alpha by Eq. (8) over every density; betas and eta are not
  * used and their gradient is 0.  Every
  * other call keeps its meaning, arguments and outputs; the stash holds the same fields

@@ -165,6 +165,11 @@ __device__ __forceinline__ void comp_entries(const Params &P, const SceneRec &sr
 // 3.5e-7 (FP32 rounding of the weight itself), while about three quarters of the pairs of a
 // typical ray have a density below it (the ray passes more than ~6 standard deviations away).
 constexpr float kCompMinDensity = 0x1p-30f;
+// Likewise, softmax adjoints z_bar_i of pairs whose normalised weight is below this are left out
+// of the adjoint's sums over the Gaussians behind: |z_bar_i| <= w_i |lin_i - kappa| while a ray's
+// largest term is at least (1/N) |lin - kappa|, so with N <= 256 a sum moves by less than
+// N^2 2^-40 < 6e-8 of the ray's scale; about three quarters of the pairs fall below it.
+constexpr float kCompMinWeight = 0x1p-40f;
 
 // Writes the segment's pairs (t_j, x_j) with x_j != 0 (DENSITY: x_j > kCompMinDensity) to its
 // LDS slots, in Gaussian order, and (0, 0) to the rest of its seg * KM slots; returns the
@@ -456,7 +461,10 @@ __global__ __launch_bounds__(kCompBlock) void bwdc_kernel(Params P, BwdIn I, con
                 }
             }
             wave_sync();  // the segment is done reading (t, delta)
-            const int cnt_b = compact_slots<KM, false>(tdl + c.sbase, c, q, zb);
+            float zp[KM];  // the terms of the behind sums
+#pragma unroll
+            for (int k = 0; k < KM; ++k) zp[k] = wt[k] >= kCompMinWeight ? zb[k] : 0.0f;
+            const int cnt_b = compact_slots<KM, false>(tdl + c.sbase, c, q, zp);
             wave_sync();
             float behind[KM];
             ordered_sums<KM, true>(tdl + c.sbase, cnt_b, c, q, behind);
