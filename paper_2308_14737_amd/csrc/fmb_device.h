@@ -32,6 +32,39 @@ __device__ __forceinline__ Ent ent_from(const float4 a, const float4 b, const fl
     return Ent{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w, d.x, d.y, d.z, d.w};
 }
 
+// Block-uniform, read-only metadata (work items, view and scene records, cameras, betas):
+// a load through the constant address space becomes a scalar load whose result stays in
+// SGPRs.  Inside a persistent loop the kernel's own stores would otherwise keep the compiler
+// from proving the records unchanged, and it would fall back to vector loads and VGPRs.  No
+// kernel writes these arrays.
+template <class T>
+__device__ __forceinline__ T ld_uniform(const T *p)
+{
+    static_assert(sizeof(T) % 4 == 0 && alignof(T) >= 4, "records of 32-bit words");
+    const __attribute__((address_space(4))) uint32_t *q = (const __attribute__((address_space(4))) uint32_t *)p;
+    uint32_t w[sizeof(T) / 4];
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = q[i];
+    T v;
+    __builtin_memcpy(&v, w, sizeof(T));
+    return v;
+}
+
+struct CamRec {  // world-to-camera [R | T] row-major, then (fx, fy, cx, cy)
+    float e[12];
+    float k[4];
+};
+
+__device__ __forceinline__ CamRec cam_of(const Params &P, int view)
+{
+    CamRec c;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) c.e[i] = ld_uniform(P.w2c + 12 * view + i);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) c.k[i] = ld_uniform(P.intr + 4 * view + i);
+    return c;
+}
+
 // Camera centre o = -R^T T in double.
 __device__ __forceinline__ void cam_centre(const float *__restrict__ e, double o[3])
 {
@@ -42,7 +75,9 @@ __device__ __forceinline__ void cam_centre(const float *__restrict__ e, double o
 }
 
 // (view, Gaussian) entry in double, rounded to float.  mu - o is split as hi + lo; the
-// pair loop forms U (t v - mu') as U (t v - hi) - U lo, so only U lo is stored.
+// pair loop forms U (t v - mu') as U (t v - hi) - U lo, so only U lo is stored.  log2 lambda
+// is the FP32 log2 (within an ulp of the rounded double): the FP64 routine's polynomial
+// constants would be hoisted out of a persistent loop and held in VGPRs for the whole kernel.
 __device__ __forceinline__ void make_entry(const float *__restrict__ mu, const float *__restrict__ u,
                                            float lam, const double o[3], float4 out[4])
 {
@@ -60,7 +95,7 @@ __device__ __forceinline__ void make_entry(const float *__restrict__ mu, const f
     out[0] = make_float4(u[0], u[1], u[2], u[3]);
     out[1] = make_float4(u[4], u[5], h0, h1);
     out[2] = make_float4(h2, (float)ul0, (float)ul1, (float)ul2);
-    out[3] = make_float4((float)c0, (float)c1, (float)c2, (float)log2((double)lam));
+    out[3] = make_float4((float)c0, (float)c1, (float)c2, log2f(lam));
 }
 
 // Unit direction of the ray through the centre of pixel (row, col).
@@ -167,7 +202,8 @@ struct Blend {
 
 __device__ __forceinline__ Blend blend_of(const Params &P, int s)
 {
-    const double b1 = P.betas[2 * s], b2 = P.betas[2 * s + 1], eta = P.eta[s];
+    const double b1 = ld_uniform(P.betas + 2 * s), b2 = ld_uniform(P.betas + 2 * s + 1);
+    const double eta = ld_uniform(P.eta + s);
     Blend b;
     b.hm = (float)(-0.5 * kLog2e);
     b.b1 = (float)b1;

@@ -46,15 +46,15 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
             __syncthreads();  // everyone is done with s_item and the tile of the last item
             if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
             __syncthreads();
-            pos = s_item;
+            pos = __builtin_amdgcn_readfirstlane(s_item);  // block-uniform: keep the item in SGPRs
         }
         if (pos >= n_items) break;
-        const int it = order ? order[pos] : pos;
-        const FwdItem item = items[it];
-        const ViewRec vr = P.views[item.view];
-        const SceneRec sr = P.scenes[vr.scene];
-        const float *__restrict__ e = P.w2c + 12 * item.view;
-        const float *__restrict__ kk = P.intr + 4 * item.view;
+        const int it = order ? ld_uniform(order + pos) : pos;
+        const FwdItem item = ld_uniform(items + it);
+        const ViewRec vr = ld_uniform(P.views + item.view);
+        const SceneRec sr = ld_uniform(P.scenes + vr.scene);
+        const CamRec cam = cam_of(P, item.view);
+        const float *e = cam.e, *kk = cam.k;
         double o[3];
         cam_centre(e, o);
         const Blend bl = blend_of(P, vr.scene);
@@ -149,8 +149,15 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
 // ------------------------------------------------------------------------------------
 
 
+// Waves per SIMD the Gaussian-lane backward is compiled for: six (at most 80 VGPRs) where the
+// variant fits without spilling, else what its registers give.
+constexpr int bwd_min_waves(int F)
+{
+    return ((F & kCol) ? F == kCol : !((F & kFlw) && (F & kPer))) ? 6 : 1;
+}
+
 template <int BLOCK, int RT, int F>
-__global__ __launch_bounds__(BLOCK) void bwd_kernel(Params P, BwdIn I, const BwdItem *__restrict__ items,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(bwd_min_waves(F)))) void bwd_kernel(Params P, BwdIn I, const BwdItem *__restrict__ items,
                                                    int n_items, const int *__restrict__ order,
                                                    int *__restrict__ counter, float *__restrict__ partial,
                                                    float *__restrict__ beta_partial)
@@ -176,15 +183,15 @@ __global__ __launch_bounds__(BLOCK) void bwd_kernel(Params P, BwdIn I, const Bwd
             __syncthreads();
             if (tid == 0) s_item = atomicAdd(counter, 1);
             __syncthreads();
-            pos = s_item;
+            pos = __builtin_amdgcn_readfirstlane(s_item);  // block-uniform: keep the item in SGPRs
         }
         if (pos >= n_items) break;
-        const int it = order ? order[pos] : pos;
-        const BwdItem item = items[it];
-        const ViewRec vr = P.views[item.view];
-        const SceneRec sr = P.scenes[vr.scene];
-        const float *__restrict__ e = P.w2c + 12 * item.view;
-        const float *__restrict__ kk = P.intr + 4 * item.view;
+        const int it = order ? ld_uniform(order + pos) : pos;
+        const BwdItem item = ld_uniform(items + it);
+        const ViewRec vr = ld_uniform(P.views + item.view);
+        const SceneRec sr = ld_uniform(P.scenes + vr.scene);
+        const CamRec cam = cam_of(P, item.view);
+        const float *e = cam.e, *kk = cam.k;
         double o[3];
         cam_centre(e, o);
         const float o0 = (float)o[0], o1 = (float)o[1], o2 = (float)o[2];
@@ -374,15 +381,15 @@ __global__ __launch_bounds__(BLOCK) void bwdr_kernel(Params P, BwdIn I, const Bw
             __syncthreads();
             if (tid == 0) s_item = atomicAdd(counter, 1);
             __syncthreads();
-            pos = s_item;
+            pos = __builtin_amdgcn_readfirstlane(s_item);  // block-uniform: keep the item in SGPRs
         }
         if (pos >= n_items) break;
-        const int it = order ? order[pos] : pos;
-        const BwdItem item = items[it];
-        const ViewRec vr = P.views[item.view];
-        const SceneRec sr = P.scenes[vr.scene];
-        const float *__restrict__ e = P.w2c + 12 * item.view;
-        const float *__restrict__ kk = P.intr + 4 * item.view;
+        const int it = order ? ld_uniform(order + pos) : pos;
+        const BwdItem item = ld_uniform(items + it);
+        const ViewRec vr = ld_uniform(P.views + item.view);
+        const SceneRec sr = ld_uniform(P.scenes + vr.scene);
+        const CamRec cam = cam_of(P, item.view);
+        const float *e = cam.e, *kk = cam.k;
         double o[3];
         cam_centre(e, o);
         const float o0 = (float)o[0], o1 = (float)o[1], o2 = (float)o[2];
