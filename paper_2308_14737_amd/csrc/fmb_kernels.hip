@@ -236,16 +236,20 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(bwd_min_w
             }
             __syncthreads();
             if (active && PLAIN) {
-                for (int j = slot; j < cnt; j += item.slots) {
-                    const float4 x0 = rays[RW * j], x1 = rays[RW * j + 1];
-                    const float4 vva = rays[RW * j + 2], vvb = rays[RW * j + 3];
+                // the lane's rays slot, slot + slots, ... < cnt, walked by address (one
+                // induction variable instead of an index and an address)
+                const float4 *const rend = rays + RW * cnt;
+                for (const float4 *rp = rays + RW * slot; rp < rend; rp += RW * item.slots) {
+                    const float4 x0 = rp[0], x1 = rp[1];
+                    const float4 vva = rp[2], vvb = rp[3];
                     float4 x4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                    if (COLOR) x4 = rays[RW * j + 4];
+                    if (COLOR) x4 = rp[4];
                     const float v0 = x0.x, v1 = x0.y, v2 = x0.z;
                     Geo q;
                     pair_geo_coarse(g, v0, v1, v2, bl.hm, bl.b1, bl.nc2, q);
                     const float delta = exp2_(q.d2);
-                    const float wt = exp2_(q.z2 - x0.w) * x1.x;   // normalised blend weight
+                    // normalised blend weight 2^(z2 - M) / S, with z2 - M = b1 d2 + (nc2 t - M)
+                    const float wt = exp2_(fmaf(bl.b1, q.d2, fmaf(bl.nc2, q.t, -x0.w))) * x1.x;
                     const float tfb = x1.y;
                     float lin = tfb * q.t;
                     if (COLOR) {
