@@ -92,11 +92,13 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
                     pair_geo_coarse(g, v0[j], v1[j], v2[j], bl.hm, bl.b1, bl.nc2, q);
                     const float delta = exp2_(q.d2);
                     D[j] += delta;
+                    // log2 of the weight relative to the running maximum, b1 d2 + (nc2 t - M)
+                    float zr = fmaf(bl.b1, q.d2, fmaf(bl.nc2, q.t, -M[j]));
                     // A weight below 2^-150 of the running maximum is zero in FP32: its terms are
                     // skipped (the branch is uniform over a wave for most distant Gaussians).
-                    if (q.z2 - M[j] < kSkipLog2) continue;
+                    if (zr < kSkipLog2) continue;
                     pair_refine(q);
-                    if (q.z2 > M[j]) {  // new running maximum: rescale the sums (rare)
+                    if (zr > 0.0f) {  // new running maximum: rescale the sums (rare)
                         const float sc = exp2_(M[j] - q.z2);
                         S[j] *= sc;
                         T[j] *= sc;
@@ -111,8 +113,9 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
                             C2[j] *= sc;
                         }
                         M[j] = q.z2;
+                        zr = 0.0f;
                     }
-                    const float ew = exp2_(q.z2 - M[j]);
+                    const float ew = exp2_(zr);
                     S[j] += ew;
                     T[j] = fmaf(ew, q.t, T[j]);
                     if (NORMALS) {
