@@ -362,7 +362,7 @@ __device__ __forceinline__ void ray_prologue(const Params &P, const BwdIn &I, in
         cb2 = I.g_color[3 * r + 2];
         kap = fmaf(cb0, I.color[3 * r], fmaf(cb1, I.color[3 * r + 1], fmaf(cb2, I.color[3 * r + 2], kap)));
     }
-    float dc = (s0.x - nc2 * tf) / b1;
+    float dc = (s0.x - nc2 * tf) * (1.0f / b1);
     if (!isfinite(dc)) dc = 0.0f;
     out[0] = make_float4(v0, v1, v2, s0.x);
     out[1] = make_float4(s0.y, tfb, nb0, nb1);
