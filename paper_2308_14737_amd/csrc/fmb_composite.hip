@@ -171,7 +171,13 @@ constexpr float kCompMinDensity = 0x1p-30f;
 // N^2 2^-40 < 6e-8 of the ray's scale; about three quarters of the pairs fall below it.
 constexpr float kCompMinWeight = 0x1p-40f;
 
-// Writes the segment's pairs (t_j, x_j) with x_j != 0 (DENSITY: x_j > kCompMinDensity) to its
+// Depths are compared in the slot loops as clamp((t_k - t_j) * 2^100, 0, 1) (one subtraction
+// with the clamp modifier on pre-scaled depths, then an FMA): 1 exactly when t_k > t_j, 0 when
+// t_k <= t_j, for every pair of depths below 2^27 in magnitude whose difference is at least
+// 2^-100, i.e. any two distinct depths this renderer meets.
+constexpr float kDepthScale = 0x1p100f;
+
+// Writes the segment's pairs (t_j kDepthScale, x_j) with x_j != 0 (DENSITY: x_j > kCompMinDensity) to its
 // LDS slots, in Gaussian order, and (0, 0) to the rest of its seg * KM slots; returns the
 // largest such count over the wave's segments, the same in every lane.  Terms left out add
 // nothing (or below rounding) to the sums below, so the slot loops run that wave-uniform count
@@ -192,7 +198,7 @@ __device__ __forceinline__ int compact_slots(float2 *__restrict__ slots, const C
         if (k < c.ke) {
             const bool nz = DENSITY ? x[k] > kCompMinDensity : x[k] != 0.0f;
             const unsigned long long bits = (__ballot(nz) >> l0) & segmask;
-            if (nz) slots[cnt + __popcll(bits & below)] = make_float2(q[k].t, x[k]);
+            if (nz) slots[cnt + __popcll(bits & below)] = make_float2(q[k].t * kDepthScale, x[k]);
             cnt += __popcll(bits);
         }
     }
@@ -210,23 +216,27 @@ __device__ __forceinline__ void ordered_sums(const float2 *__restrict__ slots, i
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
         out[k] = 0.0f;
-        t[k] = q[k].t;
+        t[k] = q[k].t * kDepthScale;
     }
+    // 1 if slot depth ts is before (AFTER: behind) t, else 0
+    auto step = [](float ts, float tk) {
+        return __builtin_amdgcn_fmed3f(AFTER ? ts - tk : tk - ts, 0.0f, 1.0f);
+    };
     int j = 0;
     for (; j + 4 <= n; j += 4) {
         const float2 a = slots[j], b = slots[j + 1], cc = slots[j + 2], d = slots[j + 3];
 #pragma unroll
         for (int k = 0; k < KM; ++k) {  // k >= ke: computed and not used
-            out[k] += (AFTER ? a.x > t[k] : a.x < t[k]) ? a.y : 0.0f;
-            out[k] += (AFTER ? b.x > t[k] : b.x < t[k]) ? b.y : 0.0f;
-            out[k] += (AFTER ? cc.x > t[k] : cc.x < t[k]) ? cc.y : 0.0f;
-            out[k] += (AFTER ? d.x > t[k] : d.x < t[k]) ? d.y : 0.0f;
+            out[k] = fmaf(step(a.x, t[k]), a.y, out[k]);
+            out[k] = fmaf(step(b.x, t[k]), b.y, out[k]);
+            out[k] = fmaf(step(cc.x, t[k]), cc.y, out[k]);
+            out[k] = fmaf(step(d.x, t[k]), d.y, out[k]);
         }
     }
     for (; j < n; ++j) {
         const float2 a = slots[j];
 #pragma unroll
-        for (int k = 0; k < KM; ++k) out[k] += (AFTER ? a.x > t[k] : a.x < t[k]) ? a.y : 0.0f;
+        for (int k = 0; k < KM; ++k) out[k] = fmaf(step(a.x, t[k]), a.y, out[k]);
     }
 #pragma unroll
     for (int k = 0; k < KM; ++k)
