@@ -394,7 +394,24 @@ def main():
                 scene_k.backward(outs_k, gdk, gak, grads=grads_k)
 
             extras[name] = leg(step_k, k, pk * sk.n)
-            del scene_k, outs_k, grads_k
+            # the same step as one graph, as the batch's step is timed (launch gaps left out)
+            s2k = torch.cuda.Stream(dev)
+            s2k.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(s2k):
+                step_k()
+            torch.cuda.current_stream().wait_stream(s2k)
+            torch.cuda.synchronize()
+            g_k = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g_k):
+                step_k()
+            for _ in range(3):
+                g_k.replay()
+            ms_k = timed(g_k.replay, k) * 1e3
+            extras[name]["eager_ms_per_step"] = extras[name]["ms_per_step"]
+            extras[name]["ms_per_step"] = ms_k
+            extras[name]["value"] = pk * sk.n / (ms_k * 1e-3)
+            extras[name]["timed"] = "replays of one graph of the step"
+            del g_k, scene_k, outs_k, grads_k
 
         # split statistic: lbar_i = (1/M) sum_j L_j w_ji over the batch's rays
         lossr = t(g.random(P).astype(np.float32))

@@ -33,7 +33,8 @@ hipError_t launch_fwd(int variant, int flags, int grid, hipStream_t st, const Pa
                       const FwdItem *items, int n, const int *order, int *counter);
 hipError_t launch_bwd(int variant, int flags, int grid, hipStream_t st, const Params &P, const BwdIn &I,
                       const BwdItem *items, int n, const int *order, int *counter, float *partial, float *bpart);
-hipError_t launch_fin(int n_tasks, int n_groups, hipStream_t st, const Params &P, const FinTask *tasks,
+hipError_t launch_fin(int n_tasks, int n_groups, int max_gc, int max_nval, hipStream_t st, const Params &P,
+                      const FinTask *tasks,
                       const FinGroup *groups, const float *partial, const float *bpart, double *stage,
                       double *stage_beta, float *g_means, float *g_prec, float *g_weights, float *g_colors,
                       float *g_betas);
@@ -222,6 +223,7 @@ struct Job {
     DevBuf d_fitems, d_forder;
     // backward work
     int bwd_variant = 2, bwd_built = -1, n_bitems = 0, n_tasks = 0, n_groups = 0;
+    int fin_max_gc = 1, fin_max_nval = 1;  // largest chunk and first-stage record (finalize grid)
     DevBuf d_bitems, d_border, d_tasks, d_groups, d_partial, d_bpart, d_stage, d_stage_beta;
     size_t partial_floats = 0;
 
@@ -448,6 +450,10 @@ struct Job {
         HIPCHK(d_stage.ensure(std::max<size_t>(soff, 1) * sizeof(double)));
         HIPCHK(d_stage_beta.ensure(std::max<size_t>(2 * groups.size(), 2) * sizeof(double)));
         n_groups = (int)groups.size();
+        fin_max_gc = 1;
+        fin_max_nval = 1;
+        for (const auto &t : tasks) fin_max_gc = std::max(fin_max_gc, t.gc);
+        for (const auto &g : groups) fin_max_nval = std::max(fin_max_nval, g.nval);
         HIPCHK(d_partial.ensure(std::max<size_t>(poff, 1) * sizeof(float)));
         HIPCHK(d_bpart.ensure(std::max<size_t>(2 * items.size(), 2) * sizeof(float)));
         partial_floats = poff;
@@ -641,7 +647,7 @@ struct Job {
             tb.stop();
         }
         TimedSpan tf(st, 2);
-        HIPCHK(launch_fin(n_tasks, n_groups, st, prm, d_tasks.as<FinTask>(), d_groups.as<FinGroup>(),
+        HIPCHK(launch_fin(n_tasks, n_groups, fin_max_gc, fin_max_nval, st, prm, d_tasks.as<FinTask>(), d_groups.as<FinGroup>(),
                           d_partial.as<float>(), d_bpart.as<float>(), d_stage.as<double>(),
                           d_stage_beta.as<double>(), G.means, G.prec, G.weights, G.colors, G.betas));
         tf.stop();

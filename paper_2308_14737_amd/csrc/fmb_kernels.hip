@@ -550,6 +550,8 @@ __device__ __forceinline__ double ordered_sum(const T *__restrict__ src, int n, 
     return s;
 }
 
+// First stage: block (group, slice) sums the values slice * BLOCK + tid, + BLOCK * slices, ...
+// of a group's records (a record of a whole large scene spreads over many blocks).
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void fin1_kernel(const FinGroup *__restrict__ groups,
                                                     const float *__restrict__ partial,
@@ -559,8 +561,10 @@ __global__ __launch_bounds__(BLOCK) void fin1_kernel(const FinGroup *__restrict_
     const FinGroup gr = groups[blockIdx.x];
     const int tid = threadIdx.x;
     const int n = gr.item_end - gr.item_begin;
-    for (int v = tid; v < gr.nval; v += BLOCK) stage[gr.soff + v] = ordered_sum(partial + gr.poff + v, n, gr.nval);
-    if (tid < 2) stage_beta[2 * blockIdx.x + tid] = ordered_sum(beta_partial + 2 * gr.item_begin + tid, n, 2);
+    for (int v = blockIdx.y * BLOCK + tid; v < gr.nval; v += BLOCK * gridDim.y)
+        stage[gr.soff + v] = ordered_sum(partial + gr.poff + v, n, gr.nval);
+    if (blockIdx.y == 0 && tid < 2)
+        stage_beta[2 * blockIdx.x + tid] = ordered_sum(beta_partial + 2 * gr.item_begin + tid, n, 2);
 }
 
 // Second stage: block (task, slice) finishes kFinSlice Gaussians of a chunk.
@@ -928,17 +932,23 @@ hipError_t launch_bwd(int variant, int flags, int grid, hipStream_t st, const Pa
     }
 }
 
-hipError_t launch_fin(int n_tasks, int n_groups, hipStream_t st, const Params &P, const FinTask *tasks,
-                      const FinGroup *groups, const float *partial, const float *bpart, double *stage,
-                      double *stage_beta, float *g_means, float *g_prec, float *g_weights, float *g_colors,
-                      float *g_betas)
+// max_gc: the largest chunk of any task (a whole scene for the ray-lane backward); max_nval: the
+// largest first-stage record of any group.
+hipError_t launch_fin(int n_tasks, int n_groups, int max_gc, int max_nval, hipStream_t st, const Params &P,
+                      const FinTask *tasks, const FinGroup *groups, const float *partial, const float *bpart,
+                      double *stage, double *stage_beta, float *g_means, float *g_prec, float *g_weights,
+                      float *g_colors, float *g_betas)
 {
-    hipLaunchKernelGGL((fin1_kernel<256>), dim3(n_groups), dim3(256), 0, st, groups, partial, bpart, stage,
+    if (max_gc < 1 || max_nval < 1) return hipErrorInvalidValue;
+    const int slices = (max_nval + 255) / 256 < 65535 ? (max_nval + 255) / 256 : 65535;
+    hipLaunchKernelGGL((fin1_kernel<256>), dim3(n_groups, slices), dim3(256), 0, st, groups, partial, bpart, stage,
                        stage_beta);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((fin2_kernel<256>), dim3(n_tasks, (kBlock + kFinSlice - 1) / kFinSlice), dim3(256), 0, st, P,
-                       tasks, groups, stage, stage_beta, g_means, g_prec, g_weights, g_colors, g_betas);
+    const int gslices = (max_gc + kFinSlice - 1) / kFinSlice;
+    if (gslices > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((fin2_kernel<256>), dim3(n_tasks, gslices), dim3(256), 0, st, P, tasks, groups, stage,
+                       stage_beta, g_means, g_prec, g_weights, g_colors, g_betas);
     return hipGetLastError();
 }
 

@@ -342,6 +342,51 @@ def test_deterministic_backward(fmb):
         assert torch.equal(g1[k], g2[k]), k
 
 
+def test_scene_step_single_graph(fmb):
+    """A single scene's step (forward with normals, backward of depth and alpha cotangents,
+    finalize) captured from its stream as one graph replays like the eager calls, with eager work
+    between the replays."""
+    w = W.make_config("fwdbwd128")
+    sc, cams = w.scenes[0], w.cameras[0]
+    _say("[scene-graph] fwdbwd128")
+    scene, _ = make_scene(fmb, torch, sc, cams, w.betas, w.eta, DEV)
+    outs = scene.render(normals=True)
+    cot = W.random_cotangents(cams.n_rays, 7, flow=False)
+    t = lambda a: torch.as_tensor(a, device=DEV).contiguous()  # noqa: E731
+    gd, ga = t(cot["depth"]), t(cot["alpha"])
+    grads = scene.backward(outs, gd, ga)
+
+    def step():
+        scene.render(normals=True, out=outs)
+        scene.backward(outs, gd, ga, grads=grads)
+
+    s2 = torch.cuda.Stream()
+    s2.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s2):
+        step()
+    torch.cuda.current_stream().wait_stream(s2)
+    torch.cuda.synchronize()
+    ref = {k: v.clone() for k, v in grads.items() if v is not None}
+    ref_depth = outs["depth"].clone()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        outs["depth"].fill_(float("nan"))
+        for v in grads.values():
+            if v is not None:
+                v.fill_(float("nan"))
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(outs["depth"], ref_depth), rep
+        for k, v in ref.items():
+            assert torch.equal(grads[k], v), (rep, k)
+        step()
+        torch.cuda.synchronize()
+        _say(f"[scene-graph] replay {rep} matches eager")
+
+
 @pytest.mark.parametrize("norm", [1, 2])
 def test_loss_grad_kernel(fmb, norm):
     """The fused loss-gradient kernel against the oracle's definition of the Sec. 4 loss."""
@@ -547,6 +592,7 @@ VARIANT_CASES = [
     ("n7_multi", 7, [(5, 3), (64, 64), (1, 1), (33, 65)]),
     ("n90", 90, [(37, 41)]),
     ("n257", 257, [(40, 50), (3, 7)]),
+    ("n600", 600, [(12, 20)]),  # a ray-lane item's chunk (the whole scene) above 256 Gaussians
 ]
 
 
