@@ -317,6 +317,16 @@ struct Job {
         return km;
     }
 
+    // The compositing forward's Gaussians per lane: three (segments of the power of two >= n / 3
+    // lanes, fewer empty slots than two per lane) while every scene has at most 192 Gaussians.
+    // The adjoint keeps comp_km(): at three per lane it needs more than 128 VGPRs.
+    int comp_km_fwd() const
+    {
+        int mx = 0;
+        for (const auto &sc : scenes) mx = std::max(mx, sc.n);
+        return mx <= 3 * 64 ? 3 : comp_km();
+    }
+
     // Backward items (and, for the compositing model, the forward items too).  The key
     // records the model, the colour record size and the blend backward's variant.
     int bwd_key(int variant, bool colour) const
@@ -599,7 +609,7 @@ struct Job {
             int rc = (bwd_built == 1 || bwd_built == 3) ? FMB_OK : build_bwd(bwd_variant, prm.colors != nullptr);
             if (rc) return rc;
             TimedSpan ts(st, 0);
-            HIPCHK(launch_fwdc(comp_km(), fwd_flags(O, false), n_bitems, st, prm, O, d_bitems.as<BwdItem>()));
+            HIPCHK(launch_fwdc(comp_km_fwd(), fwd_flags(O, false), n_bitems, st, prm, O, d_bitems.as<BwdItem>()));
             ts.stop();
             return FMB_OK;
         }

@@ -129,7 +129,7 @@ template <int KM>
 __device__ __forceinline__ CompLanes comp_lanes(int n)
 {
     CompLanes c;
-    c.seg = comp_seg(n);
+    c.seg = comp_seg(n, KM == 3 ? 3 : 2);
     c.ke = (n + c.seg - 1) / c.seg;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     c.sl = lane & (c.seg - 1);
@@ -647,6 +647,8 @@ hipError_t launch_fwdc(int km, int flags, int n_items, hipStream_t st, const Par
         FMB_COMP_DISPATCH(1, flags, FMB_FWDC_CALL)
     } else if (km == 2) {
         FMB_COMP_DISPATCH(2, flags, FMB_FWDC_CALL)
+    } else if (km == 3) {
+        FMB_COMP_DISPATCH(3, flags, FMB_FWDC_CALL)
     } else if (km == 4) {
         FMB_COMP_DISPATCH(4, flags, FMB_FWDC_CALL)
     } else {

@@ -87,12 +87,12 @@ constexpr int kPartial = 10;       // per-Gaussian partial: dU (6), sum rho (3),
 constexpr int kPartialColor = 13;  // ... and dL/d(colour) (3)
 
 // Zero-parameter (alpha-compositing) renderer: lanes per ray for a scene of n Gaussians (the
-// smallest power of two >= n / 2, at most 64, so a lane holds two Gaussians, or up to four
-// beyond 128, and the per-ray work of a segment is shared by twice the pairs) and the largest
-// scene it takes (4 Gaussians per lane).
-constexpr int comp_seg(int n)
+// smallest power of two >= n / per_lane, at most 64, so a lane holds per_lane Gaussians, or up
+// to four beyond 64 per_lane, and the per-ray work of a segment is shared by that many pairs)
+// and the largest scene it takes (4 Gaussians per lane).
+constexpr int comp_seg(int n, int per_lane = 2)
 {
-    const int h = (n + 1) / 2;
+    const int h = (n + per_lane - 1) / per_lane;
     int s = 1;
     while (s < h && s < 64) s <<= 1;
     return s;
