@@ -392,6 +392,9 @@ __global__ __launch_bounds__(kCompBlock) void bwdc_kernel(Params P, BwdIn I, con
                                                           float *__restrict__ partial, float *__restrict__ beta_partial)
 {
     constexpr bool NORMALS = (F & kNrm) != 0, COLOR = (F & kCol) != 0;
+    // without a normal cotangent the pairs take the (A, Bv, L) form of the adjoint
+    // (pair_adjoint_plain), which needs neither the refined peak nor r
+    constexpr bool PLAIN = !NORMALS;
     constexpr int RW = COLOR ? 4 : 3;                        // float4 per staged ray
     constexpr int REC = COLOR ? kPartialColor : kPartial;   // partial record per Gaussian
     constexpr int RAYS4 = kCompBlock * RW;
@@ -416,6 +419,7 @@ __global__ __launch_bounds__(kCompBlock) void bwdc_kernel(Params P, BwdIn I, con
     bool gv[KM];
     comp_entries<KM, COLOR>(P, sr, c, o, g, cc, gv);
     PairAcc acc[KM];
+    PlainAcc pacc[KM];
     float aC[KM][3];
 #pragma unroll
     for (int k = 0; k < KM; ++k) aC[k][0] = aC[k][1] = aC[k][2] = 0.0f;
@@ -448,7 +452,10 @@ __global__ __launch_bounds__(kCompBlock) void bwdc_kernel(Params P, BwdIn I, con
             for (int k = 0; k < KM; ++k) {
                 dl[k] = 0.0f;
                 if (k < c.ke) {
-                    pair_geo(g[k], v0, v1, v2, hm, 0.0f, 0.0f, q[k]);
+                    if (PLAIN)
+                        pair_geo_coarse(g[k], v0, v1, v2, hm, 0.0f, 0.0f, q[k]);
+                    else
+                        pair_geo(g[k], v0, v1, v2, hm, 0.0f, 0.0f, q[k]);
                     dl[k] = gv[k] ? exp2_(q[k].d2) : 0.0f;
                 }
             }
@@ -478,6 +485,11 @@ __global__ __launch_bounds__(kCompBlock) void bwdc_kernel(Params P, BwdIn I, con
             wave_sync();
             float behind[KM];
             ordered_sums<KM, true>(tdl + c.sbase, cnt_b, c, q, behind);
+            float4 vva = make_float4(0.0f, 0.0f, 0.0f, 0.0f), vvb = vva;  // v v^T, shared by the lane's pairs
+            if (PLAIN) {
+                vva = make_float4(v0 * v0, v0 * v1, v0 * v2, v1 * v1);
+                vvb = make_float4(v1 * v2, v2 * v2, 0.0f, 0.0f);
+            }
 #pragma unroll
             for (int k = 0; k < KM; ++k) {
                 if (k < c.ke) {
@@ -488,7 +500,10 @@ __global__ __launch_bounds__(kCompBlock) void bwdc_kernel(Params P, BwdIn I, con
                         aC[k][1] = fmaf(wt[k], x3.y, aC[k][1]);
                         aC[k][2] = fmaf(wt[k], x3.z, aC[k][2]);
                     }
-                    pair_adjoint<NORMALS>(g[k], q[k], v0, v1, v2, wt[k], pn[k], nb0, nb1, nb2, tb, db, acc[k]);
+                    if (PLAIN)
+                        pair_adjoint_plain(q[k].t, q[k].raa, v0, v1, v2, vva, vvb, tb, db, pacc[k]);
+                    else
+                        pair_adjoint<NORMALS>(g[k], q[k], v0, v1, v2, wt[k], pn[k], nb0, nb1, nb2, tb, db, acc[k]);
                 }
             }
         }
@@ -501,9 +516,15 @@ __global__ __launch_bounds__(kCompBlock) void bwdc_kernel(Params P, BwdIn I, con
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
         float *my = red + (tid * KM + k) * REC;
-        const PairAcc &a = acc[k];
-        my[0] = a.u0; my[1] = a.u1; my[2] = a.u2; my[3] = a.u3; my[4] = a.u4; my[5] = a.u5;
-        my[6] = a.p0; my[7] = a.p1; my[8] = a.p2; my[9] = a.l;
+        if (PLAIN) {
+            const PlainAcc &a = pacc[k];
+            my[0] = a.a00; my[1] = a.a01; my[2] = a.a02; my[3] = a.a11; my[4] = a.a12; my[5] = a.a22;
+            my[6] = a.b0; my[7] = a.b1; my[8] = a.b2; my[9] = a.l;
+        } else {
+            const PairAcc &a = acc[k];
+            my[0] = a.u0; my[1] = a.u1; my[2] = a.u2; my[3] = a.u3; my[4] = a.u4; my[5] = a.u5;
+            my[6] = a.p0; my[7] = a.p1; my[8] = a.p2; my[9] = a.l;
+        }
         if (COLOR) {
             my[10] = aC[k][0]; my[11] = aC[k][1]; my[12] = aC[k][2];
         }
@@ -520,7 +541,11 @@ __global__ __launch_bounds__(kCompBlock) void bwdc_kernel(Params P, BwdIn I, con
 #pragma unroll
                 for (int v = 0; v < REC; ++v) sum[v] += src[v];
             }
-        write_partial(partial + item.poff + REC * tid, sum, REC, P.means + 3 * (sr.gauss_off + tid), o);
+        const int gg = sr.gauss_off + tid;
+        if (PLAIN)
+            write_partial_plain(partial + item.poff + REC * tid, sum, REC, P.prec + 6 * gg, P.means + 3 * gg, o);
+        else
+            write_partial(partial + item.poff + REC * tid, sum, REC, P.means + 3 * gg, o);
     }
     if (tid < 2) beta_partial[2 * item.seq + tid] = 0.0f;  // the model has no blend parameters
 }

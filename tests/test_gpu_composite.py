@@ -74,6 +74,24 @@ def test_composite_parity(fmb, label, n, views):
     assert torch.count_nonzero(g["betas"]).item() == 0
 
 
+@pytest.mark.parametrize("label,n,views", [CASES[1], CASES[4], CASES[5]], ids=[CASES[i][0] for i in (1, 4, 5)])
+def test_composite_parity_without_normals(fmb, label, n, views):
+    """Without a normal cotangent the compositing adjoint takes the (A, Bv, L) form; depth, alpha,
+    two-way flow cotangents against the oracle, at two and four Gaussians per lane."""
+    sc, cams = custom_scene(n, views, seed=120 + n, flow=True)
+    _say(f"[composite-plain] {label}: N={n} views={views}")
+    scene, _ = _composite_scene(fmb, sc, cams)
+    outs = scene.render(normals=False)
+    ref, _, _ = O.render_workload_view(sc, cams, BETAS, 1.0, model="composite")
+    cot = hit_mask_cot(W.random_cotangents(cams.n_rays, 8, flow=True, normals=False), ref["alpha"])
+    g = scene.backward(outs, _t(cot["depth"]), _t(cot["alpha"]), None, _t(cot["flow"]))
+    torch.cuda.synchronize()
+    _, gref, _ = O.render_workload_view(sc, cams, BETAS, 1.0, cot=cot, model="composite")
+    eg = compare_grads(g, gref)
+    _say(f"[composite-plain] {label}: {eg}")
+    assert_grads(eg, label)
+
+
 def test_composite_ties_and_behind(fmb):
     """Copies of the same Gaussian (equal t on every ray: no mutual attenuation) and Gaussians
     behind the front camera."""
