@@ -374,6 +374,8 @@ __global__ __launch_bounds__(BLOCK) void bwdr_kernel(Params P, BwdIn I, const Bw
                                                     float *__restrict__ beta_partial)
 {
     constexpr bool NORMALS = (F & kNrm) != 0, PERSIST = (F & kPer) != 0, COLOR = (F & kCol) != 0;
+    // without a normal cotangent the pairs take the (A, Bv, L) form (pair_adjoint_plain)
+    constexpr bool PLAIN = !NORMALS;
     constexpr int EW = COLOR ? 5 : 4;                       // float4 per LDS entry
     constexpr int REC = COLOR ? kPartialColor : kPartial;  // partial record per Gaussian
     constexpr int NW = BLOCK / 64;
@@ -436,7 +438,10 @@ __global__ __launch_bounds__(BLOCK) void bwdr_kernel(Params P, BwdIn I, const Bw
                     bool need_w = false, need_d = false;
 #pragma unroll
                     for (int j = 0; j < RPT; ++j) {
-                        pair_geo(g, x0[j].x, x0[j].y, x0[j].z, bl.hm, bl.b1, bl.nc2, q[j]);
+                        if (PLAIN)
+                            pair_geo_coarse(g, x0[j].x, x0[j].y, x0[j].z, bl.hm, bl.b1, bl.nc2, q[j]);
+                        else
+                            pair_geo(g, x0[j].x, x0[j].y, x0[j].z, bl.hm, bl.b1, bl.nc2, q[j]);
                         delta[j] = exp2_(q[j].d2);
                         const bool w_on = q[j].z2 - x0[j].w >= kSkipLog2;
                         wt[j] = w_on ? exp2_(q[j].z2 - x0[j].w) * x1[j].x : 0.0f;
@@ -444,6 +449,13 @@ __global__ __launch_bounds__(BLOCK) void bwdr_kernel(Params P, BwdIn I, const Bw
                         need_d |= x2[j].z * delta[j] != 0.0f;
                     }
                     PairAcc a;
+                    PlainAcc pa;
+                    // v v^T of ray j, for the plain form
+                    auto vv = [&](int j, float4 &va, float4 &vb) {
+                        const float v0 = x0[j].x, v1 = x0[j].y, v2 = x0[j].z;
+                        va = make_float4(v0 * v0, v0 * v1, v0 * v2, v1 * v1);
+                        vb = make_float4(v1 * v2, v2 * v2, 0.0f, 0.0f);
+                    };
                     float aC0 = 0.0f, aC1 = 0.0f, aC2 = 0.0f;
                     if (__any(need_w)) {
 #pragma unroll
@@ -463,23 +475,41 @@ __global__ __launch_bounds__(BLOCK) void bwdr_kernel(Params P, BwdIn I, const Bw
                             const float db = fmaf(bl.b1, zb, x2[j].z * delta[j]);
                             aB1 = fmaf(zb, q[j].d2 - x3[j].w, aB1);
                             aB2 = fmaf(zb, q[j].t - x2[j].w, aB2);
-                            pair_adjoint<NORMALS>(g, q[j], x0[j].x, x0[j].y, x0[j].z, wt[j], pn, x1[j].z, x1[j].w,
-                                                  x2[j].x, tb, db, a);
+                            if (PLAIN) {
+                                float4 va, vb;
+                                vv(j, va, vb);
+                                pair_adjoint_plain(q[j].t, q[j].raa, x0[j].x, x0[j].y, x0[j].z, va, vb, tb, db, pa);
+                            } else {
+                                pair_adjoint<NORMALS>(g, q[j], x0[j].x, x0[j].y, x0[j].z, wt[j], pn, x1[j].z,
+                                                      x1[j].w, x2[j].x, tb, db, a);
+                            }
                         }
                     } else if (__any(need_d)) {
                         // zero weight on every ray of the wave: only d(alpha)/d(delta) remains
 #pragma unroll
                         for (int j = 0; j < RPT; ++j) {
-                            const PairNormal pn{0, 0, 0, 0, 0};
-                            pair_adjoint<false>(g, q[j], x0[j].x, x0[j].y, x0[j].z, 0.0f, pn, 0.0f, 0.0f, 0.0f,
-                                                0.0f, x2[j].z * delta[j], a);
+                            if (PLAIN) {
+                                float4 va, vb;
+                                vv(j, va, vb);
+                                pair_adjoint_plain(q[j].t, q[j].raa, x0[j].x, x0[j].y, x0[j].z, va, vb, 0.0f,
+                                                   x2[j].z * delta[j], pa);
+                            } else {
+                                const PairNormal pn{0, 0, 0, 0, 0};
+                                pair_adjoint<false>(g, q[j], x0[j].x, x0[j].y, x0[j].z, 0.0f, pn, 0.0f, 0.0f, 0.0f,
+                                                    0.0f, x2[j].z * delta[j], a);
+                            }
                         }
                     } else {
                         continue;  // no term of this Gaussian on this wave's rays
                     }
                     float v[REC];
-                    v[0] = a.u0; v[1] = a.u1; v[2] = a.u2; v[3] = a.u3; v[4] = a.u4; v[5] = a.u5;
-                    v[6] = a.p0; v[7] = a.p1; v[8] = a.p2; v[9] = a.l;
+                    if (PLAIN) {
+                        v[0] = pa.a00; v[1] = pa.a01; v[2] = pa.a02; v[3] = pa.a11; v[4] = pa.a12; v[5] = pa.a22;
+                        v[6] = pa.b0; v[7] = pa.b1; v[8] = pa.b2; v[9] = pa.l;
+                    } else {
+                        v[0] = a.u0; v[1] = a.u1; v[2] = a.u2; v[3] = a.u3; v[4] = a.u4; v[5] = a.u5;
+                        v[6] = a.p0; v[7] = a.p1; v[8] = a.p2; v[9] = a.l;
+                    }
                     if (COLOR) {
                         v[10] = aC0; v[11] = aC1; v[12] = aC2;
                     }
@@ -502,7 +532,11 @@ __global__ __launch_bounds__(BLOCK) void bwdr_kernel(Params P, BwdIn I, const Bw
 #pragma unroll
                     for (int c = 0; c < REC; ++c) sum[c] += wsum[(w * TG + q) * REC + c];
                 }
-                write_partial(partial + item.poff + REC * (gb + q), sum, REC, P.means + 3 * (sr.gauss_off + gb + q), o);
+                const int gg = sr.gauss_off + gb + q;
+                if (PLAIN)
+                    write_partial_plain(partial + item.poff + REC * (gb + q), sum, REC, P.prec + 6 * gg, P.means + 3 * gg, o);
+                else
+                    write_partial(partial + item.poff + REC * (gb + q), sum, REC, P.means + 3 * gg, o);
             }
         }
         // betas: lanes summed over the wave, then the waves in order

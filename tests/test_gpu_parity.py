@@ -628,11 +628,12 @@ def test_backward_variants(fmb, variant, label, n, views):
     assert_grads(eg, f"{label} variant {variant}")
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", range(6))
 @pytest.mark.parametrize("label,n,views", VARIANT_CASES, ids=[c[0] for c in VARIANT_CASES])
 def test_backward_variants_without_normals(fmb, variant, label, n, views):
-    """The Gaussian-lane variants without a normal cotangent take the (A, Bv, L) form of the
-    adjoint: against the oracle with depth, alpha, two-way flow and colour cotangents."""
+    """Every backward variant (Gaussian-lane 0-2, ray-lane 3-5) takes the (A, Bv, L) form of the
+    adjoint without a normal cotangent: against the oracle with depth, alpha, two-way flow and
+    colour cotangents."""
     sc, cams = custom_scene(n, views, seed=310 + n, flow=True)
     cams = W.with_backward_flow(cams, seed=311)
     g = np.random.Generator(np.random.PCG64(312))
