@@ -387,8 +387,13 @@ __global__ __launch_bounds__(kCompBlock) void fwdc_kernel(Params P, FwdOut O, co
 // Backward
 // ------------------------------------------------------------------------------------
 
+// Waves per SIMD the compositing adjoint is compiled for: five for the plain form at two
+// Gaussians per lane (96 VGPRs; it spills 11-16 of its 112-119 and still runs 6 % faster than
+// at four waves), else what its registers give.
+constexpr int bwdc_min_waves(int km, int f) { return km == 2 && (f & (kNrm | kCol)) == 0 ? 5 : 1; }
+
 template <int KM, int F>
-__global__ __launch_bounds__(kCompBlock) void bwdc_kernel(Params P, BwdIn I, const BwdItem *__restrict__ items,
+__global__ __launch_bounds__(kCompBlock) __attribute__((amdgpu_waves_per_eu(bwdc_min_waves(KM, F)))) void bwdc_kernel(Params P, BwdIn I, const BwdItem *__restrict__ items,
                                                           float *__restrict__ partial, float *__restrict__ beta_partial)
 {
     constexpr bool NORMALS = (F & kNrm) != 0, COLOR = (F & kCol) != 0;
