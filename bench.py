@@ -413,6 +413,39 @@ def main():
             extras[name]["timed"] = "replays of one graph of the step"
             del g_k, scene_k, outs_k, grads_k
 
+        # fwd64: the forward alone (depth, alpha, normals) of 40 Gaussians on one 64x64 view (a
+        # single small launch: latency, not throughput)
+        w64 = W.make_config("fwd64")
+        s64, c64 = w64.scenes[0], w64.cameras[0]
+        scene64 = fmb.Scene(t(s64.means), t(s64.prec), t(s64.weights), t(w64.betas), w64.eta,
+                            fmb.Cameras.from_numpy(c64.w2c, c64.intr, c64.hw, device=dev))
+        outs64 = scene64.render(normals=True)
+
+        def step64():
+            scene64.render(normals=True, out=outs64)
+
+        for _ in range(3):
+            step64()
+        s264 = torch.cuda.Stream(dev)
+        s264.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s264):
+            step64()
+        torch.cuda.current_stream().wait_stream(s264)
+        torch.cuda.synchronize()
+        g64 = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g64):
+            step64()
+        for _ in range(3):
+            g64.replay()
+        ms64g = timed(g64.replay, args.steps) * 1e3
+        ms64e = timed(step64, args.steps) * 1e3
+        # one small launch: a graph replay costs more than the eager call, so both are given and
+        # the value is the eager call's
+        extras["fwd64"] = {"value": scene64.n_rays * s64.n / (ms64e * 1e-3), "unit": "pairs/s",
+                           "ms_per_step": ms64e, "graph_ms_per_step": ms64g, "timed": "eager calls",
+                           "workload": "fwd64: N=40, one 64x64 view, forward with normals"}
+        del g64, scene64, outs64
+
         # split statistic: lbar_i = (1/M) sum_j L_j w_ji over the batch's rays
         lossr = t(g.random(P).astype(np.float32))
         lbar = torch.empty(sum(s.n for s in w.scenes), device=dev)

@@ -220,6 +220,7 @@ struct Job {
 
     // forward work
     int fwd_variant = 1, fwd_built = -1, n_fitems = 0;
+    bool launch_fixed = false;  // variants set by the caller or the autotuner
     DevBuf d_fitems, d_forder;
     // backward work
     int bwd_variant = 2, bwd_built = -1, n_bitems = 0, n_tasks = 0, n_groups = 0;
@@ -254,6 +255,9 @@ struct Job {
         prm.scenes = d_scenes.as<SceneRec>();
         prm.views = d_views.as<ViewRec>();
         prm.eta = d_eta.as<float>();
+        // untuned default: 512 rays per forward item, or 256 where that leaves fewer than two
+        // items per compute unit (a 64 x 64 view: 16 items instead of 8)
+        if (!launch_fixed) fwd_variant = P < 2LL * n_cu * fwd_variant_rays(1) ? 0 : 1;
         return FMB_OK;
     }
 
@@ -1102,6 +1106,7 @@ int fmb_set_config(fmb_scene *s, fmb_batch *b, int32_t fwd_variant, int32_t bwd_
     Job &j = s ? s->job : b->job;
     j.fwd_variant = fwd_variant;
     j.bwd_variant = bwd_variant;
+    j.launch_fixed = true;
     j.persist_mult[0] = fwd_grid_mult;
     j.persist_mult[1] = bwd_grid_mult;
     j.drop_graphs();
@@ -1202,6 +1207,7 @@ int fmb_autotune(fmb_scene *s, fmb_batch *b, float *depth, float *alpha, float *
                 j.bwd_variant = bv;
                 j.persist_mult[0] = mf;
                 j.persist_mult[1] = mb;
+                j.launch_fixed = true;
                 return FMB_OK;
             }
         }
@@ -1254,6 +1260,7 @@ int fmb_autotune(fmb_scene *s, fmb_batch *b, float *depth, float *alpha, float *
         }
     j.bwd_variant = bb;
     j.persist_mult[1] = bmb;
+    j.launch_fixed = true;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
