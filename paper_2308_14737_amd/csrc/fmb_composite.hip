@@ -5,8 +5,9 @@
 // Eq. (3) for depth, normals and colour; alpha is Eq. (8) as in the two-parameter model.
 //
 // Layout: one ray per segment of `seg` consecutive lanes of a wave, seg the smallest power of
-// two >= N / 2 (at most 64); lane l of the segment holds Gaussians l, l + seg, ... (ke <= KM of
-// them, two up to N = 128).  The segment writes its (t_i, delta_i) to LDS and every lane sums, for each of its
+// two >= N / 2 (at most 64; N / 3 in the forward at three Gaussians per lane, KM = 3); lane l
+// of the segment holds Gaussians l, l + seg, ... (ke <= KM of them: two up to N = 128, three
+// in the forward up to N = 192).  The segment writes its (t_i, delta_i) to LDS and every lane sums, for each of its
 // Gaussians, the densities of the Gaussians strictly in front of it: an O(N) loop of LDS
 // broadcasts per pair and no sort, with the strict inequality of Eq. (10) taken literally
 // (Gaussians at equal depth do not attenuate one another).  Segment sums (max, weights,
