@@ -147,8 +147,8 @@ def cpu_baseline(w, seconds):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              "(the renderer shards by rays or scenes across GPUs only by design)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (sharding the rays or "
+              "scenes across GPUs is designed, not implemented)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
