@@ -311,7 +311,9 @@ int fmb_split_gaussians(int32_t n, const float *means, const float *prec, const 
 /* Pin the launch configuration of a scene or batch (exactly one non-NULL) instead of
  * autotuning it: forward variant in [0, 4), backward variant in [0, 6) (see
  * fmb_get_config), persistent-grid multipliers 1 or 2.  Every variant computes the same
- * results to rounding; captured graphs are dropped.  Errors: FMB_ERR_INVALID_ARG. */
+ * results to rounding; captured graphs are dropped.  Until this call or fmb_autotune, a job
+ * takes forward variant 1 (512 rays per item), or 0 (256) when it has fewer rays than two
+ * 512-ray items per compute unit, and backward variant 2.  Errors: FMB_ERR_INVALID_ARG. */
 int fmb_set_config(fmb_scene *scene, fmb_batch *batch, int32_t fwd_variant, int32_t bwd_variant,
                    int32_t fwd_grid_mult, int32_t bwd_grid_mult);
 
