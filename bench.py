@@ -211,8 +211,9 @@ def main():
 
     # same steps, eager persistent launches, with HIP-event kernel timing
     def step_eager():
-        batch.forward(outs)
-        cotangents(outs)
+        # the forward writes the loss's depth and alpha cotangents in its per-ray epilogue (the
+        # values the loss kernel would write), then the backward
+        batch.forward_loss(outs, d_t, a_t, cot)
         batch.backward(outs, cot, grads)
 
     for _ in range(args.warmup):

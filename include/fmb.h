@@ -213,6 +213,18 @@ int64_t fmb_batch_gauss_offset(const fmb_batch *batch, int32_t i);
  * fmb_render / fmb_backward with concatenated arrays; g_betas is [s,2]. */
 int fmb_batch_forward(fmb_batch *batch, float *depth, float *alpha, float *normal, float *flow,
                       float *color, float *stash, void *stream);
+/* fmb_batch_forward with the gradient of the reconstruction loss's depth and alpha terms
+ * (Sec. 4: binary cross entropy of alpha, clamped to [1e-6, 1 - 1e-6], against the target
+ * mask alpha_t, plus w_depth times the alpha_t-weighted L1 depth error against depth_t, both
+ * averaged over the batch's rays) written in the same pass: g_depth and g_alpha [P] receive
+ * exactly what fmb_loss_grad writes for them, from the outputs this call renders, and no
+ * separate pass over the outputs is needed.  Targets are caller-owned device arrays [P]; the
+ * loss value itself and flow or colour terms are left to fmb_loss_grad.  Errors:
+ * FMB_ERR_INVALID_ARG for a NULL batch, target or cotangent pointer or a non-finite w_depth,
+ * and those of fmb_batch_forward. */
+int fmb_batch_forward_loss(fmb_batch *batch, float *depth, float *alpha, float *normal, float *flow,
+                           float *color, float *stash, const float *depth_t, const float *alpha_t,
+                           float w_depth, float *g_depth, float *g_alpha, void *stream);
 int fmb_batch_backward(fmb_batch *batch, const float *g_depth, const float *g_alpha,
                        const float *g_normal, const float *g_flow, const float *g_color,
                        const float *depth, const float *color, const float *stash,

@@ -48,6 +48,7 @@ SIGNATURES = {
     "fmb_batch_ray_offset": (_i64, [_vp, _i32]),
     "fmb_batch_gauss_offset": (_i64, [_vp, _i32]),
     "fmb_batch_forward": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "fmb_batch_forward_loss": (_int, [_vp] + [_vp] * 6 + [_vp, _vp, _f32, _vp, _vp, _vp]),
     "fmb_batch_backward": (_int, [_vp] + [_vp] * 13 + [_vp]),
     "fmb_batch_capture": (_int, [_vp] + [_vp] * 16 + [_vp]),
     "fmb_batch_graph_launch": (_int, [_vp, _i32, _vp]),

@@ -989,6 +989,24 @@ int fmb_batch_forward(fmb_batch *b, float *depth, float *alpha, float *normal, f
     return b->job.forward(FwdOut{depth, alpha, normal, flow, color, stash}, true, (hipStream_t)stream);
 }
 
+int fmb_batch_forward_loss(fmb_batch *b, float *depth, float *alpha, float *normal, float *flow, float *color,
+                           float *stash, const float *depth_t, const float *alpha_t, float w_depth,
+                           float *g_depth, float *g_alpha, void *stream)
+{
+    g_err.clear();
+    CHECK_ARG(b, "batch must be non-NULL");
+    CHECK_ARG(depth_t && alpha_t && g_depth && g_alpha, "targets and cotangent outputs must be non-NULL");
+    CHECK_ARG(std::isfinite(w_depth), "w_depth must be finite");
+    FwdOut O{depth, alpha, normal, flow, color, stash};
+    O.depth_t = depth_t;
+    O.alpha_t = alpha_t;
+    O.g_depth = g_depth;
+    O.g_alpha = g_alpha;
+    O.w_depth = w_depth;
+    O.inv_p = 1.0f / (float)b->job.P;  // as the loss kernel forms it
+    return b->job.forward(O, true, (hipStream_t)stream);
+}
+
 int fmb_batch_backward(fmb_batch *b, const float *g_depth, const float *g_alpha, const float *g_normal,
                        const float *g_flow, const float *g_color, const float *depth, const float *color,
                        const float *stash, float *g_means, float *g_prec, float *g_weights, float *g_colors,

@@ -229,6 +229,20 @@ __device__ __forceinline__ float4 colour_entry(const float *__restrict__ q)
                        (float)(1.0 / (1.0 + exp(-(double)q[2]))), 0.0f);
 }
 
+// Gradient of one ray's loss terms with respect to its alpha and depth (Sec. 4: binary cross
+// entropy of alpha, clamped to [1e-6, 1 - 1e-6], against the target mask, and the mask-weighted
+// L1 depth term with weight w_depth), each divided by the ray count (inv_p = 1/p).  The loss
+// kernel and the forward's fused epilogue both use it, so their cotangents agree bit for bit.
+__device__ __forceinline__ void loss_grad_ray(float a, float at, float d, float dt, float w_depth, float inv_p,
+                                              float &ga, float &gd)
+{
+    const float ac = fminf(fmaxf(a, 1e-6f), 1.0f - 1e-6f);
+    const bool inside = a >= 1e-6f && a <= 1.0f - 1e-6f;
+    ga = inside ? (ac - at) / (ac * (1.0f - ac)) * inv_p : 0.0f;
+    const float dd = d - dt;
+    gd = w_depth * at * (float)((dd > 0.0f) - (dd < 0.0f)) * inv_p;
+}
+
 // Outputs of ray r (global index) of view `view` from its blended sums, common to both
 // renderers: S = sum of the weights scaled by 2^-M (M the running maximum of their base-2
 // logarithms), T = sum w t, N = sum w n, C = sum w c (same scale) and D = sum delta.  Writes
@@ -245,8 +259,15 @@ __device__ __forceinline__ void write_ray(const Params &P, const FwdOut &O, int 
     const float invS = 1.0f / S;
     const float tf = T * invS;
     const float n0 = N0 * invS, n1 = N1 * invS, n2 = N2 * invS;
+    const float alpha = -expm1f(-D);
     O.depth[r] = tf;
-    O.alpha[r] = -expm1f(-D);
+    O.alpha[r] = alpha;
+    if (O.g_depth) {
+        float ga, gd;
+        loss_grad_ray(alpha, O.alpha_t[r], tf, O.depth_t[r], O.w_depth, O.inv_p, ga, gd);
+        O.g_alpha[r] = ga;
+        O.g_depth[r] = gd;
+    }
     if (NORMALS) {
         const float inn = 1.0f / sqrtf(fmaf(n0, n0, fmaf(n1, n1, fmaf(n2, n2, kEpsN))));
         O.normal[3 * r + 0] = n0 * inn;

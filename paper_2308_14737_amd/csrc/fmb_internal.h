@@ -113,6 +113,11 @@ struct Params {
 
 struct FwdOut {
     float *depth, *alpha, *normal, *flow, *color, *stash;
+    // Optional, in the per-ray epilogue: the gradient of the loss's depth and alpha terms
+    // against targets (what the loss kernel writes for them), over p rays (inv_p = 1/p).
+    const float *depth_t = nullptr, *alpha_t = nullptr;
+    float *g_depth = nullptr, *g_alpha = nullptr;
+    float w_depth = 0.0f, inv_p = 0.0f;
 };
 
 struct BwdIn {

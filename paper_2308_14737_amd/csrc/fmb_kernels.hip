@@ -784,10 +784,11 @@ __global__ __launch_bounds__(kLossBlock) void loss_kernel(int p, const float *__
         const float at = alpha_t[r];
         const float a = alpha[r];
         const float ac = fminf(fmaxf(a, 1e-6f), 1.0f - 1e-6f);
-        const bool inside = a >= 1e-6f && a <= 1.0f - 1e-6f;
-        g_alpha[r] = inside ? (ac - at) / (ac * (1.0f - ac)) * inv_p : 0.0f;
         const float dd = depth[r] - depth_t[r];
-        g_depth[r] = w_depth * at * (float)((dd > 0.0f) - (dd < 0.0f)) * inv_p;
+        float ga, gd;
+        loss_grad_ray(a, at, depth[r], depth_t[r], w_depth, inv_p, ga, gd);
+        g_alpha[r] = ga;
+        g_depth[r] = gd;
         l = -(at * logf(ac) + (1.0f - at) * logf(1.0f - ac)) + w_depth * at * fabsf(dd);
         if (flow) {
             for (int c = 0; c < flow_cols; ++c) {

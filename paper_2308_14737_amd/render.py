@@ -386,6 +386,15 @@ class Batch:
                   _stream(self.device))
         return outs
 
+    def forward_loss(self, outs: dict, depth_t, alpha_t, cot: dict, w_depth: float = 1.0):
+        """forward() with the depth and alpha cotangents of the reconstruction loss (what
+        loss_grad writes for them) computed in the same pass, into cot["depth"], cot["alpha"]."""
+        _lib.call("fmb_batch_forward_loss", self._h, _vp(outs["depth"]), _vp(outs["alpha"]),
+                  _vp(outs["normal"]), _vp(outs["flow"]), _vp(outs.get("color")), _vp(outs["stash"]),
+                  _vp(depth_t.contiguous()), _vp(alpha_t.contiguous()), ctypes.c_float(w_depth),
+                  _vp(cot["depth"]), _vp(cot["alpha"]), _stream(self.device))
+        return outs
+
     def backward(self, outs: dict, cot: dict, grads: dict):
         _lib.call("fmb_batch_backward", self._h, _vp(cot.get("depth")), _vp(cot.get("alpha")),
                   _vp(cot.get("normal")), _vp(cot.get("flow")), _vp(cot.get("color")), _vp(outs["depth"]),

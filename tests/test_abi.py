@@ -57,6 +57,7 @@ def test_invalid_arguments_rejected_without_gpu(lib):
     assert lib.fmb_set_colors(None, None, None) == 1
     assert lib.fmb_set_cameras(None, 1, None, None, None, None, None) == 1
     assert lib.fmb_batch_forward(None, None, None, None, None, None, None, None) == 1
+    assert lib.fmb_batch_forward_loss(None, *([None] * 8), f(1.0), None, None, None) == 1
     assert lib.fmb_batch_graph_launch(None, 2, None) == 1
     assert lib.fmb_scene_destroy(None) == 0
     assert lib.fmb_batch_destroy(None) == 0

@@ -144,6 +144,32 @@ def test_graph_replay(fmb, batch16):
             betas.mul_(1.01)
 
 
+@pytest.mark.parametrize("model", ["blend", "composite"])
+def test_forward_loss_fused(fmb, batch16, model):
+    """The forward with the loss's depth and alpha cotangents written in its epilogue equals the
+    forward followed by the loss kernel, outputs and cotangents bit for bit."""
+    w, b, _ = batch16
+    b.set_model(model)
+    try:
+        g = np.random.Generator(np.random.PCG64(46))
+        d_t = torch.as_tensor(3.0 + g.random(b.n_rays).astype(np.float32), device=DEV)
+        a_t = torch.as_tensor((g.random(b.n_rays) > 0.5).astype(np.float32), device=DEV)
+        _say(f"[fused-loss] {model}")
+        outs1 = b.forward(b.alloc_outputs(normals=True))
+        ref = fmb.loss_grad(outs1, d_t, a_t, w_depth=0.7)
+        outs2 = b.alloc_outputs(normals=True)
+        cot = {"depth": torch.full((b.n_rays,), float("nan"), device=DEV),
+               "alpha": torch.full((b.n_rays,), float("nan"), device=DEV)}
+        b.forward_loss(outs2, d_t, a_t, cot, w_depth=0.7)
+        torch.cuda.synchronize()
+        for k in ("depth", "alpha", "normal", "stash"):
+            assert torch.equal(outs1[k], outs2[k]), k
+        assert torch.equal(cot["depth"], ref["depth"])
+        assert torch.equal(cot["alpha"], ref["alpha"])
+    finally:
+        b.set_model("blend")
+
+
 def test_whole_step_single_graph(fmb, batch16):
     """The whole training step — forward, the loss kernel's cotangents, backward, finalize — captured
     from its stream as ONE graph replays like the eager calls, several times with eager work in
