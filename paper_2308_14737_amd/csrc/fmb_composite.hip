@@ -372,10 +372,15 @@ __global__ __launch_bounds__(kCompBlock) void fwdc_kernel(Params P, FwdOut O, co
                 const float *r = my_epi + lane * kEpiRec;
                 const int rl = __float_as_int(r[0]);
                 if (rl >= 0) {
+                    float at = 0.0f, dt = 0.0f;  // loss targets, loaded ahead of the direction
+                    if (O.g_depth) {
+                        at = O.alpha_t[vr.ray_off + rl];
+                        dt = O.depth_t[vr.ray_off + rl];
+                    }
                     float w0, w1, w2;
                     ray_dir(P, vr, e, kk, rl, w0, w1, w2);
                     write_ray<F>(P, O, item.view, vr.ray_off + rl, e, kk, o0, o1, o2, w0, w1, w2, r[1], r[2], r[3],
-                                 r[4], r[5], r[6], r[7], r[8], r[9], r[10]);
+                                 r[4], r[5], r[6], r[7], r[8], r[9], r[10], at, dt);
                 }
             }
             wave_sync();

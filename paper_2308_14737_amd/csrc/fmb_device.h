@@ -253,7 +253,7 @@ __device__ __forceinline__ void write_ray(const Params &P, const FwdOut &O, int 
                                           const float *__restrict__ e, const float *__restrict__ kk, float o0,
                                           float o1, float o2, float v0, float v1, float v2, float M, float S,
                                           float T, float N0, float N1, float N2, float C0, float C1, float C2,
-                                          float D)
+                                          float D, float alpha_t = 0.0f, float depth_t = 0.0f)
 {
     constexpr bool NORMALS = (F & kNrm) != 0, FLOW = (F & kFlw) != 0, COLOR = (F & kCol) != 0;
     const float invS = 1.0f / S;
@@ -262,9 +262,9 @@ __device__ __forceinline__ void write_ray(const Params &P, const FwdOut &O, int 
     const float alpha = -expm1f(-D);
     O.depth[r] = tf;
     O.alpha[r] = alpha;
-    if (O.g_depth) {
+    if (O.g_depth) {  // the targets alpha_t, depth_t of ray r, loaded by the caller
         float ga, gd;
-        loss_grad_ray(alpha, O.alpha_t[r], tf, O.depth_t[r], O.w_depth, O.inv_p, ga, gd);
+        loss_grad_ray(alpha, alpha_t, tf, depth_t, O.w_depth, O.inv_p, ga, gd);
         O.g_alpha[r] = ga;
         O.g_depth[r] = gd;
     }

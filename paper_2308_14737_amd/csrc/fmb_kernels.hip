@@ -62,6 +62,7 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
 
         float v0[RPT], v1[RPT], v2[RPT];
         float M[RPT], S[RPT], T[RPT], N0[RPT], N1[RPT], N2[RPT], D[RPT], C0[RPT], C1[RPT], C2[RPT];
+        float at[RPT], dt[RPT];  // loss targets, loaded now so that the epilogue does not wait
         int loc[RPT];
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
@@ -70,6 +71,11 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
             ray_dir(P, vr, e, kk, lc, v0[j], v1[j], v2[j]);
             M[j] = -INFINITY;
             S[j] = T[j] = N0[j] = N1[j] = N2[j] = D[j] = C0[j] = C1[j] = C2[j] = 0.0f;
+            at[j] = dt[j] = 0.0f;
+            if (O.g_depth) {
+                at[j] = O.alpha_t[vr.ray_off + lc];
+                dt[j] = O.depth_t[vr.ray_off + lc];
+            }
         }
 
         for (int gb = 0; gb < sr.n; gb += TG) {
@@ -141,7 +147,7 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
         for (int j = 0; j < RPT; ++j) {
             if (loc[j] >= hw) continue;
             write_ray<F>(P, O, item.view, vr.ray_off + loc[j], e, kk, o0, o1, o2, v0[j], v1[j], v2[j], M[j], S[j],
-                         T[j], N0[j], N1[j], N2[j], C0[j], C1[j], C2[j], D[j]);
+                         T[j], N0[j], N1[j], N2[j], C0[j], C1[j], C2[j], D[j], at[j], dt[j]);
         }
         if (!PERSIST) break;
     }
