@@ -499,6 +499,8 @@ def main():
         "batched_over_plain": (plain_ms / ms_step) if plain_ms else None,
         "eager_ms_per_step": ms_eager,
         "timed": "replays of one graph of the whole step" if ms_graph is not None else "eager launches",
+        "loss": "depth and alpha cotangents written by the forward's per-ray epilogue "
+                "(library_graphs_ms_per_step and the plain leg run the separate loss kernel)",
         "library_graphs_ms_per_step": ms_graph_api,
         "fp32_peak_frac_step": step_flops / (ms_step * 1e-3) / PEAK_FP32,
         "kernel_ms": {"forward": fwd_ms, "backward": bwd_ms, "finalize": fin_ms},
