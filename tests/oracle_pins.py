@@ -299,6 +299,35 @@ def pin_rays_reproject():
     _close(uv, np.stack([col + 0.5, row + 0.5], axis=1), 0, 1e-10, "reprojection")
 
 
+def pin_dir_rays():
+    """Explicit-direction rays (the random ray minibatches of Sec. 4): every ray starts at the
+    centre of its view's camera and has the unit direction of the given vector, whatever its
+    length.  Hand cases on an axis-aligned camera, then pixel-centre directions of rotated cameras
+    (formed here from R^T d_c, independently of the oracle) scaled by random positive factors,
+    which must give exactly the pixel rays' origins and unit directions."""
+    e = np.array([[1.0, 0, 0, -1], [0, 1, 0, -2], [0, 0, 1, 3]])  # R = I, centre (1, 2, -3)
+    o, v = O.dir_rays([0, 0, 0], [[0, 0, 7.5], [3, 4, 0], [0, -1e-3, 0]], e[None])
+    _close(o, np.tile([1.0, 2.0, -3.0], (3, 1)), 0, 1e-15, "camera centre")
+    _close(v, [[0, 0, 1], [0.6, 0.8, 0], [0, -1, 0]], 0, 1e-15, "unit direction")
+    g = _rng(23)
+    es = np.stack([_look_at(3 * _unit(g.standard_normal(3))) for _ in range(3)])
+    ks = np.array([[80.0, 90.0, 40.0, 30.0], [64, 64, 32, 32], [100, 100, 60, 45]])
+    view = np.repeat(np.arange(3), 6).astype(np.int32)
+    row = g.integers(0, 60, 18).astype(np.int32)
+    col = g.integers(0, 80, 18).astype(np.int32)
+    dc = np.stack([(col + 0.5 - ks[view, 2]) / ks[view, 0], (row + 0.5 - ks[view, 3]) / ks[view, 1],
+                   np.ones(18)], axis=1)
+    d = np.einsum("pji,pj->pi", es[view, :, :3], dc)  # R^T d_c per ray
+    scale = np.exp(g.uniform(-3.0, 3.0, (18, 1)))
+    o, v = O.dir_rays(view, d * scale, es)
+    op, vp = O.pixel_rays(view, row, col, es, ks)
+    centres = -np.einsum("kji,kj->ki", es[:, :, :3], es[:, :, 3])
+    _close(o, centres[view], 0, 1e-14, "origin = camera centre of the ray's view")
+    _close(o, op, 0, 1e-15, "origins of explicit and pixel rays")
+    _close(np.linalg.norm(v, axis=1), np.ones(18), 0, 1e-15, "unit length")
+    _close(v, vp, 0, 1e-15, "directions of explicit and pixel rays")
+
+
 def _flow_setup(g, n=6):
     sc, _ = _random_scene(g, n, spread=0.5)
     c = np.array([0.4, -2.6, 1.2])
@@ -860,7 +889,7 @@ def pin_loss_gradient():
 ALL_PINS = [
     pin_isotropic_closed_form, pin_bruteforce_peak, pin_interop_alpha, pin_alpha_identities,
     pin_two_gaussian_blend, pin_zero_betas_mean, pin_permutation, pin_pixel_ray_hand_case,
-    pin_rays_reproject, pin_flow_equal_poses, pin_flow_rotation_homography, pin_flow_translation,
+    pin_rays_reproject, pin_dir_rays, pin_flow_equal_poses, pin_flow_rotation_homography, pin_flow_translation,
     pin_scale_invariance, pin_rigid_motion, pin_normals_geometry, pin_gradients_fd,
     pin_isotropic_depth_gradient, pin_two_gaussian_beta_gradient, pin_loss_gradient,
     pin_colour_blend, pin_flow_both_directions, pin_max_weight,

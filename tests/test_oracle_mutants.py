@@ -52,6 +52,8 @@ MUTANTS = {
                                  "if (pq->t > q[k].t) later += zbar[k];"),
     "adj_composite_slope_dropped": ("d_bar = z_bar * log_opacity_slope(pq->delta);", "d_bar = z_bar;"),
     "split_mean_over_gaussians": ("lbar[i] = s / (double)p;", "lbar[i] = s / (double)n;"),
+    "dir_rays_unnormalised": ("double nn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);", "double nn = 1.0;"),
+    "dir_rays_first_view": ("cam_centre(w2c + 12 * (int64_t)view[r], orig + 3 * r);", "cam_centre(w2c, orig + 3 * r);"),
     "split_unweighted": ("acc[(size_t)tid * n + i] += loss[r] * wt[i];", "acc[(size_t)tid * n + i] += loss[r];"),
 }
 
