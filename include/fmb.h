@@ -56,6 +56,14 @@ extern "C" {
 
 #define FMB_ABI_VERSION 3
 
+/* Size limits, checked on the host before any work is enqueued (FMB_ERR_SHAPE beyond them):
+ * rays of a scene, batch or loss call (2^31 - 2^24: every ray index and every tile end stays a
+ * 32-bit int; per-ray output offsets such as 3 r or 4 r are formed in 64 bits), Gaussians of a
+ * scene or batch, and views of a scene or batch. */
+#define FMB_MAX_RAYS 2130706432LL
+#define FMB_MAX_GAUSSIANS 268435455
+#define FMB_MAX_VIEWS 134217727
+
 enum fmb_status {
     FMB_OK = 0,
     FMB_ERR_INVALID_ARG = 1, /* null pointer, non-positive size, bad flag or value */
@@ -86,13 +94,14 @@ const char *fmb_last_error(void);
 /* Single scene                                                                   */
 /* ------------------------------------------------------------------------------ */
 
-/* Create a scene of n >= 1 Gaussians (representation of Sec. 3.1).
+/* Create a scene of 1 <= n <= FMB_MAX_GAUSSIANS Gaussians (representation of Sec. 3.1).
  *   means   device [n,3]; prec device [n,6] packed upper U; weights device [n] (> 0);
  *   betas   device [2] (beta1, beta2 of Eq. 7); eta host scalar > 0 (Eq. 7).
  * The pointers are BORROWED: they must stay valid while the scene is used and may be
  * updated in place between calls (each render/backward reads their current values).
  * Errors: FMB_ERR_INVALID_ARG for n < 1, a NULL pointer, eta <= 0 or misaligned input;
- * FMB_ERR_HIP / FMB_ERR_OOM if the small device descriptors cannot be created.
+ * FMB_ERR_SHAPE for n > FMB_MAX_GAUSSIANS; FMB_ERR_HIP / FMB_ERR_OOM if the small device
+ * descriptors cannot be created.
  * Values are not inspected (use fmb_validate). */
 int fmb_scene_create(fmb_scene **out, int32_t n, const float *means, const float *prec,
                      const float *weights, const float *betas, float eta);
@@ -105,13 +114,13 @@ int fmb_scene_rebind(fmb_scene *scene, const float *means, const float *prec,
  * no work using the scene is still running (synchronise its streams first). */
 int fmb_scene_destroy(fmb_scene *scene);
 
-/* Set the v >= 1 views the scene is rendered from (all poses passed to the renderer,
+/* Set the 1 <= v <= FMB_MAX_VIEWS views the scene is rendered from (all poses passed to the renderer,
  * Sec. 5).  w2c device [v,3,4]; intr device [v,4] (fx, fy, cx, cy); hw host [v,2]
  * (H, W >= 1).  w2c_b / intr_b: device [v,3,4] / [v,4] second pose per view for the
  * flow output, or both NULL (no flow).  Borrowed like the scene parameters.  Sizes the
- * workspace (P = sum H W rays, at most 2^31 - 1).
+ * workspace (P = sum H W rays, at most FMB_MAX_RAYS).
  * Errors: FMB_ERR_INVALID_ARG (NULL, v < 1, H or W < 1, only one of w2c_b/intr_b),
- * FMB_ERR_SHAPE (P too large), FMB_ERR_OOM / FMB_ERR_HIP. */
+ * FMB_ERR_SHAPE (P > FMB_MAX_RAYS or v > FMB_MAX_VIEWS), FMB_ERR_OOM / FMB_ERR_HIP. */
 int fmb_set_cameras(fmb_scene *scene, int32_t v, const float *w2c, const float *intr,
                     const int32_t *hw, const float *w2c_b, const float *intr_b);
 
@@ -194,7 +203,8 @@ int fmb_backward(fmb_scene *scene, const float *g_depth, const float *g_alpha,
  *            w2c device [sum v,3,4], intr device [sum v,4], hw host [sum v,2],
  *            w2c_b / intr_b device or both NULL.
  * Rays and outputs are concatenated scene after scene, each scene in the single-scene
- * ray order.  All device pointers are borrowed (see fmb_scene_create).
+ * ray order.  All device pointers are borrowed (see fmb_scene_create).  The batch's total
+ * Gaussians, views and rays are limited by FMB_MAX_GAUSSIANS, FMB_MAX_VIEWS and FMB_MAX_RAYS.
  * Errors: as fmb_scene_create and fmb_set_cameras. */
 int fmb_batch_create(fmb_batch **out, int32_t s, const int32_t *n_host, const int32_t *v_host,
                      const float *means, const float *prec, const float *weights,
@@ -280,7 +290,7 @@ int fmb_autotune(fmb_scene *scene, fmb_batch *batch, float *depth, float *alpha,
  * |x|' is sign(x) (0 at 0).  block_loss: device [ceil(p / 1024)] or NULL; if given,
  * receives per-block partial sums of L (sum them for the loss; the order is fixed).
  * Errors: FMB_ERR_INVALID_ARG (p < 1, NULL required pointer, flow_norm not 1 or 2,
- * flow_cols not 2 or 4). */
+ * flow_cols not 2 or 4), FMB_ERR_SHAPE (p > FMB_MAX_RAYS). */
 int fmb_loss_grad(int64_t p, const float *depth, const float *alpha, const float *flow,
                   const float *color, const float *depth_t, const float *alpha_t,
                   const float *flow_t, const float *color_t, float w_depth, float w_flow,

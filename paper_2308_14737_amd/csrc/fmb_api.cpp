@@ -93,6 +93,13 @@ int fail(int code, const std::string &msg)
 
 bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
+// Size limits (FMB_MAX_* in fmb.h).  Ray indices are 32-bit in the kernels (per-ray output offsets
+// are formed in 64 bits); the 2^24 rays of headroom keep every tile or span end (spans are at most
+// 2^22 rays) inside int.  Gaussian and view counts keep 16 x index inside int.
+constexpr int64_t kMaxRays = FMB_MAX_RAYS;
+constexpr int64_t kMaxGaussians = FMB_MAX_GAUSSIANS;
+constexpr int64_t kMaxViews = FMB_MAX_VIEWS;
+
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
@@ -683,12 +690,13 @@ int check_cams(const float *w2c, const float *intr, const int32_t *hw, int v, co
     CHECK_ARG(w2c && intr && hw, "w2c, intr and hw must be non-NULL");
     CHECK_ARG(aligned(w2c, 4) && aligned(intr, 4), "camera arrays must be 4-byte aligned");
     CHECK_ARG((w2c_b == nullptr) == (intr_b == nullptr), "w2c_b and intr_b must both be given or both NULL");
+    if (v > kMaxViews) return fail(FMB_ERR_SHAPE, "more than FMB_MAX_VIEWS views");
     p = 0;
     for (int k = 0; k < v; ++k) {
         CHECK_ARG(hw[2 * k] >= 1 && hw[2 * k + 1] >= 1, "image sizes must be >= 1");
         p += (int64_t)hw[2 * k] * hw[2 * k + 1];
+        if (p > kMaxRays) return fail(FMB_ERR_SHAPE, "more than FMB_MAX_RAYS rays");
     }
-    if (p > INT32_MAX) return fail(FMB_ERR_SHAPE, "more than 2^31-1 rays");
     return FMB_OK;
 }
 
@@ -718,6 +726,7 @@ int fmb_scene_create(fmb_scene **out, int32_t n, const float *means, const float
     CHECK_ARG(std::isfinite(eta) && eta > 0.0f, "eta must be finite and > 0");
     int rc = check_params(means, prec, weights, betas);
     if (rc) return rc;
+    if (n > kMaxGaussians) return fail(FMB_ERR_SHAPE, "more than FMB_MAX_GAUSSIANS Gaussians");
     fmb_scene *s = new (std::nothrow) fmb_scene();
     if (!s) return fail(FMB_ERR_OOM, "host allocation failed");
     s->n = n;
@@ -802,13 +811,14 @@ int fmb_set_rays(fmb_scene *s, int32_t v, const float *w2c, const float *intr, c
     CHECK_ARG(counts && dirs && w2c && intr, "w2c, intr, counts and dirs must be non-NULL");
     CHECK_ARG(aligned(w2c, 4) && aligned(intr, 4) && aligned(dirs, 4), "arrays must be 4-byte aligned");
     CHECK_ARG((w2c_b == nullptr) == (intr_b == nullptr), "w2c_b and intr_b must both be given or both NULL");
+    if (v > kMaxViews) return fail(FMB_ERR_SHAPE, "more than FMB_MAX_VIEWS views");
     int64_t p = 0;
     for (int k = 0; k < v; ++k) {
         CHECK_ARG(counts[k] >= 0, "ray counts must be >= 0");
         p += counts[k];
+        if (p > kMaxRays) return fail(FMB_ERR_SHAPE, "more than FMB_MAX_RAYS rays");
     }
     CHECK_ARG(p >= 1, "at least one ray is needed");
-    if (p > INT32_MAX) return fail(FMB_ERR_SHAPE, "more than 2^31-1 rays");
     Job &j = s->job;
     j.V = v;
     j.P = p;
@@ -917,7 +927,8 @@ int fmb_batch_create(fmb_batch **out, int32_t s, const int32_t *n_host, const in
         n_total += n_host[i];
         v_total += v_host[i];
     }
-    if (n_total > INT32_MAX / 8 || v_total > INT32_MAX / 16) return fail(FMB_ERR_SHAPE, "batch too large");
+    if (n_total > kMaxGaussians) return fail(FMB_ERR_SHAPE, "more than FMB_MAX_GAUSSIANS Gaussians in the batch");
+    if (v_total > kMaxViews) return fail(FMB_ERR_SHAPE, "more than FMB_MAX_VIEWS views in the batch");
     int64_t p = 0;
     if ((rc = check_cams(w2c, intr, hw, (int)v_total, w2c_b, intr_b, p))) return rc;
     fmb_batch *b = new (std::nothrow) fmb_batch();
@@ -1295,7 +1306,8 @@ int fmb_loss_grad(int64_t p, const float *depth, const float *alpha, const float
                   float *g_depth, float *g_alpha, float *g_flow, float *g_color, float *block_loss, void *stream)
 {
     g_err.clear();
-    CHECK_ARG(p >= 1 && p <= INT32_MAX, "p must be in [1, 2^31)");
+    CHECK_ARG(p >= 1, "p must be >= 1");
+    if (p > kMaxRays) return fail(FMB_ERR_SHAPE, "more than FMB_MAX_RAYS rays");
     CHECK_ARG(depth && alpha && depth_t && alpha_t && g_depth && g_alpha, "required pointer is NULL");
     CHECK_ARG((flow == nullptr) == (flow_t == nullptr) && (flow == nullptr) == (g_flow == nullptr),
               "flow, flow_t and g_flow must all be given or all be NULL");

@@ -256,6 +256,7 @@ __device__ __forceinline__ void write_ray(const Params &P, const FwdOut &O, int 
                                           float D, float alpha_t = 0.0f, float depth_t = 0.0f)
 {
     constexpr bool NORMALS = (F & kNrm) != 0, FLOW = (F & kFlw) != 0, COLOR = (F & kCol) != 0;
+    const size_t r3 = 3 * (size_t)r;  // per-ray offsets in 64 bits: 3 r overflows int above 7.2e8 rays
     const float invS = 1.0f / S;
     const float tf = T * invS;
     const float n0 = N0 * invS, n1 = N1 * invS, n2 = N2 * invS;
@@ -270,9 +271,9 @@ __device__ __forceinline__ void write_ray(const Params &P, const FwdOut &O, int 
     }
     if (NORMALS) {
         const float inn = 1.0f / sqrtf(fmaf(n0, n0, fmaf(n1, n1, fmaf(n2, n2, kEpsN))));
-        O.normal[3 * r + 0] = n0 * inn;
-        O.normal[3 * r + 1] = n1 * inn;
-        O.normal[3 * r + 2] = n2 * inn;
+        O.normal[r3 + 0] = n0 * inn;
+        O.normal[r3 + 1] = n1 * inn;
+        O.normal[r3 + 2] = n2 * inn;
     }
     if (FLOW) {
         // flow to the second pose (and, if given, to a third: forward and backward flow)
@@ -281,19 +282,20 @@ __device__ __forceinline__ void write_ray(const Params &P, const FwdOut &O, int 
         project(P.w2c_b + 12 * view, P.intr_b + 4 * view, p0, p1, p2, ub, vb);
         project(e, kk, p0, p1, p2, ua, va);
         const int fk = P.w2c_c ? 4 : 2;
-        O.flow[fk * r + 0] = ub - ua;
-        O.flow[fk * r + 1] = vb - va;
+        float *fl = O.flow + (size_t)fk * r;
+        fl[0] = ub - ua;
+        fl[1] = vb - va;
         if (P.w2c_c) {
             float uc, vc;
             project(P.w2c_c + 12 * view, P.intr_c + 4 * view, p0, p1, p2, uc, vc);
-            O.flow[fk * r + 2] = uc - ua;
-            O.flow[fk * r + 3] = vc - va;
+            fl[2] = uc - ua;
+            fl[3] = vc - va;
         }
     }
     if (COLOR) {
-        O.color[3 * r + 0] = C0 * invS;
-        O.color[3 * r + 1] = C1 * invS;
-        O.color[3 * r + 2] = C2 * invS;
+        O.color[r3 + 0] = C0 * invS;
+        O.color[r3 + 1] = C1 * invS;
+        O.color[r3 + 2] = C2 * invS;
     }
     if (O.stash) {
         float4 *st = reinterpret_cast<float4 *>(O.stash) + 2 * (size_t)r;
@@ -349,6 +351,7 @@ __device__ __forceinline__ void ray_prologue(const Params &P, const BwdIn &I, in
     float v0, v1, v2;
     ray_dir(P, vr, e, kk, local, v0, v1, v2);
     const int r = vr.ray_off + local;
+    const size_t r3 = 3 * (size_t)r;  // 64-bit per-ray offsets (3 r overflows int above 7.2e8 rays)
     const float tf = I.depth[r];
     const float4 s0 = reinterpret_cast<const float4 *>(I.stash)[2 * (size_t)r];
     const float4 s1 = reinterpret_cast<const float4 *>(I.stash)[2 * (size_t)r + 1];
@@ -359,9 +362,10 @@ __device__ __forceinline__ void ray_prologue(const Params &P, const BwdIn &I, in
         // d flow / d t_f = J_B R_B v (and likewise for the optional third pose).
         const float p0 = fmaf(tf, v0, o0), p1 = fmaf(tf, v1, o1), p2 = fmaf(tf, v2, o2);
         const int fk = P.w2c_c ? 4 : 2;
-        tfb += flow_dot(P.w2c_b + 12 * view, P.intr_b + 4 * view, p0, p1, p2, v0, v1, v2, I.g_flow + fk * r);
+        const float *gfl = I.g_flow + (size_t)fk * r;
+        tfb += flow_dot(P.w2c_b + 12 * view, P.intr_b + 4 * view, p0, p1, p2, v0, v1, v2, gfl);
         if (P.w2c_c)
-            tfb += flow_dot(P.w2c_c + 12 * view, P.intr_c + 4 * view, p0, p1, p2, v0, v1, v2, I.g_flow + fk * r + 2);
+            tfb += flow_dot(P.w2c_c + 12 * view, P.intr_c + 4 * view, p0, p1, p2, v0, v1, v2, gfl + 2);
     }
     const float Db = I.g_alpha ? I.g_alpha[r] * expf(-Dsum) : 0.0f;
     float nb0 = 0.0f, nb1 = 0.0f, nb2 = 0.0f;
@@ -369,7 +373,7 @@ __device__ __forceinline__ void ray_prologue(const Params &P, const BwdIn &I, in
         const float s = sqrtf(fmaf(Nx, Nx, fmaf(Ny, Ny, fmaf(Nz, Nz, kEpsN))));
         const float is = 1.0f / s;
         const float f0 = Nx * is, f1 = Ny * is, f2 = Nz * is;
-        const float g0 = I.g_normal[3 * r], g1 = I.g_normal[3 * r + 1], g2 = I.g_normal[3 * r + 2];
+        const float g0 = I.g_normal[r3], g1 = I.g_normal[r3 + 1], g2 = I.g_normal[r3 + 2];
         const float dp = fmaf(f0, g0, fmaf(f1, g1, f2 * g2));
         nb0 = (g0 - f0 * dp) * is;
         nb1 = (g1 - f1 * dp) * is;
@@ -378,10 +382,10 @@ __device__ __forceinline__ void ray_prologue(const Params &P, const BwdIn &I, in
     float kap = fmaf(tfb, tf, fmaf(nb0, Nx, fmaf(nb1, Ny, nb2 * Nz)));
     float cb0 = 0.0f, cb1 = 0.0f, cb2 = 0.0f;
     if (COLOR) {
-        cb0 = I.g_color[3 * r];
-        cb1 = I.g_color[3 * r + 1];
-        cb2 = I.g_color[3 * r + 2];
-        kap = fmaf(cb0, I.color[3 * r], fmaf(cb1, I.color[3 * r + 1], fmaf(cb2, I.color[3 * r + 2], kap)));
+        cb0 = I.g_color[r3];
+        cb1 = I.g_color[r3 + 1];
+        cb2 = I.g_color[r3 + 2];
+        kap = fmaf(cb0, I.color[r3], fmaf(cb1, I.color[r3 + 1], fmaf(cb2, I.color[r3 + 2], kap)));
     }
     float dc = (s0.x - nc2 * tf) * (1.0f / b1);
     if (!isfinite(dc)) dc = 0.0f;

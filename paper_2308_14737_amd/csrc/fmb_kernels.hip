@@ -783,7 +783,8 @@ __global__ __launch_bounds__(kLossBlock) void loss_kernel(int p, const float *__
                                                          float *__restrict__ block_loss)
 {
     __shared__ float red[kLossBlock / 64];
-    const int r = blockIdx.x * kLossBlock + threadIdx.x;
+    // 64-bit ray index: the products flow_cols r and 3 r overflow int above 5.4e8 rays
+    const int64_t r = (int64_t)blockIdx.x * kLossBlock + threadIdx.x;
     const float inv_p = 1.0f / (float)p;
     float l = 0.0f;
     if (r < p) {

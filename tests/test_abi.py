@@ -96,3 +96,43 @@ def test_new_entry_points_reject_bad_arguments(lib):
     assert lib.fmb_split_gaussians(1, mean, prec, w, None, nw, None, om, op, ow, None) == 1
     assert lib.fmb_loss_grad(4, *([None] * 8), ctypes.c_float(1), ctypes.c_float(1), 2, 3, ctypes.c_float(1),
                              *([None] * 5), None) == 1
+
+
+def test_oversized_shapes_rejected_without_gpu(lib):
+    """More rays, Gaussians or views than the FMB_MAX_* limits of fmb.h are refused with
+    FMB_ERR_SHAPE on the host, before any device work (and before a scene handle is used)."""
+    max_rays, max_gauss, max_views = 2130706432, 268435455, 134217727
+    h = ctypes.c_void_p()
+    f = ctypes.c_float
+    fake = ctypes.c_void_p(4096)
+    assert lib.fmb_scene_create(ctypes.byref(h), max_gauss + 1, fake, fake, fake, fake, f(1.0)) == 2
+    assert b"FMB_MAX_GAUSSIANS" in lib.fmb_last_error()
+    one = (ctypes.c_int32 * 1)(1)
+    eta = (ctypes.c_float * 1)(1.0)
+    # one view of more than FMB_MAX_RAYS rays, then FMB_MAX_RAYS + 1 rays over two views
+    big = (ctypes.c_int32 * 2)(max_rays // 65536 + 1, 65536)
+    assert lib.fmb_batch_create(ctypes.byref(h), 1, one, one, fake, fake, fake, fake, eta, fake, fake, big,
+                                None, None) == 2
+    assert b"FMB_MAX_RAYS" in lib.fmb_last_error()
+    two = (ctypes.c_int32 * 1)(2)
+    hw2 = (ctypes.c_int32 * 4)(max_rays // 2, 1, max_rays // 2 + 1, 1)
+    assert lib.fmb_batch_create(ctypes.byref(h), 1, one, two, fake, fake, fake, fake, eta, fake, fake, hw2,
+                                None, None) == 2
+    n_big = (ctypes.c_int32 * 2)(max_gauss, 1)
+    v2 = (ctypes.c_int32 * 2)(1, 1)
+    eta2 = (ctypes.c_float * 2)(1.0, 1.0)
+    hw_small = (ctypes.c_int32 * 4)(4, 4, 4, 4)
+    assert lib.fmb_batch_create(ctypes.byref(h), 2, n_big, v2, fake, fake, fake, fake, eta2, fake, fake,
+                                hw_small, None, None) == 2
+    vmany = (ctypes.c_int32 * 1)(max_views + 1)
+    assert lib.fmb_batch_create(ctypes.byref(h), 1, one, vmany, fake, fake, fake, fake, eta, fake, fake,
+                                hw_small, None, None) == 2
+    assert b"FMB_MAX_VIEWS" in lib.fmb_last_error()
+    # per-scene cameras and explicit rays: the shape checks run before the handle is used
+    assert lib.fmb_set_cameras(fake, 1, fake, fake, big, None, None) == 2
+    counts = (ctypes.c_int32 * 2)(max_rays // 2, max_rays // 2 + 1)
+    assert lib.fmb_set_rays(fake, 2, fake, fake, counts, fake, None, None) == 2
+    assert lib.fmb_set_rays(fake, max_views + 1, fake, fake, counts, fake, None, None) == 2
+    # the loss gradient over more rays than the limit
+    assert lib.fmb_loss_grad(max_rays + 1, *([fake] * 8), f(1), f(1), 2, 2, f(1), fake, fake, None, None,
+                             None, None) == 2
