@@ -237,6 +237,10 @@ struct Job {
 
     hipGraphExec_t gexec[2] = {nullptr, nullptr};  // captured forward, backward
 
+    // Captured graphs hold the kernel arguments of their launches: the Params (colours, flow
+    // targets), the item lists, their counts and the workspace addresses.  Every change of
+    // those (a rebuilt item list, a moved buffer, new Params) drops them, so a stale graph is
+    // never replayed: fmb_batch_graph_launch then reports FMB_ERR_STATE.
     void drop_graphs()
     {
         for (auto &g : gexec) {
@@ -271,6 +275,7 @@ struct Job {
     int build_fwd(int variant)
     {
         if (fwd_built == variant) return FMB_OK;
+        drop_graphs();  // the forward graph's items (and possibly their buffer) change
         const int R = fwd_variant_rays(variant);
         std::vector<FwdItem> items;
         std::vector<double> cost;
@@ -349,6 +354,7 @@ struct Job {
     {
         const int key = bwd_key(variant, colour);
         if (bwd_built == key) return FMB_OK;
+        drop_graphs();  // items, partial records and the finalize plan change (and may move)
         const bool comp = model == FMB_MODEL_COMPOSITE;
         const int rec = colour ? kPartialColor : kPartial;
         const int RT = bwd_variant_rt(variant);
@@ -856,6 +862,7 @@ int fmb_set_flow_pose2(fmb_scene *s, fmb_batch *b, const float *w2c_c, const flo
     Job &j = s ? s->job : b->job;
     if (!j.cams_set) return fail(FMB_ERR_STATE, "set the cameras first");
     CHECK_ARG(!w2c_c || j.has_flow, "a second flow target needs the first one (w2c_b, intr_b)");
+    if (j.prm.w2c_c != w2c_c || j.prm.intr_c != intr_c) j.drop_graphs();
     j.prm.w2c_c = w2c_c;
     j.prm.intr_c = intr_c;
     return FMB_OK;
@@ -885,6 +892,7 @@ int fmb_set_colors(fmb_scene *s, fmb_batch *b, const float *colors)
     CHECK_ARG((s != nullptr) != (b != nullptr), "exactly one of scene and batch must be given");
     CHECK_ARG(!colors || aligned(colors, 4), "colors must be 4-byte aligned");
     Job &j = s ? s->job : b->job;
+    if (j.prm.colors != colors) j.drop_graphs();
     j.prm.colors = colors;
     return FMB_OK;
 }
@@ -1217,6 +1225,7 @@ int fmb_autotune(fmb_scene *s, fmb_batch *b, float *depth, float *alpha, float *
     hipStream_t st = (hipStream_t)stream;
     if (!j.cams_set) return fail(FMB_ERR_STATE, "autotune before cameras were set");
     if (j.model == FMB_MODEL_COMPOSITE) return FMB_OK;  // one launch configuration
+    j.drop_graphs();  // the variants and grids may change
     const FwdOut O{depth, alpha, normal, flow, color, stash};
     const BwdIn I{g_depth, g_alpha, g_normal, g_flow, g_color, depth, color, stash};
     const Grads G{g_means, g_prec, g_weights, g_colors, g_betas};

@@ -403,13 +403,15 @@ __global__ __launch_bounds__(kCompBlock) __attribute__((amdgpu_waves_per_eu(bwdc
                                                           float *__restrict__ partial, float *__restrict__ beta_partial)
 {
     constexpr bool NORMALS = (F & kNrm) != 0, COLOR = (F & kCol) != 0;
-    // without a normal cotangent the pairs take the (A, Bv, L) form of the adjoint
-    // (pair_adjoint_plain), which needs neither the refined peak nor r
+    // without a normal cotangent the pairs take the offset form of the adjoint
+    // (pair_adjoint_offset), which needs neither the refined peak nor r
     constexpr bool PLAIN = !NORMALS;
     constexpr int RW = COLOR ? 4 : 3;                        // float4 per staged ray
     constexpr int REC = COLOR ? kPartialColor : kPartial;   // partial record per Gaussian
+    // a lane's sums per Gaussian: (H, Bv, L) of the offset form or the general record, then colour
+    constexpr int LREC = PLAIN ? kOffsetAcc + (COLOR ? 3 : 0) : REC;
     constexpr int RAYS4 = kCompBlock * RW;
-    constexpr int RED4 = (kCompBlock * KM * REC + 3) / 4;
+    constexpr int RED4 = (kCompBlock * KM * LREC + 3) / 4;
     __shared__ float4 smem[RAYS4 > RED4 ? RAYS4 : RED4];     // staged rays, then the reduction
     __shared__ float2 tdl[kCompBlock * KM];
     const int tid = threadIdx.x;
@@ -430,7 +432,7 @@ __global__ __launch_bounds__(kCompBlock) __attribute__((amdgpu_waves_per_eu(bwdc
     bool gv[KM];
     comp_entries<KM, COLOR>(P, sr, c, o, g, cc, gv);
     PairAcc acc[KM];
-    PlainAcc pacc[KM];
+    OffsetAcc pacc[KM];
     float aC[KM][3];
 #pragma unroll
     for (int k = 0; k < KM; ++k) aC[k][0] = aC[k][1] = aC[k][2] = 0.0f;
@@ -496,11 +498,6 @@ __global__ __launch_bounds__(kCompBlock) __attribute__((amdgpu_waves_per_eu(bwdc
             wave_sync();
             float behind[KM];
             ordered_sums<KM, true>(tdl + c.sbase, cnt_b, c, q, behind);
-            float4 vva = make_float4(0.0f, 0.0f, 0.0f, 0.0f), vvb = vva;  // v v^T, shared by the lane's pairs
-            if (PLAIN) {
-                vva = make_float4(v0 * v0, v0 * v1, v0 * v2, v1 * v1);
-                vvb = make_float4(v1 * v2, v2 * v2, 0.0f, 0.0f);
-            }
 #pragma unroll
             for (int k = 0; k < KM; ++k) {
                 if (k < c.ke) {
@@ -512,7 +509,7 @@ __global__ __launch_bounds__(kCompBlock) __attribute__((amdgpu_waves_per_eu(bwdc
                         aC[k][2] = fmaf(wt[k], x3.z, aC[k][2]);
                     }
                     if (PLAIN)
-                        pair_adjoint_plain(q[k].t, q[k].raa, v0, v1, v2, vva, vvb, tb, db, pacc[k]);
+                        pair_adjoint_offset(q[k], v0, v1, v2, tb, db, pacc[k]);
                     else
                         pair_adjoint<NORMALS>(g[k], q[k], v0, v1, v2, wt[k], pn[k], nb0, nb1, nb2, tb, db, acc[k]);
                 }
@@ -526,35 +523,33 @@ __global__ __launch_bounds__(kCompBlock) __attribute__((amdgpu_waves_per_eu(bwdc
     float *red = reinterpret_cast<float *>(smem);
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
-        float *my = red + (tid * KM + k) * REC;
+        float *my = red + (tid * KM + k) * LREC;
         if (PLAIN) {
-            const PlainAcc &a = pacc[k];
-            my[0] = a.a00; my[1] = a.a01; my[2] = a.a02; my[3] = a.a11; my[4] = a.a12; my[5] = a.a22;
-            my[6] = a.b0; my[7] = a.b1; my[8] = a.b2; my[9] = a.l;
+            offset_acc_store(pacc[k], my);
         } else {
             const PairAcc &a = acc[k];
             my[0] = a.u0; my[1] = a.u1; my[2] = a.u2; my[3] = a.u3; my[4] = a.u4; my[5] = a.u5;
             my[6] = a.p0; my[7] = a.p1; my[8] = a.p2; my[9] = a.l;
         }
         if (COLOR) {
-            my[10] = aC[k][0]; my[11] = aC[k][1]; my[12] = aC[k][2];
+            my[LREC - 3] = aC[k][0]; my[LREC - 2] = aC[k][1]; my[LREC - 1] = aC[k][2];
         }
     }
     __syncthreads();
     if (tid < n) {
         const int k = tid / c.seg, l = tid % c.seg;
-        float sum[REC];
+        float sum[LREC];
 #pragma unroll
-        for (int v = 0; v < REC; ++v) sum[v] = 0.0f;
+        for (int v = 0; v < LREC; ++v) sum[v] = 0.0f;
         for (int w = 0; w < kCompBlock / 64; ++w)
             for (int s = 0; s < c.rpw; ++s) {
-                const float *src = red + ((w * 64 + s * c.seg + l) * KM + k) * REC;
+                const float *src = red + ((w * 64 + s * c.seg + l) * KM + k) * LREC;
 #pragma unroll
-                for (int v = 0; v < REC; ++v) sum[v] += src[v];
+                for (int v = 0; v < LREC; ++v) sum[v] += src[v];
             }
         const int gg = sr.gauss_off + tid;
         if (PLAIN)
-            write_partial_plain(partial + item.poff + REC * tid, sum, REC, P.prec + 6 * gg, P.means + 3 * gg, o);
+            write_partial_offset(partial + item.poff + REC * tid, sum, REC, P.prec + 6 * gg, P.means + 3 * gg, o);
         else
             write_partial(partial + item.poff + REC * tid, sum, REC, P.means + 3 * gg, o);
     }

@@ -144,6 +144,7 @@ __device__ __forceinline__ void project(const float *__restrict__ e, const float
 struct Geo {
     float a0, a1, a2, raa;  // a = U v, 1/(a.a)
     float t;                // peak depth
+    float w0, w1, w2;       // t v - mu' (the high part of mu'): the peak point relative to the mean
     float r0, r1, r2;       // r = U (t v - mu'), at the refined peak after pair_refine
     float d2, z2;           // log2 density, log2 blend weight
 };
@@ -163,12 +164,12 @@ __device__ __forceinline__ void pair_geo_coarse(const Ent &g, float v0, float v1
     const float vc = fmaf(v0, g.c0, fmaf(v1, g.c1, v2 * g.c2));
     q.raa = rcp_(aa);
     q.t = vc * q.raa;
-    const float w0 = fmaf(q.t, v0, -g.mh0);
-    const float w1 = fmaf(q.t, v1, -g.mh1);
-    const float w2 = fmaf(q.t, v2, -g.mh2);
-    q.r0 = fmaf(g.u00, w0, fmaf(g.u01, w1, fmaf(g.u02, w2, -g.ul0)));
-    q.r1 = fmaf(g.u11, w1, fmaf(g.u12, w2, -g.ul1));
-    q.r2 = fmaf(g.u22, w2, -g.ul2);
+    q.w0 = fmaf(q.t, v0, -g.mh0);
+    q.w1 = fmaf(q.t, v1, -g.mh1);
+    q.w2 = fmaf(q.t, v2, -g.mh2);
+    q.r0 = fmaf(g.u00, q.w0, fmaf(g.u01, q.w1, fmaf(g.u02, q.w2, -g.ul0)));
+    q.r1 = fmaf(g.u11, q.w1, fmaf(g.u12, q.w2, -g.ul1));
+    q.r2 = fmaf(g.u22, q.w2, -g.ul2);
     const float m = fmaf(q.r0, q.r0, fmaf(q.r1, q.r1, q.r2 * q.r2));
     q.d2 = fmaf(hm, m, g.l2l);
     q.z2 = fmaf(b1, q.d2, nc2 * q.t);
@@ -475,15 +476,20 @@ __device__ __forceinline__ void pair_adjoint(const Ent &g, const Geo &q, float v
     a.p2 += p2;
 }
 
-// Adjoint of one pair without a normal cotangent, in a form that needs neither r nor the
-// refined peak.  With a = U v, b = U mu' and r = t a - b at the peak, the per-pair terms of the
-// general adjoint are rho = -beta a + db b and k = alpha a + beta b, where
+// Adjoint of one pair without a normal cotangent in monomials of the ray direction, for Gaussians
+// seen from within kPlainMaxB standard deviations.  With a = U v, b = U mu' and r = t a - b at the
+// peak, the per-pair terms of the general adjoint are rho = -beta a + db b and k = alpha a + beta b,
+// where
 //   tau = tb / (a.a),  beta = tau + db t,  alpha = -t (tau + beta),
 // so over the rays of one view sum k v^T = U A + b Bv^T and sum rho = -U Bv + L b with
 //   A = sum alpha v v^T (symmetric),  Bv = sum beta v,  L = sum db.
-// A lane therefore accumulates A (6), Bv (3) and L; write_partial_plain forms the record.
-// The envelope condition a.r = 0 is not needed to the last bit: it enters only through terms of
-// relative size |t - t_peak| |a| / |r|, so neither t nor r needs the Newton step here.
+// A lane therefore accumulates A (6), Bv (3) and L; write_partial_plain forms the record.  The
+// record's terms are of size |b|^2 / |r|^2 times its value (the density part expands w w^T,
+// w = t v - mu', into monomials of v), so the FP32 sums' rounding reaches dU amplified by about
+// |b|^2: the kernels take this form only while |b| <= kPlainMaxB for every Gaussian of the item
+// and the offset form (pair_adjoint_offset) beyond.
+constexpr float kPlainMaxB = 100.0f;
+
 struct PlainAcc {
     float a00 = 0, a01 = 0, a02 = 0, a11 = 0, a12 = 0, a22 = 0;
     float b0 = 0, b1 = 0, b2 = 0;
@@ -510,10 +516,16 @@ __device__ __forceinline__ void pair_adjoint_plain(float t, float raa, float v0,
     a.l += db;
 }
 
-// Partial record of one Gaussian from the sums (A, Bv, L) of pair_adjoint_plain, in double:
-// dU = U A + b Bv^T - (sum rho) mu'^T (upper triangle), sum rho = L b - U Bv, dL/dlog(lambda)
-// = L, then the remaining values (colour) as given.
-__device__ __forceinline__ void write_partial_plain(float *__restrict__ dst, const float *acc, int rec,
+__device__ __forceinline__ void plain_acc_store(const PlainAcc &a, float *my)
+{
+    my[0] = a.a00; my[1] = a.a01; my[2] = a.a02; my[3] = a.a11; my[4] = a.a12; my[5] = a.a22;
+    my[6] = a.b0; my[7] = a.b1; my[8] = a.b2; my[9] = a.l;
+}
+
+// Partial record of one Gaussian from the sums (A, Bv, L) of pair_adjoint_plain (acc[0..9]), in
+// double: dU = U A + b Bv^T - (sum rho) mu'^T (upper triangle), sum rho = L b - U Bv,
+// dL/dlog(lambda) = L, then the remaining values (colour) from acc[coff...].
+__device__ __forceinline__ void write_partial_plain(float *__restrict__ dst, const float *acc, int rec, int coff,
                                                     const float *__restrict__ prec, const float *__restrict__ mu,
                                                     const double o[3])
 {
@@ -542,7 +554,96 @@ __device__ __forceinline__ void write_partial_plain(float *__restrict__ dst, con
     dst[7] = (float)r1;
     dst[8] = (float)r2;
     dst[9] = (float)L;
-    for (int c = 10; c < rec; ++c) dst[c] = acc[c];
+    for (int c = 10; c < rec; ++c) dst[c] = acc[coff + c - 10];
+}
+
+// Squared distance |U mu'|^2 of the camera centre from the mean in standard deviations, from an
+// entry (U (hi + lo) = U hi + U lo), for the choice between the two forms above.
+__device__ __forceinline__ float entry_b2(const Ent &g)
+{
+    const float b0 = fmaf(g.u00, g.mh0, fmaf(g.u01, g.mh1, fmaf(g.u02, g.mh2, g.ul0)));
+    const float b1 = fmaf(g.u11, g.mh1, fmaf(g.u12, g.mh2, g.ul1));
+    const float b2 = fmaf(g.u22, g.mh2, g.ul2);
+    return fmaf(b0, b0, fmaf(b1, b1, b2 * b2));
+}
+
+// Adjoint of one pair without a normal cotangent, summed in terms of the peak's offset from the
+// mean.  With w = t v - mu' (the peak point relative to the mean, r = U w), tau = tb / (a.a) and
+// rho = -tau a - db r (the general adjoint with no normal term), the pair adds
+//   rho w^T - tau r v^T = U X,   X = -tau (w v^T + v w^T) - db w w^T = -(h w^T + w h^T),
+//   h = tau v + (db / 2) w,
+// to dL/dU, and -U (tau v + db w) = U (db mu' - beta v), beta = tau + db t, to sum rho.  A lane
+// therefore sums H = sum h w^T (9), Bv = sum beta v (3) and L = sum db, and write_partial_offset
+// forms dU = -U (H + H^T) and sum rho = L U mu' - U Bv once per (item, Gaussian) in double.
+// Every summand of H is of the size of the pair's own contribution, where the monomial form above
+// cancels by (|mu'| / |w|)^2 ~ |b|^2 / |r|^2 (for Gaussians a few thousandths wide seen from a few
+// units away, errors of 1e-3 of the result); sum rho cancels only linearly (|mu'| / |w|).  The envelope
+// condition a.r = 0 enters only through terms of relative size |t - t_peak| |a| / |r|, so neither
+// t nor r needs the Newton step, and w is the high part t v - hi (the low part of mu' is below
+// 2^-24 |mu'|).
+struct OffsetAcc {
+    float h00 = 0, h01 = 0, h02 = 0, h10 = 0, h11 = 0, h12 = 0, h20 = 0, h21 = 0, h22 = 0;
+    float b0 = 0, b1 = 0, b2 = 0;
+    float l = 0;
+};
+constexpr int kOffsetAcc = 13;  // floats of an OffsetAcc
+
+__device__ __forceinline__ void pair_adjoint_offset(const Geo &q, float v0, float v1, float v2, float tb, float db,
+                                                    OffsetAcc &a)
+{
+    const float tau = tb * q.raa;
+    const float dh = 0.5f * db;
+    const float h0 = fmaf(tau, v0, dh * q.w0);
+    const float h1 = fmaf(tau, v1, dh * q.w1);
+    const float h2 = fmaf(tau, v2, dh * q.w2);
+    a.h00 = fmaf(h0, q.w0, a.h00);
+    a.h01 = fmaf(h0, q.w1, a.h01);
+    a.h02 = fmaf(h0, q.w2, a.h02);
+    a.h10 = fmaf(h1, q.w0, a.h10);
+    a.h11 = fmaf(h1, q.w1, a.h11);
+    a.h12 = fmaf(h1, q.w2, a.h12);
+    a.h20 = fmaf(h2, q.w0, a.h20);
+    a.h21 = fmaf(h2, q.w1, a.h21);
+    a.h22 = fmaf(h2, q.w2, a.h22);
+    const float be = fmaf(db, q.t, tau);
+    a.b0 = fmaf(be, v0, a.b0);
+    a.b1 = fmaf(be, v1, a.b1);
+    a.b2 = fmaf(be, v2, a.b2);
+    a.l += db;
+}
+
+__device__ __forceinline__ void offset_acc_store(const OffsetAcc &a, float *my)
+{
+    my[0] = a.h00; my[1] = a.h01; my[2] = a.h02; my[3] = a.h10; my[4] = a.h11; my[5] = a.h12;
+    my[6] = a.h20; my[7] = a.h21; my[8] = a.h22; my[9] = a.b0; my[10] = a.b1; my[11] = a.b2; my[12] = a.l;
+}
+
+// Partial record of one Gaussian from the sums (H, Bv, L) of pair_adjoint_offset (acc[0..12]), in
+// double: dU = U X with X = -(H + H^T) (upper triangle), sum rho = L b - U Bv with b = U mu',
+// dL/dlog(lambda) = L, then the remaining values (colour, acc[13..]) as given.
+__device__ __forceinline__ void write_partial_offset(float *__restrict__ dst, const float *acc, int rec,
+                                                     const float *__restrict__ prec, const float *__restrict__ mu,
+                                                     const double o[3])
+{
+    const double u00 = prec[0], u01 = prec[1], u02 = prec[2], u11 = prec[3], u12 = prec[4], u22 = prec[5];
+    const double m0 = (double)mu[0] - o[0], m1 = (double)mu[1] - o[1], m2 = (double)mu[2] - o[2];
+    const double X00 = -2.0 * (double)acc[0], X11 = -2.0 * (double)acc[4], X22 = -2.0 * (double)acc[8];
+    const double X01 = -((double)acc[1] + (double)acc[3]);
+    const double X02 = -((double)acc[2] + (double)acc[6]);
+    const double X12 = -((double)acc[5] + (double)acc[7]);
+    const double B0 = acc[9], B1 = acc[10], B2 = acc[11], L = acc[12];
+    const double b0 = u00 * m0 + u01 * m1 + u02 * m2, b1 = u11 * m1 + u12 * m2, b2 = u22 * m2;
+    dst[0] = (float)(u00 * X00 + u01 * X01 + u02 * X02);
+    dst[1] = (float)(u00 * X01 + u01 * X11 + u02 * X12);
+    dst[2] = (float)(u00 * X02 + u01 * X12 + u02 * X22);
+    dst[3] = (float)(u11 * X11 + u12 * X12);
+    dst[4] = (float)(u11 * X12 + u12 * X22);
+    dst[5] = (float)(u22 * X22);
+    dst[6] = (float)(L * b0 - (u00 * B0 + u01 * B1 + u02 * B2));
+    dst[7] = (float)(L * b1 - (u11 * B1 + u12 * B2));
+    dst[8] = (float)(L * b2 - u22 * B2);
+    dst[9] = (float)L;
+    for (int c = 10; c < rec; ++c) dst[c] = acc[c + kOffsetAcc - 10];
 }
 
 // Write one Gaussian's partial record: dU with the -(sum rho) mu'^T term applied in double

@@ -10,8 +10,8 @@
 //   * backward: one lane per (Gaussian, ray slot); rays of the item's span are staged
 //     through LDS with their per-ray adjoint prologue; every lane recomputes its pairs
 //     and accumulates its Gaussian's gradient in registers -- no per-pair cross-lane
-//     reduction and no P x N storage (without a normal cotangent in the short form of
-//     pair_adjoint_plain).  Partial gradients per item are reduced deterministically by
+//     reduction and no P x N storage (without a normal cotangent in the offset form of
+//     pair_adjoint_offset).  Partial gradients per item are reduced deterministically by
 //     the finalize kernel.
 //   * persistent variants pull items from a device counter (reset by a fill kernel)
 //     in the order given by the host (largest item first).
@@ -172,13 +172,15 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(bwd_min_w
                                                    float *__restrict__ beta_partial)
 {
     constexpr bool NORMALS = (F & kNrm) != 0, PERSIST = (F & kPer) != 0, COLOR = (F & kCol) != 0;
-    // Without a normal cotangent the pairs take pair_adjoint_plain: the staged ray is
-    // (v, M2) (invS, tf_bar, kappa, D_bar) (v v^T: 4) (v v^T: 2, t_f, dc) [(Cb, 0)]; with one it
-    // is the prologue as written by ray_prologue (four float4).
+    // Without a normal cotangent the pairs take pair_adjoint_plain or pair_adjoint_offset: the staged
+    // ray is (v, M2) (invS, tf_bar, kappa, D_bar) (v v^T: 4) (v v^T: 2, t_f, dc) [(Cb, 0)]; with one
+    // it is the prologue as written by ray_prologue (four float4).
     constexpr bool PLAIN = !NORMALS;
     constexpr int RW = PLAIN ? (COLOR ? 5 : 4) : 4;  // float4 per staged ray
     constexpr int REC = COLOR ? kPartialColor : kPartial;  // partial record per Gaussian
-    constexpr int RS = REC + 2;                   // reduction record per lane (+ two betas)
+    // a lane's sums: (H, Bv, L) of the offset form or the general record, then the colour sums
+    constexpr int LREC = PLAIN ? kOffsetAcc + (COLOR ? 3 : 0) : REC;
+    constexpr int RS = LREC + 2;                  // reduction record per lane (+ two betas)
     // the staged rays and, after an item's pair loop, the reduction records share the LDS
     constexpr int SM4 = RT * RW > BLOCK * RS / 4 ? RT * RW : (BLOCK * RS + 3) / 4;
     __shared__ float4 smem[SM4];
@@ -220,119 +222,138 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(bwd_min_w
             g = ent_from(q[0], q[1], q[2], q[3]);
             if (COLOR) cc = colour_entry(P.colors + 3 * gg);
         }
-        PairAcc acc;
-        PlainAcc pacc;
         float aB1 = 0, aB2 = 0;
         float aC0 = 0, aC1 = 0, aC2 = 0;
+        // Without a normal cotangent: the monomial form while every Gaussian of the item lies within
+        // kPlainMaxB standard deviations of the camera, else the offset form (a block-uniform choice).
+        const bool offset_form = PLAIN && __syncthreads_or(active && entry_b2(g) > kPlainMaxB * kPlainMaxB);
 
-        for (int r0 = item.ray0; r0 < end; r0 += RT) {
-            const int cnt = min(RT, end - r0);
-            __syncthreads();
-            for (int q = tid; q < RT; q += BLOCK) {
-                float4 pr[4];
-                ray_prologue<F>(P, I, item.view, vr, e, kk, o0, o1, o2, r0 + q, q < cnt, bl.b1, bl.nc2, pr);
-                if (PLAIN) {
-                    const float v0 = pr[0].x, v1 = pr[0].y, v2 = pr[0].z;
-                    rays[RW * q] = pr[0];
-                    rays[RW * q + 1] = make_float4(pr[1].x, pr[1].y, pr[2].y, pr[2].z);
-                    rays[RW * q + 2] = make_float4(v0 * v0, v0 * v1, v0 * v2, v1 * v1);
-                    rays[RW * q + 3] = make_float4(v1 * v2, v2 * v2, pr[2].w, pr[3].w);
-                    if (COLOR) rays[RW * q + 4] = pr[3];
-                } else {
+        // The item's rays RT at a time: staged with their prologue, then `pair` runs over this lane's
+        // rays slot, slot + slots, ... (walked by address: one induction variable).
+        auto passes = [&](auto &&pair) {
+            for (int r0 = item.ray0; r0 < end; r0 += RT) {
+                const int cnt = min(RT, end - r0);
+                __syncthreads();
+                for (int q = tid; q < RT; q += BLOCK) {
+                    float4 pr[4];
+                    ray_prologue<F>(P, I, item.view, vr, e, kk, o0, o1, o2, r0 + q, q < cnt, bl.b1, bl.nc2, pr);
+                    if (PLAIN) {
+                        const float v0 = pr[0].x, v1 = pr[0].y, v2 = pr[0].z;
+                        rays[RW * q] = pr[0];
+                        rays[RW * q + 1] = make_float4(pr[1].x, pr[1].y, pr[2].y, pr[2].z);
+                        rays[RW * q + 2] = make_float4(v0 * v0, v0 * v1, v0 * v2, v1 * v1);
+                        rays[RW * q + 3] = make_float4(v1 * v2, v2 * v2, pr[2].w, pr[3].w);
+                        if (COLOR) rays[RW * q + 4] = pr[3];
+                    } else {
 #pragma unroll
-                    for (int k = 0; k < RW; ++k) rays[RW * q + k] = pr[k];
+                        for (int k = 0; k < RW; ++k) rays[RW * q + k] = pr[k];
+                    }
+                }
+                __syncthreads();
+                if (active) {
+                    const float4 *const rend = rays + RW * cnt;
+                    for (const float4 *rp = rays + RW * slot; rp < rend; rp += RW * item.slots) pair(rp);
                 }
             }
-            __syncthreads();
-            if (active && PLAIN) {
-                // the lane's rays slot, slot + slots, ... < cnt, walked by address (one
-                // induction variable instead of an index and an address)
-                const float4 *const rend = rays + RW * cnt;
-                for (const float4 *rp = rays + RW * slot; rp < rend; rp += RW * item.slots) {
-                    const float4 x0 = rp[0], x1 = rp[1];
-                    const float4 vva = rp[2], vvb = rp[3];
-                    float4 x4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                    if (COLOR) x4 = rp[4];
-                    const float v0 = x0.x, v1 = x0.y, v2 = x0.z;
-                    Geo q;
-                    pair_geo_coarse(g, v0, v1, v2, bl.hm, bl.b1, bl.nc2, q);
-                    const float delta = exp2_(q.d2);
-                    // normalised blend weight 2^(z2 - M) / S, with z2 - M = b1 d2 + (nc2 t - M)
-                    const float wt = exp2_(fmaf(bl.b1, q.d2, fmaf(bl.nc2, q.t, -x0.w))) * x1.x;
-                    const float tfb = x1.y;
-                    float lin = tfb * q.t;
-                    if (COLOR) {
-                        lin = fmaf(x4.x, cc.x, fmaf(x4.y, cc.y, fmaf(x4.z, cc.z, lin)));
-                        aC0 = fmaf(wt, x4.x, aC0);
-                        aC1 = fmaf(wt, x4.y, aC1);
-                        aC2 = fmaf(wt, x4.z, aC2);
-                    }
-                    const float zb = wt * (lin - x1.z);
-                    const float tb = fmaf(-bl.cb, zb, wt * tfb);
-                    const float db = fmaf(bl.b1, zb, x1.w * delta);
-                    aB1 = fmaf(zb, q.d2 - vvb.w, aB1);
-                    aB2 = fmaf(zb, q.t - vvb.z, aB2);
-                    pair_adjoint_plain(q.t, q.raa, v0, v1, v2, vva, vvb, tb, db, pacc);
-                }
-            } else if (active) {
-                for (int j = slot; j < cnt; j += item.slots) {
-                    const float4 x0 = rays[RW * j], x1 = rays[RW * j + 1], x2 = rays[RW * j + 2];
-                    const float4 x3 = rays[RW * j + 3];
-                    const float v0 = x0.x, v1 = x0.y, v2 = x0.z;
-                    Geo q;
-                    pair_geo(g, v0, v1, v2, bl.hm, bl.b1, bl.nc2, q);
-                    const float delta = exp2_(q.d2);
-                    const float wt = exp2_(q.z2 - x0.w) * x1.x;   // normalised blend weight
-                    const float tfb = x1.y;
-                    PairNormal pn{0, 0, 0, 0, 0};
-                    if (NORMALS) pn = pair_normal(g, q, x1.z, x1.w, x2.x);
-                    // softmax adjoint: z_bar = wt (tf_bar t + Nb.n + Cb.c - kappa)
-                    float lin = fmaf(tfb, q.t, pn.nN);
-                    if (COLOR) {
-                        lin = fmaf(x3.x, cc.x, fmaf(x3.y, cc.y, fmaf(x3.z, cc.z, lin)));
-                        aC0 = fmaf(wt, x3.x, aC0);
-                        aC1 = fmaf(wt, x3.y, aC1);
-                        aC2 = fmaf(wt, x3.z, aC2);
-                    }
-                    const float zb = wt * (lin - x2.y);
-                    // z = beta1 d - (beta2/eta) t
-                    const float tb = fmaf(-bl.cb, zb, wt * tfb);
-                    const float db = fmaf(bl.b1, zb, x2.z * delta);
-                    aB1 = fmaf(zb, q.d2 - x3.w, aB1);
-                    aB2 = fmaf(zb, q.t - x2.w, aB2);
-                    pair_adjoint<NORMALS>(g, q, v0, v1, v2, wt, pn, x1.z, x1.w, x2.x, tb, db, acc);
-                }
+            __syncthreads();  // every lane is done with the staged rays (the LDS is reused below)
+        };
+        // One pair without a normal cotangent up to the adjoint's inputs (t_bar, d_bar); `adjoint`
+        // accumulates the chosen form.
+        auto plain_pair = [&](const float4 *rp, auto &&adjoint) {
+            const float4 x0 = rp[0], x1 = rp[1], x3 = rp[3];
+            float4 x4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (COLOR) x4 = rp[4];
+            const float v0 = x0.x, v1 = x0.y, v2 = x0.z;
+            Geo q;
+            pair_geo_coarse(g, v0, v1, v2, bl.hm, bl.b1, bl.nc2, q);
+            const float delta = exp2_(q.d2);
+            // normalised blend weight 2^(z2 - M) / S, with z2 - M = b1 d2 + (nc2 t - M)
+            const float wt = exp2_(fmaf(bl.b1, q.d2, fmaf(bl.nc2, q.t, -x0.w))) * x1.x;
+            const float tfb = x1.y;
+            float lin = tfb * q.t;
+            if (COLOR) {
+                lin = fmaf(x4.x, cc.x, fmaf(x4.y, cc.y, fmaf(x4.z, cc.z, lin)));
+                aC0 = fmaf(wt, x4.x, aC0);
+                aC1 = fmaf(wt, x4.y, aC1);
+                aC2 = fmaf(wt, x4.z, aC2);
             }
+            const float zb = wt * (lin - x1.z);
+            const float tb = fmaf(-bl.cb, zb, wt * tfb);
+            const float db = fmaf(bl.b1, zb, x1.w * delta);
+            aB1 = fmaf(zb, q.d2 - x3.w, aB1);
+            aB2 = fmaf(zb, q.t - x3.z, aB2);
+            adjoint(q, rp, v0, v1, v2, tb, db);
+        };
+        float *my = red + RS * tid;
+        if (!PLAIN) {
+            PairAcc acc;
+            passes([&](const float4 *rp) {
+                const float4 x0 = rp[0], x1 = rp[1], x2 = rp[2], x3 = rp[3];
+                const float v0 = x0.x, v1 = x0.y, v2 = x0.z;
+                Geo q;
+                pair_geo(g, v0, v1, v2, bl.hm, bl.b1, bl.nc2, q);
+                const float delta = exp2_(q.d2);
+                const float wt = exp2_(q.z2 - x0.w) * x1.x;   // normalised blend weight
+                const float tfb = x1.y;
+                PairNormal pn{0, 0, 0, 0, 0};
+                if (NORMALS) pn = pair_normal(g, q, x1.z, x1.w, x2.x);
+                // softmax adjoint: z_bar = wt (tf_bar t + Nb.n + Cb.c - kappa)
+                float lin = fmaf(tfb, q.t, pn.nN);
+                if (COLOR) {
+                    lin = fmaf(x3.x, cc.x, fmaf(x3.y, cc.y, fmaf(x3.z, cc.z, lin)));
+                    aC0 = fmaf(wt, x3.x, aC0);
+                    aC1 = fmaf(wt, x3.y, aC1);
+                    aC2 = fmaf(wt, x3.z, aC2);
+                }
+                const float zb = wt * (lin - x2.y);
+                // z = beta1 d - (beta2/eta) t
+                const float tb = fmaf(-bl.cb, zb, wt * tfb);
+                const float db = fmaf(bl.b1, zb, x2.z * delta);
+                aB1 = fmaf(zb, q.d2 - x3.w, aB1);
+                aB2 = fmaf(zb, q.t - x2.w, aB2);
+                pair_adjoint<NORMALS>(g, q, v0, v1, v2, wt, pn, x1.z, x1.w, x2.x, tb, db, acc);
+            });
+            my[0] = acc.u0; my[1] = acc.u1; my[2] = acc.u2; my[3] = acc.u3; my[4] = acc.u4; my[5] = acc.u5;
+            my[6] = acc.p0; my[7] = acc.p1; my[8] = acc.p2; my[9] = acc.l;
+        } else if (offset_form) {
+            OffsetAcc acc;
+            passes([&](const float4 *rp) {
+                plain_pair(rp, [&](const Geo &q, const float4 *, float v0, float v1, float v2, float tb, float db) {
+                    pair_adjoint_offset(q, v0, v1, v2, tb, db, acc);
+                });
+            });
+            offset_acc_store(acc, my);
+        } else {
+            PlainAcc acc;
+            passes([&](const float4 *rp) {
+                plain_pair(rp, [&](const Geo &q, const float4 *r, float v0, float v1, float v2, float tb, float db) {
+                    pair_adjoint_plain(q.t, q.raa, v0, v1, v2, r[2], r[3], tb, db, acc);
+                });
+            });
+            plain_acc_store(acc, my);
+            for (int c = 10; c < kOffsetAcc; ++c) my[c] = 0.0f;
         }
 
         // deterministic block reduction: Gaussian partials over the slots, betas over all lanes
-        __syncthreads();
-        {
-            float *my = red + RS * tid;
-            if (PLAIN) {
-                my[0] = pacc.a00; my[1] = pacc.a01; my[2] = pacc.a02; my[3] = pacc.a11; my[4] = pacc.a12;
-                my[5] = pacc.a22; my[6] = pacc.b0; my[7] = pacc.b1; my[8] = pacc.b2; my[9] = pacc.l;
-            } else {
-                my[0] = acc.u0; my[1] = acc.u1; my[2] = acc.u2; my[3] = acc.u3; my[4] = acc.u4; my[5] = acc.u5;
-                my[6] = acc.p0; my[7] = acc.p1; my[8] = acc.p2; my[9] = acc.l;
-            }
-            if (COLOR) {
-                my[10] = aC0; my[11] = aC1; my[12] = aC2;
-            }
-            my[REC] = aB1; my[REC + 1] = aB2;
+        if (COLOR) {
+            my[LREC - 3] = aC0; my[LREC - 2] = aC1; my[LREC - 1] = aC2;
         }
+        my[LREC] = aB1; my[LREC + 1] = aB2;
         __syncthreads();
         if (slot == 0 && gi < item.gc && item.g0 + gi < sr.n) {
-            float sum[REC];
+            float sum[LREC];
 #pragma unroll
-            for (int c = 0; c < REC; ++c) sum[c] = red[RS * gi + c];
+            for (int c = 0; c < LREC; ++c) sum[c] = red[RS * gi + c];
             for (int s = 1; s < item.slots; ++s) {
 #pragma unroll
-                for (int c = 0; c < REC; ++c) sum[c] += red[RS * (s * item.gc + gi) + c];
+                for (int c = 0; c < LREC; ++c) sum[c] += red[RS * (s * item.gc + gi) + c];
             }
             const int gg = sr.gauss_off + item.g0 + gi;
-            if (PLAIN)
-                write_partial_plain(partial + item.poff + REC * gi, sum, REC, P.prec + 6 * gg, P.means + 3 * gg, o);
+            if (PLAIN && offset_form)
+                write_partial_offset(partial + item.poff + REC * gi, sum, REC, P.prec + 6 * gg, P.means + 3 * gg, o);
+            else if (PLAIN)
+                write_partial_plain(partial + item.poff + REC * gi, sum, REC, LREC - 3, P.prec + 6 * gg,
+                                    P.means + 3 * gg, o);
             else
                 write_partial(partial + item.poff + REC * gi, sum, REC, P.means + 3 * gg, o);
         }
@@ -340,8 +361,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(bwd_min_w
             // lane l sums lanes l, l+64, ... in order, then a fixed butterfly over the wave
             float s1 = 0.0f, s2 = 0.0f;
             for (int k = tid; k < BLOCK; k += 64) {
-                s1 += red[RS * k + REC];
-                s2 += red[RS * k + REC + 1];
+                s1 += red[RS * k + LREC];
+                s2 += red[RS * k + LREC + 1];
             }
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) {
@@ -380,13 +401,15 @@ __global__ __launch_bounds__(BLOCK) void bwdr_kernel(Params P, BwdIn I, const Bw
                                                     float *__restrict__ beta_partial)
 {
     constexpr bool NORMALS = (F & kNrm) != 0, PERSIST = (F & kPer) != 0, COLOR = (F & kCol) != 0;
-    // without a normal cotangent the pairs take the (A, Bv, L) form (pair_adjoint_plain)
+    // without a normal cotangent the pairs take the offset form (pair_adjoint_offset)
     constexpr bool PLAIN = !NORMALS;
     constexpr int EW = COLOR ? 5 : 4;                       // float4 per LDS entry
     constexpr int REC = COLOR ? kPartialColor : kPartial;  // partial record per Gaussian
+    // sums per Gaussian and wave: (H, Bv, L) of the offset form or the general record, then colour
+    constexpr int LREC = PLAIN ? kOffsetAcc + (COLOR ? 3 : 0) : REC;
     constexpr int NW = BLOCK / 64;
     __shared__ float4 tile[TG * EW];
-    __shared__ float wsum[NW * TG * REC];   // per wave, per Gaussian of the tile
+    __shared__ float wsum[NW * TG * LREC];  // per wave, per Gaussian of the tile
     __shared__ float bsum[NW * 2];
     __shared__ int s_item;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -421,7 +444,7 @@ __global__ __launch_bounds__(BLOCK) void bwdr_kernel(Params P, BwdIn I, const Bw
                 make_entry(P.means + 3 * gi, P.prec + 6 * gi, P.weights[gi], o, &tile[EW * q]);
                 if (COLOR) tile[EW * q + 4] = colour_entry(P.colors + 3 * gi);
             }
-            for (int q = tid; q < NW * TG * REC; q += BLOCK) wsum[q] = 0.0f;
+            for (int q = tid; q < NW * TG * LREC; q += BLOCK) wsum[q] = 0.0f;
             __syncthreads();
             for (int rb = item.ray0; rb < end; rb += BLOCK * RPT) {
                 float4 x0[RPT], x1[RPT], x2[RPT], x3[RPT];
@@ -455,13 +478,7 @@ __global__ __launch_bounds__(BLOCK) void bwdr_kernel(Params P, BwdIn I, const Bw
                         need_d |= x2[j].z * delta[j] != 0.0f;
                     }
                     PairAcc a;
-                    PlainAcc pa;
-                    // v v^T of ray j, for the plain form
-                    auto vv = [&](int j, float4 &va, float4 &vb) {
-                        const float v0 = x0[j].x, v1 = x0[j].y, v2 = x0[j].z;
-                        va = make_float4(v0 * v0, v0 * v1, v0 * v2, v1 * v1);
-                        vb = make_float4(v1 * v2, v2 * v2, 0.0f, 0.0f);
-                    };
+                    OffsetAcc pa;
                     float aC0 = 0.0f, aC1 = 0.0f, aC2 = 0.0f;
                     if (__any(need_w)) {
 #pragma unroll
@@ -482,9 +499,7 @@ __global__ __launch_bounds__(BLOCK) void bwdr_kernel(Params P, BwdIn I, const Bw
                             aB1 = fmaf(zb, q[j].d2 - x3[j].w, aB1);
                             aB2 = fmaf(zb, q[j].t - x2[j].w, aB2);
                             if (PLAIN) {
-                                float4 va, vb;
-                                vv(j, va, vb);
-                                pair_adjoint_plain(q[j].t, q[j].raa, x0[j].x, x0[j].y, x0[j].z, va, vb, tb, db, pa);
+                                pair_adjoint_offset(q[j], x0[j].x, x0[j].y, x0[j].z, tb, db, pa);
                             } else {
                                 pair_adjoint<NORMALS>(g, q[j], x0[j].x, x0[j].y, x0[j].z, wt[j], pn, x1[j].z,
                                                       x1[j].w, x2[j].x, tb, db, a);
@@ -495,10 +510,7 @@ __global__ __launch_bounds__(BLOCK) void bwdr_kernel(Params P, BwdIn I, const Bw
 #pragma unroll
                         for (int j = 0; j < RPT; ++j) {
                             if (PLAIN) {
-                                float4 va, vb;
-                                vv(j, va, vb);
-                                pair_adjoint_plain(q[j].t, q[j].raa, x0[j].x, x0[j].y, x0[j].z, va, vb, 0.0f,
-                                                   x2[j].z * delta[j], pa);
+                                pair_adjoint_offset(q[j], x0[j].x, x0[j].y, x0[j].z, 0.0f, x2[j].z * delta[j], pa);
                             } else {
                                 const PairNormal pn{0, 0, 0, 0, 0};
                                 pair_adjoint<false>(g, q[j], x0[j].x, x0[j].y, x0[j].z, 0.0f, pn, 0.0f, 0.0f, 0.0f,
@@ -508,39 +520,38 @@ __global__ __launch_bounds__(BLOCK) void bwdr_kernel(Params P, BwdIn I, const Bw
                     } else {
                         continue;  // no term of this Gaussian on this wave's rays
                     }
-                    float v[REC];
+                    float v[LREC];
                     if (PLAIN) {
-                        v[0] = pa.a00; v[1] = pa.a01; v[2] = pa.a02; v[3] = pa.a11; v[4] = pa.a12; v[5] = pa.a22;
-                        v[6] = pa.b0; v[7] = pa.b1; v[8] = pa.b2; v[9] = pa.l;
+                        offset_acc_store(pa, v);
                     } else {
                         v[0] = a.u0; v[1] = a.u1; v[2] = a.u2; v[3] = a.u3; v[4] = a.u4; v[5] = a.u5;
                         v[6] = a.p0; v[7] = a.p1; v[8] = a.p2; v[9] = a.l;
                     }
                     if (COLOR) {
-                        v[10] = aC0; v[11] = aC1; v[12] = aC2;
+                        v[LREC - 3] = aC0; v[LREC - 2] = aC1; v[LREC - 1] = aC2;
                     }
 #pragma unroll
-                    for (int c = 0; c < REC; ++c) v[c] = wave_sum(v[c]);
+                    for (int c = 0; c < LREC; ++c) v[c] = wave_sum(v[c]);
                     if (lane == 0) {
-                        float *dst = wsum + (wave * TG + i) * REC;
+                        float *dst = wsum + (wave * TG + i) * LREC;
 #pragma unroll
-                        for (int c = 0; c < REC; ++c) dst[c] += v[c];
+                        for (int c = 0; c < LREC; ++c) dst[c] += v[c];
                     }
                 }
             }
             __syncthreads();
             // the tile's partial records: waves summed in order, -(sum rho) mu'^T applied in double
             for (int q = tid; q < cnt; q += BLOCK) {
-                float sum[REC];
+                float sum[LREC];
 #pragma unroll
-                for (int c = 0; c < REC; ++c) sum[c] = wsum[q * REC + c];
+                for (int c = 0; c < LREC; ++c) sum[c] = wsum[q * LREC + c];
                 for (int w = 1; w < NW; ++w) {
 #pragma unroll
-                    for (int c = 0; c < REC; ++c) sum[c] += wsum[(w * TG + q) * REC + c];
+                    for (int c = 0; c < LREC; ++c) sum[c] += wsum[(w * TG + q) * LREC + c];
                 }
                 const int gg = sr.gauss_off + gb + q;
                 if (PLAIN)
-                    write_partial_plain(partial + item.poff + REC * (gb + q), sum, REC, P.prec + 6 * gg, P.means + 3 * gg, o);
+                    write_partial_offset(partial + item.poff + REC * (gb + q), sum, REC, P.prec + 6 * gg, P.means + 3 * gg, o);
                 else
                     write_partial(partial + item.poff + REC * (gb + q), sum, REC, P.means + 3 * gg, o);
             }

@@ -36,20 +36,59 @@ def make_scene(fmb, torch, sc, cams, betas, eta, dev):
     return fmb.Scene(*params, eta, c), params
 
 
+# Rays a scene covers: oracle alpha at least this (per-pixel gates apply there).
+HIT_ALPHA = 1e-3
+# Floor of the per-pixel relative flow error (pixels) and of the per-entry relative gradient
+# error (fraction of the tensor's largest reference entry).
+FLOW_FLOOR_PX = 1e-2
+GRAD_FLOOR = 1e-3
+
+
+def per_element_max(a, b, floor):
+    """max over elements (rows, for vectors: Euclidean norm per row) of |a - b| / max(|b|, floor)."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    if b.size == 0:
+        return 0.0
+    if b.ndim > 1:
+        err, mag = np.linalg.norm(a - b, axis=-1), np.linalg.norm(b, axis=-1)
+    else:
+        err, mag = np.abs(a - b), np.abs(b)
+    return float(np.max(err / np.maximum(mag, floor)))
+
+
 def compare_forward(outs, ref, rays=None, flow=True, normals=True):
-    """Errors of GPU outputs (optionally at sampled rays) against oracle outputs."""
+    """Errors of GPU outputs (optionally at sampled rays) against oracle outputs: the contract's
+    norm-wise (depth, normal, flow) and max absolute (alpha) errors, and per-pixel maxima under
+    keys with '@': relative depth over all rays and over rays the scene covers (oracle alpha >=
+    HIT_ALPHA), the per-pixel normal error |n - n*| and relative flow error (floor FLOW_FLOOR_PX)."""
     sel = (lambda a: a) if rays is None else (lambda a: a[rays])
-    e = {"depth": normwise(sel(to_np(outs["depth"])), ref["depth"]),
-         "alpha": maxabs(sel(to_np(outs["alpha"])), ref["alpha"])}
+    d = sel(to_np(outs["depth"]))
+    hit = np.asarray(ref["alpha"]) >= HIT_ALPHA
+    e = {"depth": normwise(d, ref["depth"]),
+         "alpha": maxabs(sel(to_np(outs["alpha"])), ref["alpha"]),
+         "depth@px": per_element_max(d, ref["depth"], 1e-30),
+         "depth@px_hit": per_element_max(d[hit], ref["depth"][hit], 1e-30)}
     if normals and outs.get("normal") is not None:
-        e["normal"] = normwise(sel(to_np(outs["normal"])), ref["normal"])
+        nr = sel(to_np(outs["normal"]))
+        e["normal"] = normwise(nr, ref["normal"])
+        e["normal@px"] = per_element_max(nr, ref["normal"], 1.0)
+        e["normal@px_hit"] = per_element_max(nr[hit], ref["normal"][hit], 1.0)
     if flow and outs.get("flow") is not None and ref.get("flow") is not None:
-        e["flow"] = normwise(sel(to_np(outs["flow"])), ref["flow"])
+        fl = sel(to_np(outs["flow"]))
+        e["flow"] = normwise(fl, ref["flow"])
+        e["flow@px"] = per_element_max(fl, ref["flow"], FLOW_FLOOR_PX)
+        e["flow@px_hit"] = per_element_max(fl[hit], ref["flow"][hit], FLOW_FLOOR_PX)
     return e
 
 
-def assert_forward(e, what=""):
+def assert_forward(e, what="", per_pixel=True):
+    """The contract's norm-wise and max-abs gates; with `per_pixel`, also the relative depth of every
+    ray the scene covers within TOL_REL (not for scenes whose blended depth can cancel to near zero,
+    e.g. Gaussians on both sides of the camera)."""
     assert e["depth"] <= TOL_REL, f"{what} depth {e}"
+    if per_pixel:
+        assert e.get("depth@px_hit", 0.0) <= TOL_REL, f"{what} per-pixel depth {e}"
     assert e["alpha"] <= TOL_ALPHA, f"{what} alpha {e}"
     if "normal" in e:
         assert e["normal"] <= TOL_REL, f"{what} normal {e}"
@@ -58,12 +97,27 @@ def assert_forward(e, what=""):
 
 
 def compare_grads(g, gref):
-    return {k: normwise(to_np(g[k]), gref[k]) for k in ("means", "prec", "weights", "betas")}
+    """Norm-wise relative gradient errors per parameter tensor (the contract), and per-entry
+    maxima of |g - g*| / max(|g*|, GRAD_FLOOR max|g*|) under keys with '@'."""
+    e = {}
+    for k in ("means", "prec", "weights", "betas"):
+        a, b = to_np(g[k]), np.asarray(gref[k], np.float64)
+        e[k] = normwise(a, b)
+        scale = float(np.max(np.abs(b))) if b.size else 0.0
+        e[k + "@max"] = float(np.max(np.abs(a - b) / np.maximum(np.abs(b), GRAD_FLOOR * scale + 1e-300))) \
+            if b.size else 0.0
+    return e
 
 
 def assert_grads(e, what=""):
     for k, v in e.items():
-        assert v <= TOL_GRAD, f"{what} grad {k}: {e}"
+        if "@" not in k:
+            assert v <= TOL_GRAD, f"{what} grad {k}: {e}"
+
+
+def fmt(e):
+    """Compact error dictionary for the test log."""
+    return "{" + ", ".join(f"{k}: {v:.2e}" for k, v in e.items()) + "}"
 
 
 def custom_scene(n, views, seed, behind=False, flow=False, s_range=(0.05, 0.2)):

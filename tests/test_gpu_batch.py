@@ -7,7 +7,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from tests.gpu_util import assert_forward, assert_grads, compare_forward, compare_grads, make_scene, to_np
+from tests.gpu_util import assert_forward, assert_grads, compare_forward, compare_grads, fmt, make_scene, to_np
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -73,43 +73,39 @@ def test_batch_equals_plain_bitwise(fmb, batch16):
 
 
 def test_batch_vs_oracle(fmb, batch16):
-    """Scenes of the batch against the oracle: sampled rays forward, sampled-cotangent backward."""
+    """Every scene of the batch against the oracle: sampled rays forward, and one backward with
+    seeded cotangents on sampled rays of every scene (zero elsewhere), whose gradient over each
+    scene is compared with the oracle's over that scene's sample."""
     w, b, params = batch16
     outs = b.forward(b.alloc_outputs(normals=True))
     cot = W.random_cotangents(b.n_rays, 33, flow=False)
     g = np.random.Generator(np.random.PCG64(5))
-    for i in (0, 5, 8, 15):
-        sc, cams = w.scenes[i], w.cameras[i]
+    samples = []
+    for i, (sc, cams) in enumerate(zip(w.scenes, w.cameras)):
         r0, r1 = b.ray_off[i], b.ray_off[i + 1]
-        rays = np.sort(g.choice(r1 - r0, size=min(4000, r1 - r0), replace=False))
-        ref, _, _ = O.render_workload_view(sc, cams, w.betas, w.eta, rays=rays)
-        sub = {k: (None if v is None else v[r0:r1]) for k, v in outs.items()}
-        torch.cuda.synchronize()
-        e = compare_forward(sub, ref, rays)
-        _say(f"[batch-oracle] scene {i} N={sc.n} V={cams.v} {cams.hw[0]}: {e}")
-        assert_forward(e, f"scene {i}")
-    # backward: cotangents only on sampled rays of scene 5 (others zero)
-    i = 5
-    sc, cams = w.scenes[i], w.cameras[i]
-    r0, r1 = b.ray_off[i], b.ray_off[i + 1]
-    rays = np.sort(g.choice(r1 - r0, size=min(4000, r1 - r0), replace=False))
+        samples.append(np.sort(g.choice(r1 - r0, size=min(1500, r1 - r0), replace=False)))
     full = {k: np.zeros_like(v) for k, v in cot.items() if v is not None}
-    for k in full:
-        full[k][r0 + rays] = cot[k][r0 + rays]
+    for i, rays in enumerate(samples):
+        for k in full:
+            full[k][b.ray_off[i] + rays] = cot[k][b.ray_off[i] + rays]
     tc = {k: torch.as_tensor(v, device=DEV).contiguous() for k, v in full.items()}
     grads = b.backward(outs, tc, b.alloc_grads())
     torch.cuda.synchronize()
-    cs = {k: v[r0 + rays] for k, v in full.items()}
-    cs["flow"] = None
-    _, gref, _ = O.render_workload_view(sc, cams, w.betas, w.eta, rays=rays, cot=cs)
-    g0, g1 = b.gauss_off[i], b.gauss_off[i + 1]
-    gs = {"means": grads["means"][g0:g1], "prec": grads["prec"][g0:g1], "weights": grads["weights"][g0:g1],
-          "betas": grads["betas"][i]}
-    e = compare_grads(gs, gref)
-    _say(f"[batch-oracle] backward scene {i}: {e}")
-    assert_grads(e, "batch scene 5")
-    other = torch.cat([grads["means"][:g0].reshape(-1), grads["means"][g1:].reshape(-1)])
-    assert torch.count_nonzero(other).item() == 0
+    for i, (sc, cams) in enumerate(zip(w.scenes, w.cameras)):
+        r0, r1 = b.ray_off[i], b.ray_off[i + 1]
+        g0, g1 = b.gauss_off[i], b.gauss_off[i + 1]
+        rays = samples[i]
+        cs = {k: v[r0 + rays] for k, v in full.items()}
+        cs["flow"] = None
+        ref, gref, _ = O.render_workload_view(sc, cams, w.betas, w.eta, rays=rays, cot=cs)
+        sub = {k: (None if v is None else v[r0:r1]) for k, v in outs.items()}
+        e = compare_forward(sub, ref, rays)
+        gs = {"means": grads["means"][g0:g1], "prec": grads["prec"][g0:g1], "weights": grads["weights"][g0:g1],
+              "betas": grads["betas"][i]}
+        eg = compare_grads(gs, gref)
+        _say(f"[batch-oracle] scene {i} N={sc.n} V={cams.v} {cams.hw[0]}: {fmt(e)} {fmt(eg)}")
+        assert_forward(e, f"scene {i}")
+        assert_grads(eg, f"batch scene {i}")
 
 
 def test_graph_replay(fmb, batch16):
@@ -242,9 +238,11 @@ def test_ray_lane_batch_bitwise(fmb, batch16, variant):
 
 
 def test_bench_configuration(fmb, batch16):
-    """The benchmark's own configuration: the autotuned persistent kernels on batch16 with the
-    loss kernel's cotangents.  Forward outputs on sampled rays of four scenes and the gradient of
-    one scene (cotangents kept on sampled rays of that scene only) against the oracle."""
+    """The benchmark's own configuration: the autotuned persistent kernels on batch16, tuned with
+    the loss kernel's cotangents.  Forward outputs of every scene on sampled rays against the
+    oracle; then one backward whose cotangents are the oracle's gradient of the workload loss
+    (alpha-weighted L1 depth + BCE alpha against the oracle's render of the perturbed scene) on
+    sampled rays of every scene, zero elsewhere, against the oracle's gradient per scene."""
     w, b, (means, prec, weights, betas) = batch16
     outs = b.alloc_outputs(normals=True)
     grads = b.alloc_grads()
@@ -260,38 +258,104 @@ def test_bench_configuration(fmb, batch16):
     cfg = fmb.launch_config(batch=b)
     _say(f"[bench-config] {cfg}")
     b.forward(outs)
-    fmb.loss_grad(outs, d_t, a_t, cot=cot)
     torch.cuda.synchronize()
     sc_means = to_np(means).astype(np.float32)
     sc_prec = to_np(prec).astype(np.float32)
     sc_weights = to_np(weights).astype(np.float32)
-    for i in (0, 3, 8, 12):
-        cams = w.cameras[i]
+    full = {k: np.zeros(b.n_rays, np.float32) for k in ("depth", "alpha")}
+    per_scene = []
+    for i, cams in enumerate(w.cameras):
         g0, g1 = b.gauss_off[i], b.gauss_off[i + 1]
         r0, r1 = b.ray_off[i], b.ray_off[i + 1]
         sc = W.Scene(sc_means[g0:g1], sc_prec[g0:g1], sc_weights[g0:g1])
-        rays = np.sort(g.choice(r1 - r0, size=min(3000, r1 - r0), replace=False))
-        ref, _, _ = O.render_workload_view(sc, cams, to_np(betas[i]).astype(np.float32), w.eta, rays=rays)
+        bi = to_np(betas[i]).astype(np.float32)
+        rays = np.sort(g.choice(r1 - r0, size=min(1500, r1 - r0), replace=False))
+        ref, _, _ = O.render_workload_view(sc, cams, bi, w.eta, rays=rays)
         sub = {k: (None if v is None else v[r0:r1]) for k, v in outs.items()}
         e = compare_forward(sub, ref, rays)
-        _say(f"[bench-config] scene {i} forward {e}")
+        _say(f"[bench-config] scene {i} forward {fmt(e)}")
         assert_forward(e, f"bench configuration scene {i}")
-    i = 8
-    cams = w.cameras[i]
-    g0, g1 = b.gauss_off[i], b.gauss_off[i + 1]
-    r0, r1 = b.ray_off[i], b.ray_off[i + 1]
-    rays = np.sort(g.choice(r1 - r0, size=3000, replace=False))
-    keep = torch.zeros(b.n_rays, device=DEV)
-    keep[r0 + torch.as_tensor(rays, device=DEV)] = 1.0
-    masked = {"depth": cot["depth"] * keep, "alpha": cot["alpha"] * keep, "normal": None, "flow": None}
-    grads = b.backward(outs, masked, grads)
+        tgt, _, _ = O.render_workload_view(w.targets[i], cams, bi, w.eta, rays=rays)
+        _, lg = O.loss_grad(ref["depth"], ref["alpha"], tgt["depth"], tgt["alpha"])
+        cs = {"depth": lg["depth"].astype(np.float32), "alpha": lg["alpha"].astype(np.float32),
+              "normal": None, "flow": None}
+        full["depth"][r0 + rays] = cs["depth"]
+        full["alpha"][r0 + rays] = cs["alpha"]
+        per_scene.append((sc, cams, bi, rays, cs))
+    tc = {k: torch.as_tensor(v, device=DEV).contiguous() for k, v in full.items()}
+    tc["normal"] = tc["flow"] = None
+    grads = b.backward(outs, tc, grads)
     torch.cuda.synchronize()
-    sc = W.Scene(sc_means[g0:g1], sc_prec[g0:g1], sc_weights[g0:g1])
-    cs = {"depth": to_np(masked["depth"])[r0 + rays], "alpha": to_np(masked["alpha"])[r0 + rays],
-          "normal": None, "flow": None}
-    _, gref, _ = O.render_workload_view(sc, cams, to_np(betas[i]).astype(np.float32), w.eta, rays=rays, cot=cs)
-    gs = {"means": grads["means"][g0:g1], "prec": grads["prec"][g0:g1], "weights": grads["weights"][g0:g1],
-          "betas": grads["betas"][i]}
-    e = compare_grads(gs, gref)
-    _say(f"[bench-config] scene {i} backward {e}")
-    assert_grads(e, "bench configuration backward")
+    for i, (sc, cams, bi, rays, cs) in enumerate(per_scene):
+        g0, g1 = b.gauss_off[i], b.gauss_off[i + 1]
+        _, gref, _ = O.render_workload_view(sc, cams, bi, w.eta, rays=rays, cot=cs)
+        gs = {"means": grads["means"][g0:g1], "prec": grads["prec"][g0:g1], "weights": grads["weights"][g0:g1],
+              "betas": grads["betas"][i]}
+        e = compare_grads(gs, gref)
+        _say(f"[bench-config] scene {i} backward {fmt(e)}")
+        assert_grads(e, f"bench configuration backward, scene {i}")
+
+
+def test_graphs_dropped_when_stale(fmb):
+    """Calls that change what the captured graphs launch (autotune, a pinned launch
+    configuration, colours, a second flow target, a backward that rebuilds the work lists)
+    drop them: the next replay reports FMB_ERR_STATE before launching anything, and a new
+    capture replays like the eager calls again."""
+    from tests.gpu_util import custom_scene
+    scs = [custom_scene(n, views, seed=n, flow=True) for n, views in ((12, [(24, 20), (9, 31)]), (37, [(16, 16)]))]
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=DEV).contiguous()  # noqa: E731
+    means = t(np.concatenate([s.means for s, _ in scs]))
+    prec = t(np.concatenate([s.prec for s, _ in scs]))
+    weights = t(np.concatenate([s.weights for s, _ in scs]))
+    betas = t(np.tile(np.array([W.BETA1, W.BETA2], np.float32), (2, 1)))
+    cams = [fmb.Cameras.from_numpy(c.w2c, c.intr, c.hw, c.w2c_b, c.intr_b, device=DEV) for _, c in scs]
+    b = fmb.Batch(means, prec, weights, betas, [1.0, 1.0], [s.n for s, _ in scs], cams)
+    outs = b.alloc_outputs(normals=True)
+    grads = b.alloc_grads()
+    cot = _cotangents(b, 47, normals=False)
+    st = torch.cuda.Stream()
+    torch.cuda.synchronize()
+
+    def capture_and_replay():
+        b.capture(outs, cot, grads, st)
+        with torch.cuda.stream(st):
+            b.graph_launch(2, st)
+        st.synchronize()
+
+    def assert_stale(what):
+        with pytest.raises(fmb.FmbError) as ei:
+            b.graph_launch(2, st)
+        assert ei.value.code == 6, what
+        _say(f"[stale] after {what}: FMB_ERR_STATE")
+
+    capture_and_replay()
+    b.autotune(outs, cot, grads)
+    torch.cuda.synchronize()
+    assert_stale("autotune")
+    capture_and_replay()
+    fmb.set_launch_config(batch=b, bwd_variant=4)
+    assert_stale("set_launch_config")
+    capture_and_replay()
+    q = t((np.random.Generator(np.random.PCG64(3)).standard_normal((means.shape[0], 3))).astype(np.float32))
+    b.set_colors(q)
+    assert_stale("set_colors")
+    capture_and_replay()
+    # an eager backward with a colour cotangent rebuilds the work lists with colour records
+    outs_c = b.alloc_outputs(normals=True, color=True)
+    grads_c = b.alloc_grads(colors=True)
+    b.forward(outs_c)
+    cot_c = dict(cot)
+    cot_c["color"] = t(np.zeros((b.n_rays, 3), np.float32))
+    b.backward(outs_c, cot_c, grads_c)
+    torch.cuda.synchronize()
+    assert_stale("a backward with a colour cotangent")
+    b.set_colors(None)
+    # a fresh capture replays like the eager calls
+    capture_and_replay()
+    ref_o = b.forward(b.alloc_outputs(normals=True))
+    ref_g = b.backward(ref_o, cot, b.alloc_grads())
+    torch.cuda.synchronize()
+    for k in ("depth", "alpha", "normal"):
+        assert torch.equal(outs[k], ref_o[k]), k
+    for k in ("means", "prec", "weights", "betas"):
+        assert torch.equal(grads[k], ref_g[k]), k

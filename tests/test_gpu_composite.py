@@ -109,7 +109,8 @@ def test_composite_ties_and_behind(fmb):
     _, gref, _ = O.render_workload_view(sc, cams, BETAS, 1.0, cot=cot, model="composite")
     e, eg = compare_forward(outs, ref), compare_grads(g, gref)
     _say(f"[composite-ties] {e} {eg}")
-    assert_forward(e, "ties")
+    # Gaussians behind the camera: per pixel the blended depth can cancel to near zero (norm-wise only)
+    assert_forward(e, "ties", per_pixel=False)
     assert_grads(eg, "ties")
 
 

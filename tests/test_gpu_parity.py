@@ -17,7 +17,7 @@ import pytest
 import oracle as O
 import workloads as W
 from tests.gpu_util import (TOL_ALPHA, TOL_GRAD, TOL_REL, assert_forward, assert_grads, compare_forward,
-                            compare_grads, custom_scene, hit_mask_cot, make_scene, maxabs, normwise, to_np)
+                            compare_grads, custom_scene, fmt, hit_mask_cot, make_scene, maxabs, normwise, to_np)
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -153,7 +153,7 @@ def test_background_rays_conditioning(fmb):
             sens[k] = max(sens[k], normwise(gj[k], gref[k]))
     eg = compare_grads(g, gref)
     _say(f"[background] gpu {eg} oracle one-ulp sensitivity {sens}")
-    for k in eg:
+    for k in ("means", "prec", "weights", "betas"):
         assert eg[k] <= max(TOL_GRAD, 10.0 * sens[k]), (k, eg, sens)
 
 
@@ -196,7 +196,9 @@ def test_behind_camera_and_eta(fmb):
     g = scene.backward(outs, t(cot["depth"]), t(cot["alpha"]), t(cot["normal"]))
     torch.cuda.synchronize()
     _, gref, _ = O.render_workload_view(sc, cams, betas, 2.5, cot=cot)
-    assert_forward(compare_forward(outs, ref), "behind")
+    # per pixel, the blend of depths of both signs (Gaussians behind the camera) can cancel to near
+    # zero, where the relative depth is ill-conditioned: the norm-wise contract only
+    assert_forward(compare_forward(outs, ref), "behind", per_pixel=False)
     assert_grads(compare_grads(g, gref), "behind")
 
 
@@ -683,3 +685,65 @@ def test_forward_variants(fmb, variant):
     _say(f"[fwd-variant] {variant}: {e}")
     assert_forward(e, f"forward variant {variant}")
     assert e["color"] <= TOL_REL
+
+
+# ---------------------------------------------------------------------------------------
+# The benchmarked steps of the large and the two-way-flow workloads: cotangents of the
+# reconstruction loss (Sec. 4) only, no normal cotangent, so every backward variant takes the
+# short (A, Bv, L) adjoint.  The cotangents are the oracle's loss gradient on a seeded sample
+# of rays (targets rendered by the oracle from the perturbed scene) and zero elsewhere, so the
+# oracle's gradient over the sample is the exact reference for the GPU gradient over the image.
+# ---------------------------------------------------------------------------------------
+
+def _loss_step_setup(fmb, name, k, seed, two_way=False):
+    w = W.make_config(name)
+    sc, cams = w.scenes[0], w.cameras[0]
+    if two_way:
+        cams = W.with_backward_flow(cams, seed=11)
+    p = cams.n_rays
+    scene, _ = make_scene(fmb, torch, sc, cams, w.betas, w.eta, DEV)
+    outs = scene.render(normals=w.normals, flow=cams.has_flow)
+    rays = _sample(p, k, seed)
+    ref, _, _ = O.render_workload_view(sc, cams, w.betas, w.eta, rays=rays)
+    tgt, _, _ = O.render_workload_view(w.targets[0], cams, w.betas, w.eta, rays=rays)
+    flow = ref.get("flow") if cams.has_flow else None
+    _, lg = O.loss_grad(ref["depth"], ref["alpha"], tgt["depth"], tgt["alpha"], flow,
+                        tgt.get("flow") if flow is not None else None, 1.0, 0.1, 2)
+    cs = {"depth": lg["depth"].astype(np.float32), "alpha": lg["alpha"].astype(np.float32), "normal": None,
+          "flow": None if flow is None else lg["flow"].astype(np.float32)}
+    _, gref, _ = O.render_workload_view(sc, cams, w.betas, w.eta, rays=rays, cot=cs)
+    cot = {"normal": None, "flow": None}
+    for key in ("depth", "alpha", "flow"):
+        if cs[key] is not None:
+            full = np.zeros((p,) + cs[key].shape[1:], np.float32)
+            full[rays] = cs[key]
+            cot[key] = torch.as_tensor(full, device=DEV).contiguous()
+    torch.cuda.synchronize()
+    return scene, outs, cot, gref
+
+
+LOSS_STEPS = [("large1080", 2000, 13, False), ("flow480", 20000, 17, True)]
+
+
+@pytest.fixture(scope="module", params=LOSS_STEPS, ids=[c[0] for c in LOSS_STEPS])
+def loss_step(fmb, request):
+    name, k, seed, two_way = request.param
+    _say(f"[loss-step] {name}: oracle loss gradient on {k} sampled rays")
+    return (name,) + _loss_step_setup(fmb, name, k, seed, two_way)
+
+
+@pytest.mark.parametrize("variant", list(range(6)) + ["tuned"])
+def test_loss_step_backward_variants(fmb, loss_step, variant):
+    name, scene, outs, cot, gref = loss_step
+    grads = scene.backward(outs, cot["depth"], cot["alpha"], None, cot["flow"])
+    if variant == "tuned":
+        scene.autotune(outs, cot, grads)
+        scene.render(normals=outs.get("normal") is not None, flow=cot["flow"] is not None, out=outs)
+    else:
+        fmb.set_launch_config(scene=scene, fwd_variant=fmb.launch_config(scene=scene)["fwd_variant"],
+                              bwd_variant=variant)
+    g = scene.backward(outs, cot["depth"], cot["alpha"], None, cot["flow"], grads=grads)
+    torch.cuda.synchronize()
+    e = compare_grads(g, gref)
+    _say(f"[loss-step] {name} backward variant {variant} ({fmb.launch_config(scene=scene)}): {fmt(e)}")
+    assert_grads(e, f"{name} loss step, backward variant {variant}")
