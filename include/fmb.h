@@ -248,7 +248,15 @@ int fmb_batch_backward(fmb_batch *batch, const float *g_depth, const float *g_al
  * replays are seen (a loss can fill the cotangents between the two replays).
  * fmb_batch_graph_launch replays the forward (which = 0), the backward (1) or both (2)
  * on `stream`; FMB_ERR_STATE if nothing was captured.  Replays of one batch must not
- * overlap (they share the batch's work counters and partial-gradient workspace). */
+ * overlap (they share the batch's work counters and partial-gradient workspace).
+ * The graphs are dropped (the next fmb_batch_graph_launch returns FMB_ERR_STATE until the
+ * batch is captured again) by every call that changes what they launch: fmb_autotune,
+ * fmb_set_config, fmb_set_model, fmb_set_colors and fmb_set_flow_pose2 with a changed
+ * value, and any eager forward or backward call that rebuilds the work lists (a backward
+ * with a colour cotangent after one without, or the reverse).  Graphs that a caller
+ * captures itself around library calls (e.g. one graph of a whole training step) hold
+ * the same kernel arguments and workspace addresses: after any of these calls they must be
+ * captured again; replaying them is undefined. */
 int fmb_batch_capture(fmb_batch *batch, float *depth, float *alpha, float *normal, float *flow,
                       float *color, float *stash, const float *g_depth, const float *g_alpha,
                       const float *g_normal, const float *g_flow, const float *g_color,
