@@ -476,97 +476,6 @@ __device__ __forceinline__ void pair_adjoint(const Ent &g, const Geo &q, float v
     a.p2 += p2;
 }
 
-// Adjoint of one pair without a normal cotangent in monomials of the ray direction, for Gaussians
-// seen from within kPlainMaxB standard deviations.  With a = U v, b = U mu' and r = t a - b at the
-// peak, the per-pair terms of the general adjoint are rho = -beta a + db b and k = alpha a + beta b,
-// where
-//   tau = tb / (a.a),  beta = tau + db t,  alpha = -t (tau + beta),
-// so over the rays of one view sum k v^T = U A + b Bv^T and sum rho = -U Bv + L b with
-//   A = sum alpha v v^T (symmetric),  Bv = sum beta v,  L = sum db.
-// A lane therefore accumulates A (6), Bv (3) and L; write_partial_plain forms the record.  The
-// record's terms are of size |b|^2 / |r|^2 times its value (the density part expands w w^T,
-// w = t v - mu', into monomials of v), so the FP32 sums' rounding reaches dU amplified by about
-// |b|^2: the kernels take this form only while |b| <= kPlainMaxB for every Gaussian of the item
-// and the offset form (pair_adjoint_offset) beyond.
-constexpr float kPlainMaxB = 100.0f;
-
-struct PlainAcc {
-    float a00 = 0, a01 = 0, a02 = 0, a11 = 0, a12 = 0, a22 = 0;
-    float b0 = 0, b1 = 0, b2 = 0;
-    float l = 0;
-};
-
-// vv = (v0 v0, v0 v1, v0 v2, v1 v1) and (v1 v2, v2 v2) of the ray, staged with it.
-__device__ __forceinline__ void pair_adjoint_plain(float t, float raa, float v0, float v1, float v2,
-                                                   const float4 &vva, const float4 &vvb, float tb, float db,
-                                                   PlainAcc &a)
-{
-    const float tau = tb * raa;
-    const float be = fmaf(db, t, tau);
-    const float al = -t * (tau + be);
-    a.a00 = fmaf(al, vva.x, a.a00);
-    a.a01 = fmaf(al, vva.y, a.a01);
-    a.a02 = fmaf(al, vva.z, a.a02);
-    a.a11 = fmaf(al, vva.w, a.a11);
-    a.a12 = fmaf(al, vvb.x, a.a12);
-    a.a22 = fmaf(al, vvb.y, a.a22);
-    a.b0 = fmaf(be, v0, a.b0);
-    a.b1 = fmaf(be, v1, a.b1);
-    a.b2 = fmaf(be, v2, a.b2);
-    a.l += db;
-}
-
-__device__ __forceinline__ void plain_acc_store(const PlainAcc &a, float *my)
-{
-    my[0] = a.a00; my[1] = a.a01; my[2] = a.a02; my[3] = a.a11; my[4] = a.a12; my[5] = a.a22;
-    my[6] = a.b0; my[7] = a.b1; my[8] = a.b2; my[9] = a.l;
-}
-
-// Partial record of one Gaussian from the sums (A, Bv, L) of pair_adjoint_plain (acc[0..9]), in
-// double: dU = U A + b Bv^T - (sum rho) mu'^T (upper triangle), sum rho = L b - U Bv,
-// dL/dlog(lambda) = L, then the remaining values (colour) from acc[coff...].
-__device__ __forceinline__ void write_partial_plain(float *__restrict__ dst, const float *acc, int rec, int coff,
-                                                    const float *__restrict__ prec, const float *__restrict__ mu,
-                                                    const double o[3])
-{
-    const double u00 = prec[0], u01 = prec[1], u02 = prec[2], u11 = prec[3], u12 = prec[4], u22 = prec[5];
-    const double m0 = (double)mu[0] - o[0], m1 = (double)mu[1] - o[1], m2 = (double)mu[2] - o[2];
-    const double A00 = acc[0], A01 = acc[1], A02 = acc[2], A11 = acc[3], A12 = acc[4], A22 = acc[5];
-    const double B0 = acc[6], B1 = acc[7], B2 = acc[8], L = acc[9];
-    const double b0 = u00 * m0 + u01 * m1 + u02 * m2, b1 = u11 * m1 + u12 * m2, b2 = u22 * m2;
-    const double r0 = L * b0 - (u00 * B0 + u01 * B1 + u02 * B2);
-    const double r1 = L * b1 - (u11 * B1 + u12 * B2);
-    const double r2 = L * b2 - u22 * B2;
-    // rows of U A (upper rows only are needed: entries (0,0..2), (1,1..2), (2,2))
-    const double ua00 = u00 * A00 + u01 * A01 + u02 * A02;
-    const double ua01 = u00 * A01 + u01 * A11 + u02 * A12;
-    const double ua02 = u00 * A02 + u01 * A12 + u02 * A22;
-    const double ua11 = u11 * A11 + u12 * A12;
-    const double ua12 = u11 * A12 + u12 * A22;
-    const double ua22 = u22 * A22;
-    dst[0] = (float)(ua00 + b0 * B0 - r0 * m0);
-    dst[1] = (float)(ua01 + b0 * B1 - r0 * m1);
-    dst[2] = (float)(ua02 + b0 * B2 - r0 * m2);
-    dst[3] = (float)(ua11 + b1 * B1 - r1 * m1);
-    dst[4] = (float)(ua12 + b1 * B2 - r1 * m2);
-    dst[5] = (float)(ua22 + b2 * B2 - r2 * m2);
-    dst[6] = (float)r0;
-    dst[7] = (float)r1;
-    dst[8] = (float)r2;
-    dst[9] = (float)L;
-    for (int c = 10; c < rec; ++c) dst[c] = acc[coff + c - 10];
-}
-
-// Squared distance |U mu'|^2 of the camera centre from the mean in standard deviations, from an
-// entry (U (hi + lo) = U hi + U lo), for the choice between the two forms above.
-__device__ __forceinline__ float entry_b2(const Ent &g)
-{
-    const float b0 = fmaf(g.u00, g.mh0, fmaf(g.u01, g.mh1, fmaf(g.u02, g.mh2, g.ul0)));
-    const float b1 = fmaf(g.u11, g.mh1, fmaf(g.u12, g.mh2, g.ul1));
-    const float b2 = fmaf(g.u22, g.mh2, g.ul2);
-    return fmaf(b0, b0, fmaf(b1, b1, b2 * b2));
-}
-
 // Adjoint of one pair without a normal cotangent, summed in terms of the peak's offset from the
 // mean.  With w = t v - mu' (the peak point relative to the mean, r = U w), tau = tb / (a.a) and
 // rho = -tau a - db r (the general adjoint with no normal term), the pair adds
@@ -575,9 +484,11 @@ __device__ __forceinline__ float entry_b2(const Ent &g)
 // to dL/dU, and -U (tau v + db w) = U (db mu' - beta v), beta = tau + db t, to sum rho.  A lane
 // therefore sums H = sum h w^T (9), Bv = sum beta v (3) and L = sum db, and write_partial_offset
 // forms dU = -U (H + H^T) and sum rho = L U mu' - U Bv once per (item, Gaussian) in double.
-// Every summand of H is of the size of the pair's own contribution, where the monomial form above
-// cancels by (|mu'| / |w|)^2 ~ |b|^2 / |r|^2 (for Gaussians a few thousandths wide seen from a few
-// units away, errors of 1e-3 of the result); sum rho cancels only linearly (|mu'| / |w|).  The envelope
+// Every summand of H is of the size of the pair's own contribution.  Expanding w w^T into monomials
+// of v instead (the same sums over A = sum alpha v v^T, Bv and L with alpha = -t (2 tau + db t),
+// the record U A + b Bv^T - (L b - U Bv) mu'^T, b = U mu') is fewer operations per pair but cancels
+// by (|mu'| / |w|)^2 ~ |b|^2 / |r|^2: for Gaussians a few thousandths wide seen from a few units
+// away its FP32 sums leave errors of 1e-3 of dL/dU.  Sum rho cancels only linearly (|mu'| / |w|).  The envelope
 // condition a.r = 0 enters only through terms of relative size |t - t_peak| |a| / |r|, so neither
 // t nor r needs the Newton step, and w is the high part t v - hi (the low part of mu' is below
 // 2^-24 |mu'|).

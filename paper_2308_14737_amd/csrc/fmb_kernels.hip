@@ -172,11 +172,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(bwd_min_w
                                                    float *__restrict__ beta_partial)
 {
     constexpr bool NORMALS = (F & kNrm) != 0, PERSIST = (F & kPer) != 0, COLOR = (F & kCol) != 0;
-    // Without a normal cotangent the pairs take pair_adjoint_plain or pair_adjoint_offset: the staged
-    // ray is (v, M2) (invS, tf_bar, kappa, D_bar) (v v^T: 4) (v v^T: 2, t_f, dc) [(Cb, 0)]; with one
-    // it is the prologue as written by ray_prologue (four float4).
+    // Without a normal cotangent the pairs take pair_adjoint_offset: the staged ray is
+    // (v, M2) (invS, tf_bar, kappa, D_bar) (t_f, dc, 0, 0) [(Cb, 0)]; with one it is the prologue
+    // as written by ray_prologue (four float4).
     constexpr bool PLAIN = !NORMALS;
-    constexpr int RW = PLAIN ? (COLOR ? 5 : 4) : 4;  // float4 per staged ray
+    constexpr int RW = PLAIN ? (COLOR ? 4 : 3) : 4;  // float4 per staged ray
     constexpr int REC = COLOR ? kPartialColor : kPartial;  // partial record per Gaussian
     // a lane's sums: (H, Bv, L) of the offset form or the general record, then the colour sums
     constexpr int LREC = PLAIN ? kOffsetAcc + (COLOR ? 3 : 0) : REC;
@@ -224,10 +224,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(bwd_min_w
         }
         float aB1 = 0, aB2 = 0;
         float aC0 = 0, aC1 = 0, aC2 = 0;
-        // Without a normal cotangent: the monomial form while every Gaussian of the item lies within
-        // kPlainMaxB standard deviations of the camera, else the offset form (a block-uniform choice).
-        const bool offset_form = PLAIN && __syncthreads_or(active && entry_b2(g) > kPlainMaxB * kPlainMaxB);
-
         // The item's rays RT at a time: staged with their prologue, then `pair` runs over this lane's
         // rays slot, slot + slots, ... (walked by address: one induction variable).
         auto passes = [&](auto &&pair) {
@@ -238,12 +234,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(bwd_min_w
                     float4 pr[4];
                     ray_prologue<F>(P, I, item.view, vr, e, kk, o0, o1, o2, r0 + q, q < cnt, bl.b1, bl.nc2, pr);
                     if (PLAIN) {
-                        const float v0 = pr[0].x, v1 = pr[0].y, v2 = pr[0].z;
                         rays[RW * q] = pr[0];
                         rays[RW * q + 1] = make_float4(pr[1].x, pr[1].y, pr[2].y, pr[2].z);
-                        rays[RW * q + 2] = make_float4(v0 * v0, v0 * v1, v0 * v2, v1 * v1);
-                        rays[RW * q + 3] = make_float4(v1 * v2, v2 * v2, pr[2].w, pr[3].w);
-                        if (COLOR) rays[RW * q + 4] = pr[3];
+                        rays[RW * q + 2] = make_float4(pr[2].w, pr[3].w, 0.0f, 0.0f);
+                        if (COLOR) rays[RW * q + 3] = pr[3];
                     } else {
 #pragma unroll
                         for (int k = 0; k < RW; ++k) rays[RW * q + k] = pr[k];
@@ -257,12 +251,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(bwd_min_w
             }
             __syncthreads();  // every lane is done with the staged rays (the LDS is reused below)
         };
-        // One pair without a normal cotangent up to the adjoint's inputs (t_bar, d_bar); `adjoint`
-        // accumulates the chosen form.
-        auto plain_pair = [&](const float4 *rp, auto &&adjoint) {
-            const float4 x0 = rp[0], x1 = rp[1], x3 = rp[3];
+        // One pair without a normal cotangent, accumulated in the offset form.
+        auto plain_pair = [&](const float4 *rp, OffsetAcc &acc) {
+            const float4 x0 = rp[0], x1 = rp[1], x2 = rp[2];
             float4 x4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            if (COLOR) x4 = rp[4];
+            if (COLOR) x4 = rp[3];
             const float v0 = x0.x, v1 = x0.y, v2 = x0.z;
             Geo q;
             pair_geo_coarse(g, v0, v1, v2, bl.hm, bl.b1, bl.nc2, q);
@@ -280,9 +273,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(bwd_min_w
             const float zb = wt * (lin - x1.z);
             const float tb = fmaf(-bl.cb, zb, wt * tfb);
             const float db = fmaf(bl.b1, zb, x1.w * delta);
-            aB1 = fmaf(zb, q.d2 - x3.w, aB1);
-            aB2 = fmaf(zb, q.t - x3.z, aB2);
-            adjoint(q, rp, v0, v1, v2, tb, db);
+            aB1 = fmaf(zb, q.d2 - x2.y, aB1);
+            aB2 = fmaf(zb, q.t - x2.x, aB2);
+            pair_adjoint_offset(q, v0, v1, v2, tb, db, acc);
         };
         float *my = red + RS * tid;
         if (!PLAIN) {
@@ -315,23 +308,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(bwd_min_w
             });
             my[0] = acc.u0; my[1] = acc.u1; my[2] = acc.u2; my[3] = acc.u3; my[4] = acc.u4; my[5] = acc.u5;
             my[6] = acc.p0; my[7] = acc.p1; my[8] = acc.p2; my[9] = acc.l;
-        } else if (offset_form) {
-            OffsetAcc acc;
-            passes([&](const float4 *rp) {
-                plain_pair(rp, [&](const Geo &q, const float4 *, float v0, float v1, float v2, float tb, float db) {
-                    pair_adjoint_offset(q, v0, v1, v2, tb, db, acc);
-                });
-            });
-            offset_acc_store(acc, my);
         } else {
-            PlainAcc acc;
-            passes([&](const float4 *rp) {
-                plain_pair(rp, [&](const Geo &q, const float4 *r, float v0, float v1, float v2, float tb, float db) {
-                    pair_adjoint_plain(q.t, q.raa, v0, v1, v2, r[2], r[3], tb, db, acc);
-                });
-            });
-            plain_acc_store(acc, my);
-            for (int c = 10; c < kOffsetAcc; ++c) my[c] = 0.0f;
+            OffsetAcc acc;
+            passes([&](const float4 *rp) { plain_pair(rp, acc); });
+            offset_acc_store(acc, my);
         }
 
         // deterministic block reduction: Gaussian partials over the slots, betas over all lanes
@@ -349,11 +329,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(bwd_min_w
                 for (int c = 0; c < LREC; ++c) sum[c] += red[RS * (s * item.gc + gi) + c];
             }
             const int gg = sr.gauss_off + item.g0 + gi;
-            if (PLAIN && offset_form)
+            if (PLAIN)
                 write_partial_offset(partial + item.poff + REC * gi, sum, REC, P.prec + 6 * gg, P.means + 3 * gg, o);
-            else if (PLAIN)
-                write_partial_plain(partial + item.poff + REC * gi, sum, REC, LREC - 3, P.prec + 6 * gg,
-                                    P.means + 3 * gg, o);
             else
                 write_partial(partial + item.poff + REC * gi, sum, REC, P.means + 3 * gg, o);
         }
