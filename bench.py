@@ -118,13 +118,31 @@ def parse():
     return ap.parse_args()
 
 
+def host_cpu():
+    """CPU model, logical CPUs of the host and those this process may use (from /proc/cpuinfo)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
 def cpu_baseline(w, seconds):
     """Time the FP64 oracle (as it stands) on the same workload, scene after scene (passes over
     the batch repeated) until about `seconds` of work; returns pairs/s of forward + backward."""
     import numpy as np
 
     import oracle as O
-    threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16")), 16)
+    # the threads OpenMP is given (OMP_NUM_THREADS where it is set, e.g. a host's CPU share per
+    # GPU), else every core this process may run on
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    threads = max(1, min(int(os.environ.get("OMP_NUM_THREADS") or avail), avail))
     pairs = scenes = 0
     g = np.random.Generator(np.random.PCG64(9))
     t0 = time.perf_counter()
@@ -139,6 +157,7 @@ def cpu_baseline(w, seconds):
                 break
     dt = time.perf_counter() - t0
     return {"value": pairs / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "host": host_cpu(), "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS"),
             "sample": f"FP64 oracle forward (depth, alpha, normals) + backward (depth and alpha "
                       f"cotangents), all rays of {scenes} scenes taken in order, passes over the "
                       f"16-scene batch repeated: {pairs} pairs in {dt:.2f} s on {threads} threads"}
@@ -267,7 +286,7 @@ def main():
         print(f"# graph step {ms_graph:.3f} ms", file=sys.stderr, flush=True)
 
     # plain: one launch sequence per scene
-    plain_ms = None
+    plain_ms = plain_eager_ms = None
     if not args.no_plain:
         scenes = []
         for i, (sc, cams) in enumerate(zip(w.scenes, w.cameras)):
@@ -290,8 +309,26 @@ def main():
 
         for _ in range(args.warmup):
             step_plain()
-        plain_ms = timed(step_plain, args.steps) * 1e3
-        print(f"# plain step {plain_ms:.3f} ms", file=sys.stderr, flush=True)
+        plain_eager_ms = timed(step_plain, args.steps) * 1e3
+        print(f"# plain step (eager) {plain_eager_ms:.3f} ms", file=sys.stderr, flush=True)
+        plain_ms = plain_eager_ms
+        if not args.no_graph:
+            # like for like with the batched value: the 16 per-scene launch sequences (forward, loss
+            # kernel, backward + finalize of every scene) replayed as one graph
+            s2p = torch.cuda.Stream(dev)
+            s2p.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(s2p):
+                step_plain()
+            torch.cuda.current_stream().wait_stream(s2p)
+            torch.cuda.synchronize()
+            g_plain = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g_plain):
+                step_plain()
+            for _ in range(args.warmup):
+                g_plain.replay()
+            plain_ms = timed(g_plain.replay, args.steps) * 1e3
+            del g_plain
+            print(f"# plain step (one graph) {plain_ms:.3f} ms", file=sys.stderr, flush=True)
 
     launch = fmb.launch_config(batch=batch)
     # the zero-parameter renderer on the same batch: eager step, HIP-event kernel times
@@ -496,7 +533,11 @@ def main():
                    "parallelism": "single GPU, persistent batched kernels in HIP graphs"},
         "plain_value": (pairs / (plain_ms * 1e-3)) if plain_ms else None,
         "plain_ms_per_step": plain_ms,
+        "plain_timed": ("replays of one graph of the 16 per-scene launch sequences"
+                        if plain_ms is not None and plain_ms != plain_eager_ms else "eager launches"),
+        "plain_eager_ms_per_step": plain_eager_ms,
         "batched_over_plain": (plain_ms / ms_step) if plain_ms else None,
+        "batched_over_plain_eager": (plain_eager_ms / ms_eager) if plain_eager_ms else None,
         "eager_ms_per_step": ms_eager,
         "timed": "replays of one graph of the whole step" if ms_graph is not None else "eager launches",
         "loss": "depth and alpha cotangents written by the forward's per-ray epilogue "

@@ -350,11 +350,48 @@ struct Job {
         return model == FMB_MODEL_COMPOSITE ? (colour ? 3 : 1) : (variant * 2 + (colour ? 1 : 0)) * 2;
     }
 
+    // The backward's work plan, built on the host: items (LPT order), finalize tasks and groups, and
+    // the sizes of the partial records and reduction stages.
+    struct BwdPlan {
+        int key = -1;
+        std::vector<BwdItem> items;
+        std::vector<int> order;
+        std::vector<FinTask> tasks;
+        std::vector<FinGroup> groups;
+        size_t poff = 0, soff = 0;  // partial floats, first-stage doubles
+        int max_gc = 1, max_nval = 1;
+    };
+    BwdPlan na_plan;  // the plan of the last fmb_backward_noalloc call (host memory only)
+
     int build_bwd(int variant, bool colour)
     {
         const int key = bwd_key(variant, colour);
         if (bwd_built == key) return FMB_OK;
         drop_graphs();  // items, partial records and the finalize plan change (and may move)
+        BwdPlan pl;
+        int rc = plan_bwd(variant, colour, pl);
+        if (rc) return rc;
+        HIPCHK(d_bitems.upload(pl.items));
+        HIPCHK(d_border.upload(pl.order));
+        HIPCHK(d_tasks.upload(pl.tasks));
+        HIPCHK(d_groups.upload(pl.groups));
+        HIPCHK(d_stage.ensure(std::max<size_t>(pl.soff, 1) * sizeof(double)));
+        HIPCHK(d_stage_beta.ensure(std::max<size_t>(2 * pl.groups.size(), 2) * sizeof(double)));
+        n_groups = (int)pl.groups.size();
+        fin_max_gc = pl.max_gc;
+        fin_max_nval = pl.max_nval;
+        HIPCHK(d_partial.ensure(std::max<size_t>(pl.poff, 1) * sizeof(float)));
+        HIPCHK(d_bpart.ensure(std::max<size_t>(2 * pl.items.size(), 2) * sizeof(float)));
+        partial_floats = pl.poff;
+        n_bitems = (int)pl.items.size();
+        n_tasks = (int)pl.tasks.size();
+        bwd_built = key;
+        return FMB_OK;
+    }
+
+    int plan_bwd(int variant, bool colour, BwdPlan &pl)
+    {
+        const int key = bwd_key(variant, colour);
         const bool comp = model == FMB_MODEL_COMPOSITE;
         const int rec = colour ? kPartialColor : kPartial;
         const int RT = bwd_variant_rt(variant);
@@ -470,23 +507,17 @@ struct Job {
         std::vector<int> order(items.size());
         std::iota(order.begin(), order.end(), 0);
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-        HIPCHK(d_bitems.upload(items));
-        HIPCHK(d_border.upload(order));
-        HIPCHK(d_tasks.upload(tasks));
-        HIPCHK(d_groups.upload(groups));
-        HIPCHK(d_stage.ensure(std::max<size_t>(soff, 1) * sizeof(double)));
-        HIPCHK(d_stage_beta.ensure(std::max<size_t>(2 * groups.size(), 2) * sizeof(double)));
-        n_groups = (int)groups.size();
-        fin_max_gc = 1;
-        fin_max_nval = 1;
-        for (const auto &t : tasks) fin_max_gc = std::max(fin_max_gc, t.gc);
-        for (const auto &g : groups) fin_max_nval = std::max(fin_max_nval, g.nval);
-        HIPCHK(d_partial.ensure(std::max<size_t>(poff, 1) * sizeof(float)));
-        HIPCHK(d_bpart.ensure(std::max<size_t>(2 * items.size(), 2) * sizeof(float)));
-        partial_floats = poff;
-        n_bitems = (int)items.size();
-        n_tasks = (int)tasks.size();
-        bwd_built = key;
+        pl.key = key;
+        pl.max_gc = 1;
+        pl.max_nval = 1;
+        for (const auto &t : tasks) pl.max_gc = std::max(pl.max_gc, t.gc);
+        for (const auto &g : groups) pl.max_nval = std::max(pl.max_nval, g.nval);
+        pl.items = std::move(items);
+        pl.order = std::move(order);
+        pl.tasks = std::move(tasks);
+        pl.groups = std::move(groups);
+        pl.poff = poff;
+        pl.soff = soff;
         return FMB_OK;
     }
 
@@ -1253,11 +1284,13 @@ int fmb_autotune(fmb_scene *s, fmb_batch *b, float *depth, float *alpha, float *
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
+    // one untimed launch (it builds the variant's item lists), then kTuneLaunches timed back to back
+    constexpr int kTuneLaunches = 10;
     auto time_it = [&](auto &&fn, float &ms) -> int {
         int rc = fn();
         if (rc) return rc;
         HIPCHK(hipEventRecord(e0, st));
-        for (int r = 0; r < 3; ++r)
+        for (int r = 0; r < kTuneLaunches; ++r)
             if ((rc = fn())) return rc;
         HIPCHK(hipEventRecord(e1, st));
         HIPCHK(hipEventSynchronize(e1));
