@@ -191,6 +191,25 @@ int fmb_backward(fmb_scene *scene, const float *g_depth, const float *g_alpha,
                  const float *depth, const float *color, const float *stash, float *g_means,
                  float *g_prec, float *g_weights, float *g_colors, float *g_betas, void *stream);
 
+/* Bytes of the fixed device workspace of fmb_backward_noalloc (32 MiB per device). */
+#define FMB_NOALLOC_SCRATCH_BYTES (32ULL << 20)
+
+/* fmb_backward for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same arguments, kernels and results
+ * (bit for bit), with no device allocation.  The work lists, partial gradients and reduction
+ * stages live in a fixed array of FMB_NOALLOC_SCRATCH_BYTES that the library holds on each device
+ * it runs on until the process ends; the work lists are copied into it from host memory on
+ * `stream` at every call (the scene's work plan is built on the host once per configuration).
+ * Every call on a device shares that array and leaves its contents behind: calls that overlap on
+ * one device (other streams or threads) race, and the caller must serialise them.  The scene's
+ * device must be the current device.  Errors: those of fmb_backward; FMB_ERR_SHAPE when the
+ * scene's work needs more workspace than FMB_NOALLOC_SCRATCH_BYTES (the message gives the size;
+ * fmb_backward has no such limit); FMB_ERR_STATE when another device is current. */
+int fmb_backward_noalloc(fmb_scene *scene, const float *g_depth, const float *g_alpha,
+                         const float *g_normal, const float *g_flow, const float *g_color,
+                         const float *depth, const float *color, const float *stash, float *g_means,
+                         float *g_prec, float *g_weights, float *g_colors, float *g_betas, void *stream);
+
 /* ------------------------------------------------------------------------------ */
 /* Batch of independent scenes (uneven Gaussian counts, view counts, resolutions) */
 /* ------------------------------------------------------------------------------ */

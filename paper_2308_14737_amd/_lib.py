@@ -41,6 +41,7 @@ SIGNATURES = {
     "fmb_split_gaussians": (_int, [_i32] + [_vp] * 10),
     "fmb_render": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fmb_backward": (_int, [_vp] + [_vp] * 13 + [_vp]),
+    "fmb_backward_noalloc": (_int, [_vp] + [_vp] * 13 + [_vp]),
     "fmb_batch_create": (_int, [ctypes.POINTER(_vp), _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                 _vp, _vp, _vp, _vp, _vp]),
     "fmb_batch_destroy": (_int, [_vp]),

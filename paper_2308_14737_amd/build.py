@@ -9,7 +9,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libfmb.so")
 SOURCES = [os.path.join(PKG, "csrc", "fmb_kernels.hip"), os.path.join(PKG, "csrc", "fmb_composite.hip"),
-           os.path.join(PKG, "csrc", "fmb_api.cpp"), os.path.join(PKG, "csrc", "fmb_split.cpp")]
+           os.path.join(PKG, "csrc", "fmb_scratch.hip"), os.path.join(PKG, "csrc", "fmb_api.cpp"),
+           os.path.join(PKG, "csrc", "fmb_split.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -55,6 +55,8 @@ hipError_t launch_bwdc(int km, int flags, int n_items, hipStream_t st, const Par
                        const BwdItem *items, float *partial, float *beta_partial);
 hipError_t occupancy_fwd(int variant, int flags, int *blocks_per_cu);
 hipError_t occupancy_bwd(int variant, int flags, int *blocks_per_cu);
+hipError_t scratch_base(void **out);
+size_t scratch_bytes();
 }  // namespace fmb
 
 using namespace fmb;
@@ -711,6 +713,76 @@ struct Job {
         tf.stop();
         return FMB_OK;
     }
+
+    // fmb_backward without a device allocation: the work plan (built on the host and kept there) is
+    // copied into the library's fixed scratch array on the call's stream, and the same kernels run
+    // over it with the same one-shot launches, so the results equal fmb_backward's bit for bit.
+    int backward_noalloc(const BwdIn &I, const Grads &G, hipStream_t st)
+    {
+        if (!cams_set) return fail(FMB_ERR_STATE, "backward before cameras were set");
+        CHECK_ARG(I.depth && I.stash, "depth and stash from the forward pass are required");
+        CHECK_ARG(aligned(I.stash, 16), "stash must be 16-byte aligned");
+        CHECK_ARG(G.means && G.prec && G.weights && G.betas, "gradient outputs are required");
+        CHECK_ARG(!I.g_flow || has_flow, "flow cotangent given but the cameras have no second pose");
+        CHECK_ARG(!I.g_color || (prm.colors && I.color), "colour cotangent needs colours and the colour output");
+        const bool colour = I.g_color != nullptr;
+        if (na_plan.key != bwd_key(bwd_variant, colour)) {
+            int rc = plan_bwd(bwd_variant, colour, na_plan);
+            if (rc) return rc;
+        }
+        const BwdPlan &pl = na_plan;
+        // sections of the scratch array, each 256-byte aligned
+        size_t off = 0;
+        auto take = [&](size_t bytes) {
+            const size_t at = off;
+            off = (off + bytes + 255) & ~size_t(255);
+            return at;
+        };
+        const size_t o_items = take(pl.items.size() * sizeof(BwdItem));
+        const size_t o_tasks = take(pl.tasks.size() * sizeof(FinTask));
+        const size_t o_groups = take(pl.groups.size() * sizeof(FinGroup));
+        const size_t o_part = take(std::max<size_t>(pl.poff, 1) * sizeof(float));
+        const size_t o_bpart = take(std::max<size_t>(2 * pl.items.size(), 2) * sizeof(float));
+        const size_t o_stage = take(std::max<size_t>(pl.soff, 1) * sizeof(double));
+        const size_t o_sbeta = take(std::max<size_t>(2 * pl.groups.size(), 2) * sizeof(double));
+        if (off > scratch_bytes()) {
+            std::ostringstream m;
+            m << "the scene's backward needs " << off << " bytes of workspace; fmb_backward_noalloc has "
+              << scratch_bytes() << " (FMB_NOALLOC_SCRATCH_BYTES): use fmb_backward";
+            return fail(FMB_ERR_SHAPE, m.str());
+        }
+        int dev = -1;
+        HIPCHK(hipGetDevice(&dev));
+        if (dev != device) return fail(FMB_ERR_STATE, "the scene's device must be the current device");
+        void *base = nullptr;
+        HIPCHK(scratch_base(&base));
+        char *b = static_cast<char *>(base);
+        HIPCHK(hipMemcpyAsync(b + o_items, pl.items.data(), pl.items.size() * sizeof(BwdItem), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(b + o_tasks, pl.tasks.data(), pl.tasks.size() * sizeof(FinTask), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(b + o_groups, pl.groups.data(), pl.groups.size() * sizeof(FinGroup),
+                              hipMemcpyHostToDevice, st));
+        const BwdItem *items = reinterpret_cast<const BwdItem *>(b + o_items);
+        float *part = reinterpret_cast<float *>(b + o_part);
+        float *bpart = reinterpret_cast<float *>(b + o_bpart);
+        const int n_items = (int)pl.items.size();
+        if (model == FMB_MODEL_COMPOSITE) {
+            TimedSpan tb(st, 1);
+            HIPCHK(launch_bwdc(comp_km(), bwd_flags(I, false), n_items, st, prm, I, items, part, bpart));
+            tb.stop();
+        } else {
+            TimedSpan tb(st, 1);
+            HIPCHK(launch_bwd(bwd_variant, bwd_flags(I, false), n_items, st, prm, I, items, n_items, nullptr, nullptr,
+                              part, bpart));
+            tb.stop();
+        }
+        TimedSpan tf(st, 2);
+        HIPCHK(launch_fin((int)pl.tasks.size(), (int)pl.groups.size(), pl.max_gc, pl.max_nval, st, prm,
+                          reinterpret_cast<const FinTask *>(b + o_tasks), reinterpret_cast<const FinGroup *>(b + o_groups),
+                          part, bpart, reinterpret_cast<double *>(b + o_stage), reinterpret_cast<double *>(b + o_sbeta),
+                          G.means, G.prec, G.weights, G.colors, G.betas));
+        tf.stop();
+        return FMB_OK;
+    }
 };
 
 int check_params(const float *means, const float *prec, const float *weights, const float *betas)
@@ -945,6 +1017,17 @@ int fmb_backward(fmb_scene *s, const float *g_depth, const float *g_alpha, const
     CHECK_ARG(s, "scene must be non-NULL");
     return s->job.backward(BwdIn{g_depth, g_alpha, g_normal, g_flow, g_color, depth, color, stash},
                            Grads{g_means, g_prec, g_weights, g_colors, g_betas}, false, (hipStream_t)stream);
+}
+
+int fmb_backward_noalloc(fmb_scene *s, const float *g_depth, const float *g_alpha, const float *g_normal,
+                         const float *g_flow, const float *g_color, const float *depth, const float *color,
+                         const float *stash, float *g_means, float *g_prec, float *g_weights, float *g_colors,
+                         float *g_betas, void *stream)
+{
+    g_err.clear();
+    CHECK_ARG(s, "scene must be non-NULL");
+    return s->job.backward_noalloc(BwdIn{g_depth, g_alpha, g_normal, g_flow, g_color, depth, color, stash},
+                                   Grads{g_means, g_prec, g_weights, g_colors, g_betas}, (hipStream_t)stream);
 }
 
 int fmb_batch_create(fmb_batch **out, int32_t s, const int32_t *n_host, const int32_t *v_host, const float *means,

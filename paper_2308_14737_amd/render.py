@@ -207,7 +207,9 @@ class Scene:
         return outs["stash"][:, 1]
 
     def backward(self, outs: dict, g_depth=None, g_alpha=None, g_normal=None, g_flow=None,
-                 grads: Optional[dict] = None, g_color=None) -> dict:
+                 grads: Optional[dict] = None, g_color=None, noalloc: bool = False) -> dict:
+        """Gradients of the cotangent-weighted outputs (fmb_backward; with `noalloc`,
+        fmb_backward_noalloc: the same results from the library's fixed device workspace)."""
         dev = self.device
         g = grads or {}
         gm = g.get("means") if g.get("means") is not None else torch.empty(self.n, 3, device=dev)
@@ -218,7 +220,8 @@ class Scene:
         if g_color is not None:
             gc = g.get("colors") if g.get("colors") is not None else torch.empty(self.n, 3, device=dev)
         cot = [None if c is None else c.contiguous() for c in (g_depth, g_alpha, g_normal, g_flow, g_color)]
-        _lib.call("fmb_backward", self._h, *[_vp(c) for c in cot], _vp(outs["depth"]),
+        _lib.call("fmb_backward_noalloc" if noalloc else "fmb_backward", self._h, *[_vp(c) for c in cot],
+                  _vp(outs["depth"]),
                   _vp(outs.get("color")), _vp(outs["stash"]), _vp(gm), _vp(gp), _vp(gw), _vp(gc), _vp(gb),
                   _stream(dev))
         return {"means": gm, "prec": gp, "weights": gw, "betas": gb, "colors": gc}
