@@ -95,6 +95,20 @@ int fail(int code, const std::string &msg)
 
 bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
+// View record with its ray tiles: 8 x 8 pixel tiles for images at least 8 pixels wide, else runs
+// of 64 consecutive rays (also every view of explicit rays, stored as h x 1).
+ViewRec view_rec(int32_t h, int32_t w, int64_t ray_off, int32_t scene)
+{
+    ViewRec v{h, w, (int32_t)ray_off, scene, 0, 0};
+    if (w >= 8) {
+        v.tiles_x = (w + 7) / 8;
+        v.tiles = v.tiles_x * ((h + 7) / 8);
+    } else {
+        v.tiles = (int32_t)(((int64_t)h * w + 63) / 64);
+    }
+    return v;
+}
+
 // Size limits (FMB_MAX_* in fmb.h).  Ray indices are 32-bit in the kernels (per-ray output offsets
 // are formed in 64 bits); the 2^24 rays of headroom keep every tile or span end (spans are at most
 // 2^22 rays) inside int.  Gaussian and view counts keep 16 x index inside int.
@@ -278,15 +292,15 @@ struct Job {
     {
         if (fwd_built == variant) return FMB_OK;
         drop_graphs();  // the forward graph's items (and possibly their buffer) change
-        const int R = fwd_variant_rays(variant);
+        const int R = fwd_variant_rays(variant);  // rays of an item: R / 64 tiles
         std::vector<FwdItem> items;
         std::vector<double> cost;
         for (int k = 0; k < V; ++k) {
-            const int hw = views[k].h * views[k].w;
+            const int64_t hw = (int64_t)views[k].h * views[k].w;
             const int n = scenes[views[k].scene].n;
-            for (int r0 = 0; r0 < hw; r0 += R) {
-                items.push_back({k, r0});
-                cost.push_back((double)n * std::min(R, hw - r0));
+            for (int t0 = 0; t0 < views[k].tiles; t0 += R / 64) {
+                items.push_back({k, t0});
+                cost.push_back((double)n * std::min<int64_t>(R, hw - 64 * (int64_t)t0));
             }
         }
         std::vector<int> order(items.size());
@@ -892,7 +906,7 @@ int fmb_set_cameras(fmb_scene *s, int32_t v, const float *w2c, const float *intr
     j.views.clear();
     int64_t off = 0;
     for (int k = 0; k < v; ++k) {
-        j.views.push_back({hw[2 * k], hw[2 * k + 1], (int32_t)off, 0});
+        j.views.push_back(view_rec(hw[2 * k], hw[2 * k + 1], off, 0));
         off += (int64_t)hw[2 * k] * hw[2 * k + 1];
     }
     j.scenes[0].view_off = 0;
@@ -934,7 +948,7 @@ int fmb_set_rays(fmb_scene *s, int32_t v, const float *w2c, const float *intr, c
     j.views.clear();
     int64_t off = 0;
     for (int k = 0; k < v; ++k) {
-        j.views.push_back({counts[k], 1, (int32_t)off, 0});
+        j.views.push_back(view_rec(counts[k], 1, off, 0));
         off += counts[k];
     }
     j.scenes[0].view_off = 0;
@@ -1068,7 +1082,7 @@ int fmb_batch_create(fmb_batch **out, int32_t s, const int32_t *n_host, const in
         j.ray_off_scene.push_back(roff);
         for (int k = 0; k < v_host[i]; ++k) {
             const int kk = voff + k;
-            j.views.push_back({hw[2 * kk], hw[2 * kk + 1], (int32_t)roff, i});
+            j.views.push_back(view_rec(hw[2 * kk], hw[2 * kk + 1], roff, i));
             roff += (int64_t)hw[2 * kk] * hw[2 * kk + 1];
         }
         goff += n_host[i];

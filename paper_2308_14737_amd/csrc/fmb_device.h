@@ -129,6 +129,33 @@ __device__ __forceinline__ void ray_dir(const Params &P, const ViewRec &vr, cons
     }
 }
 
+// Ray `lane` of ray tile `tile` of view `vr` (see ViewRec): its local index (row-major pixel
+// index, or explicit-ray index), or -1 past the view's edge; `row` and `col` give the pixel of an
+// 8 x 8 tile.  `tile` is uniform over the wave.
+__device__ __forceinline__ int tile_local(const ViewRec &vr, int tile, int lane, int &row, int &col)
+{
+    if (vr.tiles_x > 0) {
+        const int ty = tile / vr.tiles_x, tx = tile - ty * vr.tiles_x;
+        row = 8 * ty + (lane >> 3);
+        col = 8 * tx + (lane & 7);
+        return (tile < vr.tiles && row < vr.h && col < vr.w) ? row * vr.w + col : -1;
+    }
+    const int local = 64 * tile + lane;
+    row = col = 0;
+    return local < vr.h * vr.w ? local : -1;
+}
+
+// Direction of the ray of a tile lane with local index `local` >= 0 (tile_local's row and col).
+__device__ __forceinline__ void tile_ray_dir(const Params &P, const ViewRec &vr, const float *__restrict__ e,
+                                             const float *__restrict__ k, int local, int row, int col, float &v0,
+                                             float &v1, float &v2)
+{
+    if (!P.dirs && vr.tiles_x > 0)
+        pixel_dir(e, k, row, col, v0, v1, v2);
+    else
+        ray_dir(P, vr, e, k, local, v0, v1, v2);
+}
+
 __device__ __forceinline__ void project(const float *__restrict__ e, const float *__restrict__ k, float p0,
                                         float p1, float p2, float &u, float &v)
 {

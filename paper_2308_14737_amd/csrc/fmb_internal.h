@@ -5,7 +5,7 @@
 // persistent kernels run the same per-item code.
 //
 // Work is cut into items:
-//   forward item  = (view, first ray of a tile of BLOCK*RPT rays of that view)
+//   forward item  = (view, first of BLOCK*RPT/64 consecutive ray tiles of that view, see ViewRec)
 //   backward item = (view, first ray of a span of rays, Gaussian chunk) plus the
 //                   (chunk size, slots) thread mapping and the offset of its partial
 //                   gradient record.
@@ -27,6 +27,10 @@ struct ViewRec {       // one per view of the batch
     int32_t h, w;      // image size (explicit rays: h = ray count, w = 1)
     int32_t ray_off;   // global index of the view's first ray
     int32_t scene;     // owning scene
+    // Ray tiles of 64 rays, the unit of a wave: 8 x 8 pixel tiles (row-major over tiles) for views
+    // at least 8 pixels wide (tiles_x tiles per tile row), else runs of 64 consecutive rays
+    // (tiles_x = 0).  `tiles` counts them.
+    int32_t tiles_x, tiles;
 };
 
 struct SceneRec {
@@ -38,7 +42,7 @@ struct SceneRec {
 
 struct FwdItem {       // 8 bytes
     int32_t view;
-    int32_t ray0;      // first local ray (pixel index within the view)
+    int32_t tile0;     // first ray tile (see ViewRec) of the view
 };
 
 struct BwdItem {       // 32 bytes

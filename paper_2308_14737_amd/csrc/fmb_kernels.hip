@@ -58,7 +58,11 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
         double o[3];
         cam_centre(e, o);
         const Blend bl = blend_of(P, vr.scene);
-        const int hw = vr.h * vr.w;
+        // ray j of a lane: lane `lane` of tile tile0 + j * NW + wave (8 x 8 pixels where the view is
+        // wide enough: a wave's rays stay close together, so the exact skip of zero weights below
+        // is uniform over the wave more often)
+        constexpr int NW = BLOCK / 64;
+        const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = threadIdx.x & 63;
 
         float v0[RPT], v1[RPT], v2[RPT];
         float M[RPT], S[RPT], T[RPT], N0[RPT], N1[RPT], N2[RPT], D[RPT], C0[RPT], C1[RPT], C2[RPT];
@@ -66,9 +70,10 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
         int loc[RPT];
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
-            loc[j] = item.ray0 + (int)threadIdx.x + j * BLOCK;
-            const int lc = loc[j] < hw ? loc[j] : hw - 1;
-            ray_dir(P, vr, e, kk, lc, v0[j], v1[j], v2[j]);
+            int row, col;
+            loc[j] = tile_local(vr, item.tile0 + j * NW + wave, lane, row, col);
+            const int lc = loc[j] >= 0 ? loc[j] : 0;  // a lane past the edge takes ray 0 (not written)
+            tile_ray_dir(P, vr, e, kk, lc, loc[j] >= 0 ? row : 0, loc[j] >= 0 ? col : 0, v0[j], v1[j], v2[j]);
             M[j] = -INFINITY;
             S[j] = T[j] = N0[j] = N1[j] = N2[j] = D[j] = C0[j] = C1[j] = C2[j] = 0.0f;
             at[j] = dt[j] = 0.0f;
@@ -145,7 +150,7 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
         const float o0 = (float)o[0], o1 = (float)o[1], o2 = (float)o[2];
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
-            if (loc[j] >= hw) continue;
+            if (loc[j] < 0) continue;
             write_ray<F>(P, O, item.view, vr.ray_off + loc[j], e, kk, o0, o1, o2, v0[j], v1[j], v2[j], M[j], S[j],
                          T[j], N0[j], N1[j], N2[j], C0[j], C1[j], C2[j], D[j], at[j], dt[j]);
         }
