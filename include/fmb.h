@@ -358,7 +358,7 @@ int fmb_split_gaussians(int32_t n, const float *means, const float *prec, const 
                         float *out_means, float *out_prec, float *out_weights, float *out_colors);
 
 /* Pin the launch configuration of a scene or batch (exactly one non-NULL) instead of
- * autotuning it: forward variant in [0, 4), backward variant in [0, 6) (see
+ * autotuning it: forward variant in [0, 4), backward variant in [0, 9) (see
  * fmb_get_config), persistent-grid multipliers 1 or 2.  Every variant computes the same
  * results to rounding; captured graphs are dropped.  Until this call or fmb_autotune, a job
  * takes forward variant 1 (512 rays per item), or 0 (256) when it has fewer rays than two
@@ -370,7 +370,10 @@ int fmb_set_config(fmb_scene *scene, fmb_batch *batch, int32_t fwd_variant, int3
  * host array out[8]: forward tile variant, rays per forward work item, backward variant,
  * rays per backward tile (staged in LDS for variants 0-2, which give each lane a Gaussian;
  * held by the block's lanes for variants 3-5, which give each lane rays as the forward pass
- * does and sum each Gaussian's terms over the wave per tile), forward and backward
+ * does and sum each Gaussian's terms over the wave per tile; the rays of an item, 8 or 16 tiles
+ * of 8 x 8 pixels, for variants 6-8 (8: blocks of 512 threads), which give each lane a ray of a tile and each wave a
+ * Gaussian at a time -- they take no normal or colour cotangent, and calls with one run variant
+ * 2), forward and backward
  * persistent-grid multipliers, and the forward and backward work-item counts (0 until the
  * first call built them). */
 int fmb_get_config(const fmb_scene *scene, const fmb_batch *batch, int32_t *out);

@@ -28,6 +28,7 @@ int fwd_variant_rays(int v);
 int num_bwd_variants();
 int bwd_variant_rt(int v);
 int bwd_variant_ray_tile(int v);
+int bwd_variant_tiles(int v);
 int block_size();
 hipError_t launch_fwd(int variant, int flags, int grid, hipStream_t st, const Params &P, const FwdOut &O,
                       const FwdItem *items, int n, const int *order, int *counter);
@@ -412,10 +413,16 @@ struct Job {
         const int rec = colour ? kPartialColor : kPartial;
         const int RT = bwd_variant_rt(variant);
         const int ray_tile = comp ? 0 : bwd_variant_ray_tile(variant);
+        const int tiles = comp ? 0 : bwd_variant_tiles(variant);  // tiled kernel: ray tiles per item
         const int B = block_size();
         std::vector<int> gcs(S), sls(S), spans(S), min_span(S);
         for (int s = 0; s < S; ++s) {
-            if (comp) {
+            if (tiles > 0) {
+                // tiled kernel: the whole scene per item, `tiles` ray tiles (ViewRec) per item
+                gcs[s] = scenes[s].n;
+                sls[s] = 1;
+                min_span[s] = spans[s] = tiles;
+            } else if (comp) {
                 // one chunk holds the whole scene; a step of the block covers 4 * 64 / seg rays
                 gcs[s] = scenes[s].n;
                 sls[s] = 1;
@@ -436,7 +443,7 @@ struct Job {
         // Span of rays per item, chosen per scene only (so a scene is cut the same way alone
         // and inside a batch): about 256 rays per lane (16 steps when compositing), at most
         // 16384 and, where the scene is small, at least 2048 items.
-        for (int s = 0; s < S; ++s) {
+        for (int s = 0; s < S && tiles == 0; ++s) {
             const int chunks = (scenes[s].n + gcs[s] - 1) / gcs[s];
             auto count_items = [&](int span) {
                 int64_t c = 0;
@@ -464,8 +471,10 @@ struct Job {
                 t.gc = std::min(gc, n - g0);
                 tasks_item_begin.push_back((int)items.size());
                 for (int k = scenes[s].view_off; k < scenes[s].view_off + scenes[s].n_views; ++k) {
+                    // ray0 and span count rays, or for the tiled kernel ray tiles
                     const int hw = views[k].h * views[k].w;
-                    for (int r0 = 0; r0 < hw; r0 += span) {
+                    const int lim = tiles > 0 ? views[k].tiles : hw;
+                    for (int r0 = 0; r0 < lim; r0 += span) {
                         BwdItem it{};
                         it.view = k;
                         it.ray0 = r0;
@@ -479,7 +488,8 @@ struct Job {
                         it.seq = (int)items.size();
                         poff += (size_t)gc * rec;
                         items.push_back(it);
-                        cost.push_back((double)t.gc * std::min(span, hw - r0));
+                        cost.push_back((double)t.gc * (tiles > 0 ? std::min<int64_t>(64LL * span, hw - 64LL * r0)
+                                                                 : std::min(span, hw - r0)));
                     }
                 }
                 tasks_item_end.push_back((int)items.size());
@@ -637,17 +647,24 @@ struct Job {
         return FMB_OK;
     }
 
-    int grid_bwd(int flags, int &grid)
+    int grid_bwd(int variant, int flags, int &grid)
     {
-        const int key = bwd_variant * 16 + (flags | kFlagPer);
+        const int key = variant * 16 + (flags | kFlagPer);
         auto it = occ_b.find(key);
         if (it == occ_b.end()) {
             int o = 0;
-            HIPCHK(occupancy_bwd(bwd_variant, flags | kFlagPer, &o));
+            HIPCHK(occupancy_bwd(variant, flags | kFlagPer, &o));
             it = occ_b.emplace(key, std::max(1, o)).first;
         }
         grid = std::max(1, std::min(n_bitems, persist_mult[1] * it->second * n_cu));
         return FMB_OK;
+    }
+
+    // The backward variant a call runs: the tiled variants take no normal or colour cotangent, so
+    // such calls run the Gaussian-lane variant 2 instead.
+    int bwd_run_variant(const BwdIn &I) const
+    {
+        return bwd_variant_tiles(bwd_variant) > 0 && (I.g_normal || I.g_color) ? 2 : bwd_variant;
     }
 
     static int fwd_flags(const FwdOut &O, bool persist)
@@ -700,7 +717,8 @@ struct Job {
         CHECK_ARG(G.means && G.prec && G.weights && G.betas, "gradient outputs are required");
         CHECK_ARG(!I.g_flow || has_flow, "flow cotangent given but the cameras have no second pose");
         CHECK_ARG(!I.g_color || (prm.colors && I.color), "colour cotangent needs colours and the colour output");
-        int rc = build_bwd(bwd_variant, I.g_color != nullptr);
+        const int bv = bwd_run_variant(I);
+        int rc = build_bwd(bv, I.g_color != nullptr);
         if (rc) return rc;
         if (model == FMB_MODEL_COMPOSITE) {
             TimedSpan tb(st, 1);
@@ -711,11 +729,11 @@ struct Job {
             const int flags = bwd_flags(I, persist);
             int grid = n_bitems;
             if (persist) {
-                if ((rc = grid_bwd(flags, grid))) return rc;
+                if ((rc = grid_bwd(bv, flags, grid))) return rc;
                 HIPCHK(launch_fill(d_counter.as<int>() + 1, 1, 0, st));
             }
             TimedSpan tb(st, 1);
-            HIPCHK(launch_bwd(bwd_variant, flags, grid, st, prm, I, d_bitems.as<BwdItem>(), n_bitems,
+            HIPCHK(launch_bwd(bv, flags, grid, st, prm, I, d_bitems.as<BwdItem>(), n_bitems,
                               persist ? d_border.as<int>() : nullptr, persist ? d_counter.as<int>() + 1 : nullptr,
                               d_partial.as<float>(), d_bpart.as<float>()));
             tb.stop();
@@ -740,8 +758,9 @@ struct Job {
         CHECK_ARG(!I.g_flow || has_flow, "flow cotangent given but the cameras have no second pose");
         CHECK_ARG(!I.g_color || (prm.colors && I.color), "colour cotangent needs colours and the colour output");
         const bool colour = I.g_color != nullptr;
-        if (na_plan.key != bwd_key(bwd_variant, colour)) {
-            int rc = plan_bwd(bwd_variant, colour, na_plan);
+        const int bv = bwd_run_variant(I);
+        if (na_plan.key != bwd_key(bv, colour)) {
+            int rc = plan_bwd(bv, colour, na_plan);
             if (rc) return rc;
         }
         const BwdPlan &pl = na_plan;
@@ -785,7 +804,7 @@ struct Job {
             tb.stop();
         } else {
             TimedSpan tb(st, 1);
-            HIPCHK(launch_bwd(bwd_variant, bwd_flags(I, false), n_items, st, prm, I, items, n_items, nullptr, nullptr,
+            HIPCHK(launch_bwd(bv, bwd_flags(I, false), n_items, st, prm, I, items, n_items, nullptr, nullptr,
                               part, bpart));
             tb.stop();
         }
@@ -1181,12 +1200,12 @@ int fmb_batch_capture(fmb_batch *b, float *depth, float *alpha, float *normal, f
     const BwdIn I{g_depth, g_alpha, g_normal, g_flow, g_color, depth, color, stash};
     const Grads G{g_means, g_prec, g_weights, g_colors, g_betas};
     // item lists and occupancy are prepared outside the capture (they use synchronous copies)
-    int rc = j.build_bwd(j.bwd_variant, g_color != nullptr);
+    int rc = j.build_bwd(j.bwd_run_variant(I), g_color != nullptr);
     if (j.model == FMB_MODEL_BLEND) {
         int gdummy = 0;
         if (!rc) rc = j.build_fwd(j.fwd_variant);
         if (!rc) rc = j.grid_fwd(Job::fwd_flags(O, true), gdummy);
-        if (!rc) rc = j.grid_bwd(Job::bwd_flags(I, true), gdummy);
+        if (!rc) rc = j.grid_bwd(j.bwd_run_variant(I), Job::bwd_flags(I, true), gdummy);
     }
     if (rc) return rc;
     j.drop_graphs();
@@ -1287,7 +1306,9 @@ int fmb_get_config(const fmb_scene *s, const fmb_batch *b, int32_t *out)
     out[0] = j.fwd_variant;
     out[1] = fwd_variant_rays(j.fwd_variant);
     out[2] = j.bwd_variant;
-    out[3] = bwd_variant_rt(j.bwd_variant) > 0 ? bwd_variant_rt(j.bwd_variant) : bwd_variant_ray_tile(j.bwd_variant);
+    out[3] = bwd_variant_rt(j.bwd_variant) > 0 ? bwd_variant_rt(j.bwd_variant)
+             : bwd_variant_tiles(j.bwd_variant) > 0 ? 64 * bwd_variant_tiles(j.bwd_variant)
+                                                    : bwd_variant_ray_tile(j.bwd_variant);
     out[4] = j.persist_mult[0];
     out[5] = j.persist_mult[1];
     // item counts of the lists built for the configuration in use (0 until built)

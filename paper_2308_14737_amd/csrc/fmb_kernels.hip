@@ -556,6 +556,165 @@ __global__ __launch_bounds__(BLOCK) void bwdr_kernel(Params P, BwdIn I, const Bw
 }
 
 // ------------------------------------------------------------------------------------
+// Backward, tiled ray-lane layout (no normal or colour cotangent): an item is T ray tiles of
+// one view (8 x 8 pixels, see ViewRec) against every Gaussian of its scene.  The item's rays
+// are staged in LDS with their adjoint prologue; each wave takes every NW-th Gaussian and walks
+// the T tiles with a lane per ray, so a lane sums that Gaussian's terms over T rays before one
+// scattered reduction over the wave.  A tile on which the Gaussian's blend weight is exactly
+// zero on every ray takes only the density term of alpha, and one whose density is zero too
+// adds nothing -- both decided uniformly over the wave (on the 16-scene batch about 58 % and
+// 34 % of (tile, Gaussian) pairs).
+// ------------------------------------------------------------------------------------
+
+// Sum over the wave of 16 values, scattered: halving exchanges 32, 16, 8 and 4 lanes apart
+// (each lane keeps half of its values and adds its partner's copy of that half), then a sum
+// over groups of 4 lanes.  Lane l ends with the total of value wave16_index(l); the order of
+// the additions is fixed.
+__device__ __forceinline__ int wave16_index(int lane)
+{
+    return ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1);
+}
+
+__device__ __forceinline__ float wave_sum16(const float x[16], int lane)
+{
+    float y[8], z[4], u[2];
+    bool up = (lane & 32) != 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) y[i] = (up ? x[i + 8] : x[i]) + __shfl_xor(up ? x[i] : x[i + 8], 32, 64);
+    up = (lane & 16) != 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) z[i] = (up ? y[i + 4] : y[i]) + __shfl_xor(up ? y[i] : y[i + 4], 16, 64);
+    up = (lane & 8) != 0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) u[i] = (up ? z[i + 2] : z[i]) + __shfl_xor(up ? z[i] : z[i + 2], 8, 64);
+    up = (lane & 4) != 0;
+    float s = (up ? u[1] : u[0]) + __shfl_xor(up ? u[0] : u[1], 4, 64);
+    s += __shfl_xor(s, 2, 64);
+    s += __shfl_xor(s, 1, 64);
+    return s;
+}
+
+template <int BLOCK, int T, int TG, int F>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void bwdt_kernel(
+    Params P, BwdIn I, const BwdItem *__restrict__ items, int n_items, const int *__restrict__ order,
+    int *__restrict__ counter, float *__restrict__ partial, float *__restrict__ beta_partial)
+{
+    static_assert((F & (kNrm | kCol)) == 0, "the tiled backward takes no normal or colour cotangent");
+    constexpr bool PERSIST = (F & kPer) != 0;
+    constexpr int NW = BLOCK / 64;
+    constexpr int RAYS = 64 * T;
+    __shared__ float4 rays[2 * RAYS];         // per ray: (v, M2 + log2 S), (tf_bar, D_bar, dc, t_f)
+    __shared__ float4 ents[4 * TG];           // the Gaussian tile's entries
+    __shared__ float rec[kOffsetAcc * TG];    // (H, Bv, L) of each Gaussian of the tile
+    __shared__ float bsum[2 * NW];
+    __shared__ int s_item;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    int pos = blockIdx.x;
+    for (;;) {
+        if (PERSIST) {
+            __syncthreads();
+            if (tid == 0) s_item = atomicAdd(counter, 1);
+            __syncthreads();
+            pos = __builtin_amdgcn_readfirstlane(s_item);  // block-uniform: keep the item in SGPRs
+        }
+        if (pos >= n_items) break;
+        const int it = order ? ld_uniform(order + pos) : pos;
+        const BwdItem item = ld_uniform(items + it);
+        const ViewRec vr = ld_uniform(P.views + item.view);
+        const SceneRec sr = ld_uniform(P.scenes + vr.scene);
+        const CamRec cam = cam_of(P, item.view);
+        const float *e = cam.e, *kk = cam.k;
+        double o[3];
+        cam_centre(e, o);
+        const float o0 = (float)o[0], o1 = (float)o[1], o2 = (float)o[2];
+        const Blend bl = blend_of(P, vr.scene);
+        const int nt = min(T, vr.tiles - item.ray0);  // the item's tiles: ray0 is its first tile
+
+        __syncthreads();  // the previous item is done with the staged rays
+        for (int q = tid; q < RAYS; q += BLOCK) {
+            int row, col;
+            const int local = (q >> 6) < nt ? tile_local(vr, item.ray0 + (q >> 6), q & 63, row, col) : -1;
+            float4 pr[4];
+            ray_prologue<F>(P, I, item.view, vr, e, kk, o0, o1, o2, local >= 0 ? local : 0, local >= 0, bl.b1, bl.nc2,
+                            pr);
+            // the weight 2^(z2 - M2) / S as 2^(z2 - M2 - log2 S); a ray past the edge has M2 = inf, S = inf
+            rays[2 * q] = make_float4(pr[0].x, pr[0].y, pr[0].z, pr[0].w - __builtin_amdgcn_logf(pr[1].x));
+            rays[2 * q + 1] = make_float4(pr[1].y, pr[2].z, pr[3].w, pr[2].w);
+        }
+        float aB1 = 0.0f, aB2 = 0.0f;
+        for (int gb = 0; gb < sr.n; gb += TG) {
+            const int cnt = min(TG, sr.n - gb);
+            __syncthreads();  // staged rays visible; the previous tile's entries and sums are consumed
+            for (int q = tid; q < cnt; q += BLOCK) {
+                const int gi = sr.gauss_off + gb + q;
+                make_entry(P.means + 3 * gi, P.prec + 6 * gi, P.weights[gi], o, &ents[4 * q]);
+            }
+            __syncthreads();
+            for (int i = wave; i < cnt; i += NW) {
+                const Ent g = ent_from(ents[4 * i], ents[4 * i + 1], ents[4 * i + 2], ents[4 * i + 3]);
+                OffsetAcc acc;
+#pragma unroll 1
+                for (int t = 0; t < nt; ++t) {
+                    const float4 x0 = rays[2 * (64 * t + lane)], x1 = rays[2 * (64 * t + lane) + 1];
+                    Geo q;
+                    pair_geo_coarse(g, x0.x, x0.y, x0.z, bl.hm, bl.b1, bl.nc2, q);
+                    // log2 of the normalised weight, and the density term D_bar delta
+                    const float zr = fmaf(bl.b1, q.d2, fmaf(bl.nc2, q.t, -x0.w));
+                    // a density below 2^-150 rounds to zero in FP32: such a tile skips the exponential
+                    const bool any_w = __any(zr >= kSkipLog2);
+                    const bool any_d = __any(q.d2 >= kSkipLog2 && x1.y != 0.0f);
+                    if (any_w || any_d) {
+                        const float dd = x1.y * exp2_(q.d2);
+                        // with zero weights on every ray of the tile only the density term remains:
+                        // t_bar = 0, d_bar = D_bar delta (the offset form then adds exactly that)
+                        float tb = 0.0f, db = dd;
+                        if (any_w) {
+                            // z_bar = wt (tf_bar t - kappa) with kappa = tf_bar t_f
+                            const float x = q.t - x1.w;
+                            const float wtf = exp2_(zr) * x1.x;
+                            const float zb = wtf * x;
+                            tb = fmaf(-bl.cb, zb, wtf);
+                            db = fmaf(bl.b1, zb, dd);
+                            aB1 = fmaf(zb, q.d2 - x1.z, aB1);
+                            aB2 = fmaf(zb, x, aB2);
+                        }
+                        // one accumulation for both cases, so the sums stay in their registers
+                        pair_adjoint_offset(q, x0.x, x0.y, x0.z, tb, db, acc);
+                    }
+                }
+                float v[16];
+                offset_acc_store(acc, v);
+                v[13] = v[14] = v[15] = 0.0f;
+                const float tot = wave_sum16(v, lane);
+                const int idx = wave16_index(lane);
+                if ((lane & 3) == 0 && idx < kOffsetAcc) rec[kOffsetAcc * i + idx] = tot;
+            }
+            __syncthreads();
+            for (int q = tid; q < cnt; q += BLOCK) {
+                const int gg = sr.gauss_off + gb + q;
+                write_partial_offset(partial + item.poff + kPartial * (gb + q), rec + kOffsetAcc * q, kPartial,
+                                     P.prec + 6 * gg, P.means + 3 * gg, o);
+            }
+        }
+        // betas: lanes summed over the wave, then the waves in order
+        aB1 = wave_sum(aB1);
+        aB2 = wave_sum(aB2);
+        if (lane == 0) {
+            bsum[2 * wave] = aB1;
+            bsum[2 * wave + 1] = aB2;
+        }
+        __syncthreads();
+        if (tid < 2) {
+            float sb = 0.0f;
+            for (int w = 0; w < NW; ++w) sb += bsum[2 * w + tid];
+            beta_partial[2 * item.seq + tid] = sb;
+        }
+        if (!PERSIST) break;
+    }
+}
+
+// ------------------------------------------------------------------------------------
 // Finalize, in two deterministic stages.
 //   stage 1: each group of <= kGroupItems consecutive items of a chunk is summed in item
 //            order in FP64 (all values of the chunk's partial record, and the betas);
@@ -882,6 +1041,13 @@ struct BwdRayVariant {
 static const BwdRayVariant kBwdRay[] = {{2, 64}, {4, 64}, {4, 128}};
 constexpr int kNumBwdGauss = (int)(sizeof kBwdRT / sizeof kBwdRT[0]);
 constexpr int kNumBwdRay = (int)(sizeof kBwdRay / sizeof kBwdRay[0]);
+// Variants 6-8: the tiled ray-lane kernel with T ray tiles per item (Gaussians staged 64 at a time);
+// without normal or colour cotangents only (the host runs variant 2 for those).
+static const int kBwdTiles[] = {8, 16, 16};
+// threads per block of the tiled variants (variant 8: eight waves share an item's 16 staged tiles)
+static const int kBwdTiledBlock[] = {256, 256, 512};
+constexpr int kNumBwdTiled = (int)(sizeof kBwdTiles / sizeof kBwdTiles[0]);
+constexpr int kBwdTiledFirst = kNumBwdGauss + kNumBwdRay;
 
 // F dispatch: calls body<F>() for the runtime flag set f (0..15).
 #define FMB_DISPATCH_F(f, CALL)                                                                            \
@@ -931,9 +1097,30 @@ static hipError_t launch_bwd_v(int f, int grid, hipStream_t st, const Params &P,
     return hipGetLastError();
 }
 
+template <int BLK, int T>
+static hipError_t launch_bwdt_v(int f, int grid, hipStream_t st, const Params &P, const BwdIn &I,
+                                const BwdItem *items, int n, const int *order, int *counter, float *partial,
+                                float *bpart)
+{
+#define FMB_BWDT_CALL(F)                                                                                   \
+    hipLaunchKernelGGL((bwdt_kernel<BLK, T, 64, F>), dim3(grid), dim3(BLK), 0, st, P, I, items, n, order,   \
+                       counter, partial, bpart)
+    switch (f) {
+    case 0: FMB_BWDT_CALL(0); break;
+    case kFlw: FMB_BWDT_CALL(kFlw); break;
+    case kPer: FMB_BWDT_CALL(kPer); break;
+    case kFlw | kPer: FMB_BWDT_CALL(kFlw | kPer); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef FMB_BWDT_CALL
+    return hipGetLastError();
+}
+
 int num_fwd_variants() { return (int)(sizeof kFwdVariants / sizeof kFwdVariants[0]); }
 int fwd_variant_rays(int v) { return kBlock * kFwdVariants[v].rpt; }
-int num_bwd_variants() { return kNumBwdGauss + kNumBwdRay; }
+int num_bwd_variants() { return kNumBwdGauss + kNumBwdRay + kNumBwdTiled; }
+// Tiled variants 6-8: ray tiles per item (0 for the others); they take no normal or colour cotangent.
+int bwd_variant_tiles(int v) { return v >= kBwdTiledFirst && v < num_bwd_variants() ? kBwdTiles[v - kBwdTiledFirst] : 0; }
 // Gaussian-lane variants: rays staged per pass; others: 0.
 int bwd_variant_rt(int v) { return v < kNumBwdGauss ? kBwdRT[v] : 0; }
 // Ray-lane variants 3-5: rays per block tile (BLOCK * RPT); others: 0.
@@ -963,6 +1150,9 @@ hipError_t launch_bwd(int variant, int flags, int grid, hipStream_t st, const Pa
     case 3: return launch_bwdr_v<2, 64>(flags, grid, st, P, I, items, n, order, counter, partial, bpart);
     case 4: return launch_bwdr_v<4, 64>(flags, grid, st, P, I, items, n, order, counter, partial, bpart);
     case 5: return launch_bwdr_v<4, 128>(flags, grid, st, P, I, items, n, order, counter, partial, bpart);
+    case 6: return launch_bwdt_v<256, 8>(flags, grid, st, P, I, items, n, order, counter, partial, bpart);
+    case 7: return launch_bwdt_v<256, 16>(flags, grid, st, P, I, items, n, order, counter, partial, bpart);
+    case 8: return launch_bwdt_v<512, 16>(flags, grid, st, P, I, items, n, order, counter, partial, bpart);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1066,10 +1256,15 @@ hipError_t occupancy_bwd(int variant, int flags, int *blocks_per_cu)
     case 3: FMB_OCC_V(2, 64)
     case 4: FMB_OCC_V(4, 64)
     case 5: FMB_OCC_V(4, 128)
-    default: return hipErrorInvalidValue;
+    default: break;
     }
 #undef FMB_OCC_V
 #undef FMB_OCC_F
+    const bool fl = (flags & kFlw) != 0;
+    auto occb = [&](auto kernel, int blk) { return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kernel, blk, 0); };
+    if (variant == 6) return fl ? occb(bwdt_kernel<256, 8, 64, kFlw | kPer>, 256) : occb(bwdt_kernel<256, 8, 64, kPer>, 256);
+    if (variant == 7) return fl ? occb(bwdt_kernel<256, 16, 64, kFlw | kPer>, 256) : occb(bwdt_kernel<256, 16, 64, kPer>, 256);
+    if (variant == 8) return fl ? occb(bwdt_kernel<512, 16, 64, kFlw | kPer>, 512) : occb(bwdt_kernel<512, 16, 64, kPer>, 512);
     return hipErrorInvalidValue;
 }
 

@@ -63,7 +63,8 @@ def test_batch_equals_plain_bitwise(fmb, batch16):
         r0, r1 = b.ray_off[i], b.ray_off[i + 1]
         g0, g1 = b.gauss_off[i], b.gauss_off[i + 1]
         o = scene.render(normals=True)
-        gi = scene.backward(o, cot["depth"][r0:r1], cot["alpha"][r0:r1], cot["normal"][r0:r1])
+        gi = scene.backward(o, cot["depth"][r0:r1], cot["alpha"][r0:r1],
+                            None if cot["normal"] is None else cot["normal"][r0:r1])
         torch.cuda.synchronize()
         for k in ("depth", "alpha", "normal", "stash"):
             assert torch.equal(o[k], outs[k][r0:r1]), (i, k)
@@ -209,15 +210,16 @@ def test_whole_step_single_graph(fmb, batch16):
         _say(f"[step-graph] replay {rep} matches eager")
 
 
-@pytest.mark.parametrize("variant", [3, 5])
+@pytest.mark.parametrize("variant", [3, 5, 6, 7, 8])
 def test_ray_lane_batch_bitwise(fmb, batch16, variant):
     """The ray-lane backward kernels, batched and persistent, equal per-scene plain launches of
-    the same variant bit for bit (items are cut per scene)."""
+    the same variant bit for bit (items are cut per scene); the tiled variants 6-7 without a
+    normal cotangent (the only case they take)."""
     w, b, params = batch16
     fmb.set_launch_config(batch=b, bwd_variant=variant)
     _say(f"[ray-lane] batch16 bwd variant {variant}")
     outs = b.forward(b.alloc_outputs(normals=True))
-    cot = _cotangents(b, 23)
+    cot = _cotangents(b, 23, normals=variant < 6)
     grads = b.backward(outs, cot, b.alloc_grads())
     torch.cuda.synchronize()
     means, prec, weights, betas = params  # the batch's current parameters (other tests update them)
@@ -229,7 +231,8 @@ def test_ray_lane_batch_bitwise(fmb, batch16, variant):
                           fmb.Cameras.from_numpy(cams.w2c, cams.intr, cams.hw, cams.w2c_b, cams.intr_b, device=DEV))
         fmb.set_launch_config(scene=scene, bwd_variant=variant)
         o = scene.render(normals=True)
-        gi = scene.backward(o, cot["depth"][r0:r1], cot["alpha"][r0:r1], cot["normal"][r0:r1])
+        gi = scene.backward(o, cot["depth"][r0:r1], cot["alpha"][r0:r1],
+                            None if cot["normal"] is None else cot["normal"][r0:r1])
         torch.cuda.synchronize()
         for k in ("means", "prec", "weights"):
             assert torch.equal(gi[k], grads[k][g0:g1]), (i, k)

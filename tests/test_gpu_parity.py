@@ -598,7 +598,7 @@ VARIANT_CASES = [
 ]
 
 
-@pytest.mark.parametrize("variant", range(6))
+@pytest.mark.parametrize("variant", range(9))
 @pytest.mark.parametrize("label,n,views", VARIANT_CASES, ids=[c[0] for c in VARIANT_CASES])
 def test_backward_variants(fmb, variant, label, n, views):
     """Every backward variant (Gaussian-lane 0-2, ray-lane 3-5) against the oracle, with normal,
@@ -630,7 +630,7 @@ def test_backward_variants(fmb, variant, label, n, views):
     assert_grads(eg, f"{label} variant {variant}")
 
 
-@pytest.mark.parametrize("variant", range(6))
+@pytest.mark.parametrize("variant", range(9))
 @pytest.mark.parametrize("label,n,views", VARIANT_CASES, ids=[c[0] for c in VARIANT_CASES])
 def test_backward_variants_without_normals(fmb, variant, label, n, views):
     """Every backward variant (Gaussian-lane 0-2, ray-lane 3-5) takes the (A, Bv, L) form of the
@@ -732,7 +732,7 @@ def loss_step(fmb, request):
     return (name,) + _loss_step_setup(fmb, name, k, seed, two_way)
 
 
-@pytest.mark.parametrize("variant", list(range(6)) + ["tuned"])
+@pytest.mark.parametrize("variant", list(range(9)) + ["tuned"])
 def test_loss_step_backward_variants(fmb, loss_step, variant):
     name, scene, outs, cot, gref = loss_step
     grads = scene.backward(outs, cot["depth"], cot["alpha"], None, cot["flow"])
