@@ -60,9 +60,18 @@ def kernel_source_sha256():
     return h.hexdigest()
 
 
-def _profile_values(name):
+def bwd_kernel_name(variant):
+    """The backward kernel a backward tile variant launches (the variant tables of the library)."""
+    if variant < 3:
+        return "bwd_kernel (persistent, Gaussian lanes)"
+    if variant < 6:
+        return "bwdr_kernel (persistent, ray lanes)"
+    return "bwdt_kernel (persistent, 8x8 ray tiles per wave)"
+
+
+def _profile_values(name, bwd_variant):
     """key: value lines of a committed rocprofv3 summary under profiles/, or {} if the kernel
-    sources have changed since it was taken."""
+    sources have changed since it was taken or it covers another backward variant."""
     path = os.path.join(ROOT, "profiles", name)
     try:
         vals = {}
@@ -71,26 +80,27 @@ def _profile_values(name):
                 if ":" in line and not line.startswith(("#", "|", " ")):
                     k, v = line.split(":", 1)
                     vals[k.strip()] = v.strip()
-        if vals.get("kernel_source_sha256") != kernel_source_sha256():
+        if vals.get("kernel_source_sha256") != kernel_source_sha256() or \
+                vals.get("bwd_variant") != str(bwd_variant):
             return {}
         return vals
     except OSError:
         return {}
 
 
-def measured_traffic():
+def measured_traffic(bwd_variant):
     """HBM bytes per launch of the persistent backward kernel, from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary, if the kernel source has not changed since it was taken."""
+    FETCH_SIZE / WRITE_SIZE summary, if it was taken of this variant's kernel as it is now."""
     try:
-        return float(_profile_values("batch16_bwd_traffic.md")["traffic_bytes_per_launch"])
+        return float(_profile_values("batch16_bwd_traffic.md", bwd_variant)["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
 
 
-def executed(pairs, bwd_ms):
+def executed(pairs, bwd_ms, bwd_variant):
     """FP32 arithmetic the backward kernel executes per pair (rocprofv3 counters, including the
     recomputed pair terms), and the resulting rate, if the committed counters are current."""
-    vals = _profile_values("batch16_valu.md")
+    vals = _profile_values("batch16_valu.md", bwd_variant)
     try:
         fl = float(vals["bwd_executed_flops_per_pair"])
     except (KeyError, ValueError):
@@ -518,7 +528,7 @@ def main():
 
     ms_step = ms_graph if ms_graph is not None else ms_eager
     value = pairs / (ms_step * 1e-3)
-    # dominant kernel: the persistent backward (adjoint with recompute)
+    # dominant kernel: the persistent backward (adjoint with recompute) of the tuned variant
     flops_bwd_launch = pairs * FLOPS_ADJ_PLAIN
     achieved = flops_bwd_launch / (bwd_ms * 1e-3)
     step_flops = pairs * (FLOPS_FWD_NORMALS + FLOPS_ADJ_PLAIN)
@@ -549,14 +559,15 @@ def main():
         "composite": comp,
         "other_rows": extras,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": measured_traffic(),
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
+                     "traffic": measured_traffic(launch["bwd_variant"]),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
-                     "kernel": "bwd_kernel (persistent)", "flops_per_pair": FLOPS_ADJ_PLAIN,
+                     "kernel": bwd_kernel_name(launch["bwd_variant"]), "flops_per_pair": FLOPS_ADJ_PLAIN,
                      "algorithmic_flops_per_pair": {"forward_normals": FLOPS_FWD_NORMALS,
                                                     "forward_plain": FLOPS_FWD_PLAIN,
                                                     "adjoint_normals": FLOPS_ADJ_NORMALS,
                                                     "adjoint_plain": FLOPS_ADJ_PLAIN},
-                     **executed(pairs, bwd_ms)},
+                     **executed(pairs, bwd_ms, launch["bwd_variant"])},
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

@@ -362,7 +362,8 @@ int fmb_split_gaussians(int32_t n, const float *means, const float *prec, const 
  * fmb_get_config), persistent-grid multipliers 1 or 2.  Every variant computes the same
  * results to rounding; captured graphs are dropped.  Until this call or fmb_autotune, a job
  * takes forward variant 1 (512 rays per item), or 0 (256) when it has fewer rays than two
- * 512-ray items per compute unit, and backward variant 2.  Errors: FMB_ERR_INVALID_ARG. */
+ * 512-ray items per compute unit, and backward variant 8 (variant 2 for calls with a normal or
+ * colour cotangent).  Errors: FMB_ERR_INVALID_ARG. */
 int fmb_set_config(fmb_scene *scene, fmb_batch *batch, int32_t fwd_variant, int32_t bwd_variant,
                    int32_t fwd_grid_mult, int32_t bwd_grid_mult);
 
@@ -371,11 +372,10 @@ int fmb_set_config(fmb_scene *scene, fmb_batch *batch, int32_t fwd_variant, int3
  * rays per backward tile (staged in LDS for variants 0-2, which give each lane a Gaussian;
  * held by the block's lanes for variants 3-5, which give each lane rays as the forward pass
  * does and sum each Gaussian's terms over the wave per tile; the rays of an item, 8 or 16 tiles
- * of 8 x 8 pixels, for variants 6-8 (8: blocks of 512 threads), which give each lane a ray of a tile and each wave a
- * Gaussian at a time -- they take no normal or colour cotangent, and calls with one run variant
- * 2), forward and backward
- * persistent-grid multipliers, and the forward and backward work-item counts (0 until the
- * first call built them). */
+ * of 8 x 8 pixels, for variants 6-8 (8: blocks of 512 threads), which give each lane a ray of
+ * a tile and each wave a Gaussian at a time -- they take no normal or colour cotangent, and
+ * calls with one run variant 2), forward and backward persistent-grid multipliers, and the
+ * forward and backward work-item counts (0 until the first call built them). */
 int fmb_get_config(const fmb_scene *scene, const fmb_batch *batch, int32_t *out);
 
 /* Check the scene's parameters on the device: writes to *bad_host a bit mask of

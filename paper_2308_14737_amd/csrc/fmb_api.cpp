@@ -247,7 +247,7 @@ struct Job {
     bool launch_fixed = false;  // variants set by the caller or the autotuner
     DevBuf d_fitems, d_forder;
     // backward work
-    int bwd_variant = 2, bwd_built = -1, n_bitems = 0, n_tasks = 0, n_groups = 0;
+    int bwd_variant = 8, bwd_built = -1, n_bitems = 0, n_tasks = 0, n_groups = 0;
     int fin_max_gc = 1, fin_max_nval = 1;  // largest chunk and first-stage record (finalize grid)
     DevBuf d_bitems, d_border, d_tasks, d_groups, d_partial, d_bpart, d_stage, d_stage_beta;
     size_t partial_floats = 0;

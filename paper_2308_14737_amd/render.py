@@ -434,7 +434,7 @@ class Batch:
 
 
 def set_launch_config(scene: Optional["Scene"] = None, batch: Optional["Batch"] = None, fwd_variant: int = 3,
-                      bwd_variant: int = 2, fwd_grid_mult: int = 1, bwd_grid_mult: int = 1):
+                      bwd_variant: int = 8, fwd_grid_mult: int = 1, bwd_grid_mult: int = 1):
     """Pin the tile variants and persistent-grid multipliers (see launch_config)."""
     _lib.call("fmb_set_config", scene.handle if scene is not None else None,
               batch._h if batch is not None else None, int(fwd_variant), int(bwd_variant), int(fwd_grid_mult),
