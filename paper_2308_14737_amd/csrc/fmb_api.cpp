@@ -45,14 +45,14 @@ hipError_t launch_loss(int p, const float *depth, const float *alpha, const floa
                        float w_depth, float w_flow, int flow_norm, int flow_cols, float w_color, float *g_depth,
                        float *g_alpha, float *g_flow, float *g_color, float *block_loss, hipStream_t st);
 hipError_t launch_validate(const Params &P, int n_total, int n_scenes, int *flags, hipStream_t st);
-hipError_t launch_fwdc(int km, int flags, int n_items, hipStream_t st, const Params &P, const FwdOut &O,
+hipError_t launch_fwdc(int flags, int n_items, hipStream_t st, const Params &P, const FwdOut &O,
                        const BwdItem *items);
 hipError_t launch_stat(int n_items, int n_tasks, int max_gc, hipStream_t st, const Params &P, const float *loss,
                        const float *stash, const BwdItem *items, const StatTask *tasks, float *partial,
                        const int64_t *rays_per_scene, float *lbar);
-hipError_t launch_statc(int km, int n_items, hipStream_t st, const Params &P, const float *loss, const float *stash,
+hipError_t launch_statc(int n_items, hipStream_t st, const Params &P, const float *loss, const float *stash,
                         const BwdItem *items, float *partial);
-hipError_t launch_bwdc(int km, int flags, int n_items, hipStream_t st, const Params &P, const BwdIn &I,
+hipError_t launch_bwdc(int flags, int n_items, hipStream_t st, const Params &P, const BwdIn &I,
                        const BwdItem *items, float *partial, float *beta_partial);
 hipError_t occupancy_fwd(int variant, int flags, int *blocks_per_cu);
 hipError_t occupancy_bwd(int variant, int flags, int *blocks_per_cu);
@@ -339,27 +339,6 @@ struct Job {
         slots = block / gc;
     }
 
-    // Lanes' Gaussians per ray slot of the compositing kernels (1, 2 or 4) for this job.
-    int comp_km() const
-    {
-        int km = 1;
-        for (const auto &sc : scenes) {
-            const int k = (sc.n + comp_seg(sc.n) - 1) / comp_seg(sc.n);
-            km = std::max(km, k <= 1 ? 1 : (k <= 2 ? 2 : 4));
-        }
-        return km;
-    }
-
-    // The compositing forward's Gaussians per lane: three (segments of the power of two >= n / 3
-    // lanes, fewer empty slots than two per lane) while every scene has at most 192 Gaussians.
-    // The adjoint keeps comp_km(): at three per lane it needs more than 128 VGPRs.
-    int comp_km_fwd() const
-    {
-        int mx = 0;
-        for (const auto &sc : scenes) mx = std::max(mx, sc.n);
-        return mx <= 3 * 64 ? 3 : comp_km();
-    }
-
     // Backward items (and, for the compositing model, the forward items too).  The key
     // records the model, the colour record size and the blend backward's variant.
     int bwd_key(int variant, bool colour) const
@@ -413,21 +392,16 @@ struct Job {
         const int rec = colour ? kPartialColor : kPartial;
         const int RT = bwd_variant_rt(variant);
         const int ray_tile = comp ? 0 : bwd_variant_ray_tile(variant);
-        const int tiles = comp ? 0 : bwd_variant_tiles(variant);  // tiled kernel: ray tiles per item
+        // ray tiles per item of the tiled kernels (the compositing kernels are tiled too)
+        const int tiles = comp ? kCompTiles : bwd_variant_tiles(variant);
         const int B = block_size();
         std::vector<int> gcs(S), sls(S), spans(S), min_span(S);
         for (int s = 0; s < S; ++s) {
             if (tiles > 0) {
-                // tiled kernel: the whole scene per item, `tiles` ray tiles (ViewRec) per item
+                // tiled kernels: the whole scene per item, `tiles` ray tiles (ViewRec) per item
                 gcs[s] = scenes[s].n;
                 sls[s] = 1;
                 min_span[s] = spans[s] = tiles;
-            } else if (comp) {
-                // one chunk holds the whole scene; a step of the block covers 4 * 64 / seg rays
-                gcs[s] = scenes[s].n;
-                sls[s] = 1;
-                min_span[s] = 4 * (64 / comp_seg(scenes[s].n));
-                spans[s] = 16 * min_span[s];
             } else if (ray_tile > 0) {
                 // ray-lane kernel: the whole scene per item, two ray tiles per item to start
                 gcs[s] = scenes[s].n;
@@ -441,8 +415,8 @@ struct Job {
             }
         }
         // Span of rays per item, chosen per scene only (so a scene is cut the same way alone
-        // and inside a batch): about 256 rays per lane (16 steps when compositing), at most
-        // 16384 and, where the scene is small, at least 2048 items.
+        // and inside a batch): about 256 rays per lane, at most 16384 and, where the scene is
+        // small, at least 2048 items.
         for (int s = 0; s < S && tiles == 0; ++s) {
             const int chunks = (scenes[s].n + gcs[s] - 1) / gcs[s];
             auto count_items = [&](int span) {
@@ -566,7 +540,7 @@ struct Job {
             const int n = scenes[s].n;
             int gc = n, sl = 1, span;
             if (comp) {
-                span = 16 * 4 * (64 / comp_seg(n));
+                span = kCompTiles;  // ray tiles (ViewRec) per item
             } else {
                 chunking(n, B, gc, sl);
                 span = 256 * sl;  // about 256 rays per lane
@@ -581,8 +555,9 @@ struct Job {
                 t.gc = std::min(gc, n - g0);
                 t.item_begin = (int)items.size();
                 for (int k = scenes[s].view_off; k < scenes[s].view_off + scenes[s].n_views; ++k) {
-                    const int hw = views[k].h * views[k].w;
-                    for (int r0 = 0; r0 < hw; r0 += span) {
+                    // ray0 and span count rays, or for the compositing kernel ray tiles
+                    const int lim = comp ? views[k].tiles : views[k].h * views[k].w;
+                    for (int r0 = 0; r0 < lim; r0 += span) {
                         BwdItem it{};
                         it.view = k;
                         it.ray0 = r0;
@@ -620,7 +595,7 @@ struct Job {
         int rc = build_stat();
         if (rc) return rc;
         if (model == FMB_MODEL_COMPOSITE) {
-            HIPCHK(launch_statc(comp_km(), n_sitems, st, prm, loss, stash, d_sitems.as<BwdItem>(),
+            HIPCHK(launch_statc(n_sitems, st, prm, loss, stash, d_sitems.as<BwdItem>(),
                                 d_spartial.as<float>()));
             HIPCHK(launch_stat(0, n_stasks, stat_max_gc, st, prm, loss, stash, d_sitems.as<BwdItem>(),
                                d_stasks.as<StatTask>(), d_spartial.as<float>(), d_srays.as<int64_t>(), lbar));
@@ -690,7 +665,7 @@ struct Job {
             int rc = (bwd_built == 1 || bwd_built == 3) ? FMB_OK : build_bwd(bwd_variant, prm.colors != nullptr);
             if (rc) return rc;
             TimedSpan ts(st, 0);
-            HIPCHK(launch_fwdc(comp_km_fwd(), fwd_flags(O, false), n_bitems, st, prm, O, d_bitems.as<BwdItem>()));
+            HIPCHK(launch_fwdc(fwd_flags(O, false), n_bitems, st, prm, O, d_bitems.as<BwdItem>()));
             ts.stop();
             return FMB_OK;
         }
@@ -722,7 +697,7 @@ struct Job {
         if (rc) return rc;
         if (model == FMB_MODEL_COMPOSITE) {
             TimedSpan tb(st, 1);
-            HIPCHK(launch_bwdc(comp_km(), bwd_flags(I, false), n_bitems, st, prm, I, d_bitems.as<BwdItem>(),
+            HIPCHK(launch_bwdc(bwd_flags(I, false), n_bitems, st, prm, I, d_bitems.as<BwdItem>(),
                                d_partial.as<float>(), d_bpart.as<float>()));
             tb.stop();
         } else {
@@ -800,7 +775,7 @@ struct Job {
         const int n_items = (int)pl.items.size();
         if (model == FMB_MODEL_COMPOSITE) {
             TimedSpan tb(st, 1);
-            HIPCHK(launch_bwdc(comp_km(), bwd_flags(I, false), n_items, st, prm, I, items, part, bpart));
+            HIPCHK(launch_bwdc(bwd_flags(I, false), n_items, st, prm, I, items, part, bpart));
             tb.stop();
         } else {
             TimedSpan tb(st, 1);
@@ -1011,9 +986,6 @@ int fmb_set_model(fmb_scene *s, fmb_batch *b, int32_t model)
     CHECK_ARG(model == FMB_MODEL_BLEND || model == FMB_MODEL_COMPOSITE, "model must be FMB_MODEL_BLEND or "
                                                                         "FMB_MODEL_COMPOSITE");
     Job &j = s ? s->job : b->job;
-    if (model == FMB_MODEL_COMPOSITE)
-        for (const auto &sc : j.scenes)
-            if (sc.n > kCompMaxN) return fail(FMB_ERR_SHAPE, "the compositing renderer takes at most 256 Gaussians per scene");
     if (model != j.model) {
         j.model = model;
         j.bwd_built = -1;

@@ -2,35 +2,55 @@
 // (alpha compositing, Keselman & Hebert, WACV 2024, Sec. 3.3, Eq. 9-10).
 //
 // Weights: w_i = T_i (1 - exp(-delta_i)), T_i = exp(-sum_j delta_j [t_j < t_i]), blended by
-// Eq. (3) for depth, normals and colour; alpha is Eq. (8) as in the two-parameter model.
+// Eq. (3) for depth, normals and colour; alpha is Eq. (8) as in the two-parameter model.  The
+// weights enter Eq. (3) as base-2 logarithms,
+//   log2 w_i = -log2(e) F_i + log2(1 - exp(-delta_i)),   F_i = sum_{t_j < t_i} delta_j,
+// normalised by their running maximum like the two-parameter weights, so rays far from every
+// Gaussian keep finite weights.  The strict inequality is taken literally: intersections at
+// equal depth do not attenuate one another.
 //
-// Layout: one ray per segment of `seg` consecutive lanes of a wave, seg the smallest power of
-// two >= N / 2 (at most 64; N / 3 in the forward at three Gaussians per lane, KM = 3); lane l
-// of the segment holds Gaussians l, l + seg, ... (ke <= KM of them: two up to N = 128, three
-// in the forward up to N = 192).  The segment writes its (t_i, delta_i) to LDS and every lane sums, for each of its
-// Gaussians, the densities of the Gaussians strictly in front of it: an O(N) loop of LDS
-// broadcasts per pair and no sort, with the strict inequality of Eq. (10) taken literally
-// (Gaussians at equal depth do not attenuate one another).  Segment sums (max, weights,
-// blended values) are butterflies over the segment's lanes.  A block of 256 lanes handles
-// 4 * 64 / seg rays per step and loops over the rays of its item.
+// Layout: one ray per lane, one 8 x 8 pixel tile (ViewRec's ray tiles) per wave, one wave per
+// block; an item is a run of consecutive tiles of one view, and the Gaussians are staged through
+// LDS in tiles of kCompTG entries (once per item when the scene fits one tile).
 //
-// Numerics: the weights enter Eq. (3) as base-2 logarithms,
-//   log2 w_i = -log2(e) sum_{t_j < t_i} delta_j + log2(1 - exp(-delta_i)),
-// shifted by their maximum over the ray, so rays far from every Gaussian keep finite weights;
-// log2(1 - exp(-delta)) = log2(delta) + log2(e) (-delta/2 + delta^2/24 - delta^4/2880) below
-// delta = 1/16 (truncation < 1e-12 relative), log2(1 - 2^(-delta log2 e)) above.
+// Front sums without a sort: F_i only needs the densities in front of t_i, and of those only the
+// significant ones (density above 2^sig, comp_sig_log2: the rest total below 2^-24, FP32's
+// rounding of T_i).  A lane keeps its ray's significant intersections, with their depths, in
+// registers and forms F_i as a sum of exact 0/1 steps over them: per pair the cost is the count of
+// significant intersections around the tile (about ten on the benchmark scenes), not N.  Slots are
+// filled in Gaussian order at positions uniform over the wave -- a lane for which the slot's
+// Gaussian is not significant leaves density 0 there -- so that filling a slot is a register move
+// and the step sums run a count uniform over the wave.
 //
-// Backward (per ray, same layout): with z_i = log w_i and z_bar_i = wt_i (tf_bar t_i +
-// Nb.n_i + Cb.c_i - kappa) the softmax adjoint, delta_j enters every z_i behind it, so
-//   d_bar_j = z_bar_j delta_j / expm1(delta_j) + delta_j (D_bar - sum_{t_j < t_i} z_bar_i),
-//   t_bar_j = wt_j tf_bar (the indicator is piecewise constant),
-// the second sum again an O(N) LDS loop; the rest of the per-pair adjoint is shared with the
-// two-parameter renderer.  Partial gradients per item go to the same deterministic finalize.
+// Depth windows: a pass fills at most kCompSlots slots.  When more Gaussians are significant for
+// the tile, a lane that meets one more than the slots hold records the nearest such depth, and the
+// pass covers only the depths in front of it: the lane's window [lo, hi).  The next pass starts at
+// hi, with the window's densities (and those at its lower edge, which do not attenuate one another)
+// added to the lane's base sum.  Every pair is blended in the window that holds its depth.  Almost
+// every tile of the benchmark scenes takes one window; a tile whose rays pass hundreds of Gaussians
+// takes several, so the renderer takes any N.
+//
+// Backward (same layout): with z_i = log w_i and z_bar_i = wt_i (lin_i - kappa) the softmax
+// adjoint (wt_i the normalised weight, lin_i the pair's share of the cotangents), delta_j enters
+// z_i of every pair behind it, so
+//   d_bar(log delta_j) = z_bar_j delta_j / expm1(delta_j) + delta_j (D_bar - B_j),
+//   B_j = sum_{t_i > t_j} z_bar_i,   t_bar_j = wt_j tf_bar,
+// and the rest is the two-parameter renderer's per-pair adjoint.  B_j is summed over the
+// significant intersections (one pass over the slots' Gaussians forms their z_bar), by the same
+// step sums; across windows the z_bar of the windows behind come from a first sweep.  The pairs
+// left out carry normalised weights below 2^-24 of the ray's largest, and delta_j B_j is itself
+// below 2^-24 of z_bar_j where every density of the ray is insignificant.  Each wave sums its pairs'
+// terms over its 64 rays for every Gaussian it touches (a fixed butterfly), adds them to the item's
+// record in LDS in tile order, and the records go to the deterministic two-stage finalize.
 #include "fmb_device.h"
 
 namespace fmb {
 
-constexpr int kCompBlock = 256;
+constexpr int kCompSlots = 32;  // significant intersections a lane holds per depth window
+constexpr int kCompTG = 128;    // Gaussians staged per LDS tile
+// Waves per SIMD the kernels are compiled for: the slots take 2 kCompSlots VGPRs (3 kCompSlots
+// in the backward); the forward fits three waves without spilling, the backward two.
+constexpr int kFwdcWaves = 3, kBwdcWaves = 2;
 
 // log2(1 - exp(-delta)) with log2(delta) = d2.
 __device__ __forceinline__ float log2_opacity(float delta, float d2)
@@ -49,343 +69,286 @@ __device__ __forceinline__ float opacity_slope(float delta)
     return delta < 0.0625f ? series : direct;
 }
 
-// Lane exchanges within groups of 4, 8 and 16 lanes (DPP): quad_perm [1,0,3,2] and [2,3,0,1],
-// and the mirror of each half-row (8 lanes) and row (16 lanes).  After the quad steps every
-// lane of a quad holds the same value, so the mirrors pair each group with its neighbour.
-template <int CTRL>
-__device__ __forceinline__ float dpp_(float x)
-{
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
-}
-
-// Sum (max) over the aligned group of `seg` lanes, left in every lane of the group.
-__device__ __forceinline__ float seg_sum(float x, int seg)
-{
-    if (seg > 1) x += dpp_<0xB1>(x);
-    if (seg > 2) x += dpp_<0x4E>(x);
-    if (seg > 4) x += dpp_<0x141>(x);
-    if (seg > 8) x += dpp_<0x140>(x);
-    if (seg > 16) x += __shfl_xor(x, 16, 64);
-    if (seg > 32) x += __shfl_xor(x, 32, 64);
-    return x;
-}
-
-// Sums of eight values over the aligned group of `seg` >= 8 lanes, scattered over its lanes:
-// three halving exchanges (each lane keeps half of its values and adds its partner's copy of
-// that half, lanes seg/2, seg/4, seg/8 apart), then a sum over the remaining groups of seg/8
-// lanes.  Lane l of the segment ends with the total of value seg8_index(l, seg) -- half the
-// exchanges of eight separate sums, and no DPP (which issues at half rate).
-__device__ __forceinline__ int seg8_index(int sl, int seg)
-{
-    return ((sl & (seg >> 1)) ? 4 : 0) + ((sl & (seg >> 2)) ? 2 : 0) + ((sl & (seg >> 3)) ? 1 : 0);
-}
-
-__device__ __forceinline__ float seg_sum8(const float x[8], int sl, int seg)
-{
-    float y[4], z[2];
-    int o = seg >> 1;
-    bool up = (sl & o) != 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) y[i] = (up ? x[i + 4] : x[i]) + __shfl_xor(up ? x[i] : x[i + 4], o, 64);
-    o >>= 1;
-    up = (sl & o) != 0;
-#pragma unroll
-    for (int i = 0; i < 2; ++i) z[i] = (up ? y[i + 2] : y[i]) + __shfl_xor(up ? y[i] : y[i + 2], o, 64);
-    o >>= 1;
-    up = (sl & o) != 0;
-    const float w = (up ? z[1] : z[0]) + __shfl_xor(up ? z[0] : z[1], o, 64);
-    return seg_sum(w, seg >> 3);
-}
-
-__device__ __forceinline__ float seg_max(float x, int seg)
-{
-    if (seg > 1) x = fmaxf(x, dpp_<0xB1>(x));
-    if (seg > 2) x = fmaxf(x, dpp_<0x4E>(x));
-    if (seg > 4) x = fmaxf(x, dpp_<0x141>(x));
-    if (seg > 8) x = fmaxf(x, dpp_<0x140>(x));
-    if (seg > 16) x = fmaxf(x, __shfl_xor(x, 16, 64));
-    if (seg > 32) x = fmaxf(x, __shfl_xor(x, 32, 64));
-    return x;
-}
-
-// Orders the LDS accesses of one wave around this point, for data that only lanes of the same
-// wave share (a segment's slots, a wave's epilogue records): the LDS performs one wave's
-// operations in program order, and the fence and barrier keep the compiler from moving them
-// across.  No block barrier, so the waves of a block do not wait for one another.
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Lane geometry of a scene with n Gaussians.
-struct CompLanes {
-    int seg, ke;        // lanes per ray, Gaussians per lane
-    int sl, sg, rpw;    // lane within the segment, segment within the wave, rays per wave
-    int sbase;          // first LDS slot of the segment
-};
-
-template <int KM>
-__device__ __forceinline__ CompLanes comp_lanes(int n)
-{
-    CompLanes c;
-    c.seg = comp_seg(n, KM == 3 ? 3 : 2);
-    c.ke = (n + c.seg - 1) / c.seg;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    c.sl = lane & (c.seg - 1);
-    c.sg = lane / c.seg;
-    c.rpw = 64 / c.seg;
-    c.sbase = (wave * 64 + c.sg * c.seg) * KM;
-    return c;
-}
-
-// Entries of the lane's Gaussians; a slot past the last Gaussian takes the last one's entry
-// (finite arithmetic, zero weight and density).
-template <int KM, bool COLOR>
-__device__ __forceinline__ void comp_entries(const Params &P, const SceneRec &sr, const CompLanes &c,
-                                             const double o[3], Ent g[KM], float4 cc[KM], bool gv[KM])
-{
-#pragma unroll
-    for (int k = 0; k < KM; ++k) {
-        gv[k] = false;
-        if (k < c.ke) {
-            const int j = k * c.seg + c.sl;
-            gv[k] = j < sr.n;
-            const int gg = sr.gauss_off + (gv[k] ? j : sr.n - 1);
-            float4 q[4];
-            make_entry(P.means + 3 * gg, P.prec + 6 * gg, P.weights[gg], o, q);
-            g[k] = ent_from(q[0], q[1], q[2], q[3]);
-            if (COLOR) cc[k] = colour_entry(P.colors + 3 * gg);
-        }
-    }
-}
-
-// Densities below this are left out of the front sums: with at most 256 Gaussians they change a
-// sum by less than 2^-22, so a log2 weight -log2(e) F + log2(1 - e^-delta) by less than
-// 3.5e-7 (FP32 rounding of the weight itself), while about three quarters of the pairs of a
-// typical ray have a density below it (the ray passes more than ~6 standard deviations away).
-constexpr float kCompMinDensity = 0x1p-30f;
-// Likewise, softmax adjoints z_bar_i of pairs whose normalised weight is below this are left out
-// of the adjoint's sums over the Gaussians behind: |z_bar_i| <= w_i |lin_i - kappa| while a ray's
-// largest term is at least (1/N) |lin - kappa|, so with N <= 256 a sum moves by less than
-// N^2 2^-40 < 6e-8 of the ray's scale; about three quarters of the pairs fall below it.
-constexpr float kCompMinWeight = 0x1p-40f;
-
-// Depths are compared in the slot loops as clamp((t_k - t_j) * 2^100, 0, 1) (one subtraction
-// with the clamp modifier on pre-scaled depths, then an FMA): 1 exactly when t_k > t_j, 0 when
-// t_k <= t_j, for every pair of depths below 2^27 in magnitude whose difference is at least
-// 2^-100, i.e. any two distinct depths this renderer meets.
+// Depths are kept and compared scaled by 2^100: clamp(b - a, 0, 1) of two scaled depths is 1
+// exactly when a < b and 0 when a >= b, for every pair of depths below 2^27 in magnitude whose
+// difference is at least 2^-100, i.e. any two distinct depths this renderer meets.
 constexpr float kDepthScale = 0x1p100f;
 
-// Writes the segment's pairs (t_j kDepthScale, x_j) with x_j != 0 (DENSITY: x_j > kCompMinDensity) to its
-// LDS slots, in Gaussian order, and (0, 0) to the rest of its seg * KM slots; returns the
-// largest such count over the wave's segments, the same in every lane.  Terms left out add
-// nothing (or below rounding) to the sums below, so the slot loops run that wave-uniform count
-// (a scalar loop) and skip the Gaussians that cannot contribute.  The zero fill and the packed
-// writes are LDS writes of one wave, which the LDS performs in program order.
-template <int KM, bool DENSITY>
-__device__ __forceinline__ int compact_slots(float2 *__restrict__ slots, const CompLanes &c, const Geo q[KM],
-                                             const float x[KM])
+__device__ __forceinline__ float before(float a, float b) { return __builtin_amdgcn_fmed3f(b - a, 0.0f, 1.0f); }
+
+// Base-2 log of the smallest significant density of a scene of n Gaussians: the densities left
+// out of a front sum total less than n 2^sig <= 2^-24 (and 2^sig <= 2^-30).
+__device__ __forceinline__ float comp_sig_log2(int n)
 {
-    const int l0 = (threadIdx.x & 63) - c.sl;  // first lane of the segment
-    const unsigned long long segmask = c.seg == 64 ? ~0ull : ((1ull << c.seg) - 1ull);
-    const unsigned long long below = (1ull << c.sl) - 1ull;
-#pragma unroll
-    for (int k = 0; k < KM; ++k) slots[c.sl + k * c.seg] = make_float2(0.0f, 0.0f);
-    int cnt = 0;
-#pragma unroll
-    for (int k = 0; k < KM; ++k) {
-        if (k < c.ke) {
-            const bool nz = DENSITY ? x[k] > kCompMinDensity : x[k] != 0.0f;
-            const unsigned long long bits = (__ballot(nz) >> l0) & segmask;
-            if (nz) slots[cnt + __popcll(bits & below)] = make_float2(q[k].t * kDepthScale, x[k]);
-            cnt += __popcll(bits);
-        }
-    }
-    for (int off = c.seg; off < 64; off <<= 1) cnt = max(cnt, __shfl_xor(cnt, off, 64));
-    return __builtin_amdgcn_readfirstlane(cnt);
+    const int lg = n > 1 ? 32 - __clz(n - 1) : 0;  // ceil(log2 n)
+    return fminf(-30.0f, -24.0f - (float)lg);
 }
 
-// For each of the lane's Gaussians k: the sum of x_j over the first n slots with t_j < t_k
-// (AFTER = false) or t_j > t_k, one pass over the slots for all of them.
-template <int KM, bool AFTER>
-__device__ __forceinline__ void ordered_sums(const float2 *__restrict__ slots, int n, const CompLanes &c,
-                                             const Geo q[KM], float out[KM])
+// A lane's slots: scaled depth and density of the significant intersection of the slot's
+// Gaussian (density 0 where that Gaussian is not significant for the lane, or not in its window).
+// One plain array, so that it stays in registers: depths at [k], densities at [kCompSlots + k].
+// A window's slots are filled by pushing at slot 0 (every slot moves up one), so slot k holds the
+// window's (ns - 1 - k)-th Gaussian in staging order, and the slots from ns on hold zeros.
+typedef float CompList[2 * kCompSlots];
+#define SLOT_T(L, k) ((L)[(k)])
+#define SLOT_D(L, k) ((L)[kCompSlots + (k)])
+
+// A lane's depth window (scaled depths): pairs with lo <= t < hi are taken in the current pass;
+// base sums the significant densities in front of lo, tie those at lo.
+struct CompWin {
+    float lo, hi, base, tie;
+};
+
+__device__ __forceinline__ void comp_clear(CompList L)
 {
-    float t[KM];
 #pragma unroll
-    for (int k = 0; k < KM; ++k) {
-        out[k] = 0.0f;
-        t[k] = q[k].t * kDepthScale;
+    for (int k = 0; k < 2 * kCompSlots; ++k) L[k] = 0.0f;
+}
+
+// Pushes (t, d) at slot 0: register moves at compile-time indices, no dynamic index.
+__device__ __forceinline__ void comp_push(CompList L, float t, float d)
+{
+#pragma unroll
+    for (int k = kCompSlots - 1; k > 0; --k) {
+        SLOT_T(L, k) = SLOT_T(L, k - 1);
+        SLOT_D(L, k) = SLOT_D(L, k - 1);
     }
-    // 1 if slot depth ts is before (AFTER: behind) t, else 0
-    auto step = [](float ts, float tk) {
-        return __builtin_amdgcn_fmed3f(AFTER ? ts - tk : tk - ts, 0.0f, 1.0f);
-    };
-    int j = 0;
-    for (; j + 4 <= n; j += 4) {
-        const float2 a = slots[j], b = slots[j + 1], cc = slots[j + 2], d = slots[j + 3];
+    SLOT_T(L, 0) = t;
+    SLOT_D(L, 0) = d;
+}
+
+__device__ __forceinline__ void comp_push_z(float z[kCompSlots], float v)
+{
 #pragma unroll
-        for (int k = 0; k < KM; ++k) {  // k >= ke: computed and not used
-            out[k] = fmaf(step(a.x, t[k]), a.y, out[k]);
-            out[k] = fmaf(step(b.x, t[k]), b.y, out[k]);
-            out[k] = fmaf(step(cc.x, t[k]), cc.y, out[k]);
-            out[k] = fmaf(step(d.x, t[k]), d.y, out[k]);
+    for (int k = kCompSlots - 1; k > 0; --k) z[k] = z[k - 1];
+    z[0] = v;
+}
+
+// Step sums over the slots in use, eight slots at a time (template recursion, so that every slot
+// index is a compile-time register index); ns is uniform, so the early exits are scalar branches,
+// and the unused slots of a group add zeros.
+constexpr int kSlotGroup = 8;
+template <int K>
+struct SlotSums {
+    // sum of the densities of the slots in front of ts
+    __device__ static __forceinline__ void front(const CompList L, int ns, float ts, float &f)
+    {
+        if (K >= ns) return;
+#pragma unroll
+        for (int k = K; k < K + kSlotGroup; ++k) f = fmaf(before(SLOT_T(L, k), ts), SLOT_D(L, k), f);
+        SlotSums<K + kSlotGroup>::front(L, ns, ts, f);
+    }
+    // sum of z over the slots behind ts
+    __device__ static __forceinline__ void behind(const CompList L, const float z[kCompSlots], int ns, float ts,
+                                                  float &b)
+    {
+        if (K >= ns) return;
+#pragma unroll
+        for (int k = K; k < K + kSlotGroup; ++k) b = fmaf(before(ts, SLOT_T(L, k)), z[k], b);
+        SlotSums<K + kSlotGroup>::behind(L, z, ns, ts, b);
+    }
+};
+template <>
+struct SlotSums<kCompSlots> {
+    __device__ static __forceinline__ void front(const CompList, int, float, float &) {}
+    __device__ static __forceinline__ void behind(const CompList, const float *, int, float, float &) {}
+};
+static_assert(kCompSlots % kSlotGroup == 0, "whole slot groups");
+
+// F at scaled depth ts inside window w: base, the densities at lo (if ts > lo), and the slots
+// in front of ts.
+__device__ __forceinline__ float comp_front(const CompList L, int ns, const CompWin &w, float ts)
+{
+    float f = ts > w.lo ? w.base + w.tie : w.base;
+    SlotSums<0>::front(L, ns, ts, f);
+    return f;
+}
+
+// Sum of z over the slots behind ts.
+__device__ __forceinline__ float comp_behind(const CompList L, const float z[kCompSlots], int ns, float ts)
+{
+    float b = 0.0f;
+    SlotSums<0>::behind(L, z, ns, ts, b);
+    return b;
+}
+
+// Entries (and colours) of Gaussians [gb, gb + cnt) of the scene into LDS, EW float4 each.
+template <int EW>
+__device__ __forceinline__ void comp_stage(const Params &P, const SceneRec &sr, int gb, int cnt, const double o[3],
+                                           float4 *__restrict__ ents)
+{
+    __syncthreads();  // the previous tile is consumed
+    for (int q = threadIdx.x; q < cnt; q += 64) {
+        const int gi = sr.gauss_off + gb + q;
+        make_entry(P.means + 3 * gi, P.prec + 6 * gi, P.weights[gi], o, &ents[EW * q]);
+        if (EW == 5) ents[EW * q + 4] = colour_entry(P.colors + 3 * gi);
+    }
+    __syncthreads();
+}
+
+template <int EW>
+__device__ __forceinline__ Ent comp_ent(const float4 *__restrict__ ents, int i)
+{
+    return ent_from(ents[EW * i], ents[EW * i + 1], ents[EW * i + 2], ents[EW * i + 3]);
+}
+
+// The slots of window w: every Gaussian significant for some lane of the wave, with a depth behind
+// lo for that lane, takes the next slot; the densities at lo go to w.tie (and each such pair, whose
+// front sum is w.base, to on_tie(g, q, density, staged index)); a lane that meets one more than the
+// slots hold lowers w.hi to its depth, and its slots at or behind w.hi are cleared (they belong to a
+// later window).  Returns the slot count (uniform); slot_g (if given) receives the slots'
+// scene-local Gaussian indices.
+template <int EW, class OnTie>
+__device__ __forceinline__ int comp_collect(const Params &P, const SceneRec &sr, const double o[3],
+                                            float4 *__restrict__ ents, bool resident, float v0, float v1,
+                                            float v2, float hm, float sig2, CompWin &w, CompList L,
+                                            int *__restrict__ slot_g, OnTie on_tie)
+{
+    int ns = 0;
+    comp_clear(L);
+    for (int gb = 0; gb < sr.n; gb += kCompTG) {
+        const int cnt = min(kCompTG, sr.n - gb);
+        if (!resident) comp_stage<EW>(P, sr, gb, cnt, o, ents);
+        for (int i = 0; i < cnt; ++i) {
+            const Ent g = comp_ent<EW>(ents, i);
+            Geo q;
+            pair_geo_coarse(g, v0, v1, v2, hm, 0.0f, 0.0f, q);
+            const bool sig = q.d2 > sig2;
+            if (!__any(sig)) continue;
+            const float ts = q.t * kDepthScale;
+            const float dl = exp2_(q.d2);
+            if (sig && ts == w.lo) {
+                w.tie += dl;
+                on_tie(g, q, dl, i);
+            }
+            const bool cand = sig && ts > w.lo;
+            if (!__any(cand)) continue;
+            if (ns < kCompSlots) {
+                comp_push(L, ts, cand ? dl : 0.0f);
+                if (slot_g && threadIdx.x == 0) slot_g[ns] = gb + i;
+                ns = __builtin_amdgcn_readfirstlane(ns + 1);
+            } else if (cand) {
+                w.hi = fminf(w.hi, ts);
+            }
         }
     }
-    for (; j < n; ++j) {
-        const float2 a = slots[j];
 #pragma unroll
-        for (int k = 0; k < KM; ++k) out[k] = fmaf(step(a.x, t[k]), a.y, out[k]);
+    for (int k = 0; k < kCompSlots; ++k) SLOT_D(L, k) = SLOT_T(L, k) >= w.hi ? 0.0f : SLOT_D(L, k);
+    return ns;
+}
+
+// Moves window w past hi (or marks the lane done); returns true while the lane has depths left.
+__device__ __forceinline__ bool comp_next(CompWin &w, const CompList L, int ns)
+{
+    if (w.hi == INFINITY) {
+        w.lo = INFINITY;
+        return false;
     }
+    float s = w.tie;
 #pragma unroll
-    for (int k = 0; k < KM; ++k)
-        if (k >= c.ke) out[k] = 0.0f;
+    for (int k = 0; k < kCompSlots; ++k) s += SLOT_D(L, k);
+    w.base += s;
+    w.lo = w.hi;
+    w.hi = INFINITY;
+    w.tie = 0.0f;
+    return true;
 }
 
 // ------------------------------------------------------------------------------------
 // Forward
 // ------------------------------------------------------------------------------------
 
-// Per-ray results wait in LDS (one record per ray) until the wave holds 64 of them; then
-// each lane writes one ray's outputs.
-constexpr int kEpiRec = 12;  // local ray index, M, S, T, N (3), C (3), D
-
-template <int KM, int F>
-__global__ __launch_bounds__(kCompBlock) void fwdc_kernel(Params P, FwdOut O, const BwdItem *__restrict__ items)
+template <int F>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kFwdcWaves))) void fwdc_kernel(Params P, FwdOut O, const BwdItem *__restrict__ items)
 {
     constexpr bool NORMALS = (F & kNrm) != 0, COLOR = (F & kCol) != 0;
-    __shared__ float2 tdl[kCompBlock * KM];
-    __shared__ float epi[kCompBlock * kEpiRec];
-    const BwdItem item = items[blockIdx.x];
-    const ViewRec vr = P.views[item.view];
-    const SceneRec sr = P.scenes[vr.scene];
-    const int n = sr.n;
-    const CompLanes c = comp_lanes<KM>(n);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const float *__restrict__ e = P.w2c + 12 * item.view;
-    const float *__restrict__ kk = P.intr + 4 * item.view;
+    constexpr int EW = COLOR ? 5 : 4;
+    __shared__ float4 ents[kCompTG * EW];
+    const int lane = threadIdx.x;
+    const BwdItem item = ld_uniform(items + blockIdx.x);
+    const ViewRec vr = ld_uniform(P.views + item.view);
+    const SceneRec sr = ld_uniform(P.scenes + vr.scene);
+    const CamRec cam = cam_of(P, item.view);
+    const float *e = cam.e, *kk = cam.k;
     double o[3];
     cam_centre(e, o);
     const float o0 = (float)o[0], o1 = (float)o[1], o2 = (float)o[2];
     const float hm = (float)(-0.5 * kLog2e);
-    Ent g[KM];
-    float4 cc[KM];
-    bool gv[KM];
-    comp_entries<KM, COLOR>(P, sr, c, o, g, cc, gv);
-    const int hw = vr.h * vr.w;
-    const int end = min(item.ray0 + item.span, hw);
-    float *__restrict__ my_epi = epi + wave * 64 * kEpiRec;
-    int filled = 0;  // records waiting in this wave's slice (the same in every wave)
+    const float sig2 = comp_sig_log2(sr.n);
+    const bool resident = sr.n <= kCompTG;
+    if (resident) comp_stage<EW>(P, sr, 0, sr.n, o, ents);
+    const int nt = min(item.span, vr.tiles - item.ray0);  // ray0: the item's first tile
 
-    for (int base = item.ray0; base < end; base += 4 * c.rpw) {
-        const int local = base + wave * c.rpw + c.sg;
-        const bool valid = local < end;
+    for (int tt = 0; tt < nt; ++tt) {
+        int row, col;
+        const int loc = tile_local(vr, item.ray0 + tt, lane, row, col);
+        const bool valid = loc >= 0;
         float v0, v1, v2;
-        ray_dir(P, vr, e, kk, valid ? local : end - 1, v0, v1, v2);
-        Geo q[KM];
-        float dl[KM];
-#pragma unroll
-        for (int k = 0; k < KM; ++k) {
-            if (k < c.ke) {
-                pair_geo(g[k], v0, v1, v2, hm, 0.0f, 0.0f, q[k]);
-                dl[k] = gv[k] ? exp2_(q[k].d2) : 0.0f;
-            } else {
-                dl[k] = 0.0f;
-            }
+        tile_ray_dir(P, vr, e, kk, valid ? loc : 0, valid ? row : 0, valid ? col : 0, v0, v1, v2);
+        float at = 0.0f, dt = 0.0f;  // loss targets, loaded ahead of the epilogue
+        if (O.g_depth && valid) {
+            at = O.alpha_t[vr.ray_off + loc];
+            dt = O.depth_t[vr.ray_off + loc];
         }
-        wave_sync();  // the previous step is done with the slots
-        const int cnt = compact_slots<KM, true>(tdl + c.sbase, c, q, dl);
-        wave_sync();
-        float front[KM];
-        ordered_sums<KM, false>(tdl + c.sbase, cnt, c, q, front);
-        float l2[KM];
-        float mx = -INFINITY;
-#pragma unroll
-        for (int k = 0; k < KM; ++k) {
-            l2[k] = -INFINITY;
-            if (k < c.ke && gv[k]) l2[k] = fmaf(-(float)kLog2e, front[k], log2_opacity(dl[k], q[k].d2));
-            mx = fmaxf(mx, l2[k]);
-        }
-        mx = seg_max(mx, c.seg);
-        float S = 0, T = 0, N0 = 0, N1 = 0, N2 = 0, C0 = 0, C1 = 0, C2 = 0, D = 0;
-#pragma unroll
-        for (int k = 0; k < KM; ++k) {
-            if (k < c.ke) {
-                const float ew = exp2_(l2[k] - mx);  // 0 for an empty slot
-                S += ew;
-                T = fmaf(ew, q[k].t, T);
-                D += dl[k];
-                if (NORMALS) {
-                    const PairNormal pn = pair_normal(g[k], q[k], 0.0f, 0.0f, 0.0f);
-                    N0 = fmaf(ew, pn.n0, N0);
-                    N1 = fmaf(ew, pn.n1, N1);
-                    N2 = fmaf(ew, pn.n2, N2);
-                }
-                if (COLOR) {
-                    C0 = fmaf(ew, cc[k].x, C0);
-                    C1 = fmaf(ew, cc[k].y, C1);
-                    C2 = fmaf(ew, cc[k].z, C2);
-                }
-            }
-        }
-        float *r = my_epi + (filled + c.sg) * kEpiRec;
-        if (c.seg >= 8) {
-            // S, T, D, N, C0, C1 scattered over the segment, each written by the lanes that hold it
-            const float x[8] = {S, T, D, N0, N1, N2, C0, C1};
-            const float v = seg_sum8(x, c.sl, c.seg);
-            if (COLOR) C2 = seg_sum(C2, c.seg);
-            if ((c.sl & ((c.seg >> 3) - 1)) == 0) {
-                const int i = seg8_index(c.sl, c.seg);
-                r[i < 2 ? 2 + i : (i == 2 ? 10 : 1 + i)] = v;  // S, T at 2, 3; D at 10; N, C0, C1 at 4..8
-            }
-            if (c.sl == 0) {
-                r[0] = __int_as_float(valid ? local : -1);
-                r[1] = mx;
-                r[9] = C2;
-            }
-        } else {
-            S = seg_sum(S, c.seg);
-            T = seg_sum(T, c.seg);
-            D = seg_sum(D, c.seg);
-            if (NORMALS) {
-                N0 = seg_sum(N0, c.seg);
-                N1 = seg_sum(N1, c.seg);
-                N2 = seg_sum(N2, c.seg);
-            }
-            if (COLOR) {
-                C0 = seg_sum(C0, c.seg);
-                C1 = seg_sum(C1, c.seg);
-                C2 = seg_sum(C2, c.seg);
-            }
-            if (c.sl == 0) {
-                r[0] = __int_as_float(valid ? local : -1);
-                r[1] = mx; r[2] = S; r[3] = T; r[4] = N0; r[5] = N1; r[6] = N2;
-                r[7] = C0; r[8] = C1; r[9] = C2; r[10] = D;
-            }
-        }
-        filled += c.rpw;
-        if (filled == 64 || base + 4 * c.rpw >= end) {
-            wave_sync();
-            if (lane < filled) {
-                const float *r = my_epi + lane * kEpiRec;
-                const int rl = __float_as_int(r[0]);
-                if (rl >= 0) {
-                    float at = 0.0f, dt = 0.0f;  // loss targets, loaded ahead of the direction
-                    if (O.g_depth) {
-                        at = O.alpha_t[vr.ray_off + rl];
-                        dt = O.depth_t[vr.ray_off + rl];
+        float M = -INFINITY, S = 0.0f, T = 0.0f, N0 = 0.0f, N1 = 0.0f, N2 = 0.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+        float D = 0.0f;
+        CompWin w{valid ? -INFINITY : INFINITY, INFINITY, 0.0f, 0.0f};
+        bool more = valid;
+        CompList L;
+        while (__any(more)) {
+            const int ns = comp_collect<EW>(P, sr, o, ents, resident, v0, v1, v2, hm, sig2, w, L, nullptr,
+                                            [](const Ent &, const Geo &, float, int) {});
+            for (int gb = 0; gb < sr.n; gb += kCompTG) {
+                const int cnt = min(kCompTG, sr.n - gb);
+                if (!resident) comp_stage<EW>(P, sr, gb, cnt, o, ents);
+                for (int i = 0; i < cnt; ++i) {
+                    const Ent g = comp_ent<EW>(ents, i);
+                    Geo q;
+                    pair_geo_coarse(g, v0, v1, v2, hm, 0.0f, 0.0f, q);
+                    const float ts = q.t * kDepthScale;
+                    // a pair of this window whose weight (at most its density) is not below
+                    // 2^-150 of the running maximum, where it would be zero in FP32
+                    const bool live = ts >= w.lo && ts < w.hi && q.d2 - M >= kSkipLog2;
+                    if (!__any(live)) continue;
+                    if (!live) continue;
+                    const float delta = exp2_(q.d2);
+                    D += delta;
+                    float lw = fmaf(-(float)kLog2e, comp_front(L, ns, w, ts), log2_opacity(delta, q.d2));
+                    if (lw > M) {  // new running maximum: rescale the sums
+                        const float sc = exp2_(M - lw);
+                        S *= sc;
+                        T *= sc;
+                        N0 *= sc;
+                        N1 *= sc;
+                        N2 *= sc;
+                        C0 *= sc;
+                        C1 *= sc;
+                        C2 *= sc;
+                        M = lw;
                     }
-                    float w0, w1, w2;
-                    ray_dir(P, vr, e, kk, rl, w0, w1, w2);
-                    write_ray<F>(P, O, item.view, vr.ray_off + rl, e, kk, o0, o1, o2, w0, w1, w2, r[1], r[2], r[3],
-                                 r[4], r[5], r[6], r[7], r[8], r[9], r[10], at, dt);
+                    const float ew = exp2_(lw - M);
+                    S += ew;
+                    T = fmaf(ew, q.t, T);
+                    if (NORMALS) {
+                        pair_refine(q);
+                        const PairNormal pn = pair_normal(g, q, 0.0f, 0.0f, 0.0f);
+                        N0 = fmaf(ew, pn.n0, N0);
+                        N1 = fmaf(ew, pn.n1, N1);
+                        N2 = fmaf(ew, pn.n2, N2);
+                    }
+                    if (COLOR) {
+                        const float4 cc = ents[EW * i + 4];
+                        C0 = fmaf(ew, cc.x, C0);
+                        C1 = fmaf(ew, cc.y, C1);
+                        C2 = fmaf(ew, cc.z, C2);
+                    }
                 }
             }
-            wave_sync();
-            filled = 0;
+            more = comp_next(w, L, ns);
         }
+        if (valid)
+            write_ray<F>(P, O, item.view, vr.ray_off + loc, e, kk, o0, o1, o2, v0, v1, v2, M, S, T, N0, N1, N2, C0,
+                         C1, C2, D, at, dt);
     }
 }
 
@@ -393,256 +356,350 @@ __global__ __launch_bounds__(kCompBlock) void fwdc_kernel(Params P, FwdOut O, co
 // Backward
 // ------------------------------------------------------------------------------------
 
-// Waves per SIMD the compositing adjoint is compiled for: five for the plain form at two
-// Gaussians per lane (96 VGPRs; it spills 11-16 of its 112-119 and still runs 6 % faster than
-// at four waves), else what its registers give.
-constexpr int bwdc_min_waves(int km, int f) { return km == 2 && (f & (kNrm | kCol)) == 0 ? 5 : 1; }
-
-template <int KM, int F>
-__global__ __launch_bounds__(kCompBlock) __attribute__((amdgpu_waves_per_eu(bwdc_min_waves(KM, F)))) void bwdc_kernel(Params P, BwdIn I, const BwdItem *__restrict__ items,
-                                                          float *__restrict__ partial, float *__restrict__ beta_partial)
+template <int F>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))) void bwdc_kernel(Params P, BwdIn I, const BwdItem *__restrict__ items,
+                                                  float *__restrict__ partial, float *__restrict__ beta_partial)
 {
     constexpr bool NORMALS = (F & kNrm) != 0, COLOR = (F & kCol) != 0;
     // without a normal cotangent the pairs take the offset form of the adjoint
     // (pair_adjoint_offset), which needs neither the refined peak nor r
     constexpr bool PLAIN = !NORMALS;
-    constexpr int RW = COLOR ? 4 : 3;                        // float4 per staged ray
+    constexpr int EW = COLOR ? 5 : 4;
     constexpr int REC = COLOR ? kPartialColor : kPartial;   // partial record per Gaussian
-    // a lane's sums per Gaussian: (H, Bv, L) of the offset form or the general record, then colour
-    constexpr int LREC = PLAIN ? kOffsetAcc + (COLOR ? 3 : 0) : REC;
-    constexpr int RAYS4 = kCompBlock * RW;
-    constexpr int RED4 = (kCompBlock * KM * LREC + 3) / 4;
-    __shared__ float4 smem[RAYS4 > RED4 ? RAYS4 : RED4];     // staged rays, then the reduction
-    __shared__ float2 tdl[kCompBlock * KM];
-    const int tid = threadIdx.x;
-    const BwdItem item = items[blockIdx.x];
-    const ViewRec vr = P.views[item.view];
-    const SceneRec sr = P.scenes[vr.scene];
-    const int n = sr.n;
-    const CompLanes c = comp_lanes<KM>(n);
-    const int wave = tid >> 6;
-    const float *__restrict__ e = P.w2c + 12 * item.view;
-    const float *__restrict__ kk = P.intr + 4 * item.view;
+    // the sums per Gaussian: (H, Bv, L) of the offset form or the general record, then colour
+    constexpr int LREC = (PLAIN ? kOffsetAcc : kPartial) + (COLOR ? 3 : 0);
+    static_assert(LREC <= 16, "one 16-value wave sum per pair");
+    __shared__ float4 ents[kCompTG * EW];
+    __shared__ float4 sents[kCompSlots * EW];  // the slots' entries (scenes beyond one LDS tile)
+    __shared__ float rec[kCompTG * LREC];      // the item's sums of the staged Gaussians
+    __shared__ int slot_g[kCompSlots];
+    __shared__ int touched[kCompTG];
+    const int lane = threadIdx.x;
+    const BwdItem item = ld_uniform(items + blockIdx.x);
+    const ViewRec vr = ld_uniform(P.views + item.view);
+    const SceneRec sr = ld_uniform(P.scenes + vr.scene);
+    const CamRec cam = cam_of(P, item.view);
+    const float *e = cam.e, *kk = cam.k;
     double o[3];
     cam_centre(e, o);
     const float o0 = (float)o[0], o1 = (float)o[1], o2 = (float)o[2];
     const float hm = (float)(-0.5 * kLog2e);
-    Ent g[KM];
-    float4 cc[KM];
-    bool gv[KM];
-    comp_entries<KM, COLOR>(P, sr, c, o, g, cc, gv);
-    PairAcc acc[KM];
-    OffsetAcc pacc[KM];
-    float aC[KM][3];
-#pragma unroll
-    for (int k = 0; k < KM; ++k) aC[k][0] = aC[k][1] = aC[k][2] = 0.0f;
-    const int hw = vr.h * vr.w;
-    const int end = min(item.ray0 + item.span, hw);
-    const int step = 4 * c.rpw;
+    const float sig2 = comp_sig_log2(sr.n);
+    const int n = sr.n;
+    const bool resident = n <= kCompTG;
+    float *__restrict__ prec_out = partial + item.poff;
+    if (resident) {
+        comp_stage<EW>(P, sr, 0, n, o, ents);
+        for (int q = lane; q < n * LREC; q += 64) rec[q] = 0.0f;
+    } else {
+        // the record is summed in place over the item's tiles and windows, one staged tile at a time
+        for (int q = lane; q < n * REC; q += 64) prec_out[q] = 0.0f;
+    }
+    __syncthreads();
+    const int nt = min(item.span, vr.tiles - item.ray0);
 
-    // rays are staged kCompBlock at a time (one prologue per thread), then taken a step of
-    // 4 * 64 / seg rays at a time
-    for (int sb = item.ray0; sb < end; sb += kCompBlock) {
-        __syncthreads();  // the previous stage is done with the staged rays
-        {
-            float4 pr[4];
-            ray_prologue<F>(P, I, item.view, vr, e, kk, o0, o1, o2, sb + tid, sb + tid < end, 0.0f, 0.0f, pr);
+    for (int tt = 0; tt < nt; ++tt) {
+        int row, col;
+        const int loc = tile_local(vr, item.ray0 + tt, lane, row, col);
+        const bool valid = loc >= 0;
+        float4 pr[4];
+        ray_prologue<F>(P, I, item.view, vr, e, kk, o0, o1, o2, valid ? loc : 0, valid, 0.0f, 0.0f, pr);
+        const float v0 = pr[0].x, v1 = pr[0].y, v2 = pr[0].z, M2 = pr[0].w;
+        const float invS = pr[1].x, tfb = pr[1].y, nb0 = pr[1].z, nb1 = pr[1].w;
+        const float nb2 = pr[2].x, kap = pr[2].y, Db = pr[2].z;
+        const float cb0 = pr[3].x, cb1 = pr[3].y, cb2 = pr[3].z;
+        // a normalised weight 2^(lw - M2) / S is zero in FP32 where lw < M2 + log2 S - 150, and
+        // lw is at most the log2 density
+        const float wskip = valid ? M2 - __builtin_amdgcn_logf(invS) + kSkipLog2 : INFINITY;
+        const CompWin w0{valid ? -INFINITY : INFINITY, INFINITY, 0.0f, 0.0f};
+        CompWin w = w0;
+        CompList L;
+        float zs[kCompSlots];
+
+        // z_bar of the slots' own pairs (the lanes' significant intersections of the window)
+        // (pushed in staging order, so that zs[k] belongs to slot k)
+        auto slot_z = [&](int ns) {
 #pragma unroll
-            for (int w = 0; w < RW; ++w) smem[RW * tid + w] = pr[w];
-        }
-        __syncthreads();  // the staged rays are visible to every wave
-        for (int s0 = 0; s0 < kCompBlock && sb + s0 < end; s0 += step) {
-            wave_sync();  // the previous step is done with the slots
-            const int ry = s0 + wave * c.rpw + c.sg;
-            const float4 x0 = smem[RW * ry], x1 = smem[RW * ry + 1], x2 = smem[RW * ry + 2];
-            float4 x3 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            if (COLOR) x3 = smem[RW * ry + 3];
-            const float v0 = x0.x, v1 = x0.y, v2 = x0.z, M2 = x0.w, invS = x1.x, tfb = x1.y;
-            const float nb0 = x1.z, nb1 = x1.w, nb2 = x2.x, kap = x2.y, Db = x2.z;
-            Geo q[KM];
-            float dl[KM];
-#pragma unroll
-            for (int k = 0; k < KM; ++k) {
-                dl[k] = 0.0f;
-                if (k < c.ke) {
-                    if (PLAIN)
-                        pair_geo_coarse(g[k], v0, v1, v2, hm, 0.0f, 0.0f, q[k]);
-                    else
-                        pair_geo(g[k], v0, v1, v2, hm, 0.0f, 0.0f, q[k]);
-                    dl[k] = gv[k] ? exp2_(q[k].d2) : 0.0f;
+            for (int k = 0; k < kCompSlots; ++k) zs[k] = 0.0f;
+            if (!resident) {
+                __syncthreads();
+                if (lane < ns) {
+                    const int gi = sr.gauss_off + slot_g[lane];
+                    make_entry(P.means + 3 * gi, P.prec + 6 * gi, P.weights[gi], o, &sents[EW * lane]);
+                    if (COLOR) sents[EW * lane + 4] = colour_entry(P.colors + 3 * gi);
                 }
+                __syncthreads();
             }
-            const int cnt = compact_slots<KM, true>(tdl + c.sbase, c, q, dl);
-            wave_sync();
-            float front[KM];
-            ordered_sums<KM, false>(tdl + c.sbase, cnt, c, q, front);
-            float wt[KM], zb[KM];
-            PairNormal pn[KM];
-#pragma unroll
-            for (int k = 0; k < KM; ++k) {
-                wt[k] = zb[k] = 0.0f;
-                pn[k] = PairNormal{0, 0, 0, 0, 0};
-                if (k < c.ke) {
-                    if (gv[k]) wt[k] = exp2_(fmaf(-(float)kLog2e, front[k], log2_opacity(dl[k], q[k].d2)) - M2) * invS;
-                    if (NORMALS) pn[k] = pair_normal(g[k], q[k], nb0, nb1, nb2);
-                    float lin = fmaf(tfb, q[k].t, pn[k].nN);
-                    if (COLOR) lin = fmaf(x3.x, cc[k].x, fmaf(x3.y, cc[k].y, fmaf(x3.z, cc[k].z, lin)));
-                    zb[k] = wt[k] * (lin - kap);
-                }
-            }
-            wave_sync();  // the segment is done reading (t, delta)
-            float zp[KM];  // the terms of the behind sums
-#pragma unroll
-            for (int k = 0; k < KM; ++k) zp[k] = wt[k] >= kCompMinWeight ? zb[k] : 0.0f;
-            const int cnt_b = compact_slots<KM, false>(tdl + c.sbase, c, q, zp);
-            wave_sync();
-            float behind[KM];
-            ordered_sums<KM, true>(tdl + c.sbase, cnt_b, c, q, behind);
-#pragma unroll
-            for (int k = 0; k < KM; ++k) {
-                if (k < c.ke) {
-                    const float db = fmaf(zb[k], opacity_slope(dl[k]), dl[k] * (Db - behind[k]));
-                    const float tb = wt[k] * tfb;
-                    if (COLOR) {
-                        aC[k][0] = fmaf(wt[k], x3.x, aC[k][0]);
-                        aC[k][1] = fmaf(wt[k], x3.y, aC[k][1]);
-                        aC[k][2] = fmaf(wt[k], x3.z, aC[k][2]);
+            for (int s = 0; s < ns; ++s) {
+                const int gs = resident ? slot_g[s] : s;
+                const float4 *src = resident ? ents : sents;
+                const Ent g = comp_ent<EW>(src, gs);
+                Geo q;
+                pair_geo_coarse(g, v0, v1, v2, hm, 0.0f, 0.0f, q);
+                const float ts = q.t * kDepthScale;
+                // the slot holds the lane's intersection when it is significant and in the window
+                const bool own = q.d2 > sig2 && ts > w.lo && ts < w.hi;
+                float z = 0.0f;
+                if (__any(own) && own) {
+                    const float lw = fmaf(-(float)kLog2e, comp_front(L, ns, w, ts), log2_opacity(exp2_(q.d2), q.d2));
+                    const float wt = exp2_(lw - M2) * invS;
+                    float lin = tfb * q.t;
+                    if (NORMALS) {
+                        pair_refine(q);
+                        lin += pair_normal(g, q, nb0, nb1, nb2).nN;
                     }
-                    if (PLAIN)
-                        pair_adjoint_offset(q[k], v0, v1, v2, tb, db, pacc[k]);
-                    else
-                        pair_adjoint<NORMALS>(g[k], q[k], v0, v1, v2, wt[k], pn[k], nb0, nb1, nb2, tb, db, acc[k]);
+                    if (COLOR) {
+                        const float4 cc = src[EW * gs + 4];
+                        lin = fmaf(cb0, cc.x, fmaf(cb1, cc.y, fmaf(cb2, cc.z, lin)));
+                    }
+                    z = wt * (lin - kap);
+                }
+                comp_push_z(zs, z);
+            }
+        };
+
+        // z_bar of the significant pairs at a window's lower edge (the depth where the previous
+        // window stopped): they take no slot, and their front sum is the window's base
+        float ztie = 0.0f;
+        auto on_tie = [&](const Ent &g, const Geo &q0, float dl, int i) {
+            Geo q = q0;
+            const float lw = fmaf(-(float)kLog2e, w.base, log2_opacity(dl, q.d2));
+            const float wt = exp2_(lw - M2) * invS;
+            float lin = tfb * q.t;
+            if (NORMALS) {
+                pair_refine(q);
+                lin += pair_normal(g, q, nb0, nb1, nb2).nN;
+            }
+            if (COLOR) {
+                const float4 cc = ents[EW * i + 4];
+                lin = fmaf(cb0, cc.x, fmaf(cb1, cc.y, fmaf(cb2, cc.z, lin)));
+            }
+            ztie = fmaf(wt, lin - kap, ztie);
+        };
+        // sum of z_bar over the window's significant pairs: the slots' and the lower edge's
+        auto window_z = [&](int ns) {
+            float s = ztie;
+#pragma unroll
+            for (int k = 0; k < kCompSlots; ++k) s += zs[k];
+            return s;
+        };
+
+        // First sweep, for tiles that take several windows: the sum of z_bar over all significant
+        // intersections of each ray, so that a window knows the z_bar of the windows behind it.
+        int ns = comp_collect<EW>(P, sr, o, ents, resident, v0, v1, v2, hm, sig2, w, L, slot_g, on_tie);
+        float zall = 0.0f;
+        if (__any(w.hi != INFINITY)) {
+            bool more = true;
+            for (;;) {
+                slot_z(ns);
+                zall += window_z(ns);
+                more = comp_next(w, L, ns);
+                if (!__any(more)) break;
+                ztie = 0.0f;
+                ns = comp_collect<EW>(P, sr, o, ents, resident, v0, v1, v2, hm, sig2, w, L, slot_g, on_tie);
+            }
+            w = w0;
+            ztie = 0.0f;
+            ns = comp_collect<EW>(P, sr, o, ents, resident, v0, v1, v2, hm, sig2, w, L, slot_g, on_tie);
+        }
+
+        float zthrough = 0.0f;
+        for (;;) {
+            slot_z(ns);
+            zthrough += window_z(ns);
+            // z_bar of the significant intersections behind this window
+            const float zafter = w.hi == INFINITY ? 0.0f : zall - zthrough;
+
+            for (int gb = 0; gb < n; gb += kCompTG) {
+                const int cnt = min(kCompTG, n - gb);
+                if (!resident) {
+                    comp_stage<EW>(P, sr, gb, cnt, o, ents);
+                    for (int q = lane; q < cnt * LREC; q += 64) rec[q] = 0.0f;
+                    for (int q = lane; q < cnt; q += 64) touched[q] = 0;
+                    __syncthreads();
+                }
+                for (int i = 0; i < cnt; ++i) {
+                    const Ent g = comp_ent<EW>(ents, i);
+                    Geo q;
+                    pair_geo_coarse(g, v0, v1, v2, hm, 0.0f, 0.0f, q);
+                    const float ts = q.t * kDepthScale;
+                    // a pair of this window with a weight or a density that is not zero in FP32
+                    const bool live = ts >= w.lo && ts < w.hi && q.d2 >= fminf(kSkipLog2, wskip);
+                    if (!__any(live)) continue;
+                    PairAcc acc;
+                    OffsetAcc oacc;
+                    float aC0 = 0.0f, aC1 = 0.0f, aC2 = 0.0f;
+                    if (live) {
+                        const float delta = exp2_(q.d2);
+                        const float lw = fmaf(-(float)kLog2e, comp_front(L, ns, w, ts), log2_opacity(delta, q.d2));
+                        const float wt = exp2_(lw - M2) * invS;
+                        PairNormal pn{0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+                        if (NORMALS) {
+                            pair_refine(q);
+                            pn = pair_normal(g, q, nb0, nb1, nb2);
+                        }
+                        float lin = fmaf(tfb, q.t, pn.nN);
+                        if (COLOR) {
+                            const float4 cc = ents[EW * i + 4];
+                            lin = fmaf(cb0, cc.x, fmaf(cb1, cc.y, fmaf(cb2, cc.z, lin)));
+                            aC0 = wt * cb0;
+                            aC1 = wt * cb1;
+                            aC2 = wt * cb2;
+                        }
+                        const float zb = wt * (lin - kap);
+                        const float bsum = zafter + comp_behind(L, zs, ns, ts);
+                        const float db = fmaf(zb, opacity_slope(delta), delta * (Db - bsum));
+                        const float tb = wt * tfb;
+                        if (PLAIN)
+                            pair_adjoint_offset(q, v0, v1, v2, tb, db, oacc);
+                        else
+                            pair_adjoint<NORMALS>(g, q, v0, v1, v2, wt, pn, nb0, nb1, nb2, tb, db, acc);
+                    }
+                    float x[16];
+                    if (PLAIN) {
+                        offset_acc_store(oacc, x);
+                    } else {
+                        x[0] = acc.u0; x[1] = acc.u1; x[2] = acc.u2; x[3] = acc.u3; x[4] = acc.u4; x[5] = acc.u5;
+                        x[6] = acc.p0; x[7] = acc.p1; x[8] = acc.p2; x[9] = acc.l;
+                    }
+                    constexpr int B0 = PLAIN ? kOffsetAcc : kPartial;
+#pragma unroll
+                    for (int c = B0; c < 16; ++c) x[c] = 0.0f;
+                    if (COLOR) {
+                        x[B0] = aC0;
+                        x[B0 + 1] = aC1;
+                        x[B0 + 2] = aC2;
+                    }
+                    const float tot = wave_sum16(x, lane);
+                    const int idx = wave16_index(lane);
+                    if ((lane & 3) == 0 && idx < LREC) rec[LREC * i + idx] += tot;
+                    if (!resident && lane == 0) touched[i] = 1;
+                }
+                if (!resident) {
+                    // add the tile's sums of this window to the item's record
+                    __syncthreads();
+                    for (int qq = lane; qq < cnt; qq += 64) {
+                        if (!touched[qq]) continue;
+                        const int gg = sr.gauss_off + gb + qq;
+                        float r[kPartialColor];
+                        if (PLAIN)
+                            write_partial_offset(r, rec + LREC * qq, REC, P.prec + 6 * gg, P.means + 3 * gg, o);
+                        else
+                            write_partial(r, rec + LREC * qq, REC, P.means + 3 * gg, o);
+                        float *dst = prec_out + REC * (gb + qq);
+                        for (int c = 0; c < REC; ++c) dst[c] += r[c];
+                    }
                 }
             }
+            const bool more = comp_next(w, L, ns);
+            if (!__any(more)) break;
+            ztie = 0.0f;
+            ns = comp_collect<EW>(P, sr, o, ents, resident, v0, v1, v2, hm, sig2, w, L, slot_g, on_tie);
         }
     }
 
-    // deterministic reduction over the block's segments: Gaussian j's record sums the lanes
-    // holding it in wave order, then segment order
-    __syncthreads();
-    float *red = reinterpret_cast<float *>(smem);
-#pragma unroll
-    for (int k = 0; k < KM; ++k) {
-        float *my = red + (tid * KM + k) * LREC;
-        if (PLAIN) {
-            offset_acc_store(pacc[k], my);
-        } else {
-            const PairAcc &a = acc[k];
-            my[0] = a.u0; my[1] = a.u1; my[2] = a.u2; my[3] = a.u3; my[4] = a.u4; my[5] = a.u5;
-            my[6] = a.p0; my[7] = a.p1; my[8] = a.p2; my[9] = a.l;
-        }
-        if (COLOR) {
-            my[LREC - 3] = aC[k][0]; my[LREC - 2] = aC[k][1]; my[LREC - 1] = aC[k][2];
+    if (resident) {
+        __syncthreads();
+        for (int q = lane; q < n; q += 64) {
+            const int gg = sr.gauss_off + q;
+            if (PLAIN)
+                write_partial_offset(prec_out + REC * q, rec + LREC * q, REC, P.prec + 6 * gg, P.means + 3 * gg, o);
+            else
+                write_partial(prec_out + REC * q, rec + LREC * q, REC, P.means + 3 * gg, o);
         }
     }
-    __syncthreads();
-    if (tid < n) {
-        const int k = tid / c.seg, l = tid % c.seg;
-        float sum[LREC];
-#pragma unroll
-        for (int v = 0; v < LREC; ++v) sum[v] = 0.0f;
-        for (int w = 0; w < kCompBlock / 64; ++w)
-            for (int s = 0; s < c.rpw; ++s) {
-                const float *src = red + ((w * 64 + s * c.seg + l) * KM + k) * LREC;
-#pragma unroll
-                for (int v = 0; v < LREC; ++v) sum[v] += src[v];
-            }
-        const int gg = sr.gauss_off + tid;
-        if (PLAIN)
-            write_partial_offset(partial + item.poff + REC * tid, sum, REC, P.prec + 6 * gg, P.means + 3 * gg, o);
-        else
-            write_partial(partial + item.poff + REC * tid, sum, REC, P.means + 3 * gg, o);
-    }
-    if (tid < 2) beta_partial[2 * item.seq + tid] = 0.0f;  // the model has no blend parameters
+    if (lane < 2) beta_partial[2 * item.seq + lane] = 0.0f;  // the model has no blend parameters
 }
 
 // ------------------------------------------------------------------------------------
-// Split statistic (Sec. 8) with the compositing weights: lbar_i = (1/M) sum_j L_j w_ji,
-// same layout as the backward; the running maximum and 1/S come from the forward's stash.
+// Split statistic (Sec. 8) with the compositing weights: lbar_i = (1/M) sum_j L_j w_ji, summed
+// here per item and Gaussian; the running maximum and 1/S come from the forward's stash.
 // ------------------------------------------------------------------------------------
 
-template <int KM>
-__global__ __launch_bounds__(kCompBlock) void statc_kernel(Params P, const float *__restrict__ loss,
-                                                           const float *__restrict__ stash,
-                                                           const BwdItem *__restrict__ items,
-                                                           float *__restrict__ partial)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kFwdcWaves))) void statc_kernel(Params P, const float *__restrict__ loss,
+                                                   const float *__restrict__ stash,
+                                                   const BwdItem *__restrict__ items, float *__restrict__ partial)
 {
-    __shared__ float4 rays[kCompBlock * 2];
-    __shared__ float2 tdl[kCompBlock * KM];
-    __shared__ float red[kCompBlock * KM];
-    const int tid = threadIdx.x;
-    const BwdItem item = items[blockIdx.x];
-    const ViewRec vr = P.views[item.view];
-    const SceneRec sr = P.scenes[vr.scene];
-    const int n = sr.n;
-    const CompLanes c = comp_lanes<KM>(n);
-    const int wave = tid >> 6;
-    const float *__restrict__ e = P.w2c + 12 * item.view;
-    const float *__restrict__ kk = P.intr + 4 * item.view;
+    constexpr int EW = 4;
+    __shared__ float4 ents[kCompTG * EW];
+    __shared__ float rec[kCompTG];
+    const int lane = threadIdx.x;
+    const BwdItem item = ld_uniform(items + blockIdx.x);
+    const ViewRec vr = ld_uniform(P.views + item.view);
+    const SceneRec sr = ld_uniform(P.scenes + vr.scene);
+    const CamRec cam = cam_of(P, item.view);
+    const float *e = cam.e, *kk = cam.k;
     double o[3];
     cam_centre(e, o);
     const float hm = (float)(-0.5 * kLog2e);
-    Ent g[KM];
-    float4 cc[KM];
-    bool gv[KM];
-    comp_entries<KM, false>(P, sr, c, o, g, cc, gv);
-    float acc[KM];
-#pragma unroll
-    for (int k = 0; k < KM; ++k) acc[k] = 0.0f;
-    const int hw = vr.h * vr.w;
-    const int end = min(item.ray0 + item.span, hw);
-    const int step = 4 * c.rpw;
-    for (int base = item.ray0; base < end; base += step) {
-        __syncthreads();
-        if (tid < step) {
-            const int local = base + tid;
-            float4 a = make_float4(0.0f, 0.0f, 1.0f, INFINITY), b = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            if (local < end) {
-                const int r = vr.ray_off + local;
-                float v0, v1, v2;
-                ray_dir(P, vr, e, kk, local, v0, v1, v2);
-                const float4 s0 = reinterpret_cast<const float4 *>(stash)[2 * (size_t)r];
-                a = make_float4(v0, v1, v2, s0.x);
-                b = make_float4(s0.y, loss[r], 0.0f, 0.0f);
-            }
-            rays[2 * tid] = a;
-            rays[2 * tid + 1] = b;
-        }
-        __syncthreads();
-        const int ry = wave * c.rpw + c.sg;
-        const float4 x0 = rays[2 * ry], x1 = rays[2 * ry + 1];
-        Geo q[KM];
-        float dl[KM];
-#pragma unroll
-        for (int k = 0; k < KM; ++k) {
-            dl[k] = 0.0f;
-            if (k < c.ke) {
-                pair_geo(g[k], x0.x, x0.y, x0.z, hm, 0.0f, 0.0f, q[k]);
-                dl[k] = gv[k] ? exp2_(q[k].d2) : 0.0f;
-            }
-        }
-        const int cnt = compact_slots<KM, true>(tdl + c.sbase, c, q, dl);
-        __syncthreads();
-        float front[KM];
-        ordered_sums<KM, false>(tdl + c.sbase, cnt, c, q, front);
-#pragma unroll
-        for (int k = 0; k < KM; ++k) {
-            if (k < c.ke && gv[k]) {
-                const float wt = exp2_(fmaf(-(float)kLog2e, front[k], log2_opacity(dl[k], q[k].d2)) - x0.w) * x1.x;
-                acc[k] = fmaf(x1.y, wt, acc[k]);
-            }
-        }
+    const float sig2 = comp_sig_log2(sr.n);
+    const int n = sr.n;
+    const bool resident = n <= kCompTG;
+    float *__restrict__ out = partial + item.poff;
+    if (resident) {
+        comp_stage<EW>(P, sr, 0, n, o, ents);
+        for (int q = lane; q < n; q += 64) rec[q] = 0.0f;
+    } else {
+        for (int q = lane; q < n; q += 64) out[q] = 0.0f;
     }
     __syncthreads();
+    const int nt = min(item.span, vr.tiles - item.ray0);
+    for (int tt = 0; tt < nt; ++tt) {
+        int row, col;
+        const int loc = tile_local(vr, item.ray0 + tt, lane, row, col);
+        const bool valid = loc >= 0;
+        float v0, v1, v2;
+        tile_ray_dir(P, vr, e, kk, valid ? loc : 0, valid ? row : 0, valid ? col : 0, v0, v1, v2);
+        float M2 = INFINITY, invS = 0.0f, lr = 0.0f;
+        if (valid) {
+            const size_t r = (size_t)vr.ray_off + loc;
+            const float4 s0 = reinterpret_cast<const float4 *>(stash)[2 * r];
+            M2 = s0.x;
+            invS = s0.y;
+            lr = loss[r];
+        }
+        const float wskip = valid ? M2 - __builtin_amdgcn_logf(invS) + kSkipLog2 : INFINITY;
+        CompWin w{valid ? -INFINITY : INFINITY, INFINITY, 0.0f, 0.0f};
+        CompList L;
+        for (;;) {
+            const int ns = comp_collect<EW>(P, sr, o, ents, resident, v0, v1, v2, hm, sig2, w, L, nullptr,
+                                            [](const Ent &, const Geo &, float, int) {});
+            for (int gb = 0; gb < n; gb += kCompTG) {
+                const int cnt = min(kCompTG, n - gb);
+                if (!resident) {
+                    comp_stage<EW>(P, sr, gb, cnt, o, ents);
+                    for (int q = lane; q < cnt; q += 64) rec[q] = 0.0f;
+                    __syncthreads();
+                }
+                for (int i = 0; i < cnt; ++i) {
+                    const Ent g = comp_ent<EW>(ents, i);
+                    Geo q;
+                    pair_geo_coarse(g, v0, v1, v2, hm, 0.0f, 0.0f, q);
+                    const float ts = q.t * kDepthScale;
+                    const bool live = ts >= w.lo && ts < w.hi && q.d2 >= wskip;
+                    if (!__any(live)) continue;
+                    float x = 0.0f;
+                    if (live) {
+                        const float lw = fmaf(-(float)kLog2e, comp_front(L, ns, w, ts), log2_opacity(exp2_(q.d2), q.d2));
+                        x = lr * (exp2_(lw - M2) * invS);
+                    }
+                    // sum over the wave in a fixed order
 #pragma unroll
-    for (int k = 0; k < KM; ++k) red[tid * KM + k] = acc[k];
-    __syncthreads();
-    if (tid < n) {
-        const int k = tid / c.seg, l = tid % c.seg;
-        float sum = 0.0f;
-        for (int w = 0; w < kCompBlock / 64; ++w)
-            for (int sgi = 0; sgi < c.rpw; ++sgi) sum += red[(w * 64 + sgi * c.seg + l) * KM + k];
-        partial[item.poff + tid] = sum;
+                    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+                    if (lane == 0) rec[i] += x;
+                }
+                if (!resident) {
+                    __syncthreads();
+                    for (int q = lane; q < cnt; q += 64) out[gb + q] += rec[q];
+                }
+            }
+            const bool more = comp_next(w, L, ns);
+            if (!__any(more)) break;
+        }
+    }
+    if (resident) {
+        __syncthreads();
+        for (int q = lane; q < n; q += 64) out[q] = rec[q];
     }
 }
 
@@ -650,73 +707,46 @@ __global__ __launch_bounds__(kCompBlock) void statc_kernel(Params P, const float
 // Launchers
 // ------------------------------------------------------------------------------------
 
-#define FMB_COMP_DISPATCH(KM_, flags, CALL)                                                                \
+#define FMB_COMP_DISPATCH(flags, CALL)                                                                     \
     switch (flags) {                                                                                      \
-    case 0: CALL(KM_, 0); break;                                                                          \
-    case 1: CALL(KM_, 1); break;                                                                          \
-    case 2: CALL(KM_, 2); break;                                                                          \
-    case 3: CALL(KM_, 3); break;                                                                          \
-    case 8: CALL(KM_, 8); break;                                                                          \
-    case 9: CALL(KM_, 9); break;                                                                          \
-    case 10: CALL(KM_, 10); break;                                                                        \
-    case 11: CALL(KM_, 11); break;                                                                        \
+    case 0: CALL(0); break;                                                                               \
+    case 1: CALL(1); break;                                                                               \
+    case 2: CALL(2); break;                                                                               \
+    case 3: CALL(3); break;                                                                               \
+    case 8: CALL(8); break;                                                                               \
+    case 9: CALL(9); break;                                                                               \
+    case 10: CALL(10); break;                                                                             \
+    case 11: CALL(11); break;                                                                             \
     default: return hipErrorInvalidValue;                                                                 \
     }
 
-#define FMB_FWDC_CALL(KM_, F_)                                                                            \
-    hipLaunchKernelGGL((fwdc_kernel<KM_, F_>), dim3(n_items), dim3(kCompBlock), 0, st, P, O, items)
-#define FMB_BWDC_CALL(KM_, F_)                                                                            \
-    hipLaunchKernelGGL((bwdc_kernel<KM_, F_>), dim3(n_items), dim3(kCompBlock), 0, st, P, I, items, partial, \
-                       beta_partial)
+#define FMB_FWDC_CALL(F_) hipLaunchKernelGGL((fwdc_kernel<F_>), dim3(n_items), dim3(64), 0, st, P, O, items)
+#define FMB_BWDC_CALL(F_)                                                                                 \
+    hipLaunchKernelGGL((bwdc_kernel<F_>), dim3(n_items), dim3(64), 0, st, P, I, items, partial, beta_partial)
 
-hipError_t launch_fwdc(int km, int flags, int n_items, hipStream_t st, const Params &P, const FwdOut &O,
+hipError_t launch_fwdc(int flags, int n_items, hipStream_t st, const Params &P, const FwdOut &O,
                        const BwdItem *items)
 {
     flags &= ~kPer;
     if (n_items < 1) return hipSuccess;
-    if (km == 1) {
-        FMB_COMP_DISPATCH(1, flags, FMB_FWDC_CALL)
-    } else if (km == 2) {
-        FMB_COMP_DISPATCH(2, flags, FMB_FWDC_CALL)
-    } else if (km == 3) {
-        FMB_COMP_DISPATCH(3, flags, FMB_FWDC_CALL)
-    } else if (km == 4) {
-        FMB_COMP_DISPATCH(4, flags, FMB_FWDC_CALL)
-    } else {
-        return hipErrorInvalidValue;
-    }
+    FMB_COMP_DISPATCH(flags, FMB_FWDC_CALL)
     return hipGetLastError();
 }
 
-hipError_t launch_bwdc(int km, int flags, int n_items, hipStream_t st, const Params &P, const BwdIn &I,
+hipError_t launch_bwdc(int flags, int n_items, hipStream_t st, const Params &P, const BwdIn &I,
                        const BwdItem *items, float *partial, float *beta_partial)
 {
     flags &= ~kPer;
     if (n_items < 1) return hipSuccess;
-    if (km == 1) {
-        FMB_COMP_DISPATCH(1, flags, FMB_BWDC_CALL)
-    } else if (km == 2) {
-        FMB_COMP_DISPATCH(2, flags, FMB_BWDC_CALL)
-    } else if (km == 4) {
-        FMB_COMP_DISPATCH(4, flags, FMB_BWDC_CALL)
-    } else {
-        return hipErrorInvalidValue;
-    }
+    FMB_COMP_DISPATCH(flags, FMB_BWDC_CALL)
     return hipGetLastError();
 }
 
-hipError_t launch_statc(int km, int n_items, hipStream_t st, const Params &P, const float *loss, const float *stash,
+hipError_t launch_statc(int n_items, hipStream_t st, const Params &P, const float *loss, const float *stash,
                         const BwdItem *items, float *partial)
 {
     if (n_items < 1) return hipSuccess;
-    if (km == 1)
-        hipLaunchKernelGGL((statc_kernel<1>), dim3(n_items), dim3(kCompBlock), 0, st, P, loss, stash, items, partial);
-    else if (km == 2)
-        hipLaunchKernelGGL((statc_kernel<2>), dim3(n_items), dim3(kCompBlock), 0, st, P, loss, stash, items, partial);
-    else if (km == 4)
-        hipLaunchKernelGGL((statc_kernel<4>), dim3(n_items), dim3(kCompBlock), 0, st, P, loss, stash, items, partial);
-    else
-        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(statc_kernel, dim3(n_items), dim3(64), 0, st, P, loss, stash, items, partial);
     return hipGetLastError();
 }
 

@@ -90,18 +90,9 @@ struct StatTask {
 constexpr int kPartial = 10;       // per-Gaussian partial: dU (6), sum rho (3), dlog(lambda) (1)
 constexpr int kPartialColor = 13;  // ... and dL/d(colour) (3)
 
-// Zero-parameter (alpha-compositing) renderer: lanes per ray for a scene of n Gaussians (the
-// smallest power of two >= n / per_lane, at most 64, so a lane holds per_lane Gaussians, or up
-// to four beyond 64 per_lane, and the per-ray work of a segment is shared by that many pairs)
-// and the largest scene it takes (4 Gaussians per lane).
-constexpr int comp_seg(int n, int per_lane = 2)
-{
-    const int h = (n + per_lane - 1) / per_lane;
-    int s = 1;
-    while (s < h && s < 64) s <<= 1;
-    return s;
-}
-constexpr int kCompMaxN = 256;
+// Zero-parameter (alpha-compositing) renderer: ray tiles (ViewRec) per work item, one wave per
+// item.
+constexpr int kCompTiles = 16;
 
 // Kernel argument blocks (passed by value).
 struct Params {

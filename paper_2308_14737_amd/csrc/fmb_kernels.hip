@@ -566,34 +566,6 @@ __global__ __launch_bounds__(BLOCK) void bwdr_kernel(Params P, BwdIn I, const Bw
 // 34 % of (tile, Gaussian) pairs).
 // ------------------------------------------------------------------------------------
 
-// Sum over the wave of 16 values, scattered: halving exchanges 32, 16, 8 and 4 lanes apart
-// (each lane keeps half of its values and adds its partner's copy of that half), then a sum
-// over groups of 4 lanes.  Lane l ends with the total of value wave16_index(l); the order of
-// the additions is fixed.
-__device__ __forceinline__ int wave16_index(int lane)
-{
-    return ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1);
-}
-
-__device__ __forceinline__ float wave_sum16(const float x[16], int lane)
-{
-    float y[8], z[4], u[2];
-    bool up = (lane & 32) != 0;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) y[i] = (up ? x[i + 8] : x[i]) + __shfl_xor(up ? x[i] : x[i + 8], 32, 64);
-    up = (lane & 16) != 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) z[i] = (up ? y[i + 4] : y[i]) + __shfl_xor(up ? y[i] : y[i + 4], 16, 64);
-    up = (lane & 8) != 0;
-#pragma unroll
-    for (int i = 0; i < 2; ++i) u[i] = (up ? z[i + 2] : z[i]) + __shfl_xor(up ? z[i] : z[i + 2], 8, 64);
-    up = (lane & 4) != 0;
-    float s = (up ? u[1] : u[0]) + __shfl_xor(up ? u[0] : u[1], 4, 64);
-    s += __shfl_xor(s, 2, 64);
-    s += __shfl_xor(s, 1, 64);
-    return s;
-}
-
 template <int BLOCK, int T, int TG, int F>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void bwdt_kernel(
     Params P, BwdIn I, const BwdItem *__restrict__ items, int n_items, const int *__restrict__ order,

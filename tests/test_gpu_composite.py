@@ -1,10 +1,11 @@
 """GPU parity of the zero-parameter renderer (alpha compositing, Eq. 9-10) against the oracle.
 
 Every case renders through the C ABI with the compositing model selected and compares with
-the FP64 oracle's compositing model on the same seeded inputs: scene sizes that use one, two
-and four Gaussians per lane (N = 1 ... 256), ragged images, tied intersections, Gaussians
-behind the camera, colours and both flow directions, the batched path, and the gradient of the
-workload loss.
+the FP64 oracle's compositing model on the same seeded inputs: scene sizes from one Gaussian to
+scenes staged in several LDS tiles (N = 1 ... 600), clustered scenes whose tiles need several
+depth windows, the 10 000-Gaussian 1080p scene on sampled rays, ragged images, tied
+intersections, Gaussians behind the camera, colours and both flow directions, the batched path,
+and the gradient of the workload loss.
 """
 
 from __future__ import annotations
@@ -175,14 +176,13 @@ def test_composite_loss_gradient_fwdbwd128(fmb):
 
 
 def test_composite_batch(fmb):
-    """Batched compositing: scenes that all fit one Gaussian per lane match their single-scene
-    renders bit for bit; a batch mixing one and two Gaussians per lane matches the oracle."""
+    """Batched compositing: every scene of a batch matches its single-scene render bit for bit
+    (items never span scenes), and the batch matches the oracle."""
     w = W.make_config("batch16")
-    for idx, exact in (([2, 8, 10], True), ([1, 12, 3], False)):
+    for idx in ([2, 8, 10], [1, 12, 3]):
         scenes = [w.scenes[i] for i in idx]
         camsl = [w.cameras[i] for i in idx]
         ns = [s.n for s in scenes]
-        assert exact == (max(ns) <= 64), ns
         means = _t(np.concatenate([s.means for s in scenes]))
         prec = _t(np.concatenate([s.prec for s in scenes]))
         weights = _t(np.concatenate([s.weights for s in scenes]))
@@ -199,26 +199,24 @@ def test_composite_batch(fmb):
         for i in range(len(scenes)):
             r0, r1 = b.ray_off[i], b.ray_off[i + 1]
             g0, g1 = b.gauss_off[i], b.gauss_off[i + 1]
-            if exact:
-                scene = fmb.Scene(means[g0:g1], prec[g0:g1], weights[g0:g1], betas[i], w.eta, cams[i])
-                scene.set_model("composite")
-                so = scene.render(normals=True)
-                sg = scene.backward(so, cot["depth"][r0:r1], cot["alpha"][r0:r1], cot["normal"][r0:r1])
-                torch.cuda.synchronize()
-                for k in ("depth", "alpha", "normal", "stash"):
-                    assert torch.equal(outs[k][r0:r1], so[k]), (idx, i, k)
-                for k in ("means", "prec", "weights"):
-                    assert torch.equal(grads[k][g0:g1], sg[k]), (idx, i, k)
-            else:
-                ref, _, _ = O.render_workload_view(scenes[i], camsl[i], w.betas, w.eta, model="composite")
-                e = compare_forward({k: v[r0:r1] if v is not None else None for k, v in outs.items()}, ref)
-                _say(f"[composite-batch] scene {idx[i]} N={ns[i]} {e}")
-                assert_forward(e, f"batch scene {idx[i]}")
+            scene = fmb.Scene(means[g0:g1], prec[g0:g1], weights[g0:g1], betas[i], w.eta, cams[i])
+            scene.set_model("composite")
+            so = scene.render(normals=True)
+            sg = scene.backward(so, cot["depth"][r0:r1], cot["alpha"][r0:r1], cot["normal"][r0:r1])
+            torch.cuda.synchronize()
+            for k in ("depth", "alpha", "normal", "stash"):
+                assert torch.equal(outs[k][r0:r1], so[k]), (idx, i, k)
+            for k in ("means", "prec", "weights"):
+                assert torch.equal(grads[k][g0:g1], sg[k]), (idx, i, k)
+            ref, _, _ = O.render_workload_view(scenes[i], camsl[i], w.betas, w.eta, model="composite")
+            e = compare_forward({k: v[r0:r1] if v is not None else None for k, v in outs.items()}, ref)
+            _say(f"[composite-batch] scene {idx[i]} N={ns[i]} {e}")
+            assert_forward(e, f"batch scene {idx[i]}")
 
 
 def test_composite_model_switch(fmb):
     """Switching a scene between the two models gives each model's own result, and the
-    compositing model rejects scenes of more than 256 Gaussians."""
+    compositing model takes scenes of any size (here 257 Gaussians, two LDS tiles)."""
     sc, cams = custom_scene(20, [(16, 16)], seed=3)
     scene, _ = make_scene(fmb, torch, sc, cams, BETAS, 1.0, DEV)
     blend1 = scene.render(normals=False)["depth"].clone()
@@ -230,9 +228,98 @@ def test_composite_model_switch(fmb):
     assert torch.equal(blend1, blend2)
     assert not torch.equal(blend1, comp)
     big, bcams = custom_scene(257, [(4, 4)], seed=4)
-    bscene, _ = make_scene(fmb, torch, big, bcams, BETAS, 1.0, DEV)
-    with pytest.raises(fmb.FmbError):
-        bscene.set_model("composite")
+    bscene, _ = _composite_scene(fmb, big, bcams)
+    outs = bscene.render(normals=True)
+    torch.cuda.synchronize()
+    ref, _, _ = O.render_workload_view(big, bcams, BETAS, 1.0, model="composite")
+    e = compare_forward(outs, ref)
+    _say(f"[composite-switch] N=257 {e}")
+    assert_forward(e, "N=257 after the switch")
+
+
+def _cluster_scene(n, views, seed, spread):
+    """n Gaussians clustered around the origin (normal, standard deviation `spread`): the rays
+    through the centre pass all of them at significant densities, so their tiles take several
+    depth windows of the compositing kernels."""
+    _, cams = custom_scene(1, views, seed)
+    g = np.random.Generator(np.random.PCG64(seed + 1))
+    return W.make_scene(g, n, g.normal(0.0, spread, (n, 3))), cams
+
+
+WINDOWS = [
+    ("n90_resident", 90, [(24, 24)], 0.05),
+    ("n300_staged", 300, [(16, 20), (9, 7)], 0.08),
+    ("n600_staged", 600, [(12, 12)], 0.1),
+]
+
+
+@pytest.mark.parametrize("label,n,views,spread", WINDOWS, ids=[c[0] for c in WINDOWS])
+def test_composite_depth_windows(fmb, label, n, views, spread):
+    """Scenes whose central tiles have more significant intersections than the kernels' slots:
+    forward and gradients over several depth windows match the oracle."""
+    sc, cams = _cluster_scene(n, views, seed=n, spread=spread)
+    _say(f"[composite-windows] {label}: N={n} views={views}")
+    scene, _ = _composite_scene(fmb, sc, cams)
+    outs = scene.render(normals=True)
+    ref, _, _ = O.render_workload_view(sc, cams, BETAS, 1.0, model="composite")
+    cot = hit_mask_cot(W.random_cotangents(cams.n_rays, 9, flow=False), ref["alpha"])
+    g = scene.backward(outs, _t(cot["depth"]), _t(cot["alpha"]), _t(cot["normal"]))
+    torch.cuda.synchronize()
+    _, gref, _ = O.render_workload_view(sc, cams, BETAS, 1.0, cot=cot, model="composite")
+    e = compare_forward(outs, ref)
+    eg = compare_grads(g, gref)
+    _say(f"[composite-windows] {label}: {e} {eg}")
+    assert_forward(e, label)
+    assert_grads(eg, label)
+    # the plain adjoint (depth and alpha cotangents) over the same windows
+    cot2 = dict(cot, normal=None)
+    g2 = scene.backward(outs, _t(cot2["depth"]), _t(cot2["alpha"]), None)
+    torch.cuda.synchronize()
+    _, gref2, _ = O.render_workload_view(sc, cams, BETAS, 1.0, cot=cot2, model="composite")
+    eg2 = compare_grads(g2, gref2)
+    _say(f"[composite-windows] {label} plain: {eg2}")
+    assert_grads(eg2, label + " plain")
+
+
+def _hit_sample(alpha, k, seed):
+    """k ray indices, half of them among the rays that see the scene (alpha >= 0.01)."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    hit = np.flatnonzero(alpha >= 0.01)
+    a = g.choice(hit, size=min(k // 2, hit.size), replace=False)
+    b = g.choice(alpha.size, size=k - a.size, replace=False)
+    return np.unique(np.concatenate([a, b]))
+
+
+def test_composite_large1080(fmb):
+    """The 10 000-Gaussian 1080p scene with the compositing model: the forward on sampled rays
+    (half of them on the object, where the tiles take several depth windows) and the gradient of
+    random cotangents on a smaller sample, against the oracle on those rays."""
+    w = W.make_config("large1080")
+    sc, cams = w.scenes[0], w.cameras[0]
+    p = cams.n_rays
+    _say(f"[composite-large1080] N={sc.n} P={p}")
+    scene, _ = _composite_scene(fmb, sc, cams)
+    outs = scene.render(normals=True)
+    torch.cuda.synchronize()
+    alpha = to_np(outs["alpha"])
+    rays = _hit_sample(alpha, 96, 5)
+    ref, _, _ = O.render_workload_view(sc, cams, w.betas, w.eta, rays=rays, model="composite")
+    e = compare_forward(outs, ref, rays)
+    _say(f"[composite-large1080] forward on {rays.size} rays: {e}")
+    assert_forward(e, "large1080 composite")
+    brays = rays[::3]
+    cot = W.random_cotangents(p, 77, flow=False, normals=False)
+    mask = np.zeros(p, dtype=bool)
+    mask[brays] = True
+    for k in ("depth", "alpha"):
+        cot[k][~mask] = 0.0
+    g = scene.backward(outs, _t(cot["depth"]), _t(cot["alpha"]), None)
+    torch.cuda.synchronize()
+    cot_s = {"depth": cot["depth"][brays], "alpha": cot["alpha"][brays], "normal": None, "flow": None}
+    _, gref, _ = O.render_workload_view(sc, cams, w.betas, w.eta, rays=brays, cot=cot_s, model="composite")
+    eg = compare_grads(g, gref)
+    _say(f"[composite-large1080] gradient of {brays.size} rays: {eg}")
+    assert_grads(eg, "large1080 composite gradient")
 
 
 def test_composite_graph_replay(fmb):
