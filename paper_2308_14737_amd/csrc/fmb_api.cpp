@@ -46,14 +46,14 @@ hipError_t launch_loss(int p, const float *depth, const float *alpha, const floa
                        float *g_alpha, float *g_flow, float *g_color, float *block_loss, hipStream_t st);
 hipError_t launch_validate(const Params &P, int n_total, int n_scenes, int *flags, hipStream_t st);
 hipError_t launch_fwdc(int flags, int n_items, hipStream_t st, const Params &P, const FwdOut &O,
-                       const BwdItem *items);
+                       const BwdItem *items, const int *order);
 hipError_t launch_stat(int n_items, int n_tasks, int max_gc, hipStream_t st, const Params &P, const float *loss,
                        const float *stash, const BwdItem *items, const StatTask *tasks, float *partial,
                        const int64_t *rays_per_scene, float *lbar);
 hipError_t launch_statc(int n_items, hipStream_t st, const Params &P, const float *loss, const float *stash,
                         const BwdItem *items, float *partial);
 hipError_t launch_bwdc(int flags, int n_items, hipStream_t st, const Params &P, const BwdIn &I,
-                       const BwdItem *items, float *partial, float *beta_partial);
+                       const BwdItem *items, const int *order, float *partial, float *beta_partial);
 hipError_t occupancy_fwd(int variant, int flags, int *blocks_per_cu);
 hipError_t occupancy_bwd(int variant, int flags, int *blocks_per_cu);
 hipError_t scratch_base(void **out);
@@ -665,7 +665,7 @@ struct Job {
             int rc = (bwd_built == 1 || bwd_built == 3) ? FMB_OK : build_bwd(bwd_variant, prm.colors != nullptr);
             if (rc) return rc;
             TimedSpan ts(st, 0);
-            HIPCHK(launch_fwdc(fwd_flags(O, false), n_bitems, st, prm, O, d_bitems.as<BwdItem>()));
+            HIPCHK(launch_fwdc(fwd_flags(O, false), n_bitems, st, prm, O, d_bitems.as<BwdItem>(), d_border.as<int>()));
             ts.stop();
             return FMB_OK;
         }
@@ -697,7 +697,7 @@ struct Job {
         if (rc) return rc;
         if (model == FMB_MODEL_COMPOSITE) {
             TimedSpan tb(st, 1);
-            HIPCHK(launch_bwdc(bwd_flags(I, false), n_bitems, st, prm, I, d_bitems.as<BwdItem>(),
+            HIPCHK(launch_bwdc(bwd_flags(I, false), n_bitems, st, prm, I, d_bitems.as<BwdItem>(), d_border.as<int>(),
                                d_partial.as<float>(), d_bpart.as<float>()));
             tb.stop();
         } else {
@@ -775,7 +775,7 @@ struct Job {
         const int n_items = (int)pl.items.size();
         if (model == FMB_MODEL_COMPOSITE) {
             TimedSpan tb(st, 1);
-            HIPCHK(launch_bwdc(bwd_flags(I, false), n_items, st, prm, I, items, part, bpart));
+            HIPCHK(launch_bwdc(bwd_flags(I, false), n_items, st, prm, I, items, nullptr, part, bpart));
             tb.stop();
         } else {
             TimedSpan tb(st, 1);

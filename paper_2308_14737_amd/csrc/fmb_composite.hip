@@ -77,11 +77,25 @@ constexpr float kDepthScale = 0x1p100f;
 __device__ __forceinline__ float before(float a, float b) { return __builtin_amdgcn_fmed3f(b - a, 0.0f, 1.0f); }
 
 // Base-2 log of the smallest significant density of a scene of n Gaussians: the densities left
-// out of a front sum total less than n 2^sig <= 2^-24 (and 2^sig <= 2^-30).
+// out of a front sum total less than n 2^sig <= 2^-36 (and 2^sig <= 2^-30).
 __device__ __forceinline__ float comp_sig_log2(int n)
 {
     const int lg = n > 1 ? 32 - __clz(n - 1) : 0;  // ceil(log2 n)
-    return fminf(-30.0f, -24.0f - (float)lg);
+    return fminf(-30.0f, -36.0f - (float)lg);
+}
+
+// A ray whose largest base-2 log weight is at least this takes only its significant pairs: the
+// others weigh less than n 2^sig <= 2^-36 together, below 2^-24 of its sum of weights.
+constexpr float kCompHitLog2 = -12.0f;
+
+// Base-2 log of the smallest normalised weight (and density) whose pair terms are evaluated: the
+// weights of Eq. (9) fall off only as fast as the densities, so pairs far from a ray keep weights far
+// above FP32's zero, but all pairs below 2^skip together move a ray's sums by less than
+// n 2^skip <= 2^-26 of their value (and 2^skip <= 2^-40).
+__device__ __forceinline__ float comp_skip_log2(int n)
+{
+    const int lg = n > 1 ? 32 - __clz(n - 1) : 0;  // ceil(log2 n)
+    return fminf(-40.0f, -26.0f - (float)lg);
 }
 
 // A lane's slots: scaled depth and density of the significant intersection of the slot's
@@ -192,6 +206,82 @@ __device__ __forceinline__ Ent comp_ent(const float4 *__restrict__ ents, int i)
     return ent_from(ents[EW * i], ents[EW * i + 1], ents[EW * i + 2], ents[EW * i + 3]);
 }
 
+// Cone of a wave's rays: unit centre direction (uniform over the wave) and the cosine and sine of
+// the largest angle between it and a ray of the wave.
+struct TileCone {
+    float c0, c1, c2, ca, sa;
+};
+
+__device__ __forceinline__ float wave_sum_f(float x)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+__device__ __forceinline__ TileCone comp_cone(float v0, float v1, float v2, bool valid)
+{
+    float c0 = wave_sum_f(valid ? v0 : 0.0f), c1 = wave_sum_f(valid ? v1 : 0.0f), c2 = wave_sum_f(valid ? v2 : 0.0f);
+    c0 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(c0)));
+    c1 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(c1)));
+    c2 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(c2)));
+    const float inv = rsq_(fmaf(c0, c0, fmaf(c1, c1, fmaf(c2, c2, kEpsN))));
+    TileCone tc;
+    tc.c0 = c0 * inv;
+    tc.c1 = c1 * inv;
+    tc.c2 = c2 * inv;
+    float ca = valid ? fmaf(tc.c0, v0, fmaf(tc.c1, v1, tc.c2 * v2)) : 1.0f;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) ca = fminf(ca, __shfl_xor(ca, off, 64));
+    // margins for the rounding of the directions and of the cone
+    tc.ca = fminf(ca, 1.0f) - 1e-5f;
+    tc.sa = sqrtf(fmaxf(0.0f, 1.0f - tc.ca * tc.ca)) + 1e-5f;
+    return tc;
+}
+
+// Upper bound of the base-2 log density of Gaussian g on any ray of the cone (origin o): with
+// p = mu - o, the squared Mahalanobis distance of a ray line is at least d^2 / s^2, d the
+// Euclidean distance of mu from the line (at least |p| sin(angle(p, centre line) - cone angle))
+// and s^2 = |U^-1|_1 |U^-1|_inf at least the largest variance |U^-1|_2^2 (equal to it for an
+// axis-aligned Gaussian).
+__device__ __forceinline__ float comp_bound_log2(const Ent &g, const TileCone &tc)
+{
+    const float pp = fmaf(g.mh0, g.mh0, fmaf(g.mh1, g.mh1, g.mh2 * g.mh2));
+    const float pv = fabsf(fmaf(g.mh0, tc.c0, fmaf(g.mh1, tc.c1, g.mh2 * tc.c2)));
+    // |p x c| from the cross product (accurate also for p close to the centre line)
+    const float x0 = fmaf(g.mh1, tc.c2, -g.mh2 * tc.c1);
+    const float x1 = fmaf(g.mh2, tc.c0, -g.mh0 * tc.c2);
+    const float x2 = fmaf(g.mh0, tc.c1, -g.mh1 * tc.c0);
+    const float px = sqrtf(fmaf(x0, x0, fmaf(x1, x1, x2 * x2)));
+    const float d = fmaxf(0.0f, fmaf(px, tc.ca, -pv * tc.sa) - 1e-5f * sqrtf(pp));
+    // U^-1 of the upper-triangular U
+    const float i00 = rcp_(g.u00), i11 = rcp_(g.u11), i22 = rcp_(g.u22);
+    const float i01 = -g.u01 * i00 * i11, i12 = -g.u12 * i11 * i22;
+    const float i02 = (g.u01 * g.u12 - g.u02 * g.u11) * i00 * i11 * i22;
+    const float c1 = fmaxf(fabsf(i00), fmaxf(fabsf(i01) + fabsf(i11), fabsf(i02) + fabsf(i12) + fabsf(i22)));
+    const float r1 = fmaxf(fabsf(i00) + fabsf(i01) + fabsf(i02), fmaxf(fabsf(i11) + fabsf(i12), fabsf(i22)));
+    const float s2 = c1 * r1 * (1.0f + 1e-5f);
+    return fmaf((float)(-0.5 * kLog2e), d * d * rcp_(s2) * (1.0f - 1e-5f), g.l2l + 1e-5f);
+}
+
+// Staged Gaussians [0, cnt) whose bound on the cone exceeds thr, as two 64-bit masks (lane j
+// tests Gaussians j and 64 + j).
+__device__ __forceinline__ void comp_cull(const float4 *__restrict__ ents, int ew, int cnt, const TileCone &tc,
+                                          float thr, unsigned long long mask[2])
+{
+    static_assert(kCompTG == 128, "two 64-bit masks per staged tile");
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int i = 64 * c + (int)threadIdx.x;
+        bool keep = false;
+        if (i < cnt) {
+            const Ent g = ent_from(ents[ew * i], ents[ew * i + 1], ents[ew * i + 2], ents[ew * i + 3]);
+            keep = comp_bound_log2(g, tc) > thr;
+        }
+        mask[c] = __ballot(keep);
+    }
+}
+
 // The slots of window w: every Gaussian significant for some lane of the wave, with a depth behind
 // lo for that lane, takes the next slot; the densities at lo go to w.tie (and each such pair, whose
 // front sum is w.base, to on_tie(g, q, density, staged index)); a lane that meets one more than the
@@ -201,20 +291,21 @@ __device__ __forceinline__ Ent comp_ent(const float4 *__restrict__ ents, int i)
 template <int EW, class OnTie>
 __device__ __forceinline__ int comp_collect(const Params &P, const SceneRec &sr, const double o[3],
                                             float4 *__restrict__ ents, bool resident, float v0, float v1,
-                                            float v2, float hm, float sig2, CompWin &w, CompList L,
-                                            int *__restrict__ slot_g, OnTie on_tie)
+                                            float v2, float hm, float sig2, const TileCone &tc, CompWin &w,
+                                            CompList L, int *__restrict__ slot_g, OnTie on_tie)
 {
     int ns = 0;
     comp_clear(L);
     for (int gb = 0; gb < sr.n; gb += kCompTG) {
         const int cnt = min(kCompTG, sr.n - gb);
         if (!resident) comp_stage<EW>(P, sr, gb, cnt, o, ents);
-        for (int i = 0; i < cnt; ++i) {
-            const Ent g = comp_ent<EW>(ents, i);
-            Geo q;
-            pair_geo_coarse(g, v0, v1, v2, hm, 0.0f, 0.0f, q);
+        // only the Gaussians that can be significant on some ray of the wave
+        unsigned long long mask[2];
+        comp_cull(ents, EW, cnt, tc, sig2, mask);
+        // the pair's share of the window: tie, slot or (a full list) the end of the window
+        auto take = [&](const Ent &g, const Geo &q, int i) {
             const bool sig = q.d2 > sig2;
-            if (!__any(sig)) continue;
+            if (!__any(sig)) return;
             const float ts = q.t * kDepthScale;
             const float dl = exp2_(q.d2);
             if (sig && ts == w.lo) {
@@ -222,13 +313,30 @@ __device__ __forceinline__ int comp_collect(const Params &P, const SceneRec &sr,
                 on_tie(g, q, dl, i);
             }
             const bool cand = sig && ts > w.lo;
-            if (!__any(cand)) continue;
+            if (!__any(cand)) return;
             if (ns < kCompSlots) {
                 comp_push(L, ts, cand ? dl : 0.0f);
                 if (slot_g && threadIdx.x == 0) slot_g[ns] = gb + i;
                 ns = __builtin_amdgcn_readfirstlane(ns + 1);
             } else if (cand) {
                 w.hi = fminf(w.hi, ts);
+            }
+        };
+        // two candidates a step, their geometry computed together (two independent chains)
+        for (int c = 0; c < 2; ++c) {
+            unsigned long long mk = mask[c];
+            while (mk) {
+                const int ia = 64 * c + __builtin_ctzll(mk);
+                mk &= mk - 1;
+                const bool two = mk != 0;
+                const int ib = two ? 64 * c + __builtin_ctzll(mk) : ia;
+                if (two) mk &= mk - 1;
+                const Ent ga = comp_ent<EW>(ents, ia), gb2 = comp_ent<EW>(ents, ib);
+                Geo qa, qb;
+                pair_geo_coarse(ga, v0, v1, v2, hm, 0.0f, 0.0f, qa);
+                pair_geo_coarse(gb2, v0, v1, v2, hm, 0.0f, 0.0f, qb);
+                take(ga, qa, ia);
+                if (two) take(gb2, qb, ib);
             }
         }
     }
@@ -259,13 +367,15 @@ __device__ __forceinline__ bool comp_next(CompWin &w, const CompList L, int ns)
 // ------------------------------------------------------------------------------------
 
 template <int F>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kFwdcWaves))) void fwdc_kernel(Params P, FwdOut O, const BwdItem *__restrict__ items)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kFwdcWaves))) void fwdc_kernel(Params P, FwdOut O, const BwdItem *__restrict__ items,
+                                                                                                      const int *__restrict__ order)
 {
     constexpr bool NORMALS = (F & kNrm) != 0, COLOR = (F & kCol) != 0;
     constexpr int EW = COLOR ? 5 : 4;
     __shared__ float4 ents[kCompTG * EW];
+    __shared__ int slot_g[kCompSlots];
     const int lane = threadIdx.x;
-    const BwdItem item = ld_uniform(items + blockIdx.x);
+    const BwdItem item = ld_uniform(items + (order ? ld_uniform(order + blockIdx.x) : (int)blockIdx.x));
     const ViewRec vr = ld_uniform(P.views + item.view);
     const SceneRec sr = ld_uniform(P.scenes + vr.scene);
     const CamRec cam = cam_of(P, item.view);
@@ -274,7 +384,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kFwdcWaves))
     cam_centre(e, o);
     const float o0 = (float)o[0], o1 = (float)o[1], o2 = (float)o[2];
     const float hm = (float)(-0.5 * kLog2e);
-    const float sig2 = comp_sig_log2(sr.n);
+    const float sig2 = comp_sig_log2(sr.n), skip2 = comp_skip_log2(sr.n);
     const bool resident = sr.n <= kCompTG;
     if (resident) comp_stage<EW>(P, sr, 0, sr.n, o, ents);
     const int nt = min(item.span, vr.tiles - item.ray0);  // ray0: the item's first tile
@@ -290,61 +400,96 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kFwdcWaves))
             at = O.alpha_t[vr.ray_off + loc];
             dt = O.depth_t[vr.ray_off + loc];
         }
-        float M = -INFINITY, S = 0.0f, T = 0.0f, N0 = 0.0f, N1 = 0.0f, N2 = 0.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-        float D = 0.0f;
+        const TileCone tc = comp_cone(v0, v1, v2, valid);
+        float M, S, T, N0, N1, N2, C0, C1, C2, D;
+        auto reset = [&]() {
+            M = -INFINITY;
+            S = T = N0 = N1 = N2 = C0 = C1 = C2 = D = 0.0f;
+        };
+        reset();
         CompWin w{valid ? -INFINITY : INFINITY, INFINITY, 0.0f, 0.0f};
-        bool more = valid;
         CompList L;
-        while (__any(more)) {
-            const int ns = comp_collect<EW>(P, sr, o, ents, resident, v0, v1, v2, hm, sig2, w, L, nullptr,
-                                            [](const Ent &, const Geo &, float, int) {});
+        // blends pair (g, q) of this lane at front sum fs; ci: the staged index of its colour
+        auto blend = [&](const Ent &g, Geo &q, float fs, int ci) {
+            const float delta = exp2_(q.d2);
+            D += delta;
+            const float lw = fmaf(-(float)kLog2e, fs, log2_opacity(delta, q.d2));
+            if (lw > M) {  // new running maximum: rescale the sums
+                const float sc = exp2_(M - lw);
+                S *= sc;
+                T *= sc;
+                N0 *= sc;
+                N1 *= sc;
+                N2 *= sc;
+                C0 *= sc;
+                C1 *= sc;
+                C2 *= sc;
+                M = lw;
+            }
+            const float ew = exp2_(lw - M);
+            S += ew;
+            T = fmaf(ew, q.t, T);
+            if (NORMALS) {
+                pair_refine(q);
+                const PairNormal pn = pair_normal(g, q, 0.0f, 0.0f, 0.0f);
+                N0 = fmaf(ew, pn.n0, N0);
+                N1 = fmaf(ew, pn.n1, N1);
+                N2 = fmaf(ew, pn.n2, N2);
+            }
+            if (COLOR) {
+                const float4 cc = ents[EW * ci + 4];
+                C0 = fmaf(ew, cc.x, C0);
+                C1 = fmaf(ew, cc.y, C1);
+                C2 = fmaf(ew, cc.z, C2);
+            }
+        };
+        const auto no_tie = [](const Ent &, const Geo &, float, int) {};
+        int ns = comp_collect<EW>(P, sr, o, ents, resident, v0, v1, v2, hm, sig2, tc, w, L, slot_g, no_tie);
+
+        // A tile of one window whose rays all weigh at least 2^kCompHitLog2 somewhere blends only the
+        // significant pairs (the slots' Gaussians), each ray its own.
+        bool done = false;
+        // (a ray without a significant intersection cannot qualify)
+        float own = 0.0f;
+#pragma unroll
+        for (int k = 0; k < kCompSlots; ++k) own += SLOT_D(L, k);
+        if (resident && ns > 0 && !__any(w.hi != INFINITY) && __all(!valid || own > 0.0f)) {
+            for (int s = 0; s < ns; s += 2) {  // two slots a step (two independent chains)
+                const bool two = s + 1 < ns;
+                const int ia = slot_g[s], ib = two ? slot_g[s + 1] : ia;
+                const Ent ga = comp_ent<EW>(ents, ia), gb = comp_ent<EW>(ents, ib);
+                Geo qa, qb;
+                pair_geo_coarse(ga, v0, v1, v2, hm, 0.0f, 0.0f, qa);
+                pair_geo_coarse(gb, v0, v1, v2, hm, 0.0f, 0.0f, qb);
+                if (valid && qa.d2 > sig2) blend(ga, qa, comp_front(L, ns, w, qa.t * kDepthScale), ia);
+                if (two && valid && qb.d2 > sig2) blend(gb, qb, comp_front(L, ns, w, qb.t * kDepthScale), ib);
+            }
+            done = __all(!valid || M >= kCompHitLog2);
+            if (!done) reset();
+        }
+        // Otherwise every pair of every window (a tile that sees background or several windows).
+        while (!done) {
             for (int gb = 0; gb < sr.n; gb += kCompTG) {
                 const int cnt = min(kCompTG, sr.n - gb);
                 if (!resident) comp_stage<EW>(P, sr, gb, cnt, o, ents);
-                for (int i = 0; i < cnt; ++i) {
-                    const Ent g = comp_ent<EW>(ents, i);
-                    Geo q;
-                    pair_geo_coarse(g, v0, v1, v2, hm, 0.0f, 0.0f, q);
-                    const float ts = q.t * kDepthScale;
+                for (int i = 0; i < cnt; i += 2) {  // two Gaussians a step (two independent chains)
+                    const bool two = i + 1 < cnt;
+                    const Ent ga = comp_ent<EW>(ents, i), gb = comp_ent<EW>(ents, two ? i + 1 : i);
+                    Geo qa, qb;
+                    pair_geo_coarse(ga, v0, v1, v2, hm, 0.0f, 0.0f, qa);
+                    pair_geo_coarse(gb, v0, v1, v2, hm, 0.0f, 0.0f, qb);
                     // a pair of this window whose weight (at most its density) is not below
-                    // 2^-150 of the running maximum, where it would be zero in FP32
-                    const bool live = ts >= w.lo && ts < w.hi && q.d2 - M >= kSkipLog2;
-                    if (!__any(live)) continue;
-                    if (!live) continue;
-                    const float delta = exp2_(q.d2);
-                    D += delta;
-                    float lw = fmaf(-(float)kLog2e, comp_front(L, ns, w, ts), log2_opacity(delta, q.d2));
-                    if (lw > M) {  // new running maximum: rescale the sums
-                        const float sc = exp2_(M - lw);
-                        S *= sc;
-                        T *= sc;
-                        N0 *= sc;
-                        N1 *= sc;
-                        N2 *= sc;
-                        C0 *= sc;
-                        C1 *= sc;
-                        C2 *= sc;
-                        M = lw;
-                    }
-                    const float ew = exp2_(lw - M);
-                    S += ew;
-                    T = fmaf(ew, q.t, T);
-                    if (NORMALS) {
-                        pair_refine(q);
-                        const PairNormal pn = pair_normal(g, q, 0.0f, 0.0f, 0.0f);
-                        N0 = fmaf(ew, pn.n0, N0);
-                        N1 = fmaf(ew, pn.n1, N1);
-                        N2 = fmaf(ew, pn.n2, N2);
-                    }
-                    if (COLOR) {
-                        const float4 cc = ents[EW * i + 4];
-                        C0 = fmaf(ew, cc.x, C0);
-                        C1 = fmaf(ew, cc.y, C1);
-                        C2 = fmaf(ew, cc.z, C2);
-                    }
+                    // 2^skip2 of the running maximum (nor is its density below 2^skip2, as M <= 0)
+                    const float tsa = qa.t * kDepthScale, tsb = qb.t * kDepthScale;
+                    const bool la = tsa >= w.lo && tsa < w.hi && qa.d2 - M >= skip2;
+                    if (__any(la) && la) blend(ga, qa, comp_front(L, ns, w, tsa), i);
+                    const bool lb = two && tsb >= w.lo && tsb < w.hi && qb.d2 - M >= skip2;
+                    if (__any(lb) && lb) blend(gb, qb, comp_front(L, ns, w, tsb), i + 1);
                 }
             }
-            more = comp_next(w, L, ns);
+            const bool more = comp_next(w, L, ns);
+            if (!__any(more)) break;
+            ns = comp_collect<EW>(P, sr, o, ents, resident, v0, v1, v2, hm, sig2, tc, w, L, slot_g, no_tie);
         }
         if (valid)
             write_ray<F>(P, O, item.view, vr.ray_off + loc, e, kk, o0, o1, o2, v0, v1, v2, M, S, T, N0, N1, N2, C0,
@@ -358,7 +503,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kFwdcWaves))
 
 template <int F>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))) void bwdc_kernel(Params P, BwdIn I, const BwdItem *__restrict__ items,
-                                                  float *__restrict__ partial, float *__restrict__ beta_partial)
+                                                  const int *__restrict__ order, float *__restrict__ partial,
+                                                  float *__restrict__ beta_partial)
 {
     constexpr bool NORMALS = (F & kNrm) != 0, COLOR = (F & kCol) != 0;
     // without a normal cotangent the pairs take the offset form of the adjoint
@@ -375,7 +521,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
     __shared__ int slot_g[kCompSlots];
     __shared__ int touched[kCompTG];
     const int lane = threadIdx.x;
-    const BwdItem item = ld_uniform(items + blockIdx.x);
+    const BwdItem item = ld_uniform(items + (order ? ld_uniform(order + blockIdx.x) : (int)blockIdx.x));
     const ViewRec vr = ld_uniform(P.views + item.view);
     const SceneRec sr = ld_uniform(P.scenes + vr.scene);
     const CamRec cam = cam_of(P, item.view);
@@ -384,7 +530,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
     cam_centre(e, o);
     const float o0 = (float)o[0], o1 = (float)o[1], o2 = (float)o[2];
     const float hm = (float)(-0.5 * kLog2e);
-    const float sig2 = comp_sig_log2(sr.n);
+    const float sig2 = comp_sig_log2(sr.n), skip2 = comp_skip_log2(sr.n);
     const int n = sr.n;
     const bool resident = n <= kCompTG;
     float *__restrict__ prec_out = partial + item.poff;
@@ -408,13 +554,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
         const float invS = pr[1].x, tfb = pr[1].y, nb0 = pr[1].z, nb1 = pr[1].w;
         const float nb2 = pr[2].x, kap = pr[2].y, Db = pr[2].z;
         const float cb0 = pr[3].x, cb1 = pr[3].y, cb2 = pr[3].z;
-        // a normalised weight 2^(lw - M2) / S is zero in FP32 where lw < M2 + log2 S - 150, and
-        // lw is at most the log2 density
-        const float wskip = valid ? M2 - __builtin_amdgcn_logf(invS) + kSkipLog2 : INFINITY;
+        // a normalised weight 2^(lw - M2) / S is below 2^skip2 where lw < M2 + log2 S + skip2,
+        // and lw is at most the log2 density
+        const float wskip = valid ? M2 - __builtin_amdgcn_logf(invS) + skip2 : INFINITY;
         const CompWin w0{valid ? -INFINITY : INFINITY, INFINITY, 0.0f, 0.0f};
         CompWin w = w0;
         CompList L;
         float zs[kCompSlots];
+        const TileCone tc = comp_cone(v0, v1, v2, valid);
 
         // z_bar of the slots' own pairs (the lanes' significant intersections of the window)
         // (pushed in staging order, so that zs[k] belongs to slot k)
@@ -430,14 +577,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
                 }
                 __syncthreads();
             }
-            for (int s = 0; s < ns; ++s) {
-                const int gs = resident ? slot_g[s] : s;
-                const float4 *src = resident ? ents : sents;
-                const Ent g = comp_ent<EW>(src, gs);
-                Geo q;
-                pair_geo_coarse(g, v0, v1, v2, hm, 0.0f, 0.0f, q);
+            const float4 *src = resident ? ents : sents;
+            // z_bar of the lane's pair (g, q) when the slot holds it: significant and in the window
+            auto own_z = [&](const Ent &g, Geo &q, int gs) {
                 const float ts = q.t * kDepthScale;
-                // the slot holds the lane's intersection when it is significant and in the window
                 const bool own = q.d2 > sig2 && ts > w.lo && ts < w.hi;
                 float z = 0.0f;
                 if (__any(own) && own) {
@@ -455,6 +598,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
                     z = wt * (lin - kap);
                 }
                 comp_push_z(zs, z);
+            };
+            for (int s = 0; s < ns; s += 2) {  // two slots a step (two independent chains)
+                const bool two = s + 1 < ns;
+                const int ga_i = resident ? slot_g[s] : s;
+                const int gb_i = two ? (resident ? slot_g[s + 1] : s + 1) : ga_i;
+                const Ent ga = comp_ent<EW>(src, ga_i), gb = comp_ent<EW>(src, gb_i);
+                Geo qa, qb;
+                pair_geo_coarse(ga, v0, v1, v2, hm, 0.0f, 0.0f, qa);
+                pair_geo_coarse(gb, v0, v1, v2, hm, 0.0f, 0.0f, qb);
+                own_z(ga, qa, ga_i);
+                if (two) own_z(gb, qb, gb_i);
             }
         };
 
@@ -486,7 +640,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
 
         // First sweep, for tiles that take several windows: the sum of z_bar over all significant
         // intersections of each ray, so that a window knows the z_bar of the windows behind it.
-        int ns = comp_collect<EW>(P, sr, o, ents, resident, v0, v1, v2, hm, sig2, w, L, slot_g, on_tie);
+        int ns = comp_collect<EW>(P, sr, o, ents, resident, v0, v1, v2, hm, sig2, tc, w, L, slot_g, on_tie);
         float zall = 0.0f;
         if (__any(w.hi != INFINITY)) {
             bool more = true;
@@ -496,12 +650,68 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
                 more = comp_next(w, L, ns);
                 if (!__any(more)) break;
                 ztie = 0.0f;
-                ns = comp_collect<EW>(P, sr, o, ents, resident, v0, v1, v2, hm, sig2, w, L, slot_g, on_tie);
+                ns = comp_collect<EW>(P, sr, o, ents, resident, v0, v1, v2, hm, sig2, tc, w, L, slot_g, on_tie);
             }
             w = w0;
             ztie = 0.0f;
-            ns = comp_collect<EW>(P, sr, o, ents, resident, v0, v1, v2, hm, sig2, w, L, slot_g, on_tie);
+            ns = comp_collect<EW>(P, sr, o, ents, resident, v0, v1, v2, hm, sig2, tc, w, L, slot_g, on_tie);
         }
+
+        // A tile of one window whose rays all weigh at least 2^kCompHitLog2 somewhere (the forward's
+        // test, on its stashed maximum) takes only the slots' Gaussians, each ray its own pairs.
+        const bool hit_tile = resident && ns > 0 && !__any(w.hi != INFINITY) && __all(!valid || M2 >= kCompHitLog2);
+
+        // Adjoint terms of this lane's pair (g, q) of Gaussian staged at index i (live: the lane
+        // has the pair), summed over the wave and added to the Gaussian's sums rec[LREC r ...].
+        auto pair_terms = [&](const Ent &g, Geo &q, float ts, bool live, int i, int r, float zafter) {
+            PairAcc acc;
+            OffsetAcc oacc;
+            float aC0 = 0.0f, aC1 = 0.0f, aC2 = 0.0f;
+            if (live) {
+                const float delta = exp2_(q.d2);
+                const float lw = fmaf(-(float)kLog2e, comp_front(L, ns, w, ts), log2_opacity(delta, q.d2));
+                const float wt = exp2_(lw - M2) * invS;
+                PairNormal pn{0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+                if (NORMALS) {
+                    pair_refine(q);
+                    pn = pair_normal(g, q, nb0, nb1, nb2);
+                }
+                float lin = fmaf(tfb, q.t, pn.nN);
+                if (COLOR) {
+                    const float4 cc = ents[EW * i + 4];
+                    lin = fmaf(cb0, cc.x, fmaf(cb1, cc.y, fmaf(cb2, cc.z, lin)));
+                    aC0 = wt * cb0;
+                    aC1 = wt * cb1;
+                    aC2 = wt * cb2;
+                }
+                const float zb = wt * (lin - kap);
+                const float bsum = zafter + comp_behind(L, zs, ns, ts);
+                const float db = fmaf(zb, opacity_slope(delta), delta * (Db - bsum));
+                const float tb = wt * tfb;
+                if (PLAIN)
+                    pair_adjoint_offset(q, v0, v1, v2, tb, db, oacc);
+                else
+                    pair_adjoint<NORMALS>(g, q, v0, v1, v2, wt, pn, nb0, nb1, nb2, tb, db, acc);
+            }
+            float x[16];
+            if (PLAIN) {
+                offset_acc_store(oacc, x);
+            } else {
+                x[0] = acc.u0; x[1] = acc.u1; x[2] = acc.u2; x[3] = acc.u3; x[4] = acc.u4; x[5] = acc.u5;
+                x[6] = acc.p0; x[7] = acc.p1; x[8] = acc.p2; x[9] = acc.l;
+            }
+            constexpr int B0 = PLAIN ? kOffsetAcc : kPartial;
+#pragma unroll
+            for (int c = B0; c < 16; ++c) x[c] = 0.0f;
+            if (COLOR) {
+                x[B0] = aC0;
+                x[B0 + 1] = aC1;
+                x[B0 + 2] = aC2;
+            }
+            const float tot = wave_sum16(x, lane);
+            const int idx = wave16_index(lane);
+            if ((lane & 3) == 0 && idx < LREC) rec[LREC * r + idx] += tot;
+        };
 
         float zthrough = 0.0f;
         for (;;) {
@@ -510,91 +720,67 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
             // z_bar of the significant intersections behind this window
             const float zafter = w.hi == INFINITY ? 0.0f : zall - zthrough;
 
-            for (int gb = 0; gb < n; gb += kCompTG) {
-                const int cnt = min(kCompTG, n - gb);
-                if (!resident) {
-                    comp_stage<EW>(P, sr, gb, cnt, o, ents);
-                    for (int q = lane; q < cnt * LREC; q += 64) rec[q] = 0.0f;
-                    for (int q = lane; q < cnt; q += 64) touched[q] = 0;
-                    __syncthreads();
+            if (hit_tile) {
+                for (int s = 0; s < ns; s += 2) {  // two slots a step (two independent chains)
+                    const bool two = s + 1 < ns;
+                    const int ia = slot_g[s], ib = two ? slot_g[s + 1] : ia;
+                    const Ent ga = comp_ent<EW>(ents, ia), gb = comp_ent<EW>(ents, ib);
+                    Geo qa, qb;
+                    pair_geo_coarse(ga, v0, v1, v2, hm, 0.0f, 0.0f, qa);
+                    pair_geo_coarse(gb, v0, v1, v2, hm, 0.0f, 0.0f, qb);
+                    pair_terms(ga, qa, qa.t * kDepthScale, valid && qa.d2 > sig2, ia, ia, zafter);
+                    if (two) pair_terms(gb, qb, qb.t * kDepthScale, valid && qb.d2 > sig2, ib, ib, zafter);
                 }
-                for (int i = 0; i < cnt; ++i) {
-                    const Ent g = comp_ent<EW>(ents, i);
-                    Geo q;
-                    pair_geo_coarse(g, v0, v1, v2, hm, 0.0f, 0.0f, q);
-                    const float ts = q.t * kDepthScale;
-                    // a pair of this window with a weight or a density that is not zero in FP32
-                    const bool live = ts >= w.lo && ts < w.hi && q.d2 >= fminf(kSkipLog2, wskip);
-                    if (!__any(live)) continue;
-                    PairAcc acc;
-                    OffsetAcc oacc;
-                    float aC0 = 0.0f, aC1 = 0.0f, aC2 = 0.0f;
-                    if (live) {
-                        const float delta = exp2_(q.d2);
-                        const float lw = fmaf(-(float)kLog2e, comp_front(L, ns, w, ts), log2_opacity(delta, q.d2));
-                        const float wt = exp2_(lw - M2) * invS;
-                        PairNormal pn{0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-                        if (NORMALS) {
-                            pair_refine(q);
-                            pn = pair_normal(g, q, nb0, nb1, nb2);
+            } else {
+                for (int gb = 0; gb < n; gb += kCompTG) {
+                    const int cnt = min(kCompTG, n - gb);
+                    if (!resident) {
+                        comp_stage<EW>(P, sr, gb, cnt, o, ents);
+                        for (int q = lane; q < cnt * LREC; q += 64) rec[q] = 0.0f;
+                        for (int q = lane; q < cnt; q += 64) touched[q] = 0;
+                        __syncthreads();
+                    }
+                    for (int i = 0; i < cnt; i += 2) {  // two Gaussians a step (two independent chains)
+                        const bool two = i + 1 < cnt;
+                        const Ent ga = comp_ent<EW>(ents, i), gb = comp_ent<EW>(ents, two ? i + 1 : i);
+                        Geo qa, qb;
+                        pair_geo_coarse(ga, v0, v1, v2, hm, 0.0f, 0.0f, qa);
+                        pair_geo_coarse(gb, v0, v1, v2, hm, 0.0f, 0.0f, qb);
+                        // a pair of this window with a normalised weight or a density not below 2^skip2
+                        const float tsa = qa.t * kDepthScale, tsb = qb.t * kDepthScale;
+                        const float lim = fminf(skip2, wskip);
+                        const bool la = tsa >= w.lo && tsa < w.hi && qa.d2 >= lim;
+                        if (__any(la)) {
+                            pair_terms(ga, qa, tsa, la, i, i, zafter);
+                            if (!resident && lane == 0) touched[i] = 1;
                         }
-                        float lin = fmaf(tfb, q.t, pn.nN);
-                        if (COLOR) {
-                            const float4 cc = ents[EW * i + 4];
-                            lin = fmaf(cb0, cc.x, fmaf(cb1, cc.y, fmaf(cb2, cc.z, lin)));
-                            aC0 = wt * cb0;
-                            aC1 = wt * cb1;
-                            aC2 = wt * cb2;
+                        const bool lb = two && tsb >= w.lo && tsb < w.hi && qb.d2 >= lim;
+                        if (__any(lb)) {
+                            pair_terms(gb, qb, tsb, lb, i + 1, i + 1, zafter);
+                            if (!resident && lane == 0) touched[i + 1] = 1;
                         }
-                        const float zb = wt * (lin - kap);
-                        const float bsum = zafter + comp_behind(L, zs, ns, ts);
-                        const float db = fmaf(zb, opacity_slope(delta), delta * (Db - bsum));
-                        const float tb = wt * tfb;
-                        if (PLAIN)
-                            pair_adjoint_offset(q, v0, v1, v2, tb, db, oacc);
-                        else
-                            pair_adjoint<NORMALS>(g, q, v0, v1, v2, wt, pn, nb0, nb1, nb2, tb, db, acc);
                     }
-                    float x[16];
-                    if (PLAIN) {
-                        offset_acc_store(oacc, x);
-                    } else {
-                        x[0] = acc.u0; x[1] = acc.u1; x[2] = acc.u2; x[3] = acc.u3; x[4] = acc.u4; x[5] = acc.u5;
-                        x[6] = acc.p0; x[7] = acc.p1; x[8] = acc.p2; x[9] = acc.l;
-                    }
-                    constexpr int B0 = PLAIN ? kOffsetAcc : kPartial;
-#pragma unroll
-                    for (int c = B0; c < 16; ++c) x[c] = 0.0f;
-                    if (COLOR) {
-                        x[B0] = aC0;
-                        x[B0 + 1] = aC1;
-                        x[B0 + 2] = aC2;
-                    }
-                    const float tot = wave_sum16(x, lane);
-                    const int idx = wave16_index(lane);
-                    if ((lane & 3) == 0 && idx < LREC) rec[LREC * i + idx] += tot;
-                    if (!resident && lane == 0) touched[i] = 1;
-                }
-                if (!resident) {
-                    // add the tile's sums of this window to the item's record
-                    __syncthreads();
-                    for (int qq = lane; qq < cnt; qq += 64) {
-                        if (!touched[qq]) continue;
-                        const int gg = sr.gauss_off + gb + qq;
-                        float r[kPartialColor];
-                        if (PLAIN)
-                            write_partial_offset(r, rec + LREC * qq, REC, P.prec + 6 * gg, P.means + 3 * gg, o);
-                        else
-                            write_partial(r, rec + LREC * qq, REC, P.means + 3 * gg, o);
-                        float *dst = prec_out + REC * (gb + qq);
-                        for (int c = 0; c < REC; ++c) dst[c] += r[c];
+                    if (!resident) {
+                        // add the tile's sums of this window to the item's record
+                        __syncthreads();
+                        for (int qq = lane; qq < cnt; qq += 64) {
+                            if (!touched[qq]) continue;
+                            const int gg = sr.gauss_off + gb + qq;
+                            float r[kPartialColor];
+                            if (PLAIN)
+                                write_partial_offset(r, rec + LREC * qq, REC, P.prec + 6 * gg, P.means + 3 * gg, o);
+                            else
+                                write_partial(r, rec + LREC * qq, REC, P.means + 3 * gg, o);
+                            float *dst = prec_out + REC * (gb + qq);
+                            for (int c = 0; c < REC; ++c) dst[c] += r[c];
+                        }
                     }
                 }
             }
             const bool more = comp_next(w, L, ns);
             if (!__any(more)) break;
             ztie = 0.0f;
-            ns = comp_collect<EW>(P, sr, o, ents, resident, v0, v1, v2, hm, sig2, w, L, slot_g, on_tie);
+            ns = comp_collect<EW>(P, sr, o, ents, resident, v0, v1, v2, hm, sig2, tc, w, L, slot_g, on_tie);
         }
     }
 
@@ -621,10 +807,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kFwdcWaves))
                                                    const BwdItem *__restrict__ items, float *__restrict__ partial)
 {
     constexpr int EW = 4;
+    const int *order = nullptr;
     __shared__ float4 ents[kCompTG * EW];
     __shared__ float rec[kCompTG];
+    __shared__ int slot_g[kCompSlots];
     const int lane = threadIdx.x;
-    const BwdItem item = ld_uniform(items + blockIdx.x);
+    const BwdItem item = ld_uniform(items + (order ? ld_uniform(order + blockIdx.x) : (int)blockIdx.x));
     const ViewRec vr = ld_uniform(P.views + item.view);
     const SceneRec sr = ld_uniform(P.scenes + vr.scene);
     const CamRec cam = cam_of(P, item.view);
@@ -632,7 +820,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kFwdcWaves))
     double o[3];
     cam_centre(e, o);
     const float hm = (float)(-0.5 * kLog2e);
-    const float sig2 = comp_sig_log2(sr.n);
+    const float sig2 = comp_sig_log2(sr.n), skip2 = comp_skip_log2(sr.n);
     const int n = sr.n;
     const bool resident = n <= kCompTG;
     float *__restrict__ out = partial + item.poff;
@@ -658,12 +846,33 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kFwdcWaves))
             invS = s0.y;
             lr = loss[r];
         }
-        const float wskip = valid ? M2 - __builtin_amdgcn_logf(invS) + kSkipLog2 : INFINITY;
+        const float wskip = valid ? M2 - __builtin_amdgcn_logf(invS) + skip2 : INFINITY;
         CompWin w{valid ? -INFINITY : INFINITY, INFINITY, 0.0f, 0.0f};
         CompList L;
-        for (;;) {
-            const int ns = comp_collect<EW>(P, sr, o, ents, resident, v0, v1, v2, hm, sig2, w, L, nullptr,
-                                            [](const Ent &, const Geo &, float, int) {});
+        const TileCone tc = comp_cone(v0, v1, v2, valid);
+        const auto no_tie = [](const Ent &, const Geo &, float, int) {};
+        for (bool first = true;; first = false) {
+            const int ns = comp_collect<EW>(P, sr, o, ents, resident, v0, v1, v2, hm, sig2, tc, w, L, slot_g, no_tie);
+            // as in the forward: a tile of one window whose rays all weigh at least 2^kCompHitLog2
+            // somewhere takes only the slots' Gaussians
+            if (first && resident && ns > 0 && !__any(w.hi != INFINITY) && __all(!valid || M2 >= kCompHitLog2)) {
+                for (int s = 0; s < ns; ++s) {
+                    const int gi = slot_g[s];
+                    const Ent g = comp_ent<EW>(ents, gi);
+                    Geo q;
+                    pair_geo_coarse(g, v0, v1, v2, hm, 0.0f, 0.0f, q);
+                    const float ts = q.t * kDepthScale;
+                    float x = 0.0f;
+                    if (valid && q.d2 > sig2) {
+                        const float lw = fmaf(-(float)kLog2e, comp_front(L, ns, w, ts), log2_opacity(exp2_(q.d2), q.d2));
+                        x = lr * (exp2_(lw - M2) * invS);
+                    }
+#pragma unroll
+                    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+                    if (lane == 0) rec[gi] += x;
+                }
+                break;
+            }
             for (int gb = 0; gb < n; gb += kCompTG) {
                 const int cnt = min(kCompTG, n - gb);
                 if (!resident) {
@@ -720,12 +929,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kFwdcWaves))
     default: return hipErrorInvalidValue;                                                                 \
     }
 
-#define FMB_FWDC_CALL(F_) hipLaunchKernelGGL((fwdc_kernel<F_>), dim3(n_items), dim3(64), 0, st, P, O, items)
+#define FMB_FWDC_CALL(F_) hipLaunchKernelGGL((fwdc_kernel<F_>), dim3(n_items), dim3(64), 0, st, P, O, items, order)
 #define FMB_BWDC_CALL(F_)                                                                                 \
-    hipLaunchKernelGGL((bwdc_kernel<F_>), dim3(n_items), dim3(64), 0, st, P, I, items, partial, beta_partial)
+    hipLaunchKernelGGL((bwdc_kernel<F_>), dim3(n_items), dim3(64), 0, st, P, I, items, order, partial,      \
+                       beta_partial)
 
+// Blocks take the items in `order` (longest first) where given, else in item order.
 hipError_t launch_fwdc(int flags, int n_items, hipStream_t st, const Params &P, const FwdOut &O,
-                       const BwdItem *items)
+                       const BwdItem *items, const int *order)
 {
     flags &= ~kPer;
     if (n_items < 1) return hipSuccess;
@@ -734,7 +945,7 @@ hipError_t launch_fwdc(int flags, int n_items, hipStream_t st, const Params &P, 
 }
 
 hipError_t launch_bwdc(int flags, int n_items, hipStream_t st, const Params &P, const BwdIn &I,
-                       const BwdItem *items, float *partial, float *beta_partial)
+                       const BwdItem *items, const int *order, float *partial, float *beta_partial)
 {
     flags &= ~kPer;
     if (n_items < 1) return hipSuccess;

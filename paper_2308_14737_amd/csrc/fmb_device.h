@@ -600,31 +600,44 @@ __device__ __forceinline__ void write_partial(float *__restrict__ dst, const flo
     for (int c = 6; c < rec; ++c) dst[c] = acc[c];
 }
 
-// Sum over the wave of 16 values, scattered: halving exchanges 32, 16, 8 and 4 lanes apart
-// (each lane keeps half of its values and adds its partner's copy of that half), then a sum
-// over groups of 4 lanes.  Lane l ends with the total of value wave16_index(l); the order of
-// the additions is fixed.
+// Sum over the wave of 16 values, scattered: halving exchanges between lanes 32, 16, 8 and 4 apart
+// (each lane keeps half of its values and adds its partner's copy of that half), then a sum over
+// groups of 4 lanes.  Lane l ends with the total of value wave16_index(l); the order of the
+// additions is fixed.  The first two exchanges are gfx950's permlane32/permlane16 swaps (the upper
+// half of one register trades places with the lower half of another, so one instruction serves two
+// values and no lane select is needed); the rest are DPP moves within rows: rotation by 8, the
+// mirror of each half-row (any pairing across the two halves serves a sum), then the quad.
 __device__ __forceinline__ int wave16_index(int lane)
 {
     return ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1);
 }
 
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
 __device__ __forceinline__ float wave_sum16(const float x[16], int lane)
 {
     float y[8], z[4], u[2];
-    bool up = (lane & 32) != 0;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) y[i] = (up ? x[i + 8] : x[i]) + __shfl_xor(up ? x[i] : x[i + 8], 32, 64);
-    up = (lane & 16) != 0;
+    for (int i = 0; i < 8; ++i) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x[i]), __float_as_uint(x[i + 8]), false, false);
+        y[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) z[i] = (up ? y[i + 4] : y[i]) + __shfl_xor(up ? y[i] : y[i + 4], 16, 64);
-    up = (lane & 8) != 0;
+    for (int i = 0; i < 4; ++i) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(y[i]), __float_as_uint(y[i + 4]), false, false);
+        z[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    bool up = (lane & 8) != 0;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) u[i] = (up ? z[i + 2] : z[i]) + __shfl_xor(up ? z[i] : z[i + 2], 8, 64);
+    for (int i = 0; i < 2; ++i) u[i] = (up ? z[i + 2] : z[i]) + dpp_mov<0x128>(up ? z[i] : z[i + 2]);  // row_ror:8
     up = (lane & 4) != 0;
-    float s = (up ? u[1] : u[0]) + __shfl_xor(up ? u[0] : u[1], 4, 64);
-    s += __shfl_xor(s, 2, 64);
-    s += __shfl_xor(s, 1, 64);
+    float s = (up ? u[1] : u[0]) + dpp_mov<0x141>(up ? u[0] : u[1]);  // row_half_mirror
+    s += dpp_mov<0x4E>(s);  // quad_perm [2, 3, 0, 1]
+    s += dpp_mov<0xB1>(s);  // quad_perm [1, 0, 3, 2]
     return s;
 }
 

@@ -8,7 +8,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from tests.gpu_util import normwise, to_np
+from tests.gpu_util import assert_forward, compare_forward, normwise, to_np
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -60,6 +60,10 @@ def test_split_statistic(fmb, model):
     o, v = O.dir_rays(views, dirs, cams.w2c)
     osc = O.OracleScene.of(sc.means, sc.prec, sc.weights, w.betas, w.eta)
     ref = O.render(osc, o, v, view=views, w2c_a=cams.w2c, intr_a=cams.intr, model=model)
+    # the forward on these scattered explicit rays (a ray tile spans the whole view)
+    ef = compare_forward(outs, ref, flow=False, normals=False)
+    _say(f"[split] {model} forward: {ef}")
+    assert_forward(ef, f"{model} forward on explicit rays")
     g = np.random.Generator(np.random.PCG64(71))
     # a per-ray loss that, like the reconstruction loss, vanishes where the ray sees nothing
     loss = (ref["alpha"] * g.uniform(0.5, 2.0, p)).astype(np.float32)
