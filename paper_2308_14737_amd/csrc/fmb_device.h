@@ -98,6 +98,23 @@ __device__ __forceinline__ void make_entry(const float *__restrict__ mu, const f
     out[3] = make_float4((float)c0, (float)c1, (float)c2, log2f(lam));
 }
 
+// The entry and, as a fifth float4, (|U mu'|^2, |Sigma^-1 mu'|_1, 0, 0): the terms of the one-FMA
+// estimate of the squared Mahalanobis distance m = |U mu'|^2 - (v.c) t and of its error bound
+// (pair_m_low).
+__device__ __forceinline__ void make_entry_est(const float *__restrict__ mu, const float *__restrict__ u,
+                                               float lam, const double o[3], float4 out[5])
+{
+    make_entry(mu, u, lam, o, out);
+    const double m0 = (double)mu[0] - o[0], m1 = (double)mu[1] - o[1], m2 = (double)mu[2] - o[2];
+    const double U00 = u[0], U01 = u[1], U02 = u[2], U11 = u[3], U12 = u[4], U22 = u[5];
+    const double b0 = U00 * m0 + U01 * m1 + U02 * m2;
+    const double b1 = U11 * m1 + U12 * m2;
+    const double b2 = U22 * m2;
+    const double c0 = U00 * b0, c1 = U01 * b0 + U11 * b1, c2 = U02 * b0 + U12 * b1 + U22 * b2;
+    out[4] = make_float4((float)(b0 * b0 + b1 * b1 + b2 * b2), (float)(fabs(c0) + fabs(c1) + fabs(c2)), 0.0f,
+                         0.0f);
+}
+
 // Unit direction of the ray through the centre of pixel (row, col).
 __device__ __forceinline__ void pixel_dir(const float *__restrict__ e, const float *__restrict__ k, int row,
                                           int col, float &v0, float &v1, float &v2)
@@ -181,8 +198,8 @@ struct Geo {
 // cond(Sigma^-1) times a few ulp (v.c is a dot product whose terms are at most that factor
 // larger than the sum); it enters m only to second order (m is minimal at the peak), so t is
 // the pair's depth and d2 and z2 are final here.
-__device__ __forceinline__ void pair_geo_coarse(const Ent &g, float v0, float v1, float v2, float hm, float b1,
-                                                float nc2, Geo &q)
+// The first half of pair_geo_coarse: a, 1/(a.a) and the peak t; returns v.c.
+__device__ __forceinline__ float pair_geo_peak(const Ent &g, float v0, float v1, float v2, Geo &q)
 {
     q.a0 = fmaf(g.u00, v0, fmaf(g.u01, v1, g.u02 * v2));
     q.a1 = fmaf(g.u11, v1, g.u12 * v2);
@@ -191,6 +208,13 @@ __device__ __forceinline__ void pair_geo_coarse(const Ent &g, float v0, float v1
     const float vc = fmaf(v0, g.c0, fmaf(v1, g.c1, v2 * g.c2));
     q.raa = rcp_(aa);
     q.t = vc * q.raa;
+    return vc;
+}
+
+// The second half: w = t v - hi, r = U w - U lo, the log2 density d2 and weight z2.
+__device__ __forceinline__ void pair_geo_resid(const Ent &g, float v0, float v1, float v2, float hm, float b1,
+                                               float nc2, Geo &q)
+{
     q.w0 = fmaf(q.t, v0, -g.mh0);
     q.w1 = fmaf(q.t, v1, -g.mh1);
     q.w2 = fmaf(q.t, v2, -g.mh2);
@@ -200,6 +224,23 @@ __device__ __forceinline__ void pair_geo_coarse(const Ent &g, float v0, float v1
     const float m = fmaf(q.r0, q.r0, fmaf(q.r1, q.r1, q.r2 * q.r2));
     q.d2 = fmaf(hm, m, g.l2l);
     q.z2 = fmaf(b1, q.d2, nc2 * q.t);
+}
+
+// A lower bound of the m that pair_geo_resid forms, from the entry's fifth float4 est and v.c:
+// m = |U mu'|^2 - (v.c)^2 / (a.a) estimated as est.x - (v.c) t in one FMA.  Its rounding error is a
+// few units of 2^-24 (|U mu'|^2 + |Sigma^-1 mu'|_1 |t|) (the terms that cancel; (v.c) t is at most
+// |U mu'|^2), and the residual form's own error is smaller still, so 2^-17 of that sum bounds both.
+__device__ __forceinline__ float pair_m_low(const float4 &est, float vc, float t)
+{
+    constexpr float kErr = 0x1p-17f;
+    return fmaf(-kErr, fmaf(est.y, fabsf(t), est.x), fmaf(-vc, t, est.x));
+}
+
+__device__ __forceinline__ void pair_geo_coarse(const Ent &g, float v0, float v1, float v2, float hm, float b1,
+                                                float nc2, Geo &q)
+{
+    pair_geo_peak(g, v0, v1, v2, q);
+    pair_geo_resid(g, v0, v1, v2, hm, b1, nc2, q);
 }
 
 // The residual at the refined peak: one Newton step on t -> |U (t v - mu')|^2 (exactly

@@ -22,6 +22,11 @@ constexpr float kEpsN = 1e-30f;
 // kernels evaluate: 2^-150 is below half of FP32's smallest subnormal, so such a weight is
 // exactly zero and its terms are skipped.
 constexpr float kSkipLog2 = -150.0f;
+// Base-2 log of the smallest density whose alpha term D_bar delta the tiled backward evaluates
+// where a tile has no weight above zero: a pair below it adds at most 2^-48 |D_bar| to its
+// Gaussian's sums, so even 2^21 rays (a 1080p view) change a Gaussian's record by less than
+// 2^-27 |D_bar|, far below the terms of the rays that see it.
+constexpr float kDensSkipLog2 = -48.0f;
 
 struct ViewRec {       // one per view of the batch
     int32_t h, w;      // image size (explicit rays: h = ray count, w = 1)

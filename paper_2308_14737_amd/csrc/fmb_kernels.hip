@@ -37,7 +37,7 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
 {
     constexpr bool NORMALS = (F & kNrm) != 0, PERSIST = (F & kPer) != 0;
     constexpr bool COLOR = (F & kCol) != 0;
-    constexpr int EW = COLOR ? 5 : 4;  // float4 per LDS entry
+    constexpr int EW = COLOR ? 6 : 5;  // float4 per LDS entry: the entry, the m estimate terms, colour
     __shared__ float4 tile[TG * EW];
     __shared__ int s_item;
     int pos = blockIdx.x;
@@ -58,6 +58,7 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
         double o[3];
         cam_centre(e, o);
         const Blend bl = blend_of(P, vr.scene);
+        const bool b1_pos = bl.b1 >= 0.0f;  // the weight bound needs beta1 >= 0
         // ray j of a lane: lane `lane` of tile tile0 + j * NW + wave (8 x 8 pixels where the view is
         // wide enough: a wave's rays stay close together, so the exact skip of zero weights below
         // is uniform over the wave more often)
@@ -88,19 +89,29 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
             if (gb > 0 || !PERSIST) __syncthreads();
             for (int q = threadIdx.x; q < cnt; q += BLOCK) {
                 const int gi = sr.gauss_off + gb + q;
-                make_entry(P.means + 3 * gi, P.prec + 6 * gi, P.weights[gi], o, &tile[EW * q]);
-                if (COLOR) tile[EW * q + 4] = colour_entry(P.colors + 3 * gi);
+                make_entry_est(P.means + 3 * gi, P.prec + 6 * gi, P.weights[gi], o, &tile[EW * q]);
+                if (COLOR) tile[EW * q + 5] = colour_entry(P.colors + 3 * gi);
             }
             __syncthreads();
 #pragma unroll 2
             for (int i = 0; i < cnt; ++i) {
                 const Ent g = ent_from(tile[EW * i], tile[EW * i + 1], tile[EW * i + 2], tile[EW * i + 3]);
+                const float4 est = tile[EW * i + 4];
                 float4 cc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                if (COLOR) cc = tile[EW * i + 4];
+                if (COLOR) cc = tile[EW * i + 5];
 #pragma unroll
                 for (int j = 0; j < RPT; ++j) {
                     Geo q;
-                    pair_geo_coarse(g, v0[j], v1[j], v2[j], bl.hm, bl.b1, bl.nc2, q);
+                    const float vc = pair_geo_peak(g, v0[j], v1[j], v2[j], q);
+                    {
+                        // upper bounds of the log2 density and weight from a lower bound of m (one
+                        // FMA): a pair below both cutoffs adds a weight that is zero in FP32 and a
+                        // density below 2^kDensSkipLog2 to alpha's sum, and skips the residual
+                        const float d2_hi = fmaf(bl.hm, pair_m_low(est, vc, q.t), g.l2l);
+                        const float zr_hi = b1_pos ? fmaf(bl.b1, d2_hi, fmaf(bl.nc2, q.t, -M[j])) : INFINITY;
+                        if (zr_hi < kSkipLog2 && d2_hi < kDensSkipLog2) continue;
+                    }
+                    pair_geo_resid(g, v0[j], v1[j], v2[j], bl.hm, bl.b1, bl.nc2, q);
                     const float delta = exp2_(q.d2);
                     D[j] += delta;
                     // log2 of the weight relative to the running maximum, b1 d2 + (nc2 t - M)
@@ -576,7 +587,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
     constexpr int NW = BLOCK / 64;
     constexpr int RAYS = 64 * T;
     __shared__ float4 rays[2 * RAYS];         // per ray: (v, M2 + log2 S), (tf_bar, D_bar, dc, t_f)
-    __shared__ float4 ents[4 * TG];           // the Gaussian tile's entries
+    __shared__ float4 ents[5 * TG];           // the Gaussian tile's entries (with the m estimate terms)
     __shared__ float rec[kOffsetAcc * TG];    // (H, Bv, L) of each Gaussian of the tile
     __shared__ float bsum[2 * NW];
     __shared__ int s_item;
@@ -601,6 +612,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
         cam_centre(e, o);
         const float o0 = (float)o[0], o1 = (float)o[1], o2 = (float)o[2];
         const Blend bl = blend_of(P, vr.scene);
+        const bool b1_pos = bl.b1 >= 0.0f;  // the weight bound needs beta1 >= 0
         const int nt = min(T, vr.tiles - item.ray0);  // the item's tiles: ray0 is its first tile
 
         __syncthreads();  // the previous item is done with the staged rays
@@ -620,22 +632,33 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
             __syncthreads();  // staged rays visible; the previous tile's entries and sums are consumed
             for (int q = tid; q < cnt; q += BLOCK) {
                 const int gi = sr.gauss_off + gb + q;
-                make_entry(P.means + 3 * gi, P.prec + 6 * gi, P.weights[gi], o, &ents[4 * q]);
+                make_entry_est(P.means + 3 * gi, P.prec + 6 * gi, P.weights[gi], o, &ents[5 * q]);
             }
             __syncthreads();
             for (int i = wave; i < cnt; i += NW) {
-                const Ent g = ent_from(ents[4 * i], ents[4 * i + 1], ents[4 * i + 2], ents[4 * i + 3]);
+                const Ent g = ent_from(ents[5 * i], ents[5 * i + 1], ents[5 * i + 2], ents[5 * i + 3]);
+                const float4 est = ents[5 * i + 4];
                 OffsetAcc acc;
 #pragma unroll 1
                 for (int t = 0; t < nt; ++t) {
                     const float4 x0 = rays[2 * (64 * t + lane)], x1 = rays[2 * (64 * t + lane) + 1];
                     Geo q;
-                    pair_geo_coarse(g, x0.x, x0.y, x0.z, bl.hm, bl.b1, bl.nc2, q);
+                    const float vc = pair_geo_peak(g, x0.x, x0.y, x0.z, q);
+                    {
+                        // upper bounds of the log2 density and of the log2 weight from a lower bound
+                        // of m (one FMA): a tile they put below both cutoffs everywhere is one the exact
+                        // test below would skip, and it skips the residual as well
+                        const float d2_hi = fmaf(bl.hm, pair_m_low(est, vc, q.t), g.l2l);
+                        const float zr_hi = b1_pos ? fmaf(bl.b1, d2_hi, fmaf(bl.nc2, q.t, -x0.w)) : INFINITY;
+                        if (!__any(zr_hi >= kSkipLog2) && !__any(d2_hi >= kDensSkipLog2 && x1.y != 0.0f)) continue;
+                    }
+                    pair_geo_resid(g, x0.x, x0.y, x0.z, bl.hm, bl.b1, bl.nc2, q);
                     // log2 of the normalised weight, and the density term D_bar delta
                     const float zr = fmaf(bl.b1, q.d2, fmaf(bl.nc2, q.t, -x0.w));
-                    // a density below 2^-150 rounds to zero in FP32: such a tile skips the exponential
+                    // a weight below 2^-150 rounds to zero in FP32, and a density below 2^kDensSkipLog2
+                    // adds nothing measurable: such a tile skips the exponential and the adjoint
                     const bool any_w = __any(zr >= kSkipLog2);
-                    const bool any_d = __any(q.d2 >= kSkipLog2 && x1.y != 0.0f);
+                    const bool any_d = __any(q.d2 >= kDensSkipLog2 && x1.y != 0.0f);
                     if (any_w || any_d) {
                         const float dd = x1.y * exp2_(q.d2);
                         // with zero weights on every ray of the tile only the density term remains:
