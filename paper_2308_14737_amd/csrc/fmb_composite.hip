@@ -186,7 +186,9 @@ __device__ __forceinline__ float comp_behind(const CompList L, const float z[kCo
     return b;
 }
 
-// Entries (and colours) of Gaussians [gb, gb + cnt) of the scene into LDS, EW float4 each.
+// Entries of Gaussians [gb, gb + cnt) of the scene into LDS, EW float4 each: the entry, the terms
+// of the m estimate (make_entry_est) and, with EW = 6, the colour.
+constexpr int kCompEst = 4, kCompCol = 5;  // float4 offsets within an LDS entry
 template <int EW>
 __device__ __forceinline__ void comp_stage(const Params &P, const SceneRec &sr, int gb, int cnt, const double o[3],
                                            float4 *__restrict__ ents)
@@ -194,10 +196,17 @@ __device__ __forceinline__ void comp_stage(const Params &P, const SceneRec &sr, 
     __syncthreads();  // the previous tile is consumed
     for (int q = threadIdx.x; q < cnt; q += 64) {
         const int gi = sr.gauss_off + gb + q;
-        make_entry(P.means + 3 * gi, P.prec + 6 * gi, P.weights[gi], o, &ents[EW * q]);
-        if (EW == 5) ents[EW * q + 4] = colour_entry(P.colors + 3 * gi);
+        make_entry_est(P.means + 3 * gi, P.prec + 6 * gi, P.weights[gi], o, &ents[EW * q]);
+        if (EW == 6) ents[EW * q + kCompCol] = colour_entry(P.colors + 3 * gi);
     }
     __syncthreads();
+}
+
+// Upper bound of the pair's log2 density from the one-FMA lower bound of m (pair_m_low), with the
+// peak already formed (pair_geo_peak returned vc).
+__device__ __forceinline__ float comp_d2_hi(const Ent &g, const float4 &est, float vc, float t, float hm)
+{
+    return fmaf(hm, pair_m_low(est, vc, t), g.l2l);
 }
 
 template <int EW>
@@ -333,10 +342,16 @@ __device__ __forceinline__ int comp_collect(const Params &P, const SceneRec &sr,
                 if (two) mk &= mk - 1;
                 const Ent ga = comp_ent<EW>(ents, ia), gb2 = comp_ent<EW>(ents, ib);
                 Geo qa, qb;
-                pair_geo_coarse(ga, v0, v1, v2, hm, 0.0f, 0.0f, qa);
-                pair_geo_coarse(gb2, v0, v1, v2, hm, 0.0f, 0.0f, qb);
-                take(ga, qa, ia);
-                if (two) take(gb2, qb, ib);
+                const float vca = pair_geo_peak(ga, v0, v1, v2, qa), vcb = pair_geo_peak(gb2, v0, v1, v2, qb);
+                // the residual only where the density bound allows a significant pair
+                if (__any(comp_d2_hi(ga, ents[EW * ia + kCompEst], vca, qa.t, hm) > sig2)) {
+                    pair_geo_resid(ga, v0, v1, v2, hm, 0.0f, 0.0f, qa);
+                    take(ga, qa, ia);
+                }
+                if (two && __any(comp_d2_hi(gb2, ents[EW * ib + kCompEst], vcb, qb.t, hm) > sig2)) {
+                    pair_geo_resid(gb2, v0, v1, v2, hm, 0.0f, 0.0f, qb);
+                    take(gb2, qb, ib);
+                }
             }
         }
     }
@@ -371,7 +386,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kFwdcWaves))
                                                                                                       const int *__restrict__ order)
 {
     constexpr bool NORMALS = (F & kNrm) != 0, COLOR = (F & kCol) != 0;
-    constexpr int EW = COLOR ? 5 : 4;
+    constexpr int EW = COLOR ? 6 : 5;
     __shared__ float4 ents[kCompTG * EW];
     __shared__ int slot_g[kCompSlots];
     const int lane = threadIdx.x;
@@ -437,7 +452,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kFwdcWaves))
                 N2 = fmaf(ew, pn.n2, N2);
             }
             if (COLOR) {
-                const float4 cc = ents[EW * ci + 4];
+                const float4 cc = ents[EW * ci + kCompCol];
                 C0 = fmaf(ew, cc.x, C0);
                 C1 = fmaf(ew, cc.y, C1);
                 C2 = fmaf(ew, cc.z, C2);
@@ -474,17 +489,25 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kFwdcWaves))
                 if (!resident) comp_stage<EW>(P, sr, gb, cnt, o, ents);
                 for (int i = 0; i < cnt; i += 2) {  // two Gaussians a step (two independent chains)
                     const bool two = i + 1 < cnt;
-                    const Ent ga = comp_ent<EW>(ents, i), gb = comp_ent<EW>(ents, two ? i + 1 : i);
+                    const int ib = two ? i + 1 : i;
+                    const Ent ga = comp_ent<EW>(ents, i), gb = comp_ent<EW>(ents, ib);
                     Geo qa, qb;
-                    pair_geo_coarse(ga, v0, v1, v2, hm, 0.0f, 0.0f, qa);
-                    pair_geo_coarse(gb, v0, v1, v2, hm, 0.0f, 0.0f, qb);
+                    const float vca = pair_geo_peak(ga, v0, v1, v2, qa), vcb = pair_geo_peak(gb, v0, v1, v2, qb);
                     // a pair of this window whose weight (at most its density) is not below
-                    // 2^skip2 of the running maximum (nor is its density below 2^skip2, as M <= 0)
+                    // 2^skip2 of the running maximum (nor is its density below 2^skip2, as M <= 0);
+                    // the density bound rules most pairs out before the residual
                     const float tsa = qa.t * kDepthScale, tsb = qb.t * kDepthScale;
-                    const bool la = tsa >= w.lo && tsa < w.hi && qa.d2 - M >= skip2;
-                    if (__any(la) && la) blend(ga, qa, comp_front(L, ns, w, tsa), i);
-                    const bool lb = two && tsb >= w.lo && tsb < w.hi && qb.d2 - M >= skip2;
-                    if (__any(lb) && lb) blend(gb, qb, comp_front(L, ns, w, tsb), i + 1);
+                    const bool ina = tsa >= w.lo && tsa < w.hi, inb = two && tsb >= w.lo && tsb < w.hi;
+                    if (__any(ina && comp_d2_hi(ga, ents[EW * i + kCompEst], vca, qa.t, hm) - M >= skip2)) {
+                        pair_geo_resid(ga, v0, v1, v2, hm, 0.0f, 0.0f, qa);
+                        const bool la = ina && qa.d2 - M >= skip2;
+                        if (__any(la) && la) blend(ga, qa, comp_front(L, ns, w, tsa), i);
+                    }
+                    if (__any(inb && comp_d2_hi(gb, ents[EW * ib + kCompEst], vcb, qb.t, hm) - M >= skip2)) {
+                        pair_geo_resid(gb, v0, v1, v2, hm, 0.0f, 0.0f, qb);
+                        const bool lb = inb && qb.d2 - M >= skip2;
+                        if (__any(lb) && lb) blend(gb, qb, comp_front(L, ns, w, tsb), ib);
+                    }
                 }
             }
             const bool more = comp_next(w, L, ns);
@@ -510,7 +533,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
     // without a normal cotangent the pairs take the offset form of the adjoint
     // (pair_adjoint_offset), which needs neither the refined peak nor r
     constexpr bool PLAIN = !NORMALS;
-    constexpr int EW = COLOR ? 5 : 4;
+    constexpr int EW = COLOR ? 6 : 5;
     constexpr int REC = COLOR ? kPartialColor : kPartial;   // partial record per Gaussian
     // the sums per Gaussian: (H, Bv, L) of the offset form or the general record, then colour
     constexpr int LREC = (PLAIN ? kOffsetAcc : kPartial) + (COLOR ? 3 : 0);
@@ -572,8 +595,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
                 __syncthreads();
                 if (lane < ns) {
                     const int gi = sr.gauss_off + slot_g[lane];
-                    make_entry(P.means + 3 * gi, P.prec + 6 * gi, P.weights[gi], o, &sents[EW * lane]);
-                    if (COLOR) sents[EW * lane + 4] = colour_entry(P.colors + 3 * gi);
+                    make_entry_est(P.means + 3 * gi, P.prec + 6 * gi, P.weights[gi], o, &sents[EW * lane]);
+                    if (COLOR) sents[EW * lane + kCompCol] = colour_entry(P.colors + 3 * gi);
                 }
                 __syncthreads();
             }
@@ -592,7 +615,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
                         lin += pair_normal(g, q, nb0, nb1, nb2).nN;
                     }
                     if (COLOR) {
-                        const float4 cc = src[EW * gs + 4];
+                        const float4 cc = src[EW * gs + kCompCol];
                         lin = fmaf(cb0, cc.x, fmaf(cb1, cc.y, fmaf(cb2, cc.z, lin)));
                     }
                     z = wt * (lin - kap);
@@ -625,7 +648,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
                 lin += pair_normal(g, q, nb0, nb1, nb2).nN;
             }
             if (COLOR) {
-                const float4 cc = ents[EW * i + 4];
+                const float4 cc = ents[EW * i + kCompCol];
                 lin = fmaf(cb0, cc.x, fmaf(cb1, cc.y, fmaf(cb2, cc.z, lin)));
             }
             ztie = fmaf(wt, lin - kap, ztie);
@@ -678,7 +701,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
                 }
                 float lin = fmaf(tfb, q.t, pn.nN);
                 if (COLOR) {
-                    const float4 cc = ents[EW * i + 4];
+                    const float4 cc = ents[EW * i + kCompCol];
                     lin = fmaf(cb0, cc.x, fmaf(cb1, cc.y, fmaf(cb2, cc.z, lin)));
                     aC0 = wt * cb0;
                     aC1 = wt * cb1;
@@ -742,22 +765,30 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
                     }
                     for (int i = 0; i < cnt; i += 2) {  // two Gaussians a step (two independent chains)
                         const bool two = i + 1 < cnt;
-                        const Ent ga = comp_ent<EW>(ents, i), gb = comp_ent<EW>(ents, two ? i + 1 : i);
+                        const int ib = two ? i + 1 : i;
+                        const Ent ga = comp_ent<EW>(ents, i), gb = comp_ent<EW>(ents, ib);
                         Geo qa, qb;
-                        pair_geo_coarse(ga, v0, v1, v2, hm, 0.0f, 0.0f, qa);
-                        pair_geo_coarse(gb, v0, v1, v2, hm, 0.0f, 0.0f, qb);
-                        // a pair of this window with a normalised weight or a density not below 2^skip2
+                        const float vca = pair_geo_peak(ga, v0, v1, v2, qa), vcb = pair_geo_peak(gb, v0, v1, v2, qb);
+                        // a pair of this window with a normalised weight or a density not below
+                        // 2^skip2 (the density bound rules most pairs out before the residual)
                         const float tsa = qa.t * kDepthScale, tsb = qb.t * kDepthScale;
                         const float lim = fminf(skip2, wskip);
-                        const bool la = tsa >= w.lo && tsa < w.hi && qa.d2 >= lim;
-                        if (__any(la)) {
-                            pair_terms(ga, qa, tsa, la, i, i, zafter);
-                            if (!resident && lane == 0) touched[i] = 1;
+                        const bool ina = tsa >= w.lo && tsa < w.hi, inb = two && tsb >= w.lo && tsb < w.hi;
+                        if (__any(ina && comp_d2_hi(ga, ents[EW * i + kCompEst], vca, qa.t, hm) >= lim)) {
+                            pair_geo_resid(ga, v0, v1, v2, hm, 0.0f, 0.0f, qa);
+                            const bool la = ina && qa.d2 >= lim;
+                            if (__any(la)) {
+                                pair_terms(ga, qa, tsa, la, i, i, zafter);
+                                if (!resident && lane == 0) touched[i] = 1;
+                            }
                         }
-                        const bool lb = two && tsb >= w.lo && tsb < w.hi && qb.d2 >= lim;
-                        if (__any(lb)) {
-                            pair_terms(gb, qb, tsb, lb, i + 1, i + 1, zafter);
-                            if (!resident && lane == 0) touched[i + 1] = 1;
+                        if (__any(inb && comp_d2_hi(gb, ents[EW * ib + kCompEst], vcb, qb.t, hm) >= lim)) {
+                            pair_geo_resid(gb, v0, v1, v2, hm, 0.0f, 0.0f, qb);
+                            const bool lb = inb && qb.d2 >= lim;
+                            if (__any(lb)) {
+                                pair_terms(gb, qb, tsb, lb, ib, ib, zafter);
+                                if (!resident && lane == 0) touched[ib] = 1;
+                            }
                         }
                     }
                     if (!resident) {
@@ -806,7 +837,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kFwdcWaves))
                                                    const float *__restrict__ stash,
                                                    const BwdItem *__restrict__ items, float *__restrict__ partial)
 {
-    constexpr int EW = 4;
+    constexpr int EW = 5;
     const int *order = nullptr;
     __shared__ float4 ents[kCompTG * EW];
     __shared__ float rec[kCompTG];
