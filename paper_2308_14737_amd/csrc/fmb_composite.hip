@@ -102,12 +102,53 @@ __device__ __forceinline__ float comp_skip_log2(int n)
 
 // A lane's slots: scaled depth and density of the significant intersection of the slot's
 // Gaussian (density 0 where that Gaussian is not significant for the lane, or not in its window).
-// One plain array, so that it stays in registers: depths at [k], densities at [kCompSlots + k].
-// A window's slots are filled by pushing at slot 0 (every slot moves up one), so slot k holds the
-// window's (ns - 1 - k)-th Gaussian in staging order, and the slots from ns on hold zeros.
-typedef float CompList[2 * kCompSlots];
-#define SLOT_T(L, k) ((L)[(k)])
-#define SLOT_D(L, k) ((L)[kCompSlots + (k)])
+// They are register vectors (slots 0..31 in the first, 32..47 in the second), read at
+// compile-time positions and written at the wave-uniform fill position by one indirect register
+// move; slot k holds the window's k-th Gaussian in staging order, and the slots from ns on hold
+// zeros.
+typedef float CompV32 __attribute__((ext_vector_type(32)));
+typedef float CompV16 __attribute__((ext_vector_type(16)));
+static_assert(kCompSlots == 48, "the slot vectors hold 32 + 16 slots");
+struct CompList {
+    CompV32 t0, d0;
+    CompV16 t1, d1;
+};
+// a value per slot (the backward's z_bar of the slots' pairs)
+struct CompZ {
+    CompV32 z0;
+    CompV16 z1;
+};
+
+__device__ __forceinline__ float slot_t(const CompList &L, int k) { return k < 32 ? L.t0[k] : L.t1[k - 32]; }
+__device__ __forceinline__ float slot_d(const CompList &L, int k) { return k < 32 ? L.d0[k] : L.d1[k - 32]; }
+__device__ __forceinline__ float slot_z(const CompZ &z, int k) { return k < 32 ? z.z0[k] : z.z1[k - 32]; }
+
+__device__ __forceinline__ void slot_set_d(CompList &L, int k, float d)
+{
+    if (k < 32)
+        L.d0[k] = d;
+    else
+        L.d1[k - 32] = d;
+}
+
+__device__ __forceinline__ void slot_set(CompList &L, int k, float t, float d)
+{
+    if (k < 32) {
+        L.t0[k] = t;
+        L.d0[k] = d;
+    } else {
+        L.t1[k - 32] = t;
+        L.d1[k - 32] = d;
+    }
+}
+
+__device__ __forceinline__ void slot_set_z(CompZ &z, int k, float v)
+{
+    if (k < 32)
+        z.z0[k] = v;
+    else
+        z.z1[k - 32] = v;
+}
 
 // A lane's depth window (scaled depths): pairs with lo <= t < hi are taken in the current pass;
 // base sums the significant densities in front of lo, tie those at lo.
@@ -115,29 +156,12 @@ struct CompWin {
     float lo, hi, base, tie;
 };
 
-__device__ __forceinline__ void comp_clear(CompList L)
+__device__ __forceinline__ void comp_clear(CompList &L)
 {
-#pragma unroll
-    for (int k = 0; k < 2 * kCompSlots; ++k) L[k] = 0.0f;
-}
-
-// Pushes (t, d) at slot 0: register moves at compile-time indices, no dynamic index.
-__device__ __forceinline__ void comp_push(CompList L, float t, float d)
-{
-#pragma unroll
-    for (int k = kCompSlots - 1; k > 0; --k) {
-        SLOT_T(L, k) = SLOT_T(L, k - 1);
-        SLOT_D(L, k) = SLOT_D(L, k - 1);
-    }
-    SLOT_T(L, 0) = t;
-    SLOT_D(L, 0) = d;
-}
-
-__device__ __forceinline__ void comp_push_z(float z[kCompSlots], float v)
-{
-#pragma unroll
-    for (int k = kCompSlots - 1; k > 0; --k) z[k] = z[k - 1];
-    z[0] = v;
+    L.t0 = (CompV32)(0.0f);
+    L.d0 = (CompV32)(0.0f);
+    L.t1 = (CompV16)(0.0f);
+    L.d1 = (CompV16)(0.0f);
 }
 
 // Step sums over the slots in use, eight slots at a time (template recursion, so that every slot
@@ -147,33 +171,32 @@ constexpr int kSlotGroup = 8;
 template <int K>
 struct SlotSums {
     // sum of the densities of the slots in front of ts
-    __device__ static __forceinline__ void front(const CompList L, int ns, float ts, float &f)
+    __device__ static __forceinline__ void front(const CompList &L, int ns, float ts, float &f)
     {
         if (K >= ns) return;
 #pragma unroll
-        for (int k = K; k < K + kSlotGroup; ++k) f = fmaf(before(SLOT_T(L, k), ts), SLOT_D(L, k), f);
+        for (int k = K; k < K + kSlotGroup; ++k) f = fmaf(before(slot_t(L, k), ts), slot_d(L, k), f);
         SlotSums<K + kSlotGroup>::front(L, ns, ts, f);
     }
     // sum of z over the slots behind ts
-    __device__ static __forceinline__ void behind(const CompList L, const float z[kCompSlots], int ns, float ts,
-                                                  float &b)
+    __device__ static __forceinline__ void behind(const CompList &L, const CompZ &z, int ns, float ts, float &b)
     {
         if (K >= ns) return;
 #pragma unroll
-        for (int k = K; k < K + kSlotGroup; ++k) b = fmaf(before(ts, SLOT_T(L, k)), z[k], b);
+        for (int k = K; k < K + kSlotGroup; ++k) b = fmaf(before(ts, slot_t(L, k)), slot_z(z, k), b);
         SlotSums<K + kSlotGroup>::behind(L, z, ns, ts, b);
     }
 };
 template <>
 struct SlotSums<kCompSlots> {
-    __device__ static __forceinline__ void front(const CompList, int, float, float &) {}
-    __device__ static __forceinline__ void behind(const CompList, const float *, int, float, float &) {}
+    __device__ static __forceinline__ void front(const CompList &, int, float, float &) {}
+    __device__ static __forceinline__ void behind(const CompList &, const CompZ &, int, float, float &) {}
 };
 static_assert(kCompSlots % kSlotGroup == 0, "whole slot groups");
 
 // F at scaled depth ts inside window w: base, the densities at lo (if ts > lo), and the slots
 // in front of ts.
-__device__ __forceinline__ float comp_front(const CompList L, int ns, const CompWin &w, float ts)
+__device__ __forceinline__ float comp_front(const CompList &L, int ns, const CompWin &w, float ts)
 {
     float f = ts > w.lo ? w.base + w.tie : w.base;
     SlotSums<0>::front(L, ns, ts, f);
@@ -181,7 +204,7 @@ __device__ __forceinline__ float comp_front(const CompList L, int ns, const Comp
 }
 
 // Sum of z over the slots behind ts.
-__device__ __forceinline__ float comp_behind(const CompList L, const float z[kCompSlots], int ns, float ts)
+__device__ __forceinline__ float comp_behind(const CompList &L, const CompZ &z, int ns, float ts)
 {
     float b = 0.0f;
     SlotSums<0>::behind(L, z, ns, ts, b);
@@ -303,7 +326,7 @@ template <int EW, class OnTie>
 __device__ __forceinline__ int comp_collect(const Params &P, const SceneRec &sr, const double o[3],
                                             float4 *__restrict__ ents, bool resident, float v0, float v1,
                                             float v2, float hm, float sig2, const TileCone &tc, CompWin &w,
-                                            CompList L, int *__restrict__ slot_g, OnTie on_tie)
+                                            CompList &L, int *__restrict__ slot_g, OnTie on_tie)
 {
     int ns = 0;
     comp_clear(L);
@@ -326,8 +349,8 @@ __device__ __forceinline__ int comp_collect(const Params &P, const SceneRec &sr,
             const bool cand = sig && ts > w.lo;
             if (!__any(cand)) return;
             if (ns < kCompSlots) {
-                comp_push(L, ts, cand ? dl : 0.0f);
-                if (slot_g && threadIdx.x == 0) slot_g[ns] = gb + i;
+                slot_set(L, ns, ts, cand ? dl : 0.0f);
+                if (threadIdx.x == 0) slot_g[ns] = gb + i;
                 ns = __builtin_amdgcn_readfirstlane(ns + 1);
             } else if (cand) {
                 w.hi = fminf(w.hi, ts);
@@ -358,12 +381,12 @@ __device__ __forceinline__ int comp_collect(const Params &P, const SceneRec &sr,
         }
     }
 #pragma unroll
-    for (int k = 0; k < kCompSlots; ++k) SLOT_D(L, k) = SLOT_T(L, k) >= w.hi ? 0.0f : SLOT_D(L, k);
+    for (int k = 0; k < kCompSlots; ++k) slot_set_d(L, k, slot_t(L, k) >= w.hi ? 0.0f : slot_d(L, k));
     return ns;
 }
 
 // Moves window w past hi (or marks the lane done); returns true while the lane has depths left.
-__device__ __forceinline__ bool comp_next(CompWin &w, const CompList L, int ns)
+__device__ __forceinline__ bool comp_next(CompWin &w, const CompList &L, int ns)
 {
     if (w.hi == INFINITY) {
         w.lo = INFINITY;
@@ -371,7 +394,7 @@ __device__ __forceinline__ bool comp_next(CompWin &w, const CompList L, int ns)
     }
     float s = w.tie;
 #pragma unroll
-    for (int k = 0; k < kCompSlots; ++k) s += SLOT_D(L, k);
+    for (int k = 0; k < kCompSlots; ++k) s += slot_d(L, k);
     w.base += s;
     w.lo = w.hi;
     w.hi = INFINITY;
@@ -469,7 +492,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kFwdcWaves))
         // (a ray without a significant intersection cannot qualify)
         float own = 0.0f;
 #pragma unroll
-        for (int k = 0; k < kCompSlots; ++k) own += SLOT_D(L, k);
+        for (int k = 0; k < kCompSlots; ++k) own += slot_d(L, k);
         if (resident && ns > 0 && !__any(w.hi != INFINITY) && __all(!valid || own > 0.0f)) {
             for (int s = 0; s < ns; s += 2) {  // two slots a step (two independent chains)
                 const bool two = s + 1 < ns;
@@ -585,14 +608,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
         const CompWin w0{valid ? -INFINITY : INFINITY, INFINITY, 0.0f, 0.0f};
         CompWin w = w0;
         CompList L;
-        float zs[kCompSlots];
+        CompZ zs;
         const TileCone tc = comp_cone(v0, v1, v2, valid);
 
         // z_bar of the slots' own pairs (the lanes' significant intersections of the window)
-        // (pushed in staging order, so that zs[k] belongs to slot k)
-        auto slot_z = [&](int ns) {
-#pragma unroll
-            for (int k = 0; k < kCompSlots; ++k) zs[k] = 0.0f;
+        auto slots_z = [&](int ns) {
+            zs.z0 = (CompV32)(0.0f);
+            zs.z1 = (CompV16)(0.0f);
             if (!resident) {
                 __syncthreads();
                 if (lane < ns) {
@@ -604,7 +626,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
             }
             const float4 *src = resident ? ents : sents;
             // z_bar of the lane's pair (g, q) when the slot holds it: significant and in the window
-            auto own_z = [&](const Ent &g, Geo &q, int gs) {
+            auto own_z = [&](const Ent &g, Geo &q, int gs, int k) {
                 const float ts = q.t * kDepthScale;
                 const bool own = q.d2 > sig2 && ts > w.lo && ts < w.hi;
                 float z = 0.0f;
@@ -622,7 +644,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
                     }
                     z = wt * (lin - kap);
                 }
-                comp_push_z(zs, z);
+                slot_set_z(zs, k, z);
             };
             for (int s = 0; s < ns; s += 2) {  // two slots a step (two independent chains)
                 const bool two = s + 1 < ns;
@@ -632,8 +654,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
                 Geo qa, qb;
                 pair_geo_coarse(ga, v0, v1, v2, hm, 0.0f, 0.0f, qa);
                 pair_geo_coarse(gb, v0, v1, v2, hm, 0.0f, 0.0f, qb);
-                own_z(ga, qa, ga_i);
-                if (two) own_z(gb, qb, gb_i);
+                own_z(ga, qa, ga_i, s);
+                if (two) own_z(gb, qb, gb_i, s + 1);
             }
         };
 
@@ -659,7 +681,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
         auto window_z = [&](int ns) {
             float s = ztie;
 #pragma unroll
-            for (int k = 0; k < kCompSlots; ++k) s += zs[k];
+            for (int k = 0; k < kCompSlots; ++k) s += slot_z(zs, k);
             return s;
         };
 
@@ -670,7 +692,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
         if (__any(w.hi != INFINITY)) {
             bool more = true;
             for (;;) {
-                slot_z(ns);
+                slots_z(ns);
                 zall += window_z(ns);
                 more = comp_next(w, L, ns);
                 if (!__any(more)) break;
@@ -740,7 +762,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
 
         float zthrough = 0.0f;
         for (;;) {
-            slot_z(ns);
+            slots_z(ns);
             zthrough += window_z(ns);
             // z_bar of the significant intersections behind this window
             const float zafter = w.hi == INFINITY ? 0.0f : zall - zthrough;
