@@ -53,7 +53,7 @@ hipError_t launch_stat(int n_items, int n_tasks, int max_gc, hipStream_t st, con
 hipError_t launch_statc(int n_items, hipStream_t st, const Params &P, const float *loss, const float *stash,
                         const BwdItem *items, float *partial);
 hipError_t launch_bwdc(int flags, int n_items, hipStream_t st, const Params &P, const BwdIn &I,
-                       const BwdItem *items, const int *order, float *partial, float *beta_partial);
+                       const BwdItem *items, const int *order, float *partial, float *beta_partial, int max_n);
 hipError_t occupancy_fwd(int variant, int flags, int *blocks_per_cu);
 hipError_t occupancy_bwd(int variant, int flags, int *blocks_per_cu);
 hipError_t scratch_base(void **out);
@@ -266,6 +266,13 @@ struct Job {
         }
     }
     ~Job() { drop_graphs(); }
+
+    int max_scene_n() const
+    {
+        int m = 0;
+        for (const auto &sc : scenes) m = std::max(m, sc.n);
+        return m;
+    }
 
     int init_device()
     {
@@ -698,7 +705,7 @@ struct Job {
         if (model == FMB_MODEL_COMPOSITE) {
             TimedSpan tb(st, 1);
             HIPCHK(launch_bwdc(bwd_flags(I, false), n_bitems, st, prm, I, d_bitems.as<BwdItem>(), d_border.as<int>(),
-                               d_partial.as<float>(), d_bpart.as<float>()));
+                               d_partial.as<float>(), d_bpart.as<float>(), max_scene_n()));
             tb.stop();
         } else {
             const int flags = bwd_flags(I, persist);
@@ -775,7 +782,7 @@ struct Job {
         const int n_items = (int)pl.items.size();
         if (model == FMB_MODEL_COMPOSITE) {
             TimedSpan tb(st, 1);
-            HIPCHK(launch_bwdc(bwd_flags(I, false), n_items, st, prm, I, items, nullptr, part, bpart));
+            HIPCHK(launch_bwdc(bwd_flags(I, false), n_items, st, prm, I, items, nullptr, part, bpart, max_scene_n()));
             tb.stop();
         } else {
             TimedSpan tb(st, 1);

@@ -166,49 +166,57 @@ __device__ __forceinline__ void comp_clear(CompList &L)
 
 // Step sums over the slots in use, eight slots at a time (template recursion, so that every slot
 // index is a compile-time register index); ns is uniform, so the early exits are scalar branches,
-// and the unused slots of a group add zeros.
+// and the unused slots of a group add zeros.  The even and the odd slots go to two sums (two
+// independent chains).
 constexpr int kSlotGroup = 8;
 template <int K>
 struct SlotSums {
     // sum of the densities of the slots in front of ts
-    __device__ static __forceinline__ void front(const CompList &L, int ns, float ts, float &f)
+    __device__ static __forceinline__ void front(const CompList &L, int ns, float ts, float &f, float &g)
     {
         if (K >= ns) return;
 #pragma unroll
-        for (int k = K; k < K + kSlotGroup; ++k) f = fmaf(before(slot_t(L, k), ts), slot_d(L, k), f);
-        SlotSums<K + kSlotGroup>::front(L, ns, ts, f);
+        for (int k = K; k < K + kSlotGroup; k += 2) {
+            f = fmaf(before(slot_t(L, k), ts), slot_d(L, k), f);
+            g = fmaf(before(slot_t(L, k + 1), ts), slot_d(L, k + 1), g);
+        }
+        SlotSums<K + kSlotGroup>::front(L, ns, ts, f, g);
     }
     // sum of z over the slots behind ts
-    __device__ static __forceinline__ void behind(const CompList &L, const CompZ &z, int ns, float ts, float &b)
+    __device__ static __forceinline__ void behind(const CompList &L, const CompZ &z, int ns, float ts, float &b,
+                                                  float &c)
     {
         if (K >= ns) return;
 #pragma unroll
-        for (int k = K; k < K + kSlotGroup; ++k) b = fmaf(before(ts, slot_t(L, k)), slot_z(z, k), b);
-        SlotSums<K + kSlotGroup>::behind(L, z, ns, ts, b);
+        for (int k = K; k < K + kSlotGroup; k += 2) {
+            b = fmaf(before(ts, slot_t(L, k)), slot_z(z, k), b);
+            c = fmaf(before(ts, slot_t(L, k + 1)), slot_z(z, k + 1), c);
+        }
+        SlotSums<K + kSlotGroup>::behind(L, z, ns, ts, b, c);
     }
 };
 template <>
 struct SlotSums<kCompSlots> {
-    __device__ static __forceinline__ void front(const CompList &, int, float, float &) {}
-    __device__ static __forceinline__ void behind(const CompList &, const CompZ &, int, float, float &) {}
+    __device__ static __forceinline__ void front(const CompList &, int, float, float &, float &) {}
+    __device__ static __forceinline__ void behind(const CompList &, const CompZ &, int, float, float &, float &) {}
 };
-static_assert(kCompSlots % kSlotGroup == 0, "whole slot groups");
+static_assert(kCompSlots % kSlotGroup == 0 && kSlotGroup % 2 == 0, "whole slot groups, of pairs");
 
 // F at scaled depth ts inside window w: base, the densities at lo (if ts > lo), and the slots
 // in front of ts.
 __device__ __forceinline__ float comp_front(const CompList &L, int ns, const CompWin &w, float ts)
 {
-    float f = ts > w.lo ? w.base + w.tie : w.base;
-    SlotSums<0>::front(L, ns, ts, f);
-    return f;
+    float f = ts > w.lo ? w.base + w.tie : w.base, g = 0.0f;
+    SlotSums<0>::front(L, ns, ts, f, g);
+    return f + g;
 }
 
 // Sum of z over the slots behind ts.
 __device__ __forceinline__ float comp_behind(const CompList &L, const CompZ &z, int ns, float ts)
 {
-    float b = 0.0f;
-    SlotSums<0>::behind(L, z, ns, ts, b);
-    return b;
+    float b = 0.0f, c = 0.0f;
+    SlotSums<0>::behind(L, z, ns, ts, b, c);
+    return b + c;
 }
 
 // Entries of Gaussians [gb, gb + cnt) of the scene into LDS, EW float4 each: the entry, the terms
@@ -564,7 +572,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
     constexpr int LREC = (PLAIN ? kOffsetAcc : kPartial) + (COLOR ? 3 : 0);
     static_assert(LREC <= 16, "one 16-value wave sum per pair");
     __shared__ float4 ents[kCompTG * EW];
-    __shared__ float4 sents[kCompSlots * EW];  // the slots' entries (scenes beyond one LDS tile)
+    // the slots' entries, for scenes beyond one LDS tile (dynamic: launched without it when every
+    // scene is resident, so that more blocks share a compute unit)
+    extern __shared__ float4 sents[];
     __shared__ float rec[kCompTG * LREC];      // the item's sums of the staged Gaussians
     __shared__ int slot_g[kCompSlots];
     __shared__ int touched[kCompTG];
@@ -986,7 +996,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kFwdcWaves))
 
 #define FMB_FWDC_CALL(F_) hipLaunchKernelGGL((fwdc_kernel<F_>), dim3(n_items), dim3(64), 0, st, P, O, items, order)
 #define FMB_BWDC_CALL(F_)                                                                                 \
-    hipLaunchKernelGGL((bwdc_kernel<F_>), dim3(n_items), dim3(64), 0, st, P, I, items, order, partial,      \
+    hipLaunchKernelGGL((bwdc_kernel<F_>), dim3(n_items), dim3(64), dyn, st, P, I, items, order, partial,    \
                        beta_partial)
 
 // Blocks take the items in `order` (longest first) where given, else in item order.
@@ -999,11 +1009,13 @@ hipError_t launch_fwdc(int flags, int n_items, hipStream_t st, const Params &P, 
     return hipGetLastError();
 }
 
+// max_n: the largest scene of the batch (the slots' entries are staged only beyond one LDS tile).
 hipError_t launch_bwdc(int flags, int n_items, hipStream_t st, const Params &P, const BwdIn &I,
-                       const BwdItem *items, const int *order, float *partial, float *beta_partial)
+                       const BwdItem *items, const int *order, float *partial, float *beta_partial, int max_n)
 {
     flags &= ~kPer;
     if (n_items < 1) return hipSuccess;
+    const size_t dyn = max_n > kCompTG ? (size_t)kCompSlots * 6 * sizeof(float4) : 0;
     FMB_COMP_DISPATCH(flags, FMB_BWDC_CALL)
     return hipGetLastError();
 }
