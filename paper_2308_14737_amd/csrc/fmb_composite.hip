@@ -219,6 +219,36 @@ __device__ __forceinline__ float comp_behind(const CompList &L, const CompZ &z, 
     return b + c;
 }
 
+// z_bar of the slots' pairs without a normal or colour cotangent, from the slots alone: the pair's
+// weight 2^(lw - M2) / S with lw = -log2(e) F + log2(1 - exp(-delta)) at the slot's depth and
+// density, times (tf_bar t - kappa); 0 where the slot is empty for the lane.
+template <int K>
+struct SlotZ {
+    __device__ static __forceinline__ void run(const CompList &L, CompZ &zs, int ns, const CompWin &w, float M2,
+                                               float invS, float tfb, float kap)
+    {
+        if (K >= ns) return;
+#pragma unroll
+        for (int k = K; k < K + kSlotGroup; ++k) {
+            const float dl = slot_d(L, k), ts = slot_t(L, k);
+            float z = 0.0f;
+            if (dl > 0.0f) {
+                const float lw = fmaf(-(float)kLog2e, comp_front(L, ns, w, ts), log2_opacity(dl, __builtin_amdgcn_logf(dl)));
+                z = exp2_(lw - M2) * invS * fmaf(tfb, ts * (1.0f / kDepthScale), -kap);
+            }
+            slot_set_z(zs, k, z);
+        }
+        SlotZ<K + kSlotGroup>::run(L, zs, ns, w, M2, invS, tfb, kap);
+    }
+};
+template <>
+struct SlotZ<kCompSlots> {
+    __device__ static __forceinline__ void run(const CompList &, CompZ &, int, const CompWin &, float, float, float,
+                                               float)
+    {
+    }
+};
+
 // Entries of Gaussians [gb, gb + cnt) of the scene into LDS, EW float4 each: the entry, the terms
 // of the m estimate (make_entry_est) and, with EW = 6, the colour.
 constexpr int kCompEst = 4, kCompCol = 5;  // float4 offsets within an LDS entry
@@ -625,6 +655,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
         auto slots_z = [&](int ns) {
             zs.z0 = (CompV32)(0.0f);
             zs.z1 = (CompV16)(0.0f);
+            if (PLAIN) {
+                // z_bar = wt (tf_bar t - kappa) needs only the slot's depth and density
+                SlotZ<0>::run(L, zs, ns, w, M2, invS, tfb, kap);
+                return;
+            }
             if (!resident) {
                 __syncthreads();
                 if (lane < ns) {
