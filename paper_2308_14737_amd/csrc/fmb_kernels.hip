@@ -1038,9 +1038,9 @@ constexpr int kNumBwdGauss = (int)(sizeof kBwdRT / sizeof kBwdRT[0]);
 constexpr int kNumBwdRay = (int)(sizeof kBwdRay / sizeof kBwdRay[0]);
 // Variants 6-8: the tiled ray-lane kernel with T ray tiles per item (Gaussians staged 64 at a time);
 // without normal or colour cotangents only (the host runs variant 2 for those).
+// (256 threads per block for variants 6 and 7; variant 8 has eight waves share an item's 16 staged
+// tiles, 512 threads)
 static const int kBwdTiles[] = {8, 16, 16};
-// threads per block of the tiled variants (variant 8: eight waves share an item's 16 staged tiles)
-static const int kBwdTiledBlock[] = {256, 256, 512};
 constexpr int kNumBwdTiled = (int)(sizeof kBwdTiles / sizeof kBwdTiles[0]);
 constexpr int kBwdTiledFirst = kNumBwdGauss + kNumBwdRay;
 
