@@ -236,6 +236,34 @@ __device__ __forceinline__ float pair_m_low(const float4 &est, float vc, float t
     return fmaf(-kErr, fmaf(est.y, fabsf(t), est.x), fmaf(-vc, t, est.x));
 }
 
+// Upper bounds of the log2 density and of beta1 log2(density) + |nc2| |t| over every ray of a
+// tile, from the tile's unit centre direction c and the largest distance rho of its unit ray
+// directions from c (tc = (c, rho)), for the Gaussian of entry g (est: its m estimate terms).
+// For a ray v, any depth t gives |U(t v - mu')| >= |U(t c - mu')| - |U|_2 |t| |v - c|, so the
+// ray's m is at least (sqrt(m_c) - |U|_2 t_max rho)^2 with m_c the centre ray's m (from below, as
+// pair_m_low bounds it) and t_max >= |t| = |(U v).(U mu')| / |U v|^2 <= |U mu'| |U^-1|_2; the
+// 2-norms are bounded by sqrt(|.|_1 |.|_inf).  The slack terms cover the FP32 rounding of the bound.
+__device__ __forceinline__ void tile_bounds(const Ent &g, const float4 &est, const float4 &tc, float hm, float b1,
+                                            float nc2, float &d2_hi, float &z_hi)
+{
+    Geo qc;
+    const float vc = pair_geo_peak(g, tc.x, tc.y, tc.z, qc);
+    const float mc = fmaxf(pair_m_low(est, vc, qc.t), 0.0f);
+    const float a00 = fabsf(g.u00), a01 = fabsf(g.u01), a02 = fabsf(g.u02);
+    const float a11 = fabsf(g.u11), a12 = fabsf(g.u12), a22 = fabsf(g.u22);
+    const float u2 = sqrtf(fmaxf(a00, fmaxf(a01 + a11, a02 + a12 + a22)) * fmaxf(a00 + a01 + a02, fmaxf(a11 + a12, a22)));
+    // U^-1 of the upper-triangular U
+    const float i00 = rcp_(g.u00), i11 = rcp_(g.u11), i22 = rcp_(g.u22);
+    const float i01 = -g.u01 * i00 * i11, i12 = -g.u12 * i11 * i22;
+    const float i02 = (g.u01 * g.u12 - g.u02 * g.u11) * i00 * i11 * i22;
+    const float c1 = fmaxf(fabsf(i00), fmaxf(fabsf(i01) + fabsf(i11), fabsf(i02) + fabsf(i12) + fabsf(i22)));
+    const float r1 = fmaxf(fabsf(i00) + fabsf(i01) + fabsf(i02), fmaxf(fabsf(i11) + fabsf(i12), fabsf(i22)));
+    const float tmax = sqrtf(est.x * c1 * r1) * (1.0f + 1e-4f);
+    const float lo = fmaxf(0.0f, sqrtf(mc) * (1.0f - 1e-4f) - u2 * tmax * tc.w * (1.0f + 1e-4f));
+    d2_hi = fmaf(hm, lo * lo * (1.0f - 1e-4f), g.l2l) + 1e-3f;
+    z_hi = fmaf(b1, d2_hi, fabsf(nc2) * tmax);
+}
+
 __device__ __forceinline__ void pair_geo_coarse(const Ent &g, float v0, float v1, float v2, float hm, float b1,
                                                 float nc2, Geo &q)
 {

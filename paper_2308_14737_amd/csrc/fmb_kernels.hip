@@ -586,7 +586,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
     constexpr bool PERSIST = (F & kPer) != 0;
     constexpr int NW = BLOCK / 64;
     constexpr int RAYS = 64 * T;
+    static_assert(T <= 32, "a 32-bit mask of the item's ray tiles");
     __shared__ float4 rays[2 * RAYS];         // per ray: (v, M2 + log2 S), (tf_bar, D_bar, dc, t_f)
+    __shared__ float4 tcone[T];               // per ray tile: unit centre direction, largest |v - c|
+    __shared__ float tnorm[T];                // per ray tile: least M2 + log2 S over its rays
     __shared__ float4 ents[5 * TG];           // the Gaussian tile's entries (with the m estimate terms)
     __shared__ float rec[kOffsetAcc * TG];    // (H, Bv, L) of each Gaussian of the tile
     __shared__ float bsum[2 * NW];
@@ -626,6 +629,32 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
             rays[2 * q] = make_float4(pr[0].x, pr[0].y, pr[0].z, pr[0].w - __builtin_amdgcn_logf(pr[1].x));
             rays[2 * q + 1] = make_float4(pr[1].y, pr[2].z, pr[3].w, pr[2].w);
         }
+        __syncthreads();
+        // each ray tile's cone (centre direction and radius) and least normaliser, for the bound
+        // that lets a wave pass over the tiles on which a Gaussian can neither weigh above FP32's
+        // zero nor add a density above 2^kDensSkipLog2 (tile_bounds)
+        for (int tt = wave; tt < nt; tt += NW) {
+            int row, col;
+            const bool ok = tile_local(vr, item.ray0 + tt, lane, row, col) >= 0;
+            const float4 x0 = rays[2 * (64 * tt + lane)];
+            float c0 = wave_sum(ok ? x0.x : 0.0f), c1 = wave_sum(ok ? x0.y : 0.0f), c2 = wave_sum(ok ? x0.z : 0.0f);
+            const float inv = rsq_(fmaf(c0, c0, fmaf(c1, c1, fmaf(c2, c2, kEpsN))));
+            c0 *= inv;
+            c1 *= inv;
+            c2 *= inv;
+            const float e0 = x0.x - c0, e1 = x0.y - c1, e2 = x0.z - c2;
+            float rho = ok ? sqrtf(fmaf(e0, e0, fmaf(e1, e1, e2 * e2))) : 0.0f;
+            float nmin = ok ? x0.w : INFINITY;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                rho = fmaxf(rho, __shfl_xor(rho, off, 64));
+                nmin = fminf(nmin, __shfl_xor(nmin, off, 64));
+            }
+            if (lane == 0) {
+                tcone[tt] = make_float4(c0, c1, c2, rho * (1.0f + 1e-4f) + 1e-6f);
+                tnorm[tt] = nmin;
+            }
+        }
         float aB1 = 0.0f, aB2 = 0.0f;
         for (int gb = 0; gb < sr.n; gb += TG) {
             const int cnt = min(TG, sr.n - gb);
@@ -638,9 +667,22 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
             for (int i = wave; i < cnt; i += NW) {
                 const Ent g = ent_from(ents[5 * i], ents[5 * i + 1], ents[5 * i + 2], ents[5 * i + 3]);
                 const float4 est = ents[5 * i + 4];
+                // the tiles the Gaussian can matter on (lane t tests tile t)
+                unsigned tmask;
+                {
+                    bool need = false;
+                    if (lane < nt) {
+                        float d2_hi, z_hi;
+                        tile_bounds(g, est, tcone[lane], bl.hm, bl.b1, bl.nc2, d2_hi, z_hi);
+                        need = !b1_pos || z_hi - tnorm[lane] >= kSkipLog2 || d2_hi >= kDensSkipLog2;
+                    }
+                    tmask = (unsigned)__ballot(need);
+                }
                 OffsetAcc acc;
 #pragma unroll 1
-                for (int t = 0; t < nt; ++t) {
+                while (tmask) {
+                    const int t = __builtin_ctz(tmask);
+                    tmask &= tmask - 1;
                     const float4 x0 = rays[2 * (64 * t + lane)], x1 = rays[2 * (64 * t + lane) + 1];
                     Geo q;
                     const float vc = pair_geo_peak(g, x0.x, x0.y, x0.z, q);
