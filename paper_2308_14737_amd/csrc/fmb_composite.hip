@@ -278,10 +278,10 @@ __device__ __forceinline__ Ent comp_ent(const float4 *__restrict__ ents, int i)
     return ent_from(ents[EW * i], ents[EW * i + 1], ents[EW * i + 2], ents[EW * i + 3]);
 }
 
-// Cone of a wave's rays: unit centre direction (uniform over the wave) and the cosine and sine of
-// the largest angle between it and a ray of the wave.
+// Cone of a wave's rays: unit centre direction (uniform over the wave) and the cosine of the
+// largest angle between it and a ray of the wave.
 struct TileCone {
-    float c0, c1, c2, ca, sa;
+    float c0, c1, c2, ca;
 };
 
 __device__ __forceinline__ float wave_sum_f(float x)
@@ -307,37 +307,12 @@ __device__ __forceinline__ TileCone comp_cone(float v0, float v1, float v2, bool
     for (int off = 32; off >= 1; off >>= 1) ca = fminf(ca, __shfl_xor(ca, off, 64));
     // margins for the rounding of the directions and of the cone
     tc.ca = fminf(ca, 1.0f) - 1e-5f;
-    tc.sa = sqrtf(fmaxf(0.0f, 1.0f - tc.ca * tc.ca)) + 1e-5f;
     return tc;
 }
 
-// Upper bound of the base-2 log density of Gaussian g on any ray of the cone (origin o): with
-// p = mu - o, the squared Mahalanobis distance of a ray line is at least d^2 / s^2, d the
-// Euclidean distance of mu from the line (at least |p| sin(angle(p, centre line) - cone angle))
-// and s^2 = |U^-1|_1 |U^-1|_inf at least the largest variance |U^-1|_2^2 (equal to it for an
-// axis-aligned Gaussian).
-__device__ __forceinline__ float comp_bound_log2(const Ent &g, const TileCone &tc)
-{
-    const float pp = fmaf(g.mh0, g.mh0, fmaf(g.mh1, g.mh1, g.mh2 * g.mh2));
-    const float pv = fabsf(fmaf(g.mh0, tc.c0, fmaf(g.mh1, tc.c1, g.mh2 * tc.c2)));
-    // |p x c| from the cross product (accurate also for p close to the centre line)
-    const float x0 = fmaf(g.mh1, tc.c2, -g.mh2 * tc.c1);
-    const float x1 = fmaf(g.mh2, tc.c0, -g.mh0 * tc.c2);
-    const float x2 = fmaf(g.mh0, tc.c1, -g.mh1 * tc.c0);
-    const float px = sqrtf(fmaf(x0, x0, fmaf(x1, x1, x2 * x2)));
-    const float d = fmaxf(0.0f, fmaf(px, tc.ca, -pv * tc.sa) - 1e-5f * sqrtf(pp));
-    // U^-1 of the upper-triangular U
-    const float i00 = rcp_(g.u00), i11 = rcp_(g.u11), i22 = rcp_(g.u22);
-    const float i01 = -g.u01 * i00 * i11, i12 = -g.u12 * i11 * i22;
-    const float i02 = (g.u01 * g.u12 - g.u02 * g.u11) * i00 * i11 * i22;
-    const float c1 = fmaxf(fabsf(i00), fmaxf(fabsf(i01) + fabsf(i11), fabsf(i02) + fabsf(i12) + fabsf(i22)));
-    const float r1 = fmaxf(fabsf(i00) + fabsf(i01) + fabsf(i02), fmaxf(fabsf(i11) + fabsf(i12), fabsf(i22)));
-    const float s2 = c1 * r1 * (1.0f + 1e-5f);
-    return fmaf((float)(-0.5 * kLog2e), d * d * rcp_(s2) * (1.0f - 1e-5f), g.l2l + 1e-5f);
-}
-
-// Staged Gaussians [0, cnt) whose bound on the cone exceeds thr, as two 64-bit masks (lane j
-// tests Gaussians j and 64 + j).
+// Staged Gaussians [0, cnt) whose log2 density can exceed thr on some ray of the cone (the bound of
+// tile_bounds from the cone's centre ray and radius), as two 64-bit masks (lane j tests Gaussians
+// j and 64 + j).
 __device__ __forceinline__ void comp_cull(const float4 *__restrict__ ents, int ew, int cnt, const TileCone &tc,
                                           float thr, unsigned long long mask[2])
 {
@@ -348,7 +323,12 @@ __device__ __forceinline__ void comp_cull(const float4 *__restrict__ ents, int e
         bool keep = false;
         if (i < cnt) {
             const Ent g = ent_from(ents[ew * i], ents[ew * i + 1], ents[ew * i + 2], ents[ew * i + 3]);
-            keep = comp_bound_log2(g, tc) > thr;
+            // the largest distance of a unit ray direction of the cone from its centre: |v - c|^2 = 2 - 2 cos
+            const float rho = sqrtf(fmaxf(0.0f, 2.0f - 2.0f * tc.ca)) * (1.0f + 1e-4f) + 1e-6f;
+            float d2_hi, z_hi;
+            tile_bounds(g, ents[ew * i + kCompEst], make_float4(tc.c0, tc.c1, tc.c2, rho), (float)(-0.5 * kLog2e),
+                        0.0f, 0.0f, d2_hi, z_hi);
+            keep = d2_hi > thr;
         }
         mask[c] = __ballot(keep);
     }
