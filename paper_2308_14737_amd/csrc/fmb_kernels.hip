@@ -83,6 +83,30 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
                 dt[j] = O.depth_t[vr.ray_off + lc];
             }
         }
+        // The cone of each of the wave's ray tiles (unit centre direction, largest |v - c|), for the
+        // bound of tile_bounds: lane l bounds Gaussian l / RPT on ray tile l % RPT (cl: its cone).
+        const int jl = lane % RPT;
+        float4 cl = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const bool ok = loc[j] >= 0;
+            float c0 = ok ? v0[j] : 0.0f, c1 = ok ? v1[j] : 0.0f, c2 = ok ? v2[j] : 0.0f;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                c0 += __shfl_xor(c0, off, 64);
+                c1 += __shfl_xor(c1, off, 64);
+                c2 += __shfl_xor(c2, off, 64);
+            }
+            const float inv = rsq_(fmaf(c0, c0, fmaf(c1, c1, fmaf(c2, c2, kEpsN))));
+            c0 *= inv;
+            c1 *= inv;
+            c2 *= inv;
+            const float e0 = v0[j] - c0, e1 = v1[j] - c1, e2 = v2[j] - c2;
+            float rho = ok ? sqrtf(fmaf(e0, e0, fmaf(e1, e1, e2 * e2))) : 0.0f;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) rho = fmaxf(rho, __shfl_xor(rho, off, 64));
+            if (jl == j) cl = make_float4(c0, c1, c2, rho * (1.0f + 1e-4f) + 1e-6f);
+        }
 
         for (int gb = 0; gb < sr.n; gb += TG) {
             const int cnt = min(TG, sr.n - gb);
@@ -93,14 +117,49 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
                 if (COLOR) tile[EW * q + 5] = colour_entry(P.colors + 3 * gi);
             }
             __syncthreads();
+            // Two sweeps over the staged Gaussians, GP at a time.  The first takes the (Gaussian, ray
+            // tile) pairs whose density can reach 2^kDensSkipLog2 on some ray of the tile -- these
+            // hold every ray's largest weights -- and the second the others, except where the tile's
+            // least running maximum then rules out a weight above FP32's zero (tile_bounds; a pair
+            // of neither sweep is one the per-pair test below would skip).  Without beta1 >= 0 the
+            // weight bound does not hold and the first sweep takes every pair.
+            constexpr int GP = 64 / RPT;
+            float mmin = -INFINITY;  // the least running maximum of lane's bound tile (second sweep)
+            for (int sweep = 0; sweep < 2; ++sweep) {
+              if (sweep == 1) {
+#pragma unroll
+                for (int j = 0; j < RPT; ++j) {
+                    float mm = loc[j] >= 0 ? M[j] : INFINITY;
+#pragma unroll
+                    for (int off = 32; off > 0; off >>= 1) mm = fminf(mm, __shfl_xor(mm, off, 64));
+                    if (jl == j) mmin = mm;
+                }
+              }
+              for (int ib = 0; ib < cnt; ib += GP) {
+                const int il = ib + lane / RPT;
+                bool need = false;
+                if (il < cnt) {
+                    const Ent gl = ent_from(tile[EW * il], tile[EW * il + 1], tile[EW * il + 2], tile[EW * il + 3]);
+                    float d2h, zh;
+                    tile_bounds(gl, tile[EW * il + 4], cl, bl.hm, bl.b1, bl.nc2, d2h, zh);
+                    const bool first = !b1_pos || d2h >= kDensSkipLog2;
+                    need = sweep == 0 ? first : (!first && zh - mmin >= kSkipLog2);
+                }
+                const unsigned long long nm = __ballot(need);
+                if (nm == 0ull) continue;
+                const int kn = min(GP, cnt - ib);
 #pragma unroll 2
-            for (int i = 0; i < cnt; ++i) {
+              for (int k = 0; k < kn; ++k) {
+                const unsigned bits = (unsigned)(nm >> (k * RPT)) & ((1u << RPT) - 1u);
+                if (bits == 0u) continue;
+                const int i = ib + k;
                 const Ent g = ent_from(tile[EW * i], tile[EW * i + 1], tile[EW * i + 2], tile[EW * i + 3]);
                 const float4 est = tile[EW * i + 4];
                 float4 cc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                 if (COLOR) cc = tile[EW * i + 5];
 #pragma unroll
                 for (int j = 0; j < RPT; ++j) {
+                    if (!((bits >> j) & 1u)) continue;  // no ray of tile j needs the pair
                     Geo q;
                     const float vc = pair_geo_peak(g, v0[j], v1[j], v2[j], q);
                     {
@@ -155,6 +214,8 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
                         C2[j] = fmaf(ew, cc.z, C2[j]);
                     }
                 }
+              }
+              }
             }
         }
 
