@@ -328,7 +328,7 @@ __device__ __forceinline__ void comp_cull(const float4 *__restrict__ ents, int e
             float d2_hi, z_hi;
             tile_bounds(g, ents[ew * i + kCompEst], make_float4(tc.c0, tc.c1, tc.c2, rho), (float)(-0.5 * kLog2e),
                         0.0f, 0.0f, d2_hi, z_hi);
-            keep = d2_hi > thr;
+            keep = !(d2_hi <= thr);  // (a NaN bound keeps the Gaussian)
         }
         mask[c] = __ballot(keep);
     }

@@ -142,8 +142,9 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
                     const Ent gl = ent_from(tile[EW * il], tile[EW * il + 1], tile[EW * il + 2], tile[EW * il + 3]);
                     float d2h, zh;
                     tile_bounds(gl, tile[EW * il + 4], cl, bl.hm, bl.b1, bl.nc2, d2h, zh);
-                    const bool first = !b1_pos || d2h >= kDensSkipLog2;
-                    need = sweep == 0 ? first : (!first && zh - mmin >= kSkipLog2);
+                    // (comparisons written so that a NaN bound keeps the pair)
+                    const bool first = !(b1_pos && d2h < kDensSkipLog2);
+                    need = sweep == 0 ? first : (!first && !(zh - mmin < kSkipLog2));
                 }
                 const unsigned long long nm = __ballot(need);
                 if (nm == 0ull) continue;
@@ -735,7 +736,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
                     if (lane < nt) {
                         float d2_hi, z_hi;
                         tile_bounds(g, est, tcone[lane], bl.hm, bl.b1, bl.nc2, d2_hi, z_hi);
-                        need = !b1_pos || z_hi - tnorm[lane] >= kSkipLog2 || d2_hi >= kDensSkipLog2;
+                        // (written so that a NaN bound keeps the tile)
+                        need = !(b1_pos && z_hi - tnorm[lane] < kSkipLog2 && d2_hi < kDensSkipLog2);
                     }
                     tmask = (unsigned)__ballot(need);
                 }
