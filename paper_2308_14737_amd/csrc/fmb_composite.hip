@@ -625,6 +625,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
         // a normalised weight 2^(lw - M2) / S is below 2^skip2 where lw < M2 + log2 S + skip2,
         // and lw is at most the log2 density
         const float wskip = valid ? M2 - __builtin_amdgcn_logf(invS) + skip2 : INFINITY;
+        // the least cutoff of the wave's rays (pairs below a ray's cutoff are not taken)
+        float lim_min = valid ? fminf(skip2, wskip) : INFINITY;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) lim_min = fminf(lim_min, __shfl_xor(lim_min, off, 64));
         const CompWin w0{valid ? -INFINITY : INFINITY, INFINITY, 0.0f, 0.0f};
         CompWin w = w0;
         CompList L;
@@ -812,9 +816,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
                         for (int q = lane; q < cnt; q += 64) touched[q] = 0;
                         __syncthreads();
                     }
-                    for (int i = 0; i < cnt; i += 2) {  // two Gaussians a step (two independent chains)
-                        const bool two = i + 1 < cnt;
-                        const int ib = two ? i + 1 : i;
+                    // only the Gaussians whose density can reach some lane's cutoff on the tile
+                    // (the tile bound of comp_cull), two a step (two independent chains)
+                    unsigned long long fm[2];
+                    comp_cull(ents, EW, cnt, tc, lim_min, fm);
+                    for (int c = 0; c < 2; ++c) {
+                      unsigned long long mk = fm[c];
+                      while (mk) {
+                        const int i = 64 * c + __builtin_ctzll(mk);
+                        mk &= mk - 1;
+                        const bool two = mk != 0;
+                        const int ib = two ? 64 * c + __builtin_ctzll(mk) : i;
+                        if (two) mk &= mk - 1;
                         const Ent ga = comp_ent<EW>(ents, i), gb = comp_ent<EW>(ents, ib);
                         Geo qa, qb;
                         const float vca = pair_geo_peak(ga, v0, v1, v2, qa), vcb = pair_geo_peak(gb, v0, v1, v2, qb);
@@ -839,6 +852,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
                                 if (!resident && lane == 0) touched[ib] = 1;
                             }
                         }
+                      }
                     }
                     if (!resident) {
                         // add the tile's sums of this window to the item's record
