@@ -125,6 +125,32 @@ def test_ragged_parity(fmb, label, n, views):
     assert_grads(eg, label)
 
 
+@pytest.mark.parametrize("model", ["blend", "composite"])
+def test_anisotropic_tile_bounds(fmb, model):
+    """Gaussians with scale ratios up to 100 (needles and discs), where the tile bound that lets a
+    wave pass over whole (ray tile, Gaussian) pairs is tightest against the true densities: the
+    forward and the gradients (depth and alpha cotangents as in the benchmarked step, and random
+    cotangents on covered rays) match the oracle in both models."""
+    sc, cams = custom_scene(60, [(64, 64), (96, 128), (48, 40)], seed=29, s_range=(0.005, 0.5))
+    betas = np.array([W.BETA1, W.BETA2], np.float32)
+    _say(f"[aniso] {model}: N=60 scale ratios up to 100")
+    scene, _ = make_scene(fmb, torch, sc, cams, betas, 1.0, DEV)
+    scene.set_model(model)
+    outs = scene.render(normals=True)
+    ref, _, _ = O.render_workload_view(sc, cams, betas, 1.0, model=model)
+    e = compare_forward(outs, ref, flow=False)
+    t = lambda a: torch.as_tensor(a, device=DEV).contiguous()  # noqa: E731
+    cot = hit_mask_cot(W.random_cotangents(cams.n_rays, 31, flow=False), ref["alpha"])
+    for c in (dict(cot, normal=None), cot):
+        g = scene.backward(outs, t(c["depth"]), t(c["alpha"]), None if c["normal"] is None else t(c["normal"]))
+        torch.cuda.synchronize()
+        _, gref, _ = O.render_workload_view(sc, cams, betas, 1.0, cot=c, model=model)
+        eg = compare_grads(g, gref)
+        _say(f"[aniso] {model} normal cotangent {c['normal'] is not None}: {e} {fmt(eg)}")
+        assert_grads(eg, f"anisotropic {model}")
+    assert_forward(e, f"anisotropic {model}")
+
+
 def test_background_rays_conditioning(fmb):
     """Unmasked random cotangents on a sparse scene whose image is mostly background.  There the
     exact gradient itself moves by ~1e-3 when the FP32 inputs move by one ulp (measured below
