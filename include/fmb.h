@@ -373,8 +373,8 @@ int fmb_set_config(fmb_scene *scene, fmb_batch *batch, int32_t fwd_variant, int3
  * held by the block's lanes for variants 3-5, which give each lane rays as the forward pass
  * does and sum each Gaussian's terms over the wave per tile; the rays of an item, 8 or 16 tiles
  * of 8 x 8 pixels, for variants 6-8 (8: blocks of 512 threads), which give each lane a ray of
- * a tile and each wave a Gaussian at a time -- they take no normal or colour cotangent, and
- * calls with one run variant 2), forward and backward persistent-grid multipliers, and the
+ * a tile and each wave a Gaussian at a time -- they take no normal cotangent, and calls with
+ * one run variant 2), forward and backward persistent-grid multipliers, and the
  * forward and backward work-item counts (0 until the first call built them). */
 int fmb_get_config(const fmb_scene *scene, const fmb_batch *batch, int32_t *out);
 

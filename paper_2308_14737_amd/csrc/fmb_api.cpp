@@ -642,11 +642,11 @@ struct Job {
         return FMB_OK;
     }
 
-    // The backward variant a call runs: the tiled variants take no normal or colour cotangent, so
-    // such calls run the Gaussian-lane variant 2 instead.
+    // The backward variant a call runs: the tiled variants take no normal cotangent, so such calls
+    // run the Gaussian-lane variant 2 instead.
     int bwd_run_variant(const BwdIn &I) const
     {
-        return bwd_variant_tiles(bwd_variant) > 0 && (I.g_normal || I.g_color) ? 2 : bwd_variant;
+        return bwd_variant_tiles(bwd_variant) > 0 && I.g_normal ? 2 : bwd_variant;
     }
 
     static int fwd_flags(const FwdOut &O, bool persist)

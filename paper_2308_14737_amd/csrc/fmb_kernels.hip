@@ -629,7 +629,7 @@ __global__ __launch_bounds__(BLOCK) void bwdr_kernel(Params P, BwdIn I, const Bw
 }
 
 // ------------------------------------------------------------------------------------
-// Backward, tiled ray-lane layout (no normal or colour cotangent): an item is T ray tiles of
+// Backward, tiled ray-lane layout (no normal cotangent): an item is T ray tiles of
 // one view (8 x 8 pixels, see ViewRec) against every Gaussian of its scene.  The item's rays
 // are staged in LDS with their adjoint prologue; each wave takes every NW-th Gaussian and walks
 // the T tiles with a lane per ray, so a lane sums that Gaussian's terms over T rays before one
@@ -644,16 +644,21 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
     Params P, BwdIn I, const BwdItem *__restrict__ items, int n_items, const int *__restrict__ order,
     int *__restrict__ counter, float *__restrict__ partial, float *__restrict__ beta_partial)
 {
-    static_assert((F & (kNrm | kCol)) == 0, "the tiled backward takes no normal or colour cotangent");
-    constexpr bool PERSIST = (F & kPer) != 0;
+    static_assert((F & kNrm) == 0, "the tiled backward takes no normal cotangent");
+    constexpr bool PERSIST = (F & kPer) != 0, COLOR = (F & kCol) != 0;
     constexpr int NW = BLOCK / 64;
     constexpr int RAYS = 64 * T;
     static_assert(T <= 32, "a 32-bit mask of the item's ray tiles");
-    __shared__ float4 rays[2 * RAYS];         // per ray: (v, M2 + log2 S), (tf_bar, D_bar, dc, t_f)
+    constexpr int RW = COLOR ? 3 : 2;                         // float4 per staged ray
+    constexpr int EW = COLOR ? 6 : 5;                         // float4 per staged Gaussian
+    constexpr int LREC = kOffsetAcc + (COLOR ? 3 : 0);        // sums per Gaussian
+    constexpr int REC = COLOR ? kPartialColor : kPartial;     // partial record per Gaussian
+    // per ray: (v, M2 + log2 S), (tf_bar, D_bar, dc, t_f) [, (C_bar, C_bar . C)]
+    __shared__ float4 rays[RW * RAYS];
     __shared__ float4 tcone[T];               // per ray tile: unit centre direction, largest |v - c|
     __shared__ float tnorm[T];                // per ray tile: least M2 + log2 S over its rays
-    __shared__ float4 ents[5 * TG];           // the Gaussian tile's entries (with the m estimate terms)
-    __shared__ float rec[kOffsetAcc * TG];    // (H, Bv, L) of each Gaussian of the tile
+    __shared__ float4 ents[EW * TG];          // the Gaussian tile's entries (m estimate terms, colour)
+    __shared__ float rec[LREC * TG];          // (H, Bv, L) [and the colour sums] of each Gaussian
     __shared__ float bsum[2 * NW];
     __shared__ int s_item;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -688,8 +693,17 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
             ray_prologue<F>(P, I, item.view, vr, e, kk, o0, o1, o2, local >= 0 ? local : 0, local >= 0, bl.b1, bl.nc2,
                             pr);
             // the weight 2^(z2 - M2) / S as 2^(z2 - M2 - log2 S); a ray past the edge has M2 = inf, S = inf
-            rays[2 * q] = make_float4(pr[0].x, pr[0].y, pr[0].z, pr[0].w - __builtin_amdgcn_logf(pr[1].x));
-            rays[2 * q + 1] = make_float4(pr[1].y, pr[2].z, pr[3].w, pr[2].w);
+            rays[RW * q] = make_float4(pr[0].x, pr[0].y, pr[0].z, pr[0].w - __builtin_amdgcn_logf(pr[1].x));
+            rays[RW * q + 1] = make_float4(pr[1].y, pr[2].z, pr[3].w, pr[2].w);
+            if (COLOR) {
+                // the colour cotangent and its product with the blended colour (kappa's colour part)
+                float kc = 0.0f;
+                if (local >= 0) {
+                    const size_t r3 = 3 * ((size_t)vr.ray_off + local);
+                    kc = fmaf(pr[3].x, I.color[r3], fmaf(pr[3].y, I.color[r3 + 1], pr[3].z * I.color[r3 + 2]));
+                }
+                rays[RW * q + 2] = make_float4(pr[3].x, pr[3].y, pr[3].z, kc);
+            }
         }
         __syncthreads();
         // each ray tile's cone (centre direction and radius) and least normaliser, for the bound
@@ -698,7 +712,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
         for (int tt = wave; tt < nt; tt += NW) {
             int row, col;
             const bool ok = tile_local(vr, item.ray0 + tt, lane, row, col) >= 0;
-            const float4 x0 = rays[2 * (64 * tt + lane)];
+            const float4 x0 = rays[RW * (64 * tt + lane)];
             float c0 = wave_sum(ok ? x0.x : 0.0f), c1 = wave_sum(ok ? x0.y : 0.0f), c2 = wave_sum(ok ? x0.z : 0.0f);
             const float inv = rsq_(fmaf(c0, c0, fmaf(c1, c1, fmaf(c2, c2, kEpsN))));
             c0 *= inv;
@@ -723,12 +737,15 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
             __syncthreads();  // staged rays visible; the previous tile's entries and sums are consumed
             for (int q = tid; q < cnt; q += BLOCK) {
                 const int gi = sr.gauss_off + gb + q;
-                make_entry_est(P.means + 3 * gi, P.prec + 6 * gi, P.weights[gi], o, &ents[5 * q]);
+                make_entry_est(P.means + 3 * gi, P.prec + 6 * gi, P.weights[gi], o, &ents[EW * q]);
+                if (COLOR) ents[EW * q + 5] = colour_entry(P.colors + 3 * gi);
             }
             __syncthreads();
             for (int i = wave; i < cnt; i += NW) {
-                const Ent g = ent_from(ents[5 * i], ents[5 * i + 1], ents[5 * i + 2], ents[5 * i + 3]);
-                const float4 est = ents[5 * i + 4];
+                const Ent g = ent_from(ents[EW * i], ents[EW * i + 1], ents[EW * i + 2], ents[EW * i + 3]);
+                const float4 est = ents[EW * i + 4];
+                float4 cc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (COLOR) cc = ents[EW * i + 5];
                 // the tiles the Gaussian can matter on (lane t tests tile t)
                 unsigned tmask;
                 {
@@ -742,11 +759,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
                     tmask = (unsigned)__ballot(need);
                 }
                 OffsetAcc acc;
+                float aC0 = 0.0f, aC1 = 0.0f, aC2 = 0.0f;  // colour sums: wt C_bar
 #pragma unroll 1
                 while (tmask) {
                     const int t = __builtin_ctz(tmask);
                     tmask &= tmask - 1;
-                    const float4 x0 = rays[2 * (64 * t + lane)], x1 = rays[2 * (64 * t + lane) + 1];
+                    const float4 x0 = rays[RW * (64 * t + lane)], x1 = rays[RW * (64 * t + lane) + 1];
                     Geo q;
                     const float vc = pair_geo_peak(g, x0.x, x0.y, x0.z, q);
                     {
@@ -770,10 +788,19 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
                         // t_bar = 0, d_bar = D_bar delta (the offset form then adds exactly that)
                         float tb = 0.0f, db = dd;
                         if (any_w) {
-                            // z_bar = wt (tf_bar t - kappa) with kappa = tf_bar t_f
+                            // z_bar = wt (tf_bar t - kappa) with kappa = tf_bar t_f [+ C_bar . C, and
+                            // C_bar . c added to the pair's share]
                             const float x = q.t - x1.w;
-                            const float wtf = exp2_(zr) * x1.x;
-                            const float zb = wtf * x;
+                            const float wt = exp2_(zr);
+                            const float wtf = wt * x1.x;
+                            float zb = wtf * x;
+                            if (COLOR) {
+                                const float4 x2 = rays[RW * (64 * t + lane) + 2];
+                                zb = fmaf(wt, fmaf(x2.x, cc.x, fmaf(x2.y, cc.y, fmaf(x2.z, cc.z, -x2.w))), zb);
+                                aC0 = fmaf(wt, x2.x, aC0);
+                                aC1 = fmaf(wt, x2.y, aC1);
+                                aC2 = fmaf(wt, x2.z, aC2);
+                            }
                             tb = fmaf(-bl.cb, zb, wtf);
                             db = fmaf(bl.b1, zb, dd);
                             aB1 = fmaf(zb, q.d2 - x1.z, aB1);
@@ -785,15 +812,18 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
                 }
                 float v[16];
                 offset_acc_store(acc, v);
-                v[13] = v[14] = v[15] = 0.0f;
+                v[13] = aC0;
+                v[14] = aC1;
+                v[15] = aC2;
+                static_assert(kOffsetAcc + 3 <= 16, "one 16-value wave sum per Gaussian");
                 const float tot = wave_sum16(v, lane);
                 const int idx = wave16_index(lane);
-                if ((lane & 3) == 0 && idx < kOffsetAcc) rec[kOffsetAcc * i + idx] = tot;
+                if ((lane & 3) == 0 && idx < LREC) rec[LREC * i + idx] = tot;
             }
             __syncthreads();
             for (int q = tid; q < cnt; q += BLOCK) {
                 const int gg = sr.gauss_off + gb + q;
-                write_partial_offset(partial + item.poff + kPartial * (gb + q), rec + kOffsetAcc * q, kPartial,
+                write_partial_offset(partial + item.poff + REC * (gb + q), rec + LREC * q, REC,
                                      P.prec + 6 * gg, P.means + 3 * gg, o);
             }
         }
@@ -1142,7 +1172,7 @@ static const BwdRayVariant kBwdRay[] = {{2, 64}, {4, 64}, {4, 128}};
 constexpr int kNumBwdGauss = (int)(sizeof kBwdRT / sizeof kBwdRT[0]);
 constexpr int kNumBwdRay = (int)(sizeof kBwdRay / sizeof kBwdRay[0]);
 // Variants 6-8: the tiled ray-lane kernel with T ray tiles per item (Gaussians staged 64 at a time);
-// without normal or colour cotangents only (the host runs variant 2 for those).
+// without a normal cotangent only (the host runs variant 2 for that).
 // (256 threads per block for variants 6 and 7; variant 8 has eight waves share an item's 16 staged
 // tiles, 512 threads)
 static const int kBwdTiles[] = {8, 16, 16};
@@ -1210,6 +1240,10 @@ static hipError_t launch_bwdt_v(int f, int grid, hipStream_t st, const Params &P
     case kFlw: FMB_BWDT_CALL(kFlw); break;
     case kPer: FMB_BWDT_CALL(kPer); break;
     case kFlw | kPer: FMB_BWDT_CALL(kFlw | kPer); break;
+    case kCol: FMB_BWDT_CALL(kCol); break;
+    case kCol | kFlw: FMB_BWDT_CALL(kCol | kFlw); break;
+    case kCol | kPer: FMB_BWDT_CALL(kCol | kPer); break;
+    case kCol | kFlw | kPer: FMB_BWDT_CALL(kCol | kFlw | kPer); break;
     default: return hipErrorInvalidValue;
     }
 #undef FMB_BWDT_CALL
@@ -1219,7 +1253,7 @@ static hipError_t launch_bwdt_v(int f, int grid, hipStream_t st, const Params &P
 int num_fwd_variants() { return (int)(sizeof kFwdVariants / sizeof kFwdVariants[0]); }
 int fwd_variant_rays(int v) { return kBlock * kFwdVariants[v].rpt; }
 int num_bwd_variants() { return kNumBwdGauss + kNumBwdRay + kNumBwdTiled; }
-// Tiled variants 6-8: ray tiles per item (0 for the others); they take no normal or colour cotangent.
+// Tiled variants 6-8: ray tiles per item (0 for the others); they take no normal cotangent.
 int bwd_variant_tiles(int v) { return v >= kBwdTiledFirst && v < num_bwd_variants() ? kBwdTiles[v - kBwdTiledFirst] : 0; }
 // Gaussian-lane variants: rays staged per pass; others: 0.
 int bwd_variant_rt(int v) { return v < kNumBwdGauss ? kBwdRT[v] : 0; }
@@ -1360,11 +1394,19 @@ hipError_t occupancy_bwd(int variant, int flags, int *blocks_per_cu)
     }
 #undef FMB_OCC_V
 #undef FMB_OCC_F
-    const bool fl = (flags & kFlw) != 0;
     auto occb = [&](auto kernel, int blk) { return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kernel, blk, 0); };
-    if (variant == 6) return fl ? occb(bwdt_kernel<256, 8, 64, kFlw | kPer>, 256) : occb(bwdt_kernel<256, 8, 64, kPer>, 256);
-    if (variant == 7) return fl ? occb(bwdt_kernel<256, 16, 64, kFlw | kPer>, 256) : occb(bwdt_kernel<256, 16, 64, kPer>, 256);
-    if (variant == 8) return fl ? occb(bwdt_kernel<512, 16, 64, kFlw | kPer>, 512) : occb(bwdt_kernel<512, 16, 64, kPer>, 512);
+    // the persistent forms the batch launches (flow and colour as given)
+#define FMB_OCC_T(BLK, T)                                                                                  \
+    switch (flags & (kFlw | kCol)) {                                                                       \
+    case 0: return occb(bwdt_kernel<BLK, T, 64, kPer>, BLK);                                              \
+    case kFlw: return occb(bwdt_kernel<BLK, T, 64, kFlw | kPer>, BLK);                                    \
+    case kCol: return occb(bwdt_kernel<BLK, T, 64, kCol | kPer>, BLK);                                    \
+    default: return occb(bwdt_kernel<BLK, T, 64, kCol | kFlw | kPer>, BLK);                               \
+    }
+    if (variant == 6) FMB_OCC_T(256, 8)
+    if (variant == 7) FMB_OCC_T(256, 16)
+    if (variant == 8) FMB_OCC_T(512, 16)
+#undef FMB_OCC_T
     return hipErrorInvalidValue;
 }
 

@@ -627,8 +627,9 @@ VARIANT_CASES = [
 @pytest.mark.parametrize("variant", range(9))
 @pytest.mark.parametrize("label,n,views", VARIANT_CASES, ids=[c[0] for c in VARIANT_CASES])
 def test_backward_variants(fmb, variant, label, n, views):
-    """Every backward variant (Gaussian-lane 0-2, ray-lane 3-5) against the oracle, with normal,
-    flow (both directions) and colour cotangents."""
+    """Every backward variant (Gaussian-lane 0-2, ray-lane 3-5, tiled 6-8, which hand a normal
+    cotangent to variant 2) against the oracle, with normal, flow (both directions) and colour
+    cotangents."""
     sc, cams = custom_scene(n, views, seed=300 + n, flow=True)
     cams = W.with_backward_flow(cams, seed=301)
     g = np.random.Generator(np.random.PCG64(302))
@@ -659,8 +660,8 @@ def test_backward_variants(fmb, variant, label, n, views):
 @pytest.mark.parametrize("variant", range(9))
 @pytest.mark.parametrize("label,n,views", VARIANT_CASES, ids=[c[0] for c in VARIANT_CASES])
 def test_backward_variants_without_normals(fmb, variant, label, n, views):
-    """Every backward variant (Gaussian-lane 0-2, ray-lane 3-5) takes the (A, Bv, L) form of the
-    adjoint without a normal cotangent: against the oracle with depth, alpha, two-way flow and
+    """Every backward variant (Gaussian-lane 0-2, ray-lane 3-5, tiled 6-8) takes the offset form of
+    the adjoint without a normal cotangent: against the oracle with depth, alpha, two-way flow and
     colour cotangents."""
     sc, cams = custom_scene(n, views, seed=310 + n, flow=True)
     cams = W.with_backward_flow(cams, seed=311)
