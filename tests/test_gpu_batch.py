@@ -7,7 +7,8 @@ import pytest
 
 import oracle as O
 import workloads as W
-from tests.gpu_util import assert_forward, assert_grads, compare_forward, compare_grads, fmt, make_scene, to_np
+from tests.gpu_util import (TOL_REL, assert_forward, assert_grads, compare_forward, compare_grads, fmt,
+                            make_scene, normwise, to_np)
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -213,8 +214,8 @@ def test_whole_step_single_graph(fmb, batch16):
 @pytest.mark.parametrize("variant", [3, 5, 6, 7, 8])
 def test_ray_lane_batch_bitwise(fmb, batch16, variant):
     """The ray-lane backward kernels, batched and persistent, equal per-scene plain launches of
-    the same variant bit for bit (items are cut per scene); the tiled variants 6-7 without a
-    normal cotangent (the only case they take)."""
+    the same variant bit for bit (items are cut per scene); the tiled variants 6-8 without a
+    normal cotangent (which they hand to variant 2)."""
     w, b, params = batch16
     fmb.set_launch_config(batch=b, bwd_variant=variant)
     _say(f"[ray-lane] batch16 bwd variant {variant}")
@@ -297,6 +298,57 @@ def test_bench_configuration(fmb, batch16):
         e = compare_grads(gs, gref)
         _say(f"[bench-config] scene {i} backward {fmt(e)}")
         assert_grads(e, f"bench configuration backward, scene {i}")
+
+
+def test_colour_batch_vs_oracle(fmb, batch16):
+    """The benchmark's colour leg through the tiled backward (variant 8, persistent): sigmoid colours
+    on every scene of batch16, the forward colour of sampled rays, and one backward with depth,
+    alpha and colour cotangents on sampled rays of every scene (zero elsewhere; depth and colour
+    only where the oracle's alpha is at least 1e-3), against the oracle's gradient per scene."""
+    w = batch16[0]
+    b, _ = _batch_inputs(w, fmb)  # fresh parameters (other tests update the shared batch's)
+    g = np.random.Generator(np.random.PCG64(94))
+    qs = [(1.5 * g.standard_normal((s.n, 3))).astype(np.float32) for s in w.scenes]
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=DEV).contiguous()  # noqa: E731
+    b.set_colors(t(np.concatenate(qs)))
+    fmb.set_launch_config(batch=b, bwd_variant=8)
+    outs = b.forward(b.alloc_outputs(normals=True, color=True))
+    torch.cuda.synchronize()
+    full = {"depth": np.zeros(b.n_rays, np.float32), "alpha": np.zeros(b.n_rays, np.float32),
+            "color": np.zeros((b.n_rays, 3), np.float32)}
+    per_scene = []
+    for i, (sc, cams) in enumerate(zip(w.scenes, w.cameras)):
+        r0, r1 = b.ray_off[i], b.ray_off[i + 1]
+        rays = np.sort(g.choice(r1 - r0, size=min(1000, r1 - r0), replace=False))
+        ref, _, _ = O.render_workload_view(sc, cams, w.betas, w.eta, rays=rays, colors=qs[i])
+        sub = {k: (None if v is None else v[r0:r1]) for k, v in outs.items()}
+        e = compare_forward(sub, ref, rays)
+        e["color"] = normwise(to_np(outs["color"][r0:r1])[rays], ref["color"])
+        _say(f"[colour-leg] scene {i} forward {fmt(e)}")
+        assert_forward(e, f"colour leg scene {i}")
+        assert e["color"] <= TOL_REL, (i, e["color"])
+        hit = ref["alpha"] >= 1e-3
+        cs = {"depth": (g.standard_normal(rays.size) * hit).astype(np.float32),
+              "alpha": g.standard_normal(rays.size).astype(np.float32),
+              "color": (g.standard_normal((rays.size, 3)) * hit[:, None]).astype(np.float32),
+              "normal": None, "flow": None}
+        for k in full:
+            full[k][r0 + rays] = cs[k]
+        per_scene.append((sc, cams, rays, cs))
+    tc = {k: t(v) for k, v in full.items()}
+    tc["normal"] = tc["flow"] = None
+    grads = b.backward(outs, tc, b.alloc_grads(colors=True))
+    torch.cuda.synchronize()
+    assert fmb.launch_config(batch=b)["bwd_variant"] == 8
+    for i, (sc, cams, rays, cs) in enumerate(per_scene):
+        g0, g1 = b.gauss_off[i], b.gauss_off[i + 1]
+        _, gref, _ = O.render_workload_view(sc, cams, w.betas, w.eta, rays=rays, cot=cs, colors=qs[i])
+        gs = {"means": grads["means"][g0:g1], "prec": grads["prec"][g0:g1], "weights": grads["weights"][g0:g1],
+              "betas": grads["betas"][i]}
+        e = compare_grads(gs, gref)
+        e["colors"] = normwise(to_np(grads["colors"][g0:g1]), gref["colors"])
+        _say(f"[colour-leg] scene {i} backward {fmt(e)}")
+        assert_grads(e, f"colour leg backward, scene {i}")
 
 
 def test_graphs_dropped_when_stale(fmb):
