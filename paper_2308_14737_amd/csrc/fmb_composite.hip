@@ -330,7 +330,7 @@ __device__ __forceinline__ void comp_cull(const float4 *__restrict__ ents, int e
                         0.0f, 0.0f, d2_hi, z_hi);
             keep = !(d2_hi <= thr);  // (a NaN bound keeps the Gaussian)
         }
-        mask[c] = __ballot(keep);
+        mask[c] = wave_ballot(keep);
     }
 }
 
@@ -357,7 +357,7 @@ __device__ __forceinline__ int comp_collect(const Params &P, const SceneRec &sr,
         // the pair's share of the window: tie, slot or (a full list) the end of the window
         auto take = [&](const Ent &g, const Geo &q, int i) {
             const bool sig = q.d2 > sig2;
-            if (!__any(sig)) return;
+            if (!wave_any(sig)) return;
             const float ts = q.t * kDepthScale;
             const float dl = exp2_(q.d2);
             if (sig && ts == w.lo) {
@@ -365,7 +365,7 @@ __device__ __forceinline__ int comp_collect(const Params &P, const SceneRec &sr,
                 on_tie(g, q, dl, i);
             }
             const bool cand = sig && ts > w.lo;
-            if (!__any(cand)) return;
+            if (!wave_any(cand)) return;
             if (ns < kCompSlots) {
                 slot_set(L, ns, ts, cand ? dl : 0.0f);
                 if (threadIdx.x == 0) slot_g[ns] = gb + i;
@@ -387,11 +387,11 @@ __device__ __forceinline__ int comp_collect(const Params &P, const SceneRec &sr,
                 Geo qa, qb;
                 const float vca = pair_geo_peak(ga, v0, v1, v2, qa), vcb = pair_geo_peak(gb2, v0, v1, v2, qb);
                 // the residual only where the density bound allows a significant pair
-                if (__any(comp_d2_hi(ga, ents[EW * ia + kCompEst], vca, qa.t, hm) > sig2)) {
+                if (wave_any(comp_d2_hi(ga, ents[EW * ia + kCompEst], vca, qa.t, hm) > sig2)) {
                     pair_geo_resid(ga, v0, v1, v2, hm, 0.0f, 0.0f, qa);
                     take(ga, qa, ia);
                 }
-                if (two && __any(comp_d2_hi(gb2, ents[EW * ib + kCompEst], vcb, qb.t, hm) > sig2)) {
+                if (two && wave_any(comp_d2_hi(gb2, ents[EW * ib + kCompEst], vcb, qb.t, hm) > sig2)) {
                     pair_geo_resid(gb2, v0, v1, v2, hm, 0.0f, 0.0f, qb);
                     take(gb2, qb, ib);
                 }
@@ -511,7 +511,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kFwdcWaves))
         float own = 0.0f;
 #pragma unroll
         for (int k = 0; k < kCompSlots; ++k) own += slot_d(L, k);
-        if (resident && ns > 0 && !__any(w.hi != INFINITY) && __all(!valid || own > 0.0f)) {
+        if (resident && ns > 0 && !wave_any(w.hi != INFINITY) && wave_all(!valid || own > 0.0f)) {
             for (int s = 0; s < ns; s += 2) {  // two slots a step (two independent chains)
                 const bool two = s + 1 < ns;
                 const int ia = slot_g[s], ib = two ? slot_g[s + 1] : ia;
@@ -522,7 +522,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kFwdcWaves))
                 if (valid && qa.d2 > sig2) blend(ga, qa, comp_front(L, ns, w, qa.t * kDepthScale), ia);
                 if (two && valid && qb.d2 > sig2) blend(gb, qb, comp_front(L, ns, w, qb.t * kDepthScale), ib);
             }
-            done = __all(!valid || M >= kCompHitLog2);
+            done = wave_all(!valid || M >= kCompHitLog2);
             if (!done) reset();
         }
         // Otherwise every pair of every window (a tile that sees background or several windows).
@@ -541,20 +541,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kFwdcWaves))
                     // the density bound rules most pairs out before the residual
                     const float tsa = qa.t * kDepthScale, tsb = qb.t * kDepthScale;
                     const bool ina = tsa >= w.lo && tsa < w.hi, inb = two && tsb >= w.lo && tsb < w.hi;
-                    if (__any(ina && comp_d2_hi(ga, ents[EW * i + kCompEst], vca, qa.t, hm) - M >= skip2)) {
+                    if (wave_any(ina && comp_d2_hi(ga, ents[EW * i + kCompEst], vca, qa.t, hm) - M >= skip2)) {
                         pair_geo_resid(ga, v0, v1, v2, hm, 0.0f, 0.0f, qa);
                         const bool la = ina && qa.d2 - M >= skip2;
-                        if (__any(la) && la) blend(ga, qa, comp_front(L, ns, w, tsa), i);
+                        if (wave_any(la) && la) blend(ga, qa, comp_front(L, ns, w, tsa), i);
                     }
-                    if (__any(inb && comp_d2_hi(gb, ents[EW * ib + kCompEst], vcb, qb.t, hm) - M >= skip2)) {
+                    if (wave_any(inb && comp_d2_hi(gb, ents[EW * ib + kCompEst], vcb, qb.t, hm) - M >= skip2)) {
                         pair_geo_resid(gb, v0, v1, v2, hm, 0.0f, 0.0f, qb);
                         const bool lb = inb && qb.d2 - M >= skip2;
-                        if (__any(lb) && lb) blend(gb, qb, comp_front(L, ns, w, tsb), ib);
+                        if (wave_any(lb) && lb) blend(gb, qb, comp_front(L, ns, w, tsb), ib);
                     }
                 }
             }
             const bool more = comp_next(w, L, ns);
-            if (!__any(more)) break;
+            if (!wave_any(more)) break;
             ns = comp_collect<EW>(P, sr, o, ents, resident, v0, v1, v2, hm, sig2, tc, w, L, slot_g, no_tie);
         }
         if (valid)
@@ -659,7 +659,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
                 const float ts = q.t * kDepthScale;
                 const bool own = q.d2 > sig2 && ts > w.lo && ts < w.hi;
                 float z = 0.0f;
-                if (__any(own) && own) {
+                if (wave_any(own) && own) {
                     const float lw = fmaf(-(float)kLog2e, comp_front(L, ns, w, ts), log2_opacity(exp2_(q.d2), q.d2));
                     const float wt = exp2_(lw - M2) * invS;
                     float lin = tfb * q.t;
@@ -718,13 +718,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
         // intersections of each ray, so that a window knows the z_bar of the windows behind it.
         int ns = comp_collect<EW>(P, sr, o, ents, resident, v0, v1, v2, hm, sig2, tc, w, L, slot_g, on_tie);
         float zall = 0.0f;
-        if (__any(w.hi != INFINITY)) {
+        if (wave_any(w.hi != INFINITY)) {
             bool more = true;
             for (;;) {
                 slots_z(ns);
                 zall += window_z(ns);
                 more = comp_next(w, L, ns);
-                if (!__any(more)) break;
+                if (!wave_any(more)) break;
                 ztie = 0.0f;
                 ns = comp_collect<EW>(P, sr, o, ents, resident, v0, v1, v2, hm, sig2, tc, w, L, slot_g, on_tie);
             }
@@ -735,7 +735,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
 
         // A tile of one window whose rays all weigh at least 2^kCompHitLog2 somewhere (the forward's
         // test, on its stashed maximum) takes only the slots' Gaussians, each ray its own pairs.
-        const bool hit_tile = resident && ns > 0 && !__any(w.hi != INFINITY) && __all(!valid || M2 >= kCompHitLog2);
+        const bool hit_tile = resident && ns > 0 && !wave_any(w.hi != INFINITY) && wave_all(!valid || M2 >= kCompHitLog2);
 
         // Adjoint terms of this lane's pair (g, q) of Gaussian staged at index i (live: the lane
         // has the pair), summed over the wave and added to the Gaussian's sums rec[LREC r ...].
@@ -836,18 +836,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
                         const float tsa = qa.t * kDepthScale, tsb = qb.t * kDepthScale;
                         const float lim = fminf(skip2, wskip);
                         const bool ina = tsa >= w.lo && tsa < w.hi, inb = two && tsb >= w.lo && tsb < w.hi;
-                        if (__any(ina && comp_d2_hi(ga, ents[EW * i + kCompEst], vca, qa.t, hm) >= lim)) {
+                        if (wave_any(ina && comp_d2_hi(ga, ents[EW * i + kCompEst], vca, qa.t, hm) >= lim)) {
                             pair_geo_resid(ga, v0, v1, v2, hm, 0.0f, 0.0f, qa);
                             const bool la = ina && qa.d2 >= lim;
-                            if (__any(la)) {
+                            if (wave_any(la)) {
                                 pair_terms(ga, qa, tsa, la, i, i, zafter);
                                 if (!resident && lane == 0) touched[i] = 1;
                             }
                         }
-                        if (__any(inb && comp_d2_hi(gb, ents[EW * ib + kCompEst], vcb, qb.t, hm) >= lim)) {
+                        if (wave_any(inb && comp_d2_hi(gb, ents[EW * ib + kCompEst], vcb, qb.t, hm) >= lim)) {
                             pair_geo_resid(gb, v0, v1, v2, hm, 0.0f, 0.0f, qb);
                             const bool lb = inb && qb.d2 >= lim;
-                            if (__any(lb)) {
+                            if (wave_any(lb)) {
                                 pair_terms(gb, qb, tsb, lb, ib, ib, zafter);
                                 if (!resident && lane == 0) touched[ib] = 1;
                             }
@@ -872,7 +872,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
                 }
             }
             const bool more = comp_next(w, L, ns);
-            if (!__any(more)) break;
+            if (!wave_any(more)) break;
             ztie = 0.0f;
             ns = comp_collect<EW>(P, sr, o, ents, resident, v0, v1, v2, hm, sig2, tc, w, L, slot_g, on_tie);
         }
@@ -949,7 +949,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kFwdcWaves))
             const int ns = comp_collect<EW>(P, sr, o, ents, resident, v0, v1, v2, hm, sig2, tc, w, L, slot_g, no_tie);
             // as in the forward: a tile of one window whose rays all weigh at least 2^kCompHitLog2
             // somewhere takes only the slots' Gaussians
-            if (first && resident && ns > 0 && !__any(w.hi != INFINITY) && __all(!valid || M2 >= kCompHitLog2)) {
+            if (first && resident && ns > 0 && !wave_any(w.hi != INFINITY) && wave_all(!valid || M2 >= kCompHitLog2)) {
                 for (int s = 0; s < ns; ++s) {
                     const int gi = slot_g[s];
                     const Ent g = comp_ent<EW>(ents, gi);
@@ -980,7 +980,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kFwdcWaves))
                     pair_geo_coarse(g, v0, v1, v2, hm, 0.0f, 0.0f, q);
                     const float ts = q.t * kDepthScale;
                     const bool live = ts >= w.lo && ts < w.hi && q.d2 >= wskip;
-                    if (!__any(live)) continue;
+                    if (!wave_any(live)) continue;
                     float x = 0.0f;
                     if (live) {
                         const float lw = fmaf(-(float)kLog2e, comp_front(L, ns, w, ts), log2_opacity(exp2_(q.d2), q.d2));
@@ -997,7 +997,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kFwdcWaves))
                 }
             }
             const bool more = comp_next(w, L, ns);
-            if (!__any(more)) break;
+            if (!wave_any(more)) break;
         }
     }
     if (resident) {

@@ -50,6 +50,13 @@ __device__ __forceinline__ T ld_uniform(const T *p)
     return v;
 }
 
+// Wave votes over the active lanes.  The predicate goes to the ballot as the lane mask its
+// comparison already produces; the int-predicate forms widen it to a 0/1 integer per lane and
+// compare that again (two extra vector instructions per vote).
+__device__ __forceinline__ unsigned long long wave_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+__device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
+__device__ __forceinline__ bool wave_all(bool p) { return __builtin_amdgcn_ballot_w64(!p) == 0; }
+
 struct CamRec {  // world-to-camera [R | T] row-major, then (fx, fy, cx, cy)
     float e[12];
     float k[4];

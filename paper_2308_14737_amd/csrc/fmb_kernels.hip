@@ -146,7 +146,7 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
                     const bool first = !(b1_pos && d2h < kDensSkipLog2);
                     need = sweep == 0 ? first : (!first && !(zh - mmin < kSkipLog2));
                 }
-                const unsigned long long nm = __ballot(need);
+                const unsigned long long nm = wave_ballot(need);
                 if (nm == 0ull) continue;
                 const int kn = min(GP, cnt - ib);
 #pragma unroll 2
@@ -535,7 +535,7 @@ __global__ __launch_bounds__(BLOCK) void bwdr_kernel(Params P, BwdIn I, const Bw
                     PairAcc a;
                     OffsetAcc pa;
                     float aC0 = 0.0f, aC1 = 0.0f, aC2 = 0.0f;
-                    if (__any(need_w)) {
+                    if (wave_any(need_w)) {
 #pragma unroll
                         for (int j = 0; j < RPT; ++j) {
                             const float tfb = x1[j].y;
@@ -560,7 +560,7 @@ __global__ __launch_bounds__(BLOCK) void bwdr_kernel(Params P, BwdIn I, const Bw
                                                       x1[j].w, x2[j].x, tb, db, a);
                             }
                         }
-                    } else if (__any(need_d)) {
+                    } else if (wave_any(need_d)) {
                         // zero weight on every ray of the wave: only d(alpha)/d(delta) remains
 #pragma unroll
                         for (int j = 0; j < RPT; ++j) {
@@ -657,6 +657,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
     __shared__ float4 rays[RW * RAYS];
     __shared__ float4 tcone[T];               // per ray tile: unit centre direction, largest |v - c|
     __shared__ float tnorm[T];                // per ray tile: least M2 + log2 S over its rays
+    __shared__ int tdb[T];                    // per ray tile: 1 if some ray has D_bar != 0, else 0
     __shared__ float4 ents[EW * TG];          // the Gaussian tile's entries (m estimate terms, colour)
     __shared__ float rec[LREC * TG];          // (H, Bv, L) [and the colour sums] of each Gaussian
     __shared__ float bsum[2 * NW];
@@ -713,6 +714,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
             int row, col;
             const bool ok = tile_local(vr, item.ray0 + tt, lane, row, col) >= 0;
             const float4 x0 = rays[RW * (64 * tt + lane)];
+            const int db_flag = wave_any(rays[RW * (64 * tt + lane) + 1].y != 0.0f) ? 1 : 0;
             float c0 = wave_sum(ok ? x0.x : 0.0f), c1 = wave_sum(ok ? x0.y : 0.0f), c2 = wave_sum(ok ? x0.z : 0.0f);
             const float inv = rsq_(fmaf(c0, c0, fmaf(c1, c1, fmaf(c2, c2, kEpsN))));
             c0 *= inv;
@@ -729,9 +731,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
             if (lane == 0) {
                 tcone[tt] = make_float4(c0, c1, c2, rho * (1.0f + 1e-4f) + 1e-6f);
                 tnorm[tt] = nmin;
+                tdb[tt] = db_flag;
             }
         }
         float aB1 = 0.0f, aB2 = 0.0f;
+        unsigned db_any = 0;  // bit t: some ray of tile t has a density cotangent
         for (int gb = 0; gb < sr.n; gb += TG) {
             const int cnt = min(TG, sr.n - gb);
             __syncthreads();  // staged rays visible; the previous tile's entries and sums are consumed
@@ -741,6 +745,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
                 if (COLOR) ents[EW * q + 5] = colour_entry(P.colors + 3 * gi);
             }
             __syncthreads();
+            if (gb == 0) db_any = (unsigned)wave_ballot(lane < nt && tdb[lane] != 0);
             for (int i = wave; i < cnt; i += NW) {
                 const Ent g = ent_from(ents[EW * i], ents[EW * i + 1], ents[EW * i + 2], ents[EW * i + 3]);
                 const float4 est = ents[EW * i + 4];
@@ -756,7 +761,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
                         // (written so that a NaN bound keeps the tile)
                         need = !(b1_pos && z_hi - tnorm[lane] < kSkipLog2 && d2_hi < kDensSkipLog2);
                     }
-                    tmask = (unsigned)__ballot(need);
+                    tmask = (unsigned)wave_ballot(need);
                 }
                 OffsetAcc acc;
                 float aC0 = 0.0f, aC1 = 0.0f, aC2 = 0.0f;  // colour sums: wt C_bar
@@ -771,18 +776,20 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
                         // upper bounds of the log2 density and of the log2 weight from a lower bound
                         // of m (one FMA): a tile they put below both cutoffs everywhere is one the exact
                         // test below would skip, and it skips the residual as well
+                        // (each vote on a single comparison; the tile's density-cotangent flag
+                        // loosens the second to rays without one, which the exact test excludes)
                         const float d2_hi = fmaf(bl.hm, pair_m_low(est, vc, q.t), g.l2l);
-                        const float zr_hi = b1_pos ? fmaf(bl.b1, d2_hi, fmaf(bl.nc2, q.t, -x0.w)) : INFINITY;
-                        if (!__any(zr_hi >= kSkipLog2) && !__any(d2_hi >= kDensSkipLog2 && x1.y != 0.0f)) continue;
+                        const bool w_hi = !b1_pos || wave_any(fmaf(bl.b1, d2_hi, fmaf(bl.nc2, q.t, -x0.w)) >= kSkipLog2);
+                        if (!w_hi && !(((db_any >> t) & 1u) && wave_any(d2_hi >= kDensSkipLog2))) continue;
                     }
                     pair_geo_resid(g, x0.x, x0.y, x0.z, bl.hm, bl.b1, bl.nc2, q);
                     // log2 of the normalised weight, and the density term D_bar delta
                     const float zr = fmaf(bl.b1, q.d2, fmaf(bl.nc2, q.t, -x0.w));
                     // a weight below 2^-150 rounds to zero in FP32, and a density below 2^kDensSkipLog2
                     // adds nothing measurable: such a tile skips the exponential and the adjoint
-                    const bool any_w = __any(zr >= kSkipLog2);
-                    const bool any_d = __any(q.d2 >= kDensSkipLog2 && x1.y != 0.0f);
-                    if (any_w || any_d) {
+                    // (the density test only where no weight is left)
+                    const bool any_w = wave_any(zr >= kSkipLog2);
+                    if (any_w || wave_any(q.d2 >= kDensSkipLog2 && x1.y != 0.0f)) {
                         const float dd = x1.y * exp2_(q.d2);
                         // with zero weights on every ray of the tile only the density term remains:
                         // t_bar = 0, d_bar = D_bar delta (the offset form then adds exactly that)
