@@ -221,33 +221,29 @@ __device__ __forceinline__ float comp_behind(const CompList &L, const CompZ &z, 
 
 // z_bar of the slots' pairs without a normal or colour cotangent, from the slots alone: the pair's
 // weight 2^(lw - M2) / S with lw = -log2(e) F + log2(1 - exp(-delta)) at the slot's depth and
-// density, times (tf_bar t - kappa); 0 where the slot is empty for the lane.
-template <int K>
-struct SlotZ {
-    __device__ static __forceinline__ void run(const CompList &L, CompZ &zs, int ns, const CompWin &w, float M2,
-                                               float invS, float tfb, float kap)
-    {
-        if (K >= ns) return;
-#pragma unroll
-        for (int k = K; k < K + kSlotGroup; ++k) {
-            const float dl = slot_d(L, k), ts = slot_t(L, k);
-            float z = 0.0f;
-            if (dl > 0.0f) {
-                const float lw = fmaf(-(float)kLog2e, comp_front(L, ns, w, ts), log2_opacity(dl, __builtin_amdgcn_logf(dl)));
-                z = exp2_(lw - M2) * invS * fmaf(tfb, ts * (1.0f / kDepthScale), -kap);
-            }
-            slot_set_z(zs, k, z);
-        }
-        SlotZ<K + kSlotGroup>::run(L, zs, ns, w, M2, invS, tfb, kap);
-    }
-};
-template <>
-struct SlotZ<kCompSlots> {
-    __device__ static __forceinline__ void run(const CompList &, CompZ &, int, const CompWin &, float, float, float,
-                                               float)
-    {
-    }
-};
+// density, times (tf_bar t - kappa); 0 where the slot is empty for the lane.  A loop over the slots
+// in use (each read and written by an indirect register move at the uniform index k) rather than
+// one unrolled over every slot: the unrolled form, a front sum per slot, was 70 KB of the adjoint
+// kernel's 118 KB of code (same speed on the benchmark scenes).
+__device__ __forceinline__ float slot_z_plain(const CompList &L, int ns, const CompWin &w, float M2, float invS,
+                                              float tfb, float kap, float dl, float ts)
+{
+    if (!(dl > 0.0f)) return 0.0f;
+    const float lw = fmaf(-(float)kLog2e, comp_front(L, ns, w, ts), log2_opacity(dl, __builtin_amdgcn_logf(dl)));
+    return exp2_(lw - M2) * invS * fmaf(tfb, ts * (1.0f / kDepthScale), -kap);
+}
+
+__device__ __forceinline__ void slots_z_plain(const CompList &L, CompZ &zs, int ns, const CompWin &w, float M2,
+                                              float invS, float tfb, float kap)
+{
+    // (one loop per register vector, so that each writes a single vector in place)
+#pragma unroll 1
+    for (int k = 0; k < min(ns, 32); ++k)
+        zs.z0[k] = slot_z_plain(L, ns, w, M2, invS, tfb, kap, L.d0[k], L.t0[k]);
+#pragma unroll 1
+    for (int k = 32; k < ns; ++k)
+        zs.z1[k - 32] = slot_z_plain(L, ns, w, M2, invS, tfb, kap, L.d1[k - 32], L.t1[k - 32]);
+}
 
 // Entries of Gaussians [gb, gb + cnt) of the scene into LDS, EW float4 each: the entry, the terms
 // of the m estimate (make_entry_est) and, with EW = 6, the colour.
@@ -641,7 +637,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
             zs.z1 = (CompV16)(0.0f);
             if (PLAIN) {
                 // z_bar = wt (tf_bar t - kappa) needs only the slot's depth and density
-                SlotZ<0>::run(L, zs, ns, w, M2, invS, tfb, kap);
+                slots_z_plain(L, zs, ns, w, M2, invS, tfb, kap);
                 return;
             }
             if (!resident) {
