@@ -225,12 +225,13 @@ __device__ __forceinline__ float comp_behind(const CompList &L, const CompZ &z, 
 // in use (each read and written by an indirect register move at the uniform index k) rather than
 // one unrolled over every slot: the unrolled form, a front sum per slot, was 70 KB of the adjoint
 // kernel's 118 KB of code (same speed on the benchmark scenes).
+__device__ __forceinline__ float slot_zf(float f, float dl, float ts, float M2, float invS, float tfb, float kap);
+
 __device__ __forceinline__ float slot_z_plain(const CompList &L, int ns, const CompWin &w, float M2, float invS,
                                               float tfb, float kap, float dl, float ts)
 {
     if (!(dl > 0.0f)) return 0.0f;
-    const float lw = fmaf(-(float)kLog2e, comp_front(L, ns, w, ts), log2_opacity(dl, __builtin_amdgcn_logf(dl)));
-    return exp2_(lw - M2) * invS * fmaf(tfb, ts * (1.0f / kDepthScale), -kap);
+    return slot_zf(comp_front(L, ns, w, ts), dl, ts, M2, invS, tfb, kap);
 }
 
 __device__ __forceinline__ void slots_z_plain(const CompList &L, CompZ &zs, int ns, const CompWin &w, float M2,
@@ -243,6 +244,34 @@ __device__ __forceinline__ void slots_z_plain(const CompList &L, CompZ &zs, int 
 #pragma unroll 1
     for (int k = 32; k < ns; ++k)
         zs.z1[k - 32] = slot_z_plain(L, ns, w, M2, invS, tfb, kap, L.d1[k - 32], L.t1[k - 32]);
+}
+
+// z_bar of a slot's pair from its front sum F, density and depth (0 where the slot is empty).
+__device__ __forceinline__ float slot_zf(float f, float dl, float ts, float M2, float invS, float tfb, float kap)
+{
+    if (!(dl > 0.0f)) return 0.0f;
+    const float lw = fmaf(-(float)kLog2e, f, log2_opacity(dl, __builtin_amdgcn_logf(dl)));
+    return exp2_(lw - M2) * invS * fmaf(tfb, ts * (1.0f / kDepthScale), -kap);
+}
+
+// The same z_bar for a tile of one window whose pairs are all slots' (no normal or colour
+// cotangent): first every slot's front sum F into zs, then every slot's z_bar into its density
+// register.  The adjoint of such a tile then takes a pair's front sum from zs and the sums of z_bar
+// behind it from the density registers: the slots' densities are needed only for the front sums,
+// and a second front sum per pair is saved.  The values are those slots_z_plain and comp_front
+// form, bit for bit.
+__device__ __forceinline__ void slots_fz_plain(CompList &L, CompZ &zs, int ns, const CompWin &w, float M2,
+                                               float invS, float tfb, float kap)
+{
+#pragma unroll 1
+    for (int k = 0; k < min(ns, 32); ++k) zs.z0[k] = comp_front(L, ns, w, L.t0[k]);
+#pragma unroll 1
+    for (int k = 32; k < ns; ++k) zs.z1[k - 32] = comp_front(L, ns, w, L.t1[k - 32]);
+#pragma unroll 1
+    for (int k = 0; k < min(ns, 32); ++k) L.d0[k] = slot_zf(zs.z0[k], L.d0[k], L.t0[k], M2, invS, tfb, kap);
+#pragma unroll 1
+    for (int k = 32; k < ns; ++k)
+        L.d1[k - 32] = slot_zf(zs.z1[k - 32], L.d1[k - 32], L.t1[k - 32], M2, invS, tfb, kap);
 }
 
 // Entries of Gaussians [gb, gb + cnt) of the scene into LDS, EW float4 each: the entry, the terms
@@ -635,8 +664,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
         auto slots_z = [&](int ns) {
             zs.z0 = (CompV32)(0.0f);
             zs.z1 = (CompV16)(0.0f);
-            if (PLAIN) {
-                // z_bar = wt (tf_bar t - kappa) needs only the slot's depth and density
+            if (PLAIN && !COLOR) {
+                // z_bar = wt (tf_bar t - kappa) needs only the slot's depth and density (a colour
+                // cotangent adds C_bar . c of the slot's Gaussian: the general form below)
                 slots_z_plain(L, zs, ns, w, M2, invS, tfb, kap);
                 return;
             }
@@ -735,13 +765,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
 
         // Adjoint terms of this lane's pair (g, q) of Gaussian staged at index i (live: the lane
         // has the pair), summed over the wave and added to the Gaussian's sums rec[LREC r ...].
-        auto pair_terms = [&](const Ent &g, Geo &q, float ts, bool live, int i, int r, float zafter) {
+        // With from_slots (a tile of slots_fz_plain) the pair's front sum is fs and z_bar of the
+        // slots is in the density registers.
+        auto pair_terms = [&](const Ent &g, Geo &q, float ts, bool live, int i, int r, float zafter, bool from_slots,
+                              float fs) {
             PairAcc acc;
             OffsetAcc oacc;
             float aC0 = 0.0f, aC1 = 0.0f, aC2 = 0.0f;
             if (live) {
                 const float delta = exp2_(q.d2);
-                const float lw = fmaf(-(float)kLog2e, comp_front(L, ns, w, ts), log2_opacity(delta, q.d2));
+                const float lw = fmaf(-(float)kLog2e, from_slots ? fs : comp_front(L, ns, w, ts), log2_opacity(delta, q.d2));
                 const float wt = exp2_(lw - M2) * invS;
                 PairNormal pn{0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
                 if (NORMALS) {
@@ -757,7 +790,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
                     aC2 = wt * cb2;
                 }
                 const float zb = wt * (lin - kap);
-                const float bsum = zafter + comp_behind(L, zs, ns, ts);
+                const float bsum = zafter + (from_slots ? comp_behind(L, CompZ{L.d0, L.d1}, ns, ts)
+                                                        : comp_behind(L, zs, ns, ts));
                 const float db = fmaf(zb, opacity_slope(delta), delta * (Db - bsum));
                 const float tb = wt * tfb;
                 if (PLAIN)
@@ -787,8 +821,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
 
         float zthrough = 0.0f;
         for (;;) {
-            slots_z(ns);
-            zthrough += window_z(ns);
+            // (a tile of one window whose pairs are all slots': the slots keep F and z_bar)
+            const bool fz = PLAIN && !COLOR && hit_tile;
+            if (fz) {
+                slots_fz_plain(L, zs, ns, w, M2, invS, tfb, kap);
+            } else {
+                slots_z(ns);
+                zthrough += window_z(ns);
+            }
             // z_bar of the significant intersections behind this window
             const float zafter = w.hi == INFINITY ? 0.0f : zall - zthrough;
 
@@ -800,8 +840,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
                     Geo qa, qb;
                     pair_geo_coarse(ga, v0, v1, v2, hm, 0.0f, 0.0f, qa);
                     pair_geo_coarse(gb, v0, v1, v2, hm, 0.0f, 0.0f, qb);
-                    pair_terms(ga, qa, qa.t * kDepthScale, valid && qa.d2 > sig2, ia, ia, zafter);
-                    if (two) pair_terms(gb, qb, qb.t * kDepthScale, valid && qb.d2 > sig2, ib, ib, zafter);
+                    // the pair of slot s is the slot's own (its front sum is F of the slot)
+                    const float fa = fz ? slot_z(zs, s) : 0.0f, fb = fz && two ? slot_z(zs, s + 1) : 0.0f;
+                    pair_terms(ga, qa, qa.t * kDepthScale, valid && qa.d2 > sig2, ia, ia, zafter, fz, fa);
+                    if (two) pair_terms(gb, qb, qb.t * kDepthScale, valid && qb.d2 > sig2, ib, ib, zafter, fz, fb);
                 }
             } else {
                 for (int gb = 0; gb < n; gb += kCompTG) {
@@ -836,7 +878,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
                             pair_geo_resid(ga, v0, v1, v2, hm, 0.0f, 0.0f, qa);
                             const bool la = ina && qa.d2 >= lim;
                             if (wave_any(la)) {
-                                pair_terms(ga, qa, tsa, la, i, i, zafter);
+                                pair_terms(ga, qa, tsa, la, i, i, zafter, false, 0.0f);
                                 if (!resident && lane == 0) touched[i] = 1;
                             }
                         }
@@ -844,7 +886,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
                             pair_geo_resid(gb, v0, v1, v2, hm, 0.0f, 0.0f, qb);
                             const bool lb = inb && qb.d2 >= lim;
                             if (wave_any(lb)) {
-                                pair_terms(gb, qb, tsb, lb, ib, ib, zafter);
+                                pair_terms(gb, qb, tsb, lb, ib, ib, zafter, false, 0.0f);
                                 if (!resident && lane == 0) touched[ib] = 1;
                             }
                         }

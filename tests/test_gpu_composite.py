@@ -93,6 +93,32 @@ def test_composite_parity_without_normals(fmb, label, n, views):
     assert_grads(eg, label)
 
 
+@pytest.mark.parametrize("label,n,views", [CASES[1], CASES[2], CASES[4]], ids=[CASES[i][0] for i in (1, 2, 4)])
+def test_composite_colour_without_normals(fmb, label, n, views):
+    """A colour cotangent without a normal cotangent: the slots' z_bar takes the colour term of
+    their Gaussians (C_bar . c), with depth, alpha and two-way flow cotangents, against the oracle."""
+    sc, cams = custom_scene(n, views, seed=140 + n, flow=True)
+    cams = W.with_backward_flow(cams, seed=141)
+    g = np.random.Generator(np.random.PCG64(142))
+    q = (1.5 * g.standard_normal((sc.n, 3))).astype(np.float32)
+    _say(f"[composite-colour-plain] {label}: N={n} views={views}")
+    scene, _ = _composite_scene(fmb, sc, cams)
+    scene.set_colors(_t(q))
+    outs = scene.render(normals=False)
+    ref, _, _ = O.render_workload_view(sc, cams, BETAS, 1.0, colors=q, model="composite")
+    hit = ref["alpha"] >= 1e-3
+    cot = hit_mask_cot(W.random_cotangents(cams.n_rays, 143, flow=False, normals=False), ref["alpha"])
+    cot["flow"] = (g.standard_normal((cams.n_rays, 4)) * hit[:, None]).astype(np.float32)
+    cot["color"] = (g.standard_normal((cams.n_rays, 3)) * hit[:, None]).astype(np.float32)
+    gr = scene.backward(outs, _t(cot["depth"]), _t(cot["alpha"]), None, _t(cot["flow"]), g_color=_t(cot["color"]))
+    torch.cuda.synchronize()
+    _, gref, _ = O.render_workload_view(sc, cams, BETAS, 1.0, cot=cot, colors=q, model="composite")
+    eg = compare_grads(gr, gref)
+    eg["colors"] = normwise(to_np(gr["colors"]), gref["colors"])
+    _say(f"[composite-colour-plain] {label}: {eg}")
+    assert_grads(eg, label)
+
+
 def test_composite_ties_and_behind(fmb):
     """Copies of the same Gaussian (equal t on every ray: no mutual attenuation) and Gaussians
     behind the front camera."""
