@@ -93,7 +93,8 @@ def test_composite_parity_without_normals(fmb, label, n, views):
     assert_grads(eg, label)
 
 
-@pytest.mark.parametrize("label,n,views", [CASES[1], CASES[2], CASES[4]], ids=[CASES[i][0] for i in (1, 2, 4)])
+@pytest.mark.parametrize("label,n,views", [CASES[1], CASES[2], CASES[4], CASES[5]],
+                         ids=[CASES[i][0] for i in (1, 2, 4, 5)])
 def test_composite_colour_without_normals(fmb, label, n, views):
     """A colour cotangent without a normal cotangent: the slots' z_bar takes the colour term of
     their Gaussians (C_bar . c), with depth, alpha and two-way flow cotangents, against the oracle."""
@@ -305,6 +306,34 @@ def test_composite_depth_windows(fmb, label, n, views, spread):
     eg2 = compare_grads(g2, gref2)
     _say(f"[composite-windows] {label} plain: {eg2}")
     assert_grads(eg2, label + " plain")
+
+
+def test_composite_colour_windows_without_normals(fmb):
+    """Colour and depth/alpha cotangents without a normal cotangent on a clustered scene staged
+    through LDS whose central tiles take several depth windows, against the oracle."""
+    label, n, views, spread = WINDOWS[1]
+    sc, cams = _cluster_scene(n, views, seed=n + 7, spread=spread)
+    g = np.random.Generator(np.random.PCG64(144))
+    q = (1.5 * g.standard_normal((sc.n, 3))).astype(np.float32)
+    _say(f"[composite-colour-windows] {label}: N={n} views={views}")
+    scene, _ = _composite_scene(fmb, sc, cams)
+    scene.set_colors(_t(q))
+    outs = scene.render(normals=False)
+    ref, _, _ = O.render_workload_view(sc, cams, BETAS, 1.0, colors=q, model="composite")
+    hit = ref["alpha"] >= 1e-3
+    cot = hit_mask_cot(W.random_cotangents(cams.n_rays, 145, flow=False, normals=False), ref["alpha"])
+    cot["color"] = (g.standard_normal((cams.n_rays, 3)) * hit[:, None]).astype(np.float32)
+    gr = scene.backward(outs, _t(cot["depth"]), _t(cot["alpha"]), None, None, g_color=_t(cot["color"]))
+    torch.cuda.synchronize()
+    _, gref, _ = O.render_workload_view(sc, cams, BETAS, 1.0, cot=cot, colors=q, model="composite")
+    e = compare_forward(outs, ref)
+    e["color"] = normwise(to_np(outs["color"]), ref["color"])
+    eg = compare_grads(gr, gref)
+    eg["colors"] = normwise(to_np(gr["colors"]), gref["colors"])
+    _say(f"[composite-colour-windows] {label}: {e} {eg}")
+    assert_forward(e, label)
+    assert e["color"] <= TOL_REL
+    assert_grads(eg, label)
 
 
 def _hit_sample(alpha, k, seed):
