@@ -445,9 +445,13 @@ def test_loss_grad_kernel(fmb, norm):
     assert abs(float(bl.double().sum()) - L) <= 1e-5 * abs(L)
 
 
-def test_explicit_ray_minibatch(fmb):
+@pytest.mark.parametrize("model,normals", [("blend", True), ("blend", False), ("composite", True),
+                                           ("composite", False)])
+def test_explicit_ray_minibatch(fmb, model, normals):
     """A random minibatch of rays across all views (uneven counts, one empty view, sub-pixel
-    directions) through fmb_set_rays, against the oracle on the same float32 directions."""
+    directions) through fmb_set_rays, against the oracle on the same float32 directions; both
+    models, with a normal cotangent and without one (the blend model's tiled backward then takes
+    tiles of 64 consecutive rays of the minibatch)."""
     w = W.make_config("flow480")
     sc, cams = w.scenes[0], w.cameras[0]
     g = np.random.Generator(np.random.PCG64(77))
@@ -461,21 +465,24 @@ def test_explicit_ray_minibatch(fmb):
     dc = np.stack([(px[:, 0] - k[:, 2]) / k[:, 0], (px[:, 1] - k[:, 3]) / k[:, 1], np.ones(p)], axis=1)
     rot = cams.w2c[views, :, :3].astype(np.float64)
     dirs = (np.einsum("pji,pj->pi", rot, dc) * g.uniform(0.5, 2.0, (p, 1))).astype(np.float32)
-    _say(f"[minibatch] flow480 views counts={counts.tolist()} P={p}")
+    _say(f"[minibatch] flow480 {model} normals={normals} views counts={counts.tolist()} P={p}")
     t = lambda a: torch.as_tensor(a, device=DEV).contiguous()  # noqa: E731
     params = (t(sc.means), t(sc.prec), t(sc.weights), t(w.betas))
     c = fmb.Cameras.from_numpy(cams.w2c, cams.intr, cams.hw, cams.w2c_b, cams.intr_b, device=DEV)
     scene = fmb.Scene(*params, w.eta)
     td = t(dirs)
     scene.set_rays(c, counts, td)
+    if model == "composite":
+        scene.set_model("composite")
     assert scene.n_rays == p
     outs = scene.render(normals=True)
     o, v = O.dir_rays(views, dirs, cams.w2c)
     osc = O.OracleScene.of(sc.means, sc.prec, sc.weights, w.betas, w.eta)
-    kw = dict(view=views, w2c_a=cams.w2c, intr_a=cams.intr, w2c_b=cams.w2c_b, intr_b=cams.intr_b)
+    kw = dict(view=views, w2c_a=cams.w2c, intr_a=cams.intr, w2c_b=cams.w2c_b, intr_b=cams.intr_b, model=model)
     ref = O.render(osc, o, v, **kw)
-    cot = hit_mask_cot(W.random_cotangents(p, 12, flow=True), ref["alpha"])
-    gr = scene.backward(outs, t(cot["depth"]), t(cot["alpha"]), t(cot["normal"]), t(cot["flow"]))
+    cot = hit_mask_cot(W.random_cotangents(p, 12, flow=True, normals=normals), ref["alpha"])
+    gn = t(cot["normal"]) if normals else None
+    gr = scene.backward(outs, t(cot["depth"]), t(cot["alpha"]), gn, t(cot["flow"]))
     torch.cuda.synchronize()
     gref = O.backward(osc, o, v, cot, **kw)
     e = compare_forward(outs, ref)
