@@ -648,7 +648,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
     constexpr bool PERSIST = (F & kPer) != 0, COLOR = (F & kCol) != 0;
     constexpr int NW = BLOCK / 64;
     constexpr int RAYS = 64 * T;
-    static_assert(T <= 32, "a 32-bit mask of the item's ray tiles");
+    static_assert(T <= 32 && 64 % T == 0, "a 32-bit mask of the item's ray tiles, whole tile sets per wave");
     constexpr int RW = COLOR ? 3 : 2;                         // float4 per staged ray
     constexpr int EW = COLOR ? 6 : 5;                         // float4 per staged Gaussian
     constexpr int LREC = kOffsetAcc + (COLOR ? 3 : 0);        // sums per Gaussian
@@ -746,23 +746,32 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
             }
             __syncthreads();
             if (gb == 0) db_any = (unsigned)wave_ballot(lane < nt && tdb[lane] != 0);
-            for (int i = wave; i < cnt; i += NW) {
+            // The wave takes Gaussians i0, i0 + NW, ... and bounds GPB of them on the item's tiles in
+            // one pass (lane: tile lane % T of Gaussian i0 + (lane / T) NW), then walks them in order.
+            constexpr int GPB = 64 / T;
+            for (int i0 = wave; i0 < cnt; i0 += GPB * NW) {
+              unsigned long long tmasks;  // bits [T k, T k + T): the tiles Gaussian i0 + k NW can matter on
+              {
+                const int ik = i0 + (lane / T) * NW, tl = lane % T;
+                bool need = false;
+                if (tl < nt && ik < cnt) {
+                    const Ent gk = ent_from(ents[EW * ik], ents[EW * ik + 1], ents[EW * ik + 2], ents[EW * ik + 3]);
+                    float d2_hi, z_hi;
+                    tile_bounds(gk, ents[EW * ik + 4], tcone[tl], bl.hm, bl.b1, bl.nc2, d2_hi, z_hi);
+                    // (written so that a NaN bound keeps the tile)
+                    need = !(b1_pos && z_hi - tnorm[tl] < kSkipLog2 && d2_hi < kDensSkipLog2);
+                }
+                tmasks = wave_ballot(need);
+              }
+              for (int k = 0; k < GPB; ++k) {
+                const int i = i0 + k * NW;
+                if (i >= cnt) break;
                 const Ent g = ent_from(ents[EW * i], ents[EW * i + 1], ents[EW * i + 2], ents[EW * i + 3]);
                 const float4 est = ents[EW * i + 4];
                 float4 cc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                 if (COLOR) cc = ents[EW * i + 5];
-                // the tiles the Gaussian can matter on (lane t tests tile t)
-                unsigned tmask;
-                {
-                    bool need = false;
-                    if (lane < nt) {
-                        float d2_hi, z_hi;
-                        tile_bounds(g, est, tcone[lane], bl.hm, bl.b1, bl.nc2, d2_hi, z_hi);
-                        // (written so that a NaN bound keeps the tile)
-                        need = !(b1_pos && z_hi - tnorm[lane] < kSkipLog2 && d2_hi < kDensSkipLog2);
-                    }
-                    tmask = (unsigned)wave_ballot(need);
-                }
+                unsigned tmask = (unsigned)(tmasks >> (T * k));
+                if (T < 32) tmask &= (1u << (T % 32)) - 1u;
                 OffsetAcc acc;
                 float aC0 = 0.0f, aC1 = 0.0f, aC2 = 0.0f;  // colour sums: wt C_bar
 #pragma unroll 1
@@ -826,6 +835,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
                 const float tot = wave_sum16(v, lane);
                 const int idx = wave16_index(lane);
                 if ((lane & 3) == 0 && idx < LREC) rec[LREC * i + idx] = tot;
+              }
             }
             __syncthreads();
             for (int q = tid; q < cnt; q += BLOCK) {
