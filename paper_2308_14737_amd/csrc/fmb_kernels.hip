@@ -766,12 +766,17 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
               for (int k = 0; k < GPB; ++k) {
                 const int i = i0 + k * NW;
                 if (i >= cnt) break;
+                unsigned tmask = (unsigned)(tmasks >> (T * k));
+                if (T < 32) tmask &= (1u << (T % 32)) - 1u;
+                if (tmask == 0u) {
+                    // no tile of the item takes a term of this Gaussian: its sums are zero
+                    if (lane < LREC) rec[LREC * i + lane] = 0.0f;
+                    continue;
+                }
                 const Ent g = ent_from(ents[EW * i], ents[EW * i + 1], ents[EW * i + 2], ents[EW * i + 3]);
                 const float4 est = ents[EW * i + 4];
                 float4 cc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                 if (COLOR) cc = ents[EW * i + 5];
-                unsigned tmask = (unsigned)(tmasks >> (T * k));
-                if (T < 32) tmask &= (1u << (T % 32)) - 1u;
                 OffsetAcc acc;
                 float aC0 = 0.0f, aC1 = 0.0f, aC2 = 0.0f;  // colour sums: wt C_bar
 #pragma unroll 1
