@@ -528,8 +528,8 @@ struct Job {
         return FMB_OK;
     }
 
-    // split statistic: its own items (Gaussian-lane chunks for the blend model, whole scenes
-    // for compositing) and buffers, so captured graphs of the passes stay valid
+    // split statistic: its own items (runs of ray tiles of one view against the whole scene, for
+    // both models) and buffers, so captured graphs of the passes stay valid
     int stat_built = -1, n_sitems = 0, n_stasks = 0, stat_max_gc = 0;
     DevBuf d_sitems, d_stasks, d_spartial, d_srays;
 
@@ -537,7 +537,6 @@ struct Job {
     {
         if (stat_built == model) return FMB_OK;
         const bool comp = model == FMB_MODEL_COMPOSITE;
-        const int B = block_size();
         std::vector<BwdItem> items;
         std::vector<StatTask> tasks;
         std::vector<int64_t> rays(S, 0);
@@ -545,13 +544,8 @@ struct Job {
         stat_max_gc = 0;
         for (int s = 0; s < S; ++s) {
             const int n = scenes[s].n;
-            int gc = n, sl = 1, span;
-            if (comp) {
-                span = kCompTiles;  // ray tiles (ViewRec) per item
-            } else {
-                chunking(n, B, gc, sl);
-                span = 256 * sl;  // about 256 rays per lane
-            }
+            const int gc = n, sl = 1;
+            const int span = comp ? kCompTiles : kStatTiles;  // ray tiles (ViewRec) per item
             stat_max_gc = std::max(stat_max_gc, gc);
             for (int k = scenes[s].view_off; k < scenes[s].view_off + scenes[s].n_views; ++k)
                 rays[s] += (int64_t)views[k].h * views[k].w;
@@ -562,8 +556,8 @@ struct Job {
                 t.gc = std::min(gc, n - g0);
                 t.item_begin = (int)items.size();
                 for (int k = scenes[s].view_off; k < scenes[s].view_off + scenes[s].n_views; ++k) {
-                    // ray0 and span count rays, or for the compositing kernel ray tiles
-                    const int lim = comp ? views[k].tiles : views[k].h * views[k].w;
+                    // ray0 and span count ray tiles
+                    const int lim = views[k].tiles;
                     for (int r0 = 0; r0 < lim; r0 += span) {
                         BwdItem it{};
                         it.view = k;

@@ -98,6 +98,7 @@ constexpr int kPartialColor = 13;  // ... and dL/d(colour) (3)
 // Zero-parameter (alpha-compositing) renderer: ray tiles (ViewRec) per work item, one wave per
 // item.
 constexpr int kCompTiles = 16;
+constexpr int kStatTiles = 16;  // ray tiles (ViewRec) per item of the blend model's split statistic
 
 // Kernel argument blocks (passed by value).
 struct Params {

@@ -977,67 +977,130 @@ __global__ __launch_bounds__(BLOCK) void fin2_kernel(Params P, const FinTask *__
 // ------------------------------------------------------------------------------------
 // Split statistic (Sec. 8): lbar_i = (1/M) sum_j L_j w_ji over a scene's M rays, w_ji the
 // normalised blend weights of Eq. (3) (Eq. 7 here), read back from the forward pass's stash.
-// Gaussian-lane layout as the backward: rays staged through LDS (direction, running max,
-// 1/S, loss), one partial sum per (item, Gaussian), reduced over the slots in LDS.
+// Tiled like the backward (bwdt_kernel): an item is T ray tiles of one view against every
+// Gaussian of its scene.  The rays are staged in LDS with M2 + log2 S (so that z2 minus it is the
+// log2 of the normalised weight) and their loss value; each wave bounds GPB Gaussians at a time on
+// the item's tiles (tile_bounds against the tile's least M2 + log2 S) and, for each Gaussian, sums
+// L w over the rays of the tiles where some weight can be above FP32's zero (the one-FMA bound
+// of m per pair first), then reduces over the wave into the item's record of one float per
+// Gaussian.
 // ------------------------------------------------------------------------------------
 
-template <int BLOCK, int RT>
-__global__ __launch_bounds__(BLOCK) void stat_kernel(Params P, const float *__restrict__ loss,
-                                                    const float *__restrict__ stash,
-                                                    const BwdItem *__restrict__ items, float *__restrict__ partial)
+template <int BLOCK, int T, int TG>
+__global__ __launch_bounds__(BLOCK) void statt_kernel(Params P, const float *__restrict__ loss,
+                                                     const float *__restrict__ stash,
+                                                     const BwdItem *__restrict__ items, float *__restrict__ partial)
 {
-    __shared__ float4 rays[RT * 2];
-    __shared__ float red[BLOCK];
-    const int tid = threadIdx.x;
-    const BwdItem item = items[blockIdx.x];
-    const ViewRec vr = P.views[item.view];
-    const SceneRec sr = P.scenes[vr.scene];
-    const float *__restrict__ e = P.w2c + 12 * item.view;
-    const float *__restrict__ kk = P.intr + 4 * item.view;
+    static_assert(T <= 32 && 64 % T == 0, "a 32-bit mask of the item's ray tiles, whole tile sets per wave");
+    constexpr int NW = BLOCK / 64, RAYS = 64 * T, GPB = 64 / T;
+    __shared__ float4 rays[RAYS];   // per ray: (v, M2 + log2 S)
+    __shared__ float lossv[RAYS];   // per ray: its loss value
+    __shared__ float4 tcone[T];     // per ray tile: unit centre direction, largest |v - c|
+    __shared__ float tnorm[T];      // per ray tile: least M2 + log2 S over its rays
+    __shared__ float4 ents[5 * TG];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const BwdItem item = ld_uniform(items + blockIdx.x);
+    const ViewRec vr = ld_uniform(P.views + item.view);
+    const SceneRec sr = ld_uniform(P.scenes + vr.scene);
+    const CamRec cam = cam_of(P, item.view);
+    const float *e = cam.e, *kk = cam.k;
     double o[3];
     cam_centre(e, o);
     const Blend bl = blend_of(P, vr.scene);
-    const int hw = vr.h * vr.w;
-    const int end = min(item.ray0 + item.span, hw);
-    const int gi = tid % item.gc;
-    const int slot = tid / item.gc;
-    const bool active = slot < item.slots && item.g0 + gi < sr.n;
-    Ent g;
-    if (active) {
-        const int gg = sr.gauss_off + item.g0 + gi;
-        float4 q[4];
-        make_entry(P.means + 3 * gg, P.prec + 6 * gg, P.weights[gg], o, q);
-        g = ent_from(q[0], q[1], q[2], q[3]);
+    const bool b1_pos = bl.b1 >= 0.0f;  // the weight bounds need beta1 >= 0
+    const int nt = min(T, vr.tiles - item.ray0);  // the item's tiles: ray0 is its first tile
+
+    for (int q = tid; q < RAYS; q += BLOCK) {
+        int row = 0, col = 0;
+        const int local = (q >> 6) < nt ? tile_local(vr, item.ray0 + (q >> 6), q & 63, row, col) : -1;
+        float v0 = 0.0f, v1 = 0.0f, v2 = 1.0f, wo = INFINITY, lr = 0.0f;  // a ray past the edge weighs 0
+        if (local >= 0) {
+            tile_ray_dir(P, vr, e, kk, local, row, col, v0, v1, v2);
+            const size_t r = (size_t)vr.ray_off + local;
+            const float4 s0 = reinterpret_cast<const float4 *>(stash)[2 * r];
+            wo = s0.x - __builtin_amdgcn_logf(s0.y);  // M2 + log2 S (s0.y = 1 / S)
+            lr = loss[r];
+        }
+        rays[q] = make_float4(v0, v1, v2, wo);
+        lossv[q] = lr;
     }
-    float acc = 0.0f;
-    for (int r0 = item.ray0; r0 < end; r0 += RT) {
-        const int cnt = min(RT, end - r0);
-        __syncthreads();
+    __syncthreads();
+    for (int tt = wave; tt < nt; tt += NW) {
+        int row, col;
+        const bool ok = tile_local(vr, item.ray0 + tt, lane, row, col) >= 0;
+        const float4 x0 = rays[64 * tt + lane];
+        float c0 = wave_sum(ok ? x0.x : 0.0f), c1 = wave_sum(ok ? x0.y : 0.0f), c2 = wave_sum(ok ? x0.z : 0.0f);
+        const float inv = rsq_(fmaf(c0, c0, fmaf(c1, c1, fmaf(c2, c2, kEpsN))));
+        c0 *= inv;
+        c1 *= inv;
+        c2 *= inv;
+        const float e0 = x0.x - c0, e1 = x0.y - c1, e2 = x0.z - c2;
+        float rho = ok ? sqrtf(fmaf(e0, e0, fmaf(e1, e1, e2 * e2))) : 0.0f;
+        float nmin = ok ? x0.w : INFINITY;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            rho = fmaxf(rho, __shfl_xor(rho, off, 64));
+            nmin = fminf(nmin, __shfl_xor(nmin, off, 64));
+        }
+        if (lane == 0) {
+            tcone[tt] = make_float4(c0, c1, c2, rho * (1.0f + 1e-4f) + 1e-6f);
+            tnorm[tt] = nmin;
+        }
+    }
+    float *__restrict__ out = partial + item.poff;
+    for (int gb = 0; gb < sr.n; gb += TG) {
+        const int cnt = min(TG, sr.n - gb);
+        __syncthreads();  // staged rays and cones visible; the previous tile's entries are consumed
         for (int q = tid; q < cnt; q += BLOCK) {
-            const int r = vr.ray_off + r0 + q;
-            float v0, v1, v2;
-            ray_dir(P, vr, e, kk, r0 + q, v0, v1, v2);
-            const float4 s0 = reinterpret_cast<const float4 *>(stash)[2 * (size_t)r];
-            rays[2 * q] = make_float4(v0, v1, v2, s0.x);
-            rays[2 * q + 1] = make_float4(s0.y, loss[r], 0.0f, 0.0f);
+            const int gi = sr.gauss_off + gb + q;
+            make_entry_est(P.means + 3 * gi, P.prec + 6 * gi, P.weights[gi], o, &ents[5 * q]);
         }
         __syncthreads();
-        if (active) {
-            for (int j = slot; j < cnt; j += item.slots) {
-                const float4 x0 = rays[2 * j], x1 = rays[2 * j + 1];
-                Geo q;  // the weight needs no residual at the peak
-                pair_geo_coarse(g, x0.x, x0.y, x0.z, bl.hm, bl.b1, bl.nc2, q);
-                if (q.z2 - x0.w >= kSkipLog2) acc = fmaf(x1.y, exp2_(q.z2 - x0.w) * x1.x, acc);
+        for (int i0 = wave; i0 < cnt; i0 += GPB * NW) {
+            unsigned long long tmasks;  // bits [T k, T k + T): the tiles Gaussian i0 + k NW can weigh on
+            {
+                const int ik = i0 + (lane / T) * NW, tl = lane % T;
+                bool need = false;
+                if (tl < nt && ik < cnt) {
+                    const Ent gk = ent_from(ents[5 * ik], ents[5 * ik + 1], ents[5 * ik + 2], ents[5 * ik + 3]);
+                    float d2_hi, z_hi;
+                    tile_bounds(gk, ents[5 * ik + 4], tcone[tl], bl.hm, bl.b1, bl.nc2, d2_hi, z_hi);
+                    // (written so that a NaN bound keeps the tile)
+                    need = !(b1_pos && z_hi - tnorm[tl] < kSkipLog2);
+                }
+                tmasks = wave_ballot(need);
+            }
+            for (int k = 0; k < GPB; ++k) {
+                const int i = i0 + k * NW;
+                if (i >= cnt) break;
+                unsigned tmask = (unsigned)(tmasks >> (T * k));
+                if (T < 32) tmask &= (1u << (T % 32)) - 1u;
+                float acc = 0.0f;
+                if (tmask != 0u) {
+                    const Ent g = ent_from(ents[5 * i], ents[5 * i + 1], ents[5 * i + 2], ents[5 * i + 3]);
+                    const float4 est = ents[5 * i + 4];
+#pragma unroll 1
+                    while (tmask) {
+                        const int t = __builtin_ctz(tmask);
+                        tmask &= tmask - 1;
+                        const float4 x0 = rays[64 * t + lane];
+                        Geo q;
+                        const float vc = pair_geo_peak(g, x0.x, x0.y, x0.z, q);
+                        if (b1_pos) {
+                            // an upper bound of the log2 weight from a lower bound of m (one FMA)
+                            const float d2_hi = fmaf(bl.hm, pair_m_low(est, vc, q.t), g.l2l);
+                            if (!wave_any(fmaf(bl.b1, d2_hi, fmaf(bl.nc2, q.t, -x0.w)) >= kSkipLog2)) continue;
+                        }
+                        pair_geo_resid(g, x0.x, x0.y, x0.z, bl.hm, bl.b1, bl.nc2, q);
+                        const float zr = fmaf(bl.b1, q.d2, fmaf(bl.nc2, q.t, -x0.w));
+                        if (zr >= kSkipLog2) acc = fmaf(lossv[64 * t + lane], exp2_(zr), acc);
+                    }
+                    acc = wave_sum(acc);
+                }
+                if (lane == 0) out[gb + i] = acc;
             }
         }
-    }
-    __syncthreads();
-    red[tid] = acc;
-    __syncthreads();
-    if (slot == 0 && gi < item.gc && item.g0 + gi < sr.n) {
-        float s = red[gi];
-        for (int k = 1; k < item.slots; ++k) s += red[k * item.gc + gi];
-        partial[item.poff + gi] = s;
     }
 }
 
@@ -1338,7 +1401,7 @@ hipError_t launch_stat(int n_items, int n_tasks, int max_gc, hipStream_t st, con
                        const int64_t *rays_per_scene, float *lbar)
 {
     if (n_items > 0)
-        hipLaunchKernelGGL((stat_kernel<kBlock, 256>), dim3(n_items), dim3(kBlock), 0, st, P, loss, stash, items,
+        hipLaunchKernelGGL((statt_kernel<512, kStatTiles, 64>), dim3(n_items), dim3(512), 0, st, P, loss, stash, items,
                            partial);
     if (n_tasks > 0)
         hipLaunchKernelGGL(stat_fin_kernel, dim3(n_tasks, max_gc), dim3(256), 0, st, P, tasks, items, partial,
