@@ -31,7 +31,7 @@ namespace fmb {
 // ------------------------------------------------------------------------------------
 
 template <int BLOCK, int RPT, int TG, int F>
-__global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const FwdItem *__restrict__ items,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void fwd_kernel(Params P, FwdOut O, const FwdItem *__restrict__ items,
                                                    int n_items, const int *__restrict__ order,
                                                    int *__restrict__ counter)
 {
@@ -39,6 +39,9 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
     constexpr bool COLOR = (F & kCol) != 0;
     constexpr int EW = COLOR ? 6 : 5;  // float4 per LDS entry: the entry, the m estimate terms, colour
     __shared__ float4 tile[TG * EW];
+    // the first sweep's weight bound of each (Gaussian, ray tile) for the second sweep (-inf where
+    // the first sweep took the pair): per wave, per group of 64 / RPT Gaussians, per lane
+    __shared__ float zsave[BLOCK / 64][TG * RPT];
     __shared__ int s_item;
     int pos = blockIdx.x;
     for (;;) {
@@ -137,14 +140,20 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(Params P, FwdOut O, const Fw
               }
               for (int ib = 0; ib < cnt; ib += GP) {
                 const int il = ib + lane / RPT;
+                float *const zs = &zsave[wave][ib * RPT + lane];
                 bool need = false;
                 if (il < cnt) {
-                    const Ent gl = ent_from(tile[EW * il], tile[EW * il + 1], tile[EW * il + 2], tile[EW * il + 3]);
-                    float d2h, zh;
-                    tile_bounds(gl, tile[EW * il + 4], cl, bl.hm, bl.b1, bl.nc2, d2h, zh);
-                    // (comparisons written so that a NaN bound keeps the pair)
-                    const bool first = !(b1_pos && d2h < kDensSkipLog2);
-                    need = sweep == 0 ? first : (!first && !(zh - mmin < kSkipLog2));
+                    if (sweep == 0) {
+                        const Ent gl = ent_from(tile[EW * il], tile[EW * il + 1], tile[EW * il + 2], tile[EW * il + 3]);
+                        float d2h, zh;
+                        tile_bounds(gl, tile[EW * il + 4], cl, bl.hm, bl.b1, bl.nc2, d2h, zh);
+                        // (comparisons written so that a NaN bound keeps the pair)
+                        need = !(b1_pos && d2h < kDensSkipLog2);
+                        *zs = need ? -INFINITY : zh;
+                    } else {
+                        const float zh = *zs;
+                        need = zh != -INFINITY && !(zh - mmin < kSkipLog2);
+                    }
                 }
                 const unsigned long long nm = wave_ballot(need);
                 if (nm == 0ull) continue;
