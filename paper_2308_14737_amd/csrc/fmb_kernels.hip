@@ -670,6 +670,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
     __shared__ float4 ents[EW * TG];          // the Gaussian tile's entries (m estimate terms, colour)
     __shared__ float rec[LREC * TG];          // (H, Bv, L) [and the colour sums] of each Gaussian
     __shared__ float bsum[2 * NW];
+    __shared__ int slist[BLOCK];              // scenes beyond BLOCK Gaussians: a round's survivors
+    __shared__ int wcnt[NW];
     __shared__ int s_item;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -745,16 +747,76 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
         }
         float aB1 = 0.0f, aB2 = 0.0f;
         unsigned db_any = 0;  // bit t: some ray of tile t has a density cotangent
-        for (int gb = 0; gb < sr.n; gb += TG) {
-            const int cnt = min(TG, sr.n - gb);
-            __syncthreads();  // staged rays visible; the previous tile's entries and sums are consumed
+        bool db_set = false;
+        // A scene of more than BLOCK Gaussians is taken in rounds of BLOCK: each Gaussian of the
+        // round is first bounded on the whole item (tile_bounds on a cone around all its tiles,
+        // against their least normaliser), and only those that can matter on some tile are staged,
+        // TG at a time, in scene order (slist: their scene-local indices); the others' records are
+        // zero, as the per-tile bounds would have left them.  Smaller scenes take one round of all
+        // their Gaussians in order.
+        const bool sparse = sr.n > BLOCK;
+        for (int rb = 0; rb < sr.n; rb += sparse ? BLOCK : sr.n) {
+          int total = sr.n;
+          if (sparse) {
+            __syncthreads();  // cones visible; the previous round's list and entries are consumed
+            float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, inorm = INFINITY;
+            for (int t = 0; t < nt; ++t) {
+                s0 += tcone[t].x;
+                s1 += tcone[t].y;
+                s2 += tcone[t].z;
+                inorm = fminf(inorm, tnorm[t]);
+            }
+            const float si = rsq_(fmaf(s0, s0, fmaf(s1, s1, fmaf(s2, s2, kEpsN))));
+            s0 *= si;
+            s1 *= si;
+            s2 *= si;
+            float irho = 0.0f;  // |v - c| <= |v - c_t| + |c_t - c| for a ray v of tile t
+            for (int t = 0; t < nt; ++t) {
+                const float4 ct = tcone[t];
+                const float d0 = ct.x - s0, d1 = ct.y - s1, d2 = ct.z - s2;
+                irho = fmaxf(irho, sqrtf(fmaf(d0, d0, fmaf(d1, d1, d2 * d2))) + ct.w);
+            }
+            const float4 icone = make_float4(s0, s1, s2, irho * (1.0f + 1e-4f) + 1e-6f);
+            const int gl = rb + tid;
+            bool keep = false;
+            if (gl < sr.n) {
+                const int gg = sr.gauss_off + gl;
+                float4 q[5];
+                make_entry_est(P.means + 3 * gg, P.prec + 6 * gg, P.weights[gg], o, q);
+                float d2_hi, z_hi;
+                tile_bounds(ent_from(q[0], q[1], q[2], q[3]), q[4], icone, bl.hm, bl.b1, bl.nc2, d2_hi, z_hi);
+                // (written so that a NaN bound keeps the Gaussian)
+                keep = !(b1_pos && z_hi - inorm < kSkipLog2 && d2_hi < kDensSkipLog2);
+                if (!keep) {
+                    float *dst = partial + item.poff + REC * gl;
+                    for (int c = 0; c < REC; ++c) dst[c] = 0.0f;
+                }
+            }
+            const unsigned long long bal = wave_ballot(keep);
+            if (lane == 0) wcnt[wave] = __popcll(bal);
+            __syncthreads();
+            int off = 0;
+            total = 0;
+            for (int w = 0; w < NW; ++w) {
+                const int c = wcnt[w];
+                off += w < wave ? c : 0;
+                total += c;
+            }
+            if (keep) slist[off + __popcll(bal & ((1ull << lane) - 1ull))] = gl;
+          }
+          for (int gb = 0; gb < total; gb += TG) {
+            const int cnt = min(TG, total - gb);
+            __syncthreads();  // staged rays (and the list) visible; the previous tile's entries and sums are consumed
             for (int q = tid; q < cnt; q += BLOCK) {
-                const int gi = sr.gauss_off + gb + q;
+                const int gi = sr.gauss_off + (sparse ? slist[gb + q] : gb + q);
                 make_entry_est(P.means + 3 * gi, P.prec + 6 * gi, P.weights[gi], o, &ents[EW * q]);
                 if (COLOR) ents[EW * q + 5] = colour_entry(P.colors + 3 * gi);
             }
             __syncthreads();
-            if (gb == 0) db_any = (unsigned)wave_ballot(lane < nt && tdb[lane] != 0);
+            if (!db_set) {  // (uniform: the first batch of the item)
+                db_any = (unsigned)wave_ballot(lane < nt && tdb[lane] != 0);
+                db_set = true;
+            }
             // The wave takes Gaussians i0, i0 + NW, ... and bounds GPB of them on the item's tiles in
             // one pass (lane: tile lane % T of Gaussian i0 + (lane / T) NW), then walks them in order.
             constexpr int GPB = 64 / T;
@@ -853,10 +915,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
             }
             __syncthreads();
             for (int q = tid; q < cnt; q += BLOCK) {
-                const int gg = sr.gauss_off + gb + q;
-                write_partial_offset(partial + item.poff + REC * (gb + q), rec + LREC * q, REC,
+                const int gl = sparse ? slist[gb + q] : gb + q;
+                const int gg = sr.gauss_off + gl;
+                write_partial_offset(partial + item.poff + REC * gl, rec + LREC * q, REC,
                                      P.prec + 6 * gg, P.means + 3 * gg, o);
             }
+          }
         }
         // betas: lanes summed over the wave, then the waves in order
         aB1 = wave_sum(aB1);
