@@ -63,7 +63,7 @@ size_t scratch_bytes();
 using namespace fmb;
 
 namespace {
-constexpr int kFlagNrm = 1, kFlagFlw = 2, kFlagPer = 4, kFlagCol = 8;
+constexpr int kFlagNrm = 1, kFlagFlw = 2, kFlagPer = 4, kFlagCol = 8, kFlagBig = 16;
 
 // Gradient outputs of a backward call.
 struct Grads {
@@ -648,6 +648,12 @@ struct Job {
         return (O.normal ? kFlagNrm : 0) | (O.flow ? kFlagFlw : 0) | (persist ? kFlagPer : 0) |
                (O.color ? kFlagCol : 0);
     }
+    // The blend forward's flags: with a scene of more than a block's count of Gaussians, the kernel
+    // form that takes such scenes in pre-culled rounds.
+    int blend_fwd_flags(const FwdOut &O, bool persist) const
+    {
+        return fwd_flags(O, persist) | (max_scene_n() > block_size() ? kFlagBig : 0);
+    }
     static int bwd_flags(const BwdIn &I, bool persist)
     {
         return (I.g_normal ? kFlagNrm : 0) | (I.g_flow ? kFlagFlw : 0) | (persist ? kFlagPer : 0) |
@@ -672,7 +678,7 @@ struct Job {
         }
         int rc = build_fwd(fwd_variant);
         if (rc) return rc;
-        const int flags = fwd_flags(O, persist);
+        const int flags = blend_fwd_flags(O, persist);
         int grid = n_fitems;
         if (persist) {
             if ((rc = grid_fwd(flags, grid))) return rc;
@@ -1177,7 +1183,7 @@ int fmb_batch_capture(fmb_batch *b, float *depth, float *alpha, float *normal, f
     if (j.model == FMB_MODEL_BLEND) {
         int gdummy = 0;
         if (!rc) rc = j.build_fwd(j.fwd_variant);
-        if (!rc) rc = j.grid_fwd(Job::fwd_flags(O, true), gdummy);
+        if (!rc) rc = j.grid_fwd(j.blend_fwd_flags(O, true), gdummy);
         if (!rc) rc = j.grid_bwd(j.bwd_run_variant(I), Job::bwd_flags(I, true), gdummy);
     }
     if (rc) return rc;

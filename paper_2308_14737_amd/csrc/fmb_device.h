@@ -325,6 +325,7 @@ constexpr int kNrm = 1;  // normals (Eq. 17)
 constexpr int kFlw = 2;  // flow to a second pose (Sec. 5)
 constexpr int kPer = 4;  // persistent work queue
 constexpr int kCol = 8;  // per-Gaussian colour blended by Eq. (3)
+constexpr int kBig = 16;  // forward: scenes beyond a block's count of Gaussians take pre-culled rounds
 
 // Colour of a Gaussian: sigmoid of the unconstrained parameters (double, rounded).
 __device__ __forceinline__ float4 colour_entry(const float *__restrict__ q)

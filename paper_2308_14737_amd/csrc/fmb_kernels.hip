@@ -36,12 +36,18 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
                                                    int *__restrict__ counter)
 {
     constexpr bool NORMALS = (F & kNrm) != 0, PERSIST = (F & kPer) != 0;
-    constexpr bool COLOR = (F & kCol) != 0;
+    constexpr bool COLOR = (F & kCol) != 0, BIG = (F & kBig) != 0;
     constexpr int EW = COLOR ? 6 : 5;  // float4 per LDS entry: the entry, the m estimate terms, colour
     __shared__ float4 tile[TG * EW];
     // the first sweep's weight bound of each (Gaussian, ray tile) for the second sweep (-inf where
     // the first sweep took the pair): per wave, per group of 64 / RPT Gaussians, per lane
     __shared__ float zsave[BLOCK / 64][TG * RPT];
+    // scenes beyond BLOCK Gaussians: the item's tile cones, the waves' least running maxima and
+    // counts of survivors, and a round's survivors
+    __shared__ float4 icones[BIG ? BLOCK / 64 * RPT : 1];
+    __shared__ float wmin[BIG ? BLOCK / 64 : 1];
+    __shared__ int wcnt[BIG ? BLOCK / 64 : 1];
+    __shared__ int slist[BIG ? BLOCK : 1];
     __shared__ int s_item;
     int pos = blockIdx.x;
     for (;;) {
@@ -111,11 +117,74 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
             if (jl == j) cl = make_float4(c0, c1, c2, rho * (1.0f + 1e-4f) + 1e-6f);
         }
 
-        for (int gb = 0; gb < sr.n; gb += TG) {
-            const int cnt = min(TG, sr.n - gb);
-            if (gb > 0 || !PERSIST) __syncthreads();
+        // A scene of more than BLOCK Gaussians is taken in rounds of BLOCK: each Gaussian of the
+        // round is first bounded on a cone around all the item's tiles, and only those whose
+        // density can reach 2^kDensSkipLog2 there, or whose weight can be above FP32's zero
+        // against the least running maximum of the item's rays so far, are staged, in scene order
+        // (slist).  The running maxima only grow, so a Gaussian left out is one whose every pair
+        // the tests below would skip when its turn came: the sums are those of the full order.
+        // Smaller scenes take one round of all their Gaussians (and launches without kBig, whose
+        // scenes are all small, have no such rounds).
+        const bool sparse = BIG && sr.n > BLOCK;
+        if (sparse && lane < RPT) icones[wave * RPT + lane] = cl;
+        for (int rb = 0; rb < sr.n; rb += sparse ? BLOCK : sr.n) {
+          int total = sr.n;
+          if (sparse) {
+            float mm = INFINITY;
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) mm = loc[j] >= 0 ? fminf(mm, M[j]) : mm;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) mm = fminf(mm, __shfl_xor(mm, off, 64));
+            __syncthreads();  // the previous round's list and staged tile are consumed
+            if (lane == 0) wmin[wave] = mm;
+            __syncthreads();  // tile cones and least maxima visible
+            float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, imin = INFINITY;
+            for (int t = 0; t < NW * RPT; ++t) {
+                s0 += icones[t].x;  // (a tile without a ray in the view has centre 0)
+                s1 += icones[t].y;
+                s2 += icones[t].z;
+            }
+            for (int w = 0; w < NW; ++w) imin = fminf(imin, wmin[w]);
+            const float si = rsq_(fmaf(s0, s0, fmaf(s1, s1, fmaf(s2, s2, kEpsN))));
+            s0 *= si;
+            s1 *= si;
+            s2 *= si;
+            float irho = 0.0f;  // |v - c| <= |v - c_t| + |c_t - c| for a ray v of tile t
+            for (int t = 0; t < NW * RPT; ++t) {
+                const float4 ct = icones[t];
+                if (fmaf(ct.x, ct.x, fmaf(ct.y, ct.y, ct.z * ct.z)) < 0.25f) continue;
+                const float d0 = ct.x - s0, d1 = ct.y - s1, d2 = ct.z - s2;
+                irho = fmaxf(irho, sqrtf(fmaf(d0, d0, fmaf(d1, d1, d2 * d2))) + ct.w);
+            }
+            const float4 icone = make_float4(s0, s1, s2, irho * (1.0f + 1e-4f) + 1e-6f);
+            const int gl = rb + (int)threadIdx.x;
+            bool keep = false;
+            if (gl < sr.n) {
+                const int gg = sr.gauss_off + gl;
+                float4 q[5];
+                make_entry_est(P.means + 3 * gg, P.prec + 6 * gg, P.weights[gg], o, q);
+                float d2_hi, z_hi;
+                tile_bounds(ent_from(q[0], q[1], q[2], q[3]), q[4], icone, bl.hm, bl.b1, bl.nc2, d2_hi, z_hi);
+                // (written so that a NaN bound keeps the Gaussian)
+                keep = !(b1_pos && d2_hi < kDensSkipLog2 && z_hi - imin < kSkipLog2);
+            }
+            const unsigned long long bal = wave_ballot(keep);
+            if (lane == 0) wcnt[wave] = __popcll(bal);
+            __syncthreads();
+            int off = 0;
+            total = 0;
+            for (int w = 0; w < NW; ++w) {
+                const int c = wcnt[w];
+                off += w < wave ? c : 0;
+                total += c;
+            }
+            if (keep) slist[off + __popcll(bal & ((1ull << lane) - 1ull))] = gl;
+          }
+        for (int gb = 0; gb < total; gb += TG) {
+            const int cnt = min(TG, total - gb);
+            if (gb > 0 || !PERSIST || sparse) __syncthreads();
             for (int q = threadIdx.x; q < cnt; q += BLOCK) {
-                const int gi = sr.gauss_off + gb + q;
+                const int gi = sr.gauss_off + (sparse ? slist[gb + q] : gb + q);
                 make_entry_est(P.means + 3 * gi, P.prec + 6 * gi, P.weights[gi], o, &tile[EW * q]);
                 if (COLOR) tile[EW * q + 5] = colour_entry(P.colors + 3 * gi);
             }
@@ -227,6 +296,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
               }
               }
             }
+        }
         }
 
         const float o0 = (float)o[0], o1 = (float)o[1], o2 = (float)o[2];
@@ -1347,6 +1417,20 @@ constexpr int kBwdTiledFirst = kNumBwdGauss + kNumBwdRay;
     default: return hipErrorInvalidValue;                                                                  \
     }
 
+// ... and over the forward's flag sets with kBig (16..31).
+#define FMB_DISPATCH_F32(f, CALL)                                                                          \
+    if ((f) < 16) {                                                                                        \
+        FMB_DISPATCH_F(f, CALL)                                                                            \
+    } else {                                                                                               \
+        switch (f) {                                                                                       \
+        case 16: CALL(16); break; case 17: CALL(17); break; case 18: CALL(18); break; case 19: CALL(19); break; \
+        case 20: CALL(20); break; case 21: CALL(21); break; case 22: CALL(22); break; case 23: CALL(23); break; \
+        case 24: CALL(24); break; case 25: CALL(25); break; case 26: CALL(26); break; case 27: CALL(27); break; \
+        case 28: CALL(28); break; case 29: CALL(29); break; case 30: CALL(30); break; case 31: CALL(31); break; \
+        default: return hipErrorInvalidValue;                                                              \
+        }                                                                                                  \
+    }
+
 template <int RPT, int TG>
 static hipError_t launch_fwd_v(int f, int grid, hipStream_t st, const Params &P, const FwdOut &O,
                                const FwdItem *items, int n, const int *order, int *counter)
@@ -1354,7 +1438,7 @@ static hipError_t launch_fwd_v(int f, int grid, hipStream_t st, const Params &P,
 #define FMB_FWD_CALL(F)                                                                                    \
     hipLaunchKernelGGL((fwd_kernel<kBlock, RPT, TG, F>), dim3(grid), dim3(kBlock), 0, st, P, O, items, n, order, \
                        counter)
-    FMB_DISPATCH_F(f, FMB_FWD_CALL)
+    FMB_DISPATCH_F32(f, FMB_FWD_CALL)
 #undef FMB_FWD_CALL
     return hipGetLastError();
 }
@@ -1508,7 +1592,7 @@ hipError_t occupancy_fwd(int variant, int flags, int *blocks_per_cu)
 #define FMB_OCC_V(RPT_, TG_)                                                                               \
     {                                                                                                      \
         constexpr int RPT = RPT_, TG = TG_;                                                                \
-        FMB_DISPATCH_F(flags, FMB_OCC_F)                                                                   \
+        FMB_DISPATCH_F32(flags, FMB_OCC_F)                                                                 \
     }
     switch (variant) {
     case 0: FMB_OCC_V(1, 128)
