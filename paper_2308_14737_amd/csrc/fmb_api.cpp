@@ -654,6 +654,12 @@ struct Job {
     {
         return fwd_flags(O, persist) | (max_scene_n() > block_size() ? kFlagBig : 0);
     }
+    // The blend backward's flags for variant v: for the tiled variants with a scene of more than a
+    // block's count of Gaussians, the kernel form that takes such scenes in pre-culled rounds.
+    int blend_bwd_flags(const BwdIn &I, bool persist, int v) const
+    {
+        return bwd_flags(I, persist) | (bwd_variant_tiles(v) > 0 && max_scene_n() > block_size() ? kFlagBig : 0);
+    }
     static int bwd_flags(const BwdIn &I, bool persist)
     {
         return (I.g_normal ? kFlagNrm : 0) | (I.g_flow ? kFlagFlw : 0) | (persist ? kFlagPer : 0) |
@@ -708,7 +714,7 @@ struct Job {
                                d_partial.as<float>(), d_bpart.as<float>(), max_scene_n()));
             tb.stop();
         } else {
-            const int flags = bwd_flags(I, persist);
+            const int flags = blend_bwd_flags(I, persist, bv);
             int grid = n_bitems;
             if (persist) {
                 if ((rc = grid_bwd(bv, flags, grid))) return rc;
@@ -786,7 +792,7 @@ struct Job {
             tb.stop();
         } else {
             TimedSpan tb(st, 1);
-            HIPCHK(launch_bwd(bv, bwd_flags(I, false), n_items, st, prm, I, items, n_items, nullptr, nullptr,
+            HIPCHK(launch_bwd(bv, blend_bwd_flags(I, false, bv), n_items, st, prm, I, items, n_items, nullptr, nullptr,
                               part, bpart));
             tb.stop();
         }
@@ -1184,7 +1190,7 @@ int fmb_batch_capture(fmb_batch *b, float *depth, float *alpha, float *normal, f
         int gdummy = 0;
         if (!rc) rc = j.build_fwd(j.fwd_variant);
         if (!rc) rc = j.grid_fwd(j.blend_fwd_flags(O, true), gdummy);
-        if (!rc) rc = j.grid_bwd(j.bwd_run_variant(I), Job::bwd_flags(I, true), gdummy);
+        if (!rc) rc = j.grid_bwd(j.bwd_run_variant(I), j.blend_bwd_flags(I, true, j.bwd_run_variant(I)), gdummy);
     }
     if (rc) return rc;
     j.drop_graphs();

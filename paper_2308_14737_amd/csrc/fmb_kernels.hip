@@ -724,7 +724,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
     int *__restrict__ counter, float *__restrict__ partial, float *__restrict__ beta_partial)
 {
     static_assert((F & kNrm) == 0, "the tiled backward takes no normal cotangent");
-    constexpr bool PERSIST = (F & kPer) != 0, COLOR = (F & kCol) != 0;
+    constexpr bool PERSIST = (F & kPer) != 0, COLOR = (F & kCol) != 0, BIG = (F & kBig) != 0;
     constexpr int NW = BLOCK / 64;
     constexpr int RAYS = 64 * T;
     static_assert(T <= 32 && 64 % T == 0, "a 32-bit mask of the item's ray tiles, whole tile sets per wave");
@@ -740,8 +740,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
     __shared__ float4 ents[EW * TG];          // the Gaussian tile's entries (m estimate terms, colour)
     __shared__ float rec[LREC * TG];          // (H, Bv, L) [and the colour sums] of each Gaussian
     __shared__ float bsum[2 * NW];
-    __shared__ int slist[BLOCK];              // scenes beyond BLOCK Gaussians: a round's survivors
-    __shared__ int wcnt[NW];
+    __shared__ int slist[BIG ? BLOCK : 1];    // scenes beyond BLOCK Gaussians: a round's survivors
+    __shared__ int wcnt[BIG ? NW : 1];
     __shared__ int s_item;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -823,8 +823,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
         // against their least normaliser), and only those that can matter on some tile are staged,
         // TG at a time, in scene order (slist: their scene-local indices); the others' records are
         // zero, as the per-tile bounds would have left them.  Smaller scenes take one round of all
-        // their Gaussians in order.
-        const bool sparse = sr.n > BLOCK;
+        // their Gaussians in order (and launches without kBig, whose scenes are all small, have no
+        // such rounds).
+        const bool sparse = BIG && sr.n > BLOCK;
         for (int rb = 0; rb < sr.n; rb += sparse ? BLOCK : sr.n) {
           int total = sr.n;
           if (sparse) {
@@ -1486,6 +1487,14 @@ static hipError_t launch_bwdt_v(int f, int grid, hipStream_t st, const Params &P
     case kCol | kFlw: FMB_BWDT_CALL(kCol | kFlw); break;
     case kCol | kPer: FMB_BWDT_CALL(kCol | kPer); break;
     case kCol | kFlw | kPer: FMB_BWDT_CALL(kCol | kFlw | kPer); break;
+    case kBig: FMB_BWDT_CALL(kBig); break;
+    case kBig | kFlw: FMB_BWDT_CALL(kBig | kFlw); break;
+    case kBig | kPer: FMB_BWDT_CALL(kBig | kPer); break;
+    case kBig | kFlw | kPer: FMB_BWDT_CALL(kBig | kFlw | kPer); break;
+    case kBig | kCol: FMB_BWDT_CALL(kBig | kCol); break;
+    case kBig | kCol | kFlw: FMB_BWDT_CALL(kBig | kCol | kFlw); break;
+    case kBig | kCol | kPer: FMB_BWDT_CALL(kBig | kCol | kPer); break;
+    case kBig | kCol | kFlw | kPer: FMB_BWDT_CALL(kBig | kCol | kFlw | kPer); break;
     default: return hipErrorInvalidValue;
     }
 #undef FMB_BWDT_CALL
@@ -1637,13 +1646,17 @@ hipError_t occupancy_bwd(int variant, int flags, int *blocks_per_cu)
 #undef FMB_OCC_V
 #undef FMB_OCC_F
     auto occb = [&](auto kernel, int blk) { return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kernel, blk, 0); };
-    // the persistent forms the batch launches (flow and colour as given)
+    // the persistent forms the batch launches (flow, colour and the large-scene form as given)
 #define FMB_OCC_T(BLK, T)                                                                                  \
-    switch (flags & (kFlw | kCol)) {                                                                       \
+    switch (flags & (kFlw | kCol | kBig)) {                                                                \
     case 0: return occb(bwdt_kernel<BLK, T, 64, kPer>, BLK);                                              \
     case kFlw: return occb(bwdt_kernel<BLK, T, 64, kFlw | kPer>, BLK);                                    \
     case kCol: return occb(bwdt_kernel<BLK, T, 64, kCol | kPer>, BLK);                                    \
-    default: return occb(bwdt_kernel<BLK, T, 64, kCol | kFlw | kPer>, BLK);                               \
+    case kCol | kFlw: return occb(bwdt_kernel<BLK, T, 64, kCol | kFlw | kPer>, BLK);                      \
+    case kBig: return occb(bwdt_kernel<BLK, T, 64, kBig | kPer>, BLK);                                    \
+    case kBig | kFlw: return occb(bwdt_kernel<BLK, T, 64, kBig | kFlw | kPer>, BLK);                      \
+    case kBig | kCol: return occb(bwdt_kernel<BLK, T, 64, kBig | kCol | kPer>, BLK);                      \
+    default: return occb(bwdt_kernel<BLK, T, 64, kBig | kCol | kFlw | kPer>, BLK);                        \
     }
     if (variant == 6) FMB_OCC_T(256, 8)
     if (variant == 7) FMB_OCC_T(256, 16)
