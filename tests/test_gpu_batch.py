@@ -351,6 +351,60 @@ def test_colour_batch_vs_oracle(fmb, batch16):
         assert_grads(e, f"colour leg backward, scene {i}")
 
 
+def test_batch_with_a_large_scene(fmb):
+    """A batch of a small scene and one of more than 256 Gaussians (which the kernel forms for large
+    scenes take in pre-culled rounds): outputs and depth/alpha gradients of every scene equal
+    per-scene launches bit for bit, and the large scene's match the oracle on sampled rays."""
+    from tests.gpu_util import custom_scene
+    betas = np.array([W.BETA1, W.BETA2], np.float32)
+    specs = [(40, [(64, 64), (48, 40)], 61, (0.05, 0.2)), (700, [(96, 128), (40, 72)], 62, (0.01, 0.05))]
+    scenes = [custom_scene(n, views, seed=sd, s_range=sr) for n, views, sd, sr in specs]
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=DEV).contiguous()  # noqa: E731
+    means = t(np.concatenate([sc.means for sc, _ in scenes]))
+    prec = t(np.concatenate([sc.prec for sc, _ in scenes]))
+    weights = t(np.concatenate([sc.weights for sc, _ in scenes]))
+    tb = t(np.tile(betas, (2, 1)))
+    cams = [fmb.Cameras.from_numpy(c.w2c, c.intr, c.hw, device=DEV) for _, c in scenes]
+    b = fmb.Batch(means, prec, weights, tb, [1.0, 1.0], [sc.n for sc, _ in scenes], cams)
+    _say(f"[large-batch] N={[sc.n for sc, _ in scenes]} P={b.n_rays}")
+    outs = b.forward(b.alloc_outputs(normals=True))
+    cot = _cotangents(b, 64, normals=False)
+    grads = b.backward(outs, cot, b.alloc_grads())
+    torch.cuda.synchronize()
+    g = np.random.Generator(np.random.PCG64(65))
+    for i, (sc, cm) in enumerate(scenes):
+        r0, r1 = b.ray_off[i], b.ray_off[i + 1]
+        g0, g1 = b.gauss_off[i], b.gauss_off[i + 1]
+        scene = fmb.Scene(means[g0:g1], prec[g0:g1], weights[g0:g1], tb[i], 1.0, cams[i])
+        o = scene.render(normals=True)
+        gi = scene.backward(o, cot["depth"][r0:r1], cot["alpha"][r0:r1], None)
+        torch.cuda.synchronize()
+        for k in ("depth", "alpha", "normal", "stash"):
+            assert torch.equal(o[k], outs[k][r0:r1]), (i, k)
+        for k in ("means", "prec", "weights"):
+            assert torch.equal(gi[k], grads[k][g0:g1]), (i, k)
+        assert torch.equal(gi["betas"], grads["betas"][i]), (i, "betas")
+        if sc.n > 256:
+            # (depth cotangents only on rays that see the scene, as in the other gradient tests)
+            rays = np.sort(g.choice(r1 - r0, size=1500, replace=False))
+            ref, _, _ = O.render_workload_view(sc, cm, betas, 1.0, rays=rays)
+            cs = {"depth": to_np(cot["depth"][r0:r1])[rays] * (ref["alpha"] >= 1e-3),
+                  "alpha": to_np(cot["alpha"][r0:r1])[rays], "normal": None, "flow": None}
+            cs["depth"] = cs["depth"].astype(np.float32)
+            _, gref, _ = O.render_workload_view(sc, cm, betas, 1.0, rays=rays, cot=cs)
+            sub = {k: (None if v is None else v[r0:r1]) for k, v in outs.items()}
+            e = compare_forward(sub, ref, rays)
+            full = {k: np.zeros(r1 - r0, np.float32) for k in ("depth", "alpha")}
+            for k in full:
+                full[k][rays] = cs[k]
+            gs = scene.backward(o, t(full["depth"]), t(full["alpha"]), None)
+            torch.cuda.synchronize()
+            eg = compare_grads(gs, gref)
+            _say(f"[large-batch] scene {i} N={sc.n}: {fmt(e)} {fmt(eg)}")
+            assert_forward(e, "large scene of a batch")
+            assert_grads(eg, "large scene of a batch")
+
+
 def test_graphs_dropped_when_stale(fmb):
     """Calls that change what the captured graphs launch (autotune, a pinned launch
     configuration, colours, a second flow target, a backward that rebuilds the work lists)
