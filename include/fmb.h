@@ -149,16 +149,19 @@ int fmb_set_flow_pose2(fmb_scene *scene, fmb_batch *batch, const float *w2c_c,
 /* Choose the blend weights of a scene or batch (exactly one non-NULL); the default is
  * FMB_MODEL_BLEND.  FMB_MODEL_COMPOSITE is the zero-parameter renderer of Sec. 3.3:
  * w_i = T_i (1 - exp(-delta_i)), T_i = exp(-sum_j delta_j [t_j < t_i]) (Eq. 9-10; Gaussians
- * at equal t_i do not attenuate one another; densities below 2^-30 are left out of the
- * sums over j, which moves a weight by less than 3.5e-7 relative, and the backward leaves
- * weights below 2^-40 out of its sums over the Gaussians behind), blended by Eq. (3) for
- * depth, normals and colour, alpha by Eq. (8) over every density; betas and eta are not
+ * at equal t_i do not attenuate one another; in a scene of n Gaussians the densities below
+ * 2^sig, sig = min(-30, -36 - ceil(log2 n)), are left out of the sums over j, which together
+ * move a sum by less than 2^-36, and pairs whose density is below 2^skip of the ray's largest
+ * weight, skip = min(-40, -26 - ceil(log2 n)), are left out of the blend and of its adjoint
+ * (which keeps those with a density of at least 2^skip)), blended by Eq. (3) for depth,
+ * normals and colour, alpha by Eq. (8) over every density; betas and eta are not
  * used and their gradient is 0.  Every
  * other call keeps its meaning, arguments and outputs; the stash holds the same fields
  * (the running maximum is that of log2 w_i).  Captured graphs are dropped when the model
  * changes; fmb_autotune leaves a compositing job as it is (one launch configuration).
- * Errors: FMB_ERR_INVALID_ARG (bad model), FMB_ERR_SHAPE (a scene has more than 256
- * Gaussians: the compositing kernels hold at most 4 per lane of a 64-lane ray). */
+ * Scenes of any size: a ray's significant intersections are taken in depth windows of at most
+ * 48 Gaussians per ray tile, one window after another.
+ * Errors: FMB_ERR_INVALID_ARG (bad model). */
 int fmb_set_model(fmb_scene *scene, fmb_batch *batch, int32_t model);
 
 /* Set (or with NULL clear) the per-Gaussian colours of a scene or batch (exactly one

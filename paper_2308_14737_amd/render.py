@@ -123,7 +123,7 @@ class Scene:
 
     def set_model(self, model: str):
         """"blend" (two-parameter weights, Eq. 7) or "composite" (zero-parameter alpha
-        compositing, Eq. 9-10; at most 256 Gaussians)."""
+        compositing, Eq. 9-10; any number of Gaussians)."""
         _lib.call("fmb_set_model", self._h, None, _model_id(model))
         self.model = model
 
