@@ -848,6 +848,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
                 irho = fmaxf(irho, sqrtf(fmaf(d0, d0, fmaf(d1, d1, d2 * d2))) + ct.w);
             }
             const float4 icone = make_float4(s0, s1, s2, irho * (1.0f + 1e-4f) + 1e-6f);
+            // the round's records start as zeros, written contiguously by all threads (the
+            // survivors' are overwritten after the barriers below)
+            {
+                float *dst = partial + item.poff + REC * rb;
+                const int nz = REC * min(BLOCK, sr.n - rb);
+                for (int c = tid; c < nz; c += BLOCK) dst[c] = 0.0f;
+            }
             const int gl = rb + tid;
             bool keep = false;
             if (gl < sr.n) {
@@ -858,10 +865,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
                 tile_bounds(ent_from(q[0], q[1], q[2], q[3]), q[4], icone, bl.hm, bl.b1, bl.nc2, d2_hi, z_hi);
                 // (written so that a NaN bound keeps the Gaussian)
                 keep = !(b1_pos && z_hi - inorm < kSkipLog2 && d2_hi < kDensSkipLog2);
-                if (!keep) {
-                    float *dst = partial + item.poff + REC * gl;
-                    for (int c = 0; c < REC; ++c) dst[c] = 0.0f;
-                }
             }
             const unsigned long long bal = wave_ballot(keep);
             if (lane == 0) wcnt[wave] = __popcll(bal);
