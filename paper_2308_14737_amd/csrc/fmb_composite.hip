@@ -49,10 +49,11 @@ namespace fmb {
 constexpr int kCompSlots = 48;  // significant intersections a lane holds per depth window
 constexpr int kCompTG = 128;    // Gaussians staged per LDS tile
 // Waves per SIMD the kernels are compiled for: the slots take 2 kCompSlots VGPRs (3 kCompSlots
-// in the backward), and both kernels fit two waves.  With 48 slots rather than 32 (three forward
-// waves) the dense tiles of the benchmark scenes take one window instead of several, which costs
-// less than the lost occupancy.
-constexpr int kFwdcWaves = 2, kBwdcWaves = 2;
+// in the backward).  With 48 slots rather than 32 the dense tiles of the benchmark scenes take one
+// window instead of several, which costs less than the lost occupancy.  The forward is held to
+// three waves (168 VGPRs, with about 48 values spilled to scratch), which
+// is faster than two waves without spills; the backward (and the split statistic) keep two.
+constexpr int kFwdcWaves = 3, kBwdcWaves = 2, kStatcWaves = 2;
 
 // log2(1 - exp(-delta)) with log2(delta) = d2.
 __device__ __forceinline__ float log2_opacity(float delta, float d2)
@@ -934,7 +935,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
 // here per item and Gaussian; the running maximum and 1/S come from the forward's stash.
 // ------------------------------------------------------------------------------------
 
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kFwdcWaves))) void statc_kernel(Params P, const float *__restrict__ loss,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kStatcWaves))) void statc_kernel(Params P, const float *__restrict__ loss,
                                                    const float *__restrict__ stash,
                                                    const BwdItem *__restrict__ items, float *__restrict__ partial)
 {
