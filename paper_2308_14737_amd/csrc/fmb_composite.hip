@@ -373,6 +373,7 @@ __device__ __forceinline__ int comp_collect(const Params &P, const SceneRec &sr,
                                             CompList &L, int *__restrict__ slot_g, OnTie on_tie)
 {
     int ns = 0;
+    bool t_inf = false;  // a slot of this lane holds an infinite scaled depth
     comp_clear(L);
     for (int gb = 0; gb < sr.n; gb += kCompTG) {
         const int cnt = min(kCompTG, sr.n - gb);
@@ -394,6 +395,7 @@ __device__ __forceinline__ int comp_collect(const Params &P, const SceneRec &sr,
             if (!wave_any(cand)) return;
             if (ns < kCompSlots) {
                 slot_set(L, ns, ts, cand ? dl : 0.0f);
+                t_inf = t_inf || (cand && ts == INFINITY);
                 if (threadIdx.x == 0) slot_g[ns] = gb + i;
                 ns = __builtin_amdgcn_readfirstlane(ns + 1);
             } else if (cand) {
@@ -424,8 +426,11 @@ __device__ __forceinline__ int comp_collect(const Params &P, const SceneRec &sr,
             }
         }
     }
+    // (where no lane's window was cut, only a slot at an infinite scaled depth can be at or behind hi)
+    if (wave_any(w.hi != INFINITY || t_inf)) {
 #pragma unroll
-    for (int k = 0; k < kCompSlots; ++k) slot_set_d(L, k, slot_t(L, k) >= w.hi ? 0.0f : slot_d(L, k));
+        for (int k = 0; k < kCompSlots; ++k) slot_set_d(L, k, slot_t(L, k) >= w.hi ? 0.0f : slot_d(L, k));
+    }
     return ns;
 }
 
@@ -834,17 +839,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kBwdcWaves))
             const float zafter = w.hi == INFINITY ? 0.0f : zall - zthrough;
 
             if (hit_tile) {
-                for (int s = 0; s < ns; s += 2) {  // two slots a step (two independent chains)
-                    const bool two = s + 1 < ns;
-                    const int ia = slot_g[s], ib = two ? slot_g[s + 1] : ia;
-                    const Ent ga = comp_ent<EW>(ents, ia), gb = comp_ent<EW>(ents, ib);
-                    Geo qa, qb;
+                for (int s = 0; s < ns; ++s) {
+                    const int ia = slot_g[s];
+                    const Ent ga = comp_ent<EW>(ents, ia);
+                    Geo qa;
                     pair_geo_coarse(ga, v0, v1, v2, hm, 0.0f, 0.0f, qa);
-                    pair_geo_coarse(gb, v0, v1, v2, hm, 0.0f, 0.0f, qb);
                     // the pair of slot s is the slot's own (its front sum is F of the slot)
-                    const float fa = fz ? slot_z(zs, s) : 0.0f, fb = fz && two ? slot_z(zs, s + 1) : 0.0f;
+                    const float fa = fz ? slot_z(zs, s) : 0.0f;
                     pair_terms(ga, qa, qa.t * kDepthScale, valid && qa.d2 > sig2, ia, ia, zafter, fz, fa);
-                    if (two) pair_terms(gb, qb, qb.t * kDepthScale, valid && qb.d2 > sig2, ib, ib, zafter, fz, fb);
                 }
             } else {
                 for (int gb = 0; gb < n; gb += kCompTG) {
